@@ -1,0 +1,234 @@
+/*
+ * gem.h -- C ABI of the MI355X (gfx950) set-to-set scoring library.
+ *
+ * The library computes the Chamfer / MaxSim similarity of GEM (arXiv 2603.20336),
+ * Def. 1 / Eq. (ch) of Sec. 3.1:
+ *
+ *     CH(Q, P) = sum over q in Q of  max over p in P of <q, p>
+ *
+ * for ragged batches of query sets against ragged document sets, in three forms:
+ *   - exact, on float32 operands (float32 products and accumulation),
+ *   - exact on bfloat16 operands (bf16 products, float32 accumulation),
+ *   - the quantized estimate: OCP FP8 E4M3 operands with one power-of-two float32
+ *     scale per vector, float32 accumulation. The paper's search scores
+ *     neighbours with a cheap quantized Chamfer estimate (qCH, Sec. 4.5) and
+ *     reranks the survivors with exact CH (Alg. 5, final step); here the estimate
+ *     is the FP8 form, and the rerank is gem_score_exact over a candidate list.
+ * plus the per-query top-k of the retrieval problem (Sec. 3.1, k-argmax of CH)
+ * and one step of batched beam expansion: score each query's candidate ids with
+ * the estimate and merge them into a bounded result set that keeps at most ef
+ * entries, evicting the worst (the set R of Alg. 5).
+ *
+ * Conventions (all entry points):
+ *   - Pointers marked [device] point to device memory on the context's device;
+ *     the caller owns every buffer, including the workspace. The library never
+ *     allocates device memory and never synchronizes the stream in these calls.
+ *   - Every call enqueues its kernels on `stream` (0 = the null stream) and
+ *     returns once they are enqueued; results are ready when the stream reaches
+ *     that point.
+ *   - Host-checkable argument errors return a status before anything is
+ *     enqueued; gem_last_error() then holds a message. Device data (offsets,
+ *     ids, values) is trusted: offsets must be non-decreasing and inside the
+ *     vector array, ids inside [0, n_sets) or negative (padding), values finite.
+ *     gem_validate_sets / gem_validate_cands check those conditions on demand.
+ *   - Vector dimension is 128 (the paper's d = 128 for every dataset, Sec. 5.1).
+ *   - Scores are float32. CH of an empty query set is 0 (empty sum); CH of a
+ *     non-empty query against an empty document is -inf (max over nothing).
+ *   - Top-k order is score descending, then id ascending; ids are distinct; a
+ *     list shorter than k is padded with (-inf, -1).
+ *   - A context is read-only after gem_create: several host threads may share it.
+ */
+#ifndef GEM_H_
+#define GEM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* hipStream_t;   /* the HIP runtime's stream handle */
+
+typedef enum {
+  GEM_OK = 0,
+  GEM_ERR_INVALID = 1,       /* bad argument (null pointer, size, dtype, k, ...) */
+  GEM_ERR_WORKSPACE = 2,     /* workspace smaller than gem_workspace_bytes() */
+  GEM_ERR_UNSUPPORTED = 3,   /* valid request outside this build's limits (dim, set length) */
+  GEM_ERR_HIP = 4,           /* a HIP runtime call or kernel launch failed */
+  GEM_ERR_DEVICE_CHECK = 5   /* a validation kernel found bad device data */
+} gem_status;
+
+typedef enum {
+  GEM_F32 = 0,               /* float32 rows, 512 bytes per 128-d vector */
+  GEM_BF16 = 1,              /* bfloat16 rows (uint16 bit patterns), 256 bytes */
+  GEM_FP8_E4M3 = 2           /* OCP E4M3 codes (uint8), 128 bytes, plus a float32 scale */
+} gem_dtype;
+
+typedef enum {
+  GEM_OP_SCORE_EXACT = 0,
+  GEM_OP_SCORE_QUANT = 1,
+  GEM_OP_TOPK = 2,
+  GEM_OP_EXPAND = 3
+} gem_op;
+
+/* Largest query set (rows) a scoring call accepts. */
+#define GEM_MAX_QUERY_LEN 256
+/* Largest k (top-k) and ef (beam width). */
+#define GEM_MAX_K 1024
+/* Vector dimension. */
+#define GEM_DIM 128
+
+typedef struct gem_ctx_s* gem_ctx;
+
+/* A ragged batch of vector sets in CSR form.
+ *   set i = rows offsets[i] .. offsets[i+1]-1 of `vecs` (absolute row indices,
+ *   so a view of sets a..b of a larger batch is {offsets + a, n_sets = b - a}).
+ *   vecs: [n_vecs][dim] row-major, element type `dtype`.
+ *   scales: FP8 only, [n_vecs] float32; row r's values are scales[r] * decode(code).
+ *           Scales must be powers of two (gem_quantize_fp8 writes such scales).
+ *   max_set_len: host-side upper bound of the set lengths (needed for query sets).
+ */
+typedef struct {
+  int32_t dtype;               /* gem_dtype */
+  int32_t dim;                 /* must be GEM_DIM */
+  int64_t n_sets;
+  int64_t n_vecs;              /* rows addressable in vecs (>= every offset) */
+  int32_t max_set_len;
+  int32_t reserved;
+  const int64_t* offsets;      /* [device] [n_sets + 1] */
+  const void* vecs;            /* [device] */
+  const float* scales;         /* [device] FP8 only, else NULL */
+} gem_sets;
+
+/* Candidate-id lists, one per query set.
+ *   list i = entries offsets[i] .. offsets[i+1]-1 of `ids` (offsets[0] may be > 0;
+ *   outputs are indexed by the absolute entry index). If offsets is NULL, list i
+ *   is entries i*stride .. i*stride + stride - 1.
+ *   An id < 0 is padding: it scores -inf and never enters a top-k or a beam.
+ *   n_entries: host-side size of `ids` (and of a per-entry score output).
+ */
+typedef struct {
+  int64_t n_lists;             /* must equal the query batch's n_sets */
+  int64_t n_entries;
+  int32_t stride;              /* list length when offsets == NULL */
+  int32_t max_list_len;        /* host-side upper bound of list lengths (0 = unknown) */
+  const int64_t* offsets;      /* [device] [n_lists + 1] or NULL */
+  const int32_t* ids;          /* [device] [n_entries] */
+} gem_cands;
+
+/* Bounded per-query result set R of Alg. 5: [n_queries][ef] (score, id), ordered
+ * by score descending then id ascending, padded with (-inf, -1). */
+typedef struct {
+  int32_t ef;
+  int32_t reserved;
+  float* scores;               /* [device] [n_queries * ef] */
+  int32_t* ids;                /* [device] [n_queries * ef] */
+} gem_beam;
+
+/* Create a context bound to HIP device `device`. Reads device properties once. */
+gem_status gem_create(gem_ctx* out, int device);
+gem_status gem_destroy(gem_ctx ctx);
+/* Static string naming a status code. */
+const char* gem_status_string(gem_status s);
+/* Message of the last failing call made on this host thread ("" if none). */
+const char* gem_last_error(void);
+/* Library version string. */
+const char* gem_version(void);
+
+/* Workspace bytes that the matching call needs for these arguments (0 if none).
+ * For GEM_OP_SCORE_*: `compute` is the gem_dtype the scoring runs in, and
+ * `scores_given` says whether the caller passes its own dense/entry score
+ * buffer (if not and k > 0, the scores are staged in the workspace). */
+size_t gem_workspace_bytes(gem_ctx ctx, int32_t op, const gem_sets* Q, const gem_sets* D,
+                           const gem_cands* C, int32_t compute, int32_t k, int32_t scores_given);
+
+/* float32 rows -> bfloat16 rows, round to nearest even (corpus / query conversion).
+ *   x: [device] [n_rows * dim] float32; out: [device] [n_rows * dim] uint16. */
+gem_status gem_convert_bf16(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim,
+                            uint16_t* out, hipStream_t stream);
+
+/* float32 rows -> OCP FP8 E4M3 codes + one power-of-two scale per row.
+ *   scale = smallest 2^e (e clamped to [-126, 127]) with max|x| <= 448 * 2^e
+ *   (1 for an all-zero row); code = E4M3(x / scale), round to nearest, ties to
+ *   even, saturating at 448. out: [device] [n_rows * dim] uint8;
+ *   scales: [device] [n_rows] float32. */
+gem_status gem_quantize_fp8(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim,
+                            uint8_t* out, float* scales, hipStream_t stream);
+
+/* Exact Chamfer scores CH(Q_i, D_j) (Def. 1).
+ *   compute = GEM_F32 or GEM_BF16: the operand type of the products; D->dtype must
+ *   equal it. Q->dtype may equal it, or be GEM_F32 when compute is GEM_BF16 (Q is
+ *   then converted into the workspace).
+ *   C == NULL: every query against every document. Score (i, j) is written to
+ *     scores[row(i) * ld_scores + j], row(i) = score_rows ? score_rows[i] : i,
+ *     ld_scores >= D->n_sets (0 means D->n_sets).
+ *   C != NULL: scores[e] = CH(Q_i, D_ids[e]) for each entry e of list i (the
+ *     exact rerank of a shortlist, Alg. 5 final step).
+ *   k > 0: per-query top-k of those scores into top_scores / top_ids [n_q][k]
+ *     (ids are document indices of D). `scores` may then be NULL (staged in ws).
+ *   k == 0: scores only.
+ *   Limits: Q->max_set_len <= GEM_MAX_QUERY_LEN, k <= GEM_MAX_K.
+ */
+gem_status gem_score_exact(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C,
+                           int32_t compute, int32_t k,
+                           float* scores, int64_t ld_scores, const int32_t* score_rows,
+                           float* top_scores, int32_t* top_ids,
+                           void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Quantized estimate: the same outputs as gem_score_exact, computed on FP8 E4M3
+ * operands with their per-vector scales (products and float32 accumulation
+ * of s_q * s_p * <code_q, code_p>). D->dtype must be GEM_FP8_E4M3. Q is either
+ * GEM_FP8_E4M3 with scales, or GEM_F32 and is quantized into the workspace by
+ * the rule of gem_quantize_fp8. */
+gem_status gem_score_quant(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C,
+                           int32_t k,
+                           float* scores, int64_t ld_scores, const int32_t* score_rows,
+                           float* top_scores, int32_t* top_ids,
+                           void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Segmented top-k (the k-argmax of Sec. 3.1 applied per segment).
+ *   seg_offsets != NULL: segment i = scores[seg_offsets[i] .. seg_offsets[i+1]-1],
+ *     ids from seg_ids (NULL: position within the segment). Entries with a
+ *     negative id are skipped. A repeated id keeps its best entry.
+ *   seg_offsets == NULL: segment i = scores[r * seg_ld .. r * seg_ld + seg_len - 1]
+ *     with r = seg_rows ? seg_rows[i] : i; ids are positions; seg_ids must be NULL.
+ *   Outputs [n_segs][k]. k <= GEM_MAX_K. */
+gem_status gem_topk(gem_ctx ctx, const float* scores, const int64_t* seg_offsets,
+                    const int32_t* seg_ids, int64_t n_segs, int64_t seg_len, int64_t seg_ld,
+                    const int32_t* seg_rows, int32_t k, float* top_scores, int32_t* top_ids,
+                    void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* One batched beam-expansion step (Alg. 5 neighbour loop, all queries at once):
+ * estimate CH(Q_i, D_id) with FP8 operands for every entry of list i, then
+ * replace beam row i by the best ef of (beam row i) U (scored entries), ids
+ * distinct (a repeated id keeps its best entry). D8->dtype must be
+ * GEM_FP8_E4M3; Q8 is GEM_FP8_E4M3 or GEM_F32 (quantized into ws). If
+ * cand_scores is not NULL the step's entry scores are also written there
+ * ([C->n_entries]). The beam is updated in place. */
+gem_status gem_expand_batch(gem_ctx ctx, const gem_sets* Q8, const gem_sets* D8, const gem_cands* C,
+                            gem_beam* beam, float* cand_scores,
+                            void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* The merge half of gem_expand_batch on scores the caller already has:
+ * beam row i becomes the best ef of (beam row i) U {(cand_scores[e], ids[e]) :
+ * e in list i}, ids distinct (a repeated id keeps its best entry), padding ids
+ * skipped. cand_scores: [device] [C->n_entries]. */
+gem_status gem_beam_merge(gem_ctx ctx, const float* cand_scores, const gem_cands* C, gem_beam* beam,
+                          hipStream_t stream);
+
+/* Fill a beam with its padding (-inf, -1): an empty R before the first step. */
+gem_status gem_beam_reset(gem_ctx ctx, gem_beam* beam, int64_t n_queries, hipStream_t stream);
+
+/* On-demand validation of device data. Checks that offsets are non-decreasing,
+ * inside [0, n_vecs] and (FP8) scales are positive powers of two; for candidate
+ * lists, that offsets are non-decreasing inside [0, n_entries] and ids < n_sets.
+ * Synchronizes `stream`; returns GEM_ERR_DEVICE_CHECK on a violation. */
+gem_status gem_validate_sets(gem_ctx ctx, const gem_sets* S, hipStream_t stream);
+gem_status gem_validate_cands(gem_ctx ctx, const gem_cands* C, int64_t n_sets, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEM_H_ */

@@ -1,0 +1,309 @@
+"""MI355X (gfx950) set-to-set scoring for multi-vector retrieval (GEM, arXiv 2603.20336).
+
+Thin Python binding of libgem.so (C ABI in include/gem.h). Every step of the
+scoring path runs in the library's HIP kernels; this module only marshals
+torch tensors (device memory) and the current torch stream into the C calls,
+and allocates outputs and workspaces with torch's allocator.
+
+    Q = Sets.from_batch(queries, device)                # float32 CSR sets
+    D = Sets.from_batch(corpus, device).to_bf16()       # corpus conversion, once
+    top_s, top_i = score_exact(Q, D, k=100, compute="bf16")
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _abi
+from ._abi import (GEM_BF16, GEM_F32, GEM_FP8_E4M3, GEM_MAX_K, GEM_MAX_QUERY_LEN, GemError)
+
+__all__ = ["Sets", "Cands", "Beam", "GemError", "convert_bf16", "quantize_fp8", "score_exact",
+           "score_quant", "topk", "expand_batch", "beam_merge", "beam_reset", "validate_sets", "validate_cands",
+           "library", "GEM_F32", "GEM_BF16", "GEM_FP8_E4M3", "GEM_MAX_K", "GEM_MAX_QUERY_LEN"]
+
+_DTYPES = {"f32": GEM_F32, "bf16": GEM_BF16, "fp8": GEM_FP8_E4M3,
+           GEM_F32: GEM_F32, GEM_BF16: GEM_BF16, GEM_FP8_E4M3: GEM_FP8_E4M3}
+_ROW_TORCH = {GEM_F32: torch.float32, GEM_BF16: torch.uint16, GEM_FP8_E4M3: torch.uint8}
+
+
+def library():
+    """The loaded libgem.so (raises ImportError if it was not built)."""
+    return _abi.load()
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class _Context:
+    def __init__(self, device: int):
+        lib = library()
+        h = ctypes.c_void_p()
+        _abi.check(lib.gem_create(ctypes.byref(h), device))
+        self.handle = h
+        self.device = device
+
+
+_contexts: dict = {}
+
+
+def _ctx(device: torch.device) -> ctypes.c_void_p:
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    c = _contexts.get(idx)
+    if c is None:
+        c = _contexts[idx] = _Context(idx)
+    return c.handle
+
+
+class Sets:
+    """A ragged batch of 128-d vector sets on the device (CSR).
+
+    vecs: [n_vecs, 128] float32 / uint16 (bf16 bits) / uint8 (E4M3 codes)
+    offsets: [n_sets + 1] int64 absolute row indices
+    scales: FP8 only, [n_vecs] float32 powers of two
+    max_len: host-side bound of the set lengths
+    """
+
+    def __init__(self, vecs: torch.Tensor, offsets: torch.Tensor, dtype, max_len: int,
+                 scales: Optional[torch.Tensor] = None, n_sets: Optional[int] = None):
+        self.dtype = _DTYPES[dtype]
+        if vecs.dtype != _ROW_TORCH[self.dtype]:
+            raise TypeError(f"vecs dtype {vecs.dtype} does not match gem dtype {self.dtype}")
+        if vecs.dim() != 2 or vecs.shape[1] != _abi.GEM_DIM or not vecs.is_contiguous():
+            raise ValueError("vecs must be a contiguous [n, 128] tensor")
+        if offsets.dtype != torch.int64 or not offsets.is_contiguous():
+            raise TypeError("offsets must be contiguous int64")
+        self.vecs, self.offsets, self.scales = vecs, offsets, scales
+        self.max_len = int(max_len)
+        self.n_sets = int(offsets.numel() - 1) if n_sets is None else int(n_sets)
+
+    @property
+    def device(self) -> torch.device:
+        return self.vecs.device
+
+    @property
+    def n_vecs(self) -> int:
+        return int(self.vecs.shape[0])
+
+    @classmethod
+    def from_batch(cls, batch, device="cuda") -> "Sets":
+        """float32 Sets from a workloads.SetBatch (host or device)."""
+        vecs = batch.vecs.to(device=device, dtype=torch.float32).contiguous()
+        off = batch.offsets.to(device=device, dtype=torch.int64).contiguous()
+        return cls(vecs, off, GEM_F32, batch.max_len())
+
+    def struct(self) -> _abi.gem_sets:
+        s = _abi.gem_sets()
+        s.dtype, s.dim, s.n_sets, s.n_vecs = self.dtype, _abi.GEM_DIM, self.n_sets, self.n_vecs
+        s.max_set_len, s.reserved = self.max_len, 0
+        s.offsets, s.vecs, s.scales = _ptr(self.offsets), _ptr(self.vecs), _ptr(self.scales)
+        return s
+
+    def view(self, a: int, b: int) -> "Sets":
+        """Sets a..b-1 as a batch of their own (no copy; ids become relative to a)."""
+        return Sets(self.vecs, self.offsets[a:b + 1], self.dtype, self.max_len, self.scales)
+
+    def to_bf16(self, stream=None) -> "Sets":
+        return convert_bf16(self, stream)
+
+    def to_fp8(self, stream=None) -> "Sets":
+        return quantize_fp8(self, stream)
+
+
+class Cands:
+    """Candidate-id lists, one per query: CSR (offsets) or fixed-length rows (stride)."""
+
+    def __init__(self, ids: torch.Tensor, offsets: Optional[torch.Tensor] = None, stride: int = 0,
+                 max_list_len: Optional[int] = None, n_lists: Optional[int] = None):
+        if ids.dtype != torch.int32 or not ids.is_contiguous():
+            raise TypeError("ids must be contiguous int32")
+        self.ids, self.offsets, self.stride = ids, offsets, int(stride)
+        if offsets is not None:
+            self.n_lists = int(offsets.numel() - 1)
+            self.max_list_len = int(max_list_len) if max_list_len is not None else \
+                int((offsets[1:] - offsets[:-1]).max().item()) if self.n_lists else 0
+        else:
+            self.n_lists = int(n_lists) if n_lists is not None else (ids.numel() // max(self.stride, 1))
+            self.max_list_len = self.stride
+
+    def struct(self) -> _abi.gem_cands:
+        c = _abi.gem_cands()
+        c.n_lists, c.n_entries = self.n_lists, int(self.ids.numel())
+        c.stride, c.max_list_len = self.stride, self.max_list_len
+        c.offsets, c.ids = _ptr(self.offsets), _ptr(self.ids)
+        return c
+
+
+class Beam:
+    """The bounded per-query result set R (Alg. 5): [n_queries, ef] scores and ids."""
+
+    def __init__(self, n_queries: int, ef: int, device="cuda", stream=None):
+        self.ef = int(ef)
+        self.scores = torch.empty(n_queries, ef, dtype=torch.float32, device=device)
+        self.ids = torch.empty(n_queries, ef, dtype=torch.int32, device=device)
+        self.reset(stream)
+
+    @property
+    def n_queries(self) -> int:
+        return int(self.scores.shape[0])
+
+    def struct(self) -> _abi.gem_beam:
+        b = _abi.gem_beam()
+        b.ef, b.reserved, b.scores, b.ids = self.ef, 0, _ptr(self.scores), _ptr(self.ids)
+        return b
+
+    def reset(self, stream=None) -> None:
+        beam_reset(self, stream)
+
+
+def _ws(n: int, device) -> Optional[torch.Tensor]:
+    return torch.empty(n, dtype=torch.uint8, device=device) if n > 0 else None
+
+
+def convert_bf16(S: Sets, stream=None) -> Sets:
+    """float32 sets -> bfloat16 sets (round to nearest even)."""
+    if S.dtype != GEM_F32:
+        raise TypeError("convert_bf16 takes float32 sets")
+    out = torch.empty(S.n_vecs, _abi.GEM_DIM, dtype=torch.uint16, device=S.device)
+    _abi.check(library().gem_convert_bf16(_ctx(S.device), _ptr(S.vecs), S.n_vecs, _abi.GEM_DIM,
+                                          _ptr(out), _stream(stream)))
+    return Sets(out, S.offsets, GEM_BF16, S.max_len, n_sets=S.n_sets)
+
+
+def quantize_fp8(S: Sets, stream=None) -> Sets:
+    """float32 sets -> E4M3 codes + one power-of-two scale per vector."""
+    if S.dtype != GEM_F32:
+        raise TypeError("quantize_fp8 takes float32 sets")
+    out = torch.empty(S.n_vecs, _abi.GEM_DIM, dtype=torch.uint8, device=S.device)
+    sc = torch.empty(S.n_vecs, dtype=torch.float32, device=S.device)
+    _abi.check(library().gem_quantize_fp8(_ctx(S.device), _ptr(S.vecs), S.n_vecs, _abi.GEM_DIM,
+                                          _ptr(out), _ptr(sc), _stream(stream)))
+    return Sets(out, S.offsets, GEM_FP8_E4M3, S.max_len, scales=sc, n_sets=S.n_sets)
+
+
+def _score(fn_exact: bool, Q: Sets, D: Sets, cands: Optional[Cands], k: int, compute: int,
+           scores: Optional[torch.Tensor], ld: int, rows: Optional[torch.Tensor], want_scores: bool,
+           stream, ws: Optional[torch.Tensor]):
+    lib = library()
+    dev = D.device
+    qs, ds = Q.struct(), D.struct()
+    cs = cands.struct() if cands is not None else None
+    pc = ctypes.byref(cs) if cs is not None else None
+    if scores is None and (want_scores or k == 0):
+        n = cands.ids.numel() if cands is not None else Q.n_sets * D.n_sets
+        shape = (n,) if cands is not None else (Q.n_sets, D.n_sets)
+        scores = torch.empty(shape, dtype=torch.float32, device=dev)
+    op = _abi.GEM_OP_SCORE_EXACT if fn_exact else _abi.GEM_OP_SCORE_QUANT
+    need = lib.gem_workspace_bytes(_ctx(dev), op, ctypes.byref(qs), ctypes.byref(ds), pc, compute, k,
+                                   int(scores is not None))
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    top_s = torch.empty(Q.n_sets, k, dtype=torch.float32, device=dev) if k > 0 else None
+    top_i = torch.empty(Q.n_sets, k, dtype=torch.int32, device=dev) if k > 0 else None
+    args = (ctypes.byref(qs), ctypes.byref(ds), pc)
+    tail = (_ptr(scores), int(ld), _ptr(rows), _ptr(top_s), _ptr(top_i), _ptr(ws),
+            0 if ws is None else ws.numel(), _stream(stream))
+    if fn_exact:
+        st = lib.gem_score_exact(_ctx(dev), *args, compute, k, *tail)
+    else:
+        st = lib.gem_score_quant(_ctx(dev), *args, k, *tail)
+    _abi.check(st)
+    if k == 0:
+        return scores
+    return (top_s, top_i, scores) if want_scores else (top_s, top_i)
+
+
+def score_exact(Q: Sets, D: Sets, cands: Optional[Cands] = None, k: int = 0, compute="f32",
+                scores: Optional[torch.Tensor] = None, ld: int = 0, rows: Optional[torch.Tensor] = None,
+                want_scores: bool = False, stream=None, ws: Optional[torch.Tensor] = None):
+    """Exact Chamfer scores (Def. 1) in float32 or bf16 operands.
+
+    cands None: every query against every document -> [n_q, n_docs] (or into
+    `scores` with row stride `ld` and optional row map `rows`). With cands:
+    one score per candidate entry. k > 0 returns (top_scores, top_ids) (and
+    the scores when want_scores)."""
+    return _score(True, Q, D, cands, k, _DTYPES[compute], scores, ld, rows, want_scores, stream, ws)
+
+
+def score_quant(Q: Sets, D8: Sets, cands: Optional[Cands] = None, k: int = 0,
+                scores: Optional[torch.Tensor] = None, ld: int = 0, rows: Optional[torch.Tensor] = None,
+                want_scores: bool = False, stream=None, ws: Optional[torch.Tensor] = None):
+    """Quantized estimate on FP8 E4M3 operands (same conventions as score_exact)."""
+    return _score(False, Q, D8, cands, k, GEM_FP8_E4M3, scores, ld, rows, want_scores, stream, ws)
+
+
+def topk(scores: torch.Tensor, k: int, seg_offsets: Optional[torch.Tensor] = None,
+         seg_ids: Optional[torch.Tensor] = None, seg_rows: Optional[torch.Tensor] = None,
+         n_segs: Optional[int] = None, seg_len: Optional[int] = None, seg_ld: int = 0, stream=None):
+    """Segmented top-k: CSR segments (seg_offsets [+ seg_ids]) or the rows of a
+    [n, L] matrix (optionally the rows listed in seg_rows). Returns (scores, ids) [n_segs, k]."""
+    lib = library()
+    dev = scores.device
+    if seg_offsets is not None:
+        n = seg_offsets.numel() - 1
+        L, ld = 0, 0
+    else:
+        if scores.dim() == 2:
+            L = scores.shape[1] if seg_len is None else seg_len
+            ld = seg_ld or scores.stride(0)
+            n = (seg_rows.numel() if seg_rows is not None else scores.shape[0]) if n_segs is None else n_segs
+        else:
+            L, ld = int(seg_len), int(seg_ld or seg_len)
+            n = int(n_segs)
+    top_s = torch.empty(n, k, dtype=torch.float32, device=dev)
+    top_i = torch.empty(n, k, dtype=torch.int32, device=dev)
+    _abi.check(lib.gem_topk(_ctx(dev), _ptr(scores), _ptr(seg_offsets), _ptr(seg_ids), n, L, ld,
+                            _ptr(seg_rows), k, _ptr(top_s), _ptr(top_i), None, 0, _stream(stream)))
+    return top_s, top_i
+
+
+def expand_batch(Q8: Sets, D8: Sets, cands: Cands, beam: Beam, cand_scores: Optional[torch.Tensor] = None,
+                 stream=None, ws: Optional[torch.Tensor] = None) -> None:
+    """One beam-expansion step: FP8-estimate every candidate and merge it into the beam in place."""
+    lib = library()
+    dev = D8.device
+    qs, ds, cs, bs = Q8.struct(), D8.struct(), cands.struct(), beam.struct()
+    need = lib.gem_workspace_bytes(_ctx(dev), _abi.GEM_OP_EXPAND, ctypes.byref(qs), ctypes.byref(ds),
+                                   ctypes.byref(cs), GEM_FP8_E4M3, 1, int(cand_scores is not None))
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    _abi.check(lib.gem_expand_batch(_ctx(dev), ctypes.byref(qs), ctypes.byref(ds), ctypes.byref(cs),
+                                    ctypes.byref(bs), _ptr(cand_scores), _ptr(ws),
+                                    0 if ws is None else ws.numel(), _stream(stream)))
+
+
+def beam_merge(cand_scores: torch.Tensor, cands: Cands, beam: Beam, stream=None) -> None:
+    """Merge already-scored candidates into the beam in place (top-ef, ids distinct)."""
+    cs, bs = cands.struct(), beam.struct()
+    _abi.check(library().gem_beam_merge(_ctx(beam.scores.device), _ptr(cand_scores), ctypes.byref(cs),
+                                        ctypes.byref(bs), _stream(stream)))
+
+
+def expand_workspace_bytes(Q8: Sets, D8: Sets, cands: Cands, with_cand_scores: bool) -> int:
+    qs, ds, cs = Q8.struct(), D8.struct(), cands.struct()
+    return int(library().gem_workspace_bytes(_ctx(D8.device), _abi.GEM_OP_EXPAND, ctypes.byref(qs),
+                                             ctypes.byref(ds), ctypes.byref(cs), GEM_FP8_E4M3, 1,
+                                             int(with_cand_scores)))
+
+
+def beam_reset(beam: Beam, stream=None) -> None:
+    b = beam.struct()
+    _abi.check(library().gem_beam_reset(_ctx(beam.scores.device), ctypes.byref(b), beam.n_queries,
+                                        _stream(stream)))
+
+
+def validate_sets(S: Sets, stream=None) -> None:
+    s = S.struct()
+    _abi.check(library().gem_validate_sets(_ctx(S.device), ctypes.byref(s), _stream(stream)))
+
+
+def validate_cands(C: Cands, n_sets: int, stream=None) -> None:
+    c = C.struct()
+    _abi.check(library().gem_validate_cands(_ctx(C.ids.device), ctypes.byref(c), int(n_sets), _stream(stream)))

@@ -1,0 +1,102 @@
+"""ctypes declarations of the C ABI in include/gem.h, and the library loader.
+
+torch is imported before the library is loaded so that the process has a
+single HIP runtime: libgem.so then binds to the libamdhip64 torch already
+loaded, and torch's streams and device pointers are valid in its calls.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (must come before the library is loaded)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgem.so")
+
+GEM_OK, GEM_ERR_INVALID, GEM_ERR_WORKSPACE, GEM_ERR_UNSUPPORTED, GEM_ERR_HIP, GEM_ERR_DEVICE_CHECK = range(6)
+GEM_F32, GEM_BF16, GEM_FP8_E4M3 = 0, 1, 2
+GEM_OP_SCORE_EXACT, GEM_OP_SCORE_QUANT, GEM_OP_TOPK, GEM_OP_EXPAND = 0, 1, 2, 3
+GEM_MAX_QUERY_LEN = 256
+GEM_MAX_K = 1024
+GEM_DIM = 128
+BEAM_MAX_ENTRIES = 4096
+
+# every function the header declares, with (restype, argtypes)
+c_p = ctypes.c_void_p
+i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+
+
+class gem_sets(ctypes.Structure):
+    _fields_ = [("dtype", i32), ("dim", i32), ("n_sets", i64), ("n_vecs", i64),
+                ("max_set_len", i32), ("reserved", i32),
+                ("offsets", c_p), ("vecs", c_p), ("scales", c_p)]
+
+
+class gem_cands(ctypes.Structure):
+    _fields_ = [("n_lists", i64), ("n_entries", i64), ("stride", i32), ("max_list_len", i32),
+                ("offsets", c_p), ("ids", c_p)]
+
+
+class gem_beam(ctypes.Structure):
+    _fields_ = [("ef", i32), ("reserved", i32), ("scores", c_p), ("ids", c_p)]
+
+
+P_SETS = ctypes.POINTER(gem_sets)
+P_CANDS = ctypes.POINTER(gem_cands)
+P_BEAM = ctypes.POINTER(gem_beam)
+
+SIGNATURES = {
+    "gem_create": (i32, [ctypes.POINTER(c_p), ctypes.c_int]),
+    "gem_destroy": (i32, [c_p]),
+    "gem_status_string": (ctypes.c_char_p, [i32]),
+    "gem_last_error": (ctypes.c_char_p, []),
+    "gem_version": (ctypes.c_char_p, []),
+    "gem_workspace_bytes": (sz, [c_p, i32, P_SETS, P_SETS, P_CANDS, i32, i32, i32]),
+    "gem_convert_bf16": (i32, [c_p, c_p, i64, i32, c_p, c_p]),
+    "gem_quantize_fp8": (i32, [c_p, c_p, i64, i32, c_p, c_p, c_p]),
+    "gem_score_exact": (i32, [c_p, P_SETS, P_SETS, P_CANDS, i32, i32, c_p, i64, c_p, c_p, c_p, c_p, sz, c_p]),
+    "gem_score_quant": (i32, [c_p, P_SETS, P_SETS, P_CANDS, i32, c_p, i64, c_p, c_p, c_p, c_p, sz, c_p]),
+    "gem_topk": (i32, [c_p, c_p, c_p, c_p, i64, i64, i64, c_p, i32, c_p, c_p, c_p, sz, c_p]),
+    "gem_expand_batch": (i32, [c_p, P_SETS, P_SETS, P_CANDS, P_BEAM, c_p, c_p, sz, c_p]),
+    "gem_beam_merge": (i32, [c_p, c_p, P_CANDS, P_BEAM, c_p]),
+    "gem_beam_reset": (i32, [c_p, P_BEAM, i64, c_p]),
+    "gem_validate_sets": (i32, [c_p, P_SETS, c_p]),
+    "gem_validate_cands": (i32, [c_p, P_CANDS, i64, c_p]),
+}
+
+_lib = None
+
+
+class GemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{status_name(status)}: {msg}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libgem.so (built by paper_2603_20336_amd.build); fails loudly if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2603_20336_amd.build` "
+                          "(the scoring path has no fallback)")
+    lib = ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_name(status: int) -> str:
+    return ["GEM_OK", "GEM_ERR_INVALID", "GEM_ERR_WORKSPACE", "GEM_ERR_UNSUPPORTED",
+            "GEM_ERR_HIP", "GEM_ERR_DEVICE_CHECK"][status] if 0 <= status <= 5 else f"status {status}"
+
+
+def check(status: int) -> None:
+    if status != GEM_OK:
+        msg = load().gem_last_error()
+        raise GemError(status, msg.decode() if msg else "")

@@ -1,0 +1,485 @@
+// C ABI of the scoring library (declared in include/gem.h): argument checks,
+// workspace layout and the kernel sequence of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "gem_internal.h"
+
+using namespace gem;
+
+struct gem_ctx_s {
+  int device;
+  int n_cu;
+  char arch[64];
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gem_status fail(gem_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+gem_status fail(gem_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+gem_status hip_fail(hipError_t e, const char* what) {
+  return fail(GEM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int row_bytes(int dtype) {
+  switch (dtype) {
+    case GEM_F32: return 4 * GEM_DIM;
+    case GEM_BF16: return 2 * GEM_DIM;
+    case GEM_FP8_E4M3: return GEM_DIM;
+    default: return 0;
+  }
+}
+
+bool valid_dtype(int32_t d) { return d == GEM_F32 || d == GEM_BF16 || d == GEM_FP8_E4M3; }
+
+gem_status check_sets(const gem_sets* S, const char* name, bool need_max_len) {
+  if (!S) return fail(GEM_ERR_INVALID, "%s is NULL", name);
+  if (!valid_dtype(S->dtype)) return fail(GEM_ERR_INVALID, "%s: unknown dtype %d", name, S->dtype);
+  if (S->dim != GEM_DIM) return fail(GEM_ERR_UNSUPPORTED, "%s: dim %d (only %d is supported)", name, S->dim, GEM_DIM);
+  if (S->n_sets < 0 || S->n_vecs < 0) return fail(GEM_ERR_INVALID, "%s: negative size", name);
+  if (S->n_sets > INT32_MAX - 1) return fail(GEM_ERR_UNSUPPORTED, "%s: more than 2^31-2 sets", name);
+  if (S->n_sets > 0 && !S->offsets) return fail(GEM_ERR_INVALID, "%s: offsets is NULL", name);
+  if (S->n_vecs > 0 && !S->vecs) return fail(GEM_ERR_INVALID, "%s: vecs is NULL", name);
+  if (S->dtype == GEM_FP8_E4M3 && S->n_vecs > 0 && !S->scales)
+    return fail(GEM_ERR_INVALID, "%s: FP8 sets need scales", name);
+  if (S->max_set_len < 0) return fail(GEM_ERR_INVALID, "%s: negative max_set_len", name);
+  if (need_max_len && S->max_set_len > GEM_MAX_QUERY_LEN)
+    return fail(GEM_ERR_UNSUPPORTED, "%s: max_set_len %d exceeds %d", name, S->max_set_len, GEM_MAX_QUERY_LEN);
+  if (need_max_len && S->n_vecs > 0 && S->max_set_len == 0 && S->n_sets > 0)
+    return fail(GEM_ERR_INVALID, "%s: max_set_len must bound the set lengths", name);
+  return GEM_OK;
+}
+
+gem_status check_cands(const gem_cands* C, int64_t n_q) {
+  if (C->n_lists != n_q) return fail(GEM_ERR_INVALID, "cands: n_lists %lld != number of query sets %lld",
+                                     (long long)C->n_lists, (long long)n_q);
+  if (C->n_entries < 0) return fail(GEM_ERR_INVALID, "cands: negative n_entries");
+  if (C->n_entries > 0 && !C->ids) return fail(GEM_ERR_INVALID, "cands: ids is NULL");
+  if (C->offsets) {
+    if (C->n_entries > 0 && C->max_list_len <= 0)
+      return fail(GEM_ERR_INVALID, "cands: max_list_len must bound the list lengths");
+  } else {
+    if (C->stride < 0) return fail(GEM_ERR_INVALID, "cands: negative stride");
+    if ((int64_t)C->stride * n_q > C->n_entries)
+      return fail(GEM_ERR_INVALID, "cands: n_lists * stride exceeds n_entries");
+  }
+  return GEM_OK;
+}
+
+int32_t list_len_bound(const gem_cands* C) { return C->offsets ? C->max_list_len : C->stride; }
+
+SetsView view(const gem_sets* S) {
+  SetsView v;
+  v.off = S->offsets; v.vecs = S->vecs; v.scales = S->scales; v.n_sets = S->n_sets;
+  return v;
+}
+
+CandsView cview(const gem_cands* C) {
+  CandsView v;
+  v.off = C->offsets; v.ids = C->ids; v.n_lists = C->n_lists; v.stride = C->stride;
+  return v;
+}
+
+// Workspace layout of a scoring call.
+struct ScoreLayout {
+  size_t q_conv = 0, q_scales = 0, qb = 0, staged = 0, total = 0;
+  int64_t n_blocks_max = 0;
+  int block_rows = 0;
+};
+
+ScoreLayout score_layout(const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t compute, int32_t k,
+                         bool scores_given) {
+  ScoreLayout L;
+  size_t off = 0;
+  if (Q->dtype != compute) {
+    L.q_conv = off;
+    off = align_up(off + (size_t)Q->n_vecs * row_bytes(compute));
+    if (compute == GEM_FP8_E4M3) {
+      L.q_scales = off;
+      off = align_up(off + (size_t)Q->n_vecs * 4);
+    }
+  }
+  if (!C) {
+    L.block_rows = dense_block_rows(compute, Q->max_set_len);
+    L.n_blocks_max = dense_blocks_upper(Q->n_sets, Q->n_vecs, L.block_rows, Q->max_set_len);
+    L.qb = off;
+    off = align_up(off + (size_t)(L.n_blocks_max + 1) * 4);
+    if (k > 0 && !scores_given) {
+      L.staged = off;
+      off = align_up(off + (size_t)Q->n_sets * (size_t)D->n_sets * 4);
+    }
+  } else if (k > 0 && !scores_given) {
+    L.staged = off;
+    off = align_up(off + (size_t)C->n_entries * 4);
+  }
+  L.total = off;
+  return L;
+}
+
+char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+gem_status convert_query(const gem_sets* Q, int32_t compute, void* ws, const ScoreLayout& L, gem_sets* Qc,
+                         hipStream_t stream) {
+  *Qc = *Q;
+  if (Q->dtype == compute) return GEM_OK;
+  if (Q->dtype != GEM_F32) return fail(GEM_ERR_INVALID, "Q: dtype must be F32 or the compute dtype");
+  hipError_t e;
+  if (compute == GEM_BF16) {
+    e = launch_convert_bf16(static_cast<const float*>(Q->vecs), Q->n_vecs * GEM_DIM,
+                            reinterpret_cast<uint16_t*>(at(ws, L.q_conv)), stream);
+  } else {
+    e = launch_quantize_fp8(static_cast<const float*>(Q->vecs), Q->n_vecs, reinterpret_cast<uint8_t*>(at(ws, L.q_conv)),
+                            reinterpret_cast<float*>(at(ws, L.q_scales)), stream);
+    Qc->scales = reinterpret_cast<const float*>(at(ws, L.q_scales));
+  }
+  if (e != hipSuccess) return hip_fail(e, "query conversion");
+  Qc->dtype = compute;
+  Qc->vecs = at(ws, L.q_conv);
+  return GEM_OK;
+}
+
+gem_status score_common(const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t compute, int32_t k,
+                        float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,
+                        int32_t* top_ids, void* ws, size_t ws_bytes, hipStream_t stream) {
+  gem_status st;
+  if ((st = check_sets(Q, "Q", true)) != GEM_OK) return st;
+  if ((st = check_sets(D, "D", false)) != GEM_OK) return st;
+  if (D->dtype != compute) return fail(GEM_ERR_INVALID, "D: dtype %d does not match the compute dtype %d", D->dtype, compute);
+  if (Q->dtype != compute && Q->dtype != GEM_F32)
+    return fail(GEM_ERR_INVALID, "Q: dtype must be F32 or the compute dtype");
+  if (k < 0 || k > GEM_MAX_K) return fail(GEM_ERR_INVALID, "k = %d outside [0, %d]", k, GEM_MAX_K);
+  if (k > 0 && (!top_scores || !top_ids)) return fail(GEM_ERR_INVALID, "k > 0 needs top_scores and top_ids");
+  if (k == 0 && !scores) return fail(GEM_ERR_INVALID, "k == 0 needs a scores buffer");
+  if (C && (st = check_cands(C, Q->n_sets)) != GEM_OK) return st;
+  if (!C) {
+    if (ld_scores == 0) ld_scores = D->n_sets;
+    if (ld_scores < D->n_sets) return fail(GEM_ERR_INVALID, "ld_scores %lld < number of documents",
+                                           (long long)ld_scores);
+  }
+  const ScoreLayout L = score_layout(Q, D, C, compute, k, scores != nullptr);
+  if (ws_bytes < L.total) return fail(GEM_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.total);
+  if (L.total > 0 && !ws) return fail(GEM_ERR_INVALID, "workspace is NULL");
+  if (Q->n_sets == 0) return GEM_OK;
+
+  gem_sets Qc;
+  if ((st = convert_query(Q, compute, ws, L, &Qc, stream)) != GEM_OK) return st;
+  hipError_t e;
+  if (!C) {
+    if (D->n_sets == 0) {
+      if (k > 0) {
+        e = launch_beam_reset(top_scores, top_ids, Q->n_sets * (int64_t)k, stream);
+        if (e != hipSuccess) return hip_fail(e, "top-k padding");
+      }
+      return GEM_OK;
+    }
+    int32_t* qb = reinterpret_cast<int32_t*>(at(ws, L.qb));
+    e = launch_plan_query_blocks(Q->offsets, Q->n_sets, L.block_rows, Q->max_set_len, qb, L.n_blocks_max, stream);
+    if (e != hipSuccess) return hip_fail(e, "query-block plan");
+    DenseOut out;
+    out.scores = scores ? scores : reinterpret_cast<float*>(at(ws, L.staged));
+    out.ld = scores ? ld_scores : D->n_sets;
+    out.rows = scores ? score_rows : nullptr;
+    e = launch_score_dense(compute, view(&Qc), view(D), qb, L.n_blocks_max, L.block_rows, out, stream);
+    if (e != hipSuccess) return hip_fail(e, "dense scoring");
+    if (k > 0) {
+      TopkSegs S;
+      S.scores = out.scores; S.off = nullptr; S.ids = nullptr; S.rows = out.rows;
+      S.n_segs = Q->n_sets; S.len = D->n_sets; S.ld = out.ld;
+      e = launch_topk(S, k, top_scores, top_ids, stream);
+      if (e != hipSuccess) return hip_fail(e, "top-k");
+    }
+  } else {
+    float* es = scores ? scores : reinterpret_cast<float*>(at(ws, L.staged));
+    e = launch_score_gather(compute, view(&Qc), view(D), cview(C), list_len_bound(C), Q->max_set_len, es, stream);
+    if (e != hipSuccess) return hip_fail(e, "gathered scoring");
+    if (k > 0) {
+      TopkSegs S;
+      S.scores = es; S.off = C->offsets; S.ids = C->ids; S.rows = nullptr;
+      S.n_segs = Q->n_sets; S.len = C->stride; S.ld = C->stride;
+      e = launch_topk(S, k, top_scores, top_ids, stream);
+      if (e != hipSuccess) return hip_fail(e, "top-k");
+    }
+  }
+  return GEM_OK;
+}
+
+__device__ unsigned long long g_validate_bad;
+
+__global__ void validate_offsets_kernel(const int64_t* off, int64_t n, int64_t hi) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i > n) return;
+  const int64_t v = off[i];
+  bool bad = v < 0 || v > hi;
+  if (i > 0 && off[i - 1] > v) bad = true;
+  if (bad) atomicAdd(&g_validate_bad, 1ull);
+}
+
+__global__ void validate_scales_kernel(const float* s, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t u = __float_as_uint(s[i]);
+  const uint32_t ex = (u >> 23) & 0xffu;
+  if ((u >> 31) || (u & 0x7fffffu) || ex == 0 || ex == 0xffu) atomicAdd(&g_validate_bad, 1ull);
+}
+
+__global__ void validate_ids_kernel(const int32_t* ids, int64_t n, int64_t n_sets) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  if (ids[i] >= n_sets) atomicAdd(&g_validate_bad, 1ull);
+}
+
+gem_status run_validation(hipStream_t stream, const char* what) {
+  unsigned long long bad = 0;
+  hipError_t e = hipMemcpyFromSymbolAsync(&bad, HIP_SYMBOL(g_validate_bad), sizeof(bad), 0, hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return hip_fail(e, "validation read-back");
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "validation sync");
+  if (bad) return fail(GEM_ERR_DEVICE_CHECK, "%s: %llu violations", what, bad);
+  return GEM_OK;
+}
+
+gem_status reset_validation(hipStream_t stream) {
+  const unsigned long long zero = 0;
+  hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(g_validate_bad), &zero, sizeof(zero), 0, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "validation reset");
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "validation reset sync");
+  return GEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gem_status gem_create(gem_ctx* out, int device) {
+  if (!out) return fail(GEM_ERR_INVALID, "out is NULL");
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device < 0 || device >= n) return fail(GEM_ERR_INVALID, "device %d of %d", device, n);
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(GEM_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
+  gem_ctx c = new (std::nothrow) gem_ctx_s;
+  if (!c) return fail(GEM_ERR_INVALID, "out of host memory");
+  c->device = device;
+  c->n_cu = prop.multiProcessorCount;
+  std::snprintf(c->arch, sizeof(c->arch), "%s", prop.gcnArchName);
+  *out = c;
+  return GEM_OK;
+}
+
+gem_status gem_destroy(gem_ctx ctx) {
+  delete ctx;
+  return GEM_OK;
+}
+
+const char* gem_status_string(gem_status s) {
+  switch (s) {
+    case GEM_OK: return "GEM_OK";
+    case GEM_ERR_INVALID: return "GEM_ERR_INVALID";
+    case GEM_ERR_WORKSPACE: return "GEM_ERR_WORKSPACE";
+    case GEM_ERR_UNSUPPORTED: return "GEM_ERR_UNSUPPORTED";
+    case GEM_ERR_HIP: return "GEM_ERR_HIP";
+    case GEM_ERR_DEVICE_CHECK: return "GEM_ERR_DEVICE_CHECK";
+    default: return "GEM_ERR_UNKNOWN";
+  }
+}
+
+const char* gem_last_error(void) { return g_last_error.c_str(); }
+
+const char* gem_version(void) { return "gem-mi355x 0.1 (gfx950)"; }
+
+size_t gem_workspace_bytes(gem_ctx ctx, int32_t op, const gem_sets* Q, const gem_sets* D, const gem_cands* C,
+                           int32_t compute, int32_t k, int32_t scores_given) {
+  (void)ctx;
+  if (!Q) return 0;
+  switch (op) {
+    case GEM_OP_SCORE_EXACT:
+    case GEM_OP_SCORE_QUANT: {
+      if (!D) return 0;
+      const int32_t cd = op == GEM_OP_SCORE_QUANT ? (int32_t)GEM_FP8_E4M3 : compute;
+      return score_layout(Q, D, C, cd, k, scores_given != 0).total;
+    }
+    case GEM_OP_EXPAND: {
+      if (!D || !C) return 0;
+      return score_layout(Q, D, C, GEM_FP8_E4M3, 1, scores_given != 0).total;
+    }
+    default:
+      return 0;
+  }
+}
+
+gem_status gem_convert_bf16(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim, uint16_t* out,
+                            hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (dim != GEM_DIM) return fail(GEM_ERR_UNSUPPORTED, "dim %d (only %d is supported)", dim, GEM_DIM);
+  if (n_rows < 0) return fail(GEM_ERR_INVALID, "negative n_rows");
+  if (n_rows > 0 && (!x || !out)) return fail(GEM_ERR_INVALID, "NULL buffer");
+  hipError_t e = launch_convert_bf16(x, n_rows * GEM_DIM, out, stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "bf16 conversion");
+}
+
+gem_status gem_quantize_fp8(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim, uint8_t* out, float* scales,
+                            hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (dim != GEM_DIM) return fail(GEM_ERR_UNSUPPORTED, "dim %d (only %d is supported)", dim, GEM_DIM);
+  if (n_rows < 0) return fail(GEM_ERR_INVALID, "negative n_rows");
+  if (n_rows > 0 && (!x || !out || !scales)) return fail(GEM_ERR_INVALID, "NULL buffer");
+  hipError_t e = launch_quantize_fp8(x, n_rows, out, scales, stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "fp8 quantization");
+}
+
+gem_status gem_score_exact(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t compute,
+                           int32_t k, float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,
+                           int32_t* top_ids, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (compute != GEM_F32 && compute != GEM_BF16)
+    return fail(GEM_ERR_INVALID, "exact scoring computes in F32 or BF16, not dtype %d", compute);
+  return score_common(Q, D, C, compute, k, scores, ld_scores, score_rows, top_scores, top_ids, ws, ws_bytes, stream);
+}
+
+gem_status gem_score_quant(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t k,
+                           float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,
+                           int32_t* top_ids, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  return score_common(Q, D, C, GEM_FP8_E4M3, k, scores, ld_scores, score_rows, top_scores, top_ids, ws, ws_bytes,
+                      stream);
+}
+
+gem_status gem_topk(gem_ctx ctx, const float* scores, const int64_t* seg_offsets, const int32_t* seg_ids,
+                    int64_t n_segs, int64_t seg_len, int64_t seg_ld, const int32_t* seg_rows, int32_t k,
+                    float* top_scores, int32_t* top_ids, void* ws, size_t ws_bytes, hipStream_t stream) {
+  (void)ws; (void)ws_bytes;
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (k < 0 || k > GEM_MAX_K) return fail(GEM_ERR_INVALID, "k = %d outside [0, %d]", k, GEM_MAX_K);
+  if (n_segs < 0) return fail(GEM_ERR_INVALID, "negative n_segs");
+  if (n_segs > INT32_MAX) return fail(GEM_ERR_UNSUPPORTED, "more than 2^31-1 segments");
+  if (n_segs == 0 || k == 0) return GEM_OK;
+  if (!top_scores || !top_ids) return fail(GEM_ERR_INVALID, "NULL output");
+  TopkSegs S;
+  S.scores = scores; S.off = seg_offsets; S.ids = seg_ids; S.rows = seg_rows; S.n_segs = n_segs;
+  S.len = seg_len; S.ld = seg_ld;
+  if (!seg_offsets) {
+    if (seg_ids) return fail(GEM_ERR_INVALID, "uniform segments take positions as ids: seg_ids must be NULL");
+    if (seg_len < 0) return fail(GEM_ERR_INVALID, "negative seg_len");
+    if (seg_ld == 0) S.ld = seg_len;
+    if (S.ld < seg_len) return fail(GEM_ERR_INVALID, "seg_ld < seg_len");
+    S.rows = seg_rows;
+  } else {
+    S.rows = nullptr;
+  }
+  if (!scores) return fail(GEM_ERR_INVALID, "scores is NULL");
+  hipError_t e = launch_topk(S, k, top_scores, top_ids, stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "top-k");
+}
+
+gem_status gem_expand_batch(gem_ctx ctx, const gem_sets* Q8, const gem_sets* D8, const gem_cands* C, gem_beam* beam,
+                            float* cand_scores, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  gem_status st;
+  if ((st = check_sets(Q8, "Q8", true)) != GEM_OK) return st;
+  if ((st = check_sets(D8, "D8", false)) != GEM_OK) return st;
+  if (D8->dtype != GEM_FP8_E4M3) return fail(GEM_ERR_INVALID, "D8 must be FP8 E4M3");
+  if (Q8->dtype != GEM_FP8_E4M3 && Q8->dtype != GEM_F32) return fail(GEM_ERR_INVALID, "Q8 must be FP8 E4M3 or F32");
+  if (!C) return fail(GEM_ERR_INVALID, "cands is NULL");
+  if ((st = check_cands(C, Q8->n_sets)) != GEM_OK) return st;
+  if (!beam) return fail(GEM_ERR_INVALID, "beam is NULL");
+  if (beam->ef < 1 || beam->ef > GEM_MAX_K) return fail(GEM_ERR_INVALID, "ef = %d outside [1, %d]", beam->ef, GEM_MAX_K);
+  if (Q8->n_sets > 0 && (!beam->scores || !beam->ids)) return fail(GEM_ERR_INVALID, "beam buffers are NULL");
+  if ((int64_t)beam->ef + list_len_bound(C) > kBeamMaxEntries)
+    return fail(GEM_ERR_UNSUPPORTED, "ef + longest list = %d exceeds %d", beam->ef + list_len_bound(C), kBeamMaxEntries);
+  const ScoreLayout L = score_layout(Q8, D8, C, GEM_FP8_E4M3, 1, cand_scores != nullptr);
+  if (ws_bytes < L.total) return fail(GEM_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.total);
+  if (L.total > 0 && !ws) return fail(GEM_ERR_INVALID, "workspace is NULL");
+  if (Q8->n_sets == 0) return GEM_OK;
+  gem_sets Qc;
+  if ((st = convert_query(Q8, GEM_FP8_E4M3, ws, L, &Qc, stream)) != GEM_OK) return st;
+  float* es = cand_scores ? cand_scores : reinterpret_cast<float*>(at(ws, L.staged));
+  hipError_t e = launch_score_gather(GEM_FP8_E4M3, view(&Qc), view(D8), cview(C), list_len_bound(C), Q8->max_set_len,
+                                     es, stream);
+  if (e != hipSuccess) return hip_fail(e, "gathered scoring");
+  e = launch_beam_merge(es, cview(C), Q8->n_sets, beam->ef, beam->scores, beam->ids, stream);
+  if (e != hipSuccess) return hip_fail(e, "beam merge");
+  return GEM_OK;
+}
+
+gem_status gem_beam_merge(gem_ctx ctx, const float* cand_scores, const gem_cands* C, gem_beam* beam,
+                          hipStream_t stream) {
+  if (!ctx || !C || !beam) return fail(GEM_ERR_INVALID, "NULL argument");
+  gem_status st = check_cands(C, C->n_lists);
+  if (st != GEM_OK) return st;
+  if (beam->ef < 1 || beam->ef > GEM_MAX_K) return fail(GEM_ERR_INVALID, "ef = %d outside [1, %d]", beam->ef, GEM_MAX_K);
+  if (C->n_lists > 0 && (!beam->scores || !beam->ids)) return fail(GEM_ERR_INVALID, "beam buffers are NULL");
+  if (C->n_entries > 0 && !cand_scores) return fail(GEM_ERR_INVALID, "cand_scores is NULL");
+  if ((int64_t)beam->ef + list_len_bound(C) > kBeamMaxEntries)
+    return fail(GEM_ERR_UNSUPPORTED, "ef + longest list = %d exceeds %d", beam->ef + list_len_bound(C), kBeamMaxEntries);
+  hipError_t e = launch_beam_merge(cand_scores, cview(C), C->n_lists, beam->ef, beam->scores, beam->ids, stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "beam merge");
+}
+
+gem_status gem_beam_reset(gem_ctx ctx, gem_beam* beam, int64_t n_queries, hipStream_t stream) {
+  if (!ctx || !beam) return fail(GEM_ERR_INVALID, "NULL argument");
+  if (beam->ef < 1 || beam->ef > GEM_MAX_K) return fail(GEM_ERR_INVALID, "ef = %d outside [1, %d]", beam->ef, GEM_MAX_K);
+  if (n_queries < 0) return fail(GEM_ERR_INVALID, "negative n_queries");
+  if (n_queries > 0 && (!beam->scores || !beam->ids)) return fail(GEM_ERR_INVALID, "beam buffers are NULL");
+  hipError_t e = launch_beam_reset(beam->scores, beam->ids, n_queries * (int64_t)beam->ef, stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "beam reset");
+}
+
+gem_status gem_validate_sets(gem_ctx ctx, const gem_sets* S, hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  gem_status st = check_sets(S, "sets", false);
+  if (st != GEM_OK) return st;
+  if ((st = reset_validation(stream)) != GEM_OK) return st;
+  if (S->n_sets > 0) {
+    hipLaunchKernelGGL(validate_offsets_kernel, dim3((unsigned)((S->n_sets + 1 + 255) / 256)), dim3(256), 0, stream,
+                       S->offsets, S->n_sets, S->n_vecs);
+  }
+  if (S->dtype == GEM_FP8_E4M3 && S->n_vecs > 0) {
+    hipLaunchKernelGGL(validate_scales_kernel, dim3((unsigned)((S->n_vecs + 255) / 256)), dim3(256), 0, stream,
+                       S->scales, S->n_vecs);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "validation launch");
+  return run_validation(stream, "sets");
+}
+
+gem_status gem_validate_cands(gem_ctx ctx, const gem_cands* C, int64_t n_sets, hipStream_t stream) {
+  if (!ctx || !C) return fail(GEM_ERR_INVALID, "NULL argument");
+  gem_status st = check_cands(C, C->n_lists);
+  if (st != GEM_OK) return st;
+  if ((st = reset_validation(stream)) != GEM_OK) return st;
+  if (C->offsets && C->n_lists > 0) {
+    hipLaunchKernelGGL(validate_offsets_kernel, dim3((unsigned)((C->n_lists + 1 + 255) / 256)), dim3(256), 0, stream,
+                       C->offsets, C->n_lists, C->n_entries);
+  }
+  if (C->n_entries > 0) {
+    hipLaunchKernelGGL(validate_ids_kernel, dim3((unsigned)((C->n_entries + 255) / 256)), dim3(256), 0, stream,
+                       C->ids, C->n_entries, n_sets);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "validation launch");
+  return run_validation(stream, "cands");
+}
+
+}  // extern "C"

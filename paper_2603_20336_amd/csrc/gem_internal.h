@@ -1,0 +1,78 @@
+// Internal host-side interface between the C ABI (capi.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/gem.h"
+
+namespace gem {
+
+// Device view of a CSR set batch.
+struct SetsView {
+  const int64_t* off;     // [n_sets + 1], absolute row indices into vecs
+  const void* vecs;       // rows of kDim elements
+  const float* scales;    // FP8: per-row power-of-two scale
+  int64_t n_sets;
+};
+
+// Device view of candidate lists: list i = [off[i], off[i+1]) or [i*stride, (i+1)*stride).
+struct CandsView {
+  const int64_t* off;
+  const int32_t* ids;
+  int64_t n_lists;
+  int32_t stride;
+};
+
+// Query blocks: block b = queries [qb_start[b], qb_start[b+1]); n_blocks_max + 1 entries.
+constexpr int kBlockMaxQueries = 64;
+
+// Row capacity (query vectors held in registers) of one pass of the dense scorer.
+int dense_pass_rows(int dtype);
+// Rows a query block may hold for a batch whose longest query has max_len rows.
+int dense_block_rows(int dtype, int max_len);
+int64_t dense_blocks_upper(int64_t n_q, int64_t n_rows, int block_rows, int max_len);
+
+hipError_t launch_plan_query_blocks(const int64_t* q_off, int64_t n_q, int block_rows, int max_len,
+                                    int32_t* qb_start, int64_t n_blocks_max, hipStream_t s);
+
+struct DenseOut {
+  float* scores;          // score (i, j) at scores[row(i) * ld + j]
+  int64_t ld;
+  const int32_t* rows;    // nullable
+};
+
+hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, const int32_t* qb_start,
+                              int64_t n_blocks_max, int block_rows, const DenseOut& out, hipStream_t s);
+
+hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C,
+                               int32_t max_list_len, int32_t max_q_len, float* scores, hipStream_t s);
+
+hipError_t launch_convert_bf16(const float* x, int64_t n_elems, uint16_t* out, hipStream_t s);
+hipError_t launch_quantize_fp8(const float* x, int64_t n_rows, uint8_t* out, float* scales, hipStream_t s);
+
+// Segments for top-k.
+struct TopkSegs {
+  const float* scores;
+  const int64_t* off;     // CSR segments, or NULL for uniform segments
+  const int32_t* ids;     // nullable: positions are the ids
+  const int32_t* rows;    // uniform mode: row of segment i (nullable: i)
+  int64_t n_segs;
+  int64_t len;            // uniform mode: entries per segment
+  int64_t ld;             // uniform mode: row stride
+};
+
+hipError_t launch_topk(const TopkSegs& segs, int32_t k, float* top_scores, int32_t* top_ids, hipStream_t s);
+
+hipError_t launch_beam_merge(const float* cand_scores, const CandsView& C, int64_t n_q, int32_t ef,
+                             float* beam_scores, int32_t* beam_ids, hipStream_t s);
+hipError_t launch_beam_reset(float* beam_scores, int32_t* beam_ids, int64_t n, hipStream_t s);
+
+constexpr int kBeamMaxEntries = 4096;   // ef + longest candidate list of a merge
+
+// Validation: returns number of violations found (synchronizes).
+hipError_t validate_sets(const SetsView& S, int64_t n_vecs, int is_fp8, hipStream_t s, int64_t* bad);
+hipError_t validate_cands(const CandsView& C, int64_t n_entries, int64_t n_sets, hipStream_t s, int64_t* bad);
+
+}  // namespace gem

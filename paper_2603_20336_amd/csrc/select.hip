@@ -1,0 +1,294 @@
+// Selection kernels: segmented top-k (the k-argmax of the retrieval problem,
+// GEM Sec. 3.1) and the bounded result-set update of beam search (the set R of
+// Alg. 5: insert the scored neighbours, keep at most ef, evict the worst).
+//
+// Entries are ranked by a 64-bit key: the score's order-preserving bits above
+// the complemented id, so a larger key is a higher score or, on equal scores,
+// a smaller id. A repeated id keeps its best entry; identical (score, id)
+// copies have identical keys.
+#include "device_common.hpp"
+#include "gem_internal.h"
+
+namespace gem {
+
+constexpr int kSelThreads = 512;
+constexpr int kSelCap = 4096;     // entries a workgroup can hold in LDS
+
+__device__ __forceinline__ uint64_t rank_key(float s, int32_t id) {
+  return ((uint64_t)float_order_key(s) << 32) | (uint64_t)(~(uint32_t)id);
+}
+__device__ __forceinline__ int32_t key_id(uint64_t k) { return (int32_t)(~(uint32_t)k); }
+__device__ __forceinline__ float key_score(uint64_t k) { return float_from_order_key((uint32_t)(k >> 32)); }
+// Same entry keyed by id first (ascending), best score first among equal ids.
+__device__ __forceinline__ uint64_t id_key(uint64_t k) {
+  return ((uint64_t)(uint32_t)key_id(k) << 32) | (uint64_t)(~(uint32_t)(k >> 32));
+}
+__device__ __forceinline__ uint64_t rank_from_id_key(uint64_t ik) {
+  return ((uint64_t)(~(uint32_t)ik) << 32) | (uint64_t)(~(uint32_t)(ik >> 32));
+}
+
+// Bitonic sort of a[0..n) (n a power of two), descending if `desc`.
+__device__ void block_bitonic_sort(uint64_t* a, int n, bool desc) {
+  for (int k = 2; k <= n; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t x = a[i], y = a[ixj];
+          const bool up = ((i & k) == 0) != desc;       // this pair ascending?
+          if ((x > y) == up) { a[i] = y; a[ixj] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__device__ __forceinline__ int pow2_ceil(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// keys[0..n): rank keys (0 = empty). Removes repeated ids (keeping the best
+// entry of each), then sorts descending. Returns the number of distinct entries.
+__device__ int dedup_and_sort(uint64_t* keys, int n, bool may_repeat, int* s_cnt) {
+  const int np = pow2_ceil(max(n, 1));
+  if (may_repeat) {
+    for (int i = threadIdx.x; i < np; i += blockDim.x) keys[i] = (i < n && keys[i]) ? id_key(keys[i]) : ~0ull;
+    __syncthreads();
+    block_bitonic_sort(keys, np, false);
+    // after the ascending id sort, copies of an id are adjacent, best first
+    uint64_t keep_key[kSelCap / kSelThreads];
+    int c = 0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x, ++c) {
+      const uint64_t ik = keys[i];
+      bool keep = ik != ~0ull;
+      if (keep && i > 0 && (uint32_t)(keys[i - 1] >> 32) == (uint32_t)(ik >> 32)) keep = false;
+      keep_key[c] = keep ? rank_from_id_key(ik) : 0ull;
+    }
+    __syncthreads();
+    c = 0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x, ++c) keys[i] = keep_key[c];
+    __syncthreads();
+  } else {
+    for (int i = threadIdx.x + n; i < np; i += blockDim.x) keys[i] = 0ull;
+    __syncthreads();
+  }
+  block_bitonic_sort(keys, np, true);
+  if (threadIdx.x == 0) *s_cnt = 0;
+  __syncthreads();
+  int c = 0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) c += keys[i] != 0ull;
+  atomicAdd(s_cnt, c);
+  __syncthreads();
+  const int d = *s_cnt;
+  __syncthreads();
+  return d;
+}
+
+struct SegAccess {
+  const float* sc;
+  const int32_t* ids;
+  int64_t n;
+  __device__ __forceinline__ int32_t id(int64_t j) const { return ids ? ids[j] : (int32_t)j; }
+};
+
+// Histogram add with one atomic per wave when all active lanes hit one bin.
+__device__ __forceinline__ void hist_add(uint32_t* hist, bool active, uint32_t bin) {
+  const uint64_t act = __ballot(active);
+  if (act == 0) return;
+  const uint32_t first = __builtin_amdgcn_readfirstlane(active ? bin : 0xffffffffu);
+  const uint64_t same = __ballot(active && bin == first);
+  if (same == act) {
+    if (lane_id() == __ffsll((unsigned long long)act) - 1) atomicAdd(&hist[first], (uint32_t)__popcll(act));
+  } else if (active) {
+    atomicAdd(&hist[bin], 1u);
+  }
+}
+
+__global__ __launch_bounds__(kSelThreads) void topk_kernel(TopkSegs S, int32_t k, float* __restrict__ top_scores,
+                                                          int32_t* __restrict__ top_ids) {
+  __shared__ uint64_t keys[kSelCap];
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t suf[257];
+  __shared__ int s_cnt, s_eq;
+  __shared__ uint32_t s_sel, s_gt;
+
+  const int64_t seg = blockIdx.x;
+  SegAccess A;
+  if (S.off) {
+    const int64_t a = S.off[seg], b = S.off[seg + 1];
+    A.sc = S.scores + a;
+    A.ids = S.ids ? S.ids + a : nullptr;
+    A.n = b - a;
+  } else {
+    const int64_t row = S.rows ? (int64_t)S.rows[seg] : seg;
+    A.sc = S.scores + row * S.ld;
+    A.ids = S.ids ? S.ids + row * S.ld : nullptr;
+    A.n = S.len;
+  }
+  const bool may_repeat = A.ids != nullptr;
+  const int tid = threadIdx.x;
+
+  int n_keys = 0;
+  if (A.n <= kSelCap) {
+    // whole segment fits: take every valid entry
+    if (tid == 0) s_cnt = 0;
+    __syncthreads();
+    for (int64_t j = tid; j < A.n; j += kSelThreads) {
+      const int32_t id = A.id(j);
+      if (id >= 0) keys[atomicAdd(&s_cnt, 1)] = rank_key(A.sc[j], id);
+    }
+    __syncthreads();
+    n_keys = s_cnt;
+    __syncthreads();
+    n_keys = dedup_and_sort(keys, n_keys, may_repeat, &s_cnt);
+  } else {
+    int K = k;
+    for (;;) {
+      // radix select of the K-th largest key (with multiplicity), 8 bits a pass
+      uint64_t prefix = 0, mask = 0;
+      int need = K;
+      bool exact = false, take_all = false;
+      for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int i = tid; i < 256; i += kSelThreads) hist[i] = 0;
+        __syncthreads();
+        for (int64_t j0 = 0; j0 < A.n; j0 += kSelThreads) {
+          const int64_t j = j0 + tid;
+          bool act = false;
+          uint32_t bin = 0;
+          if (j < A.n) {
+            const int32_t id = A.id(j);
+            if (id >= 0) {
+              const uint64_t key = rank_key(A.sc[j], id);
+              if ((key & mask) == prefix) { act = true; bin = (uint32_t)(key >> shift) & 0xffu; }
+            }
+          }
+          hist_add(hist, act, bin);
+        }
+        __syncthreads();
+        if (tid < 256) suf[tid] = hist[tid];
+        if (tid == 0) suf[256] = 0;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {          // suffix sums
+          uint32_t v = (tid < 256 && tid + o < 256) ? suf[tid + o] : 0;
+          __syncthreads();
+          if (tid < 256) suf[tid] += v;
+          __syncthreads();
+        }
+        if (shift == 56 && suf[0] <= (uint32_t)K) { take_all = true; break; }
+        if (tid < 256 && suf[tid] >= (uint32_t)need && suf[tid + 1] < (uint32_t)need) { s_sel = tid; s_gt = suf[tid + 1]; }
+        __syncthreads();
+        const uint32_t sel = s_sel;
+        need -= (int)s_gt;
+        prefix |= (uint64_t)sel << shift;
+        mask |= 0xffull << shift;
+        const bool ex = hist[sel] == (uint32_t)need;
+        __syncthreads();
+        if (ex) { exact = true; break; }
+      }
+      // collect: keys above the threshold prefix, plus the threshold's share
+      if (tid == 0) { s_cnt = 0; s_eq = 0; }
+      __syncthreads();
+      for (int64_t j = tid; j < A.n; j += kSelThreads) {
+        const int32_t id = A.id(j);
+        if (id < 0) continue;
+        const uint64_t key = rank_key(A.sc[j], id);
+        bool take;
+        if (take_all) take = true;
+        else if ((key & mask) > prefix) take = true;
+        else if ((key & mask) == prefix) take = exact ? true : (atomicAdd(&s_eq, 1) < need);
+        else take = false;
+        if (take) {
+          const int pos = atomicAdd(&s_cnt, 1);
+          if (pos < kSelCap) keys[pos] = key;
+        }
+      }
+      __syncthreads();
+      const int got = min(s_cnt, kSelCap);
+      __syncthreads();
+      n_keys = dedup_and_sort(keys, got, may_repeat, &s_cnt);
+      // repeated ids can leave fewer than k distinct entries: widen and redo
+      if (take_all || n_keys >= k || !may_repeat) break;
+      const int K2 = K + (k - n_keys);
+      if (K2 > kSelCap) break;      // more repeats than the workgroup can hold: keep what we have
+      K = K2;
+      __syncthreads();
+    }
+  }
+  for (int r = tid; r < k; r += kSelThreads) {
+    const uint64_t key = r < n_keys ? keys[r] : 0ull;
+    top_scores[seg * k + r] = key ? key_score(key) : neg_inf();
+    top_ids[seg * k + r] = key ? key_id(key) : -1;
+  }
+}
+
+hipError_t launch_topk(const TopkSegs& segs, int32_t k, float* top_scores, int32_t* top_ids, hipStream_t s) {
+  if (segs.n_segs == 0 || k == 0) return hipSuccess;
+  hipLaunchKernelGGL(topk_kernel, dim3((unsigned)segs.n_segs), dim3(kSelThreads), 0, s, segs, k, top_scores, top_ids);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Beam update: row q of the beam becomes the best ef of (row q) U (list q's
+// scored entries), ids distinct. One workgroup per query.
+__global__ __launch_bounds__(kSelThreads) void beam_merge_kernel(const float* __restrict__ cand_scores, CandsView C,
+                                                                 int32_t ef, float* __restrict__ beam_scores,
+                                                                 int32_t* __restrict__ beam_ids) {
+  __shared__ uint64_t keys[kSelCap];
+  __shared__ int s_cnt;
+  const int64_t q = blockIdx.x;
+  const int tid = threadIdx.x;
+  int64_t lb, le;
+  if (C.off) { lb = C.off[q]; le = C.off[q + 1]; }
+  else { lb = q * (int64_t)C.stride; le = lb + C.stride; }
+  if (tid == 0) s_cnt = 0;
+  __syncthreads();
+  float* bs = beam_scores + q * ef;
+  int32_t* bi = beam_ids + q * ef;
+  for (int r = tid; r < ef; r += kSelThreads) {
+    const int32_t id = bi[r];
+    if (id >= 0) {
+      const int pos = atomicAdd(&s_cnt, 1);
+      if (pos < kSelCap) keys[pos] = rank_key(bs[r], id);
+    }
+  }
+  for (int64_t e = lb + tid; e < le; e += kSelThreads) {
+    const int32_t id = C.ids[e];
+    if (id >= 0) {
+      const int pos = atomicAdd(&s_cnt, 1);
+      if (pos < kSelCap) keys[pos] = rank_key(cand_scores[e], id);
+    }
+  }
+  __syncthreads();
+  const int n = min(s_cnt, kSelCap);
+  __syncthreads();
+  const int d = dedup_and_sort(keys, n, true, &s_cnt);
+  for (int r = tid; r < ef; r += kSelThreads) {
+    const uint64_t key = r < d ? keys[r] : 0ull;
+    bs[r] = key ? key_score(key) : neg_inf();
+    bi[r] = key ? key_id(key) : -1;
+  }
+}
+
+hipError_t launch_beam_merge(const float* cand_scores, const CandsView& C, int64_t n_q, int32_t ef,
+                             float* beam_scores, int32_t* beam_ids, hipStream_t s) {
+  if (n_q == 0) return hipSuccess;
+  hipLaunchKernelGGL(beam_merge_kernel, dim3((unsigned)n_q), dim3(kSelThreads), 0, s, cand_scores, C, ef,
+                     beam_scores, beam_ids);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void beam_reset_kernel(float* __restrict__ s, int32_t* __restrict__ i, int64_t n) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j < n) { s[j] = neg_inf(); i[j] = -1; }
+}
+
+hipError_t launch_beam_reset(float* beam_scores, int32_t* beam_ids, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(beam_reset_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, beam_scores, beam_ids, n);
+  return hipGetLastError();
+}
+
+}  // namespace gem

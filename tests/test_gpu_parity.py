@@ -1,0 +1,339 @@
+"""GPU parity: the HIP path against the float64 CPU oracle on seeded inputs.
+
+Tolerances. Every product of the bf16 / FP8 operands is exact in float32, so
+the kernels differ from the oracle (run on the same rounded operands) only by
+float32 accumulation: per dot product at most gamma_128 * sum|a_t p_t|
+(gamma_n = n u / (1 - n u), u = 2^-24; about 7.6e-6 for unit vectors), and the
+max is 1-Lipschitz, so a score of m_q maxima is off by at most about
+m_q * 7.6e-6 + gamma_{m_q} |score|. Relative to max(|score|, 1) that is below
+1e-4 for m_q <= 13 and below 3e-4 at m_q = 32 in the worst case; typical
+errors are ~1e-6. The tests use 1e-4 relative (the exactness target), with
+the worst-case bound asserted separately on the largest queries.
+Top-k sets are compared outside a tie band of 2 * tol * max(|s_k|, 1).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2603_20336_amd as gem
+from paper_2603_20336_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+TOL = 1e-4
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _operands(vecs_f32: np.ndarray, dtype: str) -> np.ndarray:
+    """The exact values the GPU multiplies, computed by the oracle's own codecs."""
+    if dtype == "f32":
+        return vecs_f32.astype(np.float64)
+    if dtype == "bf16":
+        return oracle.bf16_decode(oracle.bf16_round_bits(vecs_f32))
+    codes, scales = oracle.quantize_fp8(vecs_f32)
+    return oracle.dequantize_fp8(codes, scales)
+
+
+def _device_sets(batch: wl.SetBatch, dtype: str) -> gem.Sets:
+    S = gem.Sets.from_batch(batch, DEV)
+    if dtype == "bf16":
+        return S.to_bf16()
+    if dtype == "fp8":
+        return S.to_fp8()
+    return S
+
+
+def _score(Q, D, dtype, **kw):
+    if dtype == "fp8":
+        return gem.score_quant(Q, D, **kw)
+    return gem.score_exact(Q, D, compute=dtype, **kw)
+
+
+def assert_close(got, ref, tol=TOL, what=""):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    assert got.shape == ref.shape
+    inf_ref = np.isinf(ref)
+    assert np.array_equal(np.isinf(got), inf_ref), f"{what}: -inf pattern differs"
+    assert np.array_equal(got[inf_ref], ref[inf_ref])
+    fin = ~inf_ref
+    if fin.any():
+        rel = np.abs(got[fin] - ref[fin]) / np.maximum(np.abs(ref[fin]), 1.0)
+        assert rel.max() <= tol, f"{what}: max rel err {rel.max():.3e} > {tol}"
+
+
+def _csr(lengths):
+    o = np.zeros(len(lengths) + 1, np.int64)
+    o[1:] = np.cumsum(lengths)
+    return o
+
+
+def _ragged(lengths, seed):
+    """Unit vectors from a small mixture, with the given set lengths."""
+    centers = wl.mixture_centers(8, seed)
+    g = torch.Generator().manual_seed(seed + 1)
+    vecs = wl.mixture_vectors(int(sum(lengths)), centers, 0.1, g)
+    return wl.SetBatch(vecs, torch.from_numpy(_csr(lengths)))
+
+
+# ----------------------------------------------------------------------- conversions
+def test_convert_bf16_bitwise():
+    rng = np.random.default_rng(0)
+    x = (rng.standard_normal(128 * 2000) * 10.0 ** rng.integers(-20, 20, 128 * 2000)).astype(np.float32)
+    halfway = ((rng.integers(1, 254, 4096).astype(np.uint32) << 23) | (rng.integers(0, 128, 4096).astype(np.uint32) << 16)
+               | np.uint32(0x8000)).view(np.float32)
+    x[: halfway.size] = halfway
+    x[5000:5004] = [0.0, -0.0, 3.39e38, -1e-45]
+    b = wl.SetBatch(torch.from_numpy(x.reshape(-1, 128)), torch.tensor([0, 2000], dtype=torch.int64))
+    got = _np(gem.Sets.from_batch(b, DEV).to_bf16().vecs).reshape(-1)
+    np.testing.assert_array_equal(got, oracle.bf16_round_bits(x))
+
+
+def test_quantize_fp8_bitwise():
+    c = wl.corpus(wl.WORKLOADS[1], n_docs=200)
+    x = c.vecs.numpy().copy()
+    rng = np.random.default_rng(1)
+    extra = [np.zeros(128, np.float32),                                      # all-zero row: scale 1
+             (rng.standard_normal(128) * 1e3).astype(np.float32),
+             (rng.standard_normal(128) * 1e-30).astype(np.float32),
+             (rng.standard_normal(128) * 1e-42).astype(np.float32),          # subnormal row: clamped scale
+             np.full(128, 448.0, np.float32),
+             np.linspace(-1, 1, 128).astype(np.float32)]
+    t = oracle.e4m3_decode_table()[:0x7F]
+    mids = ((t[1:] + t[:-1]) / 2)[-128:].astype(np.float32)                  # exact midpoints of the grid
+    extra.append(mids)
+    x = np.vstack([x] + [e[None] for e in extra])
+    b = wl.SetBatch(torch.from_numpy(x), torch.tensor([0, x.shape[0]], dtype=torch.int64))
+    S = gem.Sets.from_batch(b, DEV).to_fp8()
+    codes, scales = oracle.quantize_fp8(x)
+    np.testing.assert_array_equal(_np(S.scales), scales)
+    np.testing.assert_array_equal(_np(S.vecs), codes)
+
+
+# ----------------------------------------------------------------------- dense (exhaustive)
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_dense_workload1_matches_oracle(dtype):
+    w = wl.WORKLOADS[1]
+    c, q = wl.corpus(w), wl.queries(w)
+    D, Q = _device_sets(c, dtype), gem.Sets.from_batch(q, DEV)
+    top_s, top_i, scores = _score(Q, D, dtype, k=w.k, want_scores=True)
+    torch.cuda.synchronize()
+    ref = oracle.ch_dense(_operands(q.vecs.numpy(), dtype), q.offsets.numpy(),
+                          _operands(c.vecs.numpy(), dtype), c.offsets.numpy())
+    assert_close(_np(scores), ref, what=f"dense {dtype}")
+    ti, ts = _np(top_i), _np(top_s)
+    for r in range(Q.n_sets):
+        tau = 2 * TOL * max(abs(np.sort(ref[r])[::-1][w.k - 1]), 1.0)
+        ok, bad, missing = oracle.tie_aware_match(ti[r], ref[r], w.k, tau)
+        assert ok, (r, bad, missing)
+        np.testing.assert_allclose(ts[r], ref[r][ti[r]], rtol=0, atol=TOL * max(1, abs(ts[r][0])))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_dense_ragged_edges(dtype):
+    qlens = [1, 2, 31, 32, 33, 64, 0, 17, 256, 5, 128, 129]
+    dlens = [1, 15, 16, 17, 255, 256, 0, 3, 64, 65] + list(np.random.default_rng(2).integers(1, 90, 121))
+    q, c = _ragged(qlens, 10), _ragged(dlens, 20)
+    D, Q = _device_sets(c, dtype), gem.Sets.from_batch(q, DEV)
+    scores = _score(Q, D, dtype)
+    torch.cuda.synchronize()
+    ref = oracle.ch_dense(_operands(q.vecs.numpy(), dtype), q.offsets.numpy(),
+                          _operands(c.vecs.numpy(), dtype), c.offsets.numpy())
+    # the 256-vector query may reach the worst-case accumulation bound
+    assert_close(_np(scores), ref, tol=3e-4, what=f"ragged {dtype}")
+    small = np.array(qlens) <= 64
+    assert_close(_np(scores)[small], ref[small], what=f"ragged {dtype} (m_q <= 64)")
+
+
+def test_dense_rows_and_ld_layout():
+    """Scores land at row(i) * ld + j: the placement the serving loop uses."""
+    q, c = _ragged([3, 7, 2], 30), _ragged([4, 9, 1, 6, 2] * 30, 31)
+    D, Q = _device_sets(c, "bf16"), gem.Sets.from_batch(q, DEV)
+    base = _score(Q, D, "bf16")
+    out = torch.full((6, 200), 7.0, device=DEV)
+    rows = torch.tensor([4, 0, 2], dtype=torch.int32, device=DEV)
+    gem.score_exact(Q, D, compute="bf16", scores=out, ld=200, rows=rows)
+    torch.cuda.synchronize()
+    o = _np(out)
+    for i, r in enumerate([4, 0, 2]):
+        np.testing.assert_array_equal(o[r, :150], _np(base)[i])
+        assert (o[r, 150:] == 7.0).all()
+    assert (o[[1, 3, 5]] == 7.0).all()
+
+
+def test_batch_independence_bitwise():
+    """A query's scores are bitwise the same alone and inside a larger batch."""
+    w = wl.WORKLOADS[1]
+    c, q = wl.corpus(w, n_docs=300), wl.queries(w, n_queries=40, query_len=("uniform", 4, 64))
+    for dtype in ("f32", "bf16", "fp8"):
+        D = _device_sets(c, dtype)
+        full = _np(_score(gem.Sets.from_batch(q, DEV), D, dtype))
+        for i in (0, 17, 39):
+            alone = _np(_score(gem.Sets.from_batch(q.subset([i]), DEV), D, dtype))
+            np.testing.assert_array_equal(alone[0], full[i])
+        sub = _np(_score(gem.Sets.from_batch(q.subset([5, 3, 30]), DEV), D, dtype))
+        np.testing.assert_array_equal(sub, full[[5, 3, 30]])
+
+
+# ----------------------------------------------------------------------- gathered
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_gather_matches_oracle_and_dense(dtype):
+    qlens = [32, 1, 0, 64, 200, 7]
+    dlens = list(np.random.default_rng(3).integers(0, 130, 300))
+    q, c = _ragged(qlens, 40), _ragged(dlens, 41)
+    rng = np.random.default_rng(4)
+    lists = [rng.integers(0, 300, 37), np.array([5, 5, -1, 7, 0]), np.array([], np.int64),
+             rng.integers(-1, 300, 70), rng.integers(0, 300, 16), np.arange(300)]
+    co = _csr([len(x) for x in lists])
+    ci = np.concatenate(lists).astype(np.int32)
+    C = gem.Cands(torch.from_numpy(ci).to(DEV), torch.from_numpy(co).to(DEV))
+    D, Q = _device_sets(c, dtype), gem.Sets.from_batch(q, DEV)
+    got = _np(_score(Q, D, dtype, cands=C))
+    dense = _np(_score(Q, D, dtype))
+    torch.cuda.synchronize()
+    qo, do = _operands(q.vecs.numpy(), dtype), _operands(c.vecs.numpy(), dtype)
+    ref = oracle.ch_cands(qo, q.offsets.numpy(), do, c.offsets.numpy(), co, np.maximum(ci, 0))
+    ref[ci < 0] = -np.inf
+    assert_close(got, ref, tol=3e-4, what=f"gather {dtype}")
+    # the same (query, document) pair scores bitwise the same in both kernels
+    for i in range(len(lists)):
+        for e in range(co[i], co[i + 1]):
+            if ci[e] >= 0:
+                assert got[e] == dense[i, ci[e]], (dtype, i, e)
+
+
+# ----------------------------------------------------------------------- top-k
+@pytest.mark.parametrize("mode", ["csr_ids", "csr_pos", "rows"])
+def test_topk_bitwise(mode):
+    s, off = wl.random_scores(24, ("uniform", 0, 9000), seed=5, tie_frac=0.3)
+    s_np, off_np = s.numpy(), off.numpy()
+    rng = np.random.default_rng(6)
+    ids = rng.integers(-1, 5000, s_np.size).astype(np.int32)        # repeats and padding ids
+    for k in (1, 10, 100, 1000):
+        if mode == "rows":
+            n, L = 12, 7000
+            mat = np.random.default_rng(7).standard_normal((n, L)).astype(np.float32)
+            mat[:, ::7] = 0.5                                       # large ties
+            rows = np.array([3, 0, 11, 5, 5], np.int32)
+            ts, ti = gem.topk(torch.from_numpy(mat).to(DEV), k, seg_rows=torch.from_numpy(rows).to(DEV))
+            rs, ri = oracle.topk_rows(mat[rows], k)
+        elif mode == "csr_pos":
+            ts, ti = gem.topk(s.to(DEV), k, seg_offsets=off.to(DEV))
+            rs, ri = oracle.topk_segments(s_np, off_np, k)
+        else:
+            ts, ti = gem.topk(s.to(DEV), k, seg_offsets=off.to(DEV), seg_ids=torch.from_numpy(ids).to(DEV))
+            keep = ids >= 0
+            # the oracle skips padding ids: drop them from each segment first
+            seg = np.repeat(np.arange(len(off_np) - 1), np.diff(off_np))
+            o2 = np.zeros_like(off_np)
+            o2[1:] = np.cumsum(np.bincount(seg[keep], minlength=len(off_np) - 1))
+            rs, ri = oracle.topk_segments(s_np[keep], o2, k, ids[keep])
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(_np(ti), ri)
+        np.testing.assert_array_equal(_np(ts), rs.astype(np.float32))
+
+
+def test_topk_long_segments_with_repeats():
+    """Radix path (segments longer than the in-LDS capacity) with repeated ids."""
+    rng = np.random.default_rng(8)
+    n = 3
+    L = 20000
+    sc = rng.standard_normal(n * L).astype(np.float32)
+    ids = rng.integers(0, 150, n * L).astype(np.int32)              # heavy repetition
+    sc[ids < 40] = 2.5                                              # repeated ids, equal scores
+    off = np.arange(n + 1, dtype=np.int64) * L
+    for k in (5, 100):
+        ts, ti = gem.topk(torch.from_numpy(sc).to(DEV), k, seg_offsets=torch.from_numpy(off).to(DEV),
+                          seg_ids=torch.from_numpy(ids).to(DEV))
+        rs, ri = oracle.topk_segments(sc, off, k, ids)
+        np.testing.assert_array_equal(_np(ti), ri)
+        np.testing.assert_array_equal(_np(ts), rs.astype(np.float32))
+
+
+# ----------------------------------------------------------------------- beam
+def test_beam_merge_bitwise():
+    n_q, ef = 9, 50
+    beam = gem.Beam(n_q, ef, DEV)
+    steps = []
+    for st in range(6):
+        s, off = wl.random_scores(n_q, ("uniform", 0, 80), seed=100 + st, tie_frac=0.2)
+        ids = wl.candidate_ids(1, int(off[-1]) or 1, 2000, seed=200 + st).reshape(-1)[: int(off[-1])]
+        # a document keeps one score across steps
+        s = torch.from_numpy(np.sin(ids.numpy().astype(np.float64) * 0.37).astype(np.float32)) if st % 2 else s
+        C = gem.Cands(ids.contiguous().to(DEV), off.to(DEV))
+        gem.beam_merge(s.to(DEV), C, beam)
+        steps.append((s.numpy(), off.numpy(), ids.numpy()))
+    torch.cuda.synchronize()
+    rs, ri = oracle.beam_replay(n_q, ef, steps)
+    np.testing.assert_array_equal(_np(beam.ids), ri)
+    np.testing.assert_array_equal(_np(beam.scores), rs.astype(np.float32))
+
+
+def test_expand_batch_matches_oracle():
+    w = wl.WORKLOADS[4]
+    c = wl.corpus(w, n_docs=3000)
+    q = wl.queries(w, n_queries=20)
+    D8, Q = _device_sets(c, "fp8"), gem.Sets.from_batch(q, DEV)
+    Q8 = Q.to_fp8()
+    ef = 100
+    beam = gem.Beam(Q.n_sets, ef, DEV)
+    qo, do = _operands(q.vecs.numpy(), "fp8"), _operands(c.vecs.numpy(), "fp8")
+    steps = []
+    for st in range(4):
+        off, ids = wl.step_candidates(w, st, n_queries=20, n_docs=3000)
+        C = gem.Cands(ids.to(DEV), off.to(DEV), max_list_len=w.cands_per_step)
+        cs = torch.empty(ids.numel(), device=DEV)
+        gem.expand_batch(Q8 if st % 2 else Q, D8, C, beam, cand_scores=cs)
+        ref = oracle.ch_cands(qo, q.offsets.numpy(), do, c.offsets.numpy(), off.numpy(), ids.numpy())
+        steps.append((ref, off.numpy(), ids.numpy()))
+        torch.cuda.synchronize()
+        assert_close(_np(cs), ref, what="expand scores")
+    rs, ri = oracle.beam_replay(Q.n_sets, ef, steps)
+    bs, bi = _np(beam.scores), _np(beam.ids)
+    assert_close(bs, rs, what="beam scores")
+    # beam membership agrees outside the tie band at the ef-th score
+    all_ids = np.concatenate([s[2].reshape(20, -1) for s in steps], axis=1)
+    all_sc = np.concatenate([s[0].reshape(20, -1) for s in steps], axis=1)
+    for r in range(Q.n_sets):
+        u, first = np.unique(all_ids[r], return_index=True)
+        exact = np.full(3000, -np.inf)
+        exact[u] = all_sc[r][first]
+        tau = 2 * TOL * max(abs(rs[r][ef - 1]), 1.0)
+        ok, bad, missing = oracle.tie_aware_match(bi[r], exact, ef, tau)
+        assert ok, (r, bad, missing)
+
+
+def test_error_paths_enqueue_nothing():
+    q = gem.Sets.from_batch(_ragged([3], 50), DEV)
+    c = gem.Sets.from_batch(_ragged([3, 4], 51), DEV)
+    with pytest.raises(gem.GemError) as e:
+        gem.score_exact(q, c.to_bf16(), compute="f32")            # D dtype != compute
+    assert e.value.status == gem._abi.GEM_ERR_INVALID
+    with pytest.raises(gem.GemError) as e:
+        gem.score_exact(q, c, k=2000)                              # k > GEM_MAX_K
+    assert e.value.status == gem._abi.GEM_ERR_INVALID
+    big = gem.Sets.from_batch(_ragged([300], 52), DEV)
+    with pytest.raises(gem.GemError) as e:
+        gem.score_exact(big, c)                                    # query longer than 256
+    assert e.value.status == gem._abi.GEM_ERR_UNSUPPORTED
+    # a workspace smaller than gem_workspace_bytes() is refused
+    import ctypes
+    lib = gem.library()
+    qs, ds = q.struct(), c.to_bf16().struct()
+    ts = torch.empty(1, 1, device=DEV)
+    ti = torch.empty(1, 1, dtype=torch.int32, device=DEV)
+    need = lib.gem_workspace_bytes(gem._ctx(q.device), 0, ctypes.byref(qs), ctypes.byref(ds), None, 1, 1, 0)
+    assert need > 0
+    ws = torch.empty(need - 1, dtype=torch.uint8, device=DEV)
+    st = lib.gem_score_exact(gem._ctx(q.device), ctypes.byref(qs), ctypes.byref(ds), None, 1, 1, None, 0, None,
+                             ts.data_ptr(), ti.data_ptr(), ws.data_ptr(), need - 1, None)
+    assert st == gem._abi.GEM_ERR_WORKSPACE
+    bad_off = gem.Sets(c.vecs, torch.tensor([0, 5, 3], dtype=torch.int64, device=DEV), "f32", 5)
+    with pytest.raises(gem.GemError) as e:
+        gem.validate_sets(bad_off)
+    assert e.value.status == gem._abi.GEM_ERR_DEVICE_CHECK
+    gem.validate_sets(c)
