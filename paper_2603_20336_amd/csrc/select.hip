@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kSelThreads) void topk_kernel(TopkSegs S, int32_t k
   __shared__ uint64_t keys[kSelCap];
   __shared__ uint32_t hist[256];
   __shared__ uint32_t suf[257];
-  __shared__ int s_cnt, s_eq;
+  __shared__ int s_cnt;
   __shared__ uint32_t s_sel, s_gt;
 
   const int64_t seg = blockIdx.x;
@@ -144,78 +144,84 @@ __global__ __launch_bounds__(kSelThreads) void topk_kernel(TopkSegs S, int32_t k
     n_keys = s_cnt;
     __syncthreads();
     n_keys = dedup_and_sort(keys, n_keys, may_repeat, &s_cnt);
-  } else {
-    int K = k;
-    for (;;) {
-      // radix select of the K-th largest key (with multiplicity), 8 bits a pass
-      uint64_t prefix = 0, mask = 0;
-      int need = K;
-      bool exact = false, take_all = false;
-      for (int shift = 56; shift >= 0; shift -= 8) {
-        for (int i = tid; i < 256; i += kSelThreads) hist[i] = 0;
-        __syncthreads();
-        for (int64_t j0 = 0; j0 < A.n; j0 += kSelThreads) {
-          const int64_t j = j0 + tid;
-          bool act = false;
-          uint32_t bin = 0;
-          if (j < A.n) {
-            const int32_t id = A.id(j);
-            if (id >= 0) {
-              const uint64_t key = rank_key(A.sc[j], id);
-              if ((key & mask) == prefix) { act = true; bin = (uint32_t)(key >> shift) & 0xffu; }
-            }
-          }
-          hist_add(hist, act, bin);
-        }
-        __syncthreads();
-        if (tid < 256) suf[tid] = hist[tid];
-        if (tid == 0) suf[256] = 0;
-        __syncthreads();
-        for (int o = 1; o < 256; o <<= 1) {          // suffix sums
-          uint32_t v = (tid < 256 && tid + o < 256) ? suf[tid + o] : 0;
-          __syncthreads();
-          if (tid < 256) suf[tid] += v;
-          __syncthreads();
-        }
-        if (shift == 56 && suf[0] <= (uint32_t)K) { take_all = true; break; }
-        if (tid < 256 && suf[tid] >= (uint32_t)need && suf[tid + 1] < (uint32_t)need) { s_sel = tid; s_gt = suf[tid + 1]; }
-        __syncthreads();
-        const uint32_t sel = s_sel;
-        need -= (int)s_gt;
-        prefix |= (uint64_t)sel << shift;
-        mask |= 0xffull << shift;
-        const bool ex = hist[sel] == (uint32_t)need;
-        __syncthreads();
-        if (ex) { exact = true; break; }
-      }
-      // collect: keys above the threshold prefix, plus the threshold's share
-      if (tid == 0) { s_cnt = 0; s_eq = 0; }
+  } else if (may_repeat) {
+    // ids may repeat: stream the segment through LDS in chunks, keeping the
+    // best k distinct ids seen so far (an entry dropped here is beaten by k
+    // distinct ids whose kept entries can only improve later)
+    const int step = kSelCap - k;
+    int cur = 0;
+    for (int64_t c0 = 0; c0 < A.n; c0 += step) {
+      const int64_t c1 = min(A.n, c0 + (int64_t)step);
+      if (tid == 0) s_cnt = cur;
       __syncthreads();
-      for (int64_t j = tid; j < A.n; j += kSelThreads) {
+      for (int64_t j = c0 + tid; j < c1; j += kSelThreads) {
         const int32_t id = A.id(j);
-        if (id < 0) continue;
-        const uint64_t key = rank_key(A.sc[j], id);
-        bool take;
-        if (take_all) take = true;
-        else if ((key & mask) > prefix) take = true;
-        else if ((key & mask) == prefix) take = exact ? true : (atomicAdd(&s_eq, 1) < need);
-        else take = false;
-        if (take) {
-          const int pos = atomicAdd(&s_cnt, 1);
-          if (pos < kSelCap) keys[pos] = key;
-        }
+        if (id >= 0) keys[atomicAdd(&s_cnt, 1)] = rank_key(A.sc[j], id);
       }
       __syncthreads();
-      const int got = min(s_cnt, kSelCap);
+      const int n = s_cnt;
       __syncthreads();
-      n_keys = dedup_and_sort(keys, got, may_repeat, &s_cnt);
-      // repeated ids can leave fewer than k distinct entries: widen and redo
-      if (take_all || n_keys >= k || !may_repeat) break;
-      const int K2 = K + (k - n_keys);
-      if (K2 > kSelCap) break;      // more repeats than the workgroup can hold: keep what we have
-      K = K2;
-      __syncthreads();
+      cur = min(dedup_and_sort(keys, n, true, &s_cnt), (int)k);
     }
+    n_keys = cur;
+  } else {
+    // positions as ids (all distinct): radix select of the k-th largest key,
+    // 8 bits a pass, stopping as soon as the threshold bucket holds exactly
+    // the entries still needed
+    uint64_t prefix = 0, mask = 0;
+    int need = k;
+    bool exact = false, take_all = false;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      for (int i = tid; i < 256; i += kSelThreads) hist[i] = 0;
+      __syncthreads();
+      for (int64_t j0 = 0; j0 < A.n; j0 += kSelThreads) {
+        const int64_t j = j0 + tid;
+        bool act = false;
+        uint32_t bin = 0;
+        if (j < A.n) {
+          const uint64_t key = rank_key(A.sc[j], (int32_t)j);
+          if ((key & mask) == prefix) { act = true; bin = (uint32_t)(key >> shift) & 0xffu; }
+        }
+        hist_add(hist, act, bin);
+      }
+      __syncthreads();
+      if (tid < 256) suf[tid] = hist[tid];
+      if (tid == 0) suf[256] = 0;
+      __syncthreads();
+      for (int o = 1; o < 256; o <<= 1) {          // suffix sums
+        uint32_t v = (tid < 256 && tid + o < 256) ? suf[tid + o] : 0;
+        __syncthreads();
+        if (tid < 256) suf[tid] += v;
+        __syncthreads();
+      }
+      if (shift == 56 && suf[0] <= (uint32_t)k) { take_all = true; break; }
+      if (tid < 256 && suf[tid] >= (uint32_t)need && suf[tid + 1] < (uint32_t)need) { s_sel = tid; s_gt = suf[tid + 1]; }
+      __syncthreads();
+      const uint32_t sel = s_sel;
+      need -= (int)s_gt;
+      prefix |= (uint64_t)sel << shift;
+      mask |= 0xffull << shift;
+      const bool ex = hist[sel] == (uint32_t)need;
+      __syncthreads();
+      if (ex) { exact = true; break; }
+    }
+    // collect the keys above the threshold and the threshold's share (keys are
+    // distinct, so a full-width threshold is a single key)
+    if (tid == 0) s_cnt = 0;
+    __syncthreads();
+    for (int64_t j = tid; j < A.n; j += kSelThreads) {
+      const uint64_t key = rank_key(A.sc[j], (int32_t)j);
+      const bool take = take_all || (key & mask) > prefix || (exact && (key & mask) == prefix) ||
+                        (!exact && key == prefix);
+      if (take) {
+        const int pos = atomicAdd(&s_cnt, 1);
+        if (pos < kSelCap) keys[pos] = key;
+      }
+    }
+    __syncthreads();
+    const int got = min(s_cnt, kSelCap);
+    __syncthreads();
+    n_keys = dedup_and_sort(keys, got, false, &s_cnt);
   }
   for (int r = tid; r < k; r += kSelThreads) {
     const uint64_t key = r < n_keys ? keys[r] : 0ull;

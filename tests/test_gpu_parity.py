@@ -104,7 +104,8 @@ def test_quantize_fp8_bitwise():
              np.full(128, 448.0, np.float32),
              np.linspace(-1, 1, 128).astype(np.float32)]
     t = oracle.e4m3_decode_table()[:0x7F]
-    mids = ((t[1:] + t[:-1]) / 2)[-128:].astype(np.float32)                  # exact midpoints of the grid
+    mids = ((t[1:] + t[:-1]) / 2).astype(np.float32)                         # exact midpoints of the grid
+    mids = np.concatenate([mids, [447.0, -3.0]]).astype(np.float32)         # 126 + 2 = one row
     extra.append(mids)
     x = np.vstack([x] + [e[None] for e in extra])
     b = wl.SetBatch(torch.from_numpy(x), torch.tensor([0, x.shape[0]], dtype=torch.int64))
