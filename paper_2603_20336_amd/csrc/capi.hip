@@ -99,7 +99,7 @@ CandsView cview(const gem_cands* C) {
 
 // Workspace layout of a scoring call.
 struct ScoreLayout {
-  size_t q_conv = 0, q_scales = 0, qb = 0, staged = 0, total = 0;
+  size_t q_conv = 0, q_scales = 0, qb = 0, qcol = 0, staged = 0, total = 0;
   int64_t n_blocks_max = 0;
   int block_rows = 0;
 };
@@ -121,6 +121,8 @@ ScoreLayout score_layout(const gem_sets* Q, const gem_sets* D, const gem_cands* 
     L.n_blocks_max = dense_blocks_upper(Q->n_sets, Q->n_vecs, L.block_rows, Q->max_set_len);
     L.qb = off;
     off = align_up(off + (size_t)(L.n_blocks_max + 1) * 4);
+    L.qcol = off;
+    off = align_up(off + (size_t)(Q->n_sets + 1) * 8);
     if (k > 0 && !scores_given) {
       L.staged = off;
       off = align_up(off + (size_t)Q->n_sets * (size_t)D->n_sets * 4);
@@ -190,13 +192,15 @@ gem_status score_common(const gem_sets* Q, const gem_sets* D, const gem_cands* C
       return GEM_OK;
     }
     int32_t* qb = reinterpret_cast<int32_t*>(at(ws, L.qb));
-    e = launch_plan_query_blocks(Q->offsets, Q->n_sets, L.block_rows, Q->max_set_len, qb, L.n_blocks_max, stream);
+    int64_t* qcol = reinterpret_cast<int64_t*>(at(ws, L.qcol));
+    e = launch_plan_query_blocks(Q->offsets, Q->n_sets, L.block_rows, Q->max_set_len, qb, qcol, L.n_blocks_max,
+                                 stream);
     if (e != hipSuccess) return hip_fail(e, "query-block plan");
     DenseOut out;
     out.scores = scores ? scores : reinterpret_cast<float*>(at(ws, L.staged));
     out.ld = scores ? ld_scores : D->n_sets;
     out.rows = scores ? score_rows : nullptr;
-    e = launch_score_dense(compute, view(&Qc), view(D), qb, L.n_blocks_max, L.block_rows, out, stream);
+    e = launch_score_dense(compute, view(&Qc), view(D), qb, qcol, L.n_blocks_max, out, stream);
     if (e != hipSuccess) return hip_fail(e, "dense scoring");
     if (k > 0) {
       TopkSegs S;

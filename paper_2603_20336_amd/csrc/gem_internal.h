@@ -26,7 +26,8 @@ struct CandsView {
 };
 
 // Query blocks: block b = queries [qb_start[b], qb_start[b+1]); n_blocks_max + 1 entries.
-constexpr int kBlockMaxQueries = 64;
+// qcol[i]: first (16-aligned) column of query i in the padded layout, [n_q + 1].
+constexpr int kBlockMaxQueries = 32;
 
 // Row capacity (query vectors held in registers) of one pass of the dense scorer.
 int dense_pass_rows(int dtype);
@@ -35,7 +36,7 @@ int dense_block_rows(int dtype, int max_len);
 int64_t dense_blocks_upper(int64_t n_q, int64_t n_rows, int block_rows, int max_len);
 
 hipError_t launch_plan_query_blocks(const int64_t* q_off, int64_t n_q, int block_rows, int max_len,
-                                    int32_t* qb_start, int64_t n_blocks_max, hipStream_t s);
+                                    int32_t* qb_start, int64_t* qcol, int64_t n_blocks_max, hipStream_t s);
 
 struct DenseOut {
   float* scores;          // score (i, j) at scores[row(i) * ld + j]
@@ -44,7 +45,7 @@ struct DenseOut {
 };
 
 hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, const int32_t* qb_start,
-                              int64_t n_blocks_max, int block_rows, const DenseOut& out, hipStream_t s);
+                              const int64_t* qcol, int64_t n_blocks_max, const DenseOut& out, hipStream_t s);
 
 hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C,
                                int32_t max_list_len, int32_t max_q_len, float* scores, hipStream_t s);

@@ -10,10 +10,11 @@
 // end re-load its last vector, which leaves the max unchanged (max is
 // idempotent), so tiles never straddle documents and need no masking.
 //
-// The sum over a query's vectors is taken in a fixed order (vector 0, 1, ...),
-// so a (query, document) score does not depend on which other queries or
-// documents share the launch: the same pair scores bitwise the same in the
-// dense and the gathered kernel, alone or in any batch.
+// The sum over a query's vectors is taken in a fixed order that depends only on
+// the query itself (a fixed lane tree inside each 16-vector tile, then the tiles
+// in order), so a (query, document) score does not depend on which other
+// queries or documents share the launch: the same pair scores bitwise the same
+// in the dense and the gathered kernel, alone or in any batch.
 #include "device_common.hpp"
 #include "gem_internal.h"
 
@@ -92,9 +93,9 @@ template <> struct Op<GEM_FP8_E4M3> {
 
 // Column tiles (16 query vectors each) held in registers by one pass.
 template <int DT> struct DenseCfg;
-template <> struct DenseCfg<GEM_F32> { static constexpr int kNT = 8; };
-template <> struct DenseCfg<GEM_BF16> { static constexpr int kNT = 16; };
-template <> struct DenseCfg<GEM_FP8_E4M3> { static constexpr int kNT = 32; };
+template <> struct DenseCfg<GEM_F32> { static constexpr int kNT = 4; };
+template <> struct DenseCfg<GEM_BF16> { static constexpr int kNT = 8; };
+template <> struct DenseCfg<GEM_FP8_E4M3> { static constexpr int kNT = 16; };
 
 int dense_pass_rows(int dtype) {
   switch (dtype) {
@@ -104,208 +105,407 @@ int dense_pass_rows(int dtype) {
   }
 }
 
+static int pad16(int m) { return (m + 15) & ~15; }
+
 int dense_block_rows(int dtype, int max_len) {
-  int r = dense_pass_rows(dtype);
-  int passes = max_len <= r ? 1 : (max_len + r - 1) / r;
-  return r * passes;
+  const int r = dense_pass_rows(dtype);
+  const int m = pad16(max_len);
+  return m <= r ? r : ((m + r - 1) / r) * r;
 }
 
 int64_t dense_blocks_upper(int64_t n_q, int64_t n_rows, int block_rows, int max_len) {
-  int64_t win = block_rows - (max_len > 0 ? max_len : 1) + 1;   // >= 1
-  return n_rows / win + 2 + n_q / kBlockMaxQueries + 1;
+  const int64_t win = block_rows - pad16(max_len > 0 ? max_len : 1) + 1;   // >= 1
+  const int64_t cols = n_rows + 15 * n_q;                                   // padded columns, upper bound
+  return cols / win + 3 + n_q / kBlockMaxQueries;
 }
 
 // --------------------------------------------------------------------------
-// Query-block plan: cut the query batch into runs of whole queries so that a
-// run spans at most `block_rows` vectors and at most kBlockMaxQueries queries.
-// A run starts at query i when i is a multiple of kBlockMaxQueries or when the
-// start row of i falls into a new window of (block_rows - max_len + 1) rows.
+// Per-document epilogue shared by both scorers.
+//
+// rm[ct] holds, per lane, the running max over a document's rows 4g..4g+3 of
+// each tile for query column (16 ct + l % 16). Four tiles at a time:
+// two permlane16 swaps and one permlane32 swap leave tile (4i + r)'s column
+// maxima in row r (lanes 16r..16r+15) of R[i], already reduced over the four
+// lane groups; four DPP adds inside each 16-lane row then leave that tile's
+// column sum T in every lane of the row. Every step pairs fixed lanes, so T
+// depends only on the tile's own values.
+template <int NT>
+__device__ __forceinline__ void tile_sums(const float (&rm)[NT], float (&R)[NT / 4]) {
+#pragma unroll
+  for (int i = 0; i < NT / 4; ++i) {
+    auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(rm[4 * i + 0]), __float_as_uint(rm[4 * i + 1]), false, false);
+    const float ab = fmaxf(__uint_as_float(p[0]), __uint_as_float(p[1]));       // rows: A01 B01 A23 B23
+    auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(rm[4 * i + 2]), __float_as_uint(rm[4 * i + 3]), false, false);
+    const float cd = fmaxf(__uint_as_float(q[0]), __uint_as_float(q[1]));       // rows: C01 D01 C23 D23
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(ab), __float_as_uint(cd), false, false);
+    float m = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));             // rows: A B C D
+    m += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0xb1, 0xf, 0xf, false));   // lane ^ 1
+    m += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0x4e, 0xf, 0xf, false));   // lane ^ 2
+    m += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0x141, 0xf, 0xf, false));  // half mirror
+    m += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0x140, 0xf, 0xf, false));  // row mirror
+    R[i] = m;
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ float tile_sum_at(const float (&R)[NT / 4], int ct) {
+  return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(R[ct >> 2]), 16 * (ct & 3)));
+}
+
+__device__ __forceinline__ void update_max(float& rm, f32x4 a) {
+  rm = fmaxf(fmaxf(rm, a[0]), a[1]);
+  rm = fmaxf(fmaxf(rm, a[2]), a[3]);
+}
+
+// --------------------------------------------------------------------------
+// Query-block plan. Each query is laid out from a 16-aligned column (its
+// columns past the last vector are zero vectors, whose max over any document
+// is exactly 0, so they add nothing). The batch is cut into runs of whole
+// queries spanning at most `block_cols` padded columns and kBlockMaxQueries
+// queries: a run starts at query i when i is a multiple of kBlockMaxQueries or
+// when i's first padded column falls into a new window of
+// (block_cols - pad16(max_len) + 1) columns.
 __global__ __launch_bounds__(1024) void plan_query_blocks_kernel(const int64_t* __restrict__ q_off, int64_t n_q,
                                                                  int64_t win, int32_t* __restrict__ qb_start,
-                                                                 int64_t n_blocks_max) {
+                                                                 int64_t* __restrict__ qcol, int64_t n_blocks_max) {
   __shared__ int64_t part[1024];
   const int t = threadIdx.x;
   const int64_t per = (n_q + 1023) / 1024;
-  const int64_t a = t * per, b = min(n_q, a + per);
-  const int64_t base = n_q > 0 ? q_off[0] : 0;
+  const int64_t a = min(n_q, t * per), b = min(n_q, a + per);
+  auto scan = [&](int64_t v) -> int64_t {         // exclusive block scan
+    part[t] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      int64_t u = t >= o ? part[t - o] : 0;
+      __syncthreads();
+      part[t] += u;
+      __syncthreads();
+    }
+    const int64_t incl = part[t];
+    const int64_t tot = part[1023];
+    __syncthreads();
+    part[t] = tot;                                 // broadcast-free: every thread keeps the total
+    return incl - v;
+  };
+  int64_t cols = 0;
+  for (int64_t i = a; i < b; ++i) cols += (q_off[i + 1] - q_off[i] + 15) & ~(int64_t)15;
+  int64_t c = scan(cols);
+  const int64_t total_cols = part[t];
+  for (int64_t i = a; i < b; ++i) {
+    qcol[i] = c;
+    c += (q_off[i + 1] - q_off[i] + 15) & ~(int64_t)15;
+  }
+  if (t == 0) qcol[n_q] = total_cols;
+  __syncthreads();
   auto starts = [&](int64_t i) -> bool {
-    if (i == 0) return true;
     if (i % kBlockMaxQueries == 0) return true;
-    return (q_off[i] - base) / win != (q_off[i - 1] - base) / win;
+    return qcol[i] / win != qcol[i - 1] / win;
   };
   int64_t cnt = 0;
   for (int64_t i = a; i < b; ++i) cnt += starts(i) ? 1 : 0;
-  part[t] = cnt;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {          // inclusive scan
-    int64_t v = t >= o ? part[t - o] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int64_t pos = part[t] - cnt;
+  int64_t pos = scan(cnt);
+  const int64_t n_blocks = min(part[t], n_blocks_max);
   for (int64_t i = a; i < b; ++i)
-    if (starts(i) && pos <= n_blocks_max) qb_start[pos++] = (int32_t)i;
-  const int64_t n_blocks = min(part[1023], n_blocks_max);
+    if (starts(i) && pos < n_blocks_max) qb_start[pos++] = (int32_t)i;
   for (int64_t j = n_blocks + t; j <= n_blocks_max; j += 1024) qb_start[j] = (int32_t)n_q;
 }
 
 hipError_t launch_plan_query_blocks(const int64_t* q_off, int64_t n_q, int block_rows, int max_len,
-                                    int32_t* qb_start, int64_t n_blocks_max, hipStream_t s) {
-  int64_t win = block_rows - (max_len > 0 ? max_len : 1) + 1;
-  hipLaunchKernelGGL(plan_query_blocks_kernel, dim3(1), dim3(1024), 0, s, q_off, n_q, win, qb_start, n_blocks_max);
+                                    int32_t* qb_start, int64_t* qcol, int64_t n_blocks_max, hipStream_t s) {
+  const int64_t win = block_rows - pad16(max_len > 0 ? max_len : 1) + 1;
+  hipLaunchKernelGGL(plan_query_blocks_kernel, dim3(1), dim3(1024), 0, s, q_off, n_q, win, qb_start, qcol,
+                     n_blocks_max);
   return hipGetLastError();
 }
 
 // --------------------------------------------------------------------------
 // Dense scorer: every query block against every document of a 64-document
-// chunk. A workgroup is four waves = four query blocks on the same chunk, so
-// the chunk's tiles are read from HBM once and served to the waves from cache.
+// chunk. A workgroup is eight waves (two per SIMD, so one wave's MFMAs cover
+// the other's epilogue and waits) = eight query blocks on the same chunk. The
+// chunk's document tiles are staged through LDS and shared by the eight waves:
+// threads load 16-byte pieces of every tile, a group of kGroup tiles ahead,
+// into registers, then write them to one of two LDS group buffers; one
+// barrier per group. Inside a tile
+// row the 16-byte chunks are XOR-swizzled by the row index so that the 16
+// lanes reading the same chunk of 16 rows hit distinct banks.
 // Work items are laid out so that consecutive workgroups on one XCD (dispatch
 // is round-robin over the 8 XCDs) share a chunk.
 constexpr int kChunkDocs = 64;
+constexpr int kGroup = 4;
+constexpr int kDenseWaves = 8;                 // two waves per SIMD
+constexpr int kDenseThreads = 64 * kDenseWaves;
 
 struct DenseParams {
   SetsView Q, D;
   const int32_t* qb;
+  const int64_t* qcol;
   int64_t n_blocks_max, n_bgroups, n_chunks;
-  int block_rows;
   DenseOut out;
 };
 
+// LDS image of one 16-row tile: row r at r * kRowBytes, chunk c at position c ^ swz(r).
+template <int DT> struct TileStage {
+  using O = Op<DT>;
+  static constexpr int kRowBytes = O::kRowBytes;
+  static constexpr int kChunksPerRow = kRowBytes / 16;
+  static constexpr int kTileBytes = 16 * kRowBytes;
+  static constexpr int kSlots = kTileBytes / 16;                 // 16-byte pieces per tile
+  static constexpr int kPerThread = (kSlots + kDenseThreads - 1) / kDenseThreads;   // pieces a thread loads per tile
+  static constexpr bool kScales = DT == GEM_FP8_E4M3;
+  static constexpr int kStageBytes = kTileBytes + (kScales ? 64 : 0);
+
+  // chunk c of row r sits at position c ^ swz(r): the 16 rows read by one
+  // 16-lane group then cover all 64 banks (128-byte rows pair up first)
+  static __device__ __forceinline__ int swz(int r) { return kRowBytes == 128 ? ((r >> 1) & 7) : (r & 15); }
+  // global address of piece `slot` of the tile whose rows start at doc row beg
+  static __device__ __forceinline__ const uint4* src(const void* vecs, int64_t beg, int64_t len, int t, int slot) {
+    const int r = slot / kChunksPerRow, pos = slot % kChunksPerRow;
+    const int c = pos ^ swz(r);
+    const int64_t row = beg + min((int64_t)(16 * t + r), len - 1);
+    return reinterpret_cast<const uint4*>(static_cast<const char*>(vecs) + row * kRowBytes) + c;
+  }
+};
+
 template <int DT>
-__global__ __launch_bounds__(256) void score_dense_kernel(DenseParams P) {
+__device__ __forceinline__ void frag_from_lds(typename Op<DT>::Frag& f, const char* stage, int c16, int g);
+
+template <>
+__device__ __forceinline__ void frag_from_lds<GEM_F32>(Op<GEM_F32>::Frag& f, const char* stage, int c16, int g) {
+  const char* row = stage + c16 * 512;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const float4 v = *reinterpret_cast<const float4*>(row + (((8 * g + s) ^ (c16 & 15)) << 4));
+    f.v[4 * s + 0] = v.x; f.v[4 * s + 1] = v.y; f.v[4 * s + 2] = v.z; f.v[4 * s + 3] = v.w;
+  }
+}
+template <>
+__device__ __forceinline__ void frag_from_lds<GEM_BF16>(Op<GEM_BF16>::Frag& f, const char* stage, int c16, int g) {
+  const char* row = stage + c16 * 256;
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    f.v[s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(row + (((4 * g + s) ^ (c16 & 15)) << 4)));
+}
+template <>
+__device__ __forceinline__ void frag_from_lds<GEM_FP8_E4M3>(Op<GEM_FP8_E4M3>::Frag& f, const char* stage, int c16, int g) {
+  const char* row = stage + c16 * 128;
+  const uint4 a = *reinterpret_cast<const uint4*>(row + (((2 * g) ^ ((c16 >> 1) & 7)) << 4));
+  const uint4 b = *reinterpret_cast<const uint4*>(row + (((2 * g + 1) ^ ((c16 >> 1) & 7)) << 4));
+  f.v = i32x8{(int)a.x, (int)a.y, (int)a.z, (int)a.w, (int)b.x, (int)b.y, (int)b.z, (int)b.w};
+  const float sc = reinterpret_cast<const float*>(stage + 16 * 128)[c16];
+  f.scale = (int)((__float_as_uint(sc) >> 23) & 0xffu);
+}
+
+template <int DT>
+__global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams P) {
   using O = Op<DT>;
   using Frag = typename O::Frag;
+  using TS = TileStage<DT>;
   constexpr int NT = DenseCfg<DT>::kNT;
-  constexpr int PASS = 16 * NT;
-  __shared__ float lds_cm[4][PASS];
-  __shared__ float lds_sc[4][kBlockMaxQueries * kChunkDocs];
+  constexpr int PT = TS::kPerThread;
+  __shared__ float lds_sc[kDenseWaves][kBlockMaxQueries * kChunkDocs];
+  __shared__ __attribute__((aligned(16))) char lds_tiles[2][kGroup][TS::kStageBytes];
+  __shared__ int lds_npass[kDenseWaves];
 
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c16 = l & 15;
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
   const int64_t total = P.n_bgroups * P.n_chunks;
   const int64_t per = (total + 7) / 8;
   const int64_t item = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (item >= total) return;
+  if (item >= total) return;                                   // whole workgroup
   const int64_t chunk = item / P.n_bgroups;
-  const int64_t b = (item % P.n_bgroups) * 4 + w;
-  if (b >= P.n_blocks_max) return;
-  const int q0 = P.qb[b], q1 = P.qb[b + 1];
-  if (q0 >= q1) return;
-  const int nq = q1 - q0;
+  const int64_t b = (item % P.n_bgroups) * kDenseWaves + w;
+  int q0 = 0, q1 = 0;
+  if (b < P.n_blocks_max) { q0 = P.qb[b]; q1 = P.qb[b + 1]; }
+  const int nq = max(q1 - q0, 0);                              // 0: this wave only helps load
   const int64_t p0 = chunk * kChunkDocs;
   const int64_t p1 = min(P.D.n_sets, p0 + kChunkDocs);
   const int nd = (int)(p1 - p0);
+  const float ninf = neg_inf();
+  float* sc = lds_sc[w];
 
-  const int64_t r0 = P.Q.off[q0];
-  const int nrows = (int)(P.Q.off[q1] - r0);
-  // lane j < nq: query j of the block (first column, length)
-  int qcs = 0, qlen = 0;
-  if (l < nq) {
-    int64_t a = P.Q.off[q0 + l], e = P.Q.off[q0 + l + 1];
-    qcs = (int)(a - r0);
-    qlen = (int)(e - a);
+  // lane j < nq: query j of the block (first row, length, first tile, tiles)
+  int64_t qrow = 0;
+  int qm = 0, qt0 = 0, qnt = 0;
+  int total_tiles = 0;
+  if (nq > 0) {
+    const int64_t col0 = P.qcol[q0];
+    if (l < nq) {
+      qrow = P.Q.off[q0 + l];
+      qm = (int)(P.Q.off[q0 + l + 1] - qrow);
+      qt0 = (int)((P.qcol[q0 + l] - col0) >> 4);
+      qnt = (qm + 15) >> 4;
+    }
+    total_tiles = (int)((P.qcol[q1] - col0) >> 4);
   }
+  total_tiles = __builtin_amdgcn_readfirstlane(total_tiles);
+  // every wave runs the same number of passes over the chunk (it shares the loads)
+  if (l == 0) lds_npass[w] = (total_tiles + NT - 1) / NT;
   // lane j <= nd: offset of document p0 + j (lane 64 does not exist: use doff_end)
   const int64_t doff_lane = (l <= nd) ? P.D.off[p0 + l] : 0;
   const int64_t doff_end = P.D.off[p1];
-  auto doc_start = [&](int dd) -> int64_t {
-    if (dd >= 64) return doff_end;
-    uint32_t lo = __builtin_amdgcn_readlane((uint32_t)doff_lane, dd);
-    uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(doff_lane >> 32), dd);
+  auto rd64 = [&](int64_t v, int lane) -> int64_t {
+    uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
+    uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), lane);
     return (int64_t)(((uint64_t)hi << 32) | lo);
   };
+  auto doc_start = [&](int dd) -> int64_t { return dd >= 64 ? doff_end : rd64(doff_lane, dd); };
 
-  float* cm = lds_cm[w];
-  float* sc = lds_sc[w];
-  const float ninf = neg_inf();
+  // empty queries score 0 against every document; empty documents score -inf
+  if (l < nq && qm == 0)
+    for (int dd = 0; dd < nd; ++dd) sc[l * kChunkDocs + dd] = 0.0f;
+  for (int dd = 0; dd < nd; ++dd)
+    if (doc_start(dd + 1) == doc_start(dd) && l < nq) sc[l * kChunkDocs + dd] = qm > 0 ? ninf : 0.0f;
+  __syncthreads();
+  int n_pass = 0;
+#pragma unroll
+  for (int i = 0; i < kDenseWaves; ++i) n_pass = max(n_pass, lds_npass[i]);
 
-  for (int prow0 = 0; prow0 < nrows; prow0 += PASS) {
-    const int pr = min(PASS, nrows - prow0);
-    const int nct = (pr + 15) >> 4;
-    const bool first = prow0 == 0;
+  auto skip_empty = [&](int dd) -> int {
+    while (dd < nd && doc_start(dd + 1) == doc_start(dd)) ++dd;
+    return dd;
+  };
+  const int dd_first = skip_empty(0);
+  const int64_t beg_first = dd_first < nd ? doc_start(dd_first) : 0;
+  const int64_t len_first = dd_first < nd ? doc_start(dd_first + 1) - beg_first : 1;
+
+  for (int pass = 0; pass < n_pass; ++pass) {
+    const int pt0 = pass * NT;
+    const int nct = __builtin_amdgcn_readfirstlane(max(0, min(NT, total_tiles - pt0)));
+    // tile map of this pass: owner query, first/last flags, B operand rows
     Frag B[NT];
+    int tq_lane = 0;                                            // lane ct: query owning tile ct
+    uint64_t first_mask = 0, last_mask = 0;
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) {
-      const int col = prow0 + 16 * ct + c16;
-      if (ct < nct && col < nrows) O::load(B[ct], P.Q.vecs, P.Q.scales, r0 + col, g);
-      else O::zero(B[ct]);
-    }
-
-    // empty documents: record their score and move on
-    auto skip_empty = [&](int dd) -> int {
-      while (dd < nd && doc_start(dd + 1) == doc_start(dd)) {
-        if (first && l < nq) sc[l * kChunkDocs + dd] = qlen > 0 ? ninf : 0.0f;
-        ++dd;
+      O::zero(B[ct]);
+      if (ct < nct) {
+        const int t = pt0 + ct;
+        const uint64_t own = __ballot(l < nq && qt0 <= t && t < qt0 + qnt);
+        const int j = __ffsll((unsigned long long)own) - 1;
+        const int jt0 = __builtin_amdgcn_readlane(qt0, j);
+        const int jm = __builtin_amdgcn_readlane(qm, j);
+        const int64_t jrow = rd64(qrow, j);
+        const int k = t - jt0;                                  // tile index inside query j
+        if (l == ct) tq_lane = j;
+        if (k == 0) first_mask |= 1ull << ct;
+        if (16 * (k + 1) >= jm) last_mask |= 1ull << ct;
+        if (16 * k + c16 < jm) O::load(B[ct], P.Q.vecs, P.Q.scales, jrow + 16 * k + c16, g);
       }
-      return dd;
-    };
-
-    int dd = skip_empty(0);
-    int t = 0;
-    int64_t dbeg = 0, dlen = 0;
-    Frag A_next;
-    if (dd < nd) {
-      dbeg = doc_start(dd);
-      dlen = doc_start(dd + 1) - dbeg;
-      O::load(A_next, P.D.vecs, P.D.scales, dbeg + min((int64_t)c16, dlen - 1), g);
     }
     float rm[NT];
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) rm[ct] = ninf;
 
-    while (dd < nd) {
-      Frag A = A_next;
-      // position of the next tile, and its prefetch
-      int ndd = dd, nt = t + 1;
-      int64_t nbeg = dbeg, nlen = dlen;
-      const bool last_tile = (int64_t)nt * 16 >= dlen;
-      if (last_tile) {
-        ndd = skip_empty(dd + 1);
-        nt = 0;
-        if (ndd < nd) { nbeg = doc_start(ndd); nlen = doc_start(ndd + 1) - nbeg; }
-      }
-      if (ndd < nd) O::load(A_next, P.D.vecs, P.D.scales, nbeg + min((int64_t)(nt * 16 + c16), nlen - 1), g);
-
-      f32x4 acc[NT];
-#pragma unroll
-      for (int ct = 0; ct < NT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int s = 0; s < O::kSteps; ++s) {
-#pragma unroll
-        for (int ct = 0; ct < NT; ++ct)
-          if (ct < nct) acc[ct] = O::mma(A, B[ct], acc[ct], s);
-      }
-#pragma unroll
-      for (int ct = 0; ct < NT; ++ct)
-        if (ct < nct) rm[ct] = fmaxf(rm[ct], max4(acc[ct]));
-
-      if (last_tile) {
-        // max over the document's rows: finish across the four lane groups
-#pragma unroll
-        for (int ct = 0; ct < NT; ++ct) {
-          if (ct < nct) {
-            float v = max_across_groups(rm[ct]);
-            if (l < 16) cm[16 * ct + l] = v;
-          }
-          rm[ct] = ninf;
-        }
-        __builtin_amdgcn_wave_barrier();
-        // sum over each query's vectors that this pass holds, in vector order
-        if (l < nq) {
-          float acc_s = first ? 0.0f : sc[l * kChunkDocs + dd];
-          const int a0 = max(qcs - prow0, 0), a1 = min(qcs + qlen - prow0, pr);
-          for (int a = a0; a < a1; ++a) acc_s += cm[a];
-          sc[l * kChunkDocs + dd] = acc_s;
-        }
-        __builtin_amdgcn_wave_barrier();
-      }
-      dd = ndd; t = nt; dbeg = nbeg; dlen = nlen;
+    // tile pipeline: registers hold the next group while the current one is used.
+    // Load cursor (l_*) runs one group ahead of the compute cursor (c_*); past
+    // the last tile the load cursor re-reads the first tile (never used).
+    int l_dd = dd_first, l_t = 0;
+    int64_t l_beg = beg_first, l_len = len_first;
+    int c_dd = dd_first, c_t = 0;
+    int64_t c_beg = beg_first, c_len = len_first;
+    static_assert(kGroup == 4, "the staging code below is written out for four tiles");
+    uint4 R0[PT], R1[PT], R2[PT], R3[PT];                      // 16-byte pieces of the next group
+    uint4 S0 = {}, S1 = {}, S2 = {}, S3 = {};                    // FP8: four row scales per piece
+    // load one tile at the load cursor into (Rx, Sx), then advance the cursor
+#define GEM_LOAD_TILE(Rx, Sx)                                                                           \
+    {                                                                                                   \
+      const bool ok_ = l_dd < nd;                                                                       \
+      const int64_t lb_ = ok_ ? l_beg : beg_first, ll_ = ok_ ? l_len : len_first;                      \
+      const int lt_ = ok_ ? l_t : 0;                                                                    \
+      _Pragma("unroll") for (int v = 0; v < PT; ++v)                                                    \
+        if (tid + kDenseThreads * v < TS::kSlots)                                                       \
+          Rx[v] = *TS::src(P.D.vecs, lb_, ll_, lt_, tid + kDenseThreads * v);                          \
+      if (TS::kScales && tid < 4) {                                                                     \
+        const int r_ = 4 * tid;                                                                         \
+        Sx = make_uint4(__float_as_uint(P.D.scales[lb_ + min((int64_t)(16 * lt_ + r_ + 0), ll_ - 1)]),  \
+                        __float_as_uint(P.D.scales[lb_ + min((int64_t)(16 * lt_ + r_ + 1), ll_ - 1)]),  \
+                        __float_as_uint(P.D.scales[lb_ + min((int64_t)(16 * lt_ + r_ + 2), ll_ - 1)]),  \
+                        __float_as_uint(P.D.scales[lb_ + min((int64_t)(16 * lt_ + r_ + 3), ll_ - 1)])); \
+      }                                                                                                 \
+      if (ok_) {                                                                                        \
+        if ((int64_t)(l_t + 1) * 16 < l_len) ++l_t;                                                    \
+        else {                                                                                          \
+          l_dd = skip_empty(l_dd + 1); l_t = 0;                                                         \
+          if (l_dd < nd) { l_beg = doc_start(l_dd); l_len = doc_start(l_dd + 1) - l_beg; }            \
+        }                                                                                               \
+      }                                                                                                 \
     }
-  }
-  if (nrows == 0) {                    // only empty queries: every score is 0
-    for (int j = 0; j < nq; ++j)
-      if (l < nd) sc[j * kChunkDocs + l] = 0.0f;
+    // write one staged tile into slot u of an LDS group buffer
+#define GEM_STORE_TILE(Rx, Sx, u)                                                                       \
+    {                                                                                                   \
+      _Pragma("unroll") for (int v = 0; v < PT; ++v) {                                                  \
+        const int slot_ = tid + kDenseThreads * v;                                                      \
+        if (slot_ < TS::kSlots) *reinterpret_cast<uint4*>(buf + (u) * TS::kStageBytes + slot_ * 16) = Rx[v]; \
+      }                                                                                                 \
+      if constexpr (TS::kScales) {                                                                      \
+        if (tid < 4) *reinterpret_cast<uint4*>(buf + (u) * TS::kStageBytes + TS::kTileBytes + tid * 16) = Sx; \
+      }                                                                                                 \
+    }
+    GEM_LOAD_TILE(R0, S0) GEM_LOAD_TILE(R1, S1) GEM_LOAD_TILE(R2, S2) GEM_LOAD_TILE(R3, S3)
+    for (int grp = 0; c_dd < nd; ++grp) {
+      char* buf = lds_tiles[grp & 1][0];
+      // land the group that arrived, start loading the next one
+      GEM_STORE_TILE(R0, S0, 0) GEM_STORE_TILE(R1, S1, 1) GEM_STORE_TILE(R2, S2, 2) GEM_STORE_TILE(R3, S3, 3)
+      GEM_LOAD_TILE(R0, S0) GEM_LOAD_TILE(R1, S1) GEM_LOAD_TILE(R2, S2) GEM_LOAD_TILE(R3, S3)
+      __syncthreads();
+#pragma nounroll
+      for (int u = 0; u < kGroup; ++u) {
+        if (c_dd < nd) {
+          const bool last_tile = (int64_t)(c_t + 1) * 16 >= c_len;
+          if (nct > 0) {
+            Frag A;
+            frag_from_lds<DT>(A, buf + u * TS::kStageBytes, c16, g);
+            // column tiles in groups of 4 (a group past the last used tile is
+            // skipped; unused tiles inside a group have zero B operands and
+            // their maxima are never read): independent accumulators keep the
+            // MFMA pipe busy without holding every tile's accumulator at once
+#pragma unroll
+            for (int g0 = 0; g0 < NT; g0 += 4) {
+              if (g0 < nct) {
+                f32x4 acc[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < O::kSteps; ++s) {
+#pragma unroll
+                  for (int c = 0; c < 4; ++c) acc[c] = O::mma(A, B[g0 + c], acc[c], s);
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) update_max(rm[g0 + c], acc[c]);
+              }
+            }
+            if (last_tile) {
+              float Rs[NT / 4];
+              tile_sums<NT>(rm, Rs);
+              // each query's score: its tile sums in tile order
+              float s_run = 0.0f;
+              const int dd = c_dd;
+#pragma unroll
+              for (int ct = 0; ct < NT; ++ct) {
+                if (ct < nct) {
+                  const float T = tile_sum_at<NT>(Rs, ct);
+                  if ((first_mask >> ct) & 1) s_run = T;
+                  else if (ct == 0) s_run = sc[__builtin_amdgcn_readlane(tq_lane, 0) * kChunkDocs + dd] + T;
+                  else s_run += T;
+                  if ((((last_mask >> ct) & 1) || ct == nct - 1) && l == 0)
+                    sc[__builtin_amdgcn_readlane(tq_lane, ct) * kChunkDocs + dd] = s_run;
+                }
+                rm[ct] = ninf;
+              }
+            }
+          }
+          if (!last_tile) ++c_t;
+          else {
+            c_dd = skip_empty(c_dd + 1); c_t = 0;
+            if (c_dd < nd) { c_beg = doc_start(c_dd); c_len = doc_start(c_dd + 1) - c_beg; }
+          }
+        }
+      }
+    }
+    __syncthreads();                                             // buffers are reused by the next pass
+#undef GEM_LOAD_TILE
+#undef GEM_STORE_TILE
   }
   __builtin_amdgcn_wave_barrier();
   // write the chunk's scores, one 64-document row segment per query
@@ -318,20 +518,20 @@ __global__ __launch_bounds__(256) void score_dense_kernel(DenseParams P) {
 }
 
 hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, const int32_t* qb_start,
-                              int64_t n_blocks_max, int block_rows, const DenseOut& out, hipStream_t s) {
+                              const int64_t* qcol, int64_t n_blocks_max, const DenseOut& out, hipStream_t s) {
   DenseParams P;
-  P.Q = Q; P.D = D; P.qb = qb_start; P.n_blocks_max = n_blocks_max;
-  P.n_bgroups = (n_blocks_max + 3) / 4;
+  P.Q = Q; P.D = D; P.qb = qb_start; P.qcol = qcol; P.n_blocks_max = n_blocks_max;
+  P.n_bgroups = (n_blocks_max + kDenseWaves - 1) / kDenseWaves;
   P.n_chunks = (D.n_sets + kChunkDocs - 1) / kChunkDocs;
-  P.block_rows = block_rows;
   P.out = out;
   const int64_t total = P.n_bgroups * P.n_chunks;
   if (total == 0) return hipSuccess;
   const int64_t grid = ((total + 7) / 8) * 8;
+  const dim3 blk(kDenseThreads);
   switch (dtype) {
-    case GEM_F32: hipLaunchKernelGGL(score_dense_kernel<GEM_F32>, dim3((unsigned)grid), dim3(256), 0, s, P); break;
-    case GEM_BF16: hipLaunchKernelGGL(score_dense_kernel<GEM_BF16>, dim3((unsigned)grid), dim3(256), 0, s, P); break;
-    case GEM_FP8_E4M3: hipLaunchKernelGGL(score_dense_kernel<GEM_FP8_E4M3>, dim3((unsigned)grid), dim3(256), 0, s, P); break;
+    case GEM_F32: hipLaunchKernelGGL(score_dense_kernel<GEM_F32>, dim3((unsigned)grid), blk, 0, s, P); break;
+    case GEM_BF16: hipLaunchKernelGGL(score_dense_kernel<GEM_BF16>, dim3((unsigned)grid), blk, 0, s, P); break;
+    case GEM_FP8_E4M3: hipLaunchKernelGGL(score_dense_kernel<GEM_FP8_E4M3>, dim3((unsigned)grid), blk, 0, s, P); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -341,7 +541,8 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
 // Gathered scorer: one wave scores up to kGatherEntries consecutive entries of
 // one query's candidate list. The query's vectors stay in registers (64 per
 // pass); each candidate document is streamed tile by tile, the next tile's
-// load in flight while the current one is multiplied.
+// load in flight while the current one is multiplied. A score is the same sum
+// of per-tile column sums, in tile order, as in the dense scorer.
 constexpr int kGatherEntries = 16;
 constexpr int kGatherNT = 4;
 
@@ -358,7 +559,6 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
   using Frag = typename O::Frag;
   constexpr int NT = kGatherNT;
   constexpr int PASS = 16 * NT;
-  __shared__ float lds_cm[4][PASS];
   __shared__ float lds_sc[4][kGatherEntries];
 
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c16 = l & 15;
@@ -390,7 +590,6 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
 
   const int64_t r0 = P.Q.off[q];
   const int m = (int)(P.Q.off[q + 1] - r0);
-  float* cm = lds_cm[w];
   float* sc = lds_sc[w];
 
   if (m == 0) {
@@ -403,7 +602,8 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
 
   for (int prow0 = 0; prow0 < m; prow0 += PASS) {
     const int pr = min(PASS, m - prow0);
-    const int nct = (pr + 15) >> 4;
+    const int nct = __builtin_amdgcn_readfirstlane((pr + 15) >> 4);
+    const bool first_pass = prow0 == 0;
     Frag B[NT];
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) {
@@ -438,37 +638,32 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
         if (ne_ < ne) { nbeg = rd64(my_beg, ne_); nlen = rd64(my_len, ne_); }
       }
       if (ne_ < ne) O::load(A_next, P.D.vecs, P.D.scales, nbeg + min((int64_t)(nt * 16 + c16), nlen - 1), g);
+      // all NT column tiles: tiles past the query's last vector have zero B
+      // operands and their maxima are never read
       f32x4 acc[NT];
 #pragma unroll
       for (int ct = 0; ct < NT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < O::kSteps; ++s) {
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct)
-          if (ct < nct) acc[ct] = O::mma(A, B[ct], acc[ct], s);
+        for (int ct = 0; ct < NT; ++ct) acc[ct] = O::mma(A, B[ct], acc[ct], s);
       }
 #pragma unroll
-      for (int ct = 0; ct < NT; ++ct)
-        if (ct < nct) rm[ct] = fmaxf(rm[ct], max4(acc[ct]));
+      for (int ct = 0; ct < NT; ++ct) update_max(rm[ct], acc[ct]);
       if (last_tile) {
+        float R[NT / 4];
+        tile_sums<NT>(rm, R);
+        float s_run = first_pass ? tile_sum_at<NT>(R, 0) : sc[e] + tile_sum_at<NT>(R, 0);
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct) {
-          if (ct < nct) {
-            float v = max_across_groups(rm[ct]);
-            if (l < 16) cm[16 * ct + l] = v;
-          }
-          rm[ct] = ninf;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (l == 0) {
-          float s_ = sc[e];
-          for (int a = 0; a < pr; ++a) s_ += cm[a];
-          sc[e] = s_;
-        }
-        __builtin_amdgcn_wave_barrier();
+        for (int ct = 1; ct < NT; ++ct)
+          if (ct < nct) s_run += tile_sum_at<NT>(R, ct);
+        if (l == 0) sc[e] = s_run;
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) rm[ct] = ninf;
       }
       e = ne_; t = nt; dbeg = nbeg; dlen = nlen;
     }
+    __builtin_amdgcn_wave_barrier();
   }
   __builtin_amdgcn_wave_barrier();
   if (l < ne) P.scores[e0 + l] = sc[l];
