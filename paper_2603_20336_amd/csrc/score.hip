@@ -47,6 +47,8 @@ template <> struct Op<GEM_F32> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[s], b.v[s], acc, 0, 0, 0);
   }
   static constexpr int kSteps = 32;
+  static constexpr bool kColumnScale = false;
+  static __device__ __forceinline__ void load_b(Frag& f, const void* v, const float* sc, int64_t row, int g) { load(f, v, sc, row, g); }
 };
 
 template <> struct Op<GEM_BF16> {
@@ -68,6 +70,8 @@ template <> struct Op<GEM_BF16> {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v[s], b.v[s], acc, 0, 0, 0);
   }
   static constexpr int kSteps = 4;
+  static constexpr bool kColumnScale = false;
+  static __device__ __forceinline__ void load_b(Frag& f, const void* v, const float* sc, int64_t row, int g) { load(f, v, sc, row, g); }
 };
 
 template <> struct Op<GEM_FP8_E4M3> {
@@ -83,6 +87,16 @@ template <> struct Op<GEM_FP8_E4M3> {
     f.v = i32x8{0, 0, 0, 0, 0, 0, 0, 0};
     f.scale = 127;
   }
+  // Query (B) side: codes only, unit block scale; the query vector's own
+  // power-of-two scale multiplies its column after the max over the document
+  // (max(s * x) = s * max(x) exactly for s = 2^e > 0).
+  static __device__ __forceinline__ void load_b(Frag& f, const void* vecs, const float*, int64_t row, int g) {
+    const uint4* p = reinterpret_cast<const uint4*>(static_cast<const char*>(vecs) + row * kRowBytes + g * 32);
+    uint4 a = p[0], b = p[1];
+    f.v = i32x8{(int)a.x, (int)a.y, (int)a.z, (int)a.w, (int)b.x, (int)b.y, (int)b.z, (int)b.w};
+    f.scale = 127;
+  }
+  static constexpr bool kColumnScale = true;
   static __device__ __forceinline__ f32x4 mma(const Frag& a, const Frag& b, f32x4 acc, int) {
     // OCP E4M3 for both operands (format code 0), E8M0 block scales from each
     // lane's row (A) / column (B); all four 32-wide blocks of a row share it.
@@ -126,11 +140,12 @@ int64_t dense_blocks_upper(int64_t n_q, int64_t n_rows, int block_rows, int max_
 // each tile for query column (16 ct + l % 16). Four tiles at a time:
 // two permlane16 swaps and one permlane32 swap leave tile (4i + r)'s column
 // maxima in row r (lanes 16r..16r+15) of R[i], already reduced over the four
-// lane groups; four DPP adds inside each 16-lane row then leave that tile's
-// column sum T in every lane of the row. Every step pairs fixed lanes, so T
+// lane groups (for FP8 each column is then multiplied by its query vector's
+// scale); four DPP adds inside each 16-lane row then leave that tile's column
+// sum T in every lane of the row. Every step pairs fixed lanes, so T
 // depends only on the tile's own values.
-template <int NT>
-__device__ __forceinline__ void tile_sums(const float (&rm)[NT], float (&R)[NT / 4]) {
+template <int NT, bool kScaled = false>
+__device__ __forceinline__ void tile_sums(const float (&rm)[NT], float (&R)[NT / 4], const float* colscale = nullptr) {
 #pragma unroll
   for (int i = 0; i < NT / 4; ++i) {
     auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(rm[4 * i + 0]), __float_as_uint(rm[4 * i + 1]), false, false);
@@ -139,6 +154,7 @@ __device__ __forceinline__ void tile_sums(const float (&rm)[NT], float (&R)[NT /
     const float cd = fmaxf(__uint_as_float(q[0]), __uint_as_float(q[1]));       // rows: C01 D01 C23 D23
     auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(ab), __float_as_uint(cd), false, false);
     float m = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));             // rows: A B C D
+    if constexpr (kScaled) m *= colscale[i];                                    // query vector's scale
     m += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0xb1, 0xf, 0xf, false));   // lane ^ 1
     m += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0x4e, 0xf, 0xf, false));   // lane ^ 2
     m += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0x141, 0xf, 0xf, false));  // half mirror
@@ -222,19 +238,32 @@ hipError_t launch_plan_query_blocks(const int64_t* q_off, int64_t n_q, int block
 // --------------------------------------------------------------------------
 // Dense scorer: every query block against every document of a 64-document
 // chunk. A workgroup is eight waves (two per SIMD, so one wave's MFMAs cover
-// the other's epilogue and waits) = eight query blocks on the same chunk. The
-// chunk's document tiles are staged through LDS and shared by the eight waves:
-// threads load 16-byte pieces of every tile, a group of kGroup tiles ahead,
-// into registers, then write them to one of two LDS group buffers; one
-// barrier per group. Inside a tile
-// row the 16-byte chunks are XOR-swizzled by the row index so that the 16
-// lanes reading the same chunk of 16 rows hit distinct banks.
+// the other's epilogue and waits) = eight query blocks on the same chunk.
+//
+// The chunk's document tiles stream through LDS and are shared by the eight
+// waves. They are copied HBM -> LDS by direct-to-LDS loads (no registers), in
+// groups of kGroup tiles, kBuffers group buffers deep: while one group is
+// multiplied the next two are in flight. Each wave waits for its own copies
+// with an explicit vector-memory count, then one barrier per group publishes
+// the group and frees the buffer the next copy overwrites. The loop holds no
+// other vector-memory operation and reads LDS only through fixed sequences
+// that wait for themselves, so no wait is ever widened to the copies still in
+// flight. Inside a tile row the 16-byte chunks are XOR-swizzled by the row
+// index, so the 16 lanes reading one chunk of 16 rows hit distinct banks.
+//
+// Scores stay in registers: at a document's end each finished query's score
+// is written into lane (document index) of a per-tile register, and a pass
+// ends with one coalesced 64-document row store per query.
 // Work items are laid out so that consecutive workgroups on one XCD (dispatch
 // is round-robin over the 8 XCDs) share a chunk.
 constexpr int kChunkDocs = 64;
-constexpr int kGroup = 4;
+constexpr int kGroup = 4;                      // tiles per group buffer (one barrier per group)
+constexpr int kBuffers = 3;                    // group buffers: two groups in flight
 constexpr int kDenseWaves = 8;                 // two waves per SIMD
 constexpr int kDenseThreads = 64 * kDenseWaves;
+
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 struct DenseParams {
   SetsView Q, D;
@@ -251,49 +280,105 @@ template <int DT> struct TileStage {
   static constexpr int kChunksPerRow = kRowBytes / 16;
   static constexpr int kTileBytes = 16 * kRowBytes;
   static constexpr int kSlots = kTileBytes / 16;                 // 16-byte pieces per tile
-  static constexpr int kPerThread = (kSlots + kDenseThreads - 1) / kDenseThreads;   // pieces a thread loads per tile
+  static constexpr int kPieceWaves = kSlots / 64;                // waves copying one piece per lane
   static constexpr bool kScales = DT == GEM_FP8_E4M3;
   static constexpr int kStageBytes = kTileBytes + (kScales ? 64 : 0);
+  static_assert(kSlots % 64 == 0 && kPieceWaves + (kScales ? 1 : 0) <= kDenseWaves, "tile copy layout");
 
   // chunk c of row r sits at position c ^ swz(r): the 16 rows read by one
   // 16-lane group then cover all 64 banks (128-byte rows pair up first)
   static __device__ __forceinline__ int swz(int r) { return kRowBytes == 128 ? ((r >> 1) & 7) : (r & 15); }
   // global address of piece `slot` of the tile whose rows start at doc row beg
-  static __device__ __forceinline__ const uint4* src(const void* vecs, int64_t beg, int64_t len, int t, int slot) {
+  static __device__ __forceinline__ const void* src(const void* vecs, int64_t beg, int64_t len, int t, int slot) {
     const int r = slot / kChunksPerRow, pos = slot % kChunksPerRow;
     const int c = pos ^ swz(r);
     const int64_t row = beg + min((int64_t)(16 * t + r), len - 1);
-    return reinterpret_cast<const uint4*>(static_cast<const char*>(vecs) + row * kRowBytes) + c;
+    return static_cast<const char*>(vecs) + row * kRowBytes + c * 16;
+  }
+  // this wave's share of copying one tile into the stage at LDS address `stage`
+  static __device__ __forceinline__ void copy(const void* vecs, const float* scales, int64_t beg, int64_t len,
+                                              int t, char* stage, int w, int l) {
+    if (w < kPieceWaves) {
+      __builtin_amdgcn_global_load_lds(src(vecs, beg, len, t, 64 * w + l), (lds_void_ptr)(stage + 1024 * w), 16, 0, 0);
+    } else if (kScales && w == kPieceWaves) {
+      if (l < 16)
+        __builtin_amdgcn_global_load_lds(scales + beg + min((int64_t)(16 * t + l), len - 1),
+                                         (lds_void_ptr)(stage + kTileBytes), 4, 0, 0);
+    }
   }
 };
 
+// s_waitcnt with only the vector-memory count set (expcnt / lgkmcnt left open)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0f70);
+}
+
+// A operand of one tile from its LDS stage: the reads and their wait form one
+// block, so the compiler never sees an LDS read it would order after the copies.
 template <int DT>
-__device__ __forceinline__ void frag_from_lds(typename Op<DT>::Frag& f, const char* stage, int c16, int g);
+__device__ __forceinline__ void frag_from_lds(typename Op<DT>::Frag& f, uint32_t stage, int c16, int g);
 
 template <>
-__device__ __forceinline__ void frag_from_lds<GEM_F32>(Op<GEM_F32>::Frag& f, const char* stage, int c16, int g) {
-  const char* row = stage + c16 * 512;
+__device__ __forceinline__ void frag_from_lds<GEM_BF16>(Op<GEM_BF16>::Frag& f, uint32_t stage, int c16, int g) {
+  const uint32_t row = stage + c16 * 256;
+  const uint32_t a0 = row + (((4 * g + 0) ^ (c16 & 15)) << 4), a1 = row + (((4 * g + 1) ^ (c16 & 15)) << 4);
+  const uint32_t a2 = row + (((4 * g + 2) ^ (c16 & 15)) << 4), a3 = row + (((4 * g + 3) ^ (c16 & 15)) << 4);
+  u32x4 v0, v1, v2, v3;
+  asm volatile("ds_read_b128 %0, %4\n\tds_read_b128 %1, %5\n\tds_read_b128 %2, %6\n\tds_read_b128 %3, %7\n\t"
+               "s_waitcnt lgkmcnt(0)"
+               : "=&v"(v0), "=&v"(v1), "=&v"(v2), "=&v"(v3)
+               : "v"(a0), "v"(a1), "v"(a2), "v"(a3)
+               : "memory");
+  f.v[0] = __builtin_bit_cast(bf16x8, v0);
+  f.v[1] = __builtin_bit_cast(bf16x8, v1);
+  f.v[2] = __builtin_bit_cast(bf16x8, v2);
+  f.v[3] = __builtin_bit_cast(bf16x8, v3);
+}
+
+template <>
+__device__ __forceinline__ void frag_from_lds<GEM_FP8_E4M3>(Op<GEM_FP8_E4M3>::Frag& f, uint32_t stage, int c16, int g) {
+  const uint32_t row = stage + c16 * 128;
+  const uint32_t a0 = row + (((2 * g) ^ ((c16 >> 1) & 7)) << 4);
+  const uint32_t a1 = row + (((2 * g + 1) ^ ((c16 >> 1) & 7)) << 4);
+  const uint32_t as = stage + 16 * 128 + 4 * c16;
+  u32x4 v0, v1;
+  uint32_t sc;
+  asm volatile("ds_read_b128 %0, %3\n\tds_read_b128 %1, %4\n\tds_read_b32 %2, %5\n\ts_waitcnt lgkmcnt(0)"
+               : "=&v"(v0), "=&v"(v1), "=&v"(sc)
+               : "v"(a0), "v"(a1), "v"(as)
+               : "memory");
+  f.v = i32x8{(int)v0.x, (int)v0.y, (int)v0.z, (int)v0.w, (int)v1.x, (int)v1.y, (int)v1.z, (int)v1.w};
+  f.scale = (int)((sc >> 23) & 0xffu);
+}
+
+template <>
+__device__ __forceinline__ void frag_from_lds<GEM_F32>(Op<GEM_F32>::Frag& f, uint32_t stage, int c16, int g) {
+  const uint32_t row = stage + c16 * 512;
+  uint32_t a[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) a[s] = row + (((8 * g + s) ^ (c16 & 15)) << 4);
+  u32x4 v0, v1, v2, v3, v4, v5, v6, v7;
+  asm volatile("ds_read_b128 %0, %8\n\tds_read_b128 %1, %9\n\tds_read_b128 %2, %10\n\tds_read_b128 %3, %11\n\t"
+               "ds_read_b128 %4, %12\n\tds_read_b128 %5, %13\n\tds_read_b128 %6, %14\n\tds_read_b128 %7, %15\n\t"
+               "s_waitcnt lgkmcnt(0)"
+               : "=&v"(v0), "=&v"(v1), "=&v"(v2), "=&v"(v3), "=&v"(v4), "=&v"(v5), "=&v"(v6), "=&v"(v7)
+               : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]), "v"(a[7])
+               : "memory");
+  const u32x4 vv[8] = {v0, v1, v2, v3, v4, v5, v6, v7};
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
-    const float4 v = *reinterpret_cast<const float4*>(row + (((8 * g + s) ^ (c16 & 15)) << 4));
-    f.v[4 * s + 0] = v.x; f.v[4 * s + 1] = v.y; f.v[4 * s + 2] = v.z; f.v[4 * s + 3] = v.w;
+    f.v[4 * s + 0] = __uint_as_float(vv[s].x); f.v[4 * s + 1] = __uint_as_float(vv[s].y);
+    f.v[4 * s + 2] = __uint_as_float(vv[s].z); f.v[4 * s + 3] = __uint_as_float(vv[s].w);
   }
 }
-template <>
-__device__ __forceinline__ void frag_from_lds<GEM_BF16>(Op<GEM_BF16>::Frag& f, const char* stage, int c16, int g) {
-  const char* row = stage + c16 * 256;
-#pragma unroll
-  for (int s = 0; s < 4; ++s)
-    f.v[s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(row + (((4 * g + s) ^ (c16 & 15)) << 4)));
+
+__device__ __forceinline__ float writelane_f(float old, float v, int lane) {
+  return lane_id() == lane ? v : old;
 }
-template <>
-__device__ __forceinline__ void frag_from_lds<GEM_FP8_E4M3>(Op<GEM_FP8_E4M3>::Frag& f, const char* stage, int c16, int g) {
-  const char* row = stage + c16 * 128;
-  const uint4 a = *reinterpret_cast<const uint4*>(row + (((2 * g) ^ ((c16 >> 1) & 7)) << 4));
-  const uint4 b = *reinterpret_cast<const uint4*>(row + (((2 * g + 1) ^ ((c16 >> 1) & 7)) << 4));
-  f.v = i32x8{(int)a.x, (int)a.y, (int)a.z, (int)a.w, (int)b.x, (int)b.y, (int)b.z, (int)b.w};
-  const float sc = reinterpret_cast<const float*>(stage + 16 * 128)[c16];
-  f.scale = (int)((__float_as_uint(sc) >> 23) & 0xffu);
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+  return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), lane));
 }
 
 template <int DT>
@@ -302,9 +387,7 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
   using Frag = typename O::Frag;
   using TS = TileStage<DT>;
   constexpr int NT = DenseCfg<DT>::kNT;
-  constexpr int PT = TS::kPerThread;
-  __shared__ float lds_sc[kDenseWaves][kBlockMaxQueries * kChunkDocs];
-  __shared__ __attribute__((aligned(16))) char lds_tiles[2][kGroup][TS::kStageBytes];
+  __shared__ __attribute__((aligned(1024))) char lds_tiles[kBuffers][kGroup][TS::kStageBytes];
   __shared__ int lds_npass[kDenseWaves];
 
   const int tid = threadIdx.x;
@@ -314,15 +397,18 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
   const int64_t item = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (item >= total) return;                                   // whole workgroup
   const int64_t chunk = item / P.n_bgroups;
-  const int64_t b = (item % P.n_bgroups) * kDenseWaves + w;
+  const int64_t b0 = (item % P.n_bgroups) * kDenseWaves;
+  // blocks past the plan's count are empty (their start is n_q): a group whose
+  // first block is empty has nothing to do
+  if (b0 >= P.n_blocks_max || P.qb[b0] >= P.Q.n_sets) return;   // whole workgroup
+  const int64_t b = b0 + w;
   int q0 = 0, q1 = 0;
   if (b < P.n_blocks_max) { q0 = P.qb[b]; q1 = P.qb[b + 1]; }
-  const int nq = max(q1 - q0, 0);                              // 0: this wave only helps load
+  const int nq = max(q1 - q0, 0);                              // 0: this wave only helps copy
   const int64_t p0 = chunk * kChunkDocs;
   const int64_t p1 = min(P.D.n_sets, p0 + kChunkDocs);
   const int nd = (int)(p1 - p0);
   const float ninf = neg_inf();
-  float* sc = lds_sc[w];
 
   // lane j < nq: query j of the block (first row, length, first tile, tiles)
   int64_t qrow = 0;
@@ -339,28 +425,25 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
     total_tiles = (int)((P.qcol[q1] - col0) >> 4);
   }
   total_tiles = __builtin_amdgcn_readfirstlane(total_tiles);
-  // every wave runs the same number of passes over the chunk (it shares the loads)
-  if (l == 0) lds_npass[w] = (total_tiles + NT - 1) / NT;
-  // lane j <= nd: offset of document p0 + j (lane 64 does not exist: use doff_end)
+  // lane dd <= nd: offset of document p0 + dd; lane dd < nd: is document dd empty
   const int64_t doff_lane = (l <= nd) ? P.D.off[p0 + l] : 0;
   const int64_t doff_end = P.D.off[p1];
+  if (l == 0) lds_npass[w] = (total_tiles + NT - 1) / NT;
+  __builtin_amdgcn_s_waitcnt(0);                               // nothing in flight before the tile stream
+  __syncthreads();
+  int n_pass = 0;
+#pragma unroll
+  for (int i = 0; i < kDenseWaves; ++i) n_pass = max(n_pass, lds_npass[i]);
   auto rd64 = [&](int64_t v, int lane) -> int64_t {
     uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
     uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), lane);
     return (int64_t)(((uint64_t)hi << 32) | lo);
   };
   auto doc_start = [&](int dd) -> int64_t { return dd >= 64 ? doff_end : rd64(doff_lane, dd); };
-
-  // empty queries score 0 against every document; empty documents score -inf
-  if (l < nq && qm == 0)
-    for (int dd = 0; dd < nd; ++dd) sc[l * kChunkDocs + dd] = 0.0f;
-  for (int dd = 0; dd < nd; ++dd)
-    if (doc_start(dd + 1) == doc_start(dd) && l < nq) sc[l * kChunkDocs + dd] = qm > 0 ? ninf : 0.0f;
-  __syncthreads();
-  int n_pass = 0;
-#pragma unroll
-  for (int i = 0; i < kDenseWaves; ++i) n_pass = max(n_pass, lds_npass[i]);
-
+  const uint32_t nx_lo = (uint32_t)__shfl_down((int)(uint32_t)doff_lane, 1);
+  const uint32_t nx_hi = (uint32_t)__shfl_down((int)(uint32_t)(doff_lane >> 32), 1);
+  const int64_t doff_next = (l == 63) ? doff_end : (int64_t)(((uint64_t)nx_hi << 32) | nx_lo);
+  const bool doc_empty = l < nd && doff_next == doff_lane;
   auto skip_empty = [&](int dd) -> int {
     while (dd < nd && doc_start(dd + 1) == doc_start(dd)) ++dd;
     return dd;
@@ -368,12 +451,17 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
   const int dd_first = skip_empty(0);
   const int64_t beg_first = dd_first < nd ? doc_start(dd_first) : 0;
   const int64_t len_first = dd_first < nd ? doc_start(dd_first + 1) - beg_first : 1;
+  const uint32_t lds0 = (uint32_t)(size_t)(lds_void_ptr)&lds_tiles[0][0][0];
 
+  float part = 0.0f;                                            // lane dd: partial score carried to the next pass
   for (int pass = 0; pass < n_pass; ++pass) {
     const int pt0 = pass * NT;
     const int nct = __builtin_amdgcn_readfirstlane(max(0, min(NT, total_tiles - pt0)));
     // tile map of this pass: owner query, first/last flags, B operand rows
     Frag B[NT];
+    float qs[NT / 4];                                           // FP8: scale of this lane's column in R[i]
+#pragma unroll
+    for (int i = 0; i < NT / 4; ++i) qs[i] = 1.0f;
     int tq_lane = 0;                                            // lane ct: query owning tile ct
     uint64_t first_mask = 0, last_mask = 0;
 #pragma unroll
@@ -390,76 +478,59 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
         if (l == ct) tq_lane = j;
         if (k == 0) first_mask |= 1ull << ct;
         if (16 * (k + 1) >= jm) last_mask |= 1ull << ct;
-        if (16 * k + c16 < jm) O::load(B[ct], P.Q.vecs, P.Q.scales, jrow + 16 * k + c16, g);
+        if (16 * k + c16 < jm) {
+          O::load_b(B[ct], P.Q.vecs, P.Q.scales, jrow + 16 * k + c16, g);
+          if constexpr (O::kColumnScale)
+            if (g == (ct & 3)) qs[ct >> 2] = P.Q.scales[jrow + 16 * k + c16];
+        }
       }
     }
-    float rm[NT];
+    float rm[NT], scr[NT];
 #pragma unroll
-    for (int ct = 0; ct < NT; ++ct) rm[ct] = ninf;
+    for (int ct = 0; ct < NT; ++ct) { rm[ct] = ninf; scr[ct] = 0.0f; }
+    __builtin_amdgcn_s_waitcnt(0);                             // operands in; the stream starts from zero
 
-    // tile pipeline: registers hold the next group while the current one is used.
-    // Load cursor (l_*) runs one group ahead of the compute cursor (c_*); past
-    // the last tile the load cursor re-reads the first tile (never used).
+    // copy cursor (l_*) runs kBuffers-1 groups ahead of the compute cursor (c_*)
     int l_dd = dd_first, l_t = 0;
     int64_t l_beg = beg_first, l_len = len_first;
     int c_dd = dd_first, c_t = 0;
-    int64_t c_beg = beg_first, c_len = len_first;
-    static_assert(kGroup == 4, "the staging code below is written out for four tiles");
-    uint4 R0[PT], R1[PT], R2[PT], R3[PT];                      // 16-byte pieces of the next group
-    uint4 S0 = {}, S1 = {}, S2 = {}, S3 = {};                    // FP8: four row scales per piece
-    // load one tile at the load cursor into (Rx, Sx), then advance the cursor
-#define GEM_LOAD_TILE(Rx, Sx)                                                                           \
-    {                                                                                                   \
-      const bool ok_ = l_dd < nd;                                                                       \
-      const int64_t lb_ = ok_ ? l_beg : beg_first, ll_ = ok_ ? l_len : len_first;                      \
-      const int lt_ = ok_ ? l_t : 0;                                                                    \
-      _Pragma("unroll") for (int v = 0; v < PT; ++v)                                                    \
-        if (tid + kDenseThreads * v < TS::kSlots)                                                       \
-          Rx[v] = *TS::src(P.D.vecs, lb_, ll_, lt_, tid + kDenseThreads * v);                          \
-      if (TS::kScales && tid < 4) {                                                                     \
-        const int r_ = 4 * tid;                                                                         \
-        Sx = make_uint4(__float_as_uint(P.D.scales[lb_ + min((int64_t)(16 * lt_ + r_ + 0), ll_ - 1)]),  \
-                        __float_as_uint(P.D.scales[lb_ + min((int64_t)(16 * lt_ + r_ + 1), ll_ - 1)]),  \
-                        __float_as_uint(P.D.scales[lb_ + min((int64_t)(16 * lt_ + r_ + 2), ll_ - 1)]),  \
-                        __float_as_uint(P.D.scales[lb_ + min((int64_t)(16 * lt_ + r_ + 3), ll_ - 1)])); \
-      }                                                                                                 \
-      if (ok_) {                                                                                        \
-        if ((int64_t)(l_t + 1) * 16 < l_len) ++l_t;                                                    \
-        else {                                                                                          \
-          l_dd = skip_empty(l_dd + 1); l_t = 0;                                                         \
-          if (l_dd < nd) { l_beg = doc_start(l_dd); l_len = doc_start(l_dd + 1) - l_beg; }            \
-        }                                                                                               \
-      }                                                                                                 \
-    }
-    // write one staged tile into slot u of an LDS group buffer
-#define GEM_STORE_TILE(Rx, Sx, u)                                                                       \
-    {                                                                                                   \
-      _Pragma("unroll") for (int v = 0; v < PT; ++v) {                                                  \
-        const int slot_ = tid + kDenseThreads * v;                                                      \
-        if (slot_ < TS::kSlots) *reinterpret_cast<uint4*>(buf + (u) * TS::kStageBytes + slot_ * 16) = Rx[v]; \
-      }                                                                                                 \
-      if constexpr (TS::kScales) {                                                                      \
-        if (tid < 4) *reinterpret_cast<uint4*>(buf + (u) * TS::kStageBytes + TS::kTileBytes + tid * 16) = Sx; \
-      }                                                                                                 \
-    }
-    GEM_LOAD_TILE(R0, S0) GEM_LOAD_TILE(R1, S1) GEM_LOAD_TILE(R2, S2) GEM_LOAD_TILE(R3, S3)
+    int64_t c_len = len_first;
+    int issued_full = 0;                                        // groups after the current one, fully issued
+    auto issue_group = [&](int buf) -> bool {                   // true if all kGroup tiles were issued
+      int n = 0;
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) {
+        if (l_dd < nd) {
+          TS::copy(P.D.vecs, P.D.scales, l_beg, l_len, l_t, &lds_tiles[buf][u][0], w, l);
+          ++n;
+          if ((int64_t)(l_t + 1) * 16 < l_len) ++l_t;
+          else {
+            l_dd = skip_empty(l_dd + 1); l_t = 0;
+            if (l_dd < nd) { l_beg = doc_start(l_dd); l_len = doc_start(l_dd + 1) - l_beg; }
+          }
+        }
+      }
+      return n == kGroup;
+    };
+    issue_group(0);
+    issued_full = issue_group(1) ? 1 : 0;
     for (int grp = 0; c_dd < nd; ++grp) {
-      char* buf = lds_tiles[grp & 1][0];
-      // land the group that arrived, start loading the next one
-      GEM_STORE_TILE(R0, S0, 0) GEM_STORE_TILE(R1, S1, 1) GEM_STORE_TILE(R2, S2, 2) GEM_STORE_TILE(R3, S3, 3)
-      GEM_LOAD_TILE(R0, S0) GEM_LOAD_TILE(R1, S1) GEM_LOAD_TILE(R2, S2) GEM_LOAD_TILE(R3, S3)
-      __syncthreads();
+      const int buf = grp % kBuffers;
+      // this wave's copies of group grp are done when at most one later group is in flight
+      if (issued_full) wait_vm<kGroup>(); else wait_vm<0>();
+      __builtin_amdgcn_s_barrier();                             // group grp landed; buffer grp-1 is free
+      issued_full = issue_group((grp + kBuffers - 1) % kBuffers) ? 1 : 0;
+      const uint32_t gbase = lds0 + (uint32_t)(buf * kGroup * TS::kStageBytes);
 #pragma nounroll
       for (int u = 0; u < kGroup; ++u) {
         if (c_dd < nd) {
           const bool last_tile = (int64_t)(c_t + 1) * 16 >= c_len;
           if (nct > 0) {
             Frag A;
-            frag_from_lds<DT>(A, buf + u * TS::kStageBytes, c16, g);
+            frag_from_lds<DT>(A, gbase + u * TS::kStageBytes, c16, g);
             // column tiles in groups of 4 (a group past the last used tile is
             // skipped; unused tiles inside a group have zero B operands and
-            // their maxima are never read): independent accumulators keep the
-            // MFMA pipe busy without holding every tile's accumulator at once
+            // their maxima are never read)
 #pragma unroll
             for (int g0 = 0; g0 < NT; g0 += 4) {
               if (g0 < nct) {
@@ -477,19 +548,18 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
             }
             if (last_tile) {
               float Rs[NT / 4];
-              tile_sums<NT>(rm, Rs);
-              // each query's score: its tile sums in tile order
-              float s_run = 0.0f;
+              tile_sums<NT, O::kColumnScale>(rm, Rs, qs);
+              // each query's score: its tile sums in tile order, parked in lane dd
               const int dd = c_dd;
+              float s_run = 0.0f;
 #pragma unroll
               for (int ct = 0; ct < NT; ++ct) {
                 if (ct < nct) {
                   const float T = tile_sum_at<NT>(Rs, ct);
                   if ((first_mask >> ct) & 1) s_run = T;
-                  else if (ct == 0) s_run = sc[__builtin_amdgcn_readlane(tq_lane, 0) * kChunkDocs + dd] + T;
+                  else if (ct == 0) s_run = readlane_f(part, dd) + T;     // continues from the previous pass
                   else s_run += T;
-                  if ((((last_mask >> ct) & 1) || ct == nct - 1) && l == 0)
-                    sc[__builtin_amdgcn_readlane(tq_lane, ct) * kChunkDocs + dd] = s_run;
+                  if (((last_mask >> ct) & 1) || ct == nct - 1) scr[ct] = writelane_f(scr[ct], s_run, dd);
                 }
                 rm[ct] = ninf;
               }
@@ -498,21 +568,32 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
           if (!last_tile) ++c_t;
           else {
             c_dd = skip_empty(c_dd + 1); c_t = 0;
-            if (c_dd < nd) { c_beg = doc_start(c_dd); c_len = doc_start(c_dd + 1) - c_beg; }
+            if (c_dd < nd) c_len = doc_start(c_dd + 1) - doc_start(c_dd);
           }
         }
       }
     }
-    __syncthreads();                                             // buffers are reused by the next pass
-#undef GEM_LOAD_TILE
-#undef GEM_STORE_TILE
+    wait_vm<0>();                                               // no copy outlives the pass
+    __syncthreads();                                            // buffers are reused by the next pass
+    // finished queries: one 64-document row each (empty documents score -inf)
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) {
+      if (ct < nct) {
+        if ((last_mask >> ct) & 1) {
+          const int j = __builtin_amdgcn_readlane(tq_lane, ct);
+          const int64_t row = P.out.rows ? (int64_t)P.out.rows[q0 + j] : (int64_t)(q0 + j);
+          if (l < nd) P.out.scores[row * P.out.ld + p0 + l] = doc_empty ? ninf : scr[ct];
+        } else if (ct == nct - 1) {
+          part = scr[ct];
+        }
+      }
+    }
   }
-  __builtin_amdgcn_wave_barrier();
-  // write the chunk's scores, one 64-document row segment per query
+  // empty queries score 0 against every document
   for (int j = 0; j < nq; ++j) {
-    if (l < nd) {
+    if (__builtin_amdgcn_readlane(qm, j) == 0 && l < nd) {
       const int64_t row = P.out.rows ? (int64_t)P.out.rows[q0 + j] : (int64_t)(q0 + j);
-      P.out.scores[row * P.out.ld + p0 + l] = sc[j * kChunkDocs + l];
+      P.out.scores[row * P.out.ld + p0 + l] = 0.0f;
     }
   }
 }
@@ -560,6 +641,7 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
   constexpr int NT = kGatherNT;
   constexpr int PASS = 16 * NT;
   __shared__ float lds_sc[4][kGatherEntries];
+  __shared__ int64_t lds_ent[4][kGatherEntries][2];
 
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c16 = l & 15;
   const int64_t gw = (int64_t)blockIdx.x * 4 + w;
@@ -575,18 +657,19 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
   const int ne = (int)(e1 - e0);
   const float ninf = neg_inf();
 
-  // lane e < ne: the entry's document id and row range
+  // lane e < ne: the entry's document id and row range, kept in LDS so that
+  // the per-entry bookkeeping never waits on the vector-memory counter
   int32_t my_id = -1;
   int64_t my_beg = 0, my_len = 0;
   if (l < ne) {
     my_id = P.C.ids[e0 + l];
     if (my_id >= 0) { my_beg = P.D.off[my_id]; my_len = P.D.off[my_id + 1] - my_beg; }
+    lds_ent[w][l][0] = my_beg;
+    lds_ent[w][l][1] = my_len;
   }
-  auto rd64 = [&](int64_t v, int e) -> int64_t {
-    uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, e);
-    uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), e);
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-  };
+  __builtin_amdgcn_wave_barrier();
+  auto ent_beg = [&](int e) -> int64_t { return lds_ent[w][e][0]; };
+  auto ent_len = [&](int e) -> int64_t { return lds_ent[w][e][1]; };
 
   const int64_t r0 = P.Q.off[q];
   const int m = (int)(P.Q.off[q + 1] - r0);
@@ -605,14 +688,22 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
     const int nct = __builtin_amdgcn_readfirstlane((pr + 15) >> 4);
     const bool first_pass = prow0 == 0;
     Frag B[NT];
+    float qs[NT / 4];
+#pragma unroll
+    for (int i = 0; i < NT / 4; ++i) qs[i] = 1.0f;
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) {
       const int col = prow0 + 16 * ct + c16;
-      if (ct < nct && col < m) O::load(B[ct], P.Q.vecs, P.Q.scales, r0 + col, g);
-      else O::zero(B[ct]);
+      if (ct < nct && col < m) {
+        O::load_b(B[ct], P.Q.vecs, P.Q.scales, r0 + col, g);
+        if constexpr (O::kColumnScale)
+          if (g == (ct & 3)) qs[ct >> 2] = P.Q.scales[r0 + col];
+      } else {
+        O::zero(B[ct]);
+      }
     }
     auto next_entry = [&](int e) -> int {          // next entry with a non-empty document
-      while (e < ne && rd64(my_len, e) == 0) ++e;
+      while (e < ne && ent_len(e) == 0) ++e;
       return e;
     };
     int e = next_entry(0);
@@ -620,8 +711,8 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
     int64_t dbeg = 0, dlen = 0;
     Frag A_next;
     if (e < ne) {
-      dbeg = rd64(my_beg, e);
-      dlen = rd64(my_len, e);
+      dbeg = ent_beg(e);
+      dlen = ent_len(e);
       O::load(A_next, P.D.vecs, P.D.scales, dbeg + min((int64_t)c16, dlen - 1), g);
     }
     float rm[NT];
@@ -635,7 +726,7 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
       if (last_tile) {
         ne_ = next_entry(e + 1);
         nt = 0;
-        if (ne_ < ne) { nbeg = rd64(my_beg, ne_); nlen = rd64(my_len, ne_); }
+        if (ne_ < ne) { nbeg = ent_beg(ne_); nlen = ent_len(ne_); }
       }
       if (ne_ < ne) O::load(A_next, P.D.vecs, P.D.scales, nbeg + min((int64_t)(nt * 16 + c16), nlen - 1), g);
       // all NT column tiles: tiles past the query's last vector have zero B
@@ -652,7 +743,7 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
       for (int ct = 0; ct < NT; ++ct) update_max(rm[ct], acc[ct]);
       if (last_tile) {
         float R[NT / 4];
-        tile_sums<NT>(rm, R);
+        tile_sums<NT, O::kColumnScale>(rm, R, qs);
         float s_run = first_pass ? tile_sum_at<NT>(R, 0) : sc[e] + tile_sum_at<NT>(R, 0);
 #pragma unroll
         for (int ct = 1; ct < NT; ++ct)
