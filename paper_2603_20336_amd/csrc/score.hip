@@ -107,9 +107,10 @@ template <> struct Op<GEM_FP8_E4M3> {
 
 // Column tiles (16 query vectors each) held in registers by one pass.
 template <int DT> struct DenseCfg;
-template <> struct DenseCfg<GEM_F32> { static constexpr int kNT = 4; };
-template <> struct DenseCfg<GEM_BF16> { static constexpr int kNT = 8; };
-template <> struct DenseCfg<GEM_FP8_E4M3> { static constexpr int kNT = 16; };
+// kNT: 16-column tiles a wave holds; kGroup: document tiles per LDS group buffer.
+template <> struct DenseCfg<GEM_F32> { static constexpr int kNT = 4; static constexpr int kGroup = 4; };
+template <> struct DenseCfg<GEM_BF16> { static constexpr int kNT = 8; static constexpr int kGroup = 8; };
+template <> struct DenseCfg<GEM_FP8_E4M3> { static constexpr int kNT = 16; static constexpr int kGroup = 8; };
 
 int dense_pass_rows(int dtype) {
   switch (dtype) {
@@ -243,7 +244,8 @@ hipError_t launch_plan_query_blocks(const int64_t* q_off, int64_t n_q, int block
 // The chunk's document tiles stream through LDS and are shared by the eight
 // waves. They are copied HBM -> LDS by direct-to-LDS loads (no registers), in
 // groups of kGroup tiles, kBuffers group buffers deep: while one group is
-// multiplied the next two are in flight. Each wave waits for its own copies
+// multiplied the next two are in flight. The copies rotate over the waves so
+// that every wave issues the same number per group. Each wave waits for its own copies
 // with an explicit vector-memory count, then one barrier per group publishes
 // the group and frees the buffer the next copy overwrites. The loop holds no
 // other vector-memory operation and reads LDS only through fixed sequences
@@ -257,7 +259,6 @@ hipError_t launch_plan_query_blocks(const int64_t* q_off, int64_t n_q, int block
 // Work items are laid out so that consecutive workgroups on one XCD (dispatch
 // is round-robin over the 8 XCDs) share a chunk.
 constexpr int kChunkDocs = 64;
-constexpr int kGroup = 4;                      // tiles per group buffer (one barrier per group)
 constexpr int kBuffers = 3;                    // group buffers: two groups in flight
 constexpr int kDenseWaves = 8;                 // two waves per SIMD
 constexpr int kDenseThreads = 64 * kDenseWaves;
@@ -282,8 +283,14 @@ template <int DT> struct TileStage {
   static constexpr int kSlots = kTileBytes / 16;                 // 16-byte pieces per tile
   static constexpr int kPieceWaves = kSlots / 64;                // waves copying one piece per lane
   static constexpr bool kScales = DT == GEM_FP8_E4M3;
+  static constexpr int kCopyWaves = kPieceWaves + (kScales ? 1 : 0);   // waves busy copying one tile
   static constexpr int kStageBytes = kTileBytes + (kScales ? 64 : 0);
-  static_assert(kSlots % 64 == 0 && kPieceWaves + (kScales ? 1 : 0) <= kDenseWaves, "tile copy layout");
+  static constexpr int kGroup = DenseCfg<DT>::kGroup;
+  // tile u of a group is copied by waves kCopyWaves*u .. kCopyWaves*u + kCopyWaves-1
+  // (mod 8), so over a group every wave issues the same number of copies
+  static constexpr int kCopiesPerWave = kGroup * kCopyWaves / kDenseWaves;
+  static_assert(kSlots % 64 == 0 && kCopyWaves <= kDenseWaves, "tile copy layout");
+  static_assert((kGroup * kCopyWaves) % kDenseWaves == 0, "copies must spread evenly over the waves");
 
   // chunk c of row r sits at position c ^ swz(r): the 16 rows read by one
   // 16-lane group then cover all 64 banks (128-byte rows pair up first)
@@ -295,12 +302,14 @@ template <int DT> struct TileStage {
     const int64_t row = beg + min((int64_t)(16 * t + r), len - 1);
     return static_cast<const char*>(vecs) + row * kRowBytes + c * 16;
   }
-  // this wave's share of copying one tile into the stage at LDS address `stage`
+  // this wave's share of copying tile u of a group into the stage at LDS address `stage`
   static __device__ __forceinline__ void copy(const void* vecs, const float* scales, int64_t beg, int64_t len,
-                                              int t, char* stage, int w, int l) {
-    if (w < kPieceWaves) {
-      __builtin_amdgcn_global_load_lds(src(vecs, beg, len, t, 64 * w + l), (lds_void_ptr)(stage + 1024 * w), 16, 0, 0);
-    } else if (kScales && w == kPieceWaves) {
+                                              int t, char* stage, int u, int w, int l) {
+    const int role = (w - kCopyWaves * u) & (kDenseWaves - 1);
+    if (role < kPieceWaves) {
+      __builtin_amdgcn_global_load_lds(src(vecs, beg, len, t, 64 * role + l), (lds_void_ptr)(stage + 1024 * role),
+                                       16, 0, 0);
+    } else if (kScales && role == kPieceWaves) {
       if (l < 16)
         __builtin_amdgcn_global_load_lds(scales + beg + min((int64_t)(16 * t + l), len - 1),
                                          (lds_void_ptr)(stage + kTileBytes), 4, 0, 0);
@@ -387,6 +396,7 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
   using Frag = typename O::Frag;
   using TS = TileStage<DT>;
   constexpr int NT = DenseCfg<DT>::kNT;
+  constexpr int kGroup = TS::kGroup;
   __shared__ __attribute__((aligned(1024))) char lds_tiles[kBuffers][kGroup][TS::kStageBytes];
   __shared__ int lds_npass[kDenseWaves];
 
@@ -501,7 +511,7 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
 #pragma unroll
       for (int u = 0; u < kGroup; ++u) {
         if (l_dd < nd) {
-          TS::copy(P.D.vecs, P.D.scales, l_beg, l_len, l_t, &lds_tiles[buf][u][0], w, l);
+          TS::copy(P.D.vecs, P.D.scales, l_beg, l_len, l_t, &lds_tiles[buf][u][0], u, w, l);
           ++n;
           if ((int64_t)(l_t + 1) * 16 < l_len) ++l_t;
           else {
@@ -517,7 +527,7 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
     for (int grp = 0; c_dd < nd; ++grp) {
       const int buf = grp % kBuffers;
       // this wave's copies of group grp are done when at most one later group is in flight
-      if (issued_full) wait_vm<kGroup>(); else wait_vm<0>();
+      if (issued_full) wait_vm<TS::kCopiesPerWave>(); else wait_vm<0>();
       __builtin_amdgcn_s_barrier();                             // group grp landed; buffer grp-1 is free
       issued_full = issue_group((grp + kBuffers - 1) % kBuffers) ? 1 : 0;
       const uint32_t gbase = lds0 + (uint32_t)(buf * kGroup * TS::kStageBytes);
