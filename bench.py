@@ -207,7 +207,100 @@ def bench_exhaustive(args):
     line.update(res)
     if "cpu_baseline" not in line:
         line["cpu_baseline"] = None
-    return line
+    return line, (D8, D32)
+
+
+def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_chunks=8):
+    """Continuous-batching serving loop on the resident corpus: QPS and p50/p99 latency."""
+    from paper_2603_20336_amd import serve
+    w5 = wl.WORKLOADS[5]
+    q = wl.queries(w5, n_queries=n_req, query_len=q_len)
+    arrivals = wl.poisson_arrivals(rate, n_req, 0).numpy()
+    off = q.offsets.numpy()
+    vecs = q.vecs.numpy()
+    reqs = [serve.Request(i, vecs[off[i]:off[i + 1]], float(arrivals[i])) for i in range(n_req)]
+    ex = serve.DeviceExecutor(D8, D32, n_chunks=n_chunks, max_slots=1024, shortlist=w5.shortlist, k=w5.k)
+    eng = serve.ServingEngine(ex, max_slots=1024, mem_budget_bytes=8 << 30)
+    # warm-up on a few requests, then the measured run
+    warm = serve.ServingEngine(ex, max_slots=1024, mem_budget_bytes=8 << 30)
+    warm.run([serve.Request(-1 - i, r.vecs, 0.0) for i, r in enumerate(reqs[:8])])
+    torch.cuda.synchronize()
+    done = eng.run(reqs)
+    st = serve.latency_stats(done)
+    st.update({"rate_per_s": rate, "requests": n_req, "chunks": n_chunks, "iterations": eng.iteration,
+               "shortlist": w5.shortlist, "k": w5.k, "query_len": f"U{{{q_len[1]}..{q_len[2]}}}"})
+    return st
+
+
+def bench_expansion(args):
+    """Batched beam expansion on the 1M-document corpus: 20 graph-captured steps."""
+    from paper_2603_20336_amd.search import ExpansionGraph
+    dev = torch.device("cuda:0")
+    w4 = wl.WORKLOADS[4]
+    n_docs = args.expand_docs
+    log(f"expansion: generating {n_docs} documents")
+    c = wl.corpus(w4, device=dev, n_docs=n_docs)
+    q = wl.queries(w4, device=dev)
+    D32 = gem.Sets(c.vecs, c.offsets, "f32", c.max_len())
+    D8 = gem.quantize_fp8(D32)
+    Q32 = gem.Sets(q.vecs, q.offsets, "f32", q.max_len())
+    Q8 = gem.quantize_fp8(Q32)
+    steps, uniq_bytes, pair_bytes = [], 0, 0
+    lens = (c.offsets[1:] - c.offsets[:-1])
+    for st in range(w4.steps):
+        off, ids = wl.step_candidates(w4, st, device=dev, n_docs=n_docs)
+        steps.append(gem.Cands(ids, off, max_list_len=w4.cands_per_step))
+        rows = lens[ids.long()]
+        pair_bytes += int(rows.sum().item()) * 132
+        uniq = torch.unique(ids)
+        uniq_bytes += int(lens[uniq.long()].sum().item()) * 132
+    eg = ExpansionGraph(Q8, D8, steps, ef=w4.ef)
+    eg.capture()
+    eg.replay()
+    torch.cuda.synchronize()
+    ms = timed(eg.replay, 3)
+    per_step = ms / w4.steps
+    r_ms = timed(lambda: eg.rerank(Q32, D32, 100), 1)
+    pairs = sum(cc.ids.numel() for cc in steps)
+    res = {"docs": n_docs, "doc_vectors": D32.n_vecs, "queries": Q32.n_sets, "steps": w4.steps, "ef": w4.ef,
+           "cands_per_step": w4.cands_per_step, "ms_per_step": per_step,
+           "pair_scores_per_s": pairs / (ms / 1e3),
+           "gbps_per_pair_bytes": pair_bytes / w4.steps / (per_step / 1e3) / 1e9,
+           "gbps_unique_bytes": uniq_bytes / w4.steps / (per_step / 1e3) / 1e9,
+           "frac_of_hbm_peak_per_pair": pair_bytes / w4.steps / (per_step / 1e3) / PEAK_HBM,
+           "rerank_f32_top100_ms": r_ms}
+    if not args.skip_cpu:
+        # beam of a query subset against the oracle's replay of the same candidate lists
+        import oracle
+        ns = 8
+        ok = 0
+        bi = eg.beam.ids[:ns].cpu().numpy()
+        bs = eg.beam.scores[:ns].double().cpu().numpy()
+        qh = q.subset(list(range(ns)))
+        qo = qh.offsets.cpu().numpy()
+        codes, sc = oracle.quantize_fp8(qh.vecs.cpu().numpy())
+        qd = oracle.dequantize_fp8(codes, sc)
+        for i in range(ns):
+            all_ids = torch.cat([cc.ids[cc.offsets[i]:cc.offsets[i + 1]] for cc in steps]).long()
+            u = torch.unique(all_ids)
+            starts, ln = c.offsets[u], lens[u]
+            sub_off = torch.zeros(u.numel() + 1, dtype=torch.int64, device=dev)
+            sub_off[1:] = torch.cumsum(ln, 0)
+            rows = torch.repeat_interleave(starts - sub_off[:-1], ln) + torch.arange(int(sub_off[-1]), device=dev)
+            sub_vecs = c.vecs[rows].cpu().numpy()
+            dc, dsc = oracle.quantize_fp8(sub_vecs)
+            est = oracle.ch_dense(qd[qo[i]:qo[i + 1]], [0, qo[i + 1] - qo[i]], oracle.dequantize_fp8(dc, dsc),
+                                  sub_off.cpu().numpy())[0]
+            u = u.cpu()
+            full = np.full(n_docs, -np.inf)
+            full[u.numpy()] = est
+            tau = 2e-4 * max(abs(np.sort(est)[::-1][w4.ef - 1]), 1.0)
+            good, _, _ = oracle.tie_aware_match(bi[i], full, w4.ef, tau)
+            rel = np.abs(bs[i] - full[bi[i]]) / np.maximum(np.abs(full[bi[i]]), 1)
+            ok += int(good and rel.max() <= 1e-4)
+        res["beam_matches_oracle"] = f"{ok}/{ns} queries"
+    return res
+
 
 
 def main():
@@ -218,6 +311,11 @@ def main():
     ap.add_argument("--workload", type=int, default=2, choices=[2])
     ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU oracle leg and recall")
     ap.add_argument("--cpu-sample", type=int, default=8, help="query sets in the CPU-oracle sample")
+    ap.add_argument("--skip-serving", action="store_true")
+    ap.add_argument("--skip-expansion", action="store_true")
+    ap.add_argument("--serve-rates", type=str, default="2000", help="comma-separated arrival rates (1/s)")
+    ap.add_argument("--serve-requests", type=int, default=1500)
+    ap.add_argument("--expand-docs", type=int, default=1_000_000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -225,7 +323,20 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
-    line = bench_exhaustive(args)
+    line, keep = bench_exhaustive(args)
+    if not args.skip_serving:
+        D8, D32 = keep
+        line["serving"] = []
+        for rate in [float(r) for r in args.serve_rates.split(",") if r]:
+            log(f"serving at {rate:.0f} requests/s")
+            line["serving"].append(bench_serving(D8, D32, rate=rate, n_req=args.serve_requests))
+        if line["serving"]:
+            line["p50_ms"] = line["serving"][0].get("p50_ms")
+            line["p99_ms"] = line["serving"][0].get("p99_ms")
+    del keep
+    torch.cuda.empty_cache()
+    if not args.skip_expansion:
+        line["beam_expansion"] = bench_expansion(args)
     print(json.dumps(line), flush=True)
 
 

@@ -227,26 +227,25 @@ gem_status score_common(const gem_sets* Q, const gem_sets* D, const gem_cands* C
 __device__ unsigned long long g_validate_bad;
 
 __global__ void validate_offsets_kernel(const int64_t* off, int64_t n, int64_t hi) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i > n) return;
-  const int64_t v = off[i];
-  bool bad = v < 0 || v > hi;
-  if (i > 0 && off[i - 1] > v) bad = true;
-  if (bad) atomicAdd(&g_validate_bad, 1ull);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i <= n; i += (int64_t)gridDim.x * 256) {
+    const int64_t v = off[i];
+    bool bad = v < 0 || v > hi;
+    if (i > 0 && off[i - 1] > v) bad = true;
+    if (bad) atomicAdd(&g_validate_bad, 1ull);
+  }
 }
 
 __global__ void validate_scales_kernel(const float* s, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t u = __float_as_uint(s[i]);
-  const uint32_t ex = (u >> 23) & 0xffu;
-  if ((u >> 31) || (u & 0x7fffffu) || ex == 0 || ex == 0xffu) atomicAdd(&g_validate_bad, 1ull);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const uint32_t u = __float_as_uint(s[i]);
+    const uint32_t ex = (u >> 23) & 0xffu;
+    if ((u >> 31) || (u & 0x7fffffu) || ex == 0 || ex == 0xffu) atomicAdd(&g_validate_bad, 1ull);
+  }
 }
 
 __global__ void validate_ids_kernel(const int32_t* ids, int64_t n, int64_t n_sets) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  if (ids[i] >= n_sets) atomicAdd(&g_validate_bad, 1ull);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    if (ids[i] >= n_sets) atomicAdd(&g_validate_bad, 1ull);
 }
 
 gem_status run_validation(hipStream_t stream, const char* what) {
@@ -456,11 +455,11 @@ gem_status gem_validate_sets(gem_ctx ctx, const gem_sets* S, hipStream_t stream)
   if (st != GEM_OK) return st;
   if ((st = reset_validation(stream)) != GEM_OK) return st;
   if (S->n_sets > 0) {
-    hipLaunchKernelGGL(validate_offsets_kernel, dim3((unsigned)((S->n_sets + 1 + 255) / 256)), dim3(256), 0, stream,
+    hipLaunchKernelGGL(validate_offsets_kernel, dim3(capped_blocks((S->n_sets + 1 + 255) / 256, 256)), dim3(256), 0, stream,
                        S->offsets, S->n_sets, S->n_vecs);
   }
   if (S->dtype == GEM_FP8_E4M3 && S->n_vecs > 0) {
-    hipLaunchKernelGGL(validate_scales_kernel, dim3((unsigned)((S->n_vecs + 255) / 256)), dim3(256), 0, stream,
+    hipLaunchKernelGGL(validate_scales_kernel, dim3(capped_blocks((S->n_vecs + 255) / 256, 256)), dim3(256), 0, stream,
                        S->scales, S->n_vecs);
   }
   hipError_t e = hipGetLastError();
@@ -474,11 +473,11 @@ gem_status gem_validate_cands(gem_ctx ctx, const gem_cands* C, int64_t n_sets, h
   if (st != GEM_OK) return st;
   if ((st = reset_validation(stream)) != GEM_OK) return st;
   if (C->offsets && C->n_lists > 0) {
-    hipLaunchKernelGGL(validate_offsets_kernel, dim3((unsigned)((C->n_lists + 1 + 255) / 256)), dim3(256), 0, stream,
+    hipLaunchKernelGGL(validate_offsets_kernel, dim3(capped_blocks((C->n_lists + 1 + 255) / 256, 256)), dim3(256), 0, stream,
                        C->offsets, C->n_lists, C->n_entries);
   }
   if (C->n_entries > 0) {
-    hipLaunchKernelGGL(validate_ids_kernel, dim3((unsigned)((C->n_entries + 255) / 256)), dim3(256), 0, stream,
+    hipLaunchKernelGGL(validate_ids_kernel, dim3(capped_blocks((C->n_entries + 255) / 256, 256)), dim3(256), 0, stream,
                        C->ids, C->n_entries, n_sets);
   }
   hipError_t e = hipGetLastError();

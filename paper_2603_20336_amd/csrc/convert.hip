@@ -5,21 +5,23 @@
 
 namespace gem {
 
-// 8 elements per thread: two 16-byte loads, one 16-byte store.
+// 8 elements per thread and step: two 16-byte loads, one 16-byte store.
 __global__ __launch_bounds__(256) void convert_bf16_kernel(const float* __restrict__ x, int64_t n,
                                                            uint16_t* __restrict__ out) {
-  const int64_t i8 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
-  if (i8 + 8 <= n) {
-    float4 a = *reinterpret_cast<const float4*>(x + i8);
-    float4 b = *reinterpret_cast<const float4*>(x + i8 + 4);
-    uint4 r;
-    r.x = f32_to_bf16_rne(a.x) | ((uint32_t)f32_to_bf16_rne(a.y) << 16);
-    r.y = f32_to_bf16_rne(a.z) | ((uint32_t)f32_to_bf16_rne(a.w) << 16);
-    r.z = f32_to_bf16_rne(b.x) | ((uint32_t)f32_to_bf16_rne(b.y) << 16);
-    r.w = f32_to_bf16_rne(b.z) | ((uint32_t)f32_to_bf16_rne(b.w) << 16);
-    *reinterpret_cast<uint4*>(out + i8) = r;
-  } else {
-    for (int64_t i = i8; i < n; ++i) out[i] = f32_to_bf16_rne(x[i]);
+  const int64_t stride = (int64_t)gridDim.x * 256 * 8;
+  for (int64_t i8 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8; i8 < n; i8 += stride) {
+    if (i8 + 8 <= n) {
+      float4 a = *reinterpret_cast<const float4*>(x + i8);
+      float4 b = *reinterpret_cast<const float4*>(x + i8 + 4);
+      uint4 r;
+      r.x = f32_to_bf16_rne(a.x) | ((uint32_t)f32_to_bf16_rne(a.y) << 16);
+      r.y = f32_to_bf16_rne(a.z) | ((uint32_t)f32_to_bf16_rne(a.w) << 16);
+      r.z = f32_to_bf16_rne(b.x) | ((uint32_t)f32_to_bf16_rne(b.y) << 16);
+      r.w = f32_to_bf16_rne(b.z) | ((uint32_t)f32_to_bf16_rne(b.w) << 16);
+      *reinterpret_cast<uint4*>(out + i8) = r;
+    } else {
+      for (int64_t i = i8; i < n; ++i) out[i] = f32_to_bf16_rne(x[i]);
+    }
   }
 }
 
@@ -27,7 +29,7 @@ hipError_t launch_convert_bf16(const float* x, int64_t n_elems, uint16_t* out, h
   if (n_elems == 0) return hipSuccess;
   const int64_t threads = (n_elems + 7) / 8;
   const int64_t grid = (threads + 255) / 256;
-  hipLaunchKernelGGL(convert_bf16_kernel, dim3((unsigned)grid), dim3(256), 0, s, x, n_elems, out);
+  hipLaunchKernelGGL(convert_bf16_kernel, dim3(capped_blocks(grid, 256)), dim3(256), 0, s, x, n_elems, out);
   return hipGetLastError();
 }
 
@@ -35,23 +37,23 @@ hipError_t launch_convert_bf16(const float* x, int64_t n_elems, uint16_t* out, h
 // the row's power-of-two scale, then each element's E4M3 code of x / scale.
 __global__ __launch_bounds__(256) void quantize_fp8_kernel(const float* __restrict__ x, int64_t n_rows,
                                                            uint8_t* __restrict__ out, float* __restrict__ scales) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= n_rows) return;
   const int l = threadIdx.x & 63;
-  const float2 v = reinterpret_cast<const float2*>(x + row * kDim)[l];
-  const float amax = wave_max(fmaxf(fabsf(v.x), fabsf(v.y)));
-  const int e = pow2_scale_exponent(amax);
-  const float inv = ldexpf(1.0f, -e);                        // exact: x * 2^-e == x / 2^e
-  const uint32_t c0 = f32_to_e4m3_rne_sat(v.x * inv);
-  const uint32_t c1 = f32_to_e4m3_rne_sat(v.y * inv);
-  reinterpret_cast<uint16_t*>(out + row * kDim)[l] = (uint16_t)(c0 | (c1 << 8));
-  if (l == 0) scales[row] = ldexpf(1.0f, e);
+  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < n_rows; row += (int64_t)gridDim.x * 4) {
+    const float2 v = reinterpret_cast<const float2*>(x + row * kDim)[l];
+    const float amax = wave_max(fmaxf(fabsf(v.x), fabsf(v.y)));
+    const int e = pow2_scale_exponent(amax);
+    const float inv = ldexpf(1.0f, -e);                      // exact: x * 2^-e == x / 2^e
+    const uint32_t c0 = f32_to_e4m3_rne_sat(v.x * inv);
+    const uint32_t c1 = f32_to_e4m3_rne_sat(v.y * inv);
+    reinterpret_cast<uint16_t*>(out + row * kDim)[l] = (uint16_t)(c0 | (c1 << 8));
+    if (l == 0) scales[row] = ldexpf(1.0f, e);
+  }
 }
 
 hipError_t launch_quantize_fp8(const float* x, int64_t n_rows, uint8_t* out, float* scales, hipStream_t s) {
   if (n_rows == 0) return hipSuccess;
   const int64_t grid = (n_rows + 3) / 4;
-  hipLaunchKernelGGL(quantize_fp8_kernel, dim3((unsigned)grid), dim3(256), 0, s, x, n_rows, out, scales);
+  hipLaunchKernelGGL(quantize_fp8_kernel, dim3(capped_blocks(grid, 256)), dim3(256), 0, s, x, n_rows, out, scales);
   return hipGetLastError();
 }
 

@@ -9,6 +9,14 @@
 
 namespace gem {
 
+// A dispatch's work-item count is a 32-bit number: grids are capped at 2^31
+// work-items and kernels stride over the rest.
+constexpr int64_t kMaxGridThreads = int64_t(1) << 31;
+inline unsigned capped_blocks(int64_t blocks, int threads_per_block) {
+  const int64_t cap = kMaxGridThreads / threads_per_block;
+  return (unsigned)(blocks < cap ? blocks : cap);
+}
+
 // Device view of a CSR set batch.
 struct SetsView {
   const int64_t* off;     // [n_sets + 1], absolute row indices into vecs

@@ -15,6 +15,8 @@
 // in order), so a (query, document) score does not depend on which other
 // queries or documents share the launch: the same pair scores bitwise the same
 // in the dense and the gathered kernel, alone or in any batch.
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "gem_internal.h"
 
@@ -271,6 +273,7 @@ struct DenseParams {
   const int32_t* qb;
   const int64_t* qcol;
   int64_t n_blocks_max, n_bgroups, n_chunks;
+  int64_t chunk0;         // first document chunk of this launch (large batches launch in slices)
   DenseOut out;
 };
 
@@ -406,7 +409,7 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
   const int64_t per = (total + 7) / 8;
   const int64_t item = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (item >= total) return;                                   // whole workgroup
-  const int64_t chunk = item / P.n_bgroups;
+  const int64_t chunk = P.chunk0 + item / P.n_bgroups;
   const int64_t b0 = (item % P.n_bgroups) * kDenseWaves;
   // blocks past the plan's count are empty (their start is n_q): a group whose
   // first block is empty has nothing to do
@@ -613,19 +616,27 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
   DenseParams P;
   P.Q = Q; P.D = D; P.qb = qb_start; P.qcol = qcol; P.n_blocks_max = n_blocks_max;
   P.n_bgroups = (n_blocks_max + kDenseWaves - 1) / kDenseWaves;
-  P.n_chunks = (D.n_sets + kChunkDocs - 1) / kChunkDocs;
   P.out = out;
-  const int64_t total = P.n_bgroups * P.n_chunks;
-  if (total == 0) return hipSuccess;
-  const int64_t grid = ((total + 7) / 8) * 8;
+  const int64_t n_chunks = (D.n_sets + kChunkDocs - 1) / kChunkDocs;
+  if (P.n_bgroups == 0 || n_chunks == 0) return hipSuccess;
+  // slices of whole chunks, each launch within the dispatch's work-item limit
+  const int64_t max_items = (kMaxGridThreads / kDenseThreads) & ~int64_t(7);
+  const int64_t slice = std::max<int64_t>(1, max_items / P.n_bgroups);
   const dim3 blk(kDenseThreads);
-  switch (dtype) {
-    case GEM_F32: hipLaunchKernelGGL(score_dense_kernel<GEM_F32>, dim3((unsigned)grid), blk, 0, s, P); break;
-    case GEM_BF16: hipLaunchKernelGGL(score_dense_kernel<GEM_BF16>, dim3((unsigned)grid), blk, 0, s, P); break;
-    case GEM_FP8_E4M3: hipLaunchKernelGGL(score_dense_kernel<GEM_FP8_E4M3>, dim3((unsigned)grid), blk, 0, s, P); break;
-    default: return hipErrorInvalidValue;
+  for (int64_t c0 = 0; c0 < n_chunks; c0 += slice) {
+    P.chunk0 = c0;
+    P.n_chunks = std::min(slice, n_chunks - c0);
+    const int64_t grid = ((P.n_bgroups * P.n_chunks + 7) / 8) * 8;
+    switch (dtype) {
+      case GEM_F32: hipLaunchKernelGGL(score_dense_kernel<GEM_F32>, dim3((unsigned)grid), blk, 0, s, P); break;
+      case GEM_BF16: hipLaunchKernelGGL(score_dense_kernel<GEM_BF16>, dim3((unsigned)grid), blk, 0, s, P); break;
+      case GEM_FP8_E4M3: hipLaunchKernelGGL(score_dense_kernel<GEM_FP8_E4M3>, dim3((unsigned)grid), blk, 0, s, P); break;
+      default: return hipErrorInvalidValue;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 // --------------------------------------------------------------------------
@@ -641,6 +652,7 @@ struct GatherParams {
   SetsView Q, D;
   CandsView C;
   int64_t chunks_per_query;
+  int64_t wave0;          // first wave of this launch (large batches launch in slices)
   float* scores;
 };
 
@@ -654,7 +666,7 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
   __shared__ int64_t lds_ent[4][kGatherEntries][2];
 
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c16 = l & 15;
-  const int64_t gw = (int64_t)blockIdx.x * 4 + w;
+  const int64_t gw = P.wave0 + (int64_t)blockIdx.x * 4 + w;
   const int64_t q = gw / P.chunks_per_query;
   if (q >= P.C.n_lists) return;
   const int64_t ch = gw % P.chunks_per_query;
@@ -777,14 +789,20 @@ hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, 
   P.chunks_per_query = (max_list_len + kGatherEntries - 1) / kGatherEntries;
   if (P.chunks_per_query == 0 || C.n_lists == 0) return hipSuccess;
   const int64_t waves = P.chunks_per_query * C.n_lists;
-  const int64_t grid = (waves + 3) / 4;
-  switch (dtype) {
-    case GEM_F32: hipLaunchKernelGGL(score_gather_kernel<GEM_F32>, dim3((unsigned)grid), dim3(256), 0, s, P); break;
-    case GEM_BF16: hipLaunchKernelGGL(score_gather_kernel<GEM_BF16>, dim3((unsigned)grid), dim3(256), 0, s, P); break;
-    case GEM_FP8_E4M3: hipLaunchKernelGGL(score_gather_kernel<GEM_FP8_E4M3>, dim3((unsigned)grid), dim3(256), 0, s, P); break;
-    default: return hipErrorInvalidValue;
+  const int64_t max_blocks = kMaxGridThreads / 256;
+  for (int64_t b0 = 0; b0 < (waves + 3) / 4; b0 += max_blocks) {
+    P.wave0 = b0 * 4;
+    const int64_t grid = std::min(max_blocks, (waves + 3) / 4 - b0);
+    switch (dtype) {
+      case GEM_F32: hipLaunchKernelGGL(score_gather_kernel<GEM_F32>, dim3((unsigned)grid), dim3(256), 0, s, P); break;
+      case GEM_BF16: hipLaunchKernelGGL(score_gather_kernel<GEM_BF16>, dim3((unsigned)grid), dim3(256), 0, s, P); break;
+      case GEM_FP8_E4M3: hipLaunchKernelGGL(score_gather_kernel<GEM_FP8_E4M3>, dim3((unsigned)grid), dim3(256), 0, s, P); break;
+      default: return hipErrorInvalidValue;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace gem

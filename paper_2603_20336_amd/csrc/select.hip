@@ -115,7 +115,8 @@ __global__ __launch_bounds__(kSelThreads) void topk_kernel(TopkSegs S, int32_t k
   __shared__ int s_cnt;
   __shared__ uint32_t s_sel, s_gt;
 
-  const int64_t seg = blockIdx.x;
+  for (int64_t seg = blockIdx.x; seg < S.n_segs; seg += gridDim.x) {
+  __syncthreads();                                   // LDS reuse across segments
   SegAccess A;
   if (S.off) {
     const int64_t a = S.off[seg], b = S.off[seg + 1];
@@ -228,11 +229,13 @@ __global__ __launch_bounds__(kSelThreads) void topk_kernel(TopkSegs S, int32_t k
     top_scores[seg * k + r] = key ? key_score(key) : neg_inf();
     top_ids[seg * k + r] = key ? key_id(key) : -1;
   }
+  }
 }
 
 hipError_t launch_topk(const TopkSegs& segs, int32_t k, float* top_scores, int32_t* top_ids, hipStream_t s) {
   if (segs.n_segs == 0 || k == 0) return hipSuccess;
-  hipLaunchKernelGGL(topk_kernel, dim3((unsigned)segs.n_segs), dim3(kSelThreads), 0, s, segs, k, top_scores, top_ids);
+  hipLaunchKernelGGL(topk_kernel, dim3(capped_blocks(segs.n_segs, kSelThreads)), dim3(kSelThreads), 0, s, segs, k,
+                     top_scores, top_ids);
   return hipGetLastError();
 }
 
@@ -240,12 +243,14 @@ hipError_t launch_topk(const TopkSegs& segs, int32_t k, float* top_scores, int32
 // Beam update: row q of the beam becomes the best ef of (row q) U (list q's
 // scored entries), ids distinct. One workgroup per query.
 __global__ __launch_bounds__(kSelThreads) void beam_merge_kernel(const float* __restrict__ cand_scores, CandsView C,
-                                                                 int32_t ef, float* __restrict__ beam_scores,
+                                                                 int64_t n_q, int32_t ef,
+                                                                 float* __restrict__ beam_scores,
                                                                  int32_t* __restrict__ beam_ids) {
   __shared__ uint64_t keys[kSelCap];
   __shared__ int s_cnt;
-  const int64_t q = blockIdx.x;
   const int tid = threadIdx.x;
+  for (int64_t q = blockIdx.x; q < n_q; q += gridDim.x) {
+  __syncthreads();                                   // LDS reuse across queries
   int64_t lb, le;
   if (C.off) { lb = C.off[q]; le = C.off[q + 1]; }
   else { lb = q * (int64_t)C.stride; le = lb + C.stride; }
@@ -276,24 +281,28 @@ __global__ __launch_bounds__(kSelThreads) void beam_merge_kernel(const float* __
     bs[r] = key ? key_score(key) : neg_inf();
     bi[r] = key ? key_id(key) : -1;
   }
+  }
 }
 
 hipError_t launch_beam_merge(const float* cand_scores, const CandsView& C, int64_t n_q, int32_t ef,
                              float* beam_scores, int32_t* beam_ids, hipStream_t s) {
   if (n_q == 0) return hipSuccess;
-  hipLaunchKernelGGL(beam_merge_kernel, dim3((unsigned)n_q), dim3(kSelThreads), 0, s, cand_scores, C, ef,
-                     beam_scores, beam_ids);
+  hipLaunchKernelGGL(beam_merge_kernel, dim3(capped_blocks(n_q, kSelThreads)), dim3(kSelThreads), 0, s, cand_scores,
+                     C, n_q, ef, beam_scores, beam_ids);
   return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void beam_reset_kernel(float* __restrict__ s, int32_t* __restrict__ i, int64_t n) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j < n) { s[j] = neg_inf(); i[j] = -1; }
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+    s[j] = neg_inf();
+    i[j] = -1;
+  }
 }
 
 hipError_t launch_beam_reset(float* beam_scores, int32_t* beam_ids, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(beam_reset_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, beam_scores, beam_ids, n);
+  hipLaunchKernelGGL(beam_reset_kernel, dim3(capped_blocks((n + 255) / 256, 256)), dim3(256), 0, s, beam_scores,
+                     beam_ids, n);
   return hipGetLastError();
 }
 

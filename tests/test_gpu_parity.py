@@ -115,6 +115,27 @@ def test_quantize_fp8_bitwise():
     np.testing.assert_array_equal(_np(S.vecs), codes)
 
 
+def test_quantize_fp8_beyond_one_dispatch():
+    """More rows than one dispatch's 32-bit work-item count covers at one wave
+    a row (2^32 / 64 = 67,108,864): rows past that bound are quantized too."""
+    n_rows = 70_000_000
+    free, _ = torch.cuda.mem_get_info()
+    if free < n_rows * 128 * 6 + (4 << 30):
+        pytest.skip("needs about 45 GB of free device memory")
+    g = torch.Generator(device=DEV).manual_seed(7)
+    x = torch.randn(n_rows, 128, device=DEV, generator=g)
+    x[-1] *= 1e-3
+    off = torch.tensor([0, n_rows], dtype=torch.int64, device=DEV)
+    S = gem.quantize_fp8(gem.Sets(x, off, "f32", 0))
+    rows = torch.tensor([0, 1, 2**26, 67_108_863, 67_108_864, 67_108_865, 68_000_000, n_rows - 1], device=DEV)
+    xs = _np(x[rows])
+    codes, scales = oracle.quantize_fp8(xs)
+    np.testing.assert_array_equal(_np(S.scales[rows]), scales)
+    np.testing.assert_array_equal(_np(S.vecs[rows]), codes)
+    del S, x
+    torch.cuda.empty_cache()
+
+
 # ----------------------------------------------------------------------- dense (exhaustive)
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 def test_dense_workload1_matches_oracle(dtype):
@@ -338,3 +359,29 @@ def test_error_paths_enqueue_nothing():
         gem.validate_sets(bad_off)
     assert e.value.status == gem._abi.GEM_ERR_DEVICE_CHECK
     gem.validate_sets(c)
+
+
+def test_expansion_graph_replays_equal_eager():
+    """A graph of several expansion steps gives bitwise the eager result on every replay."""
+    from paper_2603_20336_amd.search import ExpansionGraph
+    w = wl.WORKLOADS[4]
+    c = wl.corpus(w, n_docs=4000)
+    q = wl.queries(w, n_queries=48)
+    D8 = _device_sets(c, "fp8")
+    Q8 = gem.Sets.from_batch(q, DEV).to_fp8()
+    steps = []
+    for st in range(5):
+        off, ids = wl.step_candidates(w, st, n_queries=48, n_docs=4000)
+        steps.append(gem.Cands(ids.to(DEV), off.to(DEV), max_list_len=w.cands_per_step))
+    eg = ExpansionGraph(Q8, D8, steps, ef=300)
+    eg.run_eager()
+    torch.cuda.synchronize()
+    ref_s, ref_i = eg.beam.scores.clone(), eg.beam.ids.clone()
+    eg.capture()
+    for rep in range(3):
+        eg.beam.scores.fill_(123.0)                  # eager work between replays
+        torch.cuda.synchronize()
+        eg.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(eg.beam.ids, ref_i), rep
+        assert torch.equal(eg.beam.scores, ref_s), rep

@@ -1,0 +1,143 @@
+"""Serving loop: scheduling on the CPU (oracle-backed executor), results on the GPU."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_20336_amd import serve
+from paper_2603_20336_amd import workloads as wl
+
+
+class OracleExecutor(serve.Executor):
+    """CPU stand-in for the device executor: float64 oracle scores, same schedule."""
+
+    def __init__(self, corpus: wl.SetBatch, n_chunks: int, shortlist: int, k: int, bytes_per_request=1000):
+        self.c = corpus
+        self.n_docs = corpus.n_sets
+        self.n_chunks = n_chunks
+        self.bounds = np.linspace(0, self.n_docs, n_chunks + 1).round().astype(int)
+        self.shortlist, self.k = shortlist, k
+        self.bytes_per_request = bytes_per_request
+        self.est = {}
+        self.batch = None
+        self.chunk_log = []
+
+    def set_batch(self, slots, queries):
+        self.batch = (list(slots), [np.asarray(q) for q in queries])
+
+    def score_chunk(self, chunk):
+        self.chunk_log.append((chunk, tuple(self.batch[0])))
+        a, b = self.bounds[chunk], self.bounds[chunk + 1]
+        dv, do = self.c.vecs.numpy(), self.c.offsets.numpy()
+        for s, q in zip(*self.batch):
+            row = self.est.setdefault(s, np.full(self.n_docs, np.nan))
+            qo = np.array([0, q.shape[0]])
+            row[a:b] = oracle.ch_dense(q, qo, dv, do[a:b + 1] - 0)[0] if b > a else row[a:b]
+
+    def finish(self, slots, queries):
+        dv, do = self.c.vecs.numpy(), self.c.offsets.numpy()
+        ts, ti = [], []
+        for s, q in zip(slots, queries):
+            row = self.est.pop(s)
+            assert not np.isnan(row).any()          # every chunk was scored exactly once
+            _, short = oracle.topk_rows(row[None], self.shortlist)
+            exact = oracle.ch_cands(q, [0, q.shape[0]], dv, do, [0, short.shape[1]], short[0])
+            a, b = oracle.topk_segments(exact, [0, len(exact)], self.k, short[0])
+            ts.append(a[0]); ti.append(b[0])
+        return np.array(ts), np.array(ti)
+
+
+class StepClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        self.t += 1e-3
+        return self.t
+
+
+def _requests(n, seed, lo=4, hi=16):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        m = int(rng.integers(lo, hi + 1))
+        v = rng.standard_normal((m, 128))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        out.append(serve.Request(i, v.astype(np.float32), t_arrival=float(rng.uniform(0, 0.02))))
+    return out
+
+
+def test_continuous_batching_schedule_and_results():
+    c = wl.corpus(wl.WORKLOADS[1], n_docs=120)
+    ex = OracleExecutor(c, n_chunks=4, shortlist=20, k=5)
+    eng = serve.ServingEngine(ex, max_slots=6, mem_budget_bytes=10 ** 9, clock=StepClock())
+    reqs = _requests(15, 0)
+    done = eng.run(reqs)
+    assert len(done) == 15 and all(r.t_done is not None and r.t_done >= r.t_arrival for r in done)
+    # each request saw every chunk exactly once, starting wherever it joined
+    for r in done:
+        seen = [ch for (ch, slots) in ex.chunk_log if r.slot in slots]
+        assert len(seen) >= 4
+    # never more than max_slots active at once
+    assert max(len(s) for (_, s) in ex.chunk_log) <= 6
+    # results equal the oracle's exact top-k of each request's own shortlist
+    dv, do = c.vecs.numpy(), c.offsets.numpy()
+    for r in done:
+        exact = oracle.ch_dense(r.vecs, [0, r.vecs.shape[0]], dv, do)[0]
+        _, short = oracle.topk_rows(exact[None], 20)
+        np.testing.assert_array_equal(np.sort(r.top_ids), np.sort(short[0][:5]))
+
+
+def test_admission_waits_for_memory():
+    c = wl.corpus(wl.WORKLOADS[1], n_docs=40)
+    ex = OracleExecutor(c, n_chunks=2, shortlist=5, k=3, bytes_per_request=1000)
+    eng = serve.ServingEngine(ex, max_slots=8, mem_budget_bytes=2500, clock=StepClock())   # room for 2
+    reqs = _requests(6, 1)
+    for r in reqs:
+        r.t_arrival = 0.0
+    done = eng.run(reqs)
+    assert len(done) == 6
+    assert max(len(s) for (_, s) in ex.chunk_log) <= 2
+    assert eng.refused_for_memory > 0
+
+
+def test_budget_smaller_than_one_request_never_admits():
+    c = wl.corpus(wl.WORKLOADS[1], n_docs=10)
+    ex = OracleExecutor(c, n_chunks=2, shortlist=3, k=2, bytes_per_request=1000)
+    eng = serve.ServingEngine(ex, max_slots=4, mem_budget_bytes=500, clock=StepClock())
+    r = _requests(1, 2)[0]
+    r.t_arrival = 0.0
+    eng.submit(r)
+    for _ in range(5):
+        assert eng.step() == []
+    assert eng.active == [] and len(eng.waiting) == 1 and eng.refused_for_memory == 5
+
+
+@pytest.mark.gpu
+def test_device_serving_alone_equals_mix_and_matches_oracle():
+    import paper_2603_20336_amd as gem
+    dev = "cuda"
+    c = wl.corpus(wl.WORKLOADS[2], n_docs=3000)
+    D32 = gem.Sets.from_batch(c, dev)
+    D8 = D32.to_fp8()
+    reqs = _requests(24, 3, lo=4, hi=64)
+    target = 7
+
+    def run(rs):
+        ex = serve.DeviceExecutor(D8, D32, n_chunks=5, max_slots=32, shortlist=200, k=20)
+        eng = serve.ServingEngine(ex, max_slots=32, mem_budget_bytes=1 << 34, clock=StepClock())
+        return {r.rid: r for r in eng.run(rs)}
+
+    alone = run([serve.Request(target, reqs[target].vecs, 0.0)])[target]
+    mix = run([serve.Request(r.rid, r.vecs, r.t_arrival) for r in reqs])
+    assert len(mix) == 24
+    np.testing.assert_array_equal(alone.top_ids, mix[target].top_ids)
+    np.testing.assert_array_equal(alone.top_scores, mix[target].top_scores)
+    # returned scores are exact float32 Chamfer scores of the returned ids
+    dv, do = c.vecs.numpy(), c.offsets.numpy()
+    for r in mix.values():
+        ex = oracle.ch_dense(r.vecs, [0, r.vecs.shape[0]], dv, do)[0]
+        got = ex[r.top_ids]
+        np.testing.assert_allclose(r.top_scores, got, rtol=0, atol=1e-4 * max(1.0, abs(got[0])))
+        # the FP8 estimate's shortlist of 200 holds the exact top-20 (recall 1 on this corpus)
+        assert oracle.recall_at_k(r.top_ids, ex, 20, tau=2e-4 * max(1, abs(got[-1]))) >= 0.95
