@@ -75,6 +75,46 @@ def cpu_baseline(q: wl.SetBatch, c: wl.SetBatch, n_sample: int):
                  "sample": f"{n_sample} query sets x {c.n_sets} documents, float64 NumPy/BLAS, {dt:.1f} s"}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "score_dense_bf16_exhaustive100k_traffic.txt")
+DENSE_SOURCES = [os.path.join(ROOT, "paper_2603_20336_amd", "csrc", f)
+                 for f in ("score.hip", "device_common.hpp", "gem_internal.h")]
+
+
+def dense_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in DENSE_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dense bf16 kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the copy-kernel factor);
+    None when there is none or the kernel's sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        if kv.get("source_sha256") != dense_source_digest():
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_calibration(n_bytes: int = 1 << 30, reps: int = 3) -> None:
+    """A plain streaming copy of known size (read n_bytes, write n_bytes), run
+    for the counter runs that scale FETCH_SIZE / WRITE_SIZE to bytes."""
+    src = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {reps} x {n_bytes} bytes read + written")
+
+
 def recall_vs_exact(top_ids: np.ndarray, exact: np.ndarray, k: int) -> float:
     import oracle
     rs = []
@@ -190,9 +230,10 @@ def bench_exhaustive(args):
                                f"{V} vectors), d=128, bf16 MFMA, top-100", "n_queries": n_q, "n_docs": n_d,
                    "doc_vectors": V, "query_vectors": q_rows, "k": k},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_BF16, "traffic": None,
+                     "frac": achieved / PEAK_BF16, "traffic": measured_traffic(),
                      "kernel": "score_dense_kernel<bf16>", "kernel_ms": t_score,
-                     "flops_per_launch": flops},
+                     "flops_per_launch": flops, "traffic_unit": "HBM bytes per launch",
+                     "algorithmic_bytes_per_launch": V * 128 * 2 + q_rows * 128 * 2 + n_q * n_d * 4},
         "stages_ms": {"query_convert": t_conv, "score_dense_bf16": t_score, "topk_100": t_topk},
         "corpus_convert_ms": {"bf16": t_bf16, "fp8": t_fp8},
         "f32_exact_path": {"ms": t_f32, "pair_scores_per_s": pairs / (t_f32 / 1e3),
@@ -316,6 +357,8 @@ def main():
     ap.add_argument("--serve-rates", type=str, default="2000", help="comma-separated arrival rates (1/s)")
     ap.add_argument("--serve-requests", type=int, default=1500)
     ap.add_argument("--expand-docs", type=int, default=1_000_000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB copy kernel (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -324,6 +367,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     line, keep = bench_exhaustive(args)
+    if args.copy_calibration:
+        copy_calibration()
     if not args.skip_serving:
         D8, D32 = keep
         line["serving"] = []
