@@ -120,7 +120,7 @@ ScoreLayout score_layout(const gem_sets* Q, const gem_sets* D, const gem_cands* 
     L.block_rows = dense_block_rows(compute, Q->max_set_len);
     L.n_blocks_max = dense_blocks_upper(Q->n_sets, Q->n_vecs, L.block_rows, Q->max_set_len);
     L.qb = off;
-    off = align_up(off + (size_t)(L.n_blocks_max + 1) * 4);
+    off = align_up(off + (size_t)(L.n_blocks_max + 2) * 4);     // starts, end, run count
     L.qcol = off;
     off = align_up(off + (size_t)(Q->n_sets + 1) * 8);
     if (k > 0 && !scores_given) {

@@ -33,7 +33,8 @@ struct CandsView {
   int32_t stride;
 };
 
-// Query blocks: block b = queries [qb_start[b], qb_start[b+1]); n_blocks_max + 1 entries.
+// Query blocks: block b = queries [qb_start[b], qb_start[b+1]); n_blocks_max + 2 entries,
+// the last one holding the number of non-empty blocks.
 // qcol[i]: first (16-aligned) column of query i in the padded layout, [n_q + 1].
 constexpr int kBlockMaxQueries = 32;
 

@@ -131,9 +131,13 @@ int dense_block_rows(int dtype, int max_len) {
 }
 
 int64_t dense_blocks_upper(int64_t n_q, int64_t n_rows, int block_rows, int max_len) {
+  // within a segment every run but the last is followed by a query (at most
+  // pad16(max_len) columns) that did not fit, so it spans more than
+  // block_rows - pad16(max_len) columns
   const int64_t win = block_rows - pad16(max_len > 0 ? max_len : 1) + 1;   // >= 1
   const int64_t cols = n_rows + 15 * n_q;                                   // padded columns, upper bound
-  return cols / win + 3 + n_q / kBlockMaxQueries;
+  const int64_t bound = cols / win + 1 + (n_q + kBlockMaxQueries - 1) / kBlockMaxQueries;
+  return bound < n_q ? bound : n_q;                                         // a run holds a query
 }
 
 // --------------------------------------------------------------------------
@@ -179,19 +183,22 @@ __device__ __forceinline__ void update_max(float& rm, f32x4 a) {
 // --------------------------------------------------------------------------
 // Query-block plan. Each query is laid out from a 16-aligned column (its
 // columns past the last vector are zero vectors, whose max over any document
-// is exactly 0, so they add nothing). The batch is cut into runs of whole
-// queries spanning at most `block_cols` padded columns and kBlockMaxQueries
-// queries: a run starts at query i when i is a multiple of kBlockMaxQueries or
-// when i's first padded column falls into a new window of
-// (block_cols - pad16(max_len) + 1) columns.
+// is exactly 0, so they add nothing). The batch is cut into segments of
+// kBlockMaxQueries consecutive queries, and each segment greedily into runs of
+// whole queries spanning at most `block_cols` padded columns: a run ends when
+// the next query would not fit. One thread plans one or more whole segments;
+// the runs' first queries go to qb_start in order, the tail up to
+// n_blocks_max is filled with n_q, and qb_start[n_blocks_max + 1] receives the
+// number of runs.
 __global__ __launch_bounds__(1024) void plan_query_blocks_kernel(const int64_t* __restrict__ q_off, int64_t n_q,
-                                                                 int64_t win, int32_t* __restrict__ qb_start,
+                                                                 int64_t block_cols, int32_t* __restrict__ qb_start,
                                                                  int64_t* __restrict__ qcol, int64_t n_blocks_max) {
   __shared__ int64_t part[1024];
   const int t = threadIdx.x;
-  const int64_t per = (n_q + 1023) / 1024;
+  const int64_t n_seg = (n_q + kBlockMaxQueries - 1) / kBlockMaxQueries;
+  const int64_t per = ((n_seg + 1023) / 1024) * kBlockMaxQueries;      // whole segments per thread
   const int64_t a = min(n_q, t * per), b = min(n_q, a + per);
-  auto scan = [&](int64_t v) -> int64_t {         // exclusive block scan
+  auto scan = [&](int64_t v) -> int64_t {         // exclusive block scan; part[t] = total afterwards
     part[t] = v;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
@@ -203,38 +210,52 @@ __global__ __launch_bounds__(1024) void plan_query_blocks_kernel(const int64_t* 
     const int64_t incl = part[t];
     const int64_t tot = part[1023];
     __syncthreads();
-    part[t] = tot;                                 // broadcast-free: every thread keeps the total
+    part[t] = tot;
     return incl - v;
   };
+  auto cols_of = [&](int64_t i) -> int64_t { return (q_off[i + 1] - q_off[i] + 15) & ~(int64_t)15; };
   int64_t cols = 0;
-  for (int64_t i = a; i < b; ++i) cols += (q_off[i + 1] - q_off[i] + 15) & ~(int64_t)15;
+  for (int64_t i = a; i < b; ++i) cols += cols_of(i);
   int64_t c = scan(cols);
   const int64_t total_cols = part[t];
-  for (int64_t i = a; i < b; ++i) {
-    qcol[i] = c;
-    c += (q_off[i + 1] - q_off[i] + 15) & ~(int64_t)15;
-  }
-  if (t == 0) qcol[n_q] = total_cols;
-  __syncthreads();
-  auto starts = [&](int64_t i) -> bool {
-    if (i % kBlockMaxQueries == 0) return true;
-    return qcol[i] / win != qcol[i - 1] / win;
-  };
+  // greedy runs over this thread's segments (columns are relative, so the
+  // scan result is not needed for the cut)
   int64_t cnt = 0;
-  for (int64_t i = a; i < b; ++i) cnt += starts(i) ? 1 : 0;
-  __syncthreads();
+  {
+    int64_t run_cols = 0;
+    for (int64_t i = a; i < b; ++i) {
+      const int64_t ci = cols_of(i);
+      if (i % kBlockMaxQueries == 0 || run_cols + ci > block_cols) { ++cnt; run_cols = 0; }
+      run_cols += ci;
+    }
+  }
   int64_t pos = scan(cnt);
   const int64_t n_blocks = min(part[t], n_blocks_max);
-  for (int64_t i = a; i < b; ++i)
-    if (starts(i) && pos < n_blocks_max) qb_start[pos++] = (int32_t)i;
+  {
+    int64_t run_cols = 0;
+    for (int64_t i = a; i < b; ++i) {
+      const int64_t ci = cols_of(i);
+      qcol[i] = c;
+      c += ci;
+      if (i % kBlockMaxQueries == 0 || run_cols + ci > block_cols) {
+        if (pos < n_blocks_max) qb_start[pos] = (int32_t)i;
+        ++pos;
+        run_cols = 0;
+      }
+      run_cols += ci;
+    }
+  }
+  if (t == 0) {
+    qcol[n_q] = total_cols;
+    qb_start[n_blocks_max + 1] = (int32_t)n_blocks;
+  }
   for (int64_t j = n_blocks + t; j <= n_blocks_max; j += 1024) qb_start[j] = (int32_t)n_q;
 }
 
-hipError_t launch_plan_query_blocks(const int64_t* q_off, int64_t n_q, int block_rows, int max_len,
+hipError_t launch_plan_query_blocks(const int64_t* q_off, int64_t n_q, int block_rows, int,
                                     int32_t* qb_start, int64_t* qcol, int64_t n_blocks_max, hipStream_t s) {
-  const int64_t win = block_rows - pad16(max_len > 0 ? max_len : 1) + 1;
-  hipLaunchKernelGGL(plan_query_blocks_kernel, dim3(1), dim3(1024), 0, s, q_off, n_q, win, qb_start, qcol,
-                     n_blocks_max);
+  hipLaunchKernelGGL(plan_query_blocks_kernel, dim3(1), dim3(1024), 0, s, q_off, n_q, (int64_t)block_rows, qb_start,
+                     qcol, n_blocks_max);
   return hipGetLastError();
 }
 
@@ -405,15 +426,18 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
-  const int64_t total = P.n_bgroups * P.n_chunks;
+  // the plan's real block count sets the work: items (chunk, block group) with
+  // the group fastest, each XCD (workgroups go round-robin over the 8 XCDs)
+  // taking one contiguous range, so that the workgroups an XCD runs at once
+  // share a chunk; the grid is sized for the upper bound and the rest exit
+  const int64_t n_bg = (P.qb[P.n_blocks_max + 1] + kDenseWaves - 1) / kDenseWaves;
+  const int64_t total = n_bg * P.n_chunks;
   const int64_t per = (total + 7) / 8;
-  const int64_t item = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (item >= total) return;                                   // whole workgroup
-  const int64_t chunk = P.chunk0 + item / P.n_bgroups;
-  const int64_t b0 = (item % P.n_bgroups) * kDenseWaves;
-  // blocks past the plan's count are empty (their start is n_q): a group whose
-  // first block is empty has nothing to do
-  if (b0 >= P.n_blocks_max || P.qb[b0] >= P.Q.n_sets) return;   // whole workgroup
+  const int64_t slot = blockIdx.x >> 3;
+  const int64_t item = (int64_t)(blockIdx.x & 7) * per + slot;
+  if (slot >= per || item >= total) return;                    // whole workgroup
+  const int64_t chunk = P.chunk0 + item / n_bg;
+  const int64_t b0 = (item % n_bg) * kDenseWaves;
   const int64_t b = b0 + w;
   int q0 = 0, q1 = 0;
   if (b < P.n_blocks_max) { q0 = P.qb[b]; q1 = P.qb[b + 1]; }
