@@ -16,6 +16,7 @@
 // queries or documents share the launch: the same pair scores bitwise the same
 // in the dense and the gathered kernel, alone or in any batch.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.hpp"
 #include "gem_internal.h"
@@ -298,7 +299,8 @@ struct DenseParams {
   DenseOut out;
 };
 
-// LDS image of one 16-row tile: row r at r * kRowBytes, chunk c at position c ^ swz(r).
+// LDS image of one 16-row tile: row r at r * kRowBytes, 16-byte chunk c at
+// position c ^ swz(r); FP8 tiles are followed by their 16 row scales.
 template <int DT> struct TileStage {
   using O = Op<DT>;
   static constexpr int kRowBytes = O::kRowBytes;
@@ -308,36 +310,42 @@ template <int DT> struct TileStage {
   static constexpr int kPieceWaves = kSlots / 64;                // waves copying one piece per lane
   static constexpr bool kScales = DT == GEM_FP8_E4M3;
   static constexpr int kCopyWaves = kPieceWaves + (kScales ? 1 : 0);   // waves busy copying one tile
-  static constexpr int kStageBytes = kTileBytes + (kScales ? 64 : 0);
+  // FP8: the tile's 16 row scales, copied by a whole wave (lanes past 16 fill
+  // the rest of the slot with repeats)
+  static constexpr int kStageBytes = kTileBytes + (kScales ? 256 : 0);
   static constexpr int kGroup = DenseCfg<DT>::kGroup;
-  // tile u of a group is copied by waves kCopyWaves*u .. kCopyWaves*u + kCopyWaves-1
-  // (mod 8), so over a group every wave issues the same number of copies
-  static constexpr int kCopiesPerWave = kGroup * kCopyWaves / kDenseWaves;
-  static_assert(kSlots % 64 == 0 && kCopyWaves <= kDenseWaves, "tile copy layout");
-  static_assert((kGroup * kCopyWaves) % kDenseWaves == 0, "copies must spread evenly over the waves");
+  static constexpr int kGroupVecs = kGroup * kStageBytes / 16;  // one group buffer in 16-byte units
+  // a group's piece copies are slots s = u * kPieceWaves + role (tile u,
+  // 1 KiB piece `role`), and wave w issues slots w, w + 8, w + 16, ...; FP8
+  // scale copies go to wave u % 8. Every wave issues the same copies.
+  static constexpr int kPieceCopiesPerWave = kGroup * kPieceWaves / kDenseWaves;
+  static constexpr int kScaleCopiesPerWave = kScales ? kGroup / kDenseWaves : 0;
+  static constexpr int kCopiesPerWave = kPieceCopiesPerWave + kScaleCopiesPerWave;
+  static_assert(kSlots % 64 == 0, "tile copy layout");
+  static_assert((kGroup * kPieceWaves) % kDenseWaves == 0 && (!kScales || kGroup % kDenseWaves == 0),
+                "copies must spread evenly over the waves");
+  static_assert(kStageBytes % 16 == 0, "stage alignment");
 
   // chunk c of row r sits at position c ^ swz(r): the 16 rows read by one
   // 16-lane group then cover all 64 banks (128-byte rows pair up first)
   static __device__ __forceinline__ int swz(int r) { return kRowBytes == 128 ? ((r >> 1) & 7) : (r & 15); }
-  // global address of piece `slot` of the tile whose rows start at doc row beg
-  static __device__ __forceinline__ const void* src(const void* vecs, int64_t beg, int64_t len, int t, int slot) {
+
+  // Piece `role` (1 KiB) of tile k of the document whose rows are
+  // base + [rs, re), into `stage`.
+  static __device__ __forceinline__ void copy_piece(const void* vecs, int64_t base, int rs, int re, int k,
+                                                    u32x4* stage, int role, int l) {
+    const int slot = 64 * role + l;
     const int r = slot / kChunksPerRow, pos = slot % kChunksPerRow;
     const int c = pos ^ swz(r);
-    const int64_t row = beg + min((int64_t)(16 * t + r), len - 1);
-    return static_cast<const char*>(vecs) + row * kRowBytes + c * 16;
+    const int64_t row = base + min(rs + 16 * k + r, re - 1);
+    __builtin_amdgcn_global_load_lds(static_cast<const char*>(vecs) + row * kRowBytes + c * 16,
+                                     (lds_void_ptr)(stage + 64 * role), 16, 0, 0);
   }
-  // this wave's share of copying tile u of a group into the stage at LDS address `stage`
-  static __device__ __forceinline__ void copy(const void* vecs, const float* scales, int64_t beg, int64_t len,
-                                              int t, char* stage, int u, int w, int l) {
-    const int role = (w - kCopyWaves * u) & (kDenseWaves - 1);
-    if (role < kPieceWaves) {
-      __builtin_amdgcn_global_load_lds(src(vecs, beg, len, t, 64 * role + l), (lds_void_ptr)(stage + 1024 * role),
-                                       16, 0, 0);
-    } else if (kScales && role == kPieceWaves) {
-      if (l < 16)
-        __builtin_amdgcn_global_load_lds(scales + beg + min((int64_t)(16 * t + l), len - 1),
-                                         (lds_void_ptr)(stage + kTileBytes), 4, 0, 0);
-    }
+  // The 16 row scales of that tile (lanes past 16 repeat them).
+  static __device__ __forceinline__ void copy_scales(const float* scales, int64_t base, int rs, int re, int k,
+                                                     u32x4* stage, int l) {
+    __builtin_amdgcn_global_load_lds(scales + base + min(rs + 16 * k + (l & 15), re - 1),
+                                     (lds_void_ptr)(stage + kTileBytes / 16), 4, 0, 0);
   }
 };
 
@@ -348,62 +356,41 @@ __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0f70);
 }
 
-// A operand of one tile from its LDS stage: the reads and their wait form one
-// block, so the compiler never sees an LDS read it would order after the copies.
+// Keeps the compiler from moving memory operations across this point (no
+// hardware wait is implied).
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
+// A operand of one tile from its LDS stage (plain loads: the compiler places
+// their waits; the copies in flight target other LDS arrays).
 template <int DT>
-__device__ __forceinline__ void frag_from_lds(typename Op<DT>::Frag& f, uint32_t stage, int c16, int g);
+__device__ __forceinline__ void frag_from_lds(typename Op<DT>::Frag& f, const u32x4* stage, int c16, int g);
 
 template <>
-__device__ __forceinline__ void frag_from_lds<GEM_BF16>(Op<GEM_BF16>::Frag& f, uint32_t stage, int c16, int g) {
-  const uint32_t row = stage + c16 * 256;
-  const uint32_t a0 = row + (((4 * g + 0) ^ (c16 & 15)) << 4), a1 = row + (((4 * g + 1) ^ (c16 & 15)) << 4);
-  const uint32_t a2 = row + (((4 * g + 2) ^ (c16 & 15)) << 4), a3 = row + (((4 * g + 3) ^ (c16 & 15)) << 4);
-  u32x4 v0, v1, v2, v3;
-  asm volatile("ds_read_b128 %0, %4\n\tds_read_b128 %1, %5\n\tds_read_b128 %2, %6\n\tds_read_b128 %3, %7\n\t"
-               "s_waitcnt lgkmcnt(0)"
-               : "=&v"(v0), "=&v"(v1), "=&v"(v2), "=&v"(v3)
-               : "v"(a0), "v"(a1), "v"(a2), "v"(a3)
-               : "memory");
-  f.v[0] = __builtin_bit_cast(bf16x8, v0);
-  f.v[1] = __builtin_bit_cast(bf16x8, v1);
-  f.v[2] = __builtin_bit_cast(bf16x8, v2);
-  f.v[3] = __builtin_bit_cast(bf16x8, v3);
+__device__ __forceinline__ void frag_from_lds<GEM_BF16>(Op<GEM_BF16>::Frag& f, const u32x4* stage, int c16, int g) {
+  const u32x4* row = stage + c16 * 16;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) f.v[s] = __builtin_bit_cast(bf16x8, row[(4 * g + s) ^ c16]);
 }
 
 template <>
-__device__ __forceinline__ void frag_from_lds<GEM_FP8_E4M3>(Op<GEM_FP8_E4M3>::Frag& f, uint32_t stage, int c16, int g) {
-  const uint32_t row = stage + c16 * 128;
-  const uint32_t a0 = row + (((2 * g) ^ ((c16 >> 1) & 7)) << 4);
-  const uint32_t a1 = row + (((2 * g + 1) ^ ((c16 >> 1) & 7)) << 4);
-  const uint32_t as = stage + 16 * 128 + 4 * c16;
-  u32x4 v0, v1;
-  uint32_t sc;
-  asm volatile("ds_read_b128 %0, %3\n\tds_read_b128 %1, %4\n\tds_read_b32 %2, %5\n\ts_waitcnt lgkmcnt(0)"
-               : "=&v"(v0), "=&v"(v1), "=&v"(sc)
-               : "v"(a0), "v"(a1), "v"(as)
-               : "memory");
+__device__ __forceinline__ void frag_from_lds<GEM_FP8_E4M3>(Op<GEM_FP8_E4M3>::Frag& f, const u32x4* stage, int c16,
+                                                            int g) {
+  const u32x4* row = stage + c16 * 8;
+  const u32x4 v0 = row[(2 * g) ^ ((c16 >> 1) & 7)];
+  const u32x4 v1 = row[(2 * g + 1) ^ ((c16 >> 1) & 7)];
+  const uint32_t sc = reinterpret_cast<const uint32_t*>(stage + 128)[c16];
   f.v = i32x8{(int)v0.x, (int)v0.y, (int)v0.z, (int)v0.w, (int)v1.x, (int)v1.y, (int)v1.z, (int)v1.w};
   f.scale = (int)((sc >> 23) & 0xffu);
 }
 
 template <>
-__device__ __forceinline__ void frag_from_lds<GEM_F32>(Op<GEM_F32>::Frag& f, uint32_t stage, int c16, int g) {
-  const uint32_t row = stage + c16 * 512;
-  uint32_t a[8];
-#pragma unroll
-  for (int s = 0; s < 8; ++s) a[s] = row + (((8 * g + s) ^ (c16 & 15)) << 4);
-  u32x4 v0, v1, v2, v3, v4, v5, v6, v7;
-  asm volatile("ds_read_b128 %0, %8\n\tds_read_b128 %1, %9\n\tds_read_b128 %2, %10\n\tds_read_b128 %3, %11\n\t"
-               "ds_read_b128 %4, %12\n\tds_read_b128 %5, %13\n\tds_read_b128 %6, %14\n\tds_read_b128 %7, %15\n\t"
-               "s_waitcnt lgkmcnt(0)"
-               : "=&v"(v0), "=&v"(v1), "=&v"(v2), "=&v"(v3), "=&v"(v4), "=&v"(v5), "=&v"(v6), "=&v"(v7)
-               : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]), "v"(a[7])
-               : "memory");
-  const u32x4 vv[8] = {v0, v1, v2, v3, v4, v5, v6, v7};
+__device__ __forceinline__ void frag_from_lds<GEM_F32>(Op<GEM_F32>::Frag& f, const u32x4* stage, int c16, int g) {
+  const u32x4* row = stage + c16 * 32;
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
-    f.v[4 * s + 0] = __uint_as_float(vv[s].x); f.v[4 * s + 1] = __uint_as_float(vv[s].y);
-    f.v[4 * s + 2] = __uint_as_float(vv[s].z); f.v[4 * s + 3] = __uint_as_float(vv[s].w);
+    const u32x4 v = row[(8 * g + s) ^ c16];
+    f.v[4 * s + 0] = __uint_as_float(v.x); f.v[4 * s + 1] = __uint_as_float(v.y);
+    f.v[4 * s + 2] = __uint_as_float(v.z); f.v[4 * s + 3] = __uint_as_float(v.w);
   }
 }
 
@@ -414,6 +401,63 @@ __device__ __forceinline__ float readlane_f(float v, int lane) {
   return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), lane));
 }
 
+// State of one wave over one pass of the dense scorer.
+template <int DT> struct DensePass {
+  using O = Op<DT>;
+  using Frag = typename O::Frag;
+  static constexpr int NT = DenseCfg<DT>::kNT;
+  Frag B[NT];                   // query columns of this pass
+  float qs[NT / 4];             // FP8: scale of this lane's column in the tile sums
+  float rm[NT];                 // running max over the current document, per column tile
+  float scr[NT];                // lane dd: score of document dd for the query finishing in tile ct
+  float part;                   // lane dd: partial score carried in from the previous pass
+  int nct, tq_lane;
+  uint64_t first_mask, last_mask;
+
+  // one document tile against the pass's column tiles; at a document's last
+  // tile, fold the maxima into per-query scores parked in lane dd
+  __device__ __forceinline__ void tile(const Frag& A, uint64_t end_mask) {
+    if (nct > 0) {
+      // column tiles in groups of 4 (a group past the last used tile is
+      // skipped; unused tiles inside a group have zero B operands and their
+      // maxima are never read)
+#pragma unroll
+      for (int g0 = 0; g0 < NT; g0 += 4) {
+        if (g0 < nct) {
+          f32x4 acc[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int s = 0; s < O::kSteps; ++s) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = O::mma(A, B[g0 + c], acc[c], s);
+          }
+#pragma unroll
+          for (int c = 0; c < 4; ++c) update_max(rm[g0 + c], acc[c]);
+        }
+      }
+      if (end_mask) {
+        const int dd = __builtin_ctzll(end_mask);
+        float Rs[NT / 4];
+        tile_sums<NT, O::kColumnScale>(rm, Rs, qs);
+        // each query's score: its tile sums in tile order, parked in lane dd
+        float s_run = 0.0f;
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+          if (ct < nct) {
+            const float T = tile_sum_at<NT>(Rs, ct);
+            if ((first_mask >> ct) & 1) s_run = T;
+            else if (ct == 0) s_run = readlane_f(part, dd) + T;     // continues from the previous pass
+            else s_run += T;
+            if (((last_mask >> ct) & 1) || ct == nct - 1) scr[ct] = writelane_f(scr[ct], s_run, dd);
+          }
+          rm[ct] = neg_inf();
+        }
+      }
+    }
+  }
+};
+
 template <int DT>
 __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams P) {
   using O = Op<DT>;
@@ -421,11 +465,15 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
   using TS = TileStage<DT>;
   constexpr int NT = DenseCfg<DT>::kNT;
   constexpr int kGroup = TS::kGroup;
-  __shared__ __attribute__((aligned(1024))) char lds_tiles[kBuffers][kGroup][TS::kStageBytes];
+  // three group buffers as separate arrays: the compiler then knows that the
+  // copies in flight (into one buffer) never alias the reads (of another)
+  __shared__ u32x4 lds_buf0[TS::kGroupVecs];
+  __shared__ u32x4 lds_buf1[TS::kGroupVecs];
+  __shared__ u32x4 lds_buf2[TS::kGroupVecs];
   __shared__ int lds_npass[kDenseWaves];
 
   const int tid = threadIdx.x;
-  const int w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, g = l >> 4, c16 = l & 15;
   // the plan's real block count sets the work: items (chunk, block group) with
   // the group fastest, each XCD (workgroups go round-robin over the 8 XCDs)
   // taking one contiguous range, so that the workgroups an XCD runs at once
@@ -462,166 +510,150 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
     total_tiles = (int)((P.qcol[q1] - col0) >> 4);
   }
   total_tiles = __builtin_amdgcn_readfirstlane(total_tiles);
-  // lane dd <= nd: offset of document p0 + dd; lane dd < nd: is document dd empty
-  const int64_t doff_lane = (l <= nd) ? P.D.off[p0 + l] : 0;
-  const int64_t doff_end = P.D.off[p1];
+
+  // the chunk's document tiles, in order: lane dd < nd holds document
+  // p0 + dd's rows (relative to the chunk's first row), its first tile in the
+  // chunk's tile sequence and its last tile (-1 when it is empty)
+  const int64_t base = P.D.off[p0];
+  int d_rs = 0, d_re = 0;
+  if (l < nd) {
+    d_rs = (int)(P.D.off[p0 + l] - base);
+    d_re = (int)(P.D.off[p0 + l + 1] - base);
+  }
+  const int d_nt = (d_re - d_rs + 15) >> 4;
+  int d_incl = d_nt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(d_incl, o);
+    if (l >= o) d_incl += v;
+  }
+  const int d_t0 = d_incl - d_nt;
+  const int d_tl = d_nt > 0 ? d_incl - 1 : -1;
+  const int n_tiles = __builtin_amdgcn_readlane(d_incl, 63);
+  const bool doc_empty = l < nd && d_nt == 0;
+  const int n_groups = (n_tiles + kGroup - 1) / kGroup;
+
   if (l == 0) lds_npass[w] = (total_tiles + NT - 1) / NT;
   __builtin_amdgcn_s_waitcnt(0);                               // nothing in flight before the tile stream
   __syncthreads();
   int n_pass = 0;
 #pragma unroll
   for (int i = 0; i < kDenseWaves; ++i) n_pass = max(n_pass, lds_npass[i]);
-  auto rd64 = [&](int64_t v, int lane) -> int64_t {
-    uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
-    uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), lane);
-    return (int64_t)(((uint64_t)hi << 32) | lo);
+
+  // copies of group G into buffer Y. Every wave issues exactly kCopiesPerWave
+  // copies per group, also past the last tile (those repeat the last tile
+  // into slots that are never read), so that the copies of later groups alone
+  // fill the wait count: the compiler can then prove that the buffer being
+  // read has landed without waiting for every copy.
+  auto issue = [&](auto ybuf, int G) {
+    constexpr int Y = decltype(ybuf)::value;
+    u32x4* buf = Y == 0 ? lds_buf0 : (Y == 1 ? lds_buf1 : lds_buf2);
+    // tile T belongs to the last non-empty document whose first tile is <= T
+    auto locate = [&](int T, int& k, int& rs, int& re) {
+      const uint64_t m = __ballot(d_nt > 0 && d_t0 <= T);
+      const int dd = 63 - __builtin_clzll(m);
+      k = T - __builtin_amdgcn_readlane(d_t0, dd);
+      rs = __builtin_amdgcn_readlane(d_rs, dd);
+      re = __builtin_amdgcn_readlane(d_re, dd);
+    };
+#pragma unroll
+    for (int j = 0; j < TS::kPieceCopiesPerWave; ++j) {
+      const int slot = kDenseWaves * j + w;
+      const int u = slot / TS::kPieceWaves, role = slot % TS::kPieceWaves;
+      int k, rs, re;
+      locate(min(G * kGroup + u, n_tiles - 1), k, rs, re);
+      TS::copy_piece(P.D.vecs, base, rs, re, k, buf + u * (TS::kStageBytes / 16), role, l);
+    }
+#pragma unroll
+    for (int j = 0; j < TS::kScaleCopiesPerWave; ++j) {
+      const int u = kDenseWaves * j + w;
+      int k, rs, re;
+      locate(min(G * kGroup + u, n_tiles - 1), k, rs, re);
+      TS::copy_scales(P.D.scales, base, rs, re, k, buf + u * (TS::kStageBytes / 16), l);
+    }
   };
-  auto doc_start = [&](int dd) -> int64_t { return dd >= 64 ? doff_end : rd64(doff_lane, dd); };
-  const uint32_t nx_lo = (uint32_t)__shfl_down((int)(uint32_t)doff_lane, 1);
-  const uint32_t nx_hi = (uint32_t)__shfl_down((int)(uint32_t)(doff_lane >> 32), 1);
-  const int64_t doff_next = (l == 63) ? doff_end : (int64_t)(((uint64_t)nx_hi << 32) | nx_lo);
-  const bool doc_empty = l < nd && doff_next == doff_lane;
-  auto skip_empty = [&](int dd) -> int {
-    while (dd < nd && doc_start(dd + 1) == doc_start(dd)) ++dd;
-    return dd;
-  };
-  const int dd_first = skip_empty(0);
-  const int64_t beg_first = dd_first < nd ? doc_start(dd_first) : 0;
-  const int64_t len_first = dd_first < nd ? doc_start(dd_first + 1) - beg_first : 1;
-  const uint32_t lds0 = (uint32_t)(size_t)(lds_void_ptr)&lds_tiles[0][0][0];
 
   float part = 0.0f;                                            // lane dd: partial score carried to the next pass
   for (int pass = 0; pass < n_pass; ++pass) {
     const int pt0 = pass * NT;
-    const int nct = __builtin_amdgcn_readfirstlane(max(0, min(NT, total_tiles - pt0)));
+    DensePass<DT> S;
+    S.nct = __builtin_amdgcn_readfirstlane(max(0, min(NT, total_tiles - pt0)));
+    S.part = part;
     // tile map of this pass: owner query, first/last flags, B operand rows
-    Frag B[NT];
-    float qs[NT / 4];                                           // FP8: scale of this lane's column in R[i]
 #pragma unroll
-    for (int i = 0; i < NT / 4; ++i) qs[i] = 1.0f;
-    int tq_lane = 0;                                            // lane ct: query owning tile ct
-    uint64_t first_mask = 0, last_mask = 0;
+    for (int i = 0; i < NT / 4; ++i) S.qs[i] = 1.0f;
+    S.tq_lane = 0;
+    S.first_mask = 0;
+    S.last_mask = 0;
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) {
-      O::zero(B[ct]);
-      if (ct < nct) {
+      O::zero(S.B[ct]);
+      if (ct < S.nct) {
         const int t = pt0 + ct;
         const uint64_t own = __ballot(l < nq && qt0 <= t && t < qt0 + qnt);
         const int j = __ffsll((unsigned long long)own) - 1;
         const int jt0 = __builtin_amdgcn_readlane(qt0, j);
         const int jm = __builtin_amdgcn_readlane(qm, j);
-        const int64_t jrow = rd64(qrow, j);
+        const int64_t jrow = (int64_t)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(qrow >> 32), j) << 32) |
+                                       __builtin_amdgcn_readlane((uint32_t)qrow, j));
         const int k = t - jt0;                                  // tile index inside query j
-        if (l == ct) tq_lane = j;
-        if (k == 0) first_mask |= 1ull << ct;
-        if (16 * (k + 1) >= jm) last_mask |= 1ull << ct;
+        if (l == ct) S.tq_lane = j;
+        if (k == 0) S.first_mask |= 1ull << ct;
+        if (16 * (k + 1) >= jm) S.last_mask |= 1ull << ct;
         if (16 * k + c16 < jm) {
-          O::load_b(B[ct], P.Q.vecs, P.Q.scales, jrow + 16 * k + c16, g);
+          O::load_b(S.B[ct], P.Q.vecs, P.Q.scales, jrow + 16 * k + c16, g);
           if constexpr (O::kColumnScale)
-            if (g == (ct & 3)) qs[ct >> 2] = P.Q.scales[jrow + 16 * k + c16];
+            if (g == (ct & 3)) S.qs[ct >> 2] = P.Q.scales[jrow + 16 * k + c16];
         }
       }
     }
-    float rm[NT], scr[NT];
 #pragma unroll
-    for (int ct = 0; ct < NT; ++ct) { rm[ct] = ninf; scr[ct] = 0.0f; }
+    for (int ct = 0; ct < NT; ++ct) { S.rm[ct] = ninf; S.scr[ct] = 0.0f; }
     __builtin_amdgcn_s_waitcnt(0);                             // operands in; the stream starts from zero
 
-    // copy cursor (l_*) runs kBuffers-1 groups ahead of the compute cursor (c_*)
-    int l_dd = dd_first, l_t = 0;
-    int64_t l_beg = beg_first, l_len = len_first;
-    int c_dd = dd_first, c_t = 0;
-    int64_t c_len = len_first;
-    int issued_full = 0;                                        // groups after the current one, fully issued
-    auto issue_group = [&](int buf) -> bool {                   // true if all kGroup tiles were issued
-      int n = 0;
-#pragma unroll
-      for (int u = 0; u < kGroup; ++u) {
-        if (l_dd < nd) {
-          TS::copy(P.D.vecs, P.D.scales, l_beg, l_len, l_t, &lds_tiles[buf][u][0], u, w, l);
-          ++n;
-          if ((int64_t)(l_t + 1) * 16 < l_len) ++l_t;
-          else {
-            l_dd = skip_empty(l_dd + 1); l_t = 0;
-            if (l_dd < nd) { l_beg = doc_start(l_dd); l_len = doc_start(l_dd + 1) - l_beg; }
-          }
-        }
-      }
-      return n == kGroup;
-    };
-    issue_group(0);
-    issued_full = issue_group(1) ? 1 : 0;
-    for (int grp = 0; c_dd < nd; ++grp) {
-      const int buf = grp % kBuffers;
-      // this wave's copies of group grp are done when at most one later group is in flight
-      if (issued_full) wait_vm<TS::kCopiesPerWave>(); else wait_vm<0>();
-      __builtin_amdgcn_s_barrier();                             // group grp landed; buffer grp-1 is free
-      issued_full = issue_group((grp + kBuffers - 1) % kBuffers) ? 1 : 0;
-      const uint32_t gbase = lds0 + (uint32_t)(buf * kGroup * TS::kStageBytes);
+    // group G (in buffer X): wait for this wave's copies of G, publish G with
+    // one barrier (which also frees the buffer G - 1 used), start the copies
+    // of G + 2 into that buffer, then multiply G's tiles
+    auto group = [&](auto xbuf, int G) {
+      constexpr int X = decltype(xbuf)::value;
+      const u32x4* buf = X == 0 ? lds_buf0 : (X == 1 ? lds_buf1 : lds_buf2);
+      wait_vm<TS::kCopiesPerWave>();                            // only group G + 1's copies may be in flight
+      compiler_fence();
+      __builtin_amdgcn_s_barrier();
+      compiler_fence();
+      issue(std::integral_constant<int, (X + 2) % 3>{}, G + 2);
+      const int nt = min(kGroup, n_tiles - G * kGroup);           // <= 0 past the end
+      const int T0 = G * kGroup;
 #pragma nounroll
-      for (int u = 0; u < kGroup; ++u) {
-        if (c_dd < nd) {
-          const bool last_tile = (int64_t)(c_t + 1) * 16 >= c_len;
-          if (nct > 0) {
-            Frag A;
-            frag_from_lds<DT>(A, gbase + u * TS::kStageBytes, c16, g);
-            // column tiles in groups of 4 (a group past the last used tile is
-            // skipped; unused tiles inside a group have zero B operands and
-            // their maxima are never read)
-#pragma unroll
-            for (int g0 = 0; g0 < NT; g0 += 4) {
-              if (g0 < nct) {
-                f32x4 acc[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int s = 0; s < O::kSteps; ++s) {
-#pragma unroll
-                  for (int c = 0; c < 4; ++c) acc[c] = O::mma(A, B[g0 + c], acc[c], s);
-                }
-#pragma unroll
-                for (int c = 0; c < 4; ++c) update_max(rm[g0 + c], acc[c]);
-              }
-            }
-            if (last_tile) {
-              float Rs[NT / 4];
-              tile_sums<NT, O::kColumnScale>(rm, Rs, qs);
-              // each query's score: its tile sums in tile order, parked in lane dd
-              const int dd = c_dd;
-              float s_run = 0.0f;
-#pragma unroll
-              for (int ct = 0; ct < NT; ++ct) {
-                if (ct < nct) {
-                  const float T = tile_sum_at<NT>(Rs, ct);
-                  if ((first_mask >> ct) & 1) s_run = T;
-                  else if (ct == 0) s_run = readlane_f(part, dd) + T;     // continues from the previous pass
-                  else s_run += T;
-                  if (((last_mask >> ct) & 1) || ct == nct - 1) scr[ct] = writelane_f(scr[ct], s_run, dd);
-                }
-                rm[ct] = ninf;
-              }
-            }
-          }
-          if (!last_tile) ++c_t;
-          else {
-            c_dd = skip_empty(c_dd + 1); c_t = 0;
-            if (c_dd < nd) c_len = doc_start(c_dd + 1) - doc_start(c_dd);
-          }
-        }
+      for (int u = 0; u < nt; ++u) {
+        Frag A;
+        frag_from_lds<DT>(A, buf + u * (TS::kStageBytes / 16), c16, g);
+        S.tile(A, __ballot(d_tl == T0 + u));
       }
+    };
+    if (n_tiles > 0) {
+      issue(std::integral_constant<int, 0>{}, 0);
+      issue(std::integral_constant<int, 1>{}, 1);
+    }
+    // whole triples of groups (the ones past the end hold no tiles), so that
+    // every path through the loop issues the same copies
+    for (int G = 0; G < n_groups; G += 3) {
+      group(std::integral_constant<int, 0>{}, G);
+      group(std::integral_constant<int, 1>{}, G + 1);
+      group(std::integral_constant<int, 2>{}, G + 2);
     }
     wait_vm<0>();                                               // no copy outlives the pass
     __syncthreads();                                            // buffers are reused by the next pass
     // finished queries: one 64-document row each (empty documents score -inf)
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) {
-      if (ct < nct) {
-        if ((last_mask >> ct) & 1) {
-          const int j = __builtin_amdgcn_readlane(tq_lane, ct);
+      if (ct < S.nct) {
+        if ((S.last_mask >> ct) & 1) {
+          const int j = __builtin_amdgcn_readlane(S.tq_lane, ct);
           const int64_t row = P.out.rows ? (int64_t)P.out.rows[q0 + j] : (int64_t)(q0 + j);
-          if (l < nd) P.out.scores[row * P.out.ld + p0 + l] = doc_empty ? ninf : scr[ct];
-        } else if (ct == nct - 1) {
-          part = scr[ct];
+          if (l < nd) P.out.scores[row * P.out.ld + p0 + l] = doc_empty ? ninf : S.scr[ct];
+        } else if (ct == S.nct - 1) {
+          part = S.scr[ct];
         }
       }
     }
