@@ -101,9 +101,10 @@ template <> struct Op<GEM_FP8_E4M3> {
   }
   static constexpr bool kColumnScale = true;
   static __device__ __forceinline__ f32x4 mma(const Frag& a, const Frag& b, f32x4 acc, int) {
-    // OCP E4M3 for both operands (format code 0), E8M0 block scales from each
-    // lane's row (A) / column (B); all four 32-wide blocks of a row share it.
-    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a.v, b.v, acc, 0, 0, 0, a.scale, 0, b.scale);
+    // OCP E4M3 for both operands (format code 0); E8M0 block scales: each
+    // lane's document row (A; all four 32-wide blocks of a row share it) and
+    // the unit scale 2^0 for the query side (B), whose scale applies later.
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a.v, b.v, acc, 0, 0, 0, a.scale, 0, 127);
   }
   static constexpr int kSteps = 1;
 };
@@ -156,12 +157,14 @@ template <int NT, bool kScaled = false>
 __device__ __forceinline__ void tile_sums(const float (&rm)[NT], float (&R)[NT / 4], const float* colscale = nullptr) {
 #pragma unroll
   for (int i = 0; i < NT / 4; ++i) {
+    // (maxima of finite or -inf values: IEEE maximum, which needs no NaN
+    // quieting of the lane-swapped operands)
     auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(rm[4 * i + 0]), __float_as_uint(rm[4 * i + 1]), false, false);
-    const float ab = fmaxf(__uint_as_float(p[0]), __uint_as_float(p[1]));       // rows: A01 B01 A23 B23
+    const float ab = __builtin_elementwise_maximum(__uint_as_float(p[0]), __uint_as_float(p[1]));   // rows: A01 B01 A23 B23
     auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(rm[4 * i + 2]), __float_as_uint(rm[4 * i + 3]), false, false);
-    const float cd = fmaxf(__uint_as_float(q[0]), __uint_as_float(q[1]));       // rows: C01 D01 C23 D23
+    const float cd = __builtin_elementwise_maximum(__uint_as_float(q[0]), __uint_as_float(q[1]));   // rows: C01 D01 C23 D23
     auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(ab), __float_as_uint(cd), false, false);
-    float m = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));             // rows: A B C D
+    float m = __builtin_elementwise_maximum(__uint_as_float(r[0]), __uint_as_float(r[1]));         // rows: A B C D
     if constexpr (kScaled) m *= colscale[i];                                    // query vector's scale
     m += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0xb1, 0xf, 0xf, false));   // lane ^ 1
     m += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0x4e, 0xf, 0xf, false));   // lane ^ 2
@@ -409,50 +412,39 @@ template <int DT> struct DensePass {
   Frag B[NT];                   // query columns of this pass
   float qs[NT / 4];             // FP8: scale of this lane's column in the tile sums
   float rm[NT];                 // running max over the current document, per column tile
-  float scr[NT];                // lane dd: score of document dd for the query finishing in tile ct
-  float part;                   // lane dd: partial score carried in from the previous pass
+  float tsum[NT];               // lane dd: column sum of tile ct's maxima for document dd
   int nct, tq_lane;
   uint64_t first_mask, last_mask;
 
-  // one document tile against the pass's column tiles; at a document's last
-  // tile, fold the maxima into per-query scores parked in lane dd
+  // one document tile against the pass's column tiles (all of them when
+  // kFull); at a document's last tile, park its tile sums in lane dd
+  template <bool kFull>
   __device__ __forceinline__ void tile(const Frag& A, uint64_t end_mask) {
-    if (nct > 0) {
-      // column tiles in groups of 4 (a group past the last used tile is
-      // skipped; unused tiles inside a group have zero B operands and their
-      // maxima are never read)
+    // column tiles in groups of 4 (a group past the last used tile is skipped;
+    // unused tiles inside a group have zero B operands and are never summed)
 #pragma unroll
-      for (int g0 = 0; g0 < NT; g0 += 4) {
-        if (g0 < nct) {
-          f32x4 acc[4];
+    for (int g0 = 0; g0 < NT; g0 += 4) {
+      if (kFull || g0 < nct) {
+        f32x4 acc[4];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int s = 0; s < O::kSteps; ++s) {
+        for (int s = 0; s < O::kSteps; ++s) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[c] = O::mma(A, B[g0 + c], acc[c], s);
-          }
-#pragma unroll
-          for (int c = 0; c < 4; ++c) update_max(rm[g0 + c], acc[c]);
+          for (int c = 0; c < 4; ++c) acc[c] = O::mma(A, B[g0 + c], acc[c], s);
         }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) update_max(rm[g0 + c], acc[c]);
       }
-      if (end_mask) {
-        const int dd = __builtin_ctzll(end_mask);
-        float Rs[NT / 4];
-        tile_sums<NT, O::kColumnScale>(rm, Rs, qs);
-        // each query's score: its tile sums in tile order, parked in lane dd
-        float s_run = 0.0f;
+    }
+    if (end_mask) {
+      const int dd = __builtin_ctzll(end_mask);
+      float Rs[NT / 4];
+      tile_sums<NT, O::kColumnScale>(rm, Rs, qs);
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct) {
-          if (ct < nct) {
-            const float T = tile_sum_at<NT>(Rs, ct);
-            if ((first_mask >> ct) & 1) s_run = T;
-            else if (ct == 0) s_run = readlane_f(part, dd) + T;     // continues from the previous pass
-            else s_run += T;
-            if (((last_mask >> ct) & 1) || ct == nct - 1) scr[ct] = writelane_f(scr[ct], s_run, dd);
-          }
-          rm[ct] = neg_inf();
-        }
+      for (int ct = 0; ct < NT; ++ct) {
+        tsum[ct] = writelane_f(tsum[ct], tile_sum_at<NT>(Rs, ct), dd);
+        rm[ct] = neg_inf();
       }
     }
   }
@@ -578,7 +570,6 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
     const int pt0 = pass * NT;
     DensePass<DT> S;
     S.nct = __builtin_amdgcn_readfirstlane(max(0, min(NT, total_tiles - pt0)));
-    S.part = part;
     // tile map of this pass: owner query, first/last flags, B operand rows
 #pragma unroll
     for (int i = 0; i < NT / 4; ++i) S.qs[i] = 1.0f;
@@ -608,7 +599,7 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
       }
     }
 #pragma unroll
-    for (int ct = 0; ct < NT; ++ct) { S.rm[ct] = ninf; S.scr[ct] = 0.0f; }
+    for (int ct = 0; ct < NT; ++ct) { S.rm[ct] = ninf; S.tsum[ct] = 0.0f; }
     __builtin_amdgcn_s_waitcnt(0);                             // operands in; the stream starts from zero
 
     // group G (in buffer X): wait for this wave's copies of G, publish G with
@@ -624,11 +615,22 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
       issue(std::integral_constant<int, (X + 2) % 3>{}, G + 2);
       const int nt = min(kGroup, n_tiles - G * kGroup);           // <= 0 past the end
       const int T0 = G * kGroup;
+      // (the unbranched body keeps two column groups' accumulators live,
+      // which only fits when a pass holds at most 8 column tiles)
+      if (NT <= 8 && S.nct == NT) {
 #pragma nounroll
-      for (int u = 0; u < nt; ++u) {
-        Frag A;
-        frag_from_lds<DT>(A, buf + u * (TS::kStageBytes / 16), c16, g);
-        S.tile(A, __ballot(d_tl == T0 + u));
+        for (int u = 0; u < nt; ++u) {
+          Frag A;
+          frag_from_lds<DT>(A, buf + u * (TS::kStageBytes / 16), c16, g);
+          S.template tile<true>(A, __ballot(d_tl == T0 + u));
+        }
+      } else if (S.nct > 0) {
+#pragma nounroll
+        for (int u = 0; u < nt; ++u) {
+          Frag A;
+          frag_from_lds<DT>(A, buf + u * (TS::kStageBytes / 16), c16, g);
+          S.template tile<false>(A, __ballot(d_tl == T0 + u));
+        }
       }
     };
     if (n_tiles > 0) {
@@ -644,19 +646,22 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
     }
     wait_vm<0>();                                               // no copy outlives the pass
     __syncthreads();                                            // buffers are reused by the next pass
-    // finished queries: one 64-document row each (empty documents score -inf)
+    // each query's score: its tile sums in tile order (continuing the partial
+    // score of a query that began in the previous pass); finished queries
+    // store one 64-document row each (empty documents score -inf)
+    float s_run = part;
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) {
       if (ct < S.nct) {
+        s_run = ((S.first_mask >> ct) & 1) ? S.tsum[ct] : s_run + S.tsum[ct];
         if ((S.last_mask >> ct) & 1) {
           const int j = __builtin_amdgcn_readlane(S.tq_lane, ct);
           const int64_t row = P.out.rows ? (int64_t)P.out.rows[q0 + j] : (int64_t)(q0 + j);
-          if (l < nd) P.out.scores[row * P.out.ld + p0 + l] = doc_empty ? ninf : S.scr[ct];
-        } else if (ct == S.nct - 1) {
-          part = S.scr[ct];
+          if (l < nd) P.out.scores[row * P.out.ld + p0 + l] = doc_empty ? ninf : s_run;
         }
       }
     }
+    part = s_run;
   }
   // empty queries score 0 against every document
   for (int j = 0; j < nq; ++j) {
