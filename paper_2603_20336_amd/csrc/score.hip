@@ -466,210 +466,249 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
 
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, g = l >> 4, c16 = l & 15;
-  // the plan's real block count sets the work: items (chunk, block group) with
-  // the group fastest, each XCD (workgroups go round-robin over the 8 XCDs)
-  // taking one contiguous range, so that the workgroups an XCD runs at once
-  // share a chunk; the grid is sized for the upper bound and the rest exit
-  const int64_t n_bg = (P.qb[P.n_blocks_max + 1] + kDenseWaves - 1) / kDenseWaves;
-  const int64_t total = n_bg * P.n_chunks;
-  const int64_t per = (total + 7) / 8;
-  const int64_t slot = blockIdx.x >> 3;
-  const int64_t item = (int64_t)(blockIdx.x & 7) * per + slot;
-  if (slot >= per || item >= total) return;                    // whole workgroup
-  const int64_t chunk = P.chunk0 + item / n_bg;
-  const int64_t b0 = (item % n_bg) * kDenseWaves;
-  const int64_t b = b0 + w;
-  int q0 = 0, q1 = 0;
-  if (b < P.n_blocks_max) { q0 = P.qb[b]; q1 = P.qb[b + 1]; }
-  const int nq = max(q1 - q0, 0);                              // 0: this wave only helps copy
-  const int64_t p0 = chunk * kChunkDocs;
-  const int64_t p1 = min(P.D.n_sets, p0 + kChunkDocs);
-  const int nd = (int)(p1 - p0);
   const float ninf = neg_inf();
+  // Persistent workgroups. Workgroups go round-robin over the 8 XCDs; XCD x
+  // owns a contiguous range of document chunks, cut into pieces, and its
+  // workgroups take items (piece, block group), the group fastest, in
+  // strides of the workgroup count. The workgroups an XCD runs at once then
+  // walk the same chunks together (one L2 fetch serves all block groups),
+  // and a workgroup whose block group does not change keeps its query
+  // operands in registers from one item to the next.
+  const int64_t n_bg = (P.qb[P.n_blocks_max + 1] + kDenseWaves - 1) / kDenseWaves;
+  const int xcd = blockIdx.x & 7;
+  const int64_t slot = blockIdx.x >> 3, n_slots = gridDim.x >> 3;
+  const int64_t c_lo = P.chunk0 + (P.n_chunks * xcd) / 8;
+  const int64_t c_hi = P.chunk0 + (P.n_chunks * (xcd + 1)) / 8;
+  // pieces sized for about 8 items per workgroup (load balance), whole
+  // ranges when block groups alone fill the workgroups
+  const int64_t piece = max((int64_t)1, ((c_hi - c_lo) * n_bg + 8 * n_slots - 1) / (8 * n_slots));
+  const int64_t n_items = ((c_hi - c_lo + piece - 1) / piece) * n_bg;
 
-  // lane j < nq: query j of the block (first row, length, first tile, tiles)
+  DensePass<DT> S;
+  int64_t cur_bg = -1;
+  int q0 = 0, nq = 0, n_pass = 0, total_tiles = 0;
   int64_t qrow = 0;
   int qm = 0, qt0 = 0, qnt = 0;
-  int total_tiles = 0;
-  if (nq > 0) {
-    const int64_t col0 = P.qcol[q0];
-    if (l < nq) {
-      qrow = P.Q.off[q0 + l];
-      qm = (int)(P.Q.off[q0 + l + 1] - qrow);
-      qt0 = (int)((P.qcol[q0 + l] - col0) >> 4);
-      qnt = (qm + 15) >> 4;
-    }
-    total_tiles = (int)((P.qcol[q1] - col0) >> 4);
-  }
-  total_tiles = __builtin_amdgcn_readfirstlane(total_tiles);
+  bool b_loaded = false;                                       // S holds pass 0 of the current block group
 
-  // the chunk's document tiles, in order: lane dd < nd holds document
-  // p0 + dd's rows (relative to the chunk's first row), its first tile in the
-  // chunk's tile sequence and its last tile (-1 when it is empty)
-  const int64_t base = P.D.off[p0];
-  int d_rs = 0, d_re = 0;
-  if (l < nd) {
-    d_rs = (int)(P.D.off[p0 + l] - base);
-    d_re = (int)(P.D.off[p0 + l + 1] - base);
-  }
-  const int d_nt = (d_re - d_rs + 15) >> 4;
-  int d_incl = d_nt;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int v = __shfl_up(d_incl, o);
-    if (l >= o) d_incl += v;
-  }
-  const int d_t0 = d_incl - d_nt;
-  const int d_tl = d_nt > 0 ? d_incl - 1 : -1;
-  const int n_tiles = __builtin_amdgcn_readlane(d_incl, 63);
-  const bool doc_empty = l < nd && d_nt == 0;
-  const int n_groups = (n_tiles + kGroup - 1) / kGroup;
-
-  if (l == 0) lds_npass[w] = (total_tiles + NT - 1) / NT;
-  __builtin_amdgcn_s_waitcnt(0);                               // nothing in flight before the tile stream
-  __syncthreads();
-  int n_pass = 0;
-#pragma unroll
-  for (int i = 0; i < kDenseWaves; ++i) n_pass = max(n_pass, lds_npass[i]);
-
-  // copies of group G into buffer Y. Every wave issues exactly kCopiesPerWave
-  // copies per group, also past the last tile (those repeat the last tile
-  // into slots that are never read), so that the copies of later groups alone
-  // fill the wait count: the compiler can then prove that the buffer being
-  // read has landed without waiting for every copy.
-  auto issue = [&](auto ybuf, int G) {
-    constexpr int Y = decltype(ybuf)::value;
-    u32x4* buf = Y == 0 ? lds_buf0 : (Y == 1 ? lds_buf1 : lds_buf2);
-    // tile T belongs to the last non-empty document whose first tile is <= T
-    auto locate = [&](int T, int& k, int& rs, int& re) {
-      const uint64_t m = __ballot(d_nt > 0 && d_t0 <= T);
-      const int dd = 63 - __builtin_clzll(m);
-      k = T - __builtin_amdgcn_readlane(d_t0, dd);
-      rs = __builtin_amdgcn_readlane(d_rs, dd);
-      re = __builtin_amdgcn_readlane(d_re, dd);
-    };
-#pragma unroll
-    for (int j = 0; j < TS::kPieceCopiesPerWave; ++j) {
-      const int slot = kDenseWaves * j + w;
-      const int u = slot / TS::kPieceWaves, role = slot % TS::kPieceWaves;
-      int k, rs, re;
-      locate(min(G * kGroup + u, n_tiles - 1), k, rs, re);
-      TS::copy_piece(P.D.vecs, base, rs, re, k, buf + u * (TS::kStageBytes / 16), role, l);
-    }
-#pragma unroll
-    for (int j = 0; j < TS::kScaleCopiesPerWave; ++j) {
-      const int u = kDenseWaves * j + w;
-      int k, rs, re;
-      locate(min(G * kGroup + u, n_tiles - 1), k, rs, re);
-      TS::copy_scales(P.D.scales, base, rs, re, k, buf + u * (TS::kStageBytes / 16), l);
-    }
-  };
-
-  float part = 0.0f;                                            // lane dd: partial score carried to the next pass
-  for (int pass = 0; pass < n_pass; ++pass) {
-    const int pt0 = pass * NT;
-    DensePass<DT> S;
-    S.nct = __builtin_amdgcn_readfirstlane(max(0, min(NT, total_tiles - pt0)));
-    // tile map of this pass: owner query, first/last flags, B operand rows
-#pragma unroll
-    for (int i = 0; i < NT / 4; ++i) S.qs[i] = 1.0f;
-    S.tq_lane = 0;
-    S.first_mask = 0;
-    S.last_mask = 0;
-#pragma unroll
-    for (int ct = 0; ct < NT; ++ct) {
-      O::zero(S.B[ct]);
-      if (ct < S.nct) {
-        const int t = pt0 + ct;
-        const uint64_t own = __ballot(l < nq && qt0 <= t && t < qt0 + qnt);
-        const int j = __ffsll((unsigned long long)own) - 1;
-        const int jt0 = __builtin_amdgcn_readlane(qt0, j);
-        const int jm = __builtin_amdgcn_readlane(qm, j);
-        const int64_t jrow = (int64_t)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(qrow >> 32), j) << 32) |
-                                       __builtin_amdgcn_readlane((uint32_t)qrow, j));
-        const int k = t - jt0;                                  // tile index inside query j
-        if (l == ct) S.tq_lane = j;
-        if (k == 0) S.first_mask |= 1ull << ct;
-        if (16 * (k + 1) >= jm) S.last_mask |= 1ull << ct;
-        if (16 * k + c16 < jm) {
-          O::load_b(S.B[ct], P.Q.vecs, P.Q.scales, jrow + 16 * k + c16, g);
-          if constexpr (O::kColumnScale)
-            if (g == (ct & 3)) S.qs[ct >> 2] = P.Q.scales[jrow + 16 * k + c16];
+  for (int64_t it = slot; it < n_items; it += n_slots) {
+    const int64_t bgi = it % n_bg;
+    if (bgi != cur_bg) {
+      cur_bg = bgi;
+      b_loaded = false;
+      const int64_t b = bgi * kDenseWaves + w;
+      int q1 = 0;
+      q0 = 0;
+      if (b < P.n_blocks_max) { q0 = P.qb[b]; q1 = P.qb[b + 1]; }
+      nq = max(q1 - q0, 0);                                    // 0: this wave only helps copy
+      // lane j < nq: query j of the block (first row, length, first tile, tiles)
+      qrow = 0; qm = 0; qt0 = 0; qnt = 0;
+      total_tiles = 0;
+      if (nq > 0) {
+        const int64_t col0 = P.qcol[q0];
+        if (l < nq) {
+          qrow = P.Q.off[q0 + l];
+          qm = (int)(P.Q.off[q0 + l + 1] - qrow);
+          qt0 = (int)((P.qcol[q0 + l] - col0) >> 4);
+          qnt = (qm + 15) >> 4;
         }
+        total_tiles = (int)((P.qcol[q1] - col0) >> 4);
       }
-    }
+      total_tiles = __builtin_amdgcn_readfirstlane(total_tiles);
+      __syncthreads();                                         // lds_npass of the previous group is read
+      if (l == 0) lds_npass[w] = (total_tiles + NT - 1) / NT;
+      __syncthreads();
+      n_pass = 0;
 #pragma unroll
-    for (int ct = 0; ct < NT; ++ct) { S.rm[ct] = ninf; S.tsum[ct] = 0.0f; }
-    __builtin_amdgcn_s_waitcnt(0);                             // operands in; the stream starts from zero
+      for (int i = 0; i < kDenseWaves; ++i) n_pass = max(n_pass, lds_npass[i]);
+    }
+    const int64_t pc0 = c_lo + (it / n_bg) * piece;
+    const int64_t pc1 = min(c_hi, pc0 + piece);
+    for (int64_t chunk = pc0; chunk < pc1; ++chunk) {
+      const int64_t p0 = chunk * kChunkDocs;
+      const int64_t p1 = min(P.D.n_sets, p0 + kChunkDocs);
+      const int nd = (int)(p1 - p0);
 
-    // group G (in buffer X): wait for this wave's copies of G, publish G with
-    // one barrier (which also frees the buffer G - 1 used), start the copies
-    // of G + 2 into that buffer, then multiply G's tiles
-    auto group = [&](auto xbuf, int G) {
-      constexpr int X = decltype(xbuf)::value;
-      const u32x4* buf = X == 0 ? lds_buf0 : (X == 1 ? lds_buf1 : lds_buf2);
-      wait_vm<TS::kCopiesPerWave>();                            // only group G + 1's copies may be in flight
-      compiler_fence();
-      __builtin_amdgcn_s_barrier();
-      compiler_fence();
-      issue(std::integral_constant<int, (X + 2) % 3>{}, G + 2);
-      const int nt = min(kGroup, n_tiles - G * kGroup);           // <= 0 past the end
-      const int T0 = G * kGroup;
-      // (the unbranched body keeps two column groups' accumulators live,
-      // which only fits when a pass holds at most 8 column tiles)
-      if (NT <= 8 && S.nct == NT) {
-#pragma nounroll
-        for (int u = 0; u < nt; ++u) {
-          Frag A;
-          frag_from_lds<DT>(A, buf + u * (TS::kStageBytes / 16), c16, g);
-          S.template tile<true>(A, __ballot(d_tl == T0 + u));
-        }
-      } else if (S.nct > 0) {
-#pragma nounroll
-        for (int u = 0; u < nt; ++u) {
-          Frag A;
-          frag_from_lds<DT>(A, buf + u * (TS::kStageBytes / 16), c16, g);
-          S.template tile<false>(A, __ballot(d_tl == T0 + u));
-        }
+      // the chunk's document tiles, in order: lane dd < nd holds document
+      // p0 + dd's rows (relative to the chunk's first row), its first tile in
+      // the chunk's tile sequence and its last tile (-1 when it is empty)
+      const int64_t base = P.D.off[p0];
+      int d_rs = 0, d_re = 0;
+      if (l < nd) {
+        d_rs = (int)(P.D.off[p0 + l] - base);
+        d_re = (int)(P.D.off[p0 + l + 1] - base);
       }
-    };
-    if (n_tiles > 0) {
-      issue(std::integral_constant<int, 0>{}, 0);
-      issue(std::integral_constant<int, 1>{}, 1);
-    }
-    // whole triples of groups (the ones past the end hold no tiles), so that
-    // every path through the loop issues the same copies
-    for (int G = 0; G < n_groups; G += 3) {
-      group(std::integral_constant<int, 0>{}, G);
-      group(std::integral_constant<int, 1>{}, G + 1);
-      group(std::integral_constant<int, 2>{}, G + 2);
-    }
-    wait_vm<0>();                                               // no copy outlives the pass
-    __syncthreads();                                            // buffers are reused by the next pass
-    // each query's score: its tile sums in tile order (continuing the partial
-    // score of a query that began in the previous pass); finished queries
-    // store one 64-document row each (empty documents score -inf)
-    float s_run = part;
+      const int d_nt = (d_re - d_rs + 15) >> 4;
+      int d_incl = d_nt;
 #pragma unroll
-    for (int ct = 0; ct < NT; ++ct) {
-      if (ct < S.nct) {
-        s_run = ((S.first_mask >> ct) & 1) ? S.tsum[ct] : s_run + S.tsum[ct];
-        if ((S.last_mask >> ct) & 1) {
-          const int j = __builtin_amdgcn_readlane(S.tq_lane, ct);
+      for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(d_incl, o);
+        if (l >= o) d_incl += v;
+      }
+      const int d_t0 = d_incl - d_nt;
+      const int d_tl = d_nt > 0 ? d_incl - 1 : -1;
+      const int n_tiles = __builtin_amdgcn_readlane(d_incl, 63);
+      const bool doc_empty = l < nd && d_nt == 0;
+      const int n_groups = (n_tiles + kGroup - 1) / kGroup;
+
+      // copies of group G into buffer Y. Every wave issues exactly
+      // kCopiesPerWave copies per group, also past the last tile (those
+      // repeat the last tile into slots that are never read), so that the
+      // copies of later groups alone fill the wait count: the compiler can
+      // then prove that the buffer being read has landed without waiting for
+      // every copy.
+      auto issue = [&](auto ybuf, int G) {
+        constexpr int Y = decltype(ybuf)::value;
+        u32x4* buf = Y == 0 ? lds_buf0 : (Y == 1 ? lds_buf1 : lds_buf2);
+        // tile T belongs to the last non-empty document whose first tile is <= T
+        auto locate = [&](int T, int& k, int& rs, int& re) {
+          const uint64_t m = __ballot(d_nt > 0 && d_t0 <= T);
+          const int dd = 63 - __builtin_clzll(m);
+          k = T - __builtin_amdgcn_readlane(d_t0, dd);
+          rs = __builtin_amdgcn_readlane(d_rs, dd);
+          re = __builtin_amdgcn_readlane(d_re, dd);
+        };
+#pragma unroll
+        for (int j = 0; j < TS::kPieceCopiesPerWave; ++j) {
+          const int slot_j = kDenseWaves * j + w;
+          const int u = slot_j / TS::kPieceWaves, role = slot_j % TS::kPieceWaves;
+          int k, rs, re;
+          locate(min(G * kGroup + u, n_tiles - 1), k, rs, re);
+          TS::copy_piece(P.D.vecs, base, rs, re, k, buf + u * (TS::kStageBytes / 16), role, l);
+        }
+#pragma unroll
+        for (int j = 0; j < TS::kScaleCopiesPerWave; ++j) {
+          const int u = kDenseWaves * j + w;
+          int k, rs, re;
+          locate(min(G * kGroup + u, n_tiles - 1), k, rs, re);
+          TS::copy_scales(P.D.scales, base, rs, re, k, buf + u * (TS::kStageBytes / 16), l);
+        }
+      };
+
+      float part = 0.0f;                                        // lane dd: partial score carried to the next pass
+      for (int pass = 0; pass < n_pass; ++pass) {
+        if (!(b_loaded && n_pass == 1)) {
+          // query columns of this pass: owner query, first/last flags, B operand rows
+          const int pt0 = pass * NT;
+          S.nct = __builtin_amdgcn_readfirstlane(max(0, min(NT, total_tiles - pt0)));
+#pragma unroll
+          for (int i = 0; i < NT / 4; ++i) S.qs[i] = 1.0f;
+          S.tq_lane = 0;
+          S.first_mask = 0;
+          S.last_mask = 0;
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct) {
+            O::zero(S.B[ct]);
+            if (ct < S.nct) {
+              const int t = pt0 + ct;
+              const uint64_t own = __ballot(l < nq && qt0 <= t && t < qt0 + qnt);
+              const int j = __ffsll((unsigned long long)own) - 1;
+              const int jt0 = __builtin_amdgcn_readlane(qt0, j);
+              const int jm = __builtin_amdgcn_readlane(qm, j);
+              const int64_t jrow = (int64_t)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(qrow >> 32), j) << 32) |
+                                             __builtin_amdgcn_readlane((uint32_t)qrow, j));
+              const int k = t - jt0;                            // tile index inside query j
+              if (l == ct) S.tq_lane = j;
+              if (k == 0) S.first_mask |= 1ull << ct;
+              if (16 * (k + 1) >= jm) S.last_mask |= 1ull << ct;
+              if (16 * k + c16 < jm) {
+                O::load_b(S.B[ct], P.Q.vecs, P.Q.scales, jrow + 16 * k + c16, g);
+                if constexpr (O::kColumnScale)
+                  if (g == (ct & 3)) S.qs[ct >> 2] = P.Q.scales[jrow + 16 * k + c16];
+              }
+            }
+          }
+          b_loaded = true;
+        }
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) { S.rm[ct] = ninf; S.tsum[ct] = 0.0f; }
+        __builtin_amdgcn_s_waitcnt(0);                         // operands in; the stream starts from zero
+
+        // group G (in buffer X): wait for this wave's copies of G, publish G
+        // with one barrier (which also frees the buffer G - 1 used), start the
+        // copies of G + 2 into that buffer, then multiply G's tiles
+        auto group = [&](auto xbuf, int G) {
+          constexpr int X = decltype(xbuf)::value;
+          const u32x4* buf = X == 0 ? lds_buf0 : (X == 1 ? lds_buf1 : lds_buf2);
+          wait_vm<TS::kCopiesPerWave>();                        // only group G + 1's copies may be in flight
+          compiler_fence();
+          __builtin_amdgcn_s_barrier();
+          compiler_fence();
+          issue(std::integral_constant<int, (X + 2) % 3>{}, G + 2);
+          const int nt = min(kGroup, n_tiles - G * kGroup);       // <= 0 past the end
+          const int T0 = G * kGroup;
+          // (the unbranched body keeps two column groups' accumulators live,
+          // which only fits when a pass holds at most 8 column tiles)
+          if (NT <= 8 && S.nct == NT) {
+#pragma nounroll
+            for (int u = 0; u < nt; ++u) {
+              Frag A;
+              frag_from_lds<DT>(A, buf + u * (TS::kStageBytes / 16), c16, g);
+              S.template tile<true>(A, __ballot(d_tl == T0 + u));
+            }
+          } else if (S.nct > 0) {
+#pragma nounroll
+            for (int u = 0; u < nt; ++u) {
+              Frag A;
+              frag_from_lds<DT>(A, buf + u * (TS::kStageBytes / 16), c16, g);
+              S.template tile<false>(A, __ballot(d_tl == T0 + u));
+            }
+          }
+        };
+        if (n_tiles > 0) {
+          issue(std::integral_constant<int, 0>{}, 0);
+          issue(std::integral_constant<int, 1>{}, 1);
+        }
+        // whole triples of groups (the ones past the end hold no tiles), so
+        // that every path through the loop issues the same copies
+        for (int G = 0; G < n_groups; G += 3) {
+          group(std::integral_constant<int, 0>{}, G);
+          group(std::integral_constant<int, 1>{}, G + 1);
+          group(std::integral_constant<int, 2>{}, G + 2);
+        }
+        wait_vm<0>();                                           // no copy outlives the pass
+        __syncthreads();                                        // buffers are reused by the next pass
+        // each query's score: its tile sums in tile order (continuing the
+        // partial score of a query that began in the previous pass); finished
+        // queries store one row of the chunk's documents each (empty
+        // documents score -inf)
+        float s_run = part;
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+          if (ct < S.nct) {
+            s_run = ((S.first_mask >> ct) & 1) ? S.tsum[ct] : s_run + S.tsum[ct];
+            if ((S.last_mask >> ct) & 1) {
+              const int j = __builtin_amdgcn_readlane(S.tq_lane, ct);
+              const int64_t row = P.out.rows ? (int64_t)P.out.rows[q0 + j] : (int64_t)(q0 + j);
+              if (l < nd) P.out.scores[row * P.out.ld + p0 + l] = doc_empty ? ninf : s_run;
+            }
+          }
+        }
+        part = s_run;
+      }
+      // empty queries score 0 against every document
+      for (int j = 0; j < nq; ++j) {
+        if (__builtin_amdgcn_readlane(qm, j) == 0 && l < nd) {
           const int64_t row = P.out.rows ? (int64_t)P.out.rows[q0 + j] : (int64_t)(q0 + j);
-          if (l < nd) P.out.scores[row * P.out.ld + p0 + l] = doc_empty ? ninf : s_run;
+          P.out.scores[row * P.out.ld + p0 + l] = 0.0f;
         }
       }
     }
-    part = s_run;
   }
-  // empty queries score 0 against every document
-  for (int j = 0; j < nq; ++j) {
-    if (__builtin_amdgcn_readlane(qm, j) == 0 && l < nd) {
-      const int64_t row = P.out.rows ? (int64_t)P.out.rows[q0 + j] : (int64_t)(q0 + j);
-      P.out.scores[row * P.out.ld + p0 + l] = 0.0f;
-    }
+}
+
+// Workgroups per XCD of the persistent dense scorer: one per compute unit
+// (the LDS stages allow one resident workgroup per CU).
+static int dense_slots_per_xcd() {
+  static int cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 32;
+  if (cached[dev] == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 8) cus = 256;
+    cached[dev] = cus / 8;
   }
+  return cached[dev];
 }
 
 hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, const int32_t* qb_start,
@@ -678,26 +717,17 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
   P.Q = Q; P.D = D; P.qb = qb_start; P.qcol = qcol; P.n_blocks_max = n_blocks_max;
   P.n_bgroups = (n_blocks_max + kDenseWaves - 1) / kDenseWaves;
   P.out = out;
-  const int64_t n_chunks = (D.n_sets + kChunkDocs - 1) / kChunkDocs;
-  if (P.n_bgroups == 0 || n_chunks == 0) return hipSuccess;
-  // slices of whole chunks, each launch within the dispatch's work-item limit
-  const int64_t max_items = (kMaxGridThreads / kDenseThreads) & ~int64_t(7);
-  const int64_t slice = std::max<int64_t>(1, max_items / P.n_bgroups);
-  const dim3 blk(kDenseThreads);
-  for (int64_t c0 = 0; c0 < n_chunks; c0 += slice) {
-    P.chunk0 = c0;
-    P.n_chunks = std::min(slice, n_chunks - c0);
-    const int64_t grid = ((P.n_bgroups * P.n_chunks + 7) / 8) * 8;
-    switch (dtype) {
-      case GEM_F32: hipLaunchKernelGGL(score_dense_kernel<GEM_F32>, dim3((unsigned)grid), blk, 0, s, P); break;
-      case GEM_BF16: hipLaunchKernelGGL(score_dense_kernel<GEM_BF16>, dim3((unsigned)grid), blk, 0, s, P); break;
-      case GEM_FP8_E4M3: hipLaunchKernelGGL(score_dense_kernel<GEM_FP8_E4M3>, dim3((unsigned)grid), blk, 0, s, P); break;
-      default: return hipErrorInvalidValue;
-    }
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  P.chunk0 = 0;
+  P.n_chunks = (D.n_sets + kChunkDocs - 1) / kChunkDocs;
+  if (P.n_bgroups == 0 || P.n_chunks == 0) return hipSuccess;
+  const dim3 grid((unsigned)(8 * dense_slots_per_xcd())), blk(kDenseThreads);
+  switch (dtype) {
+    case GEM_F32: hipLaunchKernelGGL(score_dense_kernel<GEM_F32>, grid, blk, 0, s, P); break;
+    case GEM_BF16: hipLaunchKernelGGL(score_dense_kernel<GEM_BF16>, grid, blk, 0, s, P); break;
+    case GEM_FP8_E4M3: hipLaunchKernelGGL(score_dense_kernel<GEM_FP8_E4M3>, grid, blk, 0, s, P); break;
+    default: return hipErrorInvalidValue;
   }
-  return hipSuccess;
+  return hipGetLastError();
 }
 
 // --------------------------------------------------------------------------
