@@ -479,10 +479,16 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
   const int64_t slot = blockIdx.x >> 3, n_slots = gridDim.x >> 3;
   const int64_t c_lo = P.chunk0 + (P.n_chunks * xcd) / 8;
   const int64_t c_hi = P.chunk0 + (P.n_chunks * (xcd + 1)) / 8;
-  // pieces sized for about 8 items per workgroup (load balance), whole
-  // ranges when block groups alone fill the workgroups
-  const int64_t piece = max((int64_t)1, ((c_hi - c_lo) * n_bg + 8 * n_slots - 1) / (8 * n_slots));
-  const int64_t n_items = ((c_hi - c_lo + piece - 1) / piece) * n_bg;
+  // about 8 items per workgroup, the piece count rounded so that the items
+  // divide evenly over the workgroups; piece p is chunks
+  // [c_lo + p C / np, c_lo + (p + 1) C / np)
+  const int64_t C = c_hi - c_lo;
+  int64_t ga = n_slots, gb = n_bg;
+  while (gb != 0) { const int64_t t = ga % gb; ga = gb; gb = t; }
+  const int64_t even = n_slots / ga;                           // piece counts that divide evenly: multiples of this
+  int64_t np = (8 * n_slots + n_bg - 1) / n_bg;
+  np = min(((np + even - 1) / even) * even, C);
+  const int64_t n_items = np * n_bg;
 
   DensePass<DT> S;
   int64_t cur_bg = -1;
@@ -522,8 +528,9 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
 #pragma unroll
       for (int i = 0; i < kDenseWaves; ++i) n_pass = max(n_pass, lds_npass[i]);
     }
-    const int64_t pc0 = c_lo + (it / n_bg) * piece;
-    const int64_t pc1 = min(c_hi, pc0 + piece);
+    const int64_t pidx = it / n_bg;
+    const int64_t pc0 = c_lo + (pidx * C) / np;
+    const int64_t pc1 = c_lo + ((pidx + 1) * C) / np;
     for (int64_t chunk = pc0; chunk < pc1; ++chunk) {
       const int64_t p0 = chunk * kChunkDocs;
       const int64_t p1 = min(P.D.n_sets, p0 + kChunkDocs);
