@@ -201,6 +201,87 @@ def test_batch_independence_bitwise():
         np.testing.assert_array_equal(sub, full[[5, 3, 30]])
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_dense_many_blocks_long_documents(dtype):
+    """More than 32 block groups for every dtype (more groups than workgroups
+    per XCD), documents of up to 1000 vectors and a chunk of them (a 64-document
+    chunk holding hundreds of tiles), and a document count that leaves a partial
+    last chunk."""
+    rng = np.random.default_rng(12)
+    qlens = list(rng.integers(1, 101, 1100))
+    dlens = [300, 700, 0, 1, 1000] + list(rng.integers(1, 200, 126))
+    q, c = _ragged(qlens, 50), _ragged(dlens, 51)
+    D, Q = _device_sets(c, dtype), gem.Sets.from_batch(q, DEV)
+    scores = _score(Q, D, dtype)
+    torch.cuda.synchronize()
+    ref = oracle.ch_dense(_operands(q.vecs.numpy(), dtype), q.offsets.numpy(),
+                          _operands(c.vecs.numpy(), dtype), c.offsets.numpy())
+    assert_close(_np(scores), ref, what=f"many blocks {dtype}")
+
+
+@pytest.fixture(scope="module")
+def exhaustive_100k():
+    """The exhaustive-100k workload (1000 queries x 32 vectors, 100,000 documents
+    with lognormal lengths), generated on the device as the benchmark does."""
+    w2 = wl.WORKLOADS[2]
+    c = wl.corpus(w2, device=DEV)
+    q = wl.queries(w2, device=DEV)
+    yield w2, c, q
+    del c, q
+    torch.cuda.empty_cache()
+
+
+def _sub_host(batch: wl.SetBatch, idx) -> wl.SetBatch:
+    s = batch.subset(list(idx))
+    return wl.SetBatch(s.vecs.cpu(), s.offsets.cpu())
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8", "f32"])
+def test_dense_full_size_sampled(exhaustive_100k, dtype):
+    """Full size, in the benchmark's launch configuration: sampled (query,
+    document) pairs against the oracle, including chunk-boundary documents."""
+    w2, c, q = exhaustive_100k
+    D = _device_sets(c, dtype)
+    Q = gem.Sets(q.vecs, q.offsets, "f32", q.max_len())
+    scores = _score(Q, D, dtype)
+    torch.cuda.synchronize()
+    n_d = c.n_sets
+    rng = np.random.default_rng(13)
+    qs = [0, 1, 31, 32, 499, 998, 999]
+    ds = sorted(set(rng.integers(0, n_d, 150).tolist()) | {0, 63, 64, 65, 127, 128, n_d - 65, n_d - 1})
+    sq, sd = _sub_host(q, qs), _sub_host(c, ds)
+    ref = oracle.ch_dense(_operands(sq.vecs.numpy(), dtype), sq.offsets.numpy(),
+                          _operands(sd.vecs.numpy(), dtype), sd.offsets.numpy())
+    got = _np(scores[qs][:, ds])
+    assert_close(got, ref, what=f"full size {dtype}")
+
+
+def test_dense_full_size_row_and_top100(exhaustive_100k):
+    """Full size: one query's whole bf16 row against the oracle, and its top-100
+    (the benchmark step's output) against the oracle's ranking outside ties."""
+    w2, c, q = exhaustive_100k
+    D = _device_sets(c, "bf16")
+    Q = gem.Sets(q.vecs, q.offsets, "f32", q.max_len())
+    scores = _score(Q, D, "bf16")
+    top_s, top_i = gem.topk(scores, w2.k)
+    torch.cuda.synchronize()
+    qi = 7
+    sq = _sub_host(q, [qi])
+    qop = _operands(sq.vecs.numpy(), "bf16")
+    off = c.offsets.cpu().numpy()
+    row = np.empty(c.n_sets)
+    step = 5000
+    for j0 in range(0, c.n_sets, step):
+        j1 = min(c.n_sets, j0 + step)
+        r0, r1 = int(off[j0]), int(off[j1])
+        dv = _operands(c.vecs[r0:r1].cpu().numpy(), "bf16")
+        row[j0:j1] = oracle.ch_dense(qop, sq.offsets.numpy(), dv, off[j0:j1 + 1] - r0)[0]
+    assert_close(_np(scores[qi]), row, what="full row")
+    tau = 2 * TOL * max(abs(np.sort(row)[::-1][w2.k - 1]), 1.0)
+    ok, bad, missing = oracle.tie_aware_match(_np(top_i[qi]), row, w2.k, tau)
+    assert ok, (bad, missing)
+
+
 # ----------------------------------------------------------------------- gathered
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 def test_gather_matches_oracle_and_dense(dtype):
@@ -235,7 +316,7 @@ def test_topk_bitwise(mode):
     s_np, off_np = s.numpy(), off.numpy()
     rng = np.random.default_rng(6)
     ids = rng.integers(-1, 5000, s_np.size).astype(np.int32)        # repeats and padding ids
-    for k in (1, 10, 100, 1000):
+    for k in (1, 10, 100, 1000, 1024):
         if mode == "rows":
             n, L = 12, 7000
             mat = np.random.default_rng(7).standard_normal((n, L)).astype(np.float32)
@@ -277,13 +358,15 @@ def test_topk_long_segments_with_repeats():
 
 
 # ----------------------------------------------------------------------- beam
-def test_beam_merge_bitwise():
-    n_q, ef = 9, 50
+@pytest.mark.parametrize("n_q,ef,max_list,n_docs", [(9, 50, 80, 2000), (5, 1024, 3000, 20000)])
+def test_beam_merge_bitwise(n_q, ef, max_list, n_docs):
+    """Beam updates against the oracle's replay, up to ef = 1024 with 3000-entry
+    lists (the largest merge is ef + list = 4024 entries)."""
     beam = gem.Beam(n_q, ef, DEV)
     steps = []
     for st in range(6):
-        s, off = wl.random_scores(n_q, ("uniform", 0, 80), seed=100 + st, tie_frac=0.2)
-        ids = wl.candidate_ids(1, int(off[-1]) or 1, 2000, seed=200 + st).reshape(-1)[: int(off[-1])]
+        s, off = wl.random_scores(n_q, ("uniform", 0, max_list), seed=100 + st, tie_frac=0.2)
+        ids = wl.candidate_ids(1, int(off[-1]) or 1, n_docs, seed=200 + st).reshape(-1)[: int(off[-1])]
         # a document keeps one score across steps
         s = torch.from_numpy(np.sin(ids.numpy().astype(np.float64) * 0.37).astype(np.float32)) if st % 2 else s
         C = gem.Cands(ids.contiguous().to(DEV), off.to(DEV))
