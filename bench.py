@@ -149,6 +149,10 @@ def bench_exhaustive(args):
     k = w2.k
     scores = torch.empty(n_q, n_d, dtype=torch.float32, device=dev)
     Q16 = None
+    # the autotuner picks the dense scorer's schedule for this shape (untimed)
+    sched = {}
+    sched["bf16"], _ = gem.autotune_dense(gem.convert_bf16(Q), D16, reps=2, scores=scores)
+    log(f"bf16 schedule {sched['bf16']}")
 
     def step():
         nonlocal Q16
@@ -177,6 +181,7 @@ def bench_exhaustive(args):
     log(f"bf16 step {ms_per_step:.2f} ms (convert {t_conv:.3f}, score {t_score:.2f}, top-k {t_topk:.2f})")
 
     # float32 exact path (reference "plain FP32 GPU path") on the same batch
+    sched["f32"], _ = gem.autotune_dense(Q, D32, reps=1, scores=scores)
     top32_s, top32_i = gem.score_exact(Q, D32, compute="f32", k=k)
     torch.cuda.synchronize()
     t_f32 = timed(lambda: gem.score_exact(Q, D32, compute="f32", k=k), 1)
@@ -186,6 +191,7 @@ def bench_exhaustive(args):
     sl = 1000
     Q8 = gem.quantize_fp8(Q)
     est = torch.empty(n_q, n_d, dtype=torch.float32, device=dev)
+    sched["fp8"], _ = gem.autotune_dense(Q8, D8, reps=2, scores=est)
 
     def fp8_path():
         q8 = gem.quantize_fp8(Q)
@@ -235,6 +241,7 @@ def bench_exhaustive(args):
                      "flops_per_launch": flops, "traffic_unit": "HBM bytes per launch",
                      "algorithmic_bytes_per_launch": V * 128 * 2 + q_rows * 128 * 2 + n_q * n_d * 4},
         "stages_ms": {"query_convert": t_conv, "score_dense_bf16": t_score, "topk_100": t_topk},
+        "dense_schedule": sched,
         "corpus_convert_ms": {"bf16": t_bf16, "fp8": t_fp8},
         "f32_exact_path": {"ms": t_f32, "pair_scores_per_s": pairs / (t_f32 / 1e3),
                            "tflops": flops / (t_f32 / 1e3) / 1e12,

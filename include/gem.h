@@ -36,7 +36,8 @@
  *     non-empty query against an empty document is -inf (max over nothing).
  *   - Top-k order is score descending, then id ascending; ids are distinct; a
  *     list shorter than k is padded with (-inf, -1).
- *   - A context is read-only after gem_create: several host threads may share it.
+ *   - Several host threads may share a context; its only mutable state, the
+ *     table of dense-scorer schedules, is guarded by a lock.
  */
 #ifndef GEM_H_
 #define GEM_H_
@@ -226,6 +227,46 @@ gem_status gem_beam_reset(gem_ctx ctx, gem_beam* beam, int64_t n_queries, hipStr
  * Synchronizes `stream`; returns GEM_ERR_DEVICE_CHECK on a violation. */
 gem_status gem_validate_sets(gem_ctx ctx, const gem_sets* S, hipStream_t stream);
 gem_status gem_validate_cands(gem_ctx ctx, const gem_cands* C, int64_t n_sets, hipStream_t stream);
+
+/* Schedule of the exhaustive (dense) scorer: how the work of one call is laid
+ * out over the GPU. Persistent workgroups (slots_per_xcd on each of the 8 XCDs)
+ * step through chunks of chunk_docs documents; each XCD's chunks are cut into
+ * pieces so that every workgroup gets about items_per_slot (piece, query block
+ * group) items. A schedule changes the time of a call, never its results:
+ * every schedule computes bitwise the same scores.
+ *   chunk_docs: 32 or 64; items_per_slot: 1..64; slots_per_xcd: 1..(CUs / 8).
+ */
+typedef struct {
+  int32_t chunk_docs;
+  int32_t items_per_slot;
+  int32_t slots_per_xcd;
+  int32_t reserved;
+} gem_dense_schedule;
+
+/* Schedules are kept per shape class: the compute dtype and the power-of-two
+ * classes (floor(log2(x + 1))) of the query batch's vector count and of the
+ * document count. A class without an installed schedule uses the library's
+ * default (64-document chunks, 8 items per workgroup, one workgroup per CU).
+ *   gem_get_dense_schedule: the schedule a dense call of this shape would use.
+ *   gem_set_dense_schedule: install `sched` for the class (NULL: back to the default).
+ */
+gem_status gem_get_dense_schedule(gem_ctx ctx, int32_t dtype, int64_t q_rows, int64_t n_docs,
+                                  gem_dense_schedule* out);
+gem_status gem_set_dense_schedule(gem_ctx ctx, int32_t dtype, int64_t q_rows, int64_t n_docs,
+                                  const gem_dense_schedule* sched);
+
+/* Autotuner for the dense scorer. Runs the exhaustive scoring of Q against D
+ * (as gem_score_exact / gem_score_quant with C = NULL and k = 0 would, writing
+ * scores [n_q][ld_scores]) once untimed and `reps` (1..100) times timed under
+ * each candidate schedule, installs the fastest for the call's shape class and
+ * returns it with its mean time per call in milliseconds. Synchronizes `stream`.
+ * The candidates vary chunk_docs (64, 32) and items_per_slot (4, 8, 16). The
+ * workspace must hold gem_workspace_bytes(ctx, op, Q, D, NULL, compute, 0, 1)
+ * bytes (op GEM_OP_SCORE_EXACT, or GEM_OP_SCORE_QUANT for FP8).
+ */
+gem_status gem_autotune_dense(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, int32_t compute, float* scores,
+                              int64_t ld_scores, void* ws, size_t ws_bytes, hipStream_t stream, int32_t reps,
+                              gem_dense_schedule* best, float* best_ms);
 
 #ifdef __cplusplus
 }

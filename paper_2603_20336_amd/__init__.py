@@ -21,7 +21,8 @@ from ._abi import (GEM_BF16, GEM_F32, GEM_FP8_E4M3, GEM_MAX_K, GEM_MAX_QUERY_LEN
 
 __all__ = ["Sets", "Cands", "Beam", "GemError", "convert_bf16", "quantize_fp8", "score_exact",
            "score_quant", "topk", "expand_batch", "beam_merge", "beam_reset", "validate_sets", "validate_cands",
-           "library", "GEM_F32", "GEM_BF16", "GEM_FP8_E4M3", "GEM_MAX_K", "GEM_MAX_QUERY_LEN"]
+           "library", "GEM_F32", "GEM_BF16", "GEM_FP8_E4M3", "GEM_MAX_K", "GEM_MAX_QUERY_LEN", "dense_schedule",
+           "set_dense_schedule", "autotune_dense"]
 
 _DTYPES = {"f32": GEM_F32, "bf16": GEM_BF16, "fp8": GEM_FP8_E4M3,
            GEM_F32: GEM_F32, GEM_BF16: GEM_BF16, GEM_FP8_E4M3: GEM_FP8_E4M3}
@@ -230,6 +231,50 @@ def score_exact(Q: Sets, D: Sets, cands: Optional[Cands] = None, k: int = 0, com
     one score per candidate entry. k > 0 returns (top_scores, top_ids) (and
     the scores when want_scores)."""
     return _score(True, Q, D, cands, k, _DTYPES[compute], scores, ld, rows, want_scores, stream, ws)
+
+
+def _sched_dict(s) -> dict:
+    return {"chunk_docs": int(s.chunk_docs), "items_per_slot": int(s.items_per_slot),
+            "slots_per_xcd": int(s.slots_per_xcd)}
+
+
+def dense_schedule(dtype, q_rows: int, n_docs: int, device="cuda") -> dict:
+    """The dense-scorer schedule a call of this shape class uses."""
+    s = _abi.gem_dense_schedule()
+    _abi.check(library().gem_get_dense_schedule(_ctx(torch.device(device)), _DTYPES[dtype], int(q_rows),
+                                                int(n_docs), ctypes.byref(s)))
+    return _sched_dict(s)
+
+
+def set_dense_schedule(dtype, q_rows: int, n_docs: int, schedule: Optional[dict], device="cuda") -> None:
+    """Install a schedule for the shape class (None: back to the library default)."""
+    p = None
+    if schedule is not None:
+        s = _abi.gem_dense_schedule(int(schedule["chunk_docs"]), int(schedule["items_per_slot"]),
+                                    int(schedule["slots_per_xcd"]), 0)
+        p = ctypes.byref(s)
+    _abi.check(library().gem_set_dense_schedule(_ctx(torch.device(device)), _DTYPES[dtype], int(q_rows),
+                                                int(n_docs), p))
+
+
+def autotune_dense(Q: Sets, D: Sets, compute=None, reps: int = 2, scores: Optional[torch.Tensor] = None,
+                   ld: int = 0, stream=None):
+    """Time the candidate schedules of the dense scorer on this call, install the
+    fastest for its shape class and return (schedule, ms per call)."""
+    compute = D.dtype if compute is None else _DTYPES[compute]
+    dev = D.device
+    if scores is None:
+        scores = torch.empty(Q.n_sets, D.n_sets, dtype=torch.float32, device=dev)
+    qs, ds = Q.struct(), D.struct()
+    op = _abi.GEM_OP_SCORE_QUANT if compute == GEM_FP8_E4M3 else _abi.GEM_OP_SCORE_EXACT
+    need = library().gem_workspace_bytes(_ctx(dev), op, ctypes.byref(qs), ctypes.byref(ds), None, compute, 0, 1)
+    ws = _ws(need, dev)
+    best = _abi.gem_dense_schedule()
+    ms = ctypes.c_float(0.0)
+    _abi.check(library().gem_autotune_dense(_ctx(dev), ctypes.byref(qs), ctypes.byref(ds), compute, _ptr(scores),
+                                            int(ld), _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream),
+                                            int(reps), ctypes.byref(best), ctypes.byref(ms)))
+    return _sched_dict(best), float(ms.value)
 
 
 def score_quant(Q: Sets, D8: Sets, cands: Optional[Cands] = None, k: int = 0,

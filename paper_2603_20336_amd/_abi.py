@@ -42,6 +42,10 @@ class gem_beam(ctypes.Structure):
     _fields_ = [("ef", i32), ("reserved", i32), ("scores", c_p), ("ids", c_p)]
 
 
+class gem_dense_schedule(ctypes.Structure):
+    _fields_ = [("chunk_docs", i32), ("items_per_slot", i32), ("slots_per_xcd", i32), ("reserved", i32)]
+
+
 P_SETS = ctypes.POINTER(gem_sets)
 P_CANDS = ctypes.POINTER(gem_cands)
 P_BEAM = ctypes.POINTER(gem_beam)
@@ -63,6 +67,10 @@ SIGNATURES = {
     "gem_beam_reset": (i32, [c_p, P_BEAM, i64, c_p]),
     "gem_validate_sets": (i32, [c_p, P_SETS, c_p]),
     "gem_validate_cands": (i32, [c_p, P_CANDS, i64, c_p]),
+    "gem_get_dense_schedule": (i32, [c_p, i32, i64, i64, ctypes.POINTER(gem_dense_schedule)]),
+    "gem_set_dense_schedule": (i32, [c_p, i32, i64, i64, ctypes.POINTER(gem_dense_schedule)]),
+    "gem_autotune_dense": (i32, [c_p, P_SETS, P_SETS, i32, c_p, i64, c_p, sz, c_p, i32,
+                                 ctypes.POINTER(gem_dense_schedule), ctypes.POINTER(ctypes.c_float)]),
 }
 
 _lib = None

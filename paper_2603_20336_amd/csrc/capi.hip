@@ -5,7 +5,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "gem_internal.h"
 
@@ -15,6 +18,10 @@ struct gem_ctx_s {
   int device;
   int n_cu;
   char arch[64];
+  // dense-scorer schedules installed by gem_set_dense_schedule / gem_autotune_dense,
+  // keyed by (dtype, shape class)
+  std::mutex mu;
+  std::map<uint64_t, gem::DenseSchedule> dense;
 };
 
 namespace {
@@ -157,9 +164,32 @@ gem_status convert_query(const gem_sets* Q, int32_t compute, void* ws, const Sco
   return GEM_OK;
 }
 
-gem_status score_common(const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t compute, int32_t k,
-                        float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,
-                        int32_t* top_ids, void* ws, size_t ws_bytes, hipStream_t stream) {
+int log2_class(int64_t v) {
+  int c = 0;
+  while (v > 1 && c < 62) { v >>= 1; ++c; }
+  return c;
+}
+
+// Shape class of a dense call: dtype, and the power-of-two classes of the
+// query batch's rows and of the document count.
+uint64_t dense_key(int32_t dtype, int64_t q_rows, int64_t n_docs) {
+  return ((uint64_t)(uint32_t)dtype << 16) | ((uint64_t)log2_class(q_rows + 1) << 8) |
+         (uint64_t)log2_class(n_docs + 1);
+}
+
+DenseSchedule lookup_dense(gem_ctx ctx, int32_t dtype, int64_t q_rows, int64_t n_docs) {
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto it = ctx->dense.find(dense_key(dtype, q_rows, n_docs));
+    if (it != ctx->dense.end()) return it->second;
+  }
+  return default_dense_schedule(dtype, q_rows, n_docs, ctx->n_cu / 8);
+}
+
+gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t compute,
+                        int32_t k, float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,
+                        int32_t* top_ids, void* ws, size_t ws_bytes, hipStream_t stream,
+                        const DenseSchedule* sched = nullptr) {
   gem_status st;
   if ((st = check_sets(Q, "Q", true)) != GEM_OK) return st;
   if ((st = check_sets(D, "D", false)) != GEM_OK) return st;
@@ -200,7 +230,8 @@ gem_status score_common(const gem_sets* Q, const gem_sets* D, const gem_cands* C
     out.scores = scores ? scores : reinterpret_cast<float*>(at(ws, L.staged));
     out.ld = scores ? ld_scores : D->n_sets;
     out.rows = scores ? score_rows : nullptr;
-    e = launch_score_dense(compute, view(&Qc), view(D), qb, qcol, L.n_blocks_max, out, stream);
+    const DenseSchedule ds = sched ? *sched : lookup_dense(ctx, compute, Q->n_vecs, D->n_sets);
+    e = launch_score_dense(compute, view(&Qc), view(D), qb, qcol, L.n_blocks_max, out, ds, stream);
     if (e != hipSuccess) return hip_fail(e, "dense scoring");
     if (k > 0) {
       TopkSegs S;
@@ -358,15 +389,16 @@ gem_status gem_score_exact(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, co
   if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
   if (compute != GEM_F32 && compute != GEM_BF16)
     return fail(GEM_ERR_INVALID, "exact scoring computes in F32 or BF16, not dtype %d", compute);
-  return score_common(Q, D, C, compute, k, scores, ld_scores, score_rows, top_scores, top_ids, ws, ws_bytes, stream);
+  return score_common(ctx, Q, D, C, compute, k, scores, ld_scores, score_rows, top_scores, top_ids, ws, ws_bytes,
+                      stream);
 }
 
 gem_status gem_score_quant(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t k,
                            float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,
                            int32_t* top_ids, void* ws, size_t ws_bytes, hipStream_t stream) {
   if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
-  return score_common(Q, D, C, GEM_FP8_E4M3, k, scores, ld_scores, score_rows, top_scores, top_ids, ws, ws_bytes,
-                      stream);
+  return score_common(ctx, Q, D, C, GEM_FP8_E4M3, k, scores, ld_scores, score_rows, top_scores, top_ids, ws,
+                      ws_bytes, stream);
 }
 
 gem_status gem_topk(gem_ctx ctx, const float* scores, const int64_t* seg_offsets, const int32_t* seg_ids,
@@ -483,6 +515,90 @@ gem_status gem_validate_cands(gem_ctx ctx, const gem_cands* C, int64_t n_sets, h
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "validation launch");
   return run_validation(stream, "cands");
+}
+
+
+static void to_public(const DenseSchedule& d, gem_dense_schedule* out) {
+  out->chunk_docs = d.chunk_docs;
+  out->items_per_slot = d.items_per_slot;
+  out->slots_per_xcd = d.slots_per_xcd;
+  out->reserved = 0;
+}
+
+gem_status gem_get_dense_schedule(gem_ctx ctx, int32_t dtype, int64_t q_rows, int64_t n_docs,
+                                  gem_dense_schedule* out) {
+  if (!ctx || !out) return fail(GEM_ERR_INVALID, "NULL argument");
+  if (!valid_dtype(dtype)) return fail(GEM_ERR_INVALID, "dtype %d", dtype);
+  to_public(lookup_dense(ctx, dtype, q_rows, n_docs), out);
+  return GEM_OK;
+}
+
+gem_status gem_set_dense_schedule(gem_ctx ctx, int32_t dtype, int64_t q_rows, int64_t n_docs,
+                                  const gem_dense_schedule* sched) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (!valid_dtype(dtype)) return fail(GEM_ERR_INVALID, "dtype %d", dtype);
+  const uint64_t key = dense_key(dtype, q_rows, n_docs);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (!sched) {
+    ctx->dense.erase(key);
+    return GEM_OK;
+  }
+  DenseSchedule d{sched->chunk_docs, sched->items_per_slot, sched->slots_per_xcd};
+  if (!dense_schedule_valid(d, ctx->n_cu / 8))
+    return fail(GEM_ERR_INVALID, "schedule (chunk_docs %d, items_per_slot %d, slots_per_xcd %d) outside the "
+                "supported range", d.chunk_docs, d.items_per_slot, d.slots_per_xcd);
+  ctx->dense[key] = d;
+  return GEM_OK;
+}
+
+gem_status gem_autotune_dense(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, int32_t compute, float* scores,
+                              int64_t ld_scores, void* ws, size_t ws_bytes, hipStream_t stream, int32_t reps,
+                              gem_dense_schedule* best, float* best_ms) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (!valid_dtype(compute)) return fail(GEM_ERR_INVALID, "compute dtype %d", compute);
+  if (!scores) return fail(GEM_ERR_INVALID, "autotuning needs a scores buffer");
+  if (reps < 1 || reps > 100) return fail(GEM_ERR_INVALID, "reps = %d outside [1, 100]", reps);
+  if (!Q || !D) return fail(GEM_ERR_INVALID, "NULL sets");
+  const int cpx = ctx->n_cu / 8;
+  std::vector<DenseSchedule> cand;
+  for (int cd : {64, 32})
+    for (int ips : {4, 8, 16})
+      cand.push_back(DenseSchedule{cd, ips, cpx});
+  hipEvent_t e0, e1;
+  hipError_t he = hipEventCreate(&e0);
+  if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
+  he = hipEventCreate(&e1);
+  if (he != hipSuccess) { hipEventDestroy(e0); return hip_fail(he, "hipEventCreate"); }
+  float best_t = -1.0f;
+  DenseSchedule best_s = cand[0];
+  gem_status st = GEM_OK;
+  for (const DenseSchedule& c : cand) {
+    // one untimed run, then `reps` timed back to back
+    st = score_common(ctx, Q, D, nullptr, compute, 0, scores, ld_scores, nullptr, nullptr, nullptr, ws, ws_bytes,
+                      stream, &c);
+    if (st != GEM_OK) break;
+    if ((he = hipEventRecord(e0, stream)) != hipSuccess) { st = hip_fail(he, "hipEventRecord"); break; }
+    for (int r = 0; r < reps && st == GEM_OK; ++r)
+      st = score_common(ctx, Q, D, nullptr, compute, 0, scores, ld_scores, nullptr, nullptr, nullptr, ws, ws_bytes,
+                        stream, &c);
+    if (st != GEM_OK) break;
+    if ((he = hipEventRecord(e1, stream)) != hipSuccess) { st = hip_fail(he, "hipEventRecord"); break; }
+    if ((he = hipEventSynchronize(e1)) != hipSuccess) { st = hip_fail(he, "hipEventSynchronize"); break; }
+    float ms = 0.0f;
+    if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { st = hip_fail(he, "hipEventElapsedTime"); break; }
+    ms /= (float)reps;
+    if (best_t < 0.0f || ms < best_t) { best_t = ms; best_s = c; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != GEM_OK) return st;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->dense[dense_key(compute, Q->n_vecs, D->n_sets)] = best_s;
+  }
+  if (best) to_public(best_s, best);
+  if (best_ms) *best_ms = best_t;
+  return GEM_OK;
 }
 
 }  // extern "C"

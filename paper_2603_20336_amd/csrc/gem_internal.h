@@ -53,8 +53,18 @@ struct DenseOut {
   const int32_t* rows;    // nullable
 };
 
+// Schedule of the persistent dense scorer (never changes a result).
+struct DenseSchedule {
+  int32_t chunk_docs;       // documents per chunk: 32 or 64
+  int32_t items_per_slot;   // target work items per workgroup
+  int32_t slots_per_xcd;    // workgroups per XCD (at most one per CU)
+};
+DenseSchedule default_dense_schedule(int dtype, int64_t q_rows, int64_t n_docs, int cus_per_xcd);
+bool dense_schedule_valid(const DenseSchedule& d, int cus_per_xcd);
+
 hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, const int32_t* qb_start,
-                              const int64_t* qcol, int64_t n_blocks_max, const DenseOut& out, hipStream_t s);
+                              const int64_t* qcol, int64_t n_blocks_max, const DenseOut& out,
+                              const DenseSchedule& sched, hipStream_t s);
 
 hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C,
                                int32_t max_list_len, int32_t max_q_len, float* scores, hipStream_t s);

@@ -285,7 +285,7 @@ hipError_t launch_plan_query_blocks(const int64_t* q_off, int64_t n_q, int block
 // ends with one coalesced 64-document row store per query.
 // Work items are laid out so that consecutive workgroups on one XCD (dispatch
 // is round-robin over the 8 XCDs) share a chunk.
-constexpr int kChunkDocs = 64;
+constexpr int kMaxChunkDocs = 64;               // a chunk's documents map to the 64 lanes
 constexpr int kBuffers = 3;                    // group buffers: two groups in flight
 constexpr int kDenseWaves = 8;                 // two waves per SIMD
 constexpr int kDenseThreads = 64 * kDenseWaves;
@@ -298,7 +298,9 @@ struct DenseParams {
   const int32_t* qb;
   const int64_t* qcol;
   int64_t n_blocks_max, n_bgroups, n_chunks;
-  int64_t chunk0;         // first document chunk of this launch (large batches launch in slices)
+  int64_t chunk0;         // first document chunk of this launch
+  int32_t chunk_docs;     // documents per chunk (<= kMaxChunkDocs)
+  int32_t items_per_slot; // target work items per workgroup
   DenseOut out;
 };
 
@@ -479,14 +481,14 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
   const int64_t slot = blockIdx.x >> 3, n_slots = gridDim.x >> 3;
   const int64_t c_lo = P.chunk0 + (P.n_chunks * xcd) / 8;
   const int64_t c_hi = P.chunk0 + (P.n_chunks * (xcd + 1)) / 8;
-  // about 8 items per workgroup, the piece count rounded so that the items
-  // divide evenly over the workgroups; piece p is chunks
+  // about items_per_slot items per workgroup, the piece count rounded so
+  // that the items divide evenly over the workgroups; piece p is chunks
   // [c_lo + p C / np, c_lo + (p + 1) C / np)
   const int64_t C = c_hi - c_lo;
   int64_t ga = n_slots, gb = n_bg;
   while (gb != 0) { const int64_t t = ga % gb; ga = gb; gb = t; }
   const int64_t even = n_slots / ga;                           // piece counts that divide evenly: multiples of this
-  int64_t np = (8 * n_slots + n_bg - 1) / n_bg;
+  int64_t np = ((int64_t)P.items_per_slot * n_slots + n_bg - 1) / n_bg;
   np = min(((np + even - 1) / even) * even, C);
   const int64_t n_items = np * n_bg;
 
@@ -532,8 +534,8 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
     const int64_t pc0 = c_lo + (pidx * C) / np;
     const int64_t pc1 = c_lo + ((pidx + 1) * C) / np;
     for (int64_t chunk = pc0; chunk < pc1; ++chunk) {
-      const int64_t p0 = chunk * kChunkDocs;
-      const int64_t p1 = min(P.D.n_sets, p0 + kChunkDocs);
+      const int64_t p0 = chunk * P.chunk_docs;
+      const int64_t p1 = min(P.D.n_sets, p0 + P.chunk_docs);
       const int nd = (int)(p1 - p0);
 
       // the chunk's document tiles, in order: lane dd < nd holds document
@@ -704,30 +706,35 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
   }
 }
 
-// Workgroups per XCD of the persistent dense scorer: one per compute unit
-// (the LDS stages allow one resident workgroup per CU).
-static int dense_slots_per_xcd() {
-  static int cached[64];
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 32;
-  if (cached[dev] == 0) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 8) cus = 256;
-    cached[dev] = cus / 8;
-  }
-  return cached[dev];
+DenseSchedule default_dense_schedule(int dtype, int64_t q_rows, int64_t n_docs, int cus_per_xcd) {
+  (void)dtype; (void)q_rows; (void)n_docs;
+  DenseSchedule d;
+  d.chunk_docs = kMaxChunkDocs;
+  d.items_per_slot = 8;
+  d.slots_per_xcd = cus_per_xcd;        // one resident workgroup per CU (LDS-bound)
+  return d;
+}
+
+bool dense_schedule_valid(const DenseSchedule& d, int cus_per_xcd) {
+  return (d.chunk_docs == 32 || d.chunk_docs == 64) && d.items_per_slot >= 1 && d.items_per_slot <= 64 &&
+         d.slots_per_xcd >= 1 && d.slots_per_xcd <= cus_per_xcd;
 }
 
 hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, const int32_t* qb_start,
-                              const int64_t* qcol, int64_t n_blocks_max, const DenseOut& out, hipStream_t s) {
+                              const int64_t* qcol, int64_t n_blocks_max, const DenseOut& out,
+                              const DenseSchedule& sched, hipStream_t s) {
   DenseParams P;
   P.Q = Q; P.D = D; P.qb = qb_start; P.qcol = qcol; P.n_blocks_max = n_blocks_max;
   P.n_bgroups = (n_blocks_max + kDenseWaves - 1) / kDenseWaves;
   P.out = out;
   P.chunk0 = 0;
-  P.n_chunks = (D.n_sets + kChunkDocs - 1) / kChunkDocs;
+  P.chunk_docs = sched.chunk_docs;
+  P.items_per_slot = sched.items_per_slot;
+  P.n_chunks = (D.n_sets + sched.chunk_docs - 1) / sched.chunk_docs;
   if (P.n_bgroups == 0 || P.n_chunks == 0) return hipSuccess;
-  const dim3 grid((unsigned)(8 * dense_slots_per_xcd())), blk(kDenseThreads);
+  if (sched.chunk_docs < 1 || sched.chunk_docs > kMaxChunkDocs || sched.items_per_slot < 1 || sched.slots_per_xcd < 1)
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(8 * sched.slots_per_xcd)), blk(kDenseThreads);
   switch (dtype) {
     case GEM_F32: hipLaunchKernelGGL(score_dense_kernel<GEM_F32>, grid, blk, 0, s, P); break;
     case GEM_BF16: hipLaunchKernelGGL(score_dense_kernel<GEM_BF16>, grid, blk, 0, s, P); break;

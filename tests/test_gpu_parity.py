@@ -282,6 +282,40 @@ def test_dense_full_size_row_and_top100(exhaustive_100k):
     assert ok, (bad, missing)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_dense_schedules_bitwise_and_autotune(dtype):
+    """Every dense schedule computes bitwise the same scores; the autotuner
+    installs one of them for the call's shape class, and the default returns
+    when the class is cleared."""
+    rng = np.random.default_rng(14)
+    q = _ragged(list(rng.integers(1, 65, 90)), 60)
+    c = _ragged(list(rng.integers(0, 120, 700)), 61)
+    D, Q = _device_sets(c, dtype), gem.Sets.from_batch(q, DEV)
+    gem.set_dense_schedule(dtype, Q.n_vecs, D.n_sets, None)
+    default = gem.dense_schedule(dtype, Q.n_vecs, D.n_sets)
+    base = _np(_score(Q, D, dtype))
+    ref = oracle.ch_dense(_operands(q.vecs.numpy(), dtype), q.offsets.numpy(),
+                          _operands(c.vecs.numpy(), dtype), c.offsets.numpy())
+    assert_close(base, ref, what=f"schedules {dtype}")
+    spx = default["slots_per_xcd"]
+    for cd in (32, 64):
+        for ips in (1, 3, 8, 64):
+            for slots in (spx, max(1, spx // 4)):
+                gem.set_dense_schedule(dtype, Q.n_vecs, D.n_sets,
+                                       {"chunk_docs": cd, "items_per_slot": ips, "slots_per_xcd": slots})
+                got = _np(_score(Q, D, dtype))
+                np.testing.assert_array_equal(got, base, err_msg=f"{dtype} {cd} {ips} {slots}")
+    with pytest.raises(gem.GemError):
+        gem.set_dense_schedule(dtype, Q.n_vecs, D.n_sets, {"chunk_docs": 48, "items_per_slot": 8,
+                                                           "slots_per_xcd": spx})
+    best, ms = gem.autotune_dense(Q, D, reps=1)
+    assert ms > 0 and best["chunk_docs"] in (32, 64) and best["items_per_slot"] in (4, 8, 16)
+    assert gem.dense_schedule(dtype, Q.n_vecs, D.n_sets) == best
+    np.testing.assert_array_equal(_np(_score(Q, D, dtype)), base)
+    gem.set_dense_schedule(dtype, Q.n_vecs, D.n_sets, None)
+    assert gem.dense_schedule(dtype, Q.n_vecs, D.n_sets) == default
+
+
 # ----------------------------------------------------------------------- gathered
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 def test_gather_matches_oracle_and_dense(dtype):
