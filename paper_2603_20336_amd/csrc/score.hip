@@ -747,11 +747,15 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
 // --------------------------------------------------------------------------
 // Gathered scorer: one wave scores up to kGatherEntries consecutive entries of
 // one query's candidate list. The query's vectors stay in registers (64 per
-// pass); each candidate document is streamed tile by tile, the next tile's
-// load in flight while the current one is multiplied. A score is the same sum
-// of per-tile column sums, in tile order, as in the dense scorer.
+// pass). The entries' documents form one sequence of tiles, which the wave
+// streams from memory several tiles ahead of the one being multiplied
+// (enough loads in flight to cover the memory latency). A score is the same
+// sum of per-tile column sums, in tile order, as in the dense scorer.
 constexpr int kGatherEntries = 16;
 constexpr int kGatherNT = 4;
+// tiles in flight per wave (registers: a float32 tile fragment takes 32 VGPRs,
+// bf16 16, FP8 9)
+template <int DT> struct GatherDepth { static constexpr int value = DT == GEM_F32 ? 2 : (DT == GEM_BF16 ? 4 : 6); };
 
 struct GatherParams {
   SetsView Q, D;
@@ -767,11 +771,10 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
   using Frag = typename O::Frag;
   constexpr int NT = kGatherNT;
   constexpr int PASS = 16 * NT;
-  __shared__ float lds_sc[4][kGatherEntries];
-  __shared__ int64_t lds_ent[4][kGatherEntries][2];
+  constexpr int PF = GatherDepth<DT>::value;
 
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c16 = l & 15;
-  const int64_t gw = P.wave0 + (int64_t)blockIdx.x * 4 + w;
+  const int l = threadIdx.x & 63, g = l >> 4, c16 = l & 15;
+  const int64_t gw = P.wave0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t q = gw / P.chunks_per_query;
   if (q >= P.C.n_lists) return;
   const int64_t ch = gw % P.chunks_per_query;
@@ -784,107 +787,118 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
   const int ne = (int)(e1 - e0);
   const float ninf = neg_inf();
 
-  // lane e < ne: the entry's document id and row range, kept in LDS so that
-  // the per-entry bookkeeping never waits on the vector-memory counter
+  // lane e < ne: the entry's document (first row, length), its first tile in
+  // the wave's tile sequence and its last tile (-1 for a padding id or an
+  // empty document)
   int32_t my_id = -1;
-  int64_t my_beg = 0, my_len = 0;
+  int64_t d_beg = 0;
+  int d_len = 0;
   if (l < ne) {
     my_id = P.C.ids[e0 + l];
-    if (my_id >= 0) { my_beg = P.D.off[my_id]; my_len = P.D.off[my_id + 1] - my_beg; }
-    lds_ent[w][l][0] = my_beg;
-    lds_ent[w][l][1] = my_len;
+    if (my_id >= 0) { d_beg = P.D.off[my_id]; d_len = (int)(P.D.off[my_id + 1] - d_beg); }
   }
-  __builtin_amdgcn_wave_barrier();
-  auto ent_beg = [&](int e) -> int64_t { return lds_ent[w][e][0]; };
-  auto ent_len = [&](int e) -> int64_t { return lds_ent[w][e][1]; };
+  const int d_nt = (d_len + 15) >> 4;
+  int d_incl = d_nt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(d_incl, o);
+    if (l >= o) d_incl += v;
+  }
+  const int d_t0 = d_incl - d_nt;
+  const int d_tl = d_nt > 0 ? d_incl - 1 : -1;
+  const int n_tiles = __builtin_amdgcn_readlane(d_incl, 63);
 
   const int64_t r0 = P.Q.off[q];
   const int m = (int)(P.Q.off[q + 1] - r0);
-  float* sc = lds_sc[w];
+  // lane e: the entry's score (padding ids and empty documents: -inf; an
+  // empty query: 0)
+  float res = (my_id < 0 || (d_len == 0 && m > 0)) ? ninf : 0.0f;
 
-  if (m == 0) {
-    if (l < ne) P.scores[e0 + l] = my_id < 0 ? ninf : 0.0f;
-    return;
-  }
-  // entries that score without any tile: padding ids and empty documents
-  if (l < ne) sc[l] = (my_id < 0 || my_len == 0) ? ninf : 0.0f;
-  __builtin_amdgcn_wave_barrier();
+  // row of tile T that lane row c16 loads: tile T belongs to the last entry
+  // with tiles whose first tile is <= T (T is clamped into the sequence)
+  auto tile_row = [&](int T) -> int64_t {
+    T = min(T, n_tiles - 1);
+    const uint64_t msk = __ballot(d_nt > 0 && d_t0 <= T);
+    const int e = 63 - __builtin_clzll(msk);
+    const int k = T - __builtin_amdgcn_readlane(d_t0, e);
+    const int len = __builtin_amdgcn_readlane(d_len, e);
+    const int64_t beg = (int64_t)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(d_beg >> 32), e) << 32) |
+                                  __builtin_amdgcn_readlane((uint32_t)d_beg, e));
+    return beg + min(16 * k + c16, len - 1);
+  };
 
-  for (int prow0 = 0; prow0 < m; prow0 += PASS) {
-    const int pr = min(PASS, m - prow0);
-    const int nct = __builtin_amdgcn_readfirstlane((pr + 15) >> 4);
-    const bool first_pass = prow0 == 0;
-    Frag B[NT];
-    float qs[NT / 4];
+  if (m > 0 && n_tiles > 0) {
+    for (int prow0 = 0; prow0 < m; prow0 += PASS) {
+      const int pr = min(PASS, m - prow0);
+      const int nct = __builtin_amdgcn_readfirstlane((pr + 15) >> 4);
+      const bool first_pass = prow0 == 0;
+      Frag B[NT];
+      float qs[NT / 4];
 #pragma unroll
-    for (int i = 0; i < NT / 4; ++i) qs[i] = 1.0f;
+      for (int i = 0; i < NT / 4; ++i) qs[i] = 1.0f;
 #pragma unroll
-    for (int ct = 0; ct < NT; ++ct) {
-      const int col = prow0 + 16 * ct + c16;
-      if (ct < nct && col < m) {
-        O::load_b(B[ct], P.Q.vecs, P.Q.scales, r0 + col, g);
-        if constexpr (O::kColumnScale)
-          if (g == (ct & 3)) qs[ct >> 2] = P.Q.scales[r0 + col];
-      } else {
-        O::zero(B[ct]);
+      for (int ct = 0; ct < NT; ++ct) {
+        const int col = prow0 + 16 * ct + c16;
+        if (ct < nct && col < m) {
+          O::load_b(B[ct], P.Q.vecs, P.Q.scales, r0 + col, g);
+          if constexpr (O::kColumnScale)
+            if (g == (ct & 3)) qs[ct >> 2] = P.Q.scales[r0 + col];
+        } else {
+          O::zero(B[ct]);
+        }
+      }
+      float rm[NT];
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) rm[ct] = ninf;
+      // the first PF tiles in flight; then every step multiplies one tile and
+      // starts the load PF tiles ahead (past the end: the last tile again,
+      // never used, so that every step issues the same loads)
+      Frag A[PF];
+#pragma unroll
+      for (int j = 0; j < PF; ++j) {
+        O::load(A[j], P.D.vecs, P.D.scales, tile_row(j), g);
+        __builtin_amdgcn_sched_barrier(0);                    // keep the loads in tile order
+      }
+      for (int T0 = 0; T0 < n_tiles; T0 += PF) {
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+          const int T = T0 + j;
+          f32x4 acc[NT];
+          if (T < n_tiles) {
+            // all NT column tiles: tiles past the query's last vector have zero
+            // B operands and their maxima are never summed
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < O::kSteps; ++s) {
+#pragma unroll
+              for (int ct = 0; ct < NT; ++ct) acc[ct] = O::mma(A[j], B[ct], acc[ct], s);
+            }
+          }
+          // A[j] is free once its products are issued: load the tile PF ahead
+          O::load(A[j], P.D.vecs, P.D.scales, tile_row(T + PF), g);
+          if (T < n_tiles) {
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) update_max(rm[ct], acc[ct]);
+            const uint64_t end = __ballot(d_tl == T);
+            if (end) {
+              const int e = __builtin_ctzll(end);
+              float R[NT / 4];
+              tile_sums<NT, O::kColumnScale>(rm, R, qs);
+              float s_run = first_pass ? tile_sum_at<NT>(R, 0) : readlane_f(res, e) + tile_sum_at<NT>(R, 0);
+#pragma unroll
+              for (int ct = 1; ct < NT; ++ct)
+                if (ct < nct) s_run += tile_sum_at<NT>(R, ct);
+              res = writelane_f(res, s_run, e);
+#pragma unroll
+              for (int ct = 0; ct < NT; ++ct) rm[ct] = ninf;
+            }
+          }
+        }
       }
     }
-    auto next_entry = [&](int e) -> int {          // next entry with a non-empty document
-      while (e < ne && ent_len(e) == 0) ++e;
-      return e;
-    };
-    int e = next_entry(0);
-    int t = 0;
-    int64_t dbeg = 0, dlen = 0;
-    Frag A_next;
-    if (e < ne) {
-      dbeg = ent_beg(e);
-      dlen = ent_len(e);
-      O::load(A_next, P.D.vecs, P.D.scales, dbeg + min((int64_t)c16, dlen - 1), g);
-    }
-    float rm[NT];
-#pragma unroll
-    for (int ct = 0; ct < NT; ++ct) rm[ct] = ninf;
-    while (e < ne) {
-      Frag A = A_next;
-      int ne_ = e, nt = t + 1;
-      int64_t nbeg = dbeg, nlen = dlen;
-      const bool last_tile = (int64_t)nt * 16 >= dlen;
-      if (last_tile) {
-        ne_ = next_entry(e + 1);
-        nt = 0;
-        if (ne_ < ne) { nbeg = ent_beg(ne_); nlen = ent_len(ne_); }
-      }
-      if (ne_ < ne) O::load(A_next, P.D.vecs, P.D.scales, nbeg + min((int64_t)(nt * 16 + c16), nlen - 1), g);
-      // all NT column tiles: tiles past the query's last vector have zero B
-      // operands and their maxima are never read
-      f32x4 acc[NT];
-#pragma unroll
-      for (int ct = 0; ct < NT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int s = 0; s < O::kSteps; ++s) {
-#pragma unroll
-        for (int ct = 0; ct < NT; ++ct) acc[ct] = O::mma(A, B[ct], acc[ct], s);
-      }
-#pragma unroll
-      for (int ct = 0; ct < NT; ++ct) update_max(rm[ct], acc[ct]);
-      if (last_tile) {
-        float R[NT / 4];
-        tile_sums<NT, O::kColumnScale>(rm, R, qs);
-        float s_run = first_pass ? tile_sum_at<NT>(R, 0) : sc[e] + tile_sum_at<NT>(R, 0);
-#pragma unroll
-        for (int ct = 1; ct < NT; ++ct)
-          if (ct < nct) s_run += tile_sum_at<NT>(R, ct);
-        if (l == 0) sc[e] = s_run;
-#pragma unroll
-        for (int ct = 0; ct < NT; ++ct) rm[ct] = ninf;
-      }
-      e = ne_; t = nt; dbeg = nbeg; dlen = nlen;
-    }
-    __builtin_amdgcn_wave_barrier();
   }
-  __builtin_amdgcn_wave_barrier();
-  if (l < ne) P.scores[e0 + l] = sc[l];
+  if (l < ne) P.scores[e0 + l] = res;
 }
 
 hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C,
