@@ -366,6 +366,8 @@ def main():
     ap.add_argument("--expand-docs", type=int, default=1_000_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB copy kernel (reference for the HBM byte counters)")
+    ap.add_argument("--only-expansion", action="store_true",
+                    help="run the beam-expansion leg alone (for profiling); prints its result line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -373,6 +375,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.only_expansion:
+        res = bench_expansion(args)
+        if args.copy_calibration:
+            copy_calibration()
+        print(json.dumps({"beam_expansion": res}), flush=True)
+        return
     line, keep = bench_exhaustive(args)
     if args.copy_calibration:
         copy_calibration()
