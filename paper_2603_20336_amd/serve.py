@@ -82,6 +82,7 @@ class ServingEngine:
         self.iteration = 0
         self.chunk = 0
         self.refused_for_memory = 0
+        self.active_sum = 0               # sum over iterations of the active requests (mean batch size)
         self._batch_key = None
 
     # -- clock
@@ -134,6 +135,7 @@ class ServingEngine:
             self.ex.set_batch([r.slot for r in self.active], [r.vecs for r in self.active])
             self._batch_key = key
         self.ex.score_chunk(self.chunk)
+        self.active_sum += len(self.active)
         for r in self.active:
             r.chunks_done += 1
         finished = [r for r in self.active if r.chunks_done == self.ex.n_chunks]
