@@ -414,12 +414,13 @@ template <int DT> struct DensePass {
   Frag B[NT];                   // query columns of this pass
   float qs[NT / 4];             // FP8: scale of this lane's column in the tile sums
   float rm[NT];                 // running max over the current document, per column tile
-  float tsum[NT];               // lane dd: column sum of tile ct's maxima for document dd
+  float* tsum;                  // this wave's [NT][64] LDS array: tile ct's column sum for document dd
   int nct, tq_lane;
   uint64_t first_mask, last_mask;
 
   // one document tile against the pass's column tiles (all of them when
-  // kFull); at a document's last tile, park its tile sums in lane dd
+  // kFull); at a document's last tile, park its tile sums in column dd of the
+  // wave's LDS array (the first lane of each 16-lane row stores that row's sum)
   template <bool kFull>
   __device__ __forceinline__ void tile(const Frag& A, uint64_t end_mask) {
     // column tiles in groups of 4 (a group past the last used tile is skipped;
@@ -443,11 +444,13 @@ template <int DT> struct DensePass {
       const int dd = __builtin_ctzll(end_mask);
       float Rs[NT / 4];
       tile_sums<NT, O::kColumnScale>(rm, Rs, qs);
+      const int l = lane_id();
+      if ((l & 15) == 0) {
 #pragma unroll
-      for (int ct = 0; ct < NT; ++ct) {
-        tsum[ct] = writelane_f(tsum[ct], tile_sum_at<NT>(Rs, ct), dd);
-        rm[ct] = neg_inf();
+        for (int i = 0; i < NT / 4; ++i) tsum[(4 * i + (l >> 4)) * 64 + dd] = Rs[i];
       }
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) rm[ct] = neg_inf();
     }
   }
 };
@@ -465,6 +468,7 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
   __shared__ u32x4 lds_buf1[TS::kGroupVecs];
   __shared__ u32x4 lds_buf2[TS::kGroupVecs];
   __shared__ int lds_npass[kDenseWaves];
+  __shared__ float lds_tsum[kDenseWaves][NT * 64];              // parked tile sums, per wave
 
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, g = l >> 4, c16 = l & 15;
@@ -493,6 +497,7 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
   const int64_t n_items = np * n_bg;
 
   DensePass<DT> S;
+  S.tsum = lds_tsum[w];
   int64_t cur_bg = -1;
   int q0 = 0, nq = 0, n_pass = 0, total_tiles = 0;
   int64_t qrow = 0;
@@ -630,7 +635,7 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
           b_loaded = true;
         }
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct) { S.rm[ct] = ninf; S.tsum[ct] = 0.0f; }
+        for (int ct = 0; ct < NT; ++ct) S.rm[ct] = ninf;
         __builtin_amdgcn_s_waitcnt(0);                         // operands in; the stream starts from zero
 
         // group G (in buffer X): wait for this wave's copies of G, publish G
@@ -646,9 +651,8 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
           issue(std::integral_constant<int, (X + 2) % 3>{}, G + 2);
           const int nt = min(kGroup, n_tiles - G * kGroup);       // <= 0 past the end
           const int T0 = G * kGroup;
-          // (the unbranched body keeps two column groups' accumulators live,
-          // which only fits when a pass holds at most 8 column tiles)
-          if (NT <= 8 && S.nct == NT) {
+          // (full passes take the unbranched body)
+          if (S.nct == NT) {
 #pragma nounroll
             for (int u = 0; u < nt; ++u) {
               Frag A;
@@ -685,7 +689,8 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct) {
           if (ct < S.nct) {
-            s_run = ((S.first_mask >> ct) & 1) ? S.tsum[ct] : s_run + S.tsum[ct];
+            const float tv = S.tsum[ct * 64 + l];
+            s_run = ((S.first_mask >> ct) & 1) ? tv : s_run + tv;
             if ((S.last_mask >> ct) & 1) {
               const int j = __builtin_amdgcn_readlane(S.tq_lane, ct);
               const int64_t row = P.out.rows ? (int64_t)P.out.rows[q0 + j] : (int64_t)(q0 + j);
