@@ -27,17 +27,19 @@ __device__ __forceinline__ uint64_t rank_from_id_key(uint64_t ik) {
   return ((uint64_t)(~(uint32_t)ik) << 32) | (uint64_t)(~(uint32_t)(ik >> 32));
 }
 
-// Bitonic sort of a[0..n) (n a power of two), descending if `desc`.
+// Bitonic sort of a[0..n) (n a power of two), descending if `desc`. Every
+// stage has n / 2 compare-exchange pairs; thread t takes pairs t, t + T, ...
+// (pair p of stage j is elements i = 2 j (p / j) + p % j and i + j).
 __device__ void block_bitonic_sort(uint64_t* a, int n, bool desc) {
+  const int half = n >> 1;
   for (int k = 2; k <= n; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const uint64_t x = a[i], y = a[ixj];
-          const bool up = ((i & k) == 0) != desc;       // this pair ascending?
-          if ((x > y) == up) { a[i] = y; a[ixj] = x; }
-        }
+      for (int p = threadIdx.x; p < half; p += blockDim.x) {
+        const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+        const int ixj = i + j;
+        const uint64_t x = a[i], y = a[ixj];
+        const bool up = ((i & k) == 0) != desc;         // this pair ascending?
+        if ((x > y) == up) { a[i] = y; a[ixj] = x; }
       }
       __syncthreads();
     }
