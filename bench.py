@@ -271,7 +271,7 @@ def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_
     eng = serve.ServingEngine(ex, max_slots=1024, mem_budget_bytes=8 << 30)
     # warm-up on a few requests, then the measured run
     warm = serve.ServingEngine(ex, max_slots=1024, mem_budget_bytes=8 << 30)
-    warm.run([serve.Request(-1 - i, r.vecs, 0.0) for i, r in enumerate(reqs[:8])])
+    warm.run([serve.Request(-1 - i, r.vecs, r.t_arrival) for i, r in enumerate(reqs[:200])])
     torch.cuda.synchronize()
     done = eng.run(reqs)
     st = serve.latency_stats(done)
@@ -364,7 +364,7 @@ def main():
     ap.add_argument("--skip-expansion", action="store_true")
     ap.add_argument("--serve-rates", type=str, default="1000,2000,4000,8000,16000",
                     help="comma-separated arrival rates (1/s)")
-    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=1500, help="minimum requests per rate")
     ap.add_argument("--expand-docs", type=int, default=1_000_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB copy kernel (reference for the HBM byte counters)")
@@ -391,7 +391,9 @@ def main():
         line["serving"] = []
         for ri, rate in enumerate([float(r) for r in args.serve_rates.split(",") if r]):
             log(f"serving at {rate:.0f} requests/s")
-            line["serving"].append(bench_serving(D8, D32, rate=rate, n_req=args.serve_requests, rate_idx=ri))
+            # about 1.5 s of arrivals per rate (at least --serve-requests)
+            n_req = max(args.serve_requests, int(rate * 1.5))
+            line["serving"].append(bench_serving(D8, D32, rate=rate, n_req=n_req, rate_idx=ri))
         if line["serving"]:
             # headline latency: the 2000/s point if swept, else the first rate
             ref = next((r for r in line["serving"] if r["rate_per_s"] == 2000.0), line["serving"][0])

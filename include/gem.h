@@ -157,6 +157,16 @@ gem_status gem_convert_bf16(gem_ctx ctx, const float* x, int64_t n_rows, int32_t
 gem_status gem_quantize_fp8(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim,
                             uint8_t* out, float* scales, hipStream_t stream);
 
+/* Row copies for assembling batches (a serving loop gathers the active
+ * requests' query rows from per-request slots, and writes admitted requests'
+ * rows into their slots): for i < n, row (dst_idx ? dst_idx[i] : i) of dst
+ * receives row (src_idx ? src_idx[i] : i) of src. Rows are row_bytes bytes (a
+ * multiple of 4); src, dst [device], 4-byte aligned; src_idx, dst_idx [device]
+ * int64 or NULL. Indices are trusted (device data); destination rows must be
+ * distinct. Not part of the paper's method: plumbing around it. */
+gem_status gem_copy_rows(gem_ctx ctx, const void* src, const int64_t* src_idx, void* dst, const int64_t* dst_idx,
+                         int64_t n, int64_t row_bytes, hipStream_t stream);
+
 /* Exact Chamfer scores CH(Q_i, D_j) (Def. 1).
  *   compute = GEM_F32 or GEM_BF16: the operand type of the products; D->dtype must
  *   equal it. Q->dtype may equal it, or be GEM_F32 when compute is GEM_BF16 (Q is

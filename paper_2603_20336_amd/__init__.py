@@ -22,7 +22,7 @@ from ._abi import (GEM_BF16, GEM_F32, GEM_FP8_E4M3, GEM_MAX_K, GEM_MAX_QUERY_LEN
 __all__ = ["Sets", "Cands", "Beam", "GemError", "convert_bf16", "quantize_fp8", "score_exact",
            "score_quant", "topk", "expand_batch", "beam_merge", "beam_reset", "validate_sets", "validate_cands",
            "library", "GEM_F32", "GEM_BF16", "GEM_FP8_E4M3", "GEM_MAX_K", "GEM_MAX_QUERY_LEN", "dense_schedule",
-           "set_dense_schedule", "autotune_dense"]
+           "set_dense_schedule", "autotune_dense", "copy_rows"]
 
 _DTYPES = {"f32": GEM_F32, "bf16": GEM_BF16, "fp8": GEM_FP8_E4M3,
            GEM_F32: GEM_F32, GEM_BF16: GEM_BF16, GEM_FP8_E4M3: GEM_FP8_E4M3}
@@ -231,6 +231,23 @@ def score_exact(Q: Sets, D: Sets, cands: Optional[Cands] = None, k: int = 0, com
     one score per candidate entry. k > 0 returns (top_scores, top_ids) (and
     the scores when want_scores)."""
     return _score(True, Q, D, cands, k, _DTYPES[compute], scores, ld, rows, want_scores, stream, ws)
+
+
+def copy_rows(src: torch.Tensor, dst: torch.Tensor, src_idx: Optional[torch.Tensor] = None,
+              dst_idx: Optional[torch.Tensor] = None, n: Optional[int] = None, stream=None) -> None:
+    """dst[dst_idx[i]] = src[src_idx[i]] for i < n (rows of the leading dimension;
+    an index of None is the identity). Rows of src and dst must have the same size."""
+    rb = src[0].numel() * src.element_size() if src.dim() > 1 else src.element_size()
+    rbd = dst[0].numel() * dst.element_size() if dst.dim() > 1 else dst.element_size()
+    if rb != rbd or not src.is_contiguous() or not dst.is_contiguous():
+        raise ValueError("copy_rows needs contiguous tensors with equal row sizes")
+    for t in (src_idx, dst_idx):
+        if t is not None and (t.dtype != torch.int64 or not t.is_contiguous()):
+            raise TypeError("row indices must be contiguous int64")
+    if n is None:
+        n = (src_idx if src_idx is not None else dst_idx if dst_idx is not None else src).shape[0]
+    _abi.check(library().gem_copy_rows(_ctx(dst.device), _ptr(src), _ptr(src_idx), _ptr(dst), _ptr(dst_idx), int(n),
+                                       int(rb), _stream(stream)))
 
 
 def _sched_dict(s) -> dict:

@@ -67,6 +67,7 @@ SIGNATURES = {
     "gem_beam_reset": (i32, [c_p, P_BEAM, i64, c_p]),
     "gem_validate_sets": (i32, [c_p, P_SETS, c_p]),
     "gem_validate_cands": (i32, [c_p, P_CANDS, i64, c_p]),
+    "gem_copy_rows": (i32, [c_p, c_p, c_p, c_p, c_p, i64, i64, c_p]),
     "gem_get_dense_schedule": (i32, [c_p, i32, i64, i64, ctypes.POINTER(gem_dense_schedule)]),
     "gem_set_dense_schedule": (i32, [c_p, i32, i64, i64, ctypes.POINTER(gem_dense_schedule)]),
     "gem_autotune_dense": (i32, [c_p, P_SETS, P_SETS, i32, c_p, i64, c_p, sz, c_p, i32,

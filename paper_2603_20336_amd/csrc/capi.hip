@@ -383,6 +383,17 @@ gem_status gem_quantize_fp8(gem_ctx ctx, const float* x, int64_t n_rows, int32_t
   return e == hipSuccess ? GEM_OK : hip_fail(e, "fp8 quantization");
 }
 
+gem_status gem_copy_rows(gem_ctx ctx, const void* src, const int64_t* src_idx, void* dst, const int64_t* dst_idx,
+                         int64_t n, int64_t row_bytes, hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (n < 0 || row_bytes < 0) return fail(GEM_ERR_INVALID, "negative size");
+  if (row_bytes % 4 != 0) return fail(GEM_ERR_INVALID, "row_bytes %lld is not a multiple of 4", (long long)row_bytes);
+  if (n > 0 && row_bytes > 0 && (!src || !dst)) return fail(GEM_ERR_INVALID, "NULL buffer");
+  if (((uintptr_t)src % 4) != 0 || ((uintptr_t)dst % 4) != 0) return fail(GEM_ERR_INVALID, "buffers must be 4-byte aligned");
+  hipError_t e = launch_copy_rows(src, src_idx, dst, dst_idx, n, row_bytes, stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "row copy");
+}
+
 gem_status gem_score_exact(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t compute,
                            int32_t k, float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,
                            int32_t* top_ids, void* ws, size_t ws_bytes, hipStream_t stream) {

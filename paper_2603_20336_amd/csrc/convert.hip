@@ -57,4 +57,33 @@ hipError_t launch_quantize_fp8(const float* x, int64_t n_rows, uint8_t* out, flo
   return hipGetLastError();
 }
 
+// Row copies: dst row (dst_idx ? dst_idx[i] : i) = src row (src_idx ? src_idx[i] : i)
+// for i < n, rows of `units` W-byte units (W = 16 or 4). One 64-lane wave per
+// row (a row of more than 64 units takes several steps).
+template <typename W>
+__global__ __launch_bounds__(256) void copy_rows_kernel(const W* __restrict__ src, const int64_t* __restrict__ src_idx,
+                                                        W* __restrict__ dst, const int64_t* __restrict__ dst_idx,
+                                                        int64_t n, int64_t units) {
+  const int l = threadIdx.x & 63;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+    const int64_t s = src_idx ? src_idx[i] : i;
+    const int64_t d = dst_idx ? dst_idx[i] : i;
+    for (int64_t u = l; u < units; u += 64) dst[d * units + u] = src[s * units + u];
+  }
+}
+
+hipError_t launch_copy_rows(const void* src, const int64_t* src_idx, void* dst, const int64_t* dst_idx, int64_t n,
+                            int64_t row_bytes, hipStream_t s) {
+  if (n == 0 || row_bytes == 0) return hipSuccess;
+  const unsigned grid = capped_blocks((n + 3) / 4, 256);
+  if (row_bytes % 16 == 0 && ((uintptr_t)src % 16) == 0 && ((uintptr_t)dst % 16) == 0) {
+    hipLaunchKernelGGL(copy_rows_kernel<uint4>, dim3(grid), dim3(256), 0, s, static_cast<const uint4*>(src), src_idx,
+                       static_cast<uint4*>(dst), dst_idx, n, row_bytes / 16);
+  } else {
+    hipLaunchKernelGGL(copy_rows_kernel<uint32_t>, dim3(grid), dim3(256), 0, s, static_cast<const uint32_t*>(src),
+                       src_idx, static_cast<uint32_t*>(dst), dst_idx, n, row_bytes / 4);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace gem

@@ -71,6 +71,8 @@ hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, 
 
 hipError_t launch_convert_bf16(const float* x, int64_t n_elems, uint16_t* out, hipStream_t s);
 hipError_t launch_quantize_fp8(const float* x, int64_t n_rows, uint8_t* out, float* scales, hipStream_t s);
+hipError_t launch_copy_rows(const void* src, const int64_t* src_idx, void* dst, const int64_t* dst_idx, int64_t n,
+                            int64_t row_bytes, hipStream_t s);
 
 // Segments for top-k.
 struct TopkSegs {

@@ -869,15 +869,21 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
         for (int j = 0; j < PF; ++j) {
           const int T = T0 + j;
           f32x4 acc[NT];
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
           if (T < n_tiles) {
-            // all NT column tiles: tiles past the query's last vector have zero
-            // B operands and their maxima are never summed
+            // column tiles in pairs, a pair only if the query reaches it (a
+            // tile past the query's last vector has zero B operands and its
+            // maxima are never summed)
 #pragma unroll
-            for (int ct = 0; ct < NT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int c0 = 0; c0 < NT; c0 += 2) {
+              if (c0 < nct) {
 #pragma unroll
-            for (int s = 0; s < O::kSteps; ++s) {
-#pragma unroll
-              for (int ct = 0; ct < NT; ++ct) acc[ct] = O::mma(A[j], B[ct], acc[ct], s);
+                for (int s = 0; s < O::kSteps; ++s) {
+                  acc[c0] = O::mma(A[j], B[c0], acc[c0], s);
+                  acc[c0 + 1] = O::mma(A[j], B[c0 + 1], acc[c0 + 1], s);
+                }
+              }
             }
           }
           // A[j] is free once its products are issued: load the tile PF ahead

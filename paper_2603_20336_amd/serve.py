@@ -14,9 +14,13 @@ and the top k are returned (the rerank of GEM's search, Alg. 5 final step).
 Because a (query, document) score does not depend on which other queries
 share a launch, a request's result is bitwise the same alone and in any mix.
 
-The engine only schedules. Device work goes through an executor with three
-calls (set_batch, score_chunk, finish); `DeviceExecutor` runs them with the
-library's kernels.
+The engine only schedules. Device work goes through an executor (admit,
+set_batch, score_chunk, finish_async / ready / results); `DeviceExecutor` runs
+them with the library's kernels. A request's query vectors are uploaded and
+quantized once, at admission, into a device slot; a batch is gathered from the
+slots on the device; finished requests' results come back through an
+asynchronous copy that the engine polls, so the host never waits for the
+device inside the loop.
 """
 from __future__ import annotations
 
@@ -54,6 +58,9 @@ class Executor:
     n_chunks: int
     bytes_per_request: int
 
+    def admit(self, slots: Sequence[int], queries: Sequence[np.ndarray]) -> None:
+        """New requests take these slots (upload their queries)."""
+
     def set_batch(self, slots: Sequence[int], queries: Sequence[np.ndarray]) -> None:
         raise NotImplementedError
 
@@ -63,6 +70,16 @@ class Executor:
     def finish(self, slots: Sequence[int], queries: Sequence[np.ndarray]):
         """-> (top_scores [n, k], top_ids [n, k]) numpy arrays, results on the host."""
         raise NotImplementedError
+
+    # asynchronous completion (default: the synchronous finish, ready at once)
+    def finish_async(self, slots: Sequence[int], queries: Sequence[np.ndarray]):
+        return self.finish(slots, queries)
+
+    def ready(self, handle) -> bool:
+        return True
+
+    def results(self, handle):
+        return handle
 
 
 class ServingEngine:
@@ -83,6 +100,7 @@ class ServingEngine:
         self.chunk = 0
         self.refused_for_memory = 0
         self.active_sum = 0               # sum over iterations of the active requests (mean batch size)
+        self.pending: List[tuple] = []    # (handle, finished requests) awaiting their results
         self._batch_key = None
 
     # -- clock
@@ -109,7 +127,7 @@ class ServingEngine:
         self.waiting.append(req)
 
     def admit(self) -> int:
-        n = 0
+        new = []
         now = self.now()
         while self.waiting and self.waiting[0].t_arrival <= now:
             if not self.can_admit():
@@ -122,14 +140,34 @@ class ServingEngine:
             r.chunks_done = 0
             r.t_admit = now
             self.active.append(r)
-            n += 1
-        return n
+            new.append(r)
+        if new:
+            self.ex.admit([r.slot for r in new], [r.vecs for r in new])
+        return len(new)
+
+    def poll(self) -> List[Request]:
+        """Complete the finished requests whose results have reached the host."""
+        out, keep = [], []
+        for handle, reqs in self.pending:
+            if self.ex.ready(handle):
+                ts, ti = self.ex.results(handle)
+                t = self.now()
+                for i, r in enumerate(reqs):
+                    r.top_scores, r.top_ids, r.t_done = ts[i], ti[i], t
+                self.done.extend(reqs)
+                out.extend(reqs)
+            else:
+                keep.append((handle, reqs))
+        self.pending = keep
+        return out
 
     # -- one iteration: one corpus chunk for every active request
     def step(self) -> List[Request]:
+        """One iteration; returns the requests completed (results on the host) during it."""
+        completed = self.poll()
         self.admit()
         if not self.active:
-            return []
+            return completed
         key = tuple(r.slot for r in self.active)
         if key != self._batch_key:
             self.ex.set_batch([r.slot for r in self.active], [r.vecs for r in self.active])
@@ -140,16 +178,16 @@ class ServingEngine:
             r.chunks_done += 1
         finished = [r for r in self.active if r.chunks_done == self.ex.n_chunks]
         if finished:
-            ts, ti = self.ex.finish([r.slot for r in finished], [r.vecs for r in finished])
-            t = self.now()
-            for i, r in enumerate(finished):
-                r.top_scores, r.top_ids, r.t_done = ts[i], ti[i], t
+            # the slots are free at once: later work on them is ordered after
+            # this request's on the device stream
+            handle = self.ex.finish_async([r.slot for r in finished], [r.vecs for r in finished])
+            self.pending.append((handle, finished))
+            for r in finished:
                 self.free_slots.append(r.slot)
             self.active = [r for r in self.active if r.chunks_done < self.ex.n_chunks]
-            self.done.extend(finished)
         self.chunk = (self.chunk + 1) % self.ex.n_chunks
         self.iteration += 1
-        return finished
+        return completed + self.poll()
 
     def run(self, requests: Sequence[Request], idle_sleep: float = 0.0) -> List[Request]:
         """Serve requests (sorted by arrival) until all are done."""
@@ -157,8 +195,8 @@ class ServingEngine:
             self.submit(r)
         if self._clock is None:
             self.start_clock()
-        while self.waiting or self.active:
-            if not self.active and self.waiting:
+        while self.waiting or self.active or self.pending:
+            if not self.active and self.waiting and not self.pending:
                 wait = self.waiting[0].t_arrival - self.now()
                 if wait > 0:
                     if self._clock is not None:
@@ -181,10 +219,14 @@ def latency_stats(reqs: Sequence[Request]) -> dict:
 
 
 class DeviceExecutor(Executor):
-    """Executor on the library's kernels: FP8 estimate per chunk, float32 rerank at the end."""
+    """Executor on the library's kernels: FP8 estimate per chunk, float32 rerank at the end.
+
+    Each slot holds one request's query vectors on the device (float32 for the
+    rerank, FP8 codes and scales for the estimate), written once at admission.
+    """
 
     def __init__(self, D8, D32, n_chunks: int, max_slots: int, shortlist: int = 1000, k: int = 100,
-                 max_query_len: int = 64, stream=None):
+                 max_query_len: int = 64, stream=None, copy_stream: bool = False):
         import importlib
         self._gem = importlib.import_module(__package__)
         self.D8, self.D32 = D8, D32
@@ -193,42 +235,184 @@ class DeviceExecutor(Executor):
         bounds = np.linspace(0, self.n_docs, self.n_chunks + 1).round().astype(np.int64)
         self.bounds = [int(b) for b in bounds]
         self.shortlist, self.k = int(shortlist), int(k)
-        self.max_query_len = int(max_query_len)
+        self.L = int(max_query_len)
+        self.max_slots = int(max_slots)
         self.device = D8.device
         self.stream = stream
         self.est = torch.empty(max_slots, self.n_docs, dtype=torch.float32, device=self.device)
         self.bytes_per_request = self.n_docs * 4 + max_query_len * 128 * 9 + shortlist * 8
+        # slot storage: slot s owns rows [s L, s L + len)
+        n_rows = self.max_slots * self.L
+        self.q32 = torch.zeros(n_rows, 128, dtype=torch.float32, device=self.device)
+        self.q8 = torch.zeros(n_rows, 128, dtype=torch.uint8, device=self.device)
+        self.q8s = torch.ones(n_rows, dtype=torch.float32, device=self.device)
+        self.lens = np.zeros(self.max_slots, np.int64)
+        # packed batches, gathered from the slots into fixed buffers (no
+        # allocation per membership change): the estimate batch and the
+        # finishing requests' float32 queries
+        self.pk8 = torch.empty(n_rows, 128, dtype=torch.uint8, device=self.device)
+        self.pk8s = torch.empty(n_rows, dtype=torch.float32, device=self.device)
+        self.pk32 = torch.empty(n_rows, 128, dtype=torch.float32, device=self.device)
+        # pinned staging for uploads, which run on a copy stream of their own
+        # (so that they never queue behind the scoring work); the staging is
+        # reused once the previous upload is done
+        # a ring of staging buffers: one is reused only after the upload issued
+        # from it several uploads ago has completed, which is almost never a wait
+        # (admission vectors and index lists have rings of their own; an
+        # iteration takes up to one vector and three index buffers)
+        self._rings = {
+            "v": [torch.empty(n_rows, 128, dtype=torch.float32).pin_memory() for _ in range(4)],
+            "i": [torch.empty(2 * n_rows + 2 * self.max_slots + 2, dtype=torch.int64).pin_memory()
+                  for _ in range(12)]}
+        self._ring_evt = {k: [None] * len(v) for k, v in self._rings.items()}
+        self._ring_at = {"v": 0, "i": 0}
+        self._copy = torch.cuda.Stream(device=self.device) if copy_stream else None
+        # ring of pinned result buffers for finished requests
+        self._ring = [(torch.empty(self.max_slots, self.k, dtype=torch.float32).pin_memory(),
+                       torch.empty(self.max_slots, self.k, dtype=torch.int32).pin_memory(), [None])
+                      for _ in range(16)]
+        self._ring_pos = 0
+        self._off2 = torch.zeros(2, dtype=torch.int64, device=self.device)
+        self._iter_evts = []
         self.Q8 = None
         self.rows = None
 
-    def _pack(self, queries: Sequence[np.ndarray]):
-        lens = [int(q.shape[0]) for q in queries]
-        off = np.zeros(len(lens) + 1, np.int64)
+    def _stream(self):
+        return self.stream if self.stream is not None else torch.cuda.current_stream(self.device)
+
+    def _stage(self, kind: str):
+        """The next staging buffer of a ring, once its last upload is done; -> (buffer, ring index)."""
+        j = self._ring_at[kind]
+        self._ring_at[kind] = (j + 1) % len(self._rings[kind])
+        evt = self._ring_evt[kind][j]
+        if evt is not None:
+            evt.synchronize()
+        return self._rings[kind][j], j
+
+    def _upload(self, host: torch.Tensor, kind: str, j: int) -> torch.Tensor:
+        """Copy pinned `host` (ring `kind`, buffer j) to the device: on the
+        compute stream, or on the copy stream with the compute stream waiting
+        for it on the device."""
+        cs = self._stream()
+        st = cs if self._copy is None else self._copy
+        with torch.cuda.stream(st):
+            dev = host.to(self.device, non_blocking=True)
+            evt = torch.cuda.Event()
+            evt.record(st)
+        self._ring_evt[kind][j] = evt
+        if self._copy is not None:
+            cs.wait_event(evt)
+            dev.record_stream(cs)
+        return dev
+
+    def _rows_of(self, slots) -> np.ndarray:
+        slots = np.asarray(slots, np.int64)
+        lens = self.lens[slots]
+        starts = slots * self.L
+        tot = int(lens.sum())
+        idx = np.repeat(starts - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens) + np.arange(tot)
+        return idx, lens
+
+    def admit(self, slots, queries):
+        g = self._gem
+        lens = np.array([q.shape[0] for q in queries], np.int64)
+        if (lens > self.L).any():
+            raise ValueError(f"query longer than {self.L} vectors")
+        for s, m in zip(slots, lens):
+            self.lens[s] = m
+        tot = int(lens.sum())
+        if tot == 0:
+            return
+        hv, jv = self._stage("v")
+        hi, ji = self._stage("i")
+        sv = hv[:tot].numpy()
+        np.concatenate(queries, 0, out=sv) if len(queries) > 1 else np.copyto(sv, queries[0])
+        idx, _ = self._rows_of(slots)
+        hi.numpy()[:tot] = idx
+        v = self._upload(hv[:tot], "v", jv)
+        ri = self._upload(hi[:tot], "i", ji)
+        cs = self._stream()
+        with torch.cuda.stream(cs):
+            g.copy_rows(v, self.q32, dst_idx=ri, n=tot, stream=cs)
+            # (the quantizer reads rows only; the offsets just complete the view)
+            q8 = g.quantize_fp8(g.Sets(v, self._off2, "f32", int(lens.max())), stream=cs)
+            g.copy_rows(q8.vecs, self.q8, dst_idx=ri, n=tot, stream=cs)
+            g.copy_rows(q8.scales, self.q8s, dst_idx=ri, n=tot, stream=cs)
+
+    def _gather(self, slots, fp8: bool):
+        """Packed sets of the slots' queries, gathered on the device."""
+        g = self._gem
+        idx, lens = self._rows_of(slots)
+        n = len(slots)
+        off = np.zeros(n + 1, np.int64)
         off[1:] = np.cumsum(lens)
-        vecs = np.concatenate(queries, 0).astype(np.float32) if queries else np.zeros((0, 128), np.float32)
-        v = torch.from_numpy(vecs).pin_memory().to(self.device, non_blocking=True)
-        o = torch.from_numpy(off).pin_memory().to(self.device, non_blocking=True)
-        return self._gem.Sets(v, o, "f32", max(lens) if lens else 0)
+        hi, ji = self._stage("i")
+        st = hi.numpy()
+        st[:idx.size] = idx
+        st[idx.size:idx.size + n + 1] = off
+        st[idx.size + n + 1:idx.size + 2 * n + 1] = slots
+        dev = self._upload(hi[:idx.size + 2 * n + 1], "i", ji)
+        with torch.cuda.stream(self._stream()):
+            ri, o, rows = dev[:idx.size], dev[idx.size:idx.size + n + 1], dev[idx.size + n + 1:]
+            mx = int(lens.max()) if n else 0
+            r = idx.size
+            cs = self._stream()
+            if fp8:
+                g.copy_rows(self.q8, self.pk8, src_idx=ri, n=r, stream=cs)
+                g.copy_rows(self.q8s, self.pk8s, src_idx=ri, n=r, stream=cs)
+                S = g.Sets(self.pk8[:r], o, "fp8", mx, scales=self.pk8s[:r])
+            else:
+                g.copy_rows(self.q32, self.pk32, src_idx=ri, n=r, stream=cs)
+                S = g.Sets(self.pk32[:r], o, "f32", mx)
+            rows32 = rows.to(torch.int32)
+        return S, rows32
 
     def set_batch(self, slots, queries):
-        Q = self._pack(queries)
-        self.Q8 = self._gem.quantize_fp8(Q, stream=self.stream)
-        self.rows = torch.tensor(list(slots), dtype=torch.int32).pin_memory().to(self.device, non_blocking=True)
+        self.Q8, self.rows = self._gather(slots, fp8=True)
 
     def score_chunk(self, chunk: int) -> None:
+        # the host runs at most two iterations ahead of the device: deeper
+        # queues add their whole backlog to a new request's latency
+        if len(self._iter_evts) >= 2:
+            self._iter_evts.pop(0).synchronize()
         a, b = self.bounds[chunk], self.bounds[chunk + 1]
-        if b <= a:
-            return
-        Dc = self.D8.view(a, b)
-        out = self.est[:, a:]
-        self._gem.score_quant(self.Q8, Dc, scores=out, ld=self.n_docs, rows=self.rows, stream=self.stream)
+        if b > a:
+            Dc = self.D8.view(a, b)
+            out = self.est[:, a:]
+            self._gem.score_quant(self.Q8, Dc, scores=out, ld=self.n_docs, rows=self.rows, stream=self.stream)
+        evt = torch.cuda.Event()
+        evt.record(self._stream())
+        self._iter_evts.append(evt)
+
+    def finish_async(self, slots, queries):
+        g = self._gem
+        Q, rows = self._gather(slots, fp8=False)
+        sl = min(self.shortlist, self.n_docs)
+        with torch.cuda.stream(self._stream()):
+            _, short_i = g.topk(self.est, sl, seg_rows=rows, stream=self.stream)
+            C = g.Cands(short_i.reshape(-1), stride=sl, n_lists=len(slots))
+            ts, ti = g.score_exact(Q, self.D32, cands=C, compute="f32", k=self.k, stream=self.stream)
+            hs_full, hi_full, slot_evt = self._ring[self._ring_pos]
+            self._ring_pos = (self._ring_pos + 1) % len(self._ring)
+            if slot_evt[0] is not None:
+                slot_evt[0].synchronize()                       # the buffer's previous results were read
+            n = len(slots)
+            hs, hi = hs_full[:n], hi_full[:n]
+            hs.copy_(ts, non_blocking=True)
+            hi.copy_(ti, non_blocking=True)
+            evt = torch.cuda.Event()
+            evt.record(self._stream())
+            slot_evt[0] = evt
+        return (evt, hs, hi, ts, ti)
+
+    def ready(self, handle) -> bool:
+        return handle[0].query()
+
+    def results(self, handle):
+        evt, hs, hi = handle[0], handle[1], handle[2]
+        evt.synchronize()
+        return hs.numpy().copy(), hi.numpy().copy()
 
     def finish(self, slots, queries):
-        g = self._gem
-        rows = torch.tensor(list(slots), dtype=torch.int32).pin_memory().to(self.device, non_blocking=True)
-        sl = min(self.shortlist, self.n_docs)
-        _, short_i = g.topk(self.est, sl, seg_rows=rows, stream=self.stream)
-        Q = self._pack(queries)
-        C = g.Cands(short_i.reshape(-1), stride=sl, n_lists=len(slots))
-        ts, ti = g.score_exact(Q, self.D32, cands=C, compute="f32", k=self.k, stream=self.stream)
-        return ts.cpu().numpy(), ti.cpu().numpy()
+        h = self.finish_async(slots, queries)
+        return self.results(h)

@@ -136,6 +136,28 @@ def test_quantize_fp8_beyond_one_dispatch():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("row_bytes", [512, 128, 20])
+def test_copy_rows_gather_scatter_bitwise(row_bytes):
+    rng = np.random.default_rng(row_bytes)
+    n_src, n_dst, n = 300, 260, 200
+    src = torch.from_numpy(rng.integers(0, 2**32, (n_src, row_bytes // 4), dtype=np.uint32).view(np.int32)).to(DEV)
+    dst0 = rng.integers(0, 2**32, (n_dst, row_bytes // 4), dtype=np.uint32).view(np.int32)
+    si = rng.integers(0, n_src, n).astype(np.int64)
+    di = rng.permutation(n_dst)[:n].astype(np.int64)
+    dst = torch.from_numpy(dst0.copy()).to(DEV)
+    gem.copy_rows(src, dst, src_idx=torch.from_numpy(si).to(DEV), dst_idx=torch.from_numpy(di).to(DEV))
+    want = dst0.copy()
+    want[di] = src.cpu().numpy()[si]
+    np.testing.assert_array_equal(dst.cpu().numpy(), want)
+    dst = torch.from_numpy(dst0.copy()).to(DEV)
+    gem.copy_rows(src, dst, src_idx=torch.from_numpy(si).to(DEV), n=n)           # gather into the leading rows
+    want = dst0.copy()
+    want[:n] = src.cpu().numpy()[si]
+    np.testing.assert_array_equal(dst.cpu().numpy(), want)
+    gem.copy_rows(src, dst, n=0)                                                  # empty copy is a no-op
+    np.testing.assert_array_equal(dst.cpu().numpy(), want)
+
+
 # ----------------------------------------------------------------------- dense (exhaustive)
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 def test_dense_workload1_matches_oracle(dtype):
