@@ -8,6 +8,8 @@ path computes, written from the paper (GEM, arXiv 2603.20336):
   * the bounded result set R of Alg. 5 (Sec. 4.5): keep at most ef, evict the worst
   * the final exact rerank of Alg. 5 and the #rerank pool (Sec. 5, "Effect of #rerank")
   * Recall@k, Sec. 5.1 "Evaluation Metrics"
+  * the centroid codebook C_quant (k-means, Sec. 4.1), the nearest-centroid map
+    NN (Sec. 4.2) and the quantized Chamfer estimate qCH (Sec. 4.5, Eq. qCH)
   * the bf16 / OCP FP8 E4M3 codecs used for the quantized estimate (the paper's
     qCH replaces vectors by coarser codes, Sec. 4.2 "Quantization"; here the
     code is an FP8 E4M3 value times a per-vector power-of-two scale)
@@ -23,6 +25,8 @@ independent float8 / bfloat16 casts.
 """
 from .chamfer import (ch_pair, ch_dense, ch_cands, topk_rows, topk_segments, beam_merge,
                       beam_replay, recall_at_k, tie_aware_match)
+from .codebook import (codebook_size, sq_distances, nn_assign, lloyd_update, kmeans, kmeans_objective,
+                       qch_pair, qch_dense, qch_cands)
 from .codecs import (bf16_round_bits, bf16_decode, e4m3_decode, e4m3_decode_table,
                      e4m3_encode, pow2_scale, quantize_fp8, dequantize_fp8)
 
@@ -31,4 +35,6 @@ __all__ = [
     "beam_replay", "recall_at_k", "tie_aware_match",
     "bf16_round_bits", "bf16_decode", "e4m3_decode", "e4m3_decode_table", "e4m3_encode",
     "pow2_scale", "quantize_fp8", "dequantize_fp8",
+    "codebook_size", "sq_distances", "nn_assign", "lloyd_update", "kmeans", "kmeans_objective",
+    "qch_pair", "qch_dense", "qch_cands",
 ]
