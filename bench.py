@@ -77,7 +77,7 @@ def cpu_baseline(q: wl.SetBatch, c: wl.SetBatch, n_sample: int):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "score_dense_bf16_exhaustive100k_traffic.txt")
 DENSE_SOURCES = [os.path.join(ROOT, "paper_2603_20336_amd", "csrc", f)
-                 for f in ("score.hip", "device_common.hpp", "gem_internal.h")]
+                 for f in ("score.hip", "mfma_ops.hpp", "device_common.hpp", "gem_internal.h")]
 
 
 def dense_source_digest() -> str:

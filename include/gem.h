@@ -70,7 +70,9 @@ typedef enum {
   GEM_OP_SCORE_EXACT = 0,
   GEM_OP_SCORE_QUANT = 1,
   GEM_OP_TOPK = 2,
-  GEM_OP_EXPAND = 3
+  GEM_OP_EXPAND = 3,
+  GEM_OP_NEAREST_CENTROID = 4,
+  GEM_OP_CENTROID_UPDATE = 5
 } gem_op;
 
 /* Largest query set (rows) a scoring call accepts. */
@@ -89,17 +91,30 @@ typedef struct gem_ctx_s* gem_ctx;
  *   scales: FP8 only, [n_vecs] float32; row r's values are scales[r] * decode(code).
  *           Scales must be powers of two (gem_quantize_fp8 writes such scales).
  *   max_set_len: host-side upper bound of the set lengths (needed for query sets).
+ *
+ * Code sets (the quantized representation of Secs. 4.2 and 4.5, where every
+ * vector is replaced by its nearest centroid NN(x) of the k-means vocabulary
+ * C_quant): when `codes` is not NULL, the sets hold codes instead of rows.
+ * Entry r of the batch (r < n_vecs, offsets index the entries) stands for row
+ * codes[r] of `vecs`, which then holds the codebook: codebook_rows centroid
+ * rows of element type `dtype` (FP8: scales[codes[r]] is that row's scale).
+ * CH over code sets is the paper's quantized Chamfer estimate
+ * qCH(Q, P) = sum_q max_p <NN(q), NN(p)>, computed in the compute dtype
+ * (float32 compute gives the centroid products of the paper's float table).
+ * Codes must lie in [0, codebook_rows) (gem_validate_sets checks them).
  */
 typedef struct {
   int32_t dtype;               /* gem_dtype */
   int32_t dim;                 /* must be GEM_DIM */
   int64_t n_sets;
-  int64_t n_vecs;              /* rows addressable in vecs (>= every offset) */
+  int64_t n_vecs;              /* rows addressable in vecs (>= every offset); code sets: entries of codes */
   int32_t max_set_len;
   int32_t reserved;
   const int64_t* offsets;      /* [device] [n_sets + 1] */
-  const void* vecs;            /* [device] */
-  const float* scales;         /* [device] FP8 only, else NULL */
+  const void* vecs;            /* [device] rows, or the codebook of a code set */
+  const float* scales;         /* [device] FP8 only, else NULL (code sets: per codebook row) */
+  int64_t codebook_rows;       /* code sets: rows of vecs; else 0 */
+  const int32_t* codes;        /* [device] [n_vecs] code sets only, else NULL */
 } gem_sets;
 
 /* Candidate-id lists, one per query set.
@@ -156,6 +171,38 @@ gem_status gem_convert_bf16(gem_ctx ctx, const float* x, int64_t n_rows, int32_t
  *   scales: [device] [n_rows] float32. */
 gem_status gem_quantize_fp8(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim,
                             uint8_t* out, float* scales, hipStream_t stream);
+
+/* Nearest centroid (the map NN of Sec. 4.2 onto the k-means vocabulary of
+ * Sec. 4.1): codes[i] = argmin_j ||x_i - c_j||^2, ties to the smallest j,
+ * evaluated as argmax_j (<x_i, c_j> - ||c_j||^2 / 2) with MFMA inner products
+ * in `dtype` (GEM_F32: float32 products; GEM_BF16: bfloat16 operands) and
+ * float32 accumulation. The result is the same for any launch split.
+ *   x: [device] [n_rows * dim] rows of `dtype`; centroids: [device]
+ *   [n_centroids * dim] rows of `dtype`; codes: [device] [n_rows] int32.
+ *   ws: [device] at least gem_codebook_workspace_bytes(GEM_OP_NEAREST_CENTROID,
+ *   n_rows, n_centroids) bytes. Values must be finite. */
+gem_status gem_nearest_centroid(gem_ctx ctx, const void* x, int64_t n_rows, const void* centroids,
+                                int64_t n_centroids, int32_t dim, int32_t dtype, int32_t* codes, void* ws,
+                                size_t ws_bytes, hipStream_t stream);
+
+/* One k-means centroid update (Lloyd's step behind C_quant, Sec. 4.1): centroid
+ * j becomes the mean of the rows x_i with codes[i] == j; a centroid with no
+ * rows keeps its old value. The sums are exact integer sums of the rows scaled
+ * by a power of two chosen from max |x| and n_rows (rounding each element to
+ * that grid, below 2^-30 relative to max |x|), so the result does not depend on
+ * the order of the atomic adds.
+ *   x: [device] [n_rows * dim] float32; codes: [device] [n_rows] in
+ *   [0, n_centroids); centroids (old), new_centroids: [device]
+ *   [n_centroids * dim] float32 (may be the same buffer); counts: [device]
+ *   [n_centroids] int32 (rows per centroid), or NULL. ws: [device] at least
+ *   gem_codebook_workspace_bytes(GEM_OP_CENTROID_UPDATE, n_rows, n_centroids). */
+gem_status gem_centroid_update(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim, const int32_t* codes,
+                               const float* centroids, int64_t n_centroids, float* new_centroids, int32_t* counts,
+                               void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes of gem_nearest_centroid / gem_centroid_update (op is
+ * GEM_OP_NEAREST_CENTROID or GEM_OP_CENTROID_UPDATE; 0 for anything else). */
+size_t gem_codebook_workspace_bytes(int32_t op, int64_t n_rows, int64_t n_centroids);
 
 /* Row copies for assembling batches (a serving loop gathers the active
  * requests' query rows from per-request slots, and writes admitted requests'

@@ -22,7 +22,8 @@ from ._abi import (GEM_BF16, GEM_F32, GEM_FP8_E4M3, GEM_MAX_K, GEM_MAX_QUERY_LEN
 __all__ = ["Sets", "Cands", "Beam", "GemError", "convert_bf16", "quantize_fp8", "score_exact",
            "score_quant", "topk", "expand_batch", "beam_merge", "beam_reset", "validate_sets", "validate_cands",
            "library", "GEM_F32", "GEM_BF16", "GEM_FP8_E4M3", "GEM_MAX_K", "GEM_MAX_QUERY_LEN", "dense_schedule",
-           "set_dense_schedule", "autotune_dense", "copy_rows"]
+           "set_dense_schedule", "autotune_dense", "copy_rows", "nearest_centroid", "centroid_update",
+           "kmeans", "encode"]
 
 _DTYPES = {"f32": GEM_F32, "bf16": GEM_BF16, "fp8": GEM_FP8_E4M3,
            GEM_F32: GEM_F32, GEM_BF16: GEM_BF16, GEM_FP8_E4M3: GEM_FP8_E4M3}
@@ -70,10 +71,14 @@ class Sets:
     offsets: [n_sets + 1] int64 absolute row indices
     scales: FP8 only, [n_vecs] float32 powers of two
     max_len: host-side bound of the set lengths
+    codes: code sets only, [n_vecs] int32: entry r stands for row codes[r] of
+        vecs, which then holds the codebook (its nearest centroid, Sec. 4.2);
+        CH over code sets is the quantized estimate qCH of Sec. 4.5
     """
 
     def __init__(self, vecs: torch.Tensor, offsets: torch.Tensor, dtype, max_len: int,
-                 scales: Optional[torch.Tensor] = None, n_sets: Optional[int] = None):
+                 scales: Optional[torch.Tensor] = None, n_sets: Optional[int] = None,
+                 codes: Optional[torch.Tensor] = None):
         self.dtype = _DTYPES[dtype]
         if vecs.dtype != _ROW_TORCH[self.dtype]:
             raise TypeError(f"vecs dtype {vecs.dtype} does not match gem dtype {self.dtype}")
@@ -81,7 +86,9 @@ class Sets:
             raise ValueError("vecs must be a contiguous [n, 128] tensor")
         if offsets.dtype != torch.int64 or not offsets.is_contiguous():
             raise TypeError("offsets must be contiguous int64")
-        self.vecs, self.offsets, self.scales = vecs, offsets, scales
+        if codes is not None and (codes.dtype != torch.int32 or codes.dim() != 1 or not codes.is_contiguous()):
+            raise TypeError("codes must be a contiguous 1-d int32 tensor")
+        self.vecs, self.offsets, self.scales, self.codes = vecs, offsets, scales, codes
         self.max_len = int(max_len)
         self.n_sets = int(offsets.numel() - 1) if n_sets is None else int(n_sets)
 
@@ -91,7 +98,7 @@ class Sets:
 
     @property
     def n_vecs(self) -> int:
-        return int(self.vecs.shape[0])
+        return int(self.codes.numel() if self.codes is not None else self.vecs.shape[0])
 
     @classmethod
     def from_batch(cls, batch, device="cuda") -> "Sets":
@@ -105,11 +112,13 @@ class Sets:
         s.dtype, s.dim, s.n_sets, s.n_vecs = self.dtype, _abi.GEM_DIM, self.n_sets, self.n_vecs
         s.max_set_len, s.reserved = self.max_len, 0
         s.offsets, s.vecs, s.scales = _ptr(self.offsets), _ptr(self.vecs), _ptr(self.scales)
+        s.codebook_rows = int(self.vecs.shape[0]) if self.codes is not None else 0
+        s.codes = _ptr(self.codes)
         return s
 
     def view(self, a: int, b: int) -> "Sets":
         """Sets a..b-1 as a batch of their own (no copy; ids become relative to a)."""
-        return Sets(self.vecs, self.offsets[a:b + 1], self.dtype, self.max_len, self.scales)
+        return Sets(self.vecs, self.offsets[a:b + 1], self.dtype, self.max_len, self.scales, codes=self.codes)
 
     def to_bf16(self, stream=None) -> "Sets":
         return convert_bf16(self, stream)
@@ -172,21 +181,23 @@ def convert_bf16(S: Sets, stream=None) -> Sets:
     """float32 sets -> bfloat16 sets (round to nearest even)."""
     if S.dtype != GEM_F32:
         raise TypeError("convert_bf16 takes float32 sets")
-    out = torch.empty(S.n_vecs, _abi.GEM_DIM, dtype=torch.uint16, device=S.device)
-    _abi.check(library().gem_convert_bf16(_ctx(S.device), _ptr(S.vecs), S.n_vecs, _abi.GEM_DIM,
+    n = int(S.vecs.shape[0])                       # (a code set converts its codebook)
+    out = torch.empty(n, _abi.GEM_DIM, dtype=torch.uint16, device=S.device)
+    _abi.check(library().gem_convert_bf16(_ctx(S.device), _ptr(S.vecs), n, _abi.GEM_DIM,
                                           _ptr(out), _stream(stream)))
-    return Sets(out, S.offsets, GEM_BF16, S.max_len, n_sets=S.n_sets)
+    return Sets(out, S.offsets, GEM_BF16, S.max_len, n_sets=S.n_sets, codes=S.codes)
 
 
 def quantize_fp8(S: Sets, stream=None) -> Sets:
     """float32 sets -> E4M3 codes + one power-of-two scale per vector."""
     if S.dtype != GEM_F32:
         raise TypeError("quantize_fp8 takes float32 sets")
-    out = torch.empty(S.n_vecs, _abi.GEM_DIM, dtype=torch.uint8, device=S.device)
-    sc = torch.empty(S.n_vecs, dtype=torch.float32, device=S.device)
-    _abi.check(library().gem_quantize_fp8(_ctx(S.device), _ptr(S.vecs), S.n_vecs, _abi.GEM_DIM,
+    n = int(S.vecs.shape[0])                       # (a code set converts its codebook)
+    out = torch.empty(n, _abi.GEM_DIM, dtype=torch.uint8, device=S.device)
+    sc = torch.empty(n, dtype=torch.float32, device=S.device)
+    _abi.check(library().gem_quantize_fp8(_ctx(S.device), _ptr(S.vecs), n, _abi.GEM_DIM,
                                           _ptr(out), _ptr(sc), _stream(stream)))
-    return Sets(out, S.offsets, GEM_FP8_E4M3, S.max_len, scales=sc, n_sets=S.n_sets)
+    return Sets(out, S.offsets, GEM_FP8_E4M3, S.max_len, scales=sc, n_sets=S.n_sets, codes=S.codes)
 
 
 def _score(fn_exact: bool, Q: Sets, D: Sets, cands: Optional[Cands], k: int, compute: int,
@@ -248,6 +259,85 @@ def copy_rows(src: torch.Tensor, dst: torch.Tensor, src_idx: Optional[torch.Tens
         n = (src_idx if src_idx is not None else dst_idx if dst_idx is not None else src).shape[0]
     _abi.check(library().gem_copy_rows(_ctx(dst.device), _ptr(src), _ptr(src_idx), _ptr(dst), _ptr(dst_idx), int(n),
                                        int(rb), _stream(stream)))
+
+
+def _rows(x: torch.Tensor, what: str) -> int:
+    if x.dim() != 2 or x.shape[1] != _abi.GEM_DIM or not x.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous [n, 128] tensor")
+    return int(x.shape[0])
+
+
+def nearest_centroid(x: torch.Tensor, centroids: torch.Tensor, stream=None) -> torch.Tensor:
+    """NN(x) of Sec. 4.2 as int32 centroid indices: argmin_j ||x_i - c_j||^2, ties to
+    the smallest j. x and centroids are float32 rows (float32 products) or bfloat16
+    bit patterns (uint16; bf16 products), both of the same type."""
+    dt = {torch.float32: GEM_F32, torch.uint16: GEM_BF16}.get(x.dtype)
+    if dt is None or centroids.dtype != x.dtype:
+        raise TypeError("x and centroids must both be float32 or both bfloat16 bit patterns (uint16)")
+    n, k = _rows(x, "x"), _rows(centroids, "centroids")
+    lib = library()
+    codes = torch.empty(n, dtype=torch.int32, device=x.device)
+    need = lib.gem_codebook_workspace_bytes(_abi.GEM_OP_NEAREST_CENTROID, n, k)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    _abi.check(lib.gem_nearest_centroid(_ctx(x.device), _ptr(x), n, _ptr(centroids), k, _abi.GEM_DIM, dt,
+                                        _ptr(codes), _ptr(ws), need, _stream(stream)))
+    return codes
+
+
+def centroid_update(x: torch.Tensor, codes: torch.Tensor, centroids: torch.Tensor,
+                    out: Optional[torch.Tensor] = None, stream=None):
+    """One k-means update (Sec. 4.1): each centroid moves to the mean of its rows;
+    one without rows stays. Returns (new centroids, rows per centroid)."""
+    if x.dtype != torch.float32 or centroids.dtype != torch.float32:
+        raise TypeError("centroid_update takes float32 rows and centroids")
+    if codes.dtype != torch.int32 or not codes.is_contiguous() or codes.numel() != x.shape[0]:
+        raise TypeError("codes must be contiguous int32, one per row")
+    n, k = _rows(x, "x"), _rows(centroids, "centroids")
+    out = torch.empty_like(centroids) if out is None else out
+    counts = torch.empty(k, dtype=torch.int32, device=x.device)
+    lib = library()
+    need = lib.gem_codebook_workspace_bytes(_abi.GEM_OP_CENTROID_UPDATE, n, k)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    _abi.check(lib.gem_centroid_update(_ctx(x.device), _ptr(x), n, _abi.GEM_DIM, _ptr(codes), _ptr(centroids), k,
+                                       _ptr(out), _ptr(counts), _ptr(ws), need, _stream(stream)))
+    return out, counts
+
+
+def _bf16_rows(x: torch.Tensor, stream=None) -> torch.Tensor:
+    out = torch.empty(x.shape[0], _abi.GEM_DIM, dtype=torch.uint16, device=x.device)
+    _abi.check(library().gem_convert_bf16(_ctx(x.device), _ptr(x), int(x.shape[0]), _abi.GEM_DIM, _ptr(out),
+                                          _stream(stream)))
+    return out
+
+
+def kmeans(x: torch.Tensor, init_rows: torch.Tensor, n_iter: int, assign: str = "f32", stream=None) -> torch.Tensor:
+    """The k-means vocabulary C_quant of Sec. 4.1: Lloyd's algorithm on the float32
+    rows x from the centroids x[init_rows] (the caller draws init_rows), n_iter
+    rounds of (nearest centroid, update). `assign` is the precision of the
+    nearest-centroid step ("f32" or "bf16"); the update is always float32."""
+    if init_rows.dtype != torch.int64:
+        raise TypeError("init_rows must be int64")
+    k = int(init_rows.numel())
+    C = torch.empty(k, _abi.GEM_DIM, dtype=torch.float32, device=x.device)
+    copy_rows(x, C, src_idx=init_rows.to(x.device).contiguous(), n=k, stream=stream)
+    xa = _bf16_rows(x, stream) if assign == "bf16" else x
+    for _ in range(n_iter):
+        Ca = _bf16_rows(C, stream) if assign == "bf16" else C
+        codes = nearest_centroid(xa, Ca, stream)
+        C, _ = centroid_update(x, codes, C, out=C, stream=stream)
+    return C
+
+
+def encode(S: Sets, centroids: torch.Tensor, assign: str = "f32", stream=None) -> Sets:
+    """The code set of float32 sets S over a float32 codebook: every vector is
+    replaced by the index of its nearest centroid (Sec. 4.2)."""
+    if S.dtype != GEM_F32 or S.codes is not None:
+        raise TypeError("encode takes float32 sets of vectors")
+    if assign == "bf16":
+        codes = nearest_centroid(_bf16_rows(S.vecs, stream), _bf16_rows(centroids, stream), stream)
+    else:
+        codes = nearest_centroid(S.vecs, centroids, stream)
+    return Sets(centroids, S.offsets, GEM_F32, S.max_len, n_sets=S.n_sets, codes=codes)
 
 
 def _sched_dict(s) -> dict:

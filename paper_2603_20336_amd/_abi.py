@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libgem.so")
 GEM_OK, GEM_ERR_INVALID, GEM_ERR_WORKSPACE, GEM_ERR_UNSUPPORTED, GEM_ERR_HIP, GEM_ERR_DEVICE_CHECK = range(6)
 GEM_F32, GEM_BF16, GEM_FP8_E4M3 = 0, 1, 2
 GEM_OP_SCORE_EXACT, GEM_OP_SCORE_QUANT, GEM_OP_TOPK, GEM_OP_EXPAND = 0, 1, 2, 3
+GEM_OP_NEAREST_CENTROID, GEM_OP_CENTROID_UPDATE = 4, 5
 GEM_MAX_QUERY_LEN = 256
 GEM_MAX_K = 1024
 GEM_DIM = 128
@@ -30,7 +31,8 @@ i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
 class gem_sets(ctypes.Structure):
     _fields_ = [("dtype", i32), ("dim", i32), ("n_sets", i64), ("n_vecs", i64),
                 ("max_set_len", i32), ("reserved", i32),
-                ("offsets", c_p), ("vecs", c_p), ("scales", c_p)]
+                ("offsets", c_p), ("vecs", c_p), ("scales", c_p),
+                ("codebook_rows", i64), ("codes", c_p)]
 
 
 class gem_cands(ctypes.Structure):
@@ -68,6 +70,9 @@ SIGNATURES = {
     "gem_validate_sets": (i32, [c_p, P_SETS, c_p]),
     "gem_validate_cands": (i32, [c_p, P_CANDS, i64, c_p]),
     "gem_copy_rows": (i32, [c_p, c_p, c_p, c_p, c_p, i64, i64, c_p]),
+    "gem_nearest_centroid": (i32, [c_p, c_p, i64, c_p, i64, i32, i32, c_p, c_p, sz, c_p]),
+    "gem_centroid_update": (i32, [c_p, c_p, i64, i32, c_p, c_p, i64, c_p, c_p, c_p, sz, c_p]),
+    "gem_codebook_workspace_bytes": (sz, [i32, i64, i64]),
     "gem_get_dense_schedule": (i32, [c_p, i32, i64, i64, ctypes.POINTER(gem_dense_schedule)]),
     "gem_set_dense_schedule": (i32, [c_p, i32, i64, i64, ctypes.POINTER(gem_dense_schedule)]),
     "gem_autotune_dense": (i32, [c_p, P_SETS, P_SETS, i32, c_p, i64, c_p, sz, c_p, i32,

@@ -71,8 +71,20 @@ gem_status check_sets(const gem_sets* S, const char* name, bool need_max_len) {
     return fail(GEM_ERR_UNSUPPORTED, "%s: max_set_len %d exceeds %d", name, S->max_set_len, GEM_MAX_QUERY_LEN);
   if (need_max_len && S->n_vecs > 0 && S->max_set_len == 0 && S->n_sets > 0)
     return fail(GEM_ERR_INVALID, "%s: max_set_len must bound the set lengths", name);
+  if (S->codes) {
+    if (S->codebook_rows <= 0 && S->n_vecs > 0) return fail(GEM_ERR_INVALID, "%s: code set with an empty codebook", name);
+    if (S->codebook_rows > INT32_MAX) return fail(GEM_ERR_UNSUPPORTED, "%s: codebook of more than 2^31-1 rows", name);
+    if (S->codebook_rows > 0 && !S->vecs) return fail(GEM_ERR_INVALID, "%s: codebook (vecs) is NULL", name);
+    if (S->dtype == GEM_FP8_E4M3 && S->codebook_rows > 0 && !S->scales)
+      return fail(GEM_ERR_INVALID, "%s: FP8 codebook needs scales", name);
+  } else if (S->codebook_rows != 0) {
+    return fail(GEM_ERR_INVALID, "%s: codebook_rows set without codes", name);
+  }
   return GEM_OK;
 }
+
+// Rows of S's vector array: the codebook of a code set, else one per entry.
+int64_t vec_rows(const gem_sets* S) { return S->codes ? S->codebook_rows : S->n_vecs; }
 
 gem_status check_cands(const gem_cands* C, int64_t n_q) {
   if (C->n_lists != n_q) return fail(GEM_ERR_INVALID, "cands: n_lists %lld != number of query sets %lld",
@@ -94,7 +106,7 @@ int32_t list_len_bound(const gem_cands* C) { return C->offsets ? C->max_list_len
 
 SetsView view(const gem_sets* S) {
   SetsView v;
-  v.off = S->offsets; v.vecs = S->vecs; v.scales = S->scales; v.n_sets = S->n_sets;
+  v.off = S->offsets; v.vecs = S->vecs; v.scales = S->scales; v.codes = S->codes; v.n_sets = S->n_sets;
   return v;
 }
 
@@ -117,10 +129,10 @@ ScoreLayout score_layout(const gem_sets* Q, const gem_sets* D, const gem_cands* 
   size_t off = 0;
   if (Q->dtype != compute) {
     L.q_conv = off;
-    off = align_up(off + (size_t)Q->n_vecs * row_bytes(compute));
+    off = align_up(off + (size_t)vec_rows(Q) * row_bytes(compute));
     if (compute == GEM_FP8_E4M3) {
       L.q_scales = off;
-      off = align_up(off + (size_t)Q->n_vecs * 4);
+      off = align_up(off + (size_t)vec_rows(Q) * 4);
     }
   }
   if (!C) {
@@ -150,11 +162,12 @@ gem_status convert_query(const gem_sets* Q, int32_t compute, void* ws, const Sco
   if (Q->dtype == compute) return GEM_OK;
   if (Q->dtype != GEM_F32) return fail(GEM_ERR_INVALID, "Q: dtype must be F32 or the compute dtype");
   hipError_t e;
+  // (a code set converts its codebook; the codes stay as they are)
   if (compute == GEM_BF16) {
-    e = launch_convert_bf16(static_cast<const float*>(Q->vecs), Q->n_vecs * GEM_DIM,
+    e = launch_convert_bf16(static_cast<const float*>(Q->vecs), vec_rows(Q) * GEM_DIM,
                             reinterpret_cast<uint16_t*>(at(ws, L.q_conv)), stream);
   } else {
-    e = launch_quantize_fp8(static_cast<const float*>(Q->vecs), Q->n_vecs, reinterpret_cast<uint8_t*>(at(ws, L.q_conv)),
+    e = launch_quantize_fp8(static_cast<const float*>(Q->vecs), vec_rows(Q), reinterpret_cast<uint8_t*>(at(ws, L.q_conv)),
                             reinterpret_cast<float*>(at(ws, L.q_scales)), stream);
     Qc->scales = reinterpret_cast<const float*>(at(ws, L.q_scales));
   }
@@ -279,6 +292,11 @@ __global__ void validate_ids_kernel(const int32_t* ids, int64_t n, int64_t n_set
     if (ids[i] >= n_sets) atomicAdd(&g_validate_bad, 1ull);
 }
 
+__global__ void validate_codes_kernel(const int32_t* codes, int64_t n, int64_t n_rows) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    if (codes[i] < 0 || codes[i] >= n_rows) atomicAdd(&g_validate_bad, 1ull);
+}
+
 gem_status run_validation(hipStream_t stream, const char* what) {
   unsigned long long bad = 0;
   hipError_t e = hipMemcpyFromSymbolAsync(&bad, HIP_SYMBOL(g_validate_bad), sizeof(bad), 0, hipMemcpyDeviceToHost, stream);
@@ -381,6 +399,49 @@ gem_status gem_quantize_fp8(gem_ctx ctx, const float* x, int64_t n_rows, int32_t
   if (n_rows > 0 && (!x || !out || !scales)) return fail(GEM_ERR_INVALID, "NULL buffer");
   hipError_t e = launch_quantize_fp8(x, n_rows, out, scales, stream);
   return e == hipSuccess ? GEM_OK : hip_fail(e, "fp8 quantization");
+}
+
+size_t gem_codebook_workspace_bytes(int32_t op, int64_t n_rows, int64_t n_centroids) {
+  if (n_rows < 0 || n_centroids < 0) return 0;
+  switch (op) {
+    case GEM_OP_NEAREST_CENTROID: return nearest_centroid_ws_bytes(n_rows, n_centroids);
+    case GEM_OP_CENTROID_UPDATE: return centroid_update_ws_bytes(n_rows, n_centroids);
+    default: return 0;
+  }
+}
+
+gem_status gem_nearest_centroid(gem_ctx ctx, const void* x, int64_t n_rows, const void* centroids, int64_t n_centroids,
+                                int32_t dim, int32_t dtype, int32_t* codes, void* ws, size_t ws_bytes,
+                                hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (dim != GEM_DIM) return fail(GEM_ERR_UNSUPPORTED, "dim %d (only %d is supported)", dim, GEM_DIM);
+  if (dtype != GEM_F32 && dtype != GEM_BF16)
+    return fail(GEM_ERR_UNSUPPORTED, "nearest centroid runs in F32 or BF16, not dtype %d", dtype);
+  if (n_rows < 0 || n_centroids < 0) return fail(GEM_ERR_INVALID, "negative size");
+  if (n_centroids > INT32_MAX - 16) return fail(GEM_ERR_UNSUPPORTED, "more than 2^31-17 centroids");
+  if (n_rows == 0) return GEM_OK;
+  if (n_centroids == 0) return fail(GEM_ERR_INVALID, "no centroids");
+  if (!x || !centroids || !codes) return fail(GEM_ERR_INVALID, "NULL buffer");
+  const size_t need = nearest_centroid_ws_bytes(n_rows, n_centroids);
+  if (ws_bytes < need) return fail(GEM_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+  if (!ws) return fail(GEM_ERR_INVALID, "workspace is NULL");
+  hipError_t e = launch_nearest_centroid(dtype, x, n_rows, centroids, n_centroids, codes, ws, ctx->n_cu, stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "nearest centroid");
+}
+
+gem_status gem_centroid_update(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim, const int32_t* codes,
+                               const float* centroids, int64_t n_centroids, float* new_centroids, int32_t* counts,
+                               void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (dim != GEM_DIM) return fail(GEM_ERR_UNSUPPORTED, "dim %d (only %d is supported)", dim, GEM_DIM);
+  if (n_rows < 0 || n_centroids < 0) return fail(GEM_ERR_INVALID, "negative size");
+  if (n_centroids == 0) return n_rows == 0 ? GEM_OK : fail(GEM_ERR_INVALID, "rows without centroids");
+  if (!centroids || !new_centroids || (n_rows > 0 && (!x || !codes))) return fail(GEM_ERR_INVALID, "NULL buffer");
+  const size_t need = centroid_update_ws_bytes(n_rows, n_centroids);
+  if (ws_bytes < need) return fail(GEM_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+  if (!ws) return fail(GEM_ERR_INVALID, "workspace is NULL");
+  hipError_t e = launch_centroid_update(x, n_rows, codes, centroids, n_centroids, new_centroids, counts, ws, stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "centroid update");
 }
 
 gem_status gem_copy_rows(gem_ctx ctx, const void* src, const int64_t* src_idx, void* dst, const int64_t* dst_idx,
@@ -501,9 +562,14 @@ gem_status gem_validate_sets(gem_ctx ctx, const gem_sets* S, hipStream_t stream)
     hipLaunchKernelGGL(validate_offsets_kernel, dim3(capped_blocks((S->n_sets + 1 + 255) / 256, 256)), dim3(256), 0, stream,
                        S->offsets, S->n_sets, S->n_vecs);
   }
-  if (S->dtype == GEM_FP8_E4M3 && S->n_vecs > 0) {
-    hipLaunchKernelGGL(validate_scales_kernel, dim3(capped_blocks((S->n_vecs + 255) / 256, 256)), dim3(256), 0, stream,
-                       S->scales, S->n_vecs);
+  const int64_t rows = vec_rows(S);
+  if (S->dtype == GEM_FP8_E4M3 && rows > 0) {
+    hipLaunchKernelGGL(validate_scales_kernel, dim3(capped_blocks((rows + 255) / 256, 256)), dim3(256), 0, stream,
+                       S->scales, rows);
+  }
+  if (S->codes && S->n_vecs > 0) {
+    hipLaunchKernelGGL(validate_codes_kernel, dim3(capped_blocks((S->n_vecs + 255) / 256, 256)), dim3(256), 0, stream,
+                       S->codes, S->n_vecs, S->codebook_rows);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "validation launch");
@@ -579,7 +645,7 @@ gem_status gem_autotune_dense(gem_ctx ctx, const gem_sets* Q, const gem_sets* D,
   hipError_t he = hipEventCreate(&e0);
   if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
   he = hipEventCreate(&e1);
-  if (he != hipSuccess) { hipEventDestroy(e0); return hip_fail(he, "hipEventCreate"); }
+  if (he != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(he, "hipEventCreate"); }
   float best_t = -1.0f;
   DenseSchedule best_s = cand[0];
   gem_status st = GEM_OK;
@@ -600,8 +666,8 @@ gem_status gem_autotune_dense(gem_ctx ctx, const gem_sets* Q, const gem_sets* D,
     ms /= (float)reps;
     if (best_t < 0.0f || ms < best_t) { best_t = ms; best_s = c; }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st != GEM_OK) return st;
   {
     std::lock_guard<std::mutex> g(ctx->mu);

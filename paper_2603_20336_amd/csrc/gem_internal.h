@@ -19,9 +19,10 @@ inline unsigned capped_blocks(int64_t blocks, int threads_per_block) {
 
 // Device view of a CSR set batch.
 struct SetsView {
-  const int64_t* off;     // [n_sets + 1], absolute row indices into vecs
-  const void* vecs;       // rows of kDim elements
+  const int64_t* off;     // [n_sets + 1], absolute entry indices
+  const void* vecs;       // rows of kDim elements (the codebook of a code set)
   const float* scales;    // FP8: per-row power-of-two scale
+  const int32_t* codes;   // code sets: entry r is row codes[r] of vecs; else NULL (entry r is row r)
   int64_t n_sets;
 };
 
@@ -71,6 +72,14 @@ hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, 
 
 hipError_t launch_convert_bf16(const float* x, int64_t n_elems, uint16_t* out, hipStream_t s);
 hipError_t launch_quantize_fp8(const float* x, int64_t n_rows, uint8_t* out, float* scales, hipStream_t s);
+// Codebook kernels (nearest centroid, k-means update).
+size_t nearest_centroid_ws_bytes(int64_t n_rows, int64_t n_centroids);
+hipError_t launch_nearest_centroid(int dtype, const void* x, int64_t n_rows, const void* centroids,
+                                   int64_t n_centroids, int32_t* codes, void* ws, int n_cu, hipStream_t s);
+size_t centroid_update_ws_bytes(int64_t n_rows, int64_t n_centroids);
+hipError_t launch_centroid_update(const float* x, int64_t n_rows, const int32_t* codes, const float* centroids,
+                                  int64_t n_centroids, float* new_centroids, int32_t* counts, void* ws, hipStream_t s);
+
 hipError_t launch_copy_rows(const void* src, const int64_t* src_idx, void* dst, const int64_t* dst_idx, int64_t n,
                             int64_t row_bytes, hipStream_t s);
 

@@ -20,94 +20,14 @@
 
 #include "device_common.hpp"
 #include "gem_internal.h"
+#include "mfma_ops.hpp"
 
 namespace gem {
 
-// --------------------------------------------------------------------------
-// Operand fragments. For every type, lane l loads row (l % 16) of a 16-row tile
-// and lane group g = l / 16 loads dimensions [32g, 32g + 32) of that row. Inside
-// each MFMA the k-slots a lane feeds are a permutation of those dimensions; A
-// and B use the same permutation, so each dot product covers all 128 terms.
-// Output layout: lane l holds D[4g + v][l % 16], v = 0..3.
-template <int DT> struct Op;
-
-template <> struct Op<GEM_F32> {
-  static constexpr int kRowBytes = 512;
-  struct Frag { float v[32]; };
-  static __device__ __forceinline__ void load(Frag& f, const void* vecs, const float*, int64_t row, int g) {
-    const float4* p = reinterpret_cast<const float4*>(static_cast<const char*>(vecs) + row * kRowBytes + g * 128);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      float4 t = p[i];
-      f.v[4 * i + 0] = t.x; f.v[4 * i + 1] = t.y; f.v[4 * i + 2] = t.z; f.v[4 * i + 3] = t.w;
-    }
-  }
-  static __device__ __forceinline__ void zero(Frag& f) {
-#pragma unroll
-    for (int i = 0; i < 32; ++i) f.v[i] = 0.0f;
-  }
-  static __device__ __forceinline__ f32x4 mma(const Frag& a, const Frag& b, f32x4 acc, int s) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[s], b.v[s], acc, 0, 0, 0);
-  }
-  static constexpr int kSteps = 32;
-  static constexpr bool kColumnScale = false;
-  static __device__ __forceinline__ void load_b(Frag& f, const void* v, const float* sc, int64_t row, int g) { load(f, v, sc, row, g); }
-};
-
-template <> struct Op<GEM_BF16> {
-  static constexpr int kRowBytes = 256;
-  struct Frag { bf16x8 v[4]; };
-  static __device__ __forceinline__ void load(Frag& f, const void* vecs, const float*, int64_t row, int g) {
-    const uint4* p = reinterpret_cast<const uint4*>(static_cast<const char*>(vecs) + row * kRowBytes + g * 64);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      uint4 t = p[i];
-      f.v[i] = __builtin_bit_cast(bf16x8, t);
-    }
-  }
-  static __device__ __forceinline__ void zero(Frag& f) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) f.v[i] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
-  }
-  static __device__ __forceinline__ f32x4 mma(const Frag& a, const Frag& b, f32x4 acc, int s) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v[s], b.v[s], acc, 0, 0, 0);
-  }
-  static constexpr int kSteps = 4;
-  static constexpr bool kColumnScale = false;
-  static __device__ __forceinline__ void load_b(Frag& f, const void* v, const float* sc, int64_t row, int g) { load(f, v, sc, row, g); }
-};
-
-template <> struct Op<GEM_FP8_E4M3> {
-  static constexpr int kRowBytes = 128;
-  struct Frag { i32x8 v; int scale; };   // scale: E8M0 exponent byte of the row's power-of-two scale
-  static __device__ __forceinline__ void load(Frag& f, const void* vecs, const float* scales, int64_t row, int g) {
-    const uint4* p = reinterpret_cast<const uint4*>(static_cast<const char*>(vecs) + row * kRowBytes + g * 32);
-    uint4 a = p[0], b = p[1];
-    f.v = i32x8{(int)a.x, (int)a.y, (int)a.z, (int)a.w, (int)b.x, (int)b.y, (int)b.z, (int)b.w};
-    f.scale = (int)((__float_as_uint(scales[row]) >> 23) & 0xffu);
-  }
-  static __device__ __forceinline__ void zero(Frag& f) {
-    f.v = i32x8{0, 0, 0, 0, 0, 0, 0, 0};
-    f.scale = 127;
-  }
-  // Query (B) side: codes only, unit block scale; the query vector's own
-  // power-of-two scale multiplies its column after the max over the document
-  // (max(s * x) = s * max(x) exactly for s = 2^e > 0).
-  static __device__ __forceinline__ void load_b(Frag& f, const void* vecs, const float*, int64_t row, int g) {
-    const uint4* p = reinterpret_cast<const uint4*>(static_cast<const char*>(vecs) + row * kRowBytes + g * 32);
-    uint4 a = p[0], b = p[1];
-    f.v = i32x8{(int)a.x, (int)a.y, (int)a.z, (int)a.w, (int)b.x, (int)b.y, (int)b.z, (int)b.w};
-    f.scale = 127;
-  }
-  static constexpr bool kColumnScale = true;
-  static __device__ __forceinline__ f32x4 mma(const Frag& a, const Frag& b, f32x4 acc, int) {
-    // OCP E4M3 for both operands (format code 0); E8M0 block scales: each
-    // lane's document row (A; all four 32-wide blocks of a row share it) and
-    // the unit scale 2^0 for the query side (B), whose scale applies later.
-    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a.v, b.v, acc, 0, 0, 0, a.scale, 0, 127);
-  }
-  static constexpr int kSteps = 1;
-};
+// Row of S's vector array that entry r stands for (code sets: its centroid).
+__device__ __forceinline__ int64_t vec_row(const SetsView& S, int64_t r) {
+  return S.codes ? (int64_t)S.codes[r] : r;
+}
 
 // Column tiles (16 query vectors each) held in registers by one pass.
 template <int DT> struct DenseCfg;
@@ -346,6 +266,21 @@ template <int DT> struct TileStage {
     __builtin_amdgcn_global_load_lds(static_cast<const char*>(vecs) + row * kRowBytes + c * 16,
                                      (lds_void_ptr)(stage + 64 * role), 16, 0, 0);
   }
+  // Code sets: the same piece, when the lane's row of the vector array is
+  // already known (its code).
+  static __device__ __forceinline__ void copy_piece_row(const void* vecs, int64_t vrow, u32x4* stage, int role,
+                                                        int l) {
+    const int slot = 64 * role + l;
+    const int r = slot / kChunksPerRow, pos = slot % kChunksPerRow;
+    const int c = pos ^ swz(r);
+    __builtin_amdgcn_global_load_lds(static_cast<const char*>(vecs) + vrow * kRowBytes + c * 16,
+                                     (lds_void_ptr)(stage + 64 * role), 16, 0, 0);
+  }
+  // Entry index whose row lane l copies in piece `role` of tile k.
+  static __device__ __forceinline__ int64_t piece_entry(int64_t base, int rs, int re, int k, int role, int l) {
+    const int r = (64 * role + l) / kChunksPerRow;
+    return base + min(rs + 16 * k + r, re - 1);
+  }
   // The 16 row scales of that tile (lanes past 16 repeat them).
   static __device__ __forceinline__ void copy_scales(const float* scales, int64_t base, int rs, int re, int k,
                                                      u32x4* stage, int l) {
@@ -455,13 +390,24 @@ template <int DT> struct DensePass {
   }
 };
 
-template <int DT>
+// kCodes: the documents are a code set. Each tile copy then needs the code of
+// the row it copies; every wave fetches the codes of its own copies into its
+// slots of one of three LDS code arrays (one per group buffer) two groups
+// ahead, with the copies of the group two before, so that a copy never waits
+// on a dependent load and the wait counts stay static.
+template <int DT, bool kCodes>
 __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams P) {
   using O = Op<DT>;
   using Frag = typename O::Frag;
   using TS = TileStage<DT>;
   constexpr int NT = DenseCfg<DT>::kNT;
   constexpr int kGroup = TS::kGroup;
+  constexpr int kCodeCopies = TS::kCopiesPerWave;               // one code per copy
+  constexpr int kIssueOps = TS::kCopiesPerWave + (kCodes ? kCodeCopies : 0);
+  constexpr int kCodeWords = kCodes ? kDenseWaves * kCodeCopies * 64 : 1;
+  __shared__ int32_t lds_code0[kCodeWords];
+  __shared__ int32_t lds_code1[kCodeWords];
+  __shared__ int32_t lds_code2[kCodeWords];
   // three group buffers as separate arrays: the compiler then knows that the
   // copies in flight (into one buffer) never alias the reads (of another)
   __shared__ u32x4 lds_buf0[TS::kGroupVecs];
@@ -571,31 +517,74 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
       // copies of later groups alone fill the wait count: the compiler can
       // then prove that the buffer being read has landed without waiting for
       // every copy.
-      auto issue = [&](auto ybuf, int G) {
-        constexpr int Y = decltype(ybuf)::value;
-        u32x4* buf = Y == 0 ? lds_buf0 : (Y == 1 ? lds_buf1 : lds_buf2);
-        // tile T belongs to the last non-empty document whose first tile is <= T
-        auto locate = [&](int T, int& k, int& rs, int& re) {
-          const uint64_t m = __ballot(d_nt > 0 && d_t0 <= T);
-          const int dd = 63 - __builtin_clzll(m);
-          k = T - __builtin_amdgcn_readlane(d_t0, dd);
-          rs = __builtin_amdgcn_readlane(d_rs, dd);
-          re = __builtin_amdgcn_readlane(d_re, dd);
-        };
+      // tile T belongs to the last non-empty document whose first tile is <= T
+      auto locate = [&](int T, int& k, int& rs, int& re) {
+        const uint64_t m = __ballot(d_nt > 0 && d_t0 <= T);
+        const int dd = 63 - __builtin_clzll(m);
+        k = T - __builtin_amdgcn_readlane(d_t0, dd);
+        rs = __builtin_amdgcn_readlane(d_rs, dd);
+        re = __builtin_amdgcn_readlane(d_re, dd);
+      };
+      // code sets: the codes of this wave's copies of group G into array Z
+      // (slot j of the wave: copy j's rows, one per lane)
+      auto fetch_codes = [&](auto zbuf, int G) {
+        constexpr int Z = decltype(zbuf)::value;
+        int32_t* cb = (Z == 0 ? lds_code0 : (Z == 1 ? lds_code1 : lds_code2)) + w * kCodeCopies * 64;
 #pragma unroll
         for (int j = 0; j < TS::kPieceCopiesPerWave; ++j) {
           const int slot_j = kDenseWaves * j + w;
           const int u = slot_j / TS::kPieceWaves, role = slot_j % TS::kPieceWaves;
           int k, rs, re;
           locate(min(G * kGroup + u, n_tiles - 1), k, rs, re);
-          TS::copy_piece(P.D.vecs, base, rs, re, k, buf + u * (TS::kStageBytes / 16), role, l);
+          __builtin_amdgcn_global_load_lds(P.D.codes + TS::piece_entry(base, rs, re, k, role, l),
+                                           (lds_void_ptr)(cb + 64 * j), 4, 0, 0);
         }
 #pragma unroll
         for (int j = 0; j < TS::kScaleCopiesPerWave; ++j) {
           const int u = kDenseWaves * j + w;
           int k, rs, re;
           locate(min(G * kGroup + u, n_tiles - 1), k, rs, re);
-          TS::copy_scales(P.D.scales, base, rs, re, k, buf + u * (TS::kStageBytes / 16), l);
+          __builtin_amdgcn_global_load_lds(P.D.codes + base + min(rs + 16 * k + (l & 15), re - 1),
+                                           (lds_void_ptr)(cb + 64 * (TS::kPieceCopiesPerWave + j)), 4, 0, 0);
+        }
+      };
+      auto issue = [&](auto ybuf, int G) {
+        constexpr int Y = decltype(ybuf)::value;
+        u32x4* buf = Y == 0 ? lds_buf0 : (Y == 1 ? lds_buf1 : lds_buf2);
+        if constexpr (kCodes) {
+          // this group's codes (array Y, fetched two groups ago), then the
+          // codes of group G + 2 into the array whose group is already issued
+          const int32_t* cb = (Y == 0 ? lds_code0 : (Y == 1 ? lds_code1 : lds_code2)) + w * kCodeCopies * 64;
+#pragma unroll
+          for (int j = 0; j < TS::kPieceCopiesPerWave; ++j) {
+            const int slot_j = kDenseWaves * j + w;
+            const int u = slot_j / TS::kPieceWaves, role = slot_j % TS::kPieceWaves;
+            TS::copy_piece_row(P.D.vecs, (int64_t)cb[64 * j + l], buf + u * (TS::kStageBytes / 16), role, l);
+          }
+#pragma unroll
+          for (int j = 0; j < TS::kScaleCopiesPerWave; ++j) {
+            const int u = kDenseWaves * j + w;
+            __builtin_amdgcn_global_load_lds(P.D.scales + cb[64 * (TS::kPieceCopiesPerWave + j) + l],
+                                             (lds_void_ptr)(buf + u * (TS::kStageBytes / 16) + TS::kTileBytes / 16),
+                                             4, 0, 0);
+          }
+          fetch_codes(std::integral_constant<int, (Y + 2) % 3>{}, G + 2);
+        } else {
+#pragma unroll
+          for (int j = 0; j < TS::kPieceCopiesPerWave; ++j) {
+            const int slot_j = kDenseWaves * j + w;
+            const int u = slot_j / TS::kPieceWaves, role = slot_j % TS::kPieceWaves;
+            int k, rs, re;
+            locate(min(G * kGroup + u, n_tiles - 1), k, rs, re);
+            TS::copy_piece(P.D.vecs, base, rs, re, k, buf + u * (TS::kStageBytes / 16), role, l);
+          }
+#pragma unroll
+          for (int j = 0; j < TS::kScaleCopiesPerWave; ++j) {
+            const int u = kDenseWaves * j + w;
+            int k, rs, re;
+            locate(min(G * kGroup + u, n_tiles - 1), k, rs, re);
+            TS::copy_scales(P.D.scales, base, rs, re, k, buf + u * (TS::kStageBytes / 16), l);
+          }
         }
       };
 
@@ -626,9 +615,10 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
               if (k == 0) S.first_mask |= 1ull << ct;
               if (16 * (k + 1) >= jm) S.last_mask |= 1ull << ct;
               if (16 * k + c16 < jm) {
-                O::load_b(S.B[ct], P.Q.vecs, P.Q.scales, jrow + 16 * k + c16, g);
+                const int64_t vr = vec_row(P.Q, jrow + 16 * k + c16);
+                O::load_b(S.B[ct], P.Q.vecs, P.Q.scales, vr, g);
                 if constexpr (O::kColumnScale)
-                  if (g == (ct & 3)) S.qs[ct >> 2] = P.Q.scales[jrow + 16 * k + c16];
+                  if (g == (ct & 3)) S.qs[ct >> 2] = P.Q.scales[vr];
               }
             }
           }
@@ -644,7 +634,7 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
         auto group = [&](auto xbuf, int G) {
           constexpr int X = decltype(xbuf)::value;
           const u32x4* buf = X == 0 ? lds_buf0 : (X == 1 ? lds_buf1 : lds_buf2);
-          wait_vm<TS::kCopiesPerWave>();                        // only group G + 1's copies may be in flight
+          wait_vm<kIssueOps>();                                 // only group G + 1's copies may be in flight
           compiler_fence();
           __builtin_amdgcn_s_barrier();
           compiler_fence();
@@ -669,6 +659,11 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
           }
         };
         if (n_tiles > 0) {
+          if constexpr (kCodes) {
+            fetch_codes(std::integral_constant<int, 0>{}, 0);
+            fetch_codes(std::integral_constant<int, 1>{}, 1);
+            wait_vm<0>();                                       // (each wave reads only its own codes)
+          }
           issue(std::integral_constant<int, 0>{}, 0);
           issue(std::integral_constant<int, 1>{}, 1);
         }
@@ -740,10 +735,20 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
   if (sched.chunk_docs < 1 || sched.chunk_docs > kMaxChunkDocs || sched.items_per_slot < 1 || sched.slots_per_xcd < 1)
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)(8 * sched.slots_per_xcd)), blk(kDenseThreads);
+  const bool codes = D.codes != nullptr;
   switch (dtype) {
-    case GEM_F32: hipLaunchKernelGGL(score_dense_kernel<GEM_F32>, grid, blk, 0, s, P); break;
-    case GEM_BF16: hipLaunchKernelGGL(score_dense_kernel<GEM_BF16>, grid, blk, 0, s, P); break;
-    case GEM_FP8_E4M3: hipLaunchKernelGGL(score_dense_kernel<GEM_FP8_E4M3>, grid, blk, 0, s, P); break;
+    case GEM_F32:
+      if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_F32, true>), grid, blk, 0, s, P);
+      else hipLaunchKernelGGL((score_dense_kernel<GEM_F32, false>), grid, blk, 0, s, P);
+      break;
+    case GEM_BF16:
+      if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_BF16, true>), grid, blk, 0, s, P);
+      else hipLaunchKernelGGL((score_dense_kernel<GEM_BF16, false>), grid, blk, 0, s, P);
+      break;
+    case GEM_FP8_E4M3:
+      if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_FP8_E4M3, true>), grid, blk, 0, s, P);
+      else hipLaunchKernelGGL((score_dense_kernel<GEM_FP8_E4M3, false>), grid, blk, 0, s, P);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -770,7 +775,10 @@ struct GatherParams {
   float* scores;
 };
 
-template <int DT>
+// kCodes: the documents are a code set. Each lane then loads the code of the
+// row it will load PF tiles before that row's load is issued (a second ring of
+// PF codes), so tile loads never wait on a dependent load.
+template <int DT, bool kCodes>
 __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
   using O = Op<DT>;
   using Frag = typename O::Frag;
@@ -845,9 +853,10 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
       for (int ct = 0; ct < NT; ++ct) {
         const int col = prow0 + 16 * ct + c16;
         if (ct < nct && col < m) {
-          O::load_b(B[ct], P.Q.vecs, P.Q.scales, r0 + col, g);
+          const int64_t vr = vec_row(P.Q, r0 + col);
+          O::load_b(B[ct], P.Q.vecs, P.Q.scales, vr, g);
           if constexpr (O::kColumnScale)
-            if (g == (ct & 3)) qs[ct >> 2] = P.Q.scales[r0 + col];
+            if (g == (ct & 3)) qs[ct >> 2] = P.Q.scales[vr];
         } else {
           O::zero(B[ct]);
         }
@@ -859,10 +868,22 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
       // starts the load PF tiles ahead (past the end: the last tile again,
       // never used, so that every step issues the same loads)
       Frag A[PF];
+      int code[PF];                                           // code sets: rows of the tiles PF ahead of A
+      if constexpr (kCodes) {
 #pragma unroll
-      for (int j = 0; j < PF; ++j) {
-        O::load(A[j], P.D.vecs, P.D.scales, tile_row(j), g);
-        __builtin_amdgcn_sched_barrier(0);                    // keep the loads in tile order
+        for (int j = 0; j < PF; ++j) code[j] = P.D.codes[tile_row(j)];
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+          O::load(A[j], P.D.vecs, P.D.scales, code[j], g);
+          code[j] = P.D.codes[tile_row(PF + j)];
+          __builtin_amdgcn_sched_barrier(0);                  // keep the loads in tile order
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+          O::load(A[j], P.D.vecs, P.D.scales, tile_row(j), g);
+          __builtin_amdgcn_sched_barrier(0);                  // keep the loads in tile order
+        }
       }
       for (int T0 = 0; T0 < n_tiles; T0 += PF) {
 #pragma unroll
@@ -887,7 +908,12 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
             }
           }
           // A[j] is free once its products are issued: load the tile PF ahead
-          O::load(A[j], P.D.vecs, P.D.scales, tile_row(T + PF), g);
+          if constexpr (kCodes) {
+            O::load(A[j], P.D.vecs, P.D.scales, code[j], g);
+            code[j] = P.D.codes[tile_row(T + 2 * PF)];
+          } else {
+            O::load(A[j], P.D.vecs, P.D.scales, tile_row(T + PF), g);
+          }
           if (T < n_tiles) {
 #pragma unroll
             for (int ct = 0; ct < NT; ++ct) update_max(rm[ct], acc[ct]);
@@ -923,10 +949,21 @@ hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, 
   for (int64_t b0 = 0; b0 < (waves + 3) / 4; b0 += max_blocks) {
     P.wave0 = b0 * 4;
     const int64_t grid = std::min(max_blocks, (waves + 3) / 4 - b0);
+    const dim3 gr((unsigned)grid), blk(256);
+    const bool codes = D.codes != nullptr;
     switch (dtype) {
-      case GEM_F32: hipLaunchKernelGGL(score_gather_kernel<GEM_F32>, dim3((unsigned)grid), dim3(256), 0, s, P); break;
-      case GEM_BF16: hipLaunchKernelGGL(score_gather_kernel<GEM_BF16>, dim3((unsigned)grid), dim3(256), 0, s, P); break;
-      case GEM_FP8_E4M3: hipLaunchKernelGGL(score_gather_kernel<GEM_FP8_E4M3>, dim3((unsigned)grid), dim3(256), 0, s, P); break;
+      case GEM_F32:
+        if (codes) hipLaunchKernelGGL((score_gather_kernel<GEM_F32, true>), gr, blk, 0, s, P);
+        else hipLaunchKernelGGL((score_gather_kernel<GEM_F32, false>), gr, blk, 0, s, P);
+        break;
+      case GEM_BF16:
+        if (codes) hipLaunchKernelGGL((score_gather_kernel<GEM_BF16, true>), gr, blk, 0, s, P);
+        else hipLaunchKernelGGL((score_gather_kernel<GEM_BF16, false>), gr, blk, 0, s, P);
+        break;
+      case GEM_FP8_E4M3:
+        if (codes) hipLaunchKernelGGL((score_gather_kernel<GEM_FP8_E4M3, true>), gr, blk, 0, s, P);
+        else hipLaunchKernelGGL((score_gather_kernel<GEM_FP8_E4M3, false>), gr, blk, 0, s, P);
+        break;
       default: return hipErrorInvalidValue;
     }
     const hipError_t e = hipGetLastError();
