@@ -56,6 +56,39 @@ def timed(fn, reps: int, stream=None):
     return e0.elapsed_time(e1) / reps
 
 
+def timed_once(fn, stream=None):
+    """(milliseconds, result) of one call of fn(), from HIP events on the current stream."""
+    s = torch.cuda.current_stream() if stream is None else stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    out = fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1), out
+
+
+def build_codebook(D32, n_iter: int, assign: str, seed: int, per_centroid: int = 64):
+    """C_quant for a corpus: k-means (Lloyd, n_iter rounds) on a seeded sample of
+    per_centroid rows per centroid, from seeded initial rows; then every corpus
+    vector's code. Returns (codebook, code sets, timings)."""
+    dev = D32.device
+    V = D32.n_vecs
+    k1 = gem.codebook_size(V)
+    n_sample = min(V, per_centroid * k1)
+    rng = np.random.default_rng(seed)
+    rows = torch.from_numpy(np.sort(rng.choice(V, n_sample, replace=False)).astype(np.int64)).to(dev)
+    xs = torch.empty(n_sample, 128, dtype=torch.float32, device=dev)
+    gem.copy_rows(D32.vecs, xs, src_idx=rows)
+    init = torch.from_numpy(rng.choice(n_sample, k1, replace=False).astype(np.int64))
+    t_km, C = timed_once(lambda: gem.kmeans(xs, init, n_iter, assign=assign))
+    del xs
+    t_enc, Dc = timed_once(lambda: gem.encode(D32, C, assign=assign))
+    info = {"codebook_size": k1, "kmeans_sample_rows": n_sample, "kmeans_iters": n_iter, "assign": assign,
+            "kmeans_ms": t_km, "encode_corpus_ms": t_enc,
+            "encode_tflops": 2.0 * 128 * V * k1 / (t_enc / 1e3) / 1e12}
+    return C, Dc, info
+
+
 def cpu_baseline(q: wl.SetBatch, c: wl.SetBatch, n_sample: int):
     """The float64 oracle on a bounded sample of queries against the whole corpus."""
     import oracle
@@ -206,6 +239,45 @@ def bench_exhaustive(args):
     t_fp8_score = timed(lambda: gem.score_quant(Q8, D8, scores=est), max(1, args.steps))
     log(f"fp8 estimate + rerank path {t_fp8_path:.2f} ms (fp8 scoring {t_fp8_score:.2f} ms)")
 
+    # qCH (Sec. 4.5): every vector replaced by its nearest centroid of the
+    # k-means codebook (Secs. 4.1, 4.2); estimate -> top-1000 -> f32 rerank
+    log("qCH: k-means codebook and corpus codes")
+    C, Dc, qch = build_codebook(D32, n_iter=8, assign="f32", seed=7)
+    qch_top = {}
+    for cdt in ("bf16", "fp8"):
+        Dcc = Dc.to_bf16() if cdt == "bf16" else Dc.to_fp8()
+
+        def qch_path(Dcc=Dcc, cdt=cdt):
+            Qc = gem.encode(Q, C, assign="f32")                        # NN(q) of every query vector
+            Qcc = Qc.to_bf16() if cdt == "bf16" else Qc.to_fp8()
+            if cdt == "bf16":
+                gem.score_exact(Qcc, Dcc, compute="bf16", scores=est)
+            else:
+                gem.score_quant(Qcc, Dcc, scores=est)
+            _, short_i = gem.topk(est, sl)
+            Cs = gem.Cands(short_i.reshape(-1), stride=sl, n_lists=n_q)
+            return gem.score_exact(Q, D32, cands=Cs, compute="f32", k=k)
+
+        qch_top[cdt] = qch_path()
+        torch.cuda.synchronize()
+        t_path = timed(qch_path, max(1, args.steps // 2))
+        Qc = gem.encode(Q, C, assign="f32")
+        Qcc = Qc.to_bf16() if cdt == "bf16" else Qc.to_fp8()
+        t_enc_q = timed(lambda: gem.encode(Q, C, assign="f32"), max(1, args.steps // 2))
+        if cdt == "bf16":
+            t_sc = timed(lambda: gem.score_exact(Qcc, Dcc, compute="bf16", scores=est), max(1, args.steps // 2))
+        else:
+            t_sc = timed(lambda: gem.score_quant(Qcc, Dcc, scores=est), max(1, args.steps // 2))
+        peak = PEAK_BF16 if cdt == "bf16" else PEAK_FP8
+        qch[cdt] = {"path_ms": t_path, "query_encode_ms": t_enc_q, "score_ms": t_sc,
+                    "score_frac_of_peak": flops / (t_sc / 1e3) / peak,
+                    "pair_scores_per_s": pairs / (t_path / 1e3), "speedup_vs_f32_path": t_f32 / t_path}
+        log(f"qCH {cdt}: path {t_path:.2f} ms (query codes {t_enc_q:.2f}, scoring {t_sc:.2f})")
+    qch["corpus_code_bytes"] = D32.n_vecs * 4
+    qch["codebook_bytes_bf16"] = qch["codebook_size"] * 256
+    qch["shortlist"] = sl
+    qch_q8 = qch_top
+
     # accuracy on a sample of queries against float64 exact scores (CPU oracle)
     c_host = wl.SetBatch(c_dev.vecs.cpu(), c_dev.offsets.cpu())
     q_host = wl.SetBatch(q_dev.vecs.cpu(), q_dev.offsets.cpu())
@@ -219,6 +291,8 @@ def bench_exhaustive(args):
         res["recall_at_100_bf16"] = recall_vs_exact(top_i[:ns].cpu().numpy(), ref, k)
         res["recall_at_100_f32"] = recall_vs_exact(top32_i[:ns].cpu().numpy(), ref, k)
         res["recall_at_100_fp8_rerank"] = recall_vs_exact(r8_i[:ns].cpu().numpy(), ref, k)
+        for cdt, (_, qi) in qch_q8.items():
+            qch[cdt]["recall_at_100_rerank"] = recall_vs_exact(qi[:ns].cpu().numpy(), ref, k)
         est_np = est[:ns].double().cpu().numpy()
         res["fp8_estimate_rel_err_p50"] = float(np.median(np.abs(est_np - ref) / np.maximum(np.abs(ref), 1)))
         res["recall_sample_queries"] = ns
@@ -251,6 +325,7 @@ def bench_exhaustive(args):
                             "fp8_score_ms": t_fp8_score,
                             "fp8_tflops": flops / (t_fp8_score / 1e3) / 1e12,
                             "fp8_frac_of_peak": flops / (t_fp8_score / 1e3) / PEAK_FP8},
+        "qch_rerank_path": qch,
     }
     line.update(res)
     if "cpu_baseline" not in line:
@@ -318,6 +393,29 @@ def bench_expansion(args):
            "gbps_unique_bytes": uniq_bytes / w4.steps / (per_step / 1e3) / 1e9,
            "frac_of_hbm_peak_per_pair": pair_bytes / w4.steps / (per_step / 1e3) / PEAK_HBM,
            "rerank_f32_top100_ms": r_ms}
+    # qCH expansion: the same steps with the corpus and the queries as codes
+    # over an FP8 codebook (Secs. 4.2, 4.5): 4 bytes of code per vector
+    # instead of its 132-byte FP8 row; the centroid rows are few enough to
+    # stay in the caches
+    log("expansion qCH: k-means codebook and corpus codes")
+    C, Dc, qinfo = build_codebook(D32, n_iter=4, assign="bf16", seed=11, per_centroid=32)
+    Dc8 = Dc.to_fp8()
+    t_qenc, Qc = timed_once(lambda: gem.encode(Q32, C, assign="f32"))
+    Qc8 = Qc.to_fp8()
+    egq = ExpansionGraph(Qc8, Dc8, steps, ef=w4.ef)
+    egq.capture()
+    egq.replay()
+    torch.cuda.synchronize()
+    ms_q = timed(egq.replay, 3)
+    a, b = eg.beam.ids.cpu().numpy(), egq.beam.ids.cpu().numpy()
+    overlap = np.mean([np.intersect1d(a[i][a[i] >= 0], b[i][b[i] >= 0]).size / w4.ef for i in range(a.shape[0])])
+    qinfo.update({"ms_per_step": ms_q / w4.steps, "speedup_vs_fp8_rows": per_step / (ms_q / w4.steps),
+                  "query_encode_ms": t_qenc, "pair_scores_per_s": pairs / (ms_q / 1e3),
+                  "code_bytes_per_step": pair_bytes / 132 * 4 / w4.steps,
+                  "beam_overlap_with_fp8_rows": float(overlap)})
+    res["qch"] = qinfo
+    log(f"qCH expansion {ms_q / w4.steps:.3f} ms/step (FP8 rows {per_step:.3f})")
+    del egq, Dc8, Dc, Qc8, Qc, C
     if not args.skip_cpu:
         # beam of a query subset against the oracle's replay of the same candidate lists
         import oracle

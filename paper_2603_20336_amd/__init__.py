@@ -12,6 +12,7 @@ and allocates outputs and workspaces with torch's allocator.
 from __future__ import annotations
 
 import ctypes
+import math
 from typing import Optional
 
 import torch
@@ -23,7 +24,7 @@ __all__ = ["Sets", "Cands", "Beam", "GemError", "convert_bf16", "quantize_fp8", 
            "score_quant", "topk", "expand_batch", "beam_merge", "beam_reset", "validate_sets", "validate_cands",
            "library", "GEM_F32", "GEM_BF16", "GEM_FP8_E4M3", "GEM_MAX_K", "GEM_MAX_QUERY_LEN", "dense_schedule",
            "set_dense_schedule", "autotune_dense", "copy_rows", "nearest_centroid", "centroid_update",
-           "kmeans", "encode"]
+           "kmeans", "encode", "codebook_size"]
 
 _DTYPES = {"f32": GEM_F32, "bf16": GEM_BF16, "fp8": GEM_FP8_E4M3,
            GEM_F32: GEM_F32, GEM_BF16: GEM_BF16, GEM_FP8_E4M3: GEM_FP8_E4M3}
@@ -265,6 +266,11 @@ def _rows(x: torch.Tensor, what: str) -> int:
     if x.dim() != 2 or x.shape[1] != _abi.GEM_DIM or not x.is_contiguous():
         raise ValueError(f"{what} must be a contiguous [n, 128] tensor")
     return int(x.shape[0])
+
+
+def codebook_size(n_vectors: int) -> int:
+    """|C_quant| of Sec. 5.1: the power of two 2^floor(log2(16 sqrt(n_vectors)))."""
+    return 1 << int(math.floor(math.log2(16.0 * math.sqrt(max(1, n_vectors)))))
 
 
 def nearest_centroid(x: torch.Tensor, centroids: torch.Tensor, stream=None) -> torch.Tensor:
