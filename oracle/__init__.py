@@ -10,6 +10,8 @@ path computes, written from the paper (GEM, arXiv 2603.20336):
   * Recall@k, Sec. 5.1 "Evaluation Metrics"
   * the centroid codebook C_quant (k-means, Sec. 4.1), the nearest-centroid map
     NN (Sec. 4.2) and the quantized Chamfer estimate qCH (Sec. 4.5, Eq. qCH)
+  * the cluster-guided beam search of Alg. 5 (Sec. 4.5) with the TF-IDF
+    set-level clustering of Sec. 4.1, in a batched reading
   * MXFP4 (OCP Microscaling, E2M1 elements with one power-of-two scale per
     32-element block), the ultra-low-bit estimate the paper names as future
     work (Sec. 6)
@@ -30,6 +32,8 @@ from .chamfer import (ch_pair, ch_dense, ch_cands, topk_rows, topk_segments, bea
                       beam_replay, recall_at_k, tie_aware_match)
 from .codebook import (codebook_size, sq_distances, nn_assign, lloyd_update, kmeans, kmeans_objective,
                        qch_pair, qch_dense, qch_cands)
+from .search import (tfidf_top_clusters, cluster_members, query_clusters, entry_points, beam_search,
+                     ch_scorer)
 from .mx import e2m1_decode, e2m1_table, e2m1_encode, block_exponent, quantize_mxfp4, dequantize_mxfp4
 from .codecs import (bf16_round_bits, bf16_decode, e4m3_decode, e4m3_decode_table,
                      e4m3_encode, pow2_scale, quantize_fp8, dequantize_fp8)
@@ -41,5 +45,6 @@ __all__ = [
     "pow2_scale", "quantize_fp8", "dequantize_fp8",
     "codebook_size", "sq_distances", "nn_assign", "lloyd_update", "kmeans", "kmeans_objective",
     "qch_pair", "qch_dense", "qch_cands",
+    "tfidf_top_clusters", "cluster_members", "query_clusters", "entry_points", "beam_search", "ch_scorer",
     "e2m1_decode", "e2m1_table", "e2m1_encode", "block_exponent", "quantize_mxfp4", "dequantize_mxfp4",
 ]
