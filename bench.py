@@ -36,6 +36,7 @@ from paper_2603_20336_amd import workloads as wl  # noqa: E402
 
 PEAK_BF16 = 2.5e15
 PEAK_FP8 = 5.0e15
+PEAK_FP4 = 10.1e15
 PEAK_FP32_MATRIX = 157.3e12
 PEAK_HBM = 8.0e12
 
@@ -239,6 +240,26 @@ def bench_exhaustive(args):
     t_fp8_score = timed(lambda: gem.score_quant(Q8, D8, scores=est), max(1, args.steps))
     log(f"fp8 estimate + rerank path {t_fp8_path:.2f} ms (fp8 scoring {t_fp8_score:.2f} ms)")
 
+    # MXFP4 estimate (E2M1 codes, a power-of-two scale per 32 dims) -> top-1000
+    # -> f32 rerank -> top-100: half the bytes and twice the MFMA rate of FP8
+    D4 = gem.quantize_mxfp4(D32)
+    Q4 = gem.quantize_mxfp4(Q)
+    sched["mxfp4"], _ = gem.autotune_dense(Q4, D4, reps=2, scores=est)
+
+    def mx_path():
+        q4 = gem.quantize_mxfp4(Q)
+        gem.score_quant(q4, D4, scores=est)
+        _, short_i = gem.topk(est, sl)
+        C = gem.Cands(short_i.reshape(-1), stride=sl, n_lists=n_q)
+        return gem.score_exact(Q, D32, cands=C, compute="f32", k=k)
+
+    r4_s, r4_i = mx_path()
+    torch.cuda.synchronize()
+    t_mx_path = timed(mx_path, max(1, args.steps))
+    t_mx_score = timed(lambda: gem.score_quant(Q4, D4, scores=est), max(1, args.steps))
+    log(f"mxfp4 estimate + rerank path {t_mx_path:.2f} ms (mxfp4 scoring {t_mx_score:.2f} ms)")
+    del D4, Q4
+
     # qCH (Sec. 4.5): every vector replaced by its nearest centroid of the
     # k-means codebook (Secs. 4.1, 4.2); estimate -> top-1000 -> f32 rerank
     log("qCH: k-means codebook and corpus codes")
@@ -291,6 +312,7 @@ def bench_exhaustive(args):
         res["recall_at_100_bf16"] = recall_vs_exact(top_i[:ns].cpu().numpy(), ref, k)
         res["recall_at_100_f32"] = recall_vs_exact(top32_i[:ns].cpu().numpy(), ref, k)
         res["recall_at_100_fp8_rerank"] = recall_vs_exact(r8_i[:ns].cpu().numpy(), ref, k)
+        res["recall_at_100_mxfp4_rerank"] = recall_vs_exact(r4_i[:ns].cpu().numpy(), ref, k)
         for cdt, (_, qi) in qch_q8.items():
             qch[cdt]["recall_at_100_rerank"] = recall_vs_exact(qi[:ns].cpu().numpy(), ref, k)
         est_np = est[:ns].double().cpu().numpy()
@@ -325,6 +347,12 @@ def bench_exhaustive(args):
                             "fp8_score_ms": t_fp8_score,
                             "fp8_tflops": flops / (t_fp8_score / 1e3) / 1e12,
                             "fp8_frac_of_peak": flops / (t_fp8_score / 1e3) / PEAK_FP8},
+        "mxfp4_rerank_path": {"ms": t_mx_path, "pair_scores_per_s": pairs / (t_mx_path / 1e3),
+                              "speedup_vs_f32_path": t_f32 / t_mx_path, "shortlist": sl,
+                              "mxfp4_score_ms": t_mx_score,
+                              "mxfp4_tflops": flops / (t_mx_score / 1e3) / 1e12,
+                              "mxfp4_frac_of_peak": flops / (t_mx_score / 1e3) / PEAK_FP4,
+                              "corpus_bytes": V * 68},
         "qch_rerank_path": qch,
     }
     line.update(res)
@@ -343,14 +371,17 @@ def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_
     vecs = q.vecs.numpy()
     reqs = [serve.Request(i, vecs[off[i]:off[i + 1]], float(arrivals[i])) for i in range(n_req)]
     ex = serve.DeviceExecutor(D8, D32, n_chunks=n_chunks, max_slots=1024, shortlist=w5.shortlist, k=w5.k)
-    eng = serve.ServingEngine(ex, max_slots=1024, mem_budget_bytes=8 << 30)
+    # an iteration scores as many chunks as fit 8192 (query vectors x chunks)
+    work = 8192
+    eng = serve.ServingEngine(ex, max_slots=1024, mem_budget_bytes=8 << 30, chunk_work=work)
     # warm-up on a few requests, then the measured run
-    warm = serve.ServingEngine(ex, max_slots=1024, mem_budget_bytes=8 << 30)
+    warm = serve.ServingEngine(ex, max_slots=1024, mem_budget_bytes=8 << 30, chunk_work=work)
     warm.run([serve.Request(-1 - i, r.vecs, r.t_arrival) for i, r in enumerate(reqs[:200])])
     torch.cuda.synchronize()
     done = eng.run(reqs)
     st = serve.latency_stats(done)
-    st.update({"rate_per_s": rate, "requests": n_req, "chunks": n_chunks, "iterations": eng.iteration,
+    st.update({"rate_per_s": rate, "requests": n_req, "chunks": n_chunks, "chunk_work": work,
+               "iterations": eng.iteration,
                "mean_active": eng.active_sum / max(1, eng.iteration),
                "shortlist": w5.shortlist, "k": w5.k, "query_len": f"U{{{q_len[1]}..{q_len[2]}}}"})
     return st
@@ -393,6 +424,23 @@ def bench_expansion(args):
            "gbps_unique_bytes": uniq_bytes / w4.steps / (per_step / 1e3) / 1e9,
            "frac_of_hbm_peak_per_pair": pair_bytes / w4.steps / (per_step / 1e3) / PEAK_HBM,
            "rerank_f32_top100_ms": r_ms}
+    # MXFP4 rows: 64 bytes of codes + 4 exponent bytes per vector
+    D4 = gem.quantize_mxfp4(D32)
+    Q4 = gem.quantize_mxfp4(Q32)
+    eg4 = ExpansionGraph(Q4, D4, steps, ef=w4.ef)
+    eg4.capture()
+    eg4.replay()
+    torch.cuda.synchronize()
+    ms4 = timed(eg4.replay, 3)
+    b4 = eg4.beam.ids.cpu().numpy()
+    a8 = eg.beam.ids.cpu().numpy()
+    ov4 = np.mean([np.intersect1d(a8[i][a8[i] >= 0], b4[i][b4[i] >= 0]).size / w4.ef for i in range(a8.shape[0])])
+    res["mxfp4"] = {"ms_per_step": ms4 / w4.steps, "speedup_vs_fp8_rows": per_step / (ms4 / w4.steps),
+                    "gbps_per_pair_bytes": pair_bytes / 132 * 68 / w4.steps / (ms4 / w4.steps / 1e3) / 1e9,
+                    "pair_scores_per_s": pairs / (ms4 / 1e3), "beam_overlap_with_fp8_rows": float(ov4)}
+    log(f"mxfp4 expansion {ms4 / w4.steps:.3f} ms/step")
+    del eg4, D4, Q4
+
     # qCH expansion: the same steps with the corpus and the queries as codes
     # over an FP8 codebook (Secs. 4.2, 4.5): 4 bytes of code per vector
     # instead of its 132-byte FP8 row; the centroid rows are few enough to

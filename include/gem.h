@@ -63,7 +63,10 @@ typedef enum {
 typedef enum {
   GEM_F32 = 0,               /* float32 rows, 512 bytes per 128-d vector */
   GEM_BF16 = 1,              /* bfloat16 rows (uint16 bit patterns), 256 bytes */
-  GEM_FP8_E4M3 = 2           /* OCP E4M3 codes (uint8), 128 bytes, plus a float32 scale */
+  GEM_FP8_E4M3 = 2,          /* OCP E4M3 codes (uint8), 128 bytes, plus a float32 scale */
+  GEM_MXFP4 = 3              /* OCP MXFP4: E2M1 codes, 64 bytes (element t in byte t/2, the low
+                                nibble for even t), plus 4 E8M0 block exponents (one per 32
+                                elements) per row */
 } gem_dtype;
 
 typedef enum {
@@ -88,8 +91,10 @@ typedef struct gem_ctx_s* gem_ctx;
  *   set i = rows offsets[i] .. offsets[i+1]-1 of `vecs` (absolute row indices,
  *   so a view of sets a..b of a larger batch is {offsets + a, n_sets = b - a}).
  *   vecs: [n_vecs][dim] row-major, element type `dtype`.
- *   scales: FP8 only, [n_vecs] float32; row r's values are scales[r] * decode(code).
+ *   scales: FP8: [n_vecs] float32; row r's values are scales[r] * decode(code).
  *           Scales must be powers of two (gem_quantize_fp8 writes such scales).
+ *           MXFP4: [n_vecs] 32-bit words of 4 E8M0 bytes; byte j of row r's word
+ *           is the exponent e + 127 of the scale 2^e of dims 32j .. 32j + 31.
  *   max_set_len: host-side upper bound of the set lengths (needed for query sets).
  *
  * Code sets (the quantized representation of Secs. 4.2 and 4.5, where every
@@ -204,6 +209,16 @@ gem_status gem_centroid_update(gem_ctx ctx, const float* x, int64_t n_rows, int3
  * GEM_OP_NEAREST_CENTROID or GEM_OP_CENTROID_UPDATE; 0 for anything else). */
 size_t gem_codebook_workspace_bytes(int32_t op, int64_t n_rows, int64_t n_centroids);
 
+/* float32 rows -> OCP MXFP4: per block of 32 consecutive dims, the scale 2^e
+ * with the smallest e in [-127, 127] such that max|x| <= 6 * 2^e (2^0 for an
+ * all-zero block), and each element's E2M1 code of x / 2^e (nearest value,
+ * ties to the even code; zero is code 0). The ultra-low-bit form of the
+ * quantized estimate (named as future work in the paper's conclusion, Sec. 6).
+ *   out: [device] [n_rows * 64] packed codes; exps: [device] [n_rows * 4] E8M0
+ *   bytes (the `scales` of a GEM_MXFP4 set). */
+gem_status gem_quantize_mxfp4(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim, uint8_t* out,
+                              uint8_t* exps, hipStream_t stream);
+
 /* Row copies for assembling batches (a serving loop gathers the active
  * requests' query rows from per-request slots, and writes admitted requests'
  * rows into their slots): for i < n, row (dst_idx ? dst_idx[i] : i) of dst
@@ -234,11 +249,12 @@ gem_status gem_score_exact(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, co
                            float* top_scores, int32_t* top_ids,
                            void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* Quantized estimate: the same outputs as gem_score_exact, computed on FP8 E4M3
- * operands with their per-vector scales (products and float32 accumulation
- * of s_q * s_p * <code_q, code_p>). D->dtype must be GEM_FP8_E4M3. Q is either
- * GEM_FP8_E4M3 with scales, or GEM_F32 and is quantized into the workspace by
- * the rule of gem_quantize_fp8. */
+/* Quantized estimate: the same outputs as gem_score_exact, computed on the
+ * quantized operands of D's format with their scales (products and float32
+ * accumulation of scaled code products): D->dtype is GEM_FP8_E4M3 (a scale per
+ * vector) or GEM_MXFP4 (a scale per 32-element block). Q is either in D's
+ * format, or GEM_F32 and is quantized into the workspace by the rule of
+ * gem_quantize_fp8 / gem_quantize_mxfp4. */
 gem_status gem_score_quant(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C,
                            int32_t k,
                            float* scores, int64_t ld_scores, const int32_t* score_rows,
@@ -258,10 +274,11 @@ gem_status gem_topk(gem_ctx ctx, const float* scores, const int64_t* seg_offsets
                     void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* One batched beam-expansion step (Alg. 5 neighbour loop, all queries at once):
- * estimate CH(Q_i, D_id) with FP8 operands for every entry of list i, then
- * replace beam row i by the best ef of (beam row i) U (scored entries), ids
- * distinct (a repeated id keeps its best entry). D8->dtype must be
- * GEM_FP8_E4M3; Q8 is GEM_FP8_E4M3 or GEM_F32 (quantized into ws). If
+ * estimate CH(Q_i, D_id) with quantized operands for every entry of list i,
+ * then replace beam row i by the best ef of (beam row i) U (scored entries),
+ * ids distinct (a repeated id keeps its best entry). D8->dtype is
+ * GEM_FP8_E4M3 or GEM_MXFP4; Q8 is in D8's format or GEM_F32 (quantized into
+ * ws). If
  * cand_scores is not NULL the step's entry scores are also written there
  * ([C->n_entries]). The beam is updated in place. */
 gem_status gem_expand_batch(gem_ctx ctx, const gem_sets* Q8, const gem_sets* D8, const gem_cands* C,
@@ -284,6 +301,73 @@ gem_status gem_beam_reset(gem_ctx ctx, gem_beam* beam, int64_t n_queries, hipStr
  * Synchronizes `stream`; returns GEM_ERR_DEVICE_CHECK on a violation. */
 gem_status gem_validate_sets(gem_ctx ctx, const gem_sets* S, hipStream_t stream);
 gem_status gem_validate_cands(gem_ctx ctx, const gem_cands* C, int64_t n_sets, hipStream_t stream);
+
+/* ---------------------------------------------------------------- search
+ * Cluster-guided beam search (Alg. 5, Sec. 4.5) for a batch of queries, over
+ * a graph whose sets carry the set-level clusters of Sec. 4.1. */
+
+/* Set-level clustering with TF-IDF guided pruning (Sec. 4.1): for every set P,
+ * TF(j, P) = its vectors whose cluster is j (vec_clusters[i] in [0, k2): the
+ * nearest C_index centroid, e.g. from gem_nearest_centroid), IDF(j) =
+ * log(N / (1 + sets with TF(j, .) > 0)) in float32, and C_top(P) = the r
+ * clusters with the largest TF * IDF (ties to the smaller cluster; only
+ * clusters P touches). Writes set_masks [n_sets][(k2 + 31) / 32] (bit j of a
+ * mask: cluster j), member_offsets [k2 + 1] and members [<= n_sets * r]: the
+ * sets of each cluster in id order. k2 <= 1024. ws: GEM_SEARCH_CLUSTER_WS
+ * bytes [device]. */
+#define GEM_SEARCH_CLUSTER_WS 8192
+gem_status gem_set_clusters(gem_ctx ctx, const int32_t* vec_clusters, const int64_t* set_offsets, int64_t n_sets,
+                            int32_t k2, int32_t r, uint32_t* set_masks, int64_t* member_offsets, int32_t* members,
+                            void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Cluster filter (Sec. 4.5, S = C Q^T): query_masks row i = the union over
+ * query i's vectors of their top-t centroids by inner product (float32
+ * products, ties to the smaller index). Q: GEM_F32 sets; centroids: [device]
+ * [k2][128] float32 (C_index). */
+gem_status gem_query_clusters(gem_ctx ctx, const gem_sets* Q, const float* centroids, int32_t k2, int32_t t,
+                              uint32_t* query_masks, hipStream_t stream);
+
+/* The graph: neighbour lists plus the outputs of gem_set_clusters. */
+typedef struct {
+  int64_t n_sets;                 /* sets of the graph (the scored document sets) */
+  int32_t k2;                     /* clusters, <= 1024 */
+  int32_t degree;                 /* neighbours per set, <= 64 */
+  const int32_t* neighbors;       /* [device] [n_sets][degree], -1 padded */
+  const uint32_t* set_masks;      /* [device] [n_sets][(k2 + 31) / 32] */
+  const int64_t* member_offsets;  /* [device] [k2 + 1] */
+  const int32_t* members;         /* [device] */
+} gem_graph;
+
+/* One batch's search state, caller-owned device buffers for n_q queries.
+ * cand_ids / cand_scores rows hold max(k2, width * degree) entries. */
+typedef struct {
+  int32_t width;                  /* sets expanded per query and step (w) */
+  int32_t reserved;
+  const uint32_t* query_masks;    /* [n_q][(k2 + 31) / 32] (gem_query_clusters) */
+  uint32_t* visited;              /* [n_q][(n_sets + 31) / 32] */
+  uint32_t* expanded;             /* [n_q][(n_sets + 31) / 32] */
+  int32_t* frontier;              /* [n_q][width] */
+  int32_t* cand_ids;              /* [n_q][row] */
+  float* cand_scores;             /* [n_q][row] */
+  uint32_t* active;               /* [1]: queries that expanded something in the last step */
+} gem_search_state;
+
+/* Start a batch: clears the visited and expanded maps, takes one entry per
+ * cluster of each query's C_query (member floor(u * count / 2^32) of the
+ * cluster, u = random_words[i * k2 + j], drawn by the caller), scores the
+ * entries and makes them the beam (R of Alg. 5; ef <= GEM_MAX_K). Scores are
+ * CH in D's dtype (the estimate for FP8 / MXFP4 sets, qCH for code sets); Q
+ * must already be in D's dtype. */
+gem_status gem_search_begin(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_graph* G,
+                            gem_search_state* S, const uint32_t* random_words, gem_beam* beam, hipStream_t stream);
+
+/* One step for every query: the w best entries of R not yet expanded are
+ * expanded; their neighbours that are unvisited and share a cluster with
+ * C_query are marked visited, scored and merged into R. *S->active (device)
+ * counts the queries that still had something to expand; the batch is done
+ * when it reads 0. */
+gem_status gem_search_step(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_graph* G,
+                           gem_search_state* S, gem_beam* beam, hipStream_t stream);
 
 /* Schedule of the exhaustive (dense) scorer: how the work of one call is laid
  * out over the GPU. Persistent workgroups (slots_per_xcd on each of the 8 XCDs)

@@ -18,17 +18,19 @@ from typing import Optional
 import torch
 
 from . import _abi
-from ._abi import (GEM_BF16, GEM_F32, GEM_FP8_E4M3, GEM_MAX_K, GEM_MAX_QUERY_LEN, GemError)
+from ._abi import (GEM_BF16, GEM_F32, GEM_FP8_E4M3, GEM_MAX_K, GEM_MAX_QUERY_LEN, GEM_MXFP4, GemError)
 
 __all__ = ["Sets", "Cands", "Beam", "GemError", "convert_bf16", "quantize_fp8", "score_exact",
            "score_quant", "topk", "expand_batch", "beam_merge", "beam_reset", "validate_sets", "validate_cands",
-           "library", "GEM_F32", "GEM_BF16", "GEM_FP8_E4M3", "GEM_MAX_K", "GEM_MAX_QUERY_LEN", "dense_schedule",
+           "library", "GEM_F32", "GEM_BF16", "GEM_FP8_E4M3", "GEM_MXFP4", "quantize_mxfp4", "GEM_MAX_K", "GEM_MAX_QUERY_LEN", "dense_schedule",
            "set_dense_schedule", "autotune_dense", "copy_rows", "nearest_centroid", "centroid_update",
            "kmeans", "encode", "codebook_size"]
 
-_DTYPES = {"f32": GEM_F32, "bf16": GEM_BF16, "fp8": GEM_FP8_E4M3,
-           GEM_F32: GEM_F32, GEM_BF16: GEM_BF16, GEM_FP8_E4M3: GEM_FP8_E4M3}
-_ROW_TORCH = {GEM_F32: torch.float32, GEM_BF16: torch.uint16, GEM_FP8_E4M3: torch.uint8}
+_DTYPES = {"f32": GEM_F32, "bf16": GEM_BF16, "fp8": GEM_FP8_E4M3, "mxfp4": GEM_MXFP4,
+           GEM_F32: GEM_F32, GEM_BF16: GEM_BF16, GEM_FP8_E4M3: GEM_FP8_E4M3, GEM_MXFP4: GEM_MXFP4}
+_ROW_TORCH = {GEM_F32: torch.float32, GEM_BF16: torch.uint16, GEM_FP8_E4M3: torch.uint8, GEM_MXFP4: torch.uint8}
+_ROW_WIDTH = {GEM_F32: 128, GEM_BF16: 128, GEM_FP8_E4M3: 128, GEM_MXFP4: 64}     # tensor columns per row
+_QUANT = (GEM_FP8_E4M3, GEM_MXFP4)
 
 
 def library():
@@ -68,9 +70,11 @@ def _ctx(device: torch.device) -> ctypes.c_void_p:
 class Sets:
     """A ragged batch of 128-d vector sets on the device (CSR).
 
-    vecs: [n_vecs, 128] float32 / uint16 (bf16 bits) / uint8 (E4M3 codes)
+    vecs: [n_vecs, 128] float32 / uint16 (bf16 bits) / uint8 (E4M3 codes), or
+        [n_vecs, 64] uint8 (MXFP4: two E2M1 codes a byte)
     offsets: [n_sets + 1] int64 absolute row indices
-    scales: FP8 only, [n_vecs] float32 powers of two
+    scales: FP8: [n_vecs] float32 powers of two; MXFP4: [n_vecs, 4] uint8 E8M0
+        block exponents
     max_len: host-side bound of the set lengths
     codes: code sets only, [n_vecs] int32: entry r stands for row codes[r] of
         vecs, which then holds the codebook (its nearest centroid, Sec. 4.2);
@@ -83,8 +87,8 @@ class Sets:
         self.dtype = _DTYPES[dtype]
         if vecs.dtype != _ROW_TORCH[self.dtype]:
             raise TypeError(f"vecs dtype {vecs.dtype} does not match gem dtype {self.dtype}")
-        if vecs.dim() != 2 or vecs.shape[1] != _abi.GEM_DIM or not vecs.is_contiguous():
-            raise ValueError("vecs must be a contiguous [n, 128] tensor")
+        if vecs.dim() != 2 or vecs.shape[1] != _ROW_WIDTH[self.dtype] or not vecs.is_contiguous():
+            raise ValueError(f"vecs must be a contiguous [n, {_ROW_WIDTH[self.dtype]}] tensor")
         if offsets.dtype != torch.int64 or not offsets.is_contiguous():
             raise TypeError("offsets must be contiguous int64")
         if codes is not None and (codes.dtype != torch.int32 or codes.dim() != 1 or not codes.is_contiguous()):
@@ -126,6 +130,9 @@ class Sets:
 
     def to_fp8(self, stream=None) -> "Sets":
         return quantize_fp8(self, stream)
+
+    def to_mxfp4(self, stream=None) -> "Sets":
+        return quantize_mxfp4(self, stream)
 
 
 class Cands:
@@ -199,6 +206,18 @@ def quantize_fp8(S: Sets, stream=None) -> Sets:
     _abi.check(library().gem_quantize_fp8(_ctx(S.device), _ptr(S.vecs), n, _abi.GEM_DIM,
                                           _ptr(out), _ptr(sc), _stream(stream)))
     return Sets(out, S.offsets, GEM_FP8_E4M3, S.max_len, scales=sc, n_sets=S.n_sets, codes=S.codes)
+
+
+def quantize_mxfp4(S: Sets, stream=None) -> Sets:
+    """float32 sets -> MXFP4: E2M1 codes with one power-of-two scale per 32-element block."""
+    if S.dtype != GEM_F32:
+        raise TypeError("quantize_mxfp4 takes float32 sets")
+    n = int(S.vecs.shape[0])                       # (a code set converts its codebook)
+    out = torch.empty(n, 64, dtype=torch.uint8, device=S.device)
+    ex = torch.empty(n, 4, dtype=torch.uint8, device=S.device)
+    _abi.check(library().gem_quantize_mxfp4(_ctx(S.device), _ptr(S.vecs), n, _abi.GEM_DIM, _ptr(out), _ptr(ex),
+                                            _stream(stream)))
+    return Sets(out, S.offsets, GEM_MXFP4, S.max_len, scales=ex, n_sets=S.n_sets, codes=S.codes)
 
 
 def _score(fn_exact: bool, Q: Sets, D: Sets, cands: Optional[Cands], k: int, compute: int,
@@ -379,7 +398,7 @@ def autotune_dense(Q: Sets, D: Sets, compute=None, reps: int = 2, scores: Option
     if scores is None:
         scores = torch.empty(Q.n_sets, D.n_sets, dtype=torch.float32, device=dev)
     qs, ds = Q.struct(), D.struct()
-    op = _abi.GEM_OP_SCORE_QUANT if compute == GEM_FP8_E4M3 else _abi.GEM_OP_SCORE_EXACT
+    op = _abi.GEM_OP_SCORE_QUANT if compute in _QUANT else _abi.GEM_OP_SCORE_EXACT
     need = library().gem_workspace_bytes(_ctx(dev), op, ctypes.byref(qs), ctypes.byref(ds), None, compute, 0, 1)
     ws = _ws(need, dev)
     best = _abi.gem_dense_schedule()
@@ -393,8 +412,10 @@ def autotune_dense(Q: Sets, D: Sets, compute=None, reps: int = 2, scores: Option
 def score_quant(Q: Sets, D8: Sets, cands: Optional[Cands] = None, k: int = 0,
                 scores: Optional[torch.Tensor] = None, ld: int = 0, rows: Optional[torch.Tensor] = None,
                 want_scores: bool = False, stream=None, ws: Optional[torch.Tensor] = None):
-    """Quantized estimate on FP8 E4M3 operands (same conventions as score_exact)."""
-    return _score(False, Q, D8, cands, k, GEM_FP8_E4M3, scores, ld, rows, want_scores, stream, ws)
+    """Quantized estimate in D8's format, FP8 E4M3 or MXFP4 (same conventions as score_exact)."""
+    if D8.dtype not in _QUANT:
+        raise TypeError("score_quant takes FP8 or MXFP4 documents")
+    return _score(False, Q, D8, cands, k, D8.dtype, scores, ld, rows, want_scores, stream, ws)
 
 
 def topk(scores: torch.Tensor, k: int, seg_offsets: Optional[torch.Tensor] = None,
@@ -429,7 +450,7 @@ def expand_batch(Q8: Sets, D8: Sets, cands: Cands, beam: Beam, cand_scores: Opti
     dev = D8.device
     qs, ds, cs, bs = Q8.struct(), D8.struct(), cands.struct(), beam.struct()
     need = lib.gem_workspace_bytes(_ctx(dev), _abi.GEM_OP_EXPAND, ctypes.byref(qs), ctypes.byref(ds),
-                                   ctypes.byref(cs), GEM_FP8_E4M3, 1, int(cand_scores is not None))
+                                   ctypes.byref(cs), D8.dtype, 1, int(cand_scores is not None))
     if ws is None or ws.numel() < need:
         ws = _ws(need, dev)
     _abi.check(lib.gem_expand_batch(_ctx(dev), ctypes.byref(qs), ctypes.byref(ds), ctypes.byref(cs),
@@ -447,7 +468,7 @@ def beam_merge(cand_scores: torch.Tensor, cands: Cands, beam: Beam, stream=None)
 def expand_workspace_bytes(Q8: Sets, D8: Sets, cands: Cands, with_cand_scores: bool) -> int:
     qs, ds, cs = Q8.struct(), D8.struct(), cands.struct()
     return int(library().gem_workspace_bytes(_ctx(D8.device), _abi.GEM_OP_EXPAND, ctypes.byref(qs),
-                                             ctypes.byref(ds), ctypes.byref(cs), GEM_FP8_E4M3, 1,
+                                             ctypes.byref(ds), ctypes.byref(cs), D8.dtype, 1,
                                              int(with_cand_scores)))
 
 

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgem.so")
 
 GEM_OK, GEM_ERR_INVALID, GEM_ERR_WORKSPACE, GEM_ERR_UNSUPPORTED, GEM_ERR_HIP, GEM_ERR_DEVICE_CHECK = range(6)
-GEM_F32, GEM_BF16, GEM_FP8_E4M3 = 0, 1, 2
+GEM_F32, GEM_BF16, GEM_FP8_E4M3, GEM_MXFP4 = 0, 1, 2, 3
 GEM_OP_SCORE_EXACT, GEM_OP_SCORE_QUANT, GEM_OP_TOPK, GEM_OP_EXPAND = 0, 1, 2, 3
 GEM_OP_NEAREST_CENTROID, GEM_OP_CENTROID_UPDATE = 4, 5
 GEM_MAX_QUERY_LEN = 256
@@ -48,6 +48,18 @@ class gem_dense_schedule(ctypes.Structure):
     _fields_ = [("chunk_docs", i32), ("items_per_slot", i32), ("slots_per_xcd", i32), ("reserved", i32)]
 
 
+class gem_graph(ctypes.Structure):
+    _fields_ = [("n_sets", i64), ("k2", i32), ("degree", i32), ("neighbors", c_p), ("set_masks", c_p),
+                ("member_offsets", c_p), ("members", c_p)]
+
+
+class gem_search_state(ctypes.Structure):
+    _fields_ = [("width", i32), ("reserved", i32), ("query_masks", c_p), ("visited", c_p), ("expanded", c_p),
+                ("frontier", c_p), ("cand_ids", c_p), ("cand_scores", c_p), ("active", c_p)]
+
+
+GEM_SEARCH_CLUSTER_WS = 8192
+
 P_SETS = ctypes.POINTER(gem_sets)
 P_CANDS = ctypes.POINTER(gem_cands)
 P_BEAM = ctypes.POINTER(gem_beam)
@@ -61,6 +73,7 @@ SIGNATURES = {
     "gem_workspace_bytes": (sz, [c_p, i32, P_SETS, P_SETS, P_CANDS, i32, i32, i32]),
     "gem_convert_bf16": (i32, [c_p, c_p, i64, i32, c_p, c_p]),
     "gem_quantize_fp8": (i32, [c_p, c_p, i64, i32, c_p, c_p, c_p]),
+    "gem_quantize_mxfp4": (i32, [c_p, c_p, i64, i32, c_p, c_p, c_p]),
     "gem_score_exact": (i32, [c_p, P_SETS, P_SETS, P_CANDS, i32, i32, c_p, i64, c_p, c_p, c_p, c_p, sz, c_p]),
     "gem_score_quant": (i32, [c_p, P_SETS, P_SETS, P_CANDS, i32, c_p, i64, c_p, c_p, c_p, c_p, sz, c_p]),
     "gem_topk": (i32, [c_p, c_p, c_p, c_p, i64, i64, i64, c_p, i32, c_p, c_p, c_p, sz, c_p]),
@@ -73,6 +86,12 @@ SIGNATURES = {
     "gem_nearest_centroid": (i32, [c_p, c_p, i64, c_p, i64, i32, i32, c_p, c_p, sz, c_p]),
     "gem_centroid_update": (i32, [c_p, c_p, i64, i32, c_p, c_p, i64, c_p, c_p, c_p, sz, c_p]),
     "gem_codebook_workspace_bytes": (sz, [i32, i64, i64]),
+    "gem_set_clusters": (i32, [c_p, c_p, c_p, i64, i32, i32, c_p, c_p, c_p, c_p, sz, c_p]),
+    "gem_query_clusters": (i32, [c_p, P_SETS, c_p, i32, i32, c_p, c_p]),
+    "gem_search_begin": (i32, [c_p, P_SETS, P_SETS, ctypes.POINTER(gem_graph), ctypes.POINTER(gem_search_state),
+                               c_p, P_BEAM, c_p]),
+    "gem_search_step": (i32, [c_p, P_SETS, P_SETS, ctypes.POINTER(gem_graph), ctypes.POINTER(gem_search_state),
+                              P_BEAM, c_p]),
     "gem_get_dense_schedule": (i32, [c_p, i32, i64, i64, ctypes.POINTER(gem_dense_schedule)]),
     "gem_set_dense_schedule": (i32, [c_p, i32, i64, i64, ctypes.POINTER(gem_dense_schedule)]),
     "gem_autotune_dense": (i32, [c_p, P_SETS, P_SETS, i32, c_p, i64, c_p, sz, c_p, i32,

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -50,11 +51,15 @@ int row_bytes(int dtype) {
     case GEM_F32: return 4 * GEM_DIM;
     case GEM_BF16: return 2 * GEM_DIM;
     case GEM_FP8_E4M3: return GEM_DIM;
+    case GEM_MXFP4: return GEM_DIM / 2;
     default: return 0;
   }
 }
 
-bool valid_dtype(int32_t d) { return d == GEM_F32 || d == GEM_BF16 || d == GEM_FP8_E4M3; }
+bool valid_dtype(int32_t d) { return d == GEM_F32 || d == GEM_BF16 || d == GEM_FP8_E4M3 || d == GEM_MXFP4; }
+// Formats that carry a 32-bit scale word per row.
+bool scaled_dtype(int32_t d) { return d == GEM_FP8_E4M3 || d == GEM_MXFP4; }
+bool quant_dtype(int32_t d) { return d == GEM_FP8_E4M3 || d == GEM_MXFP4; }
 
 gem_status check_sets(const gem_sets* S, const char* name, bool need_max_len) {
   if (!S) return fail(GEM_ERR_INVALID, "%s is NULL", name);
@@ -64,8 +69,8 @@ gem_status check_sets(const gem_sets* S, const char* name, bool need_max_len) {
   if (S->n_sets > INT32_MAX - 1) return fail(GEM_ERR_UNSUPPORTED, "%s: more than 2^31-2 sets", name);
   if (S->n_sets > 0 && !S->offsets) return fail(GEM_ERR_INVALID, "%s: offsets is NULL", name);
   if (S->n_vecs > 0 && !S->vecs) return fail(GEM_ERR_INVALID, "%s: vecs is NULL", name);
-  if (S->dtype == GEM_FP8_E4M3 && S->n_vecs > 0 && !S->scales)
-    return fail(GEM_ERR_INVALID, "%s: FP8 sets need scales", name);
+  if (scaled_dtype(S->dtype) && S->n_vecs > 0 && !S->scales)
+    return fail(GEM_ERR_INVALID, "%s: FP8 and MXFP4 sets need scales", name);
   if (S->max_set_len < 0) return fail(GEM_ERR_INVALID, "%s: negative max_set_len", name);
   if (need_max_len && S->max_set_len > GEM_MAX_QUERY_LEN)
     return fail(GEM_ERR_UNSUPPORTED, "%s: max_set_len %d exceeds %d", name, S->max_set_len, GEM_MAX_QUERY_LEN);
@@ -75,8 +80,8 @@ gem_status check_sets(const gem_sets* S, const char* name, bool need_max_len) {
     if (S->codebook_rows <= 0 && S->n_vecs > 0) return fail(GEM_ERR_INVALID, "%s: code set with an empty codebook", name);
     if (S->codebook_rows > INT32_MAX) return fail(GEM_ERR_UNSUPPORTED, "%s: codebook of more than 2^31-1 rows", name);
     if (S->codebook_rows > 0 && !S->vecs) return fail(GEM_ERR_INVALID, "%s: codebook (vecs) is NULL", name);
-    if (S->dtype == GEM_FP8_E4M3 && S->codebook_rows > 0 && !S->scales)
-      return fail(GEM_ERR_INVALID, "%s: FP8 codebook needs scales", name);
+    if (scaled_dtype(S->dtype) && S->codebook_rows > 0 && !S->scales)
+      return fail(GEM_ERR_INVALID, "%s: FP8 and MXFP4 codebooks need scales", name);
   } else if (S->codebook_rows != 0) {
     return fail(GEM_ERR_INVALID, "%s: codebook_rows set without codes", name);
   }
@@ -130,7 +135,7 @@ ScoreLayout score_layout(const gem_sets* Q, const gem_sets* D, const gem_cands* 
   if (Q->dtype != compute) {
     L.q_conv = off;
     off = align_up(off + (size_t)vec_rows(Q) * row_bytes(compute));
-    if (compute == GEM_FP8_E4M3) {
+    if (scaled_dtype(compute)) {
       L.q_scales = off;
       off = align_up(off + (size_t)vec_rows(Q) * 4);
     }
@@ -166,6 +171,11 @@ gem_status convert_query(const gem_sets* Q, int32_t compute, void* ws, const Sco
   if (compute == GEM_BF16) {
     e = launch_convert_bf16(static_cast<const float*>(Q->vecs), vec_rows(Q) * GEM_DIM,
                             reinterpret_cast<uint16_t*>(at(ws, L.q_conv)), stream);
+  } else if (compute == GEM_MXFP4) {
+    e = launch_quantize_mxfp4(static_cast<const float*>(Q->vecs), vec_rows(Q),
+                              reinterpret_cast<uint8_t*>(at(ws, L.q_conv)),
+                              reinterpret_cast<uint8_t*>(at(ws, L.q_scales)), stream);
+    Qc->scales = reinterpret_cast<const float*>(at(ws, L.q_scales));
   } else {
     e = launch_quantize_fp8(static_cast<const float*>(Q->vecs), vec_rows(Q), reinterpret_cast<uint8_t*>(at(ws, L.q_conv)),
                             reinterpret_cast<float*>(at(ws, L.q_scales)), stream);
@@ -292,6 +302,16 @@ __global__ void validate_ids_kernel(const int32_t* ids, int64_t n, int64_t n_set
     if (ids[i] >= n_sets) atomicAdd(&g_validate_bad, 1ull);
 }
 
+// E8M0 byte 0xFF is NaN: no block scale may use it.
+__global__ void validate_mx_exps_kernel(const uint32_t* w, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const uint32_t v = w[i];
+    bool bad = false;
+    for (int b = 0; b < 4; ++b) bad |= ((v >> (8 * b)) & 0xffu) == 0xffu;
+    if (bad) atomicAdd(&g_validate_bad, 1ull);
+  }
+}
+
 __global__ void validate_codes_kernel(const int32_t* codes, int64_t n, int64_t n_rows) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
     if (codes[i] < 0 || codes[i] >= n_rows) atomicAdd(&g_validate_bad, 1ull);
@@ -369,12 +389,13 @@ size_t gem_workspace_bytes(gem_ctx ctx, int32_t op, const gem_sets* Q, const gem
     case GEM_OP_SCORE_EXACT:
     case GEM_OP_SCORE_QUANT: {
       if (!D) return 0;
-      const int32_t cd = op == GEM_OP_SCORE_QUANT ? (int32_t)GEM_FP8_E4M3 : compute;
+      const int32_t cd = op == GEM_OP_SCORE_QUANT ? (D->dtype == GEM_MXFP4 ? (int32_t)GEM_MXFP4 : (int32_t)GEM_FP8_E4M3)
+                                                  : compute;
       return score_layout(Q, D, C, cd, k, scores_given != 0).total;
     }
     case GEM_OP_EXPAND: {
       if (!D || !C) return 0;
-      return score_layout(Q, D, C, GEM_FP8_E4M3, 1, scores_given != 0).total;
+      return score_layout(Q, D, C, D->dtype == GEM_MXFP4 ? GEM_MXFP4 : GEM_FP8_E4M3, 1, scores_given != 0).total;
     }
     default:
       return 0;
@@ -399,6 +420,16 @@ gem_status gem_quantize_fp8(gem_ctx ctx, const float* x, int64_t n_rows, int32_t
   if (n_rows > 0 && (!x || !out || !scales)) return fail(GEM_ERR_INVALID, "NULL buffer");
   hipError_t e = launch_quantize_fp8(x, n_rows, out, scales, stream);
   return e == hipSuccess ? GEM_OK : hip_fail(e, "fp8 quantization");
+}
+
+gem_status gem_quantize_mxfp4(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim, uint8_t* out, uint8_t* exps,
+                              hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (dim != GEM_DIM) return fail(GEM_ERR_UNSUPPORTED, "dim %d (only %d is supported)", dim, GEM_DIM);
+  if (n_rows < 0) return fail(GEM_ERR_INVALID, "negative n_rows");
+  if (n_rows > 0 && (!x || !out || !exps)) return fail(GEM_ERR_INVALID, "NULL buffer");
+  hipError_t e = launch_quantize_mxfp4(x, n_rows, out, exps, stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "mxfp4 quantization");
 }
 
 size_t gem_codebook_workspace_bytes(int32_t op, int64_t n_rows, int64_t n_centroids) {
@@ -469,8 +500,10 @@ gem_status gem_score_quant(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, co
                            float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,
                            int32_t* top_ids, void* ws, size_t ws_bytes, hipStream_t stream) {
   if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
-  return score_common(ctx, Q, D, C, GEM_FP8_E4M3, k, scores, ld_scores, score_rows, top_scores, top_ids, ws,
-                      ws_bytes, stream);
+  if (!D) return fail(GEM_ERR_INVALID, "D is NULL");
+  if (!quant_dtype(D->dtype)) return fail(GEM_ERR_INVALID, "D: dtype %d is not a quantized format", D->dtype);
+  return score_common(ctx, Q, D, C, D->dtype, k, scores, ld_scores, score_rows, top_scores, top_ids, ws, ws_bytes,
+                      stream);
 }
 
 gem_status gem_topk(gem_ctx ctx, const float* scores, const int64_t* seg_offsets, const int32_t* seg_ids,
@@ -506,8 +539,9 @@ gem_status gem_expand_batch(gem_ctx ctx, const gem_sets* Q8, const gem_sets* D8,
   gem_status st;
   if ((st = check_sets(Q8, "Q8", true)) != GEM_OK) return st;
   if ((st = check_sets(D8, "D8", false)) != GEM_OK) return st;
-  if (D8->dtype != GEM_FP8_E4M3) return fail(GEM_ERR_INVALID, "D8 must be FP8 E4M3");
-  if (Q8->dtype != GEM_FP8_E4M3 && Q8->dtype != GEM_F32) return fail(GEM_ERR_INVALID, "Q8 must be FP8 E4M3 or F32");
+  if (!quant_dtype(D8->dtype)) return fail(GEM_ERR_INVALID, "D8 must be FP8 E4M3 or MXFP4");
+  const int32_t cd = D8->dtype;
+  if (Q8->dtype != cd && Q8->dtype != GEM_F32) return fail(GEM_ERR_INVALID, "Q8 must be in D8's format or F32");
   if (!C) return fail(GEM_ERR_INVALID, "cands is NULL");
   if ((st = check_cands(C, Q8->n_sets)) != GEM_OK) return st;
   if (!beam) return fail(GEM_ERR_INVALID, "beam is NULL");
@@ -515,19 +549,120 @@ gem_status gem_expand_batch(gem_ctx ctx, const gem_sets* Q8, const gem_sets* D8,
   if (Q8->n_sets > 0 && (!beam->scores || !beam->ids)) return fail(GEM_ERR_INVALID, "beam buffers are NULL");
   if ((int64_t)beam->ef + list_len_bound(C) > kBeamMaxEntries)
     return fail(GEM_ERR_UNSUPPORTED, "ef + longest list = %d exceeds %d", beam->ef + list_len_bound(C), kBeamMaxEntries);
-  const ScoreLayout L = score_layout(Q8, D8, C, GEM_FP8_E4M3, 1, cand_scores != nullptr);
+  const ScoreLayout L = score_layout(Q8, D8, C, cd, 1, cand_scores != nullptr);
   if (ws_bytes < L.total) return fail(GEM_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.total);
   if (L.total > 0 && !ws) return fail(GEM_ERR_INVALID, "workspace is NULL");
   if (Q8->n_sets == 0) return GEM_OK;
   gem_sets Qc;
-  if ((st = convert_query(Q8, GEM_FP8_E4M3, ws, L, &Qc, stream)) != GEM_OK) return st;
+  if ((st = convert_query(Q8, cd, ws, L, &Qc, stream)) != GEM_OK) return st;
   float* es = cand_scores ? cand_scores : reinterpret_cast<float*>(at(ws, L.staged));
-  hipError_t e = launch_score_gather(GEM_FP8_E4M3, view(&Qc), view(D8), cview(C), list_len_bound(C), Q8->max_set_len,
+  hipError_t e = launch_score_gather(cd, view(&Qc), view(D8), cview(C), list_len_bound(C), Q8->max_set_len,
                                      es, stream);
   if (e != hipSuccess) return hip_fail(e, "gathered scoring");
   e = launch_beam_merge(es, cview(C), Q8->n_sets, beam->ef, beam->scores, beam->ids, stream);
   if (e != hipSuccess) return hip_fail(e, "beam merge");
   return GEM_OK;
+}
+
+gem_status gem_set_clusters(gem_ctx ctx, const int32_t* vec_clusters, const int64_t* set_offsets, int64_t n_sets,
+                            int32_t k2, int32_t r, uint32_t* set_masks, int64_t* member_offsets, int32_t* members,
+                            void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (k2 < 1 || k2 > kMaxSearchClusters) return fail(GEM_ERR_UNSUPPORTED, "k2 = %d outside [1, %d]", k2, kMaxSearchClusters);
+  if (r < 1 || r > k2) return fail(GEM_ERR_INVALID, "r = %d outside [1, k2]", r);
+  if (n_sets < 0 || n_sets > INT32_MAX) return fail(GEM_ERR_INVALID, "n_sets out of range");
+  if (ws_bytes < GEM_SEARCH_CLUSTER_WS || !ws) return fail(GEM_ERR_WORKSPACE, "workspace of %d bytes needed", GEM_SEARCH_CLUSTER_WS);
+  if (!member_offsets || (n_sets > 0 && (!vec_clusters || !set_offsets || !set_masks || !members)))
+    return fail(GEM_ERR_INVALID, "NULL buffer");
+  hipError_t e = launch_set_clusters(vec_clusters, set_offsets, n_sets, k2, r, set_masks, member_offsets, members,
+                                     static_cast<int32_t*>(ws), stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "set clusters");
+}
+
+gem_status gem_query_clusters(gem_ctx ctx, const gem_sets* Q, const float* centroids, int32_t k2, int32_t t,
+                              uint32_t* query_masks, hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  gem_status st;
+  if ((st = check_sets(Q, "Q", false)) != GEM_OK) return st;
+  if (Q->dtype != GEM_F32 || Q->codes) return fail(GEM_ERR_INVALID, "Q must be float32 rows");
+  if (k2 < 1 || k2 > kMaxSearchClusters) return fail(GEM_ERR_UNSUPPORTED, "k2 = %d outside [1, %d]", k2, kMaxSearchClusters);
+  if (t < 1) return fail(GEM_ERR_INVALID, "t = %d", t);
+  if (Q->n_sets > 0 && (!centroids || !query_masks)) return fail(GEM_ERR_INVALID, "NULL buffer");
+  hipError_t e = launch_query_clusters(Q->offsets, static_cast<const float*>(Q->vecs), Q->n_sets, centroids, k2, t,
+                                       query_masks, stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "query clusters");
+}
+
+namespace {
+
+gem_status check_search(const gem_sets* Q, const gem_sets* D, const gem_graph* G, const gem_search_state* S,
+                        const gem_beam* beam, SearchView* v, int32_t* row) {
+  gem_status st;
+  if ((st = check_sets(Q, "Q", true)) != GEM_OK) return st;
+  if ((st = check_sets(D, "D", false)) != GEM_OK) return st;
+  if (!G || !S || !beam) return fail(GEM_ERR_INVALID, "NULL argument");
+  if (Q->dtype != D->dtype) return fail(GEM_ERR_INVALID, "Q must be in D's dtype");
+  if (G->n_sets != D->n_sets) return fail(GEM_ERR_INVALID, "graph has %lld sets, D %lld", (long long)G->n_sets,
+                                          (long long)D->n_sets);
+  if (G->k2 < 1 || G->k2 > kMaxSearchClusters) return fail(GEM_ERR_UNSUPPORTED, "k2 = %d", G->k2);
+  if (G->degree < 1 || G->degree > 64) return fail(GEM_ERR_UNSUPPORTED, "degree = %d outside [1, 64]", G->degree);
+  if (S->width < 1 || S->width > 64) return fail(GEM_ERR_UNSUPPORTED, "width = %d outside [1, 64]", S->width);
+  if (beam->ef < 1 || beam->ef > GEM_MAX_K) return fail(GEM_ERR_INVALID, "ef = %d outside [1, %d]", beam->ef, GEM_MAX_K);
+  *row = std::max(G->k2, S->width * G->degree);
+  if ((int64_t)beam->ef + *row > kBeamMaxEntries)
+    return fail(GEM_ERR_UNSUPPORTED, "ef + candidate row = %d exceeds %d", beam->ef + *row, kBeamMaxEntries);
+  if (Q->n_sets > 0 && (!G->neighbors || !G->set_masks || !G->member_offsets || !G->members || !S->query_masks ||
+                        !S->visited || !S->expanded || !S->frontier || !S->cand_ids || !S->cand_scores || !S->active ||
+                        !beam->scores || !beam->ids))
+    return fail(GEM_ERR_INVALID, "NULL buffer");
+  v->k2 = G->k2; v->width = S->width; v->degree = G->degree;
+  v->neighbors = G->neighbors; v->set_mask = G->set_masks; v->qmask = S->query_masks;
+  v->member_off = G->member_offsets; v->members = G->members;
+  v->visited = S->visited; v->expanded = S->expanded; v->frontier = S->frontier; v->active = S->active;
+  v->bitmap_words = (G->n_sets + 31) / 32;
+  return GEM_OK;
+}
+
+gem_status search_score_merge(const gem_sets* Q, const gem_sets* D, const gem_search_state* S, gem_beam* beam,
+                              int32_t row, hipStream_t stream) {
+  CandsView c;
+  c.off = nullptr; c.ids = S->cand_ids; c.n_lists = Q->n_sets; c.stride = row;
+  hipError_t e = launch_score_gather(D->dtype, view(Q), view(D), c, row, Q->max_set_len, S->cand_scores, stream);
+  if (e != hipSuccess) return hip_fail(e, "search scoring");
+  e = launch_beam_merge(S->cand_scores, c, Q->n_sets, beam->ef, beam->scores, beam->ids, stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "search merge");
+}
+
+}  // namespace
+
+gem_status gem_search_begin(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_graph* G,
+                            gem_search_state* S, const uint32_t* random_words, gem_beam* beam, hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  SearchView v;
+  int32_t row = 0;
+  gem_status st = check_search(Q, D, G, S, beam, &v, &row);
+  if (st != GEM_OK) return st;
+  if (Q->n_sets > 0 && !random_words) return fail(GEM_ERR_INVALID, "random_words is NULL");
+  if (Q->n_sets == 0) return GEM_OK;
+  hipError_t e = launch_search_clear(v, Q->n_sets, stream);
+  if (e == hipSuccess) e = launch_search_entries(v, Q->n_sets, random_words, S->cand_ids, row, stream);
+  if (e == hipSuccess) e = launch_beam_reset(beam->scores, beam->ids, Q->n_sets * (int64_t)beam->ef, stream);
+  if (e != hipSuccess) return hip_fail(e, "search start");
+  return search_score_merge(Q, D, S, beam, row, stream);
+}
+
+gem_status gem_search_step(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_graph* G,
+                           gem_search_state* S, gem_beam* beam, hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  SearchView v;
+  int32_t row = 0;
+  gem_status st = check_search(Q, D, G, S, beam, &v, &row);
+  if (st != GEM_OK) return st;
+  hipError_t e = launch_search_select(v, Q->n_sets, beam->ids, beam->ef, stream);
+  if (e == hipSuccess) e = launch_search_expand(v, Q->n_sets, S->cand_ids, row, stream);
+  if (e != hipSuccess) return hip_fail(e, "search step");
+  if (Q->n_sets == 0) return GEM_OK;
+  return search_score_merge(Q, D, S, beam, row, stream);
 }
 
 gem_status gem_beam_merge(gem_ctx ctx, const float* cand_scores, const gem_cands* C, gem_beam* beam,
@@ -563,6 +698,10 @@ gem_status gem_validate_sets(gem_ctx ctx, const gem_sets* S, hipStream_t stream)
                        S->offsets, S->n_sets, S->n_vecs);
   }
   const int64_t rows = vec_rows(S);
+  if (S->dtype == GEM_MXFP4 && rows > 0) {
+    hipLaunchKernelGGL(validate_mx_exps_kernel, dim3(capped_blocks((rows + 255) / 256, 256)), dim3(256), 0, stream,
+                       reinterpret_cast<const uint32_t*>(S->scales), rows);
+  }
   if (S->dtype == GEM_FP8_E4M3 && rows > 0) {
     hipLaunchKernelGGL(validate_scales_kernel, dim3(capped_blocks((rows + 255) / 256, 256)), dim3(256), 0, stream,
                        S->scales, rows);

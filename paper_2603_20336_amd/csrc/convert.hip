@@ -57,6 +57,52 @@ hipError_t launch_quantize_fp8(const float* x, int64_t n_rows, uint8_t* out, flo
   return hipGetLastError();
 }
 
+// float32 rows -> OCP MXFP4. One wave per row, two elements per lane; the 16
+// lanes of a 32-element block share its scale 2^e, the smallest with
+// max|x| <= 6 * 2^e. E2M1 code of y = x / 2^e: round to nearest on the grid
+// 0, .5, 1, 1.5, 2, 3, 4, 6 with ties to the even code, i.e. the count of
+// midpoints below |y| (a tie at .25, 1.25, 2.5 or 5 stays on the lower, even
+// code; at .75, 1.75 or 3.5 it moves to the upper, even code).
+__device__ __forceinline__ uint32_t e2m1_code(float y) {
+  const float a = fabsf(y);
+  const uint32_t m = (uint32_t)(a > 0.25f) + (uint32_t)(a >= 0.75f) + (uint32_t)(a > 1.25f) + (uint32_t)(a >= 1.75f) +
+                     (uint32_t)(a > 2.5f) + (uint32_t)(a >= 3.5f) + (uint32_t)(a > 5.0f);
+  return m | ((y < 0.0f && m != 0u) ? 8u : 0u);
+}
+
+__device__ __forceinline__ int mx_block_exponent(float amax) {
+  if (!(amax > 0.0f)) return 0;
+  int E;
+  (void)frexpf(amax, &E);                                   // amax = f * 2^E, f in [0.5, 1)
+  int e = E - 4;
+  while (amax > ldexpf(6.0f, e)) ++e;
+  return e < -127 ? -127 : (e > 127 ? 127 : e);
+}
+
+__global__ __launch_bounds__(256) void quantize_mxfp4_kernel(const float* __restrict__ x, int64_t n_rows,
+                                                             uint8_t* __restrict__ out, uint8_t* __restrict__ exps) {
+  const int l = threadIdx.x & 63;
+  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < n_rows; row += (int64_t)gridDim.x * 4) {
+    const float2 v = reinterpret_cast<const float2*>(x + row * kDim)[l];
+    float amax = fmaxf(fabsf(v.x), fabsf(v.y));
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) amax = fmaxf(amax, __shfl_xor(amax, o));   // within the 16-lane block
+    const int e = mx_block_exponent(amax);
+    // x * 2^-e, exact: two steps keep the factor a normal float for e = 127
+    const float y0 = ldexpf(ldexpf(v.x, -e / 2), -(e - e / 2));
+    const float y1 = ldexpf(ldexpf(v.y, -e / 2), -(e - e / 2));
+    out[row * 64 + l] = (uint8_t)(e2m1_code(y0) | (e2m1_code(y1) << 4));
+    if ((l & 15) == 0) exps[row * 4 + (l >> 4)] = (uint8_t)(e + 127);
+  }
+}
+
+hipError_t launch_quantize_mxfp4(const float* x, int64_t n_rows, uint8_t* out, uint8_t* exps, hipStream_t s) {
+  if (n_rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(quantize_mxfp4_kernel, dim3(capped_blocks((n_rows + 3) / 4, 256)), dim3(256), 0, s, x, n_rows, out,
+                     exps);
+  return hipGetLastError();
+}
+
 // Row copies: dst row (dst_idx ? dst_idx[i] : i) = src row (src_idx ? src_idx[i] : i)
 // for i < n, rows of `units` W-byte units (W = 16 or 4). One 64-lane wave per
 // row (a row of more than 64 units takes several steps).

@@ -72,6 +72,7 @@ hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, 
 
 hipError_t launch_convert_bf16(const float* x, int64_t n_elems, uint16_t* out, hipStream_t s);
 hipError_t launch_quantize_fp8(const float* x, int64_t n_rows, uint8_t* out, float* scales, hipStream_t s);
+hipError_t launch_quantize_mxfp4(const float* x, int64_t n_rows, uint8_t* out, uint8_t* exps, hipStream_t s);
 // Codebook kernels (nearest centroid, k-means update).
 size_t nearest_centroid_ws_bytes(int64_t n_rows, int64_t n_centroids);
 hipError_t launch_nearest_centroid(int dtype, const void* x, int64_t n_rows, const void* centroids,
@@ -101,6 +102,35 @@ hipError_t launch_beam_merge(const float* cand_scores, const CandsView& C, int64
 hipError_t launch_beam_reset(float* beam_scores, int32_t* beam_ids, int64_t n, hipStream_t s);
 
 constexpr int kBeamMaxEntries = 4096;   // ef + longest candidate list of a merge
+
+// Batched cluster-guided search (Alg. 5): the graph, the set clusters and one
+// batch's state, all device memory owned by the caller.
+struct SearchView {
+  int32_t k2;                 // coarse clusters (<= 1024)
+  int32_t width;              // sets expanded per query and step
+  int32_t degree;             // neighbours per set
+  const int32_t* neighbors;   // [n_sets][degree], -1 padded
+  const uint32_t* set_mask;   // [n_sets][words] C_top masks
+  const uint32_t* qmask;      // [n_q][words] C_query masks
+  const int64_t* member_off;  // [k2 + 1]
+  const int32_t* members;     // sets per cluster, in id order
+  uint32_t* visited;          // [n_q][bitmap_words]
+  uint32_t* expanded;         // [n_q][bitmap_words]
+  int32_t* frontier;          // [n_q][width]
+  uint32_t* active;           // [1]: queries with a frontier in the last select
+  int64_t bitmap_words;       // (n_sets + 31) / 32
+};
+constexpr int kMaxSearchClusters = 1024;
+
+hipError_t launch_set_clusters(const int32_t* vec_clusters, const int64_t* set_off, int64_t n_sets, int k2, int r,
+                               uint32_t* mask, int64_t* member_off, int32_t* members, int32_t* ws, hipStream_t s);
+hipError_t launch_query_clusters(const int64_t* q_off, const float* q, int64_t n_q, const float* C, int k2, int t,
+                                 uint32_t* qmask, hipStream_t s);
+hipError_t launch_search_clear(const SearchView& S, int64_t n_q, hipStream_t s);
+hipError_t launch_search_entries(const SearchView& S, int64_t n_q, const uint32_t* u, int32_t* cand, int32_t stride,
+                                 hipStream_t s);
+hipError_t launch_search_select(const SearchView& S, int64_t n_q, const int32_t* beam_ids, int32_t ef, hipStream_t s);
+hipError_t launch_search_expand(const SearchView& S, int64_t n_q, int32_t* cand, int32_t stride, hipStream_t s);
 
 // Validation: returns number of violations found (synchronizes).
 hipError_t validate_sets(const SetsView& S, int64_t n_vecs, int is_fp8, hipStream_t s, int64_t* bad);

@@ -93,4 +93,33 @@ template <> struct Op<GEM_FP8_E4M3> {
   static constexpr int kSteps = 1;
 };
 
+// OCP MXFP4: lane group g holds block g of the row (dims 32g .. 32g + 31, 16
+// bytes of E2M1 codes) with that block's E8M0 exponent as the lane's MFMA
+// scale, for A and B alike, so the instruction applies the microscaling
+// blocks itself. The FP4 operand takes four registers.
+template <> struct Op<GEM_MXFP4> {
+  static constexpr int kRowBytes = 64;
+  struct Frag { i32x4 v; int scale; };
+  static __device__ __forceinline__ void load(Frag& f, const void* vecs, const float* scales, int64_t row, int g) {
+    const uint4 a = *reinterpret_cast<const uint4*>(static_cast<const char*>(vecs) + row * kRowBytes + g * 16);
+    f.v = i32x4{(int)a.x, (int)a.y, (int)a.z, (int)a.w};
+    f.scale = (int)reinterpret_cast<const uint8_t*>(scales)[row * 4 + g];
+  }
+  static __device__ __forceinline__ void zero(Frag& f) {
+    f.v = i32x4{0, 0, 0, 0};
+    f.scale = 127;
+  }
+  static __device__ __forceinline__ void load_b(Frag& f, const void* v, const float* sc, int64_t row, int g) {
+    load(f, v, sc, row, g);
+  }
+  static constexpr bool kColumnScale = false;
+  static __device__ __forceinline__ f32x4 mma(const Frag& a, const Frag& b, f32x4 acc, int) {
+    // E2M1 for both operands (format code 4); each lane's block exponent
+    const i32x8 av = i32x8{a.v.x, a.v.y, a.v.z, a.v.w, 0, 0, 0, 0};
+    const i32x8 bv = i32x8{b.v.x, b.v.y, b.v.z, b.v.w, 0, 0, 0, 0};
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc, 4, 4, 0, a.scale, 0, b.scale);
+  }
+  static constexpr int kSteps = 1;
+};
+
 }  // namespace gem

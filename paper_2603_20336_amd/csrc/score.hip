@@ -35,6 +35,7 @@ template <int DT> struct DenseCfg;
 template <> struct DenseCfg<GEM_F32> { static constexpr int kNT = 4; static constexpr int kGroup = 4; };
 template <> struct DenseCfg<GEM_BF16> { static constexpr int kNT = 8; static constexpr int kGroup = 8; };
 template <> struct DenseCfg<GEM_FP8_E4M3> { static constexpr int kNT = 16; static constexpr int kGroup = 8; };
+template <> struct DenseCfg<GEM_MXFP4> { static constexpr int kNT = 16; static constexpr int kGroup = 8; };
 
 int dense_pass_rows(int dtype) {
   switch (dtype) {
@@ -233,7 +234,7 @@ template <int DT> struct TileStage {
   static constexpr int kTileBytes = 16 * kRowBytes;
   static constexpr int kSlots = kTileBytes / 16;                 // 16-byte pieces per tile
   static constexpr int kPieceWaves = kSlots / 64;                // waves copying one piece per lane
-  static constexpr bool kScales = DT == GEM_FP8_E4M3;
+  static constexpr bool kScales = DT == GEM_FP8_E4M3 || DT == GEM_MXFP4;   // one 32-bit scale word per row
   static constexpr int kCopyWaves = kPieceWaves + (kScales ? 1 : 0);   // waves busy copying one tile
   // FP8: the tile's 16 row scales, copied by a whole wave (lanes past 16 fill
   // the rest of the slot with repeats)
@@ -253,7 +254,9 @@ template <int DT> struct TileStage {
 
   // chunk c of row r sits at position c ^ swz(r): the 16 rows read by one
   // 16-lane group then cover all 64 banks (128-byte rows pair up first)
-  static __device__ __forceinline__ int swz(int r) { return kRowBytes == 128 ? ((r >> 1) & 7) : (r & 15); }
+  static __device__ __forceinline__ int swz(int r) {
+    return kRowBytes == 64 ? ((r >> 2) & 3) : (kRowBytes == 128 ? ((r >> 1) & 7) : (r & 15));
+  }
 
   // Piece `role` (1 KiB) of tile k of the document whose rows are
   // base + [rs, re), into `stage`.
@@ -321,6 +324,14 @@ __device__ __forceinline__ void frag_from_lds<GEM_FP8_E4M3>(Op<GEM_FP8_E4M3>::Fr
   const uint32_t sc = reinterpret_cast<const uint32_t*>(stage + 128)[c16];
   f.v = i32x8{(int)v0.x, (int)v0.y, (int)v0.z, (int)v0.w, (int)v1.x, (int)v1.y, (int)v1.z, (int)v1.w};
   f.scale = (int)((sc >> 23) & 0xffu);
+}
+
+template <>
+__device__ __forceinline__ void frag_from_lds<GEM_MXFP4>(Op<GEM_MXFP4>::Frag& f, const u32x4* stage, int c16, int g) {
+  const u32x4 v = stage[c16 * 4 + (g ^ ((c16 >> 2) & 3))];
+  const uint32_t sc = reinterpret_cast<const uint32_t*>(stage + 64)[c16];
+  f.v = i32x4{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+  f.scale = (int)((sc >> (8 * g)) & 0xffu);
 }
 
 template <>
@@ -749,6 +760,10 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
       if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_FP8_E4M3, true>), grid, blk, 0, s, P);
       else hipLaunchKernelGGL((score_dense_kernel<GEM_FP8_E4M3, false>), grid, blk, 0, s, P);
       break;
+    case GEM_MXFP4:
+      if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_MXFP4, true>), grid, blk, 0, s, P);
+      else hipLaunchKernelGGL((score_dense_kernel<GEM_MXFP4, false>), grid, blk, 0, s, P);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -765,7 +780,9 @@ constexpr int kGatherEntries = 16;
 constexpr int kGatherNT = 4;
 // tiles in flight per wave (registers: a float32 tile fragment takes 32 VGPRs,
 // bf16 16, FP8 9)
-template <int DT> struct GatherDepth { static constexpr int value = DT == GEM_F32 ? 2 : (DT == GEM_BF16 ? 4 : 6); };
+template <int DT> struct GatherDepth {
+  static constexpr int value = DT == GEM_F32 ? 2 : (DT == GEM_BF16 ? 4 : (DT == GEM_FP8_E4M3 ? 6 : 8));
+};
 
 struct GatherParams {
   SetsView Q, D;
@@ -963,6 +980,10 @@ hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, 
       case GEM_FP8_E4M3:
         if (codes) hipLaunchKernelGGL((score_gather_kernel<GEM_FP8_E4M3, true>), gr, blk, 0, s, P);
         else hipLaunchKernelGGL((score_gather_kernel<GEM_FP8_E4M3, false>), gr, blk, 0, s, P);
+        break;
+      case GEM_MXFP4:
+        if (codes) hipLaunchKernelGGL((score_gather_kernel<GEM_MXFP4, true>), gr, blk, 0, s, P);
+        else hipLaunchKernelGGL((score_gather_kernel<GEM_MXFP4, false>), gr, blk, 0, s, P);
         break;
       default: return hipErrorInvalidValue;
     }

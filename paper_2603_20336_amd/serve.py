@@ -7,9 +7,11 @@ chunks. Every iteration scores one chunk -- the next one in round-robin order
 active queries against that chunk, one launch). A request that arrives while
 others are running is admitted at the next iteration, whatever chunk comes
 next, as soon as a slot and device memory are free; it has seen the whole
-corpus after `n_chunks` iterations. It then finishes: the top `shortlist`
-documents of its estimate row are reranked with exact float32 Chamfer scores
-and the top k are returned (the rerank of GEM's search, Alg. 5 final step).
+corpus after `n_chunks` chunks (an iteration may score several consecutive
+chunks when the active batch is light: `chunk_work`). It then finishes: the
+top `shortlist` documents of its estimate row are reranked with exact float32
+Chamfer scores and the top k are returned (the rerank of GEM's search, Alg. 5
+final step).
 
 Because a (query, document) score does not depend on which other queries
 share a launch, a request's result is bitwise the same alone and in any mix.
@@ -67,6 +69,11 @@ class Executor:
     def score_chunk(self, chunk: int) -> None:
         raise NotImplementedError
 
+    def score_chunks(self, chunk: int, span: int) -> None:
+        """Chunks chunk, chunk + 1, ... (span of them, wrapping around the corpus)."""
+        for i in range(span):
+            self.score_chunk((chunk + i) % self.n_chunks)
+
     def finish(self, slots: Sequence[int], queries: Sequence[np.ndarray]):
         """-> (top_scores [n, k], top_ids [n, k]) numpy arrays, results on the host."""
         raise NotImplementedError
@@ -86,8 +93,14 @@ class ServingEngine:
     """Admission, round-robin chunk schedule and completion bookkeeping."""
 
     def __init__(self, executor: Executor, max_slots: int, mem_budget_bytes: int,
-                 clock: Optional[Callable[[], float]] = None):
+                 clock: Optional[Callable[[], float]] = None, chunk_work: int = 0):
+        """chunk_work: if > 0, an iteration scores as many consecutive chunks as
+        fit chunk_work (query vectors x chunks) for the active batch, at least
+        one: a light batch then takes the corpus in fewer, fuller iterations
+        (less per-iteration host time in each request's latency), a heavy one
+        keeps one chunk per iteration. 0: always one chunk."""
         self.ex = executor
+        self.chunk_work = int(chunk_work)
         self.max_slots = int(max_slots)
         self.mem_budget = int(mem_budget_bytes)
         self._t0 = None
@@ -172,11 +185,15 @@ class ServingEngine:
         if key != self._batch_key:
             self.ex.set_batch([r.slot for r in self.active], [r.vecs for r in self.active])
             self._batch_key = key
-        self.ex.score_chunk(self.chunk)
+        span = self.span()
+        self.ex.score_chunks(self.chunk, span)
         self.active_sum += len(self.active)
         for r in self.active:
-            r.chunks_done += 1
-        finished = [r for r in self.active if r.chunks_done == self.ex.n_chunks]
+            r.chunks_done += span
+        # (a request whose revolution ends inside the span scores a few of its
+        # chunks twice; a score does not depend on the batch, so the repeat
+        # writes the same values)
+        finished = [r for r in self.active if r.chunks_done >= self.ex.n_chunks]
         if finished:
             # the slots are free at once: later work on them is ordered after
             # this request's on the device stream
@@ -185,9 +202,16 @@ class ServingEngine:
             for r in finished:
                 self.free_slots.append(r.slot)
             self.active = [r for r in self.active if r.chunks_done < self.ex.n_chunks]
-        self.chunk = (self.chunk + 1) % self.ex.n_chunks
+        self.chunk = (self.chunk + span) % self.ex.n_chunks
         self.iteration += 1
         return completed + self.poll()
+
+    def span(self) -> int:
+        """Chunks the next iteration scores."""
+        if self.chunk_work <= 0:
+            return 1
+        qv = sum(r.vecs.shape[0] for r in self.active)
+        return max(1, min(self.ex.n_chunks, self.chunk_work // max(1, qv)))
 
     def run(self, requests: Sequence[Request], idle_sleep: float = 0.0) -> List[Request]:
         """Serve requests (sorted by arrival) until all are done."""
@@ -197,10 +221,14 @@ class ServingEngine:
             self.start_clock()
         while self.waiting or self.active or self.pending:
             if not self.active and self.waiting and not self.pending:
-                wait = self.waiting[0].t_arrival - self.now()
+                t = self.now()
+                wait = self.waiting[0].t_arrival - t
                 if wait > 0:
                     if self._clock is not None:
-                        raise RuntimeError("a simulated clock must advance by itself")
+                        # a simulated clock advances as it is read
+                        if self.now() <= t:
+                            raise RuntimeError("a simulated clock must advance by itself")
+                        continue
                     if idle_sleep:
                         time.sleep(min(wait, idle_sleep))
                     continue
@@ -371,15 +399,23 @@ class DeviceExecutor(Executor):
         self.Q8, self.rows = self._gather(slots, fp8=True)
 
     def score_chunk(self, chunk: int) -> None:
+        self.score_chunks(chunk, 1)
+
+    def score_chunks(self, chunk: int, span: int) -> None:
         # the host runs at most two iterations ahead of the device: deeper
         # queues add their whole backlog to a new request's latency
         if len(self._iter_evts) >= 2:
             self._iter_evts.pop(0).synchronize()
-        a, b = self.bounds[chunk], self.bounds[chunk + 1]
-        if b > a:
-            Dc = self.D8.view(a, b)
-            out = self.est[:, a:]
-            self._gem.score_quant(self.Q8, Dc, scores=out, ld=self.n_docs, rows=self.rows, stream=self.stream)
+        end = chunk + span
+        ranges = [(chunk, min(end, self.n_chunks))]
+        if end > self.n_chunks:
+            ranges.append((0, end - self.n_chunks))             # wrapped around the corpus
+        for c0, c1 in ranges:
+            a, b = self.bounds[c0], self.bounds[c1]
+            if b > a:
+                Dc = self.D8.view(a, b)
+                out = self.est[:, a:]
+                self._gem.score_quant(self.Q8, Dc, scores=out, ld=self.n_docs, rows=self.rows, stream=self.stream)
         evt = torch.cuda.Event()
         evt.record(self._stream())
         self._iter_evts.append(evt)

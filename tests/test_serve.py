@@ -88,6 +88,20 @@ def test_continuous_batching_schedule_and_results():
         np.testing.assert_array_equal(np.sort(r.top_ids), np.sort(short[0][:5]))
 
 
+def test_multi_chunk_iterations_give_the_same_results():
+    c = wl.corpus(wl.WORKLOADS[1], n_docs=120)
+    reqs = _requests(12, 5)
+    out = {}
+    for work in (0, 40, 10 ** 6):          # one chunk; a few chunks; the whole corpus per iteration
+        ex = OracleExecutor(c, n_chunks=5, shortlist=20, k=5)
+        eng = serve.ServingEngine(ex, max_slots=6, mem_budget_bytes=10 ** 9, clock=StepClock(), chunk_work=work)
+        done = eng.run([serve.Request(r.rid, r.vecs, r.t_arrival) for r in reqs])
+        assert len(done) == 12
+        out[work] = ({r.rid: tuple(r.top_ids) for r in done}, eng.iteration)
+    assert out[0][0] == out[40][0] == out[10 ** 6][0]
+    assert out[10 ** 6][1] < out[40][1] <= out[0][1]
+
+
 def test_admission_waits_for_memory():
     c = wl.corpus(wl.WORKLOADS[1], n_docs=40)
     ex = OracleExecutor(c, n_chunks=2, shortlist=5, k=3, bytes_per_request=1000)
@@ -123,9 +137,9 @@ def test_device_serving_alone_equals_mix_and_matches_oracle():
     reqs = _requests(24, 3, lo=4, hi=64)
     target = 7
 
-    def run(rs):
+    def run(rs, work=0):
         ex = serve.DeviceExecutor(D8, D32, n_chunks=5, max_slots=32, shortlist=200, k=20)
-        eng = serve.ServingEngine(ex, max_slots=32, mem_budget_bytes=1 << 34, clock=StepClock())
+        eng = serve.ServingEngine(ex, max_slots=32, mem_budget_bytes=1 << 34, clock=StepClock(), chunk_work=work)
         return {r.rid: r for r in eng.run(rs)}
 
     alone = run([serve.Request(target, reqs[target].vecs, 0.0)])[target]
@@ -133,6 +147,11 @@ def test_device_serving_alone_equals_mix_and_matches_oracle():
     assert len(mix) == 24
     np.testing.assert_array_equal(alone.top_ids, mix[target].top_ids)
     np.testing.assert_array_equal(alone.top_scores, mix[target].top_scores)
+    # several chunks per iteration (wrapping around the corpus): the same results
+    multi = run([serve.Request(r.rid, r.vecs, r.t_arrival) for r in reqs], work=300)
+    for rid, r in mix.items():
+        np.testing.assert_array_equal(multi[rid].top_ids, r.top_ids)
+        np.testing.assert_array_equal(multi[rid].top_scores, r.top_scores)
     # returned scores are exact float32 Chamfer scores of the returned ids
     dv, do = c.vecs.numpy(), c.offsets.numpy()
     for r in mix.values():
