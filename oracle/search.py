@@ -22,8 +22,8 @@ Readings (each listed in the design notes):
     in the top-t go to the smaller cluster index; a cluster a set does not
     touch is never in its C_top (TF = 0);
   * members of a cluster are the sets whose C_top holds it, in id order; the
-    random entry of cluster j is member floor(u_j * count_j) for a uniform u_j
-    the caller draws;
+    random entry of cluster j is member floor(u_j * count_j / 2^32) for a
+    random 32-bit word u_j the caller draws;
   * the parallel paths of Alg. 5 become one batched loop per query: each step
     takes the w best entries of R not yet expanded (all paths advance at once),
     marks them expanded, and scores their unvisited, unpruned neighbours
@@ -80,13 +80,14 @@ def query_clusters(q_vecs, centroids, t: int) -> np.ndarray:
 
 
 def entry_points(cq, members, u) -> np.ndarray:
-    """One set per cluster of C_query (member floor(u_j * count_j)), duplicates dropped."""
+    """One set per cluster of C_query (member floor(u_j * count_j / 2^32) for the
+    random 32-bit words u), duplicates dropped."""
     out = []
     for j in cq:
         m = members[int(j)]
         if len(m) == 0:
             continue
-        pick = int(m[min(len(m) - 1, int(math.floor(u[int(j)] * len(m))))])
+        pick = int(m[(int(u[int(j)]) * len(m)) >> 32])
         if pick not in out:
             out.append(pick)
     return np.array(out, np.int64)

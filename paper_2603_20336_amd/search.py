@@ -7,22 +7,28 @@ worst evicted). Here a step is one gem_expand_batch call for all queries at
 once, and a run of steps -- with candidate lists fixed in device memory -- is
 recorded once into a graph and replayed, so the host issues one launch per
 run instead of two kernels per step.
+
+The second half runs the whole of Alg. 5 on a graph of the document sets:
+set-level clusters (Sec. 4.1), the C Q^T cluster filter, one entry per
+selected cluster, and search steps whose candidates are the unvisited,
+unpruned neighbours of the best unexpanded results (GraphSearch).
 """
 from __future__ import annotations
 
+import ctypes
 from typing import List, Optional, Sequence
 
 import torch
 
-from . import Beam, Cands, Sets, expand_batch, expand_workspace_bytes, score_exact
+from . import GEM_FP8_E4M3, GEM_MXFP4, Beam, Cands, Sets, expand_batch, expand_workspace_bytes, score_exact
 
 
 class ExpansionGraph:
     """`steps` beam-expansion steps over fixed candidate lists, recorded into a graph."""
 
     def __init__(self, Q8: Sets, D8: Sets, steps: Sequence[Cands], ef: int, stream=None):
-        if Q8.dtype != 2:
-            raise TypeError("Q8 must hold FP8 query sets (quantize them once, outside the graph)")
+        if Q8.dtype != D8.dtype or D8.dtype not in (GEM_FP8_E4M3, GEM_MXFP4):
+            raise TypeError("Q8 and D8 must both be FP8 or both MXFP4 (quantize the queries once, outside the graph)")
         self.Q8, self.D8, self.steps = Q8, D8, list(steps)
         self.device = D8.device
         self.beam = Beam(Q8.n_sets, ef, self.device)
@@ -30,7 +36,7 @@ class ExpansionGraph:
         self.cand_scores = torch.empty(max(n, 1), dtype=torch.float32, device=self.device)
         for c in self.steps:
             if expand_workspace_bytes(Q8, D8, c, True) != 0:
-                raise RuntimeError("expansion with FP8 queries and a score buffer needs no workspace")
+                raise RuntimeError("expansion with quantized queries and a score buffer needs no workspace")
         self.graph: Optional[torch.cuda.CUDAGraph] = None
 
     def run_eager(self, stream=None) -> None:
@@ -57,5 +63,145 @@ class ExpansionGraph:
 
     def rerank(self, Q32: Sets, D32: Sets, k: int):
         """Exact float32 Chamfer rerank of the beam (Alg. 5 final step) -> (scores, ids) [n_q, k]."""
+        C = Cands(self.beam.ids.reshape(-1), stride=self.beam.ef, n_lists=Q32.n_sets)
+        return score_exact(Q32, D32, cands=C, compute="f32", k=k)
+
+
+# ---------------------------------------------------------------------------
+# Cluster-guided beam search (Alg. 5) over a graph of the document sets.
+
+def _lib_ctx(device):
+    from . import _ctx, _stream, library
+    return library(), _ctx(torch.device(device)), _stream
+
+
+def set_clusters(vec_clusters: torch.Tensor, set_offsets: torch.Tensor, k2: int, r: int, stream=None):
+    """Set-level clusters of Sec. 4.1 (TF-IDF pruning): (masks [N, words] int32 bit
+    patterns, member offsets [k2 + 1], members) from each vector's cluster."""
+    from . import _abi, _ptr
+    dev = vec_clusters.device
+    lib, ctx, _stream = _lib_ctx(dev)
+    n = int(set_offsets.numel() - 1)
+    words = (k2 + 31) // 32
+    masks = torch.empty(n, words, dtype=torch.int32, device=dev)
+    moff = torch.empty(k2 + 1, dtype=torch.int64, device=dev)
+    members = torch.empty(max(1, n * r), dtype=torch.int32, device=dev)
+    ws = torch.empty(_abi.GEM_SEARCH_CLUSTER_WS, dtype=torch.uint8, device=dev)
+    _abi.check(lib.gem_set_clusters(ctx, _ptr(vec_clusters), _ptr(set_offsets), n, int(k2), int(r), _ptr(masks),
+                                    _ptr(moff), _ptr(members), _ptr(ws), ws.numel(), _stream(stream)))
+    return masks, moff, members
+
+
+def query_clusters(Q32: Sets, centroids: torch.Tensor, t: int, stream=None) -> torch.Tensor:
+    """C_query masks [n_q, words] (S = C Q^T, top-t per query vector, Sec. 4.5)."""
+    from . import _abi, _ptr
+    dev = Q32.device
+    lib, ctx, _stream = _lib_ctx(dev)
+    k2 = int(centroids.shape[0])
+    masks = torch.empty(Q32.n_sets, (k2 + 31) // 32, dtype=torch.int32, device=dev)
+    qs = Q32.struct()
+    _abi.check(lib.gem_query_clusters(ctx, ctypes.byref(qs), _ptr(centroids), k2, int(t), _ptr(masks),
+                                      _stream(stream)))
+    return masks
+
+
+def knn_graph(D_as_queries: Sets, D: Sets, degree: int, batch: int = 2000, stream=None) -> torch.Tensor:
+    """A kNN graph of the document sets: row p lists the `degree` sets with the best
+    score(P, .) in D's dtype (P itself included), best first. D_as_queries holds
+    the same sets in a query-side dtype (float32 rows, converted per batch)."""
+    from . import score_exact, score_quant, topk, _QUANT
+    n = D.n_sets
+    out = torch.empty(n, degree, dtype=torch.int32, device=D.device)
+    scores = torch.empty(min(batch, n), n, dtype=torch.float32, device=D.device)
+    for a in range(0, n, batch):
+        b = min(n, a + batch)
+        Qb = D_as_queries.view(a, b)
+        sc = scores[: b - a]
+        if D.dtype in _QUANT:
+            score_quant(Qb, D, scores=sc, stream=stream)
+        else:
+            score_exact(Qb, D, compute=D.dtype, scores=sc, stream=stream)
+        _, ids = topk(sc, degree, stream=stream)
+        out[a:b] = ids
+    return out
+
+
+class ClusterIndex:
+    """The searchable index: neighbour lists and set clusters (device tensors)."""
+
+    def __init__(self, neighbors: torch.Tensor, set_masks: torch.Tensor, member_offsets: torch.Tensor,
+                 members: torch.Tensor, centroids: torch.Tensor):
+        self.neighbors, self.set_masks = neighbors.contiguous(), set_masks.contiguous()
+        self.member_offsets, self.members, self.centroids = member_offsets, members, centroids
+        self.k2 = int(centroids.shape[0])
+
+    def struct(self):
+        from . import _abi, _ptr
+        g = _abi.gem_graph()
+        g.n_sets, g.k2, g.degree = int(self.neighbors.shape[0]), self.k2, int(self.neighbors.shape[1])
+        g.neighbors, g.set_masks = _ptr(self.neighbors), _ptr(self.set_masks)
+        g.member_offsets, g.members = _ptr(self.member_offsets), _ptr(self.members)
+        return g
+
+
+class GraphSearch:
+    """One batch of queries searched together (Alg. 5, every path of every query
+    advancing per step): R in `beam`, the visited / expanded maps and the
+    candidate rows in device buffers allocated once."""
+
+    def __init__(self, Q: Sets, D: Sets, index: ClusterIndex, query_masks: torch.Tensor, ef: int, width: int = 4):
+        from . import _abi, _ptr
+        self.Q, self.D, self.index = Q, D, index
+        dev = D.device
+        n_q, n = Q.n_sets, D.n_sets
+        deg = int(index.neighbors.shape[1])
+        self.row = max(index.k2, width * deg)
+        bw = (n + 31) // 32
+        self.visited = torch.empty(n_q, bw, dtype=torch.int32, device=dev)
+        self.expanded = torch.empty(n_q, bw, dtype=torch.int32, device=dev)
+        self.frontier = torch.empty(n_q, width, dtype=torch.int32, device=dev)
+        self.cand_ids = torch.empty(n_q, self.row, dtype=torch.int32, device=dev)
+        self.cand_scores = torch.empty(n_q, self.row, dtype=torch.float32, device=dev)
+        self.active = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.query_masks = query_masks.contiguous()
+        self.beam = Beam(n_q, ef, dev)
+        st = _abi.gem_search_state()
+        st.width, st.reserved = int(width), 0
+        st.query_masks, st.visited, st.expanded = _ptr(self.query_masks), _ptr(self.visited), _ptr(self.expanded)
+        st.frontier, st.cand_ids, st.cand_scores = _ptr(self.frontier), _ptr(self.cand_ids), _ptr(self.cand_scores)
+        st.active = _ptr(self.active)
+        self._state, self._graph = st, index.struct()
+        self._qs, self._ds = Q.struct(), D.struct()
+        self.steps = 0
+
+    def begin(self, random_words: torch.Tensor, stream=None) -> None:
+        """random_words: [n_q, k2] uint32 (int32 bit patterns) drawn by the caller."""
+        from . import _abi, _ptr
+        lib, ctx, _stream = _lib_ctx(self.D.device)
+        _abi.check(lib.gem_search_begin(ctx, ctypes.byref(self._qs), ctypes.byref(self._ds), ctypes.byref(self._graph),
+                                        ctypes.byref(self._state), _ptr(random_words), ctypes.byref(self.beam.struct()),
+                                        _stream(stream)))
+        self.steps = 0
+
+    def step(self, stream=None) -> None:
+        from . import _abi
+        lib, ctx, _stream = _lib_ctx(self.D.device)
+        _abi.check(lib.gem_search_step(ctx, ctypes.byref(self._qs), ctypes.byref(self._ds), ctypes.byref(self._graph),
+                                       ctypes.byref(self._state), ctypes.byref(self.beam.struct()), _stream(stream)))
+        self.steps += 1
+
+    def run(self, random_words: torch.Tensor, max_steps: int = 10000, check_every: int = 2, stream=None) -> int:
+        """Search until no query has anything left to expand (checked every
+        `check_every` steps; a finished query's extra steps change nothing)."""
+        self.begin(random_words, stream)
+        while self.steps < max_steps:
+            for _ in range(check_every):
+                self.step(stream)
+            if int(self.active.item()) == 0:
+                break
+        return self.steps
+
+    def rerank(self, Q32: Sets, D32: Sets, k: int):
+        """Exact float32 Chamfer rerank of R (Alg. 5, last line) -> (scores, ids) [n_q, k]."""
         C = Cands(self.beam.ids.reshape(-1), stride=self.beam.ef, n_lists=Q32.n_sets)
         return score_exact(Q32, D32, cands=C, compute="f32", k=k)

@@ -74,9 +74,11 @@ def test_query_clusters_match_stable_argsort():
 
 def test_entry_points_closed_forms():
     members = [np.array([3, 5, 9]), np.array([]), np.array([5, 7])]
-    np.testing.assert_array_equal(osr.entry_points([0, 1, 2], members, np.zeros(3)), [3, 5])
-    np.testing.assert_array_equal(osr.entry_points([0, 2], members, np.array([0.99, 0, 0.5])), [9, 7])
-    np.testing.assert_array_equal(osr.entry_points([0, 2], members, np.array([0.4, 0, 0.0])), [5])   # 5 twice
+    top = 2 ** 32 - 1
+    np.testing.assert_array_equal(osr.entry_points([0, 1, 2], members, np.zeros(3, np.uint64)), [3, 5])
+    np.testing.assert_array_equal(osr.entry_points([0, 2], members, np.array([top, 0, 2 ** 31], np.uint64)), [9, 7])
+    # 2^32 / 3 picks member 1 of 3 (5), and member 0 of cluster 2 is 5 again: dropped
+    np.testing.assert_array_equal(osr.entry_points([0, 2], members, np.array([2 ** 32 // 3 + 1, 0, 0], np.uint64)), [5])
 
 
 def _problem(seed, n=60):
