@@ -12,6 +12,8 @@ path computes, written from the paper (GEM, arXiv 2603.20336):
     NN (Sec. 4.2) and the quantized Chamfer estimate qCH (Sec. 4.5, Eq. qCH)
   * the cluster-guided beam search of Alg. 5 (Sec. 4.5) with the TF-IDF
     set-level clustering of Sec. 4.1, in a batched reading
+  * EMD between vector sets (Sec. 4.2, Eq. EMD / qEMD), exact and as the
+    entropic Sinkhorn approximation the GPU computes
   * MXFP4 (OCP Microscaling, E2M1 elements with one power-of-two scale per
     32-element block), the ultra-low-bit estimate the paper names as future
     work (Sec. 6)
@@ -34,6 +36,7 @@ from .codebook import (codebook_size, sq_distances, nn_assign, lloyd_update, kme
                        qch_pair, qch_dense, qch_cands)
 from .search import (tfidf_top_clusters, cluster_members, query_clusters, entry_points, beam_search,
                      ch_scorer)
+from .emd import cost_matrix, emd_exact, sinkhorn, chamfer_distance
 from .mx import e2m1_decode, e2m1_table, e2m1_encode, block_exponent, quantize_mxfp4, dequantize_mxfp4
 from .codecs import (bf16_round_bits, bf16_decode, e4m3_decode, e4m3_decode_table,
                      e4m3_encode, pow2_scale, quantize_fp8, dequantize_fp8)
@@ -46,5 +49,6 @@ __all__ = [
     "codebook_size", "sq_distances", "nn_assign", "lloyd_update", "kmeans", "kmeans_objective",
     "qch_pair", "qch_dense", "qch_cands",
     "tfidf_top_clusters", "cluster_members", "query_clusters", "entry_points", "beam_search", "ch_scorer",
+    "cost_matrix", "emd_exact", "sinkhorn", "chamfer_distance",
     "e2m1_decode", "e2m1_table", "e2m1_encode", "block_exponent", "quantize_mxfp4", "dequantize_mxfp4",
 ]
