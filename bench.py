@@ -90,6 +90,101 @@ def build_codebook(D32, n_iter: int, assign: str, seed: int, per_centroid: int =
     return C, Dc, info
 
 
+def bench_graph_search(seed: int = 13):
+    """Alg. 5 on a kNN graph of the topical 100k corpus: C_quant (k-means of the
+    vectors), C_index (k-means of the C_quant centroids) and the TF-IDF set
+    clusters (Sec. 4.1), the C Q^T filter, and the batched search of all
+    queries with the FP8 estimate, then the exact f32 rerank of R; recall
+    against the exhaustive float32 top-k."""
+    from paper_2603_20336_amd import search as gs
+    dev = torch.device("cuda:0")
+    w6 = wl.WORKLOADS[6]
+    k = w6.k
+    log("graph search: topical 100k corpus")
+    c, q = wl.corpus(w6, device=dev), wl.queries(w6, device=dev)
+    D32 = gem.Sets(c.vecs, c.offsets, "f32", c.max_len())
+    Q = gem.Sets(q.vecs, q.offsets, "f32", q.max_len())
+    D8 = gem.quantize_fp8(D32)
+    C_quant, Dc, cb = build_codebook(D32, n_iter=8, assign="f32", seed=seed)
+    _, exact_ids = gem.score_exact(Q, D32, compute="f32", k=k)
+    t_exh = timed(lambda: gem.score_exact(Q, D32, cands=gem.Cands(gem.topk(gem.score_quant(gem.quantize_fp8(Q), D8),
+                                                                           1000)[1].reshape(-1), stride=1000,
+                                                                  n_lists=Q.n_sets), compute="f32", k=k), 1)
+    res = {"workload": w6.name, "docs": D32.n_sets, "doc_vectors": D32.n_vecs, "queries": Q.n_sets, "k": k,
+           "codebook_size": cb["codebook_size"], "exhaustive_fp8_rerank_ms": t_exh}
+    k2, r, t, degree, width = 128, 2, 4, 24, 4
+    rng = np.random.default_rng(seed)
+    init = torch.from_numpy(rng.choice(C_quant.shape[0], k2, replace=False).astype(np.int64))
+    t_idx, C_index = timed_once(lambda: gem.kmeans(C_quant, init, 6))
+    vc = gem.nearest_centroid(D32.vecs, C_index)
+    masks, moff, members = gs.set_clusters(vc, D32.offsets, k2, r)
+    torch.cuda.synchronize()
+    t_graph, nbrs = timed_once(lambda: gs.knn_graph(D32, D8, degree, batch=2000))
+    index = gs.ClusterIndex(nbrs, masks, moff, members, C_index)
+    res.update({"k2": k2, "r": r, "t": t, "degree": degree, "width": width, "index_kmeans_ms": t_idx,
+                "knn_graph_ms": t_graph, "mean_clusters_per_set": float(moff[-1].item()) / D32.n_sets})
+    Q8 = gem.quantize_fp8(Q)
+    n_q = Q.n_sets
+    words = torch.from_numpy(rng.integers(0, 2 ** 32, (n_q, k2), dtype=np.uint64).astype(np.uint32).view(np.int32))
+    words = words.to(dev)
+    runs = []
+    for ef in (32, 64, 128, 256):
+        def go(ef=ef):
+            qmask = gs.query_clusters(Q, C_index, t)
+            srch = gs.GraphSearch(Q8, D8, index, qmask, ef=ef, width=width)
+            srch.run(words, check_every=2)
+            return srch, srch.rerank(Q, D32, k)
+        go()                                                     # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        srch, (_, top) = go()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        vis = srch.visited.view(torch.uint8)
+        scored = torch.stack([(vis >> b) & 1 for b in range(8)]).sum().item() / n_q
+        tn, en = top.cpu().numpy(), exact_ids.cpu().numpy()
+        rec = float(np.mean([len(set(tn[i][:k]) & set(en[i][:k])) / k for i in range(n_q)]))
+        # of the exact top-k: the share the search scored at all, and the share in R
+        ex = exact_ids.long()
+        vbits = (srch.visited.gather(1, (ex >> 5)) >> (ex & 31)) & 1
+        reached = float(vbits.float().mean().item())
+        bi = srch.beam.ids.cpu().numpy()
+        in_r = float(np.mean([len(set(bi[i]) & set(en[i][:k])) / k for i in range(n_q)]))
+        runs.append({"ef": ef, "ms": ms, "qps": n_q / (ms / 1e3), "steps": srch.steps,
+                     "sets_scored_per_query": scored, f"recall_at_{k}_vs_f32_exact": rec,
+                     "exact_topk_scored": reached, "exact_topk_in_R": in_r})
+        log(f"graph search ef={ef}: {ms:.1f} ms for {n_q} queries, {srch.steps} steps, "
+            f"{scored:.0f} sets scored per query, recall@{k} {rec:.3f} (exact top-{k}: {reached:.3f} scored, "
+            f"{in_r:.3f} in R)")
+    res["runs"] = runs
+    # what bounds the recall: the share of the exact top-k that passes the
+    # cluster test, and the same search without it
+    qmask = gs.query_clusters(Q, C_index, t)
+    pm = masks[exact_ids.long()]                                    # [n_q, k, words]
+    res["exact_topk_passing_cluster_filter"] = float(((pm & qmask[:, None, :]) != 0).any(-1).float().mean().item())
+    srch = gs.GraphSearch(Q8, D8, index, torch.full_like(qmask, -1), ef=128, width=width)
+    srch.run(words, check_every=2)
+    _, top = srch.rerank(Q, D32, k)
+    tn, en = top.cpu().numpy(), exact_ids.cpu().numpy()
+    res["recall_without_cluster_filter_ef128"] = float(np.mean([len(set(tn[i][:k]) & set(en[i][:k])) / k
+                                                              for i in range(n_q)]))
+    log(f"exact top-{k} passing the cluster filter: {res['exact_topk_passing_cluster_filter']:.3f}; "
+        f"recall without the filter (ef 128): {res['recall_without_cluster_filter_ef128']:.3f}")
+    # EMD of graph edges (Sec. 4.2: the construction metric), on the vectors and
+    # as qEMD on the codes; entropic, eps 0.05, 50 Sinkhorn rounds
+    n_pairs = 20000
+    a_idx = torch.from_numpy(rng.integers(0, D32.n_sets, n_pairs).astype(np.int32)).to(dev)
+    b_idx = nbrs[a_idx.long(), 1].contiguous()
+    emd = {"pairs": n_pairs, "eps": 0.05, "n_iter": 50}
+    for name, S in (("emd_vectors", D32), ("qemd_codes", Dc)):
+        gem.emd_sinkhorn(S, S, a_idx[:64], b_idx[:64], 0.05, 50)
+        ms = timed(lambda S=S: gem.emd_sinkhorn(S, S, a_idx, b_idx, 0.05, 50), 1)
+        emd[name] = {"ms": ms, "pairs_per_s": n_pairs / (ms / 1e3)}
+        log(f"{name}: {n_pairs} pairs in {ms:.1f} ms")
+    res["emd_sinkhorn"] = emd
+    return res
+
+
 def cpu_baseline(q: wl.SetBatch, c: wl.SetBatch, n_sample: int):
     """The float64 oracle on a bounded sample of queries against the whole corpus."""
     import oracle
@@ -508,6 +603,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8, help="query sets in the CPU-oracle sample")
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--skip-expansion", action="store_true")
+    ap.add_argument("--skip-graph", action="store_true", help="skip the graph-search leg (Alg. 5)")
+    ap.add_argument("--only-graph", action="store_true", help="run the graph-search leg alone")
     ap.add_argument("--serve-rates", type=str, default="1000,2000,4000,8000,16000",
                     help="comma-separated arrival rates (1/s)")
     ap.add_argument("--serve-requests", type=int, default=1500, help="minimum requests per rate")
@@ -523,6 +620,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.only_graph:
+        print(json.dumps({"graph_search": bench_graph_search()}), flush=True)
+        return
     if args.only_expansion:
         res = bench_expansion(args)
         if args.copy_calibration:
@@ -550,6 +650,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.skip_expansion:
         line["beam_expansion"] = bench_expansion(args)
+        torch.cuda.empty_cache()
+    if not args.skip_graph:
+        line["graph_search"] = bench_graph_search()
     print(json.dumps(line), flush=True)
 
 

@@ -302,6 +302,25 @@ gem_status gem_beam_reset(gem_ctx ctx, gem_beam* beam, int64_t n_queries, hipStr
 gem_status gem_validate_sets(gem_ctx ctx, const gem_sets* S, hipStream_t stream);
 gem_status gem_validate_cands(gem_ctx ctx, const gem_cands* C, int64_t n_sets, hipStream_t stream);
 
+/* Entropic Earth Mover's Distance of set pairs (Sec. 4.2, Eq. EMD: the
+ * transport plan with row sums 1/m1 and column sums 1/m2 minimizing
+ * sum_ij t_ij d(p_i, p'_j), d Euclidean; with code sets it is Eq. qEMD over
+ * the centroids). The Sinkhorn iteration of Cuturi (2013) in the log domain:
+ * from g = 0, n_iter rounds of f_i = -log m1 - logsumexp_j(g_j - C_ij / eps),
+ * g_j = -log m2 - logsumexp_i(f_i - C_ij / eps); out[p] = sum_ij
+ * exp(f_i + g_j - C_ij / eps) C_ij for the pair (A set a_idx[p], B set
+ * b_idx[p]), float32 throughout. Converges to EMD from above as eps -> 0.
+ *   A, B: GEM_F32 sets or code sets over float32 codebooks; max_set_len <= 256.
+ *   a_idx, b_idx: [device] [n_pairs] set indices (trusted); out: [device]
+ *   [n_pairs]; an empty set gives NaN. eps > 0, 1 <= n_iter <= 100000.
+ *   ws: [device] gem_emd_workspace_bytes(n_pairs) bytes (pair flags, and the
+ *   cost matrices of pairs with more than 36864 entries, which a second pass
+ *   keeps in device memory instead of LDS). */
+size_t gem_emd_workspace_bytes(int64_t n_pairs);
+gem_status gem_emd_sinkhorn(gem_ctx ctx, const gem_sets* A, const gem_sets* B, const int32_t* a_idx,
+                            const int32_t* b_idx, int64_t n_pairs, float eps, int32_t n_iter, float* out, void* ws,
+                            size_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------- search
  * Cluster-guided beam search (Alg. 5, Sec. 4.5) for a batch of queries, over
  * a graph whose sets carry the set-level clusters of Sec. 4.1. */

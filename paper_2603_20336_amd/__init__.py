@@ -24,7 +24,8 @@ __all__ = ["Sets", "Cands", "Beam", "GemError", "convert_bf16", "quantize_fp8", 
            "score_quant", "topk", "expand_batch", "beam_merge", "beam_reset", "validate_sets", "validate_cands",
            "library", "GEM_F32", "GEM_BF16", "GEM_FP8_E4M3", "GEM_MXFP4", "quantize_mxfp4", "GEM_MAX_K", "GEM_MAX_QUERY_LEN", "dense_schedule",
            "set_dense_schedule", "autotune_dense", "copy_rows", "nearest_centroid", "centroid_update",
-           "kmeans", "encode", "codebook_size"]
+           "kmeans", "encode", "codebook_size",
+           "emd_sinkhorn"]
 
 _DTYPES = {"f32": GEM_F32, "bf16": GEM_BF16, "fp8": GEM_FP8_E4M3, "mxfp4": GEM_MXFP4,
            GEM_F32: GEM_F32, GEM_BF16: GEM_BF16, GEM_FP8_E4M3: GEM_FP8_E4M3, GEM_MXFP4: GEM_MXFP4}
@@ -363,6 +364,25 @@ def encode(S: Sets, centroids: torch.Tensor, assign: str = "f32", stream=None) -
     else:
         codes = nearest_centroid(S.vecs, centroids, stream)
     return Sets(centroids, S.offsets, GEM_F32, S.max_len, n_sets=S.n_sets, codes=codes)
+
+
+def emd_sinkhorn(A: Sets, B: Sets, a_idx: torch.Tensor, b_idx: torch.Tensor, eps: float = 0.05, n_iter: int = 100,
+                 stream=None) -> torch.Tensor:
+    """Entropic EMD (Sec. 4.2; Sinkhorn in the log domain) of the set pairs
+    (A[a_idx[p]], B[b_idx[p]]); float32 sets, or code sets over float32
+    codebooks for qEMD. Returns [n_pairs] float32 (NaN for an empty set)."""
+    for t in (a_idx, b_idx):
+        if t.dtype != torch.int32 or not t.is_contiguous():
+            raise TypeError("pair indices must be contiguous int32")
+    n = int(a_idx.numel())
+    out = torch.empty(n, dtype=torch.float32, device=A.device)
+    sa, sb = A.struct(), B.struct()
+    lib = library()
+    need = lib.gem_emd_workspace_bytes(n)
+    ws = _ws(need, A.device)
+    _abi.check(lib.gem_emd_sinkhorn(_ctx(A.device), ctypes.byref(sa), ctypes.byref(sb), _ptr(a_idx), _ptr(b_idx),
+                                    n, float(eps), int(n_iter), _ptr(out), _ptr(ws), need, _stream(stream)))
+    return out
 
 
 def _sched_dict(s) -> dict:

@@ -86,6 +86,8 @@ SIGNATURES = {
     "gem_nearest_centroid": (i32, [c_p, c_p, i64, c_p, i64, i32, i32, c_p, c_p, sz, c_p]),
     "gem_centroid_update": (i32, [c_p, c_p, i64, i32, c_p, c_p, i64, c_p, c_p, c_p, sz, c_p]),
     "gem_codebook_workspace_bytes": (sz, [i32, i64, i64]),
+    "gem_emd_sinkhorn": (i32, [c_p, P_SETS, P_SETS, c_p, c_p, i64, ctypes.c_float, i32, c_p, c_p, sz, c_p]),
+    "gem_emd_workspace_bytes": (sz, [i64]),
     "gem_set_clusters": (i32, [c_p, c_p, c_p, i64, i32, i32, c_p, c_p, c_p, c_p, sz, c_p]),
     "gem_query_clusters": (i32, [c_p, P_SETS, c_p, i32, i32, c_p, c_p]),
     "gem_search_begin": (i32, [c_p, P_SETS, P_SETS, ctypes.POINTER(gem_graph), ctypes.POINTER(gem_search_state),

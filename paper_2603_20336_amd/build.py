@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgem.so")
-SOURCES = ["capi.hip", "score.hip", "select.hip", "convert.hip", "codebook.hip", "search.hip"]
+SOURCES = ["capi.hip", "score.hip", "select.hip", "convert.hip", "codebook.hip", "search.hip", "emd.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -564,6 +564,31 @@ gem_status gem_expand_batch(gem_ctx ctx, const gem_sets* Q8, const gem_sets* D8,
   return GEM_OK;
 }
 
+size_t gem_emd_workspace_bytes(int64_t n_pairs) { return n_pairs > 0 ? emd_ws_bytes(n_pairs) : 0; }
+
+gem_status gem_emd_sinkhorn(gem_ctx ctx, const gem_sets* A, const gem_sets* B, const int32_t* a_idx,
+                            const int32_t* b_idx, int64_t n_pairs, float eps, int32_t n_iter, float* out, void* ws,
+                            size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  gem_status st;
+  if ((st = check_sets(A, "A", false)) != GEM_OK) return st;
+  if ((st = check_sets(B, "B", false)) != GEM_OK) return st;
+  if (A->dtype != GEM_F32 || B->dtype != GEM_F32) return fail(GEM_ERR_INVALID, "EMD takes float32 sets");
+  if (A->max_set_len > 256 || B->max_set_len > 256)
+    return fail(GEM_ERR_UNSUPPORTED, "set lengths %d, %d exceed 256", A->max_set_len, B->max_set_len);
+  if (!(eps > 0.0f) || eps > 1e30f) return fail(GEM_ERR_INVALID, "eps = %g", (double)eps);
+  if (n_iter < 1 || n_iter > 100000) return fail(GEM_ERR_INVALID, "n_iter = %d", n_iter);
+  if (n_pairs < 0) return fail(GEM_ERR_INVALID, "negative n_pairs");
+  if (n_pairs > 0 && (!a_idx || !b_idx || !out)) return fail(GEM_ERR_INVALID, "NULL buffer");
+  const size_t need = emd_ws_bytes(n_pairs);
+  if (n_pairs > 0 && (ws_bytes < need || !ws)) return fail(GEM_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+  EmdParams P;
+  P.A = view(A); P.B = view(B); P.a_idx = a_idx; P.b_idx = b_idx; P.n_pairs = n_pairs;
+  P.eps = eps; P.n_iter = n_iter; P.out = out;
+  hipError_t e = launch_emd_sinkhorn(P, ws, stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "emd");
+}
+
 gem_status gem_set_clusters(gem_ctx ctx, const int32_t* vec_clusters, const int64_t* set_offsets, int64_t n_sets,
                             int32_t k2, int32_t r, uint32_t* set_masks, int64_t* member_offsets, int32_t* members,
                             void* ws, size_t ws_bytes, hipStream_t stream) {

@@ -132,6 +132,24 @@ hipError_t launch_search_entries(const SearchView& S, int64_t n_q, const uint32_
 hipError_t launch_search_select(const SearchView& S, int64_t n_q, const int32_t* beam_ids, int32_t ef, hipStream_t s);
 hipError_t launch_search_expand(const SearchView& S, int64_t n_q, int32_t* cand, int32_t stride, hipStream_t s);
 
+// Entropic EMD of set pairs (one workgroup per pair).
+constexpr int kMaxEmdCost = 36864;     // entries of the LDS cost matrix (m1 * m2)
+constexpr int kEmdMaxSet = 256;        // longest set
+constexpr int kEmdBigBlocks = 256;     // workgroups of the pass over larger matrices
+struct EmdParams {
+  SetsView A, B;                       // float32 rows (or code sets over float32 codebooks)
+  const int32_t* a_idx;                // [n_pairs] sets of A
+  const int32_t* b_idx;                // [n_pairs] sets of B
+  int64_t n_pairs;
+  float eps;
+  int32_t n_iter;
+  float* out;                          // [n_pairs]
+  uint8_t* flags;                      // [n_pairs] workspace: pairs for the second pass
+  float* big;                          // workspace: kEmdBigBlocks matrices of kEmdMaxSet^2
+};
+size_t emd_ws_bytes(int64_t n_pairs);
+hipError_t launch_emd_sinkhorn(EmdParams P, void* ws, hipStream_t s);
+
 // Validation: returns number of violations found (synchronizes).
 hipError_t validate_sets(const SetsView& S, int64_t n_vecs, int is_fp8, hipStream_t s, int64_t* bad);
 hipError_t validate_cands(const CandsView& C, int64_t n_entries, int64_t n_sets, hipStream_t s, int64_t* bad);

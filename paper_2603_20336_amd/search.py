@@ -105,25 +105,48 @@ def query_clusters(Q32: Sets, centroids: torch.Tensor, t: int, stream=None) -> t
     return masks
 
 
-def knn_graph(D_as_queries: Sets, D: Sets, degree: int, batch: int = 2000, stream=None) -> torch.Tensor:
-    """A kNN graph of the document sets: row p lists the `degree` sets with the best
-    score(P, .) in D's dtype (P itself included), best first. D_as_queries holds
-    the same sets in a query-side dtype (float32 rows, converted per batch)."""
-    from . import score_exact, score_quant, topk, _QUANT
-    n = D.n_sets
-    out = torch.empty(n, degree, dtype=torch.int32, device=D.device)
-    scores = torch.empty(min(batch, n), n, dtype=torch.float32, device=D.device)
+def _score_any(Q: Sets, D: Sets, **kw):
+    from . import score_exact, score_quant, _QUANT
+    if D.dtype in _QUANT:
+        return score_quant(Q, D, **kw)
+    return score_exact(Q, D, compute=D.dtype, **kw)
+
+
+def knn_graph(D_as_queries: Sets, D: Sets, degree: int, candidates: int = 64, batch: int = 2000,
+              stream=None) -> torch.Tensor:
+    """A kNN graph of the document sets under the symmetric Chamfer similarity
+    CH(P, P') / |P| + CH(P', P) / |P'| (in D's dtype): row p lists the `degree`
+    best of P's `candidates` best sets by CH(P, .), best first, P itself left
+    out. CH of one direction favours long targets (a max over more vectors),
+    which makes the same long sets everyone's neighbours; the reverse term
+    cancels that. D_as_queries holds the same sets in a query-side dtype."""
+    from . import topk
+    n, dev = D.n_sets, D.device
+    cand = torch.empty(n, candidates, dtype=torch.int32, device=dev)
+    fwd = torch.empty(n, candidates, dtype=torch.float32, device=dev)
+    scores = torch.empty(min(batch, n), n, dtype=torch.float32, device=dev)
     for a in range(0, n, batch):
         b = min(n, a + batch)
-        Qb = D_as_queries.view(a, b)
         sc = scores[: b - a]
-        if D.dtype in _QUANT:
-            score_quant(Qb, D, scores=sc, stream=stream)
-        else:
-            score_exact(Qb, D, compute=D.dtype, scores=sc, stream=stream)
-        _, ids = topk(sc, degree, stream=stream)
-        out[a:b] = ids
-    return out
+        _score_any(D_as_queries.view(a, b), D, scores=sc, stream=stream)
+        s, ids = topk(sc, candidates, stream=stream)
+        fwd[a:b], cand[a:b] = s, ids
+    # reverse direction: CH(P', P) for every listed pair, the pairs grouped by P'
+    src = torch.arange(n, device=dev, dtype=torch.int64).repeat_interleave(candidates)
+    dst = cand.reshape(-1).long()
+    order = torch.argsort(dst, stable=True)
+    counts = torch.bincount(dst, minlength=n)
+    off = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    off[1:] = torch.cumsum(counts, 0)
+    rc = Cands(src[order].to(torch.int32).contiguous(), off, max_list_len=int(counts.max().item()))
+    rev_sorted = _score_any(D_as_queries, D, cands=rc, stream=stream)
+    rev = torch.empty_like(rev_sorted)
+    rev[order] = rev_sorted
+    lens = (D.offsets[1:] - D.offsets[:-1]).to(torch.float32)
+    sym = fwd / lens[:, None] + rev.reshape(n, candidates) / lens[cand.long()]
+    sym = torch.where(cand.long() == torch.arange(n, device=dev)[:, None], torch.full_like(sym, float("-inf")), sym)
+    _, pos = topk(sym, degree, stream=stream)
+    return torch.gather(cand, 1, pos.long())
 
 
 class ClusterIndex:

@@ -21,6 +21,14 @@ Recipe (every workload):
   * request arrivals: Poisson process                            (seed 4000 + rate index)
 where i is the workload number (1..5). Workloads 3 and 5 reuse workload 2's
 corpus; workload 3 also reuses its queries.
+
+Workload 6 (graph search) gives the sets topical structure, as passages of
+real text have: the K centres form T topics of K / T centres each, a topic's
+centres scattered around a topic direction (c = normalize(g_t + 0.5 eps /
+sqrt(d)), so that two centres of one topic have an inner product near 0.8);
+every set picks a topic and draws each vector's centre from it with
+probability 0.8, else from all K centres. Centres seed 600, topics and
+vectors seed 1006 (corpus) and 2006 (queries).
 """
 from __future__ import annotations
 
@@ -105,7 +113,14 @@ WORKLOADS = {
                 4096, ("uniform", 8, 64), 0, cands_per_step=512, steps=20, ef=1000),
     5: Workload(5, "serving-100k", 100_000, ("lognormal", 80.0, 0.5, 32, 256), 4096,
                 0, ("uniform", 4, 64), 100, shortlist=1000, corpus_of=2),
+    6: Workload(6, "graph-search-100k-topical", 100_000, ("lognormal", 80.0, 0.5, 32, 256), 4096,
+                1000, ("fixed", 32), 10),
 }
+
+# topical structure of workload 6
+TOPICS = 256
+TOPIC_SPREAD = 0.5
+P_TOPIC = 0.8
 
 
 def _gen(seed: int, device) -> torch.Generator:
@@ -168,13 +183,54 @@ def make_sets(n_sets: int, len_spec: tuple, centers: torch.Tensor, sigma: float,
     return SetBatch(vecs, off)
 
 
+def topical_centers(n_centers: int, n_topics: int, spread: float, seed: int, device="cpu", dim: int = DIM):
+    """Centres grouped into topics: centre k belongs to topic k // (K / T) and is
+    normalize(g_t + spread * eps / sqrt(d)) for the topic's direction g_t (float64)."""
+    g = _gen(seed, device)
+    dirs = torch.randn(n_topics, dim, generator=g, dtype=torch.float64, device=device)
+    dirs = dirs / dirs.norm(dim=1, keepdim=True)
+    per = n_centers // n_topics
+    eps = torch.randn(n_topics * per, dim, generator=g, dtype=torch.float64, device=device)
+    c = dirs.repeat_interleave(per, 0) + (spread / math.sqrt(dim)) * eps
+    return c / c.norm(dim=1, keepdim=True)
+
+
+def topical_sets(n_sets: int, len_spec: tuple, centers: torch.Tensor, n_topics: int, p_topic: float, sigma: float,
+                 seed: int) -> SetBatch:
+    """Sets whose vectors come from their topic's centres with probability p_topic."""
+    device = centers.device
+    K, dim = centers.shape
+    per = K // n_topics
+    g = _gen(seed, device)
+    lens = set_lengths(n_sets, len_spec, g, device)
+    off = _csr(lens)
+    n = int(off[-1].item())
+    topic = torch.randint(0, n_topics, (n_sets,), generator=g, device=device)
+    owner = torch.repeat_interleave(torch.arange(n_sets, device=device), lens)
+    in_topic = torch.rand(n, generator=g, device=device, dtype=torch.float64) < p_topic
+    z_topic = topic[owner] * per + torch.randint(0, per, (n,), generator=g, device=device)
+    z_any = torch.randint(0, K, (n,), generator=g, device=device)
+    z = torch.where(in_topic, z_topic, z_any)
+    out = torch.empty(n, dim, dtype=torch.float32, device=device)
+    chunk = 1 << 21
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        eps = torch.randn(b - a, dim, generator=g, dtype=torch.float64, device=device)
+        x = centers[z[a:b]] + sigma * eps
+        out[a:b] = (x / x.norm(dim=1, keepdim=True)).to(torch.float32)
+    return SetBatch(out, off)
+
+
 def corpus(w: Workload, device="cpu", n_docs: Optional[int] = None) -> SetBatch:
     """The workload's document corpus (n_docs overrides the size for small tests)."""
     src = WORKLOADS[w.corpus_of] if w.corpus_of else w
     i = src.number
+    n = n_docs if n_docs is not None else src.n_docs
+    if i == 6:
+        centers = topical_centers(src.n_centers, TOPICS, TOPIC_SPREAD, 600, device)
+        return topical_sets(n, src.doc_len, centers, TOPICS, P_TOPIC, src.sigma, 1000 + i)
     centers = mixture_centers(src.n_centers, 100 + i, device)
-    return make_sets(n_docs if n_docs is not None else src.n_docs, src.doc_len, centers,
-                     src.sigma, 1000 + i)
+    return make_sets(n, src.doc_len, centers, src.sigma, 1000 + i)
 
 
 def queries(w: Workload, device="cpu", n_queries: Optional[int] = None,
@@ -182,8 +238,11 @@ def queries(w: Workload, device="cpu", n_queries: Optional[int] = None,
     """The workload's query sets, drawn from the corpus's mixture."""
     src = WORKLOADS[w.corpus_of] if w.corpus_of else w
     qsrc = WORKLOADS[w.queries_of] if w.queries_of else w
-    centers = mixture_centers(src.n_centers, 100 + src.number, device)
     n = n_queries if n_queries is not None else qsrc.n_queries
+    if src.number == 6:
+        centers = topical_centers(src.n_centers, TOPICS, TOPIC_SPREAD, 600, device)
+        return topical_sets(n, query_len or qsrc.query_len, centers, TOPICS, P_TOPIC, src.sigma, 2000 + qsrc.number)
+    centers = mixture_centers(src.n_centers, 100 + src.number, device)
     return make_sets(n, query_len or qsrc.query_len, centers, src.sigma, 2000 + qsrc.number)
 
 
