@@ -113,13 +113,16 @@ def _score_any(Q: Sets, D: Sets, **kw):
 
 
 def knn_graph(D_as_queries: Sets, D: Sets, degree: int, candidates: int = 64, batch: int = 2000,
-              stream=None) -> torch.Tensor:
-    """A kNN graph of the document sets under the symmetric Chamfer similarity
-    CH(P, P') / |P| + CH(P', P) / |P'| (in D's dtype): row p lists the `degree`
-    best of P's `candidates` best sets by CH(P, .), best first, P itself left
-    out. CH of one direction favours long targets (a max over more vectors),
-    which makes the same long sets everyone's neighbours; the reverse term
-    cancels that. D_as_queries holds the same sets in a query-side dtype."""
+              forward: Optional[int] = None, stream=None) -> torch.Tensor:
+    """A kNN graph of the document sets (scores in D's dtype): row p lists
+    `forward` sets by CH(P, .), then the best of the rest of P's `candidates`
+    by the symmetric Chamfer similarity CH(P, P') / |P| + CH(P', P) / |P'|,
+    P itself left out (default: half and half). CH of one direction favours
+    long targets (a max over more vectors), as queries do; alone it makes the
+    same long sets everyone's neighbours, and the symmetric half keeps the
+    rest of the neighbourhood reachable. D_as_queries holds the same sets in a
+    query-side dtype."""
+    forward = degree // 2 if forward is None else int(forward)
     from . import topk
     n, dev = D.n_sets, D.device
     cand = torch.empty(n, candidates, dtype=torch.int32, device=dev)
@@ -144,9 +147,14 @@ def knn_graph(D_as_queries: Sets, D: Sets, degree: int, candidates: int = 64, ba
     rev[order] = rev_sorted
     lens = (D.offsets[1:] - D.offsets[:-1]).to(torch.float32)
     sym = fwd / lens[:, None] + rev.reshape(n, candidates) / lens[cand.long()]
-    sym = torch.where(cand.long() == torch.arange(n, device=dev)[:, None], torch.full_like(sym, float("-inf")), sym)
-    _, pos = topk(sym, degree, stream=stream)
-    return torch.gather(cand, 1, pos.long())
+    own = cand.long() == torch.arange(n, device=dev)[:, None]
+    # forward part: the best by CH(P, .) (candidates are sorted), P left out
+    rank = torch.cumsum((~own).to(torch.int32), 1) - 1
+    take_fwd = (~own) & (rank < forward)
+    sym = torch.where(own | take_fwd, torch.full_like(sym, float("-inf")), sym)
+    _, pos = topk(sym, degree - forward, stream=stream)
+    fwd_ids = cand.masked_select(take_fwd).reshape(n, forward)
+    return torch.cat([fwd_ids, torch.gather(cand, 1, pos.long())], 1).contiguous()
 
 
 class ClusterIndex:

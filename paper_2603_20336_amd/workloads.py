@@ -27,8 +27,10 @@ real text have: the K centres form T topics of K / T centres each, a topic's
 centres scattered around a topic direction (c = normalize(g_t + 0.5 eps /
 sqrt(d)), so that two centres of one topic have an inner product near 0.8);
 every set picks a topic and draws each vector's centre from it with
-probability 0.8, else from all K centres. Centres seed 600, topics and
-vectors seed 1006 (corpus) and 2006 (queries).
+probability 0.8, else from all K centres. T = 64 topics of 64 centres, so
+that a topic holds about 1,500 sets, the cluster size the paper aims its
+coarse clusters at (Sec. 5.1). Centres seed 600, topics and vectors seed 1006
+(corpus) and 2006 (queries).
 """
 from __future__ import annotations
 
@@ -118,7 +120,7 @@ WORKLOADS = {
 }
 
 # topical structure of workload 6
-TOPICS = 256
+TOPICS = 64
 TOPIC_SPREAD = 0.5
 P_TOPIC = 0.8
 
