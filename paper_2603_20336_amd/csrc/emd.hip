@@ -11,10 +11,10 @@
 //
 // One workgroup per pair. Thread i < m1 holds row i of the first set in
 // registers; the second set streams through LDS in chunks of 16 rows; the
-// matrix -C / eps stays in LDS for the whole iteration (at most kMaxEmdCost
-// entries), or for larger pairs in a slice of the workspace (a second pass
-// over the pairs the first one flagged). Every reduction runs in a fixed
-// order, so the result does not depend on the batch.
+// matrix of -C / eps (base 2) stays in LDS for the whole iteration (at most
+// kMaxEmdCost entries), or for larger pairs in a slice of the workspace (a
+// second pass over the pairs the first one flagged). Every reduction runs in
+// a fixed order, so the result does not depend on the batch.
 #include <algorithm>
 
 #include "device_common.hpp"
@@ -27,37 +27,70 @@ constexpr int kEmdThreads = 256;
 constexpr int kChunk = 16;
 }  // namespace
 
-__device__ __forceinline__ float wave_sum(float v) {
+// One thread per row (then per column) of the matrix: each logsumexp is a
+// serial two-pass loop (max, then the sum of powers) with no cross-lane work.
+// The matrix is stored with an odd row stride, so the row pass (threads walk
+// their own rows) and the column pass (threads walk their own columns) both
+// read distinct LDS banks. The iteration runs in base 2: with L_ij = -C_ij
+// log2(e) / eps and potentials in log2 units it is the same iteration (every
+// term scaled by log2 e), evaluated with the hardware exp2 / log2.
+__device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+
+// log2 of sum_k 2^(p[k * ps] + q[k * qs]) over k < n: the maximum, then the
+// sum of powers, each over eight interleaved partial results (eight loads in
+// flight: a workgroup per CU leaves few waves to hide LDS latency), combined
+// in a fixed order.
+__device__ __forceinline__ float lse2(const float* p, int ps, const float* q, int qs, int n) {
+  constexpr int U = 8;
+  float m[U];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  for (int u = 0; u < U; ++u) m[u] = -INFINITY;
+  int k = 0;
+  for (; k + U <= n; k += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) m[u] = fmaxf(m[u], p[(k + u) * ps] + q[(k + u) * qs]);
+  }
+  for (int u = 0; k + u < n; ++u) m[u] = fmaxf(m[u], p[(k + u) * ps] + q[(k + u) * qs]);
+  float mx = m[0];
+#pragma unroll
+  for (int u = 1; u < U; ++u) mx = fmaxf(mx, m[u]);
+  float sm[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) sm[u] = 0.0f;
+  k = 0;
+  for (; k + U <= n; k += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) sm[u] += hw_exp2(p[(k + u) * ps] + q[(k + u) * qs] - mx);
+  }
+  for (int u = 0; k + u < n; ++u) sm[u] += hw_exp2(p[(k + u) * ps] + q[(k + u) * qs] - mx);
+  float s = sm[0];
+#pragma unroll
+  for (int u = 1; u < U; ++u) s += sm[u];
+  return mx + hw_log2(s);
 }
 
-__device__ __forceinline__ float wave_max_f(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  return v;
-}
-
-// kBig = false: pairs whose matrix fits LDS (kMaxEmdCost entries); larger
-// pairs are flagged for the second pass. kBig = true: the flagged pairs, the
-// matrix in this workgroup's slice of the workspace (kMaxSetLen^2 floats).
+// kBig = false: pairs whose matrix fits LDS (kMaxEmdCost entries, stride
+// included); larger pairs are flagged for the second pass. kBig = true: the
+// flagged pairs, the matrix in this workgroup's slice of the workspace.
 template <bool kBig>
 __global__ __launch_bounds__(kEmdThreads) void emd_sinkhorn_kernel(EmdParams P) {
-  __shared__ float K_lds[kBig ? 1 : kMaxEmdCost];   // -C / eps, row-major [m1][m2]
+  __shared__ float K_lds[kBig ? 1 : kMaxEmdCost];   // L = -C log2(e) / eps, [m1][stride]
   __shared__ float fpot[kEmdMaxSet], gpot[kEmdMaxSet];
   __shared__ float brow[kChunk][kDim];
-  __shared__ float red[kEmdThreads / 64];
-  const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const float inv_eps = 1.0f / P.eps;
-  float* K = kBig ? P.big + (int64_t)blockIdx.x * kEmdMaxSet * kEmdMaxSet : K_lds;
+  __shared__ float red[kEmdThreads];
+  const int t = threadIdx.x;
+  const float kLog2e = 1.4426950408889634f;
+  const float scale = kLog2e / P.eps;                // L = -C * scale
+  float* K = kBig ? P.big + (int64_t)blockIdx.x * kEmdMaxSet * (kEmdMaxSet + 1) : K_lds;
   for (int64_t pr = blockIdx.x; pr < P.n_pairs; pr += gridDim.x) {
     if (kBig && !P.flags[pr]) continue;
     const int64_t ia = P.a_idx[pr], ib = P.b_idx[pr];
     const int64_t a0 = P.A.off[ia], b0 = P.B.off[ib];
     const int m1 = (int)(P.A.off[ia + 1] - a0), m2 = (int)(P.B.off[ib + 1] - b0);
+    const int ld = m2 | 1;                                    // odd row stride
     if (!kBig) {
-      const bool big = m1 * m2 > kMaxEmdCost && m1 <= kEmdMaxSet && m2 <= kEmdMaxSet;
+      const bool big = m1 * ld > kMaxEmdCost && m1 <= kEmdMaxSet && m2 <= kEmdMaxSet;
       if (t == 0) P.flags[pr] = big ? 1 : 0;
       // no transport plan for an empty set, nor for a set longer than the
       // bound the host checked: NaN; large matrices wait for the second pass
@@ -77,7 +110,7 @@ __global__ __launch_bounds__(kEmdThreads) void emd_sinkhorn_kernel(EmdParams P) 
         a[4 * i] = v.x; a[4 * i + 1] = v.y; a[4 * i + 2] = v.z; a[4 * i + 3] = v.w;
       }
     }
-    // -C / eps, 16 rows of the second set at a time
+    // L, 16 rows of the second set at a time
     for (int j0 = 0; j0 < m2; j0 += kChunk) {
       const int nj = min(kChunk, m2 - j0);
       for (int e = t; e < nj * kDim; e += kEmdThreads) {
@@ -94,53 +127,31 @@ __global__ __launch_bounds__(kEmdThreads) void emd_sinkhorn_kernel(EmdParams P) 
             const float df = a[d] - brow[jj][d];
             s = fmaf(df, df, s);
           }
-          K[t * m2 + j0 + jj] = -sqrtf(s) * inv_eps;
+          K[t * ld + j0 + jj] = -sqrtf(s) * scale;
         }
       }
       __syncthreads();
     }
-    const float la = -logf((float)m1), lb = -logf((float)m2);
-    for (int j = t; j < m2; j += kEmdThreads) gpot[j] = 0.0f;
+    const float la = -hw_log2((float)m1), lb = -hw_log2((float)m2);
+    if (t < m2) gpot[t] = 0.0f;
     __syncthreads();
     for (int it = 0; it < P.n_iter; ++it) {
-      // rows: one wave per row, lanes over the columns
-      for (int i = w; i < m1; i += kEmdThreads / 64) {
-        float mx = neg_inf();
-        for (int j = l; j < m2; j += 64) mx = fmaxf(mx, gpot[j] + K[i * m2 + j]);
-        mx = wave_max_f(mx);
-        float s = 0.0f;
-        for (int j = l; j < m2; j += 64) s += expf(gpot[j] + K[i * m2 + j] - mx);
-        s = wave_sum(s);
-        if (l == 0) fpot[i] = la - (mx + logf(s));
-      }
+      if (t < m1) fpot[t] = la - lse2(gpot, 1, K + t * ld, 1, m2);    // row t
       __syncthreads();
-      // columns: one wave per column, lanes over the rows
-      for (int j = w; j < m2; j += kEmdThreads / 64) {
-        float mx = neg_inf();
-        for (int i = l; i < m1; i += 64) mx = fmaxf(mx, fpot[i] + K[i * m2 + j]);
-        mx = wave_max_f(mx);
-        float s = 0.0f;
-        for (int i = l; i < m1; i += 64) s += expf(fpot[i] + K[i * m2 + j] - mx);
-        s = wave_sum(s);
-        if (l == 0) gpot[j] = lb - (mx + logf(s));
-      }
+      if (t < m2) gpot[t] = lb - lse2(fpot, 1, K + t, ld, m1);       // column t
       __syncthreads();
     }
-    // cost of the plan: rows over the waves, then the waves in order
+    // cost of the plan: each thread its row, then the rows in order
     float acc = 0.0f;
-    for (int i = w; i < m1; i += kEmdThreads / 64) {
-      float s = 0.0f;
-      for (int j = l; j < m2; j += 64) {
-        const float k = K[i * m2 + j];
-        s += expf(fpot[i] + gpot[j] + k) * (-k * P.eps);
-      }
-      acc += wave_sum(s);
+    if (t < m1) {
+      const float* row = K + t * ld;
+      for (int j = 0; j < m2; ++j) acc += hw_exp2(fpot[t] + gpot[j] + row[j]) * (-row[j] / scale);
     }
-    if (l == 0) red[w] = acc;
+    red[t] = acc;
     __syncthreads();
     if (t == 0) {
       float tot = 0.0f;
-      for (int i = 0; i < kEmdThreads / 64; ++i) tot += red[i];
+      for (int i = 0; i < m1; ++i) tot += red[i];
       P.out[pr] = tot;
     }
     __syncthreads();
@@ -148,7 +159,7 @@ __global__ __launch_bounds__(kEmdThreads) void emd_sinkhorn_kernel(EmdParams P) 
 }
 
 size_t emd_ws_bytes(int64_t n_pairs) {
-  return (((size_t)n_pairs + 255) & ~(size_t)255) + (size_t)kEmdBigBlocks * kEmdMaxSet * kEmdMaxSet * 4;
+  return (((size_t)n_pairs + 255) & ~(size_t)255) + (size_t)kEmdBigBlocks * kEmdMaxSet * (kEmdMaxSet + 1) * 4;
 }
 
 hipError_t launch_emd_sinkhorn(EmdParams P, void* ws, hipStream_t s) {
