@@ -132,7 +132,7 @@ def bench_graph_search(seed: int = 13):
         def go(ef=ef):
             qmask = gs.query_clusters(Q, C_index, t)
             srch = gs.GraphSearch(Q8, D8, index, qmask, ef=ef, width=width)
-            srch.run(words, check_every=2)
+            srch.run(words, check_every=4)                      # 4 steps per graph replay
             return srch, srch.rerank(Q, D32, k)
         go()                                                     # warm-up
         torch.cuda.synchronize()
@@ -163,7 +163,7 @@ def bench_graph_search(seed: int = 13):
     pm = masks[exact_ids.long()]                                    # [n_q, k, words]
     res["exact_topk_passing_cluster_filter"] = float(((pm & qmask[:, None, :]) != 0).any(-1).float().mean().item())
     srch = gs.GraphSearch(Q8, D8, index, torch.full_like(qmask, -1), ef=128, width=width)
-    srch.run(words, check_every=2)
+    srch.run(words, check_every=4)
     _, top = srch.rerank(Q, D32, k)
     tn, en = top.cpu().numpy(), exact_ids.cpu().numpy()
     res["recall_without_cluster_filter_ef128"] = float(np.mean([len(set(tn[i][:k]) & set(en[i][:k])) / k

@@ -183,7 +183,7 @@ class GraphSearch:
     def __init__(self, Q: Sets, D: Sets, index: ClusterIndex, query_masks: torch.Tensor, ef: int, width: int = 4):
         from . import _abi, _ptr
         self.Q, self.D, self.index = Q, D, index
-        dev = D.device
+        dev = self.device = D.device
         n_q, n = Q.n_sets, D.n_sets
         deg = int(index.neighbors.shape[1])
         self.row = max(index.k2, width * deg)
@@ -204,6 +204,8 @@ class GraphSearch:
         self._state, self._graph = st, index.struct()
         self._qs, self._ds = Q.struct(), D.struct()
         self.steps = 0
+        self._hip_graph: Optional[torch.cuda.CUDAGraph] = None
+        self._hip_graph_steps = 0
 
     def begin(self, random_words: torch.Tensor, stream=None) -> None:
         """random_words: [n_q, k2] uint32 (int32 bit patterns) drawn by the caller."""
@@ -221,10 +223,36 @@ class GraphSearch:
                                        ctypes.byref(self._state), ctypes.byref(self.beam.struct()), _stream(stream)))
         self.steps += 1
 
-    def run(self, random_words: torch.Tensor, max_steps: int = 10000, check_every: int = 2, stream=None) -> int:
-        """Search until no query has anything left to expand (checked every
-        `check_every` steps; a finished query's extra steps change nothing)."""
+    def capture(self, n_steps: int) -> None:
+        """Record n_steps search steps into one HIP graph. Every step reads and
+        writes only this object's device buffers, so the graph replays on any
+        state that begin() left there (recording runs nothing)."""
+        s = torch.cuda.Stream(device=self.device)
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(n_steps):
+                self.step(s)
+        torch.cuda.current_stream(self.device).wait_stream(s)
+        self.steps = 0
+        self._hip_graph, self._hip_graph_steps = g, n_steps
+
+    def run(self, random_words: torch.Tensor, max_steps: int = 10000, check_every: int = 4, graph: bool = True,
+            stream=None) -> int:
+        """Search until no query has anything left to expand, checking every
+        `check_every` steps (a finished query's extra steps change nothing).
+        With graph=True the block of steps between checks is one replay of a
+        captured HIP graph."""
         self.begin(random_words, stream)
+        if graph:
+            if self._hip_graph is None or self._hip_graph_steps != check_every:
+                self.capture(check_every)
+            while self.steps < max_steps:
+                self._hip_graph.replay()
+                self.steps += check_every
+                if int(self.active.item()) == 0:
+                    break
+            return self.steps
         while self.steps < max_steps:
             for _ in range(check_every):
                 self.step(stream)

@@ -115,8 +115,17 @@ def test_search_matches_oracle_exactly(ef, width):
                             torch.zeros(k2, 128, device=DEV))
     qmask = torch.from_numpy(_masks(cq, k2).view(np.int32)).to(DEV)
     srch = gs.GraphSearch(Q8, D8, index, qmask, ef=ef, width=width)
-    steps = srch.run(torch.from_numpy(u.astype(np.uint32).view(np.int32)).to(DEV), check_every=1)
+    words = torch.from_numpy(u.astype(np.uint32).view(np.int32)).to(DEV)
+    steps = srch.run(words, check_every=1, graph=False)
     bs, bi = _np(srch.beam.scores), _np(srch.beam.ids)
+    # the same search from a captured graph of 3 steps, replayed, twice over
+    # (with eager work and synchronizations between the runs)
+    for _ in range(2):
+        srch.run(words, check_every=3, graph=True)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(_np(srch.beam.ids), bi)
+        np.testing.assert_array_equal(_np(srch.beam.scores), bs)
+        gem.score_quant(Q8, D8, k=2)
     # the oracle on the same (exact) operand values
     dvals = oracle.dequantize_fp8(*oracle.quantize_fp8(dv))
     qvals = oracle.dequantize_fp8(*oracle.quantize_fp8(qv))
