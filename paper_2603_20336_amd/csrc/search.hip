@@ -42,8 +42,10 @@ __global__ __launch_bounds__(256) void set_df_kernel(const int32_t* __restrict__
                                                      int64_t n_sets, int k2, int32_t* __restrict__ df) {
   __shared__ int hist[4][kMaxClusters];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int64_t s = (int64_t)blockIdx.x * 4 + w; s < n_sets + 3; s += (int64_t)gridDim.x * 4) {
-    // (every wave runs the same number of rounds: the barriers stay uniform)
+  // rounds over the workgroup's base index: every wave runs the same rounds,
+  // so the barriers stay uniform
+  for (int64_t base = (int64_t)blockIdx.x * 4; base < n_sets; base += (int64_t)gridDim.x * 4) {
+    const int64_t s = base + w;
     const bool live = s < n_sets;
     for (int j = l; j < k2; j += 64) hist[w][j] = 0;
     __syncthreads();
@@ -69,7 +71,8 @@ __global__ __launch_bounds__(256) void set_top_clusters_kernel(const int32_t* __
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int words = (k2 + 31) / 32;
   const float n = (float)n_sets;
-  for (int64_t s = (int64_t)blockIdx.x * 4 + w; s < n_sets + 3; s += (int64_t)gridDim.x * 4) {
+  for (int64_t base = (int64_t)blockIdx.x * 4; base < n_sets; base += (int64_t)gridDim.x * 4) {
+    const int64_t s = base + w;
     const bool live = s < n_sets;
     for (int j = l; j < k2; j += 64) hist[w][j] = 0;
     __syncthreads();
@@ -170,7 +173,7 @@ hipError_t launch_set_clusters(const int32_t* vec_clusters, const int64_t* set_o
   int32_t* df = ws;
   int32_t* counts = ws + kMaxClusters;
   hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(256), 0, s, ws, (int64_t)(2 * kMaxClusters), 0);
-  const unsigned g = capped_blocks((n_sets + 3) / 4 + 1, 256);
+  const unsigned g = capped_blocks((n_sets + 3) / 4, 256);
   if (n_sets > 0) {
     hipLaunchKernelGGL(set_df_kernel, dim3(g), dim3(256), 0, s, vec_clusters, set_off, n_sets, k2, df);
     hipLaunchKernelGGL(set_top_clusters_kernel, dim3(g), dim3(256), 0, s, vec_clusters, set_off, n_sets, k2, r, df,
