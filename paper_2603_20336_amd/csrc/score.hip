@@ -242,14 +242,23 @@ template <int DT> struct TileStage {
   static constexpr int kGroup = DenseCfg<DT>::kGroup;
   static constexpr int kGroupVecs = kGroup * kStageBytes / 16;  // one group buffer in 16-byte units
   // a group's piece copies are slots s = u * kPieceWaves + role (tile u,
-  // 1 KiB piece `role`), and wave w issues slots w, w + 8, w + 16, ...; FP8
-  // scale copies go to wave u % 8. Every wave issues the same copies.
+  // 1 KiB piece `role`); wave w issues the contiguous slots [w K, w K + K)
+  // (K = kPieceCopiesPerWave), which lie in one tile, so that one document
+  // lookup serves all of them; the scale copies of that tile are the same
+  // wave's. Every wave issues the same number of copies.
   static constexpr int kPieceCopiesPerWave = kGroup * kPieceWaves / kDenseWaves;
   static constexpr int kScaleCopiesPerWave = kScales ? kGroup / kDenseWaves : 0;
   static constexpr int kCopiesPerWave = kPieceCopiesPerWave + kScaleCopiesPerWave;
   static_assert(kSlots % 64 == 0, "tile copy layout");
   static_assert((kGroup * kPieceWaves) % kDenseWaves == 0 && (!kScales || kGroup % kDenseWaves == 0),
                 "copies must spread evenly over the waves");
+  static_assert(kPieceCopiesPerWave <= kPieceWaves && kPieceWaves % kPieceCopiesPerWave == 0,
+                "a wave's piece copies lie in one tile");
+  static_assert(!kScales || (kPieceCopiesPerWave == kPieceWaves && kScaleCopiesPerWave == 1),
+                "a wave copies the scales of its own tile");
+  // the tile of the group that wave w copies, and the piece of its copy j
+  static __device__ __forceinline__ int wave_tile(int w) { return w * kPieceCopiesPerWave / kPieceWaves; }
+  static __device__ __forceinline__ int wave_piece(int w, int j) { return (w * kPieceCopiesPerWave + j) % kPieceWaves; }
   static_assert(kStageBytes % 16 == 0, "stage alignment");
 
   // chunk c of row r sits at position c ^ swz(r): the 16 rows read by one
@@ -365,12 +374,13 @@ template <int DT> struct DensePass {
   uint64_t first_mask, last_mask;
 
   // one document tile against the pass's column tiles (all of them when
-  // kFull); at a document's last tile, park its tile sums in column dd of the
-  // wave's LDS array (the first lane of each 16-lane row stores that row's sum)
+  // kFull; a group past the last used tile is skipped, and unused tiles
+  // inside a group have zero B operands and are never summed), then the next
+  // tile's A operand, read into A once the last product has taken it. At a
+  // document's last tile its tile sums are parked in column dd of the wave's
+  // LDS array (the first lane of each 16-lane row stores that row's sum).
   template <bool kFull>
-  __device__ __forceinline__ void tile(const Frag& A, uint64_t end_mask) {
-    // column tiles in groups of 4 (a group past the last used tile is skipped;
-    // unused tiles inside a group have zero B operands and are never summed)
+  __device__ __forceinline__ void tile(Frag& A, const u32x4* next, int c16, int g, uint64_t end_mask) {
 #pragma unroll
     for (int g0 = 0; g0 < NT; g0 += 4) {
       if (kFull || g0 < nct) {
@@ -382,10 +392,12 @@ template <int DT> struct DensePass {
 #pragma unroll
           for (int c = 0; c < 4; ++c) acc[c] = O::mma(A, B[g0 + c], acc[c], s);
         }
+        if (kFull && g0 + 4 == NT) frag_from_lds<DT>(A, next, c16, g);
 #pragma unroll
         for (int c = 0; c < 4; ++c) update_max(rm[g0 + c], acc[c]);
       }
     }
+    if (!kFull) frag_from_lds<DT>(A, next, c16, g);
     if (end_mask) {
       const int dd = __builtin_ctzll(end_mask);
       float Rs[NT / 4];
@@ -541,61 +553,41 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
       auto fetch_codes = [&](auto zbuf, int G) {
         constexpr int Z = decltype(zbuf)::value;
         int32_t* cb = (Z == 0 ? lds_code0 : (Z == 1 ? lds_code1 : lds_code2)) + w * kCodeCopies * 64;
+        int k, rs, re;
+        locate(min(G * kGroup + TS::wave_tile(w), n_tiles - 1), k, rs, re);
 #pragma unroll
-        for (int j = 0; j < TS::kPieceCopiesPerWave; ++j) {
-          const int slot_j = kDenseWaves * j + w;
-          const int u = slot_j / TS::kPieceWaves, role = slot_j % TS::kPieceWaves;
-          int k, rs, re;
-          locate(min(G * kGroup + u, n_tiles - 1), k, rs, re);
-          __builtin_amdgcn_global_load_lds(P.D.codes + TS::piece_entry(base, rs, re, k, role, l),
+        for (int j = 0; j < TS::kPieceCopiesPerWave; ++j)
+          __builtin_amdgcn_global_load_lds(P.D.codes + TS::piece_entry(base, rs, re, k, TS::wave_piece(w, j), l),
                                            (lds_void_ptr)(cb + 64 * j), 4, 0, 0);
-        }
 #pragma unroll
-        for (int j = 0; j < TS::kScaleCopiesPerWave; ++j) {
-          const int u = kDenseWaves * j + w;
-          int k, rs, re;
-          locate(min(G * kGroup + u, n_tiles - 1), k, rs, re);
+        for (int j = 0; j < TS::kScaleCopiesPerWave; ++j)
           __builtin_amdgcn_global_load_lds(P.D.codes + base + min(rs + 16 * k + (l & 15), re - 1),
                                            (lds_void_ptr)(cb + 64 * (TS::kPieceCopiesPerWave + j)), 4, 0, 0);
-        }
       };
       auto issue = [&](auto ybuf, int G) {
         constexpr int Y = decltype(ybuf)::value;
         u32x4* buf = Y == 0 ? lds_buf0 : (Y == 1 ? lds_buf1 : lds_buf2);
+        u32x4* stage = buf + TS::wave_tile(w) * (TS::kStageBytes / 16);
         if constexpr (kCodes) {
           // this group's codes (array Y, fetched two groups ago), then the
           // codes of group G + 2 into the array whose group is already issued
           const int32_t* cb = (Y == 0 ? lds_code0 : (Y == 1 ? lds_code1 : lds_code2)) + w * kCodeCopies * 64;
 #pragma unroll
-          for (int j = 0; j < TS::kPieceCopiesPerWave; ++j) {
-            const int slot_j = kDenseWaves * j + w;
-            const int u = slot_j / TS::kPieceWaves, role = slot_j % TS::kPieceWaves;
-            TS::copy_piece_row(P.D.vecs, (int64_t)cb[64 * j + l], buf + u * (TS::kStageBytes / 16), role, l);
-          }
+          for (int j = 0; j < TS::kPieceCopiesPerWave; ++j)
+            TS::copy_piece_row(P.D.vecs, (int64_t)cb[64 * j + l], stage, TS::wave_piece(w, j), l);
 #pragma unroll
-          for (int j = 0; j < TS::kScaleCopiesPerWave; ++j) {
-            const int u = kDenseWaves * j + w;
+          for (int j = 0; j < TS::kScaleCopiesPerWave; ++j)
             __builtin_amdgcn_global_load_lds(P.D.scales + cb[64 * (TS::kPieceCopiesPerWave + j) + l],
-                                             (lds_void_ptr)(buf + u * (TS::kStageBytes / 16) + TS::kTileBytes / 16),
-                                             4, 0, 0);
-          }
+                                             (lds_void_ptr)(stage + TS::kTileBytes / 16), 4, 0, 0);
           fetch_codes(std::integral_constant<int, (Y + 2) % 3>{}, G + 2);
         } else {
+          int k, rs, re;
+          locate(min(G * kGroup + TS::wave_tile(w), n_tiles - 1), k, rs, re);
 #pragma unroll
-          for (int j = 0; j < TS::kPieceCopiesPerWave; ++j) {
-            const int slot_j = kDenseWaves * j + w;
-            const int u = slot_j / TS::kPieceWaves, role = slot_j % TS::kPieceWaves;
-            int k, rs, re;
-            locate(min(G * kGroup + u, n_tiles - 1), k, rs, re);
-            TS::copy_piece(P.D.vecs, base, rs, re, k, buf + u * (TS::kStageBytes / 16), role, l);
-          }
+          for (int j = 0; j < TS::kPieceCopiesPerWave; ++j)
+            TS::copy_piece(P.D.vecs, base, rs, re, k, stage, TS::wave_piece(w, j), l);
 #pragma unroll
-          for (int j = 0; j < TS::kScaleCopiesPerWave; ++j) {
-            const int u = kDenseWaves * j + w;
-            int k, rs, re;
-            locate(min(G * kGroup + u, n_tiles - 1), k, rs, re);
-            TS::copy_scales(P.D.scales, base, rs, re, k, buf + u * (TS::kStageBytes / 16), l);
-          }
+          for (int j = 0; j < TS::kScaleCopiesPerWave; ++j) TS::copy_scales(P.D.scales, base, rs, re, k, stage, l);
         }
       };
 
@@ -653,20 +645,17 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
           const int nt = min(kGroup, n_tiles - G * kGroup);       // <= 0 past the end
           const int T0 = G * kGroup;
           // (full passes take the unbranched body)
-          if (S.nct == NT) {
+          auto tiles = [&](auto full) {
+            Frag A;
+            frag_from_lds<DT>(A, buf, c16, g);
 #pragma nounroll
-            for (int u = 0; u < nt; ++u) {
-              Frag A;
-              frag_from_lds<DT>(A, buf + u * (TS::kStageBytes / 16), c16, g);
-              S.template tile<true>(A, __ballot(d_tl == T0 + u));
-            }
-          } else if (S.nct > 0) {
-#pragma nounroll
-            for (int u = 0; u < nt; ++u) {
-              Frag A;
-              frag_from_lds<DT>(A, buf + u * (TS::kStageBytes / 16), c16, g);
-              S.template tile<false>(A, __ballot(d_tl == T0 + u));
-            }
+            for (int u = 0; u < nt; ++u)
+              S.template tile<decltype(full)::value>(A, buf + min(u + 1, nt - 1) * (TS::kStageBytes / 16), c16, g,
+                                                     __ballot(d_tl == T0 + u));
+          };
+          if (nt > 0) {
+            if (S.nct == NT) tiles(std::true_type{});
+            else if (S.nct > 0) tiles(std::false_type{});
           }
         };
         if (n_tiles > 0) {
