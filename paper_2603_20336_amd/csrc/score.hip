@@ -760,7 +760,8 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
 
 // --------------------------------------------------------------------------
 // Gathered scorer: one wave scores up to kGatherEntries consecutive entries of
-// one query's candidate list. The query's vectors stay in registers (64 per
+// one query's candidate list (fewer when a call has too few entries to give
+// every CU several waves: an entry's score does not depend on its wave). The query's vectors stay in registers (64 per
 // pass). The entries' documents form one sequence of tiles, which the wave
 // streams from memory several tiles ahead of the one being multiplied
 // (enough loads in flight to cover the memory latency). A score is the same
@@ -778,6 +779,7 @@ struct GatherParams {
   CandsView C;
   int64_t chunks_per_query;
   int64_t wave0;          // first wave of this launch (large batches launch in slices)
+  int32_t entries_per_wave;
   float* scores;
 };
 
@@ -800,8 +802,8 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
   int64_t lb, le;
   if (P.C.off) { lb = P.C.off[q]; le = P.C.off[q + 1]; }
   else { lb = q * (int64_t)P.C.stride; le = lb + P.C.stride; }
-  const int64_t e0 = lb + ch * kGatherEntries;
-  const int64_t e1 = min(le, e0 + kGatherEntries);
+  const int64_t e0 = lb + ch * P.entries_per_wave;
+  const int64_t e1 = min(le, e0 + P.entries_per_wave);
   if (e0 >= e1) return;
   const int ne = (int)(e1 - e0);
   const float ninf = neg_inf();
@@ -948,7 +950,15 @@ hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, 
                                int32_t max_list_len, int32_t, float* scores, hipStream_t s) {
   GatherParams P;
   P.Q = Q; P.D = D; P.C = C; P.scores = scores;
-  P.chunks_per_query = (max_list_len + kGatherEntries - 1) / kGatherEntries;
+  // entries per wave: kGatherEntries, or as few as one when the call holds
+  // fewer than kGatherWaves full waves (a single request's rerank of 1000
+  // candidates then runs on 1000 waves rather than 63)
+  constexpr int64_t kGatherWaves = 4096;
+  const int64_t cap = C.n_lists * (int64_t)std::max(max_list_len, 0);
+  P.entries_per_wave = cap >= kGatherEntries * kGatherWaves
+                           ? kGatherEntries
+                           : (int32_t)std::max<int64_t>(1, (cap + kGatherWaves - 1) / kGatherWaves);
+  P.chunks_per_query = (max_list_len + P.entries_per_wave - 1) / P.entries_per_wave;
   if (P.chunks_per_query == 0 || C.n_lists == 0) return hipSuccess;
   const int64_t waves = P.chunks_per_query * C.n_lists;
   const int64_t max_blocks = kMaxGridThreads / 256;

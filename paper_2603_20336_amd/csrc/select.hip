@@ -13,6 +13,7 @@ namespace gem {
 
 constexpr int kSelThreads = 512;
 constexpr int kSelCap = 4096;     // entries a workgroup can hold in LDS
+constexpr int kSelUnroll = 8;     // score loads in flight per thread in the radix passes
 
 __device__ __forceinline__ uint64_t rank_key(float s, int32_t id) {
   return ((uint64_t)float_order_key(s) << 32) | (uint64_t)(~(uint32_t)id);
@@ -177,15 +178,25 @@ __global__ __launch_bounds__(kSelThreads) void topk_kernel(TopkSegs S, int32_t k
     for (int shift = 56; shift >= 0; shift -= 8) {
       for (int i = tid; i < 256; i += kSelThreads) hist[i] = 0;
       __syncthreads();
-      for (int64_t j0 = 0; j0 < A.n; j0 += kSelThreads) {
-        const int64_t j = j0 + tid;
-        bool act = false;
-        uint32_t bin = 0;
-        if (j < A.n) {
-          const uint64_t key = rank_key(A.sc[j], (int32_t)j);
-          if ((key & mask) == prefix) { act = true; bin = (uint32_t)(key >> shift) & 0xffu; }
+      // kSelUnroll loads in flight per thread before their histogram adds
+      for (int64_t j0 = 0; j0 < A.n; j0 += (int64_t)kSelThreads * kSelUnroll) {
+        float v[kSelUnroll];
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+          const int64_t j = j0 + u * kSelThreads + tid;
+          v[u] = j < A.n ? A.sc[j] : 0.0f;
         }
-        hist_add(hist, act, bin);
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+          const int64_t j = j0 + u * kSelThreads + tid;
+          bool act = false;
+          uint32_t bin = 0;
+          if (j < A.n) {
+            const uint64_t key = rank_key(v[u], (int32_t)j);
+            if ((key & mask) == prefix) { act = true; bin = (uint32_t)(key >> shift) & 0xffu; }
+          }
+          hist_add(hist, act, bin);
+        }
       }
       __syncthreads();
       if (tid < 256) suf[tid] = hist[tid];
@@ -212,13 +223,24 @@ __global__ __launch_bounds__(kSelThreads) void topk_kernel(TopkSegs S, int32_t k
     // distinct, so a full-width threshold is a single key)
     if (tid == 0) s_cnt = 0;
     __syncthreads();
-    for (int64_t j = tid; j < A.n; j += kSelThreads) {
-      const uint64_t key = rank_key(A.sc[j], (int32_t)j);
-      const bool take = take_all || (key & mask) > prefix || (exact && (key & mask) == prefix) ||
-                        (!exact && key == prefix);
-      if (take) {
-        const int pos = atomicAdd(&s_cnt, 1);
-        if (pos < kSelCap) keys[pos] = key;
+    for (int64_t j0 = 0; j0 < A.n; j0 += (int64_t)kSelThreads * kSelUnroll) {
+      float v[kSelUnroll];
+#pragma unroll
+      for (int u = 0; u < kSelUnroll; ++u) {
+        const int64_t j = j0 + u * kSelThreads + tid;
+        v[u] = j < A.n ? A.sc[j] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < kSelUnroll; ++u) {
+        const int64_t j = j0 + u * kSelThreads + tid;
+        if (j >= A.n) continue;
+        const uint64_t key = rank_key(v[u], (int32_t)j);
+        const bool take = take_all || (key & mask) > prefix || (exact && (key & mask) == prefix) ||
+                          (!exact && key == prefix);
+        if (take) {
+          const int pos = atomicAdd(&s_cnt, 1);
+          if (pos < kSelCap) keys[pos] = key;
+        }
       }
     }
     __syncthreads();
