@@ -209,6 +209,10 @@ DenseSchedule lookup_dense(gem_ctx ctx, int32_t dtype, int64_t q_rows, int64_t n
   return default_dense_schedule(dtype, q_rows, n_docs, ctx->n_cu / 8);
 }
 
+// Query batches up to this size take the streamed (gathered) path of a dense
+// call: at most this many passes over the corpus, each at memory speed.
+constexpr int64_t kRangeMaxQueries = 6;
+
 gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t compute,
                         int32_t k, float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,
                         int32_t* top_ids, void* ws, size_t ws_bytes, hipStream_t stream,
@@ -244,18 +248,25 @@ gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const
       }
       return GEM_OK;
     }
-    int32_t* qb = reinterpret_cast<int32_t*>(at(ws, L.qb));
-    int64_t* qcol = reinterpret_cast<int64_t*>(at(ws, L.qcol));
-    e = launch_plan_query_blocks(Q->offsets, Q->n_sets, L.block_rows, Q->max_set_len, qb, qcol, L.n_blocks_max,
-                                 stream);
-    if (e != hipSuccess) return hip_fail(e, "query-block plan");
     DenseOut out;
     out.scores = scores ? scores : reinterpret_cast<float*>(at(ws, L.staged));
     out.ld = scores ? ld_scores : D->n_sets;
     out.rows = scores ? score_rows : nullptr;
-    const DenseSchedule ds = sched ? *sched : lookup_dense(ctx, compute, Q->n_vecs, D->n_sets);
-    e = launch_score_dense(compute, view(&Qc), view(D), qb, qcol, L.n_blocks_max, out, ds, stream);
-    if (e != hipSuccess) return hip_fail(e, "dense scoring");
+    if (Q->n_sets <= kRangeMaxQueries && !sched) {
+      // a few queries: every document streamed by the gathered scorer (the
+      // same scores; the dense scorer would run one lightly loaded block group)
+      e = launch_score_range(compute, view(&Qc), view(D), out, stream);
+      if (e != hipSuccess) return hip_fail(e, "dense scoring (streamed)");
+    } else {
+      int32_t* qb = reinterpret_cast<int32_t*>(at(ws, L.qb));
+      int64_t* qcol = reinterpret_cast<int64_t*>(at(ws, L.qcol));
+      e = launch_plan_query_blocks(Q->offsets, Q->n_sets, L.block_rows, Q->max_set_len, qb, qcol, L.n_blocks_max,
+                                   stream);
+      if (e != hipSuccess) return hip_fail(e, "query-block plan");
+      const DenseSchedule ds = sched ? *sched : lookup_dense(ctx, compute, Q->n_vecs, D->n_sets);
+      e = launch_score_dense(compute, view(&Qc), view(D), qb, qcol, L.n_blocks_max, out, ds, stream);
+      if (e != hipSuccess) return hip_fail(e, "dense scoring");
+    }
     if (k > 0) {
       TopkSegs S;
       S.scores = out.scores; S.off = nullptr; S.ids = nullptr; S.rows = out.rows;

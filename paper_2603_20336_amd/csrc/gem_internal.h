@@ -69,6 +69,11 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
 
 hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C,
                                int32_t max_list_len, int32_t max_q_len, float* scores, hipStream_t s);
+// The dense output of a small query batch by the gathered scorer: every
+// document of D is an entry of every query's list (bitwise the dense scorer's
+// scores, one wave per few documents: memory-bound streaming instead of one
+// lightly loaded block group).
+hipError_t launch_score_range(int dtype, const SetsView& Q, const SetsView& D, const DenseOut& out, hipStream_t s);
 
 hipError_t launch_convert_bf16(const float* x, int64_t n_elems, uint16_t* out, hipStream_t s);
 hipError_t launch_quantize_fp8(const float* x, int64_t n_rows, uint8_t* out, float* scales, hipStream_t s);

@@ -781,6 +781,11 @@ struct GatherParams {
   int64_t wave0;          // first wave of this launch (large batches launch in slices)
   int32_t entries_per_wave;
   float* scores;
+  // range mode: list q is every document of D, in order (no ids), and entry
+  // e's score goes to scores[(out_rows ? out_rows[q] : q) * out_ld + e]
+  int32_t range;
+  const int32_t* out_rows;
+  int64_t out_ld;
 };
 
 // kCodes: the documents are a code set. Each lane then loads the code of the
@@ -800,7 +805,8 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
   if (q >= P.C.n_lists) return;
   const int64_t ch = gw % P.chunks_per_query;
   int64_t lb, le;
-  if (P.C.off) { lb = P.C.off[q]; le = P.C.off[q + 1]; }
+  if (P.range) { lb = 0; le = P.D.n_sets; }
+  else if (P.C.off) { lb = P.C.off[q]; le = P.C.off[q + 1]; }
   else { lb = q * (int64_t)P.C.stride; le = lb + P.C.stride; }
   const int64_t e0 = lb + ch * P.entries_per_wave;
   const int64_t e1 = min(le, e0 + P.entries_per_wave);
@@ -815,7 +821,7 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
   int64_t d_beg = 0;
   int d_len = 0;
   if (l < ne) {
-    my_id = P.C.ids[e0 + l];
+    my_id = P.range ? (int32_t)(e0 + l) : P.C.ids[e0 + l];
     if (my_id >= 0) { d_beg = P.D.off[my_id]; d_len = (int)(P.D.off[my_id + 1] - d_beg); }
   }
   const int d_nt = (d_len + 15) >> 4;
@@ -943,30 +949,32 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
       }
     }
   }
-  if (l < ne) P.scores[e0 + l] = res;
+  if (l < ne) {
+    if (P.range) P.scores[(P.out_rows ? (int64_t)P.out_rows[q] : q) * P.out_ld + e0 + l] = res;
+    else P.scores[e0 + l] = res;
+  }
 }
 
-hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C,
-                               int32_t max_list_len, int32_t, float* scores, hipStream_t s) {
-  GatherParams P;
-  P.Q = Q; P.D = D; P.C = C; P.scores = scores;
+// Launches the gathered scorer over C.n_lists lists of at most max_list_len
+// entries (in slices of at most kMaxGridThreads threads).
+static hipError_t run_gather(int dtype, GatherParams P, int64_t max_list_len, hipStream_t s) {
   // entries per wave: kGatherEntries, or as few as one when the call holds
   // fewer than kGatherWaves full waves (a single request's rerank of 1000
   // candidates then runs on 1000 waves rather than 63)
   constexpr int64_t kGatherWaves = 4096;
-  const int64_t cap = C.n_lists * (int64_t)std::max(max_list_len, 0);
+  const int64_t cap = P.C.n_lists * std::max<int64_t>(max_list_len, 0);
   P.entries_per_wave = cap >= kGatherEntries * kGatherWaves
                            ? kGatherEntries
                            : (int32_t)std::max<int64_t>(1, (cap + kGatherWaves - 1) / kGatherWaves);
   P.chunks_per_query = (max_list_len + P.entries_per_wave - 1) / P.entries_per_wave;
-  if (P.chunks_per_query == 0 || C.n_lists == 0) return hipSuccess;
-  const int64_t waves = P.chunks_per_query * C.n_lists;
+  if (P.chunks_per_query == 0 || P.C.n_lists == 0) return hipSuccess;
+  const int64_t waves = P.chunks_per_query * P.C.n_lists;
   const int64_t max_blocks = kMaxGridThreads / 256;
   for (int64_t b0 = 0; b0 < (waves + 3) / 4; b0 += max_blocks) {
     P.wave0 = b0 * 4;
     const int64_t grid = std::min(max_blocks, (waves + 3) / 4 - b0);
     const dim3 gr((unsigned)grid), blk(256);
-    const bool codes = D.codes != nullptr;
+    const bool codes = P.D.codes != nullptr;
     switch (dtype) {
       case GEM_F32:
         if (codes) hipLaunchKernelGGL((score_gather_kernel<GEM_F32, true>), gr, blk, 0, s, P);
@@ -990,6 +998,24 @@ hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, 
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C,
+                               int32_t max_list_len, int32_t, float* scores, hipStream_t s) {
+  GatherParams P{};
+  P.Q = Q; P.D = D; P.C = C; P.scores = scores;
+  P.range = 0;
+  return run_gather(dtype, P, max_list_len, s);
+}
+
+hipError_t launch_score_range(int dtype, const SetsView& Q, const SetsView& D, const DenseOut& out, hipStream_t s) {
+  if (D.n_sets > INT32_MAX) return hipErrorInvalidValue;
+  GatherParams P{};
+  P.Q = Q; P.D = D;
+  P.C.off = nullptr; P.C.ids = nullptr; P.C.n_lists = Q.n_sets; P.C.stride = 0;
+  P.scores = out.scores; P.out_rows = out.rows; P.out_ld = out.ld;
+  P.range = 1;
+  return run_gather(dtype, P, D.n_sets, s);
 }
 
 }  // namespace gem

@@ -223,6 +223,37 @@ def test_batch_independence_bitwise():
         np.testing.assert_array_equal(sub, full[[5, 3, 30]])
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8", "mxfp4"])
+def test_small_batches_stream_bitwise_as_dense(dtype):
+    """Up to six queries take the streamed path of a dense call: the same
+    scores, bitwise, as the dense scorer gives them inside a larger batch (and
+    the oracle's), with empty and long queries, empty and long documents, and
+    the rows / ld placement."""
+    qlens = [0, 1, 33, 64, 256, 17]
+    dlens = [1, 15, 16, 17, 255, 256, 0, 3, 64, 65] + list(np.random.default_rng(3).integers(1, 90, 150))
+    q, c = _ragged(qlens + [5, 9, 40, 2], 40), _ragged(dlens, 41)
+    S = gem.Sets.from_batch(c, DEV)
+    D = S.to_mxfp4() if dtype == "mxfp4" else _device_sets(c, dtype)
+    score = (lambda Q, **kw: gem.score_quant(Q, D, **kw)) if dtype == "mxfp4" else \
+        (lambda Q, **kw: _score(Q, D, dtype, **kw))
+    big = _np(score(gem.Sets.from_batch(q, DEV)))                       # ten queries: the dense scorer
+    for idx in ([0, 1, 2, 3, 4, 5], [4], [2, 0, 5]):
+        small = _np(score(gem.Sets.from_batch(q.subset(idx), DEV)))
+        np.testing.assert_array_equal(small, big[idx])
+    out = torch.full((8, 200), 7.0, device=DEV)
+    rows = torch.tensor([6, 1, 3], dtype=torch.int32, device=DEV)
+    score(gem.Sets.from_batch(q.subset([3, 4, 5]), DEV), scores=out[:, 20:], ld=200, rows=rows)
+    o = _np(out)
+    for i, r in enumerate([6, 1, 3]):
+        np.testing.assert_array_equal(o[r, 20:180], big[3 + i])
+        assert (o[r, :20] == 7.0).all() and (o[r, 180:] == 7.0).all()
+    assert (o[[0, 2, 4, 5, 7]] == 7.0).all()
+    if dtype != "mxfp4":
+        ref = oracle.ch_dense(_operands(q.vecs.numpy(), dtype), q.offsets.numpy(),
+                              _operands(c.vecs.numpy(), dtype), c.offsets.numpy())
+        assert_close(big[:6], ref[:6], tol=3e-4, what=f"streamed {dtype}")
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 def test_dense_many_blocks_long_documents(dtype):
     """More than 32 block groups for every dtype (more groups than workgroups
