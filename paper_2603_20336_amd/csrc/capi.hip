@@ -141,7 +141,7 @@ ScoreLayout score_layout(const gem_sets* Q, const gem_sets* D, const gem_cands* 
     }
   }
   if (!C) {
-    L.block_rows = dense_block_rows(compute, Q->max_set_len);
+    L.block_rows = dense_block_rows_for(compute, Q->max_set_len, Q->n_sets, Q->n_vecs);
     L.n_blocks_max = dense_blocks_upper(Q->n_sets, Q->n_vecs, L.block_rows, Q->max_set_len);
     L.qb = off;
     off = align_up(off + (size_t)(L.n_blocks_max + 2) * 4);     // starts, end, run count
@@ -211,7 +211,7 @@ DenseSchedule lookup_dense(gem_ctx ctx, int32_t dtype, int64_t q_rows, int64_t n
 
 // Query batches up to this size take the streamed (gathered) path of a dense
 // call: at most this many passes over the corpus, each at memory speed.
-constexpr int64_t kRangeMaxQueries = 6;
+constexpr int64_t kRangeMaxQueries = 3;
 
 gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t compute,
                         int32_t k, float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,

@@ -43,6 +43,7 @@ constexpr int kBlockMaxQueries = 32;
 int dense_pass_rows(int dtype);
 // Rows a query block may hold for a batch whose longest query has max_len rows.
 int dense_block_rows(int dtype, int max_len);
+int dense_block_rows_for(int dtype, int max_len, int64_t n_q, int64_t n_vecs);
 int64_t dense_blocks_upper(int64_t n_q, int64_t n_rows, int block_rows, int max_len);
 
 hipError_t launch_plan_query_blocks(const int64_t* q_off, int64_t n_q, int block_rows, int max_len,

@@ -46,11 +46,24 @@ int dense_pass_rows(int dtype) {
 }
 
 static int pad16(int m) { return (m + 15) & ~15; }
+constexpr int64_t kDenseWavesPerGroup = 8;       // query blocks per block group (waves per workgroup)
 
 int dense_block_rows(int dtype, int max_len) {
   const int r = dense_pass_rows(dtype);
   const int m = pad16(max_len);
   return m <= r ? r : ((m + r - 1) / r) * r;
+}
+
+// Block width for a batch of n_q queries holding n_vecs vectors: the full
+// width, or for a small batch one narrow enough to give each wave of a block
+// group a block of its own (a narrower block only changes the plan, never a
+// score).
+int dense_block_rows_for(int dtype, int max_len, int64_t n_q, int64_t n_vecs) {
+  const int full = dense_block_rows(dtype, max_len);
+  const int64_t cols = n_vecs + 15 * n_q;                                   // padded columns, upper bound
+  const int64_t per_wave = (((cols + kDenseWavesPerGroup - 1) / kDenseWavesPerGroup) + 15) & ~(int64_t)15;
+  const int64_t narrow = std::max<int64_t>(pad16(max_len > 0 ? max_len : 1), per_wave);
+  return narrow < full ? (int)narrow : full;
 }
 
 int64_t dense_blocks_upper(int64_t n_q, int64_t n_rows, int block_rows, int max_len) {
@@ -209,6 +222,7 @@ hipError_t launch_plan_query_blocks(const int64_t* q_off, int64_t n_q, int block
 constexpr int kMaxChunkDocs = 64;               // a chunk's documents map to the 64 lanes
 constexpr int kBuffers = 3;                    // group buffers: two groups in flight
 constexpr int kDenseWaves = 8;                 // two waves per SIMD
+static_assert(kDenseWaves == kDenseWavesPerGroup, "block groups hold one block per wave");
 constexpr int kDenseThreads = 64 * kDenseWaves;
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;

@@ -225,7 +225,7 @@ def test_batch_independence_bitwise():
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8", "mxfp4"])
 def test_small_batches_stream_bitwise_as_dense(dtype):
-    """Up to six queries take the streamed path of a dense call: the same
+    """Up to three queries take the streamed path of a dense call: the same
     scores, bitwise, as the dense scorer gives them inside a larger batch (and
     the oracle's), with empty and long queries, empty and long documents, and
     the rows / ld placement."""
@@ -237,7 +237,7 @@ def test_small_batches_stream_bitwise_as_dense(dtype):
     score = (lambda Q, **kw: gem.score_quant(Q, D, **kw)) if dtype == "mxfp4" else \
         (lambda Q, **kw: _score(Q, D, dtype, **kw))
     big = _np(score(gem.Sets.from_batch(q, DEV)))                       # ten queries: the dense scorer
-    for idx in ([0, 1, 2, 3, 4, 5], [4], [2, 0, 5]):
+    for idx in ([0, 1, 2, 3, 4, 5], [4], [2, 0, 5], [1, 3]):
         small = _np(score(gem.Sets.from_batch(q.subset(idx), DEV)))
         np.testing.assert_array_equal(small, big[idx])
     out = torch.full((8, 200), 7.0, device=DEV)
@@ -252,6 +252,16 @@ def test_small_batches_stream_bitwise_as_dense(dtype):
         ref = oracle.ch_dense(_operands(q.vecs.numpy(), dtype), q.offsets.numpy(),
                               _operands(c.vecs.numpy(), dtype), c.offsets.numpy())
         assert_close(big[:6], ref[:6], tol=3e-4, what=f"streamed {dtype}")
+    # a dozen short queries: the dense scorer with narrowed query blocks (one
+    # per wave) against the same queries inside a batch of 80 (full blocks)
+    q2 = _ragged(list(np.random.default_rng(4).integers(1, 41, 80)), 42)
+    big2 = _np(score(gem.Sets.from_batch(q2, DEV)))
+    idx = [3, 7, 0, 12, 40, 41, 42, 43, 44, 60, 61, 79]
+    np.testing.assert_array_equal(_np(score(gem.Sets.from_batch(q2.subset(idx), DEV))), big2[idx])
+    if dtype != "mxfp4":
+        ref2 = oracle.ch_dense(_operands(q2.vecs.numpy(), dtype), q2.offsets.numpy(),
+                               _operands(c.vecs.numpy(), dtype), c.offsets.numpy())
+        assert_close(big2, ref2, what=f"dense {dtype}, 80 short queries")
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
