@@ -410,6 +410,12 @@ def bench_exhaustive(args):
         res["recall_at_100_mxfp4_rerank"] = recall_vs_exact(r4_i[:ns].cpu().numpy(), ref, k)
         for cdt, (_, qi) in qch_q8.items():
             qch[cdt]["recall_at_100_rerank"] = recall_vs_exact(qi[:ns].cpu().numpy(), ref, k)
+        # exact-mode error: the f32 path's and the FP8 + rerank path's top-100
+        # scores against the float64 scores of the same documents
+        for name, (ts_, ti_) in (("f32", (top32_s, top32_i)), ("fp8_rerank", (r8_s, r8_i))):
+            ts_np, ti_np = ts_[:ns].double().cpu().numpy(), ti_[:ns].cpu().numpy()
+            rr = np.take_along_axis(ref, ti_np, axis=1)
+            res[f"{name}_top100_max_rel_err"] = float((np.abs(ts_np - rr) / np.maximum(np.abs(rr), 1)).max())
         est_np = est[:ns].double().cpu().numpy()
         res["fp8_estimate_rel_err_p50"] = float(np.median(np.abs(est_np - ref) / np.maximum(np.abs(ref), 1)))
         res["recall_sample_queries"] = ns
