@@ -570,7 +570,8 @@ gem_status gem_expand_batch(gem_ctx ctx, const gem_sets* Q8, const gem_sets* D8,
   hipError_t e = launch_score_gather(cd, view(&Qc), view(D8), cview(C), list_len_bound(C), Q8->max_set_len,
                                      es, stream);
   if (e != hipSuccess) return hip_fail(e, "gathered scoring");
-  e = launch_beam_merge(es, cview(C), Q8->n_sets, beam->ef, beam->scores, beam->ids, stream);
+  e = launch_beam_merge(es, cview(C), Q8->n_sets, beam->ef, beam->scores, beam->ids,
+                        list_len_bound(C) > 0 ? beam->ef + list_len_bound(C) : 0, stream);
   if (e != hipSuccess) return hip_fail(e, "beam merge");
   return GEM_OK;
 }
@@ -665,7 +666,7 @@ gem_status search_score_merge(const gem_sets* Q, const gem_sets* D, const gem_se
   c.off = nullptr; c.ids = S->cand_ids; c.n_lists = Q->n_sets; c.stride = row;
   hipError_t e = launch_score_gather(D->dtype, view(Q), view(D), c, row, Q->max_set_len, S->cand_scores, stream);
   if (e != hipSuccess) return hip_fail(e, "search scoring");
-  e = launch_beam_merge(S->cand_scores, c, Q->n_sets, beam->ef, beam->scores, beam->ids, stream);
+  e = launch_beam_merge(S->cand_scores, c, Q->n_sets, beam->ef, beam->scores, beam->ids, beam->ef + row, stream);
   return e == hipSuccess ? GEM_OK : hip_fail(e, "search merge");
 }
 
@@ -711,7 +712,8 @@ gem_status gem_beam_merge(gem_ctx ctx, const float* cand_scores, const gem_cands
   if (C->n_entries > 0 && !cand_scores) return fail(GEM_ERR_INVALID, "cand_scores is NULL");
   if ((int64_t)beam->ef + list_len_bound(C) > kBeamMaxEntries)
     return fail(GEM_ERR_UNSUPPORTED, "ef + longest list = %d exceeds %d", beam->ef + list_len_bound(C), kBeamMaxEntries);
-  hipError_t e = launch_beam_merge(cand_scores, cview(C), C->n_lists, beam->ef, beam->scores, beam->ids, stream);
+  hipError_t e = launch_beam_merge(cand_scores, cview(C), C->n_lists, beam->ef, beam->scores, beam->ids,
+                                   list_len_bound(C) > 0 ? beam->ef + list_len_bound(C) : 0, stream);
   return e == hipSuccess ? GEM_OK : hip_fail(e, "beam merge");
 }
 

@@ -104,7 +104,7 @@ struct TopkSegs {
 hipError_t launch_topk(const TopkSegs& segs, int32_t k, float* top_scores, int32_t* top_ids, hipStream_t s);
 
 hipError_t launch_beam_merge(const float* cand_scores, const CandsView& C, int64_t n_q, int32_t ef,
-                             float* beam_scores, int32_t* beam_ids, hipStream_t s);
+                             float* beam_scores, int32_t* beam_ids, int32_t max_entries, hipStream_t s);
 hipError_t launch_beam_reset(float* beam_scores, int32_t* beam_ids, int64_t n, hipStream_t s);
 
 constexpr int kBeamMaxEntries = 4096;   // ef + longest candidate list of a merge

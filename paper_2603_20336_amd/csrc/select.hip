@@ -55,6 +55,7 @@ __device__ __forceinline__ int pow2_ceil(int n) {
 
 // keys[0..n): rank keys (0 = empty). Removes repeated ids (keeping the best
 // entry of each), then sorts descending. Returns the number of distinct entries.
+template <int kCap, int kThreads>
 __device__ int dedup_and_sort(uint64_t* keys, int n, bool may_repeat, int* s_cnt) {
   const int np = pow2_ceil(max(n, 1));
   if (may_repeat) {
@@ -62,7 +63,7 @@ __device__ int dedup_and_sort(uint64_t* keys, int n, bool may_repeat, int* s_cnt
     __syncthreads();
     block_bitonic_sort(keys, np, false);
     // after the ascending id sort, copies of an id are adjacent, best first
-    uint64_t keep_key[kSelCap / kSelThreads];
+    uint64_t keep_key[kCap / kThreads];
     int c = 0;
     for (int i = threadIdx.x; i < np; i += blockDim.x, ++c) {
       const uint64_t ik = keys[i];
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(kSelThreads) void topk_kernel(TopkSegs S, int32_t k
     __syncthreads();
     n_keys = s_cnt;
     __syncthreads();
-    n_keys = dedup_and_sort(keys, n_keys, may_repeat, &s_cnt);
+    n_keys = dedup_and_sort<kSelCap, kSelThreads>(keys, n_keys, may_repeat, &s_cnt);
   } else if (may_repeat) {
     // ids may repeat: stream the segment through LDS in chunks, keeping the
     // best k distinct ids seen so far (an entry dropped here is beaten by k
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(kSelThreads) void topk_kernel(TopkSegs S, int32_t k
       __syncthreads();
       const int n = s_cnt;
       __syncthreads();
-      cur = min(dedup_and_sort(keys, n, true, &s_cnt), (int)k);
+      cur = min(dedup_and_sort<kSelCap, kSelThreads>(keys, n, true, &s_cnt), (int)k);
     }
     n_keys = cur;
   } else {
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(kSelThreads) void topk_kernel(TopkSegs S, int32_t k
     __syncthreads();
     const int got = min(s_cnt, kSelCap);
     __syncthreads();
-    n_keys = dedup_and_sort(keys, got, false, &s_cnt);
+    n_keys = dedup_and_sort<kSelCap, kSelThreads>(keys, got, false, &s_cnt);
   }
   for (int r = tid; r < k; r += kSelThreads) {
     const uint64_t key = r < n_keys ? keys[r] : 0ull;
@@ -266,11 +267,12 @@ hipError_t launch_topk(const TopkSegs& segs, int32_t k, float* top_scores, int32
 // --------------------------------------------------------------------------
 // Beam update: row q of the beam becomes the best ef of (row q) U (list q's
 // scored entries), ids distinct. One workgroup per query.
-__global__ __launch_bounds__(kSelThreads) void beam_merge_kernel(const float* __restrict__ cand_scores, CandsView C,
+template <int kCap, int kThreads>
+__global__ __launch_bounds__(kThreads) void beam_merge_kernel(const float* __restrict__ cand_scores, CandsView C,
                                                                  int64_t n_q, int32_t ef,
                                                                  float* __restrict__ beam_scores,
                                                                  int32_t* __restrict__ beam_ids) {
-  __shared__ uint64_t keys[kSelCap];
+  __shared__ uint64_t keys[kCap];
   __shared__ int s_cnt;
   const int tid = threadIdx.x;
   for (int64_t q = blockIdx.x; q < n_q; q += gridDim.x) {
@@ -282,25 +284,25 @@ __global__ __launch_bounds__(kSelThreads) void beam_merge_kernel(const float* __
   __syncthreads();
   float* bs = beam_scores + q * ef;
   int32_t* bi = beam_ids + q * ef;
-  for (int r = tid; r < ef; r += kSelThreads) {
+  for (int r = tid; r < ef; r += kThreads) {
     const int32_t id = bi[r];
     if (id >= 0) {
       const int pos = atomicAdd(&s_cnt, 1);
-      if (pos < kSelCap) keys[pos] = rank_key(bs[r], id);
+      if (pos < kCap) keys[pos] = rank_key(bs[r], id);
     }
   }
-  for (int64_t e = lb + tid; e < le; e += kSelThreads) {
+  for (int64_t e = lb + tid; e < le; e += kThreads) {
     const int32_t id = C.ids[e];
     if (id >= 0) {
       const int pos = atomicAdd(&s_cnt, 1);
-      if (pos < kSelCap) keys[pos] = rank_key(cand_scores[e], id);
+      if (pos < kCap) keys[pos] = rank_key(cand_scores[e], id);
     }
   }
   __syncthreads();
-  const int n = min(s_cnt, kSelCap);
+  const int n = min(s_cnt, kCap);
   __syncthreads();
-  const int d = dedup_and_sort(keys, n, true, &s_cnt);
-  for (int r = tid; r < ef; r += kSelThreads) {
+  const int d = dedup_and_sort<kCap, kThreads>(keys, n, true, &s_cnt);
+  for (int r = tid; r < ef; r += kThreads) {
     const uint64_t key = r < d ? keys[r] : 0ull;
     bs[r] = key ? key_score(key) : neg_inf();
     bi[r] = key ? key_id(key) : -1;
@@ -309,10 +311,16 @@ __global__ __launch_bounds__(kSelThreads) void beam_merge_kernel(const float* __
 }
 
 hipError_t launch_beam_merge(const float* cand_scores, const CandsView& C, int64_t n_q, int32_t ef,
-                             float* beam_scores, int32_t* beam_ids, hipStream_t s) {
+                             float* beam_scores, int32_t* beam_ids, int32_t max_entries, hipStream_t s) {
   if (n_q == 0) return hipSuccess;
-  hipLaunchKernelGGL(beam_merge_kernel, dim3(capped_blocks(n_q, kSelThreads)), dim3(kSelThreads), 0, s, cand_scores,
-                     C, n_q, ef, beam_scores, beam_ids);
+  // merges of at most 2048 entries (ef + the longest list, when known) run
+  // in half the LDS with 256 threads: twice the workgroups per CU
+  if (max_entries > 0 && max_entries <= 2048)
+    hipLaunchKernelGGL((beam_merge_kernel<2048, 256>), dim3(capped_blocks(n_q, 256)), dim3(256), 0, s, cand_scores,
+                       C, n_q, ef, beam_scores, beam_ids);
+  else
+    hipLaunchKernelGGL((beam_merge_kernel<kSelCap, kSelThreads>), dim3(capped_blocks(n_q, kSelThreads)),
+                       dim3(kSelThreads), 0, s, cand_scores, C, n_q, ef, beam_scores, beam_ids);
   return hipGetLastError();
 }
 
