@@ -14,6 +14,7 @@ namespace gem {
 constexpr int kSelThreads = 512;
 constexpr int kSelCap = 4096;     // entries a workgroup can hold in LDS
 constexpr int kSelUnroll = 8;     // score loads in flight per thread in the radix passes
+constexpr int kTopkSample = 2048; // entries sampled for the threshold of a long positional segment
 
 __device__ __forceinline__ uint64_t rank_key(float s, int32_t id) {
   return ((uint64_t)float_order_key(s) << 32) | (uint64_t)(~(uint32_t)id);
@@ -170,16 +171,24 @@ __global__ __launch_bounds__(kSelThreads) void topk_kernel(TopkSegs S, int32_t k
     }
     n_keys = cur;
   } else {
-    // positions as ids (all distinct): radix select of the k-th largest key,
-    // 8 bits a pass, stopping as soon as the threshold bucket holds exactly
-    // the entries still needed
-    uint64_t prefix = 0, mask = 0;
-    int need = k;
-    bool exact = false, take_all = false;
-    for (int shift = 56; shift >= 0; shift -= 8) {
-      for (int i = tid; i < 256; i += kSelThreads) hist[i] = 0;
+    // positions as ids (all distinct). First a sampled threshold: the r-th
+    // best of kSample evenly spaced entries, r a wide margin above the
+    // sample's expected share of the top k; every entry at least as good is
+    // collected in one pass, and when that is between k and kSelCap entries
+    // the top k are among them (keys are distinct), so one sort finishes.
+    // Otherwise (heavy ties, skewed orders) the radix select below.
+    bool done = false;
+    if (k <= kSelCap / 4) {
+      const int64_t stride = A.n / kTopkSample;                  // >= 1: A.n > kSelCap
+      for (int i = tid; i < kTopkSample; i += kSelThreads)
+        keys[i] = rank_key(A.sc[i * stride], (int32_t)(i * stride));
       __syncthreads();
-      // kSelUnroll loads in flight per thread before their histogram adds
+      block_bitonic_sort(keys, kTopkSample, true);
+      const int r = (int)min<int64_t>(kTopkSample - 1, (3 * (int64_t)k * kTopkSample) / (2 * A.n) + 16);
+      const uint64_t thr = keys[r];
+      __syncthreads();
+      if (tid == 0) s_cnt = 0;
+      __syncthreads();
       for (int64_t j0 = 0; j0 < A.n; j0 += (int64_t)kSelThreads * kSelUnroll) {
         float v[kSelUnroll];
 #pragma unroll
@@ -190,64 +199,102 @@ __global__ __launch_bounds__(kSelThreads) void topk_kernel(TopkSegs S, int32_t k
 #pragma unroll
         for (int u = 0; u < kSelUnroll; ++u) {
           const int64_t j = j0 + u * kSelThreads + tid;
-          bool act = false;
-          uint32_t bin = 0;
-          if (j < A.n) {
-            const uint64_t key = rank_key(v[u], (int32_t)j);
-            if ((key & mask) == prefix) { act = true; bin = (uint32_t)(key >> shift) & 0xffu; }
+          if (j >= A.n) continue;
+          const uint64_t key = rank_key(v[u], (int32_t)j);
+          if (key >= thr) {
+            const int pos = atomicAdd(&s_cnt, 1);
+            if (pos < kSelCap) keys[pos] = key;
           }
-          hist_add(hist, act, bin);
         }
       }
       __syncthreads();
-      if (tid < 256) suf[tid] = hist[tid];
-      if (tid == 0) suf[256] = 0;
+      const int got = s_cnt;
       __syncthreads();
-      for (int o = 1; o < 256; o <<= 1) {          // suffix sums
-        uint32_t v = (tid < 256 && tid + o < 256) ? suf[tid + o] : 0;
-        __syncthreads();
-        if (tid < 256) suf[tid] += v;
-        __syncthreads();
+      if (got >= k && got <= kSelCap) {
+        n_keys = dedup_and_sort<kSelCap, kSelThreads>(keys, got, false, &s_cnt);
+        done = true;
       }
-      if (shift == 56 && suf[0] <= (uint32_t)k) { take_all = true; break; }
-      if (tid < 256 && suf[tid] >= (uint32_t)need && suf[tid + 1] < (uint32_t)need) { s_sel = tid; s_gt = suf[tid + 1]; }
-      __syncthreads();
-      const uint32_t sel = s_sel;
-      need -= (int)s_gt;
-      prefix |= (uint64_t)sel << shift;
-      mask |= 0xffull << shift;
-      const bool ex = hist[sel] == (uint32_t)need;
-      __syncthreads();
-      if (ex) { exact = true; break; }
     }
-    // collect the keys above the threshold and the threshold's share (keys are
-    // distinct, so a full-width threshold is a single key)
-    if (tid == 0) s_cnt = 0;
-    __syncthreads();
-    for (int64_t j0 = 0; j0 < A.n; j0 += (int64_t)kSelThreads * kSelUnroll) {
-      float v[kSelUnroll];
+    if (!done) {
+      // positions as ids (all distinct): radix select of the k-th largest key,
+      // 8 bits a pass, stopping as soon as the threshold bucket holds exactly
+      // the entries still needed
+      uint64_t prefix = 0, mask = 0;
+      int need = k;
+      bool exact = false, take_all = false;
+      for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int i = tid; i < 256; i += kSelThreads) hist[i] = 0;
+        __syncthreads();
+        // kSelUnroll loads in flight per thread before their histogram adds
+        for (int64_t j0 = 0; j0 < A.n; j0 += (int64_t)kSelThreads * kSelUnroll) {
+          float v[kSelUnroll];
 #pragma unroll
-      for (int u = 0; u < kSelUnroll; ++u) {
-        const int64_t j = j0 + u * kSelThreads + tid;
-        v[u] = j < A.n ? A.sc[j] : 0.0f;
+          for (int u = 0; u < kSelUnroll; ++u) {
+            const int64_t j = j0 + u * kSelThreads + tid;
+            v[u] = j < A.n ? A.sc[j] : 0.0f;
+          }
+#pragma unroll
+          for (int u = 0; u < kSelUnroll; ++u) {
+            const int64_t j = j0 + u * kSelThreads + tid;
+            bool act = false;
+            uint32_t bin = 0;
+            if (j < A.n) {
+              const uint64_t key = rank_key(v[u], (int32_t)j);
+              if ((key & mask) == prefix) { act = true; bin = (uint32_t)(key >> shift) & 0xffu; }
+            }
+            hist_add(hist, act, bin);
+          }
+        }
+        __syncthreads();
+        if (tid < 256) suf[tid] = hist[tid];
+        if (tid == 0) suf[256] = 0;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {          // suffix sums
+          uint32_t v = (tid < 256 && tid + o < 256) ? suf[tid + o] : 0;
+          __syncthreads();
+          if (tid < 256) suf[tid] += v;
+          __syncthreads();
+        }
+        if (shift == 56 && suf[0] <= (uint32_t)k) { take_all = true; break; }
+        if (tid < 256 && suf[tid] >= (uint32_t)need && suf[tid + 1] < (uint32_t)need) { s_sel = tid; s_gt = suf[tid + 1]; }
+        __syncthreads();
+        const uint32_t sel = s_sel;
+        need -= (int)s_gt;
+        prefix |= (uint64_t)sel << shift;
+        mask |= 0xffull << shift;
+        const bool ex = hist[sel] == (uint32_t)need;
+        __syncthreads();
+        if (ex) { exact = true; break; }
       }
+      // collect the keys above the threshold and the threshold's share (keys are
+      // distinct, so a full-width threshold is a single key)
+      if (tid == 0) s_cnt = 0;
+      __syncthreads();
+      for (int64_t j0 = 0; j0 < A.n; j0 += (int64_t)kSelThreads * kSelUnroll) {
+        float v[kSelUnroll];
 #pragma unroll
-      for (int u = 0; u < kSelUnroll; ++u) {
-        const int64_t j = j0 + u * kSelThreads + tid;
-        if (j >= A.n) continue;
-        const uint64_t key = rank_key(v[u], (int32_t)j);
-        const bool take = take_all || (key & mask) > prefix || (exact && (key & mask) == prefix) ||
-                          (!exact && key == prefix);
-        if (take) {
-          const int pos = atomicAdd(&s_cnt, 1);
-          if (pos < kSelCap) keys[pos] = key;
+        for (int u = 0; u < kSelUnroll; ++u) {
+          const int64_t j = j0 + u * kSelThreads + tid;
+          v[u] = j < A.n ? A.sc[j] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+          const int64_t j = j0 + u * kSelThreads + tid;
+          if (j >= A.n) continue;
+          const uint64_t key = rank_key(v[u], (int32_t)j);
+          const bool take = take_all || (key & mask) > prefix || (exact && (key & mask) == prefix) ||
+                            (!exact && key == prefix);
+          if (take) {
+            const int pos = atomicAdd(&s_cnt, 1);
+            if (pos < kSelCap) keys[pos] = key;
+          }
         }
       }
+      __syncthreads();
+      const int got = min(s_cnt, kSelCap);
+      __syncthreads();
+      n_keys = dedup_and_sort<kSelCap, kSelThreads>(keys, got, false, &s_cnt);
     }
-    __syncthreads();
-    const int got = min(s_cnt, kSelCap);
-    __syncthreads();
-    n_keys = dedup_and_sort<kSelCap, kSelThreads>(keys, got, false, &s_cnt);
   }
   for (int r = tid; r < k; r += kSelThreads) {
     const uint64_t key = r < n_keys ? keys[r] : 0ull;
