@@ -9,11 +9,11 @@
 //   g_j <- -log m2 - logsumexp_i (f_i - C_ij / eps)
 // then the cost sum_ij exp(f_i + g_j - C_ij / eps) C_ij of that plan.
 //
-// One workgroup per pair. Thread i < m1 holds row i of the first set in
-// registers; the second set streams through LDS in chunks of 16 rows; the
-// matrix of -C / eps (base 2) stays in LDS for the whole iteration (at most
-// kMaxEmdCost entries), or for larger pairs in a slice of the workspace (a
-// second pass over the pairs the first one flagged). Every reduction runs in
+// One workgroup per pair. To build the matrix, each lane group of row i holds
+// row i of the first set in registers while the second set streams through
+// LDS in chunks of 16 rows; the matrix of -C / eps (base 2) stays in LDS for the
+// whole iteration (at most kMaxEmdCost entries), or for larger pairs in a
+// slice of the workspace (a second pass over the pairs the first one flagged). Every reduction runs in
 // a fixed order, so the result does not depend on the batch.
 #include <algorithm>
 
@@ -27,48 +27,63 @@ constexpr int kEmdThreads = 256;
 constexpr int kChunk = 16;
 }  // namespace
 
-// One thread per row (then per column) of the matrix: each logsumexp is a
-// serial two-pass loop (max, then the sum of powers) with no cross-lane work.
-// The matrix is stored with an odd row stride, so the row pass (threads walk
-// their own rows) and the column pass (threads walk their own columns) both
-// read distinct LDS banks. The iteration runs in base 2: with L_ij = -C_ij
+// A group of up to eight consecutive lanes per row (then per column) of the
+// matrix, as many as the 256 threads allow: each logsumexp is a two-pass loop
+// (max, then the sum of powers) over the group's interleaved share of the row,
+// then a butterfly over the group. The matrix is stored with an odd row
+// stride, so the row pass (lanes walk rows) and the column pass (lanes walk
+// columns) both read distinct LDS banks. The iteration runs in base 2: with L_ij = -C_ij
 // log2(e) / eps and potentials in log2 units it is the same iteration (every
 // term scaled by log2 e), evaluated with the hardware exp2 / log2.
 __device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
 
-// log2 of sum_k 2^(p[k * ps] + q[k * qs]) over k < n: the maximum, then the
-// sum of powers, each over eight interleaved partial results (eight loads in
-// flight: a workgroup per CU leaves few waves to hide LDS latency), combined
-// in a fixed order.
-__device__ __forceinline__ float lse2(const float* p, int ps, const float* q, int qs, int n) {
-  constexpr int U = 8;
-  float m[U];
+// log2 of sum_k 2^(p[k * ps] + q[k * qs]) over k < n, split over s lanes (s
+// a power of two, the group's lanes consecutive): lane j of the group takes
+// k = j, j + s, ..., first the maximum, then the sum of powers, each over four
+// interleaved partial results (loads in flight: a workgroup per CU leaves few
+// waves to hide LDS latency); the lanes' partial maxima and sums are then
+// combined across the group by an xor butterfly (a fixed order), and every
+// lane of the group returns the total.
+__device__ __forceinline__ float lse2_split(const float* p, int ps, const float* q, int qs, int n, int j, int s,
+                                            bool active) {
+  constexpr int U = 4;
+  float m[U], sm[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) m[u] = -INFINITY;
-  int k = 0;
-  for (; k + U <= n; k += U) {
+  for (int u = 0; u < U; ++u) { m[u] = -INFINITY; sm[u] = 0.0f; }
+  if (active) {
+    int k = j;
+    for (; k + (U - 1) * s < n; k += U * s) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) m[u] = fmaxf(m[u], p[(k + u) * ps] + q[(k + u) * qs]);
+      for (int u = 0; u < U; ++u) m[u] = fmaxf(m[u], p[(k + u * s) * ps] + q[(k + u * s) * qs]);
+    }
+    for (int u = 0; k < n; ++u, k += s) m[u] = fmaxf(m[u], p[k * ps] + q[k * qs]);
   }
-  for (int u = 0; k + u < n; ++u) m[u] = fmaxf(m[u], p[(k + u) * ps] + q[(k + u) * qs]);
   float mx = m[0];
 #pragma unroll
   for (int u = 1; u < U; ++u) mx = fmaxf(mx, m[u]);
-  float sm[U];
+  if (active && mx > -INFINITY) {
+    int k = j;
+    for (; k + (U - 1) * s < n; k += U * s) {
 #pragma unroll
-  for (int u = 0; u < U; ++u) sm[u] = 0.0f;
-  k = 0;
-  for (; k + U <= n; k += U) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) sm[u] += hw_exp2(p[(k + u) * ps] + q[(k + u) * qs] - mx);
+      for (int u = 0; u < U; ++u) sm[u] += hw_exp2(p[(k + u * s) * ps] + q[(k + u * s) * qs] - mx);
+    }
+    for (int u = 0; k < n; ++u, k += s) sm[u] += hw_exp2(p[k * ps] + q[k * qs] - mx);
   }
-  for (int u = 0; k + u < n; ++u) sm[u] += hw_exp2(p[(k + u) * ps] + q[(k + u) * qs] - mx);
-  float s = sm[0];
+  float sum = sm[0];
 #pragma unroll
-  for (int u = 1; u < U; ++u) s += sm[u];
-  return mx + hw_log2(s);
+  for (int u = 1; u < U; ++u) sum += sm[u];
+  for (int o = 1; o < s; o <<= 1) {
+    const float om = __shfl_xor(mx, o), os = __shfl_xor(sum, o);
+    const float nm = fmaxf(mx, om);
+    sum = (mx > -INFINITY ? sum * hw_exp2(mx - nm) : 0.0f) + (om > -INFINITY ? os * hw_exp2(om - nm) : 0.0f);
+    mx = nm;
+  }
+  return mx + hw_log2(sum);
 }
+
+// lanes per row (or column) for n rows: as many as 256 threads allow, a power of two up to 8
+__device__ __forceinline__ int lse_split(int n) { return n > 128 ? 1 : (n > 64 ? 2 : (n > 32 ? 4 : 8)); }
 
 // kBig = false: pairs whose matrix fits LDS (kMaxEmdCost entries, stride
 // included); larger pairs are flagged for the second pass. kBig = true: the
@@ -99,10 +114,13 @@ __global__ __launch_bounds__(kEmdThreads) void emd_sinkhorn_kernel(EmdParams P) 
         continue;
       }
     }
-    // row t of the first set in registers
+    // groups of sr (sc) consecutive lanes per row (column) of the matrix
+    const int sr = lse_split(m1), sc = lse_split(m2);
+    const int ri = t / sr, rj = t % sr, ci = t / sc, cj = t % sc;
+    // row ri of the first set in registers (in every lane of its group)
     float a[kDim];
-    if (t < m1) {
-      const int64_t r = P.A.codes ? (int64_t)P.A.codes[a0 + t] : a0 + t;
+    if (ri < m1) {
+      const int64_t r = P.A.codes ? (int64_t)P.A.codes[a0 + ri] : a0 + ri;
       const float4* src = reinterpret_cast<const float4*>(static_cast<const float*>(P.A.vecs) + r * kDim);
 #pragma unroll
       for (int i = 0; i < kDim / 4; ++i) {
@@ -110,7 +128,8 @@ __global__ __launch_bounds__(kEmdThreads) void emd_sinkhorn_kernel(EmdParams P) 
         a[4 * i] = v.x; a[4 * i + 1] = v.y; a[4 * i + 2] = v.z; a[4 * i + 3] = v.w;
       }
     }
-    // L, 16 rows of the second set at a time
+    // L, 16 rows of the second set at a time; lane rj of row ri's group
+    // takes the chunk's rows rj, rj + sr, ...
     for (int j0 = 0; j0 < m2; j0 += kChunk) {
       const int nj = min(kChunk, m2 - j0);
       for (int e = t; e < nj * kDim; e += kEmdThreads) {
@@ -119,15 +138,15 @@ __global__ __launch_bounds__(kEmdThreads) void emd_sinkhorn_kernel(EmdParams P) 
         brow[jj][d] = static_cast<const float*>(P.B.vecs)[r * kDim + d];
       }
       __syncthreads();
-      if (t < m1) {
-        for (int jj = 0; jj < nj; ++jj) {
+      if (ri < m1) {
+        for (int jj = rj; jj < nj; jj += sr) {
           float s = 0.0f;
 #pragma unroll
           for (int d = 0; d < kDim; ++d) {
             const float df = a[d] - brow[jj][d];
             s = fmaf(df, df, s);
           }
-          K[t * ld + j0 + jj] = -sqrtf(s) * scale;
+          K[ri * ld + j0 + jj] = -sqrtf(s) * scale;
         }
       }
       __syncthreads();
@@ -136,9 +155,11 @@ __global__ __launch_bounds__(kEmdThreads) void emd_sinkhorn_kernel(EmdParams P) 
     if (t < m2) gpot[t] = 0.0f;
     __syncthreads();
     for (int it = 0; it < P.n_iter; ++it) {
-      if (t < m1) fpot[t] = la - lse2(gpot, 1, K + t * ld, 1, m2);    // row t
+      const float fr = la - lse2_split(gpot, 1, K + min(ri, m1 - 1) * ld, 1, m2, rj, sr, ri < m1);   // row ri
+      if (ri < m1 && rj == 0) fpot[ri] = fr;
       __syncthreads();
-      if (t < m2) gpot[t] = lb - lse2(fpot, 1, K + t, ld, m1);       // column t
+      const float gc = lb - lse2_split(fpot, 1, K + min(ci, m2 - 1), ld, m1, cj, sc, ci < m2);       // column ci
+      if (ci < m2 && cj == 0) gpot[ci] = gc;
       __syncthreads();
     }
     // cost of the plan: each thread its row, then the rows in order
