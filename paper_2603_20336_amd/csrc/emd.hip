@@ -40,14 +40,14 @@ __device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf
 
 // log2 of sum_k 2^(p[k * ps] + q[k * qs]) over k < n, split over s lanes (s
 // a power of two, the group's lanes consecutive): lane j of the group takes
-// k = j, j + s, ..., first the maximum, then the sum of powers, each over four
+// k = j, j + s, ..., first the maximum, then the sum of powers, each over U
 // interleaved partial results (loads in flight: a workgroup per CU leaves few
-// waves to hide LDS latency); the lanes' partial maxima and sums are then
+// waves to hide the latency); the lanes' partial maxima and sums are then
 // combined across the group by an xor butterfly (a fixed order), and every
 // lane of the group returns the total.
-__device__ __forceinline__ float lse2_split(const float* p, int ps, const float* q, int qs, int n, int j, int s,
+template <int U, int s>
+__device__ __forceinline__ float lse2_split(const float* p, int ps, const float* q, int qs, int n, int j,
                                             bool active) {
-  constexpr int U = 4;
   float m[U], sm[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) { m[u] = -INFINITY; sm[u] = 0.0f; }
@@ -84,6 +84,17 @@ __device__ __forceinline__ float lse2_split(const float* p, int ps, const float*
 
 // lanes per row (or column) for n rows: as many as 256 threads allow, a power of two up to 8
 __device__ __forceinline__ int lse_split(int n) { return n > 128 ? 1 : (n > 64 ? 2 : (n > 32 ? 4 : 8)); }
+
+// lse2_split with the group size s (uniform over the workgroup) as a constant
+__device__ __forceinline__ float lse2_groups(const float* p, int ps, const float* q, int qs, int n, int j, int s,
+                                             bool active) {
+  switch (s) {
+    case 1: return lse2_split<8, 1>(p, ps, q, qs, n, j, active);
+    case 2: return lse2_split<8, 2>(p, ps, q, qs, n, j, active);
+    case 4: return lse2_split<8, 4>(p, ps, q, qs, n, j, active);
+    default: return lse2_split<8, 8>(p, ps, q, qs, n, j, active);
+  }
+}
 
 // kBig = false: pairs whose matrix fits LDS (kMaxEmdCost entries, stride
 // included); larger pairs are flagged for the second pass. kBig = true: the
@@ -155,10 +166,10 @@ __global__ __launch_bounds__(kEmdThreads) void emd_sinkhorn_kernel(EmdParams P) 
     if (t < m2) gpot[t] = 0.0f;
     __syncthreads();
     for (int it = 0; it < P.n_iter; ++it) {
-      const float fr = la - lse2_split(gpot, 1, K + min(ri, m1 - 1) * ld, 1, m2, rj, sr, ri < m1);   // row ri
+      const float fr = la - lse2_groups(gpot, 1, K + min(ri, m1 - 1) * ld, 1, m2, rj, sr, ri < m1);
       if (ri < m1 && rj == 0) fpot[ri] = fr;
       __syncthreads();
-      const float gc = lb - lse2_split(fpot, 1, K + min(ci, m2 - 1), ld, m1, cj, sc, ci < m2);       // column ci
+      const float gc = lb - lse2_groups(fpot, 1, K + min(ci, m2 - 1), ld, m1, cj, sc, ci < m2);
       if (ci < m2 && cj == 0) gpot[ci] = gc;
       __syncthreads();
     }
