@@ -19,6 +19,7 @@ figures, and the CPU oracle timed on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -299,11 +300,13 @@ def bench_exhaustive(args):
     t_topk = timed(lambda: gem.topk(scores, k), max(1, args.steps))
 
     torch.cuda.synchronize()
+    gc.disable()                        # no collector pause inside the timed steps
     t0 = time.perf_counter()
     for _ in range(args.steps):
         top_s, top_i = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    gc.enable()
     ms_per_step = dt * 1e3 / args.steps
     pairs = n_q * n_d
     flops = 2.0 * 128 * q_rows * V
@@ -605,7 +608,7 @@ def bench_expansion(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=2, choices=[2])
     ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU oracle leg and recall")
