@@ -210,8 +210,11 @@ DenseSchedule lookup_dense(gem_ctx ctx, int32_t dtype, int64_t q_rows, int64_t n
 }
 
 // Query batches up to this size take the streamed (gathered) path of a dense
-// call: at most this many passes over the corpus, each at memory speed.
+// call: at most this many passes over the corpus, each at memory speed. FP8
+// batches of two or more queries do better on the dense scorer's narrow-block
+// variant (two workgroups per CU), other formats only from four queries on.
 constexpr int64_t kRangeMaxQueries = 3;
+constexpr int64_t kRangeMaxQueriesFp8 = 1;
 
 gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t compute,
                         int32_t k, float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,
@@ -252,7 +255,7 @@ gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const
     out.scores = scores ? scores : reinterpret_cast<float*>(at(ws, L.staged));
     out.ld = scores ? ld_scores : D->n_sets;
     out.rows = scores ? score_rows : nullptr;
-    if (Q->n_sets <= kRangeMaxQueries && !sched) {
+    if (Q->n_sets <= (compute == GEM_FP8_E4M3 ? kRangeMaxQueriesFp8 : kRangeMaxQueries) && !sched) {
       // a few queries: every document streamed by the gathered scorer (the
       // same scores; the dense scorer would run one lightly loaded block group)
       e = launch_score_range(compute, view(&Qc), view(D), out, stream);
@@ -264,7 +267,7 @@ gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const
                                    stream);
       if (e != hipSuccess) return hip_fail(e, "query-block plan");
       const DenseSchedule ds = sched ? *sched : lookup_dense(ctx, compute, Q->n_vecs, D->n_sets);
-      e = launch_score_dense(compute, view(&Qc), view(D), qb, qcol, L.n_blocks_max, out, ds, stream);
+      e = launch_score_dense(compute, view(&Qc), view(D), qb, qcol, L.n_blocks_max, out, ds, L.block_rows, stream);
       if (e != hipSuccess) return hip_fail(e, "dense scoring");
     }
     if (k > 0) {

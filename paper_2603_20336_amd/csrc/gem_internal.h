@@ -66,7 +66,7 @@ bool dense_schedule_valid(const DenseSchedule& d, int cus_per_xcd);
 
 hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, const int32_t* qb_start,
                               const int64_t* qcol, int64_t n_blocks_max, const DenseOut& out,
-                              const DenseSchedule& sched, hipStream_t s);
+                              const DenseSchedule& sched, int32_t block_rows, hipStream_t s);
 
 hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C,
                                int32_t max_list_len, int32_t max_q_len, float* scores, hipStream_t s);

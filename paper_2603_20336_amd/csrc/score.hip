@@ -376,10 +376,10 @@ __device__ __forceinline__ float readlane_f(float v, int lane) {
 }
 
 // State of one wave over one pass of the dense scorer.
-template <int DT> struct DensePass {
+template <int DT, int NTO = 0> struct DensePass {
   using O = Op<DT>;
   using Frag = typename O::Frag;
-  static constexpr int NT = DenseCfg<DT>::kNT;
+  static constexpr int NT = NTO ? NTO : DenseCfg<DT>::kNT;
   Frag B[NT];                   // query columns of this pass
   float qs[NT / 4];             // FP8: scale of this lane's column in the tile sums
   float rm[NT];                 // running max over the current document, per column tile
@@ -432,12 +432,12 @@ template <int DT> struct DensePass {
 // slots of one of three LDS code arrays (one per group buffer) two groups
 // ahead, with the copies of the group two before, so that a copy never waits
 // on a dependent load and the wait counts stay static.
-template <int DT, bool kCodes>
-__global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams P) {
+template <int DT, bool kCodes, int NTO>
+__device__ __forceinline__ void dense_body(const DenseParams& P) {
   using O = Op<DT>;
   using Frag = typename O::Frag;
   using TS = TileStage<DT>;
-  constexpr int NT = DenseCfg<DT>::kNT;
+  constexpr int NT = NTO ? NTO : DenseCfg<DT>::kNT;
   constexpr int kGroup = TS::kGroup;
   constexpr int kCodeCopies = TS::kCopiesPerWave;               // one code per copy
   constexpr int kIssueOps = TS::kCopiesPerWave + (kCodes ? kCodeCopies : 0);
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
   np = min(((np + even - 1) / even) * even, C);
   const int64_t n_items = np * n_bg;
 
-  DensePass<DT> S;
+  DensePass<DT, NT> S;
   S.tsum = lds_tsum[w];
   int64_t cur_bg = -1;
   int q0 = 0, nq = 0, n_pass = 0, total_tiles = 0;
@@ -720,6 +720,19 @@ __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams 
   }
 }
 
+// The persistent scorer, and its variant for plans of narrow query blocks
+// (small batches): four column tiles a wave, a quarter of the parked-sum LDS
+// and of the query registers, compiled for four waves per SIMD (two resident
+// workgroups per CU).
+template <int DT, bool kCodes>
+__global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams P) {
+  dense_body<DT, kCodes, 0>(P);
+}
+template <int DT>
+__global__ __launch_bounds__(kDenseThreads, 4) void score_dense_narrow_kernel(DenseParams P) {
+  dense_body<DT, false, 4>(P);
+}
+
 DenseSchedule default_dense_schedule(int dtype, int64_t q_rows, int64_t n_docs, int cus_per_xcd) {
   (void)dtype; (void)q_rows; (void)n_docs;
   DenseSchedule d;
@@ -736,7 +749,7 @@ bool dense_schedule_valid(const DenseSchedule& d, int cus_per_xcd) {
 
 hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, const int32_t* qb_start,
                               const int64_t* qcol, int64_t n_blocks_max, const DenseOut& out,
-                              const DenseSchedule& sched, hipStream_t s) {
+                              const DenseSchedule& sched, int32_t block_rows, hipStream_t s) {
   DenseParams P;
   P.Q = Q; P.D = D; P.qb = qb_start; P.qcol = qcol; P.n_blocks_max = n_blocks_max;
   P.n_bgroups = (n_blocks_max + kDenseWaves - 1) / kDenseWaves;
@@ -761,6 +774,8 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
       break;
     case GEM_FP8_E4M3:
       if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_FP8_E4M3, true>), grid, blk, 0, s, P);
+      else if (block_rows <= 64)                             // two workgroups per CU
+        hipLaunchKernelGGL(score_dense_narrow_kernel<GEM_FP8_E4M3>, dim3(2 * grid.x), blk, 0, s, P);
       else hipLaunchKernelGGL((score_dense_kernel<GEM_FP8_E4M3, false>), grid, blk, 0, s, P);
       break;
     case GEM_MXFP4:

@@ -225,7 +225,8 @@ def test_batch_independence_bitwise():
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8", "mxfp4"])
 def test_small_batches_stream_bitwise_as_dense(dtype):
-    """Up to three queries take the streamed path of a dense call: the same
+    """A few queries (up to three; one for FP8) take the streamed path of a
+    dense call, a few more short ones the narrow-block scorer: the same
     scores, bitwise, as the dense scorer gives them inside a larger batch (and
     the oracle's), with empty and long queries, empty and long documents, and
     the rows / ld placement."""
@@ -253,7 +254,8 @@ def test_small_batches_stream_bitwise_as_dense(dtype):
                               _operands(c.vecs.numpy(), dtype), c.offsets.numpy())
         assert_close(big[:6], ref[:6], tol=3e-4, what=f"streamed {dtype}")
     # a dozen short queries: the dense scorer with narrowed query blocks (one
-    # per wave) against the same queries inside a batch of 80 (full blocks)
+    # per wave; for FP8 the narrow-block variant) against the same queries
+    # inside a batch of 80 (full blocks)
     q2 = _ragged(list(np.random.default_rng(4).integers(1, 41, 80)), 42)
     big2 = _np(score(gem.Sets.from_batch(q2, DEV)))
     idx = [3, 7, 0, 12, 40, 41, 42, 43, 44, 60, 61, 79]
