@@ -260,6 +260,8 @@ def test_small_batches_stream_bitwise_as_dense(dtype):
     big2 = _np(score(gem.Sets.from_batch(q2, DEV)))
     idx = [3, 7, 0, 12, 40, 41, 42, 43, 44, 60, 61, 79]
     np.testing.assert_array_equal(_np(score(gem.Sets.from_batch(q2.subset(idx), DEV))), big2[idx])
+    idx = list(range(20, 45))                           # FP8: two block groups of narrow blocks
+    np.testing.assert_array_equal(_np(score(gem.Sets.from_batch(q2.subset(idx), DEV))), big2[idx])
     if dtype != "mxfp4":
         ref2 = oracle.ch_dense(_operands(q2.vecs.numpy(), dtype), q2.offsets.numpy(),
                                _operands(c.vecs.numpy(), dtype), c.offsets.numpy())
