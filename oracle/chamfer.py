@@ -13,6 +13,8 @@ justification in the design notes):
     empty document scores -inf (max over nothing).
   * top-k keeps ids distinct (the best entry of a repeated id wins) and pads
     with (-inf, -1) when fewer than k entries exist.
+  * A negative id is padding (of a candidate list, a segment or the beam): it
+    is never ranked, whatever its score.
 """
 from __future__ import annotations
 
@@ -116,6 +118,8 @@ def _order(scores: np.ndarray, ids: np.ndarray) -> np.ndarray:
 
 
 def _topk_one(scores: np.ndarray, ids: np.ndarray, k: int):
+    live = np.asarray(ids) >= 0                          # a negative id is padding, never ranked
+    scores, ids = np.asarray(scores)[live], np.asarray(ids)[live]
     o = _order(scores, ids)
     s, i = scores[o], ids[o]
     _, first = np.unique(i, return_index=True)         # first occurrence = best entry of each id
@@ -159,7 +163,8 @@ def beam_merge(beam_scores, beam_ids, cand_scores, cand_offsets, cand_ids, ef: i
     """One update of the bounded result set R (Alg. 5): insert the step's scored
     candidates, keep ids distinct, keep the best ef (evicting the worst).
 
-    beam_* are [n_q, ef] (padding id -1 is ignored); candidates are CSR per query.
+    beam_* are [n_q, ef]; candidates are CSR per query; padding ids (negative)
+    on either side are ignored.
     """
     bs, bi = _f64(beam_scores), np.asarray(beam_ids, np.int64)
     cs, ci = _f64(cand_scores), np.asarray(cand_ids, np.int64)

@@ -194,6 +194,18 @@ def test_topk_segments_positions_and_padding():
     assert ts[1, 0] == -math.inf
 
 
+def test_padding_ids_never_ranked():
+    """A negative id is padding: even with the best score it enters neither a
+    top-k nor the beam, and the rest rank as if it were absent."""
+    ts, ti = oracle.topk_segments(np.array([9.0, 1.0, 9.0, 2.0]), [0, 4], 3, seg_ids=np.array([-1, 4, -7, 3]))
+    np.testing.assert_array_equal(ti[0], [3, 4, -1])
+    np.testing.assert_array_equal(ts[0], [2.0, 1.0, -math.inf])
+    bs, bi = oracle.beam_merge(np.array([[5.0, -math.inf]]), np.array([[8, -1]]), np.array([7.0, 6.0, 4.0]),
+                               [0, 3], np.array([-1, 2, -1]), 2)
+    np.testing.assert_array_equal(bi[0], [2, 8])
+    np.testing.assert_array_equal(bs[0], [6.0, 5.0])
+
+
 # --------------------------------------------------------------------- beam (bounded R)
 def test_beam_replay_equals_one_shot_top_ef():
     """After any number of steps the bounded beam equals the top-ef of everything
