@@ -314,12 +314,166 @@ hipError_t launch_topk(const TopkSegs& segs, int32_t k, float* top_scores, int32
 // --------------------------------------------------------------------------
 // Beam update: row q of the beam becomes the best ef of (row q) U (list q's
 // scored entries), ids distinct. One workgroup per query.
+// Slot of an id in the merge's hash table of beam positions (Fibonacci hashing).
+template <int kSlots>
+__device__ __forceinline__ uint32_t beam_hash(int32_t id) {
+  static_assert((kSlots & (kSlots - 1)) == 0, "power of two");
+  return ((uint32_t)id * 0x9E3779B1u) >> (32 - __builtin_ctz((unsigned)kSlots));
+}
+
+// Merge of beam row `q` in its stored form (rank keys strictly descending,
+// padding only at the tail, ids distinct; the form this merge and the reset
+// leave) with a list of at most kCap / 2 entries, ef <= kCap / 2. Only the
+// list is sorted: by id to keep the best entry of each id, then by rank. A
+// listed id that the beam holds keeps the better of the two entries (the beam's
+// on equal keys). Each survivor's output position is its rank in its own
+// sorted run plus the count of entries of the other run ranked above it
+// (keys are distinct between the runs), found by binary search. Returns false,
+// with nothing written, when the row is not in the stored form; the caller then
+// merges by the full sort, which gives the same result on any row.
 template <int kCap, int kThreads>
+__device__ bool merge_sorted_beam(uint64_t* keys, uint32_t* slots, uint32_t* drop, int* s_int,
+                                  const float* __restrict__ cand_scores, const int32_t* __restrict__ cids,
+                                  int nl, int ef, float* bs, int32_t* bi) {
+  constexpr int kHalf = kCap / 2;
+  constexpr int kSlots = kCap;                       // twice the largest beam
+  constexpr uint32_t kEmpty = 0xffffffffu;
+  constexpr int kPer = kHalf / kThreads;
+  uint64_t* bk = keys;                               // the beam's rank keys, [0, ef)
+  uint64_t* ck = keys + kHalf;                       // the list's keys, [0, nc)
+  const int tid = threadIdx.x;
+  const int nc = pow2_ceil(max(nl, 1));
+  // s_int: [0] not in stored form, [1] valid beam entries, [2] dropped beam
+  // entries, [3] surviving list entries
+  if (tid < 4) s_int[tid] = 0;
+  for (int r = tid; r < ef; r += kThreads) {
+    const int32_t id = bi[r];
+    bk[r] = id >= 0 ? rank_key(bs[r], id) : 0ull;
+    drop[r] = 0;
+  }
+  for (int h = tid; h < kSlots; h += kThreads) slots[h] = kEmpty;
+  for (int j = tid; j < nc; j += kThreads) {
+    const int32_t id = j < nl ? cids[j] : -1;
+    ck[j] = id >= 0 ? id_key(rank_key(cand_scores[j], id)) : ~0ull;
+  }
+  __syncthreads();
+  int bad = 0, valid = 0;
+  for (int r = tid; r < ef; r += kThreads) {
+    const uint64_t k = bk[r];
+    if (r + 1 < ef) {
+      const uint64_t k2 = bk[r + 1];
+      if (k2 != 0ull && (k == 0ull || k2 >= k)) bad = 1;
+    }
+    if (k == 0ull) continue;
+    ++valid;
+    const int32_t id = key_id(k);
+    uint32_t h = beam_hash<kSlots>(id);
+    for (;;) {                                       // at most ef of 2 ef slots are taken: ends
+      const uint32_t prev = atomicCAS(&slots[h], kEmpty, (uint32_t)r);
+      if (prev == kEmpty) break;
+      if (key_id(bk[prev]) == id) { bad = 1; break; }
+      h = (h + 1) & (kSlots - 1);
+    }
+  }
+  if (bad) atomicOr(&s_int[0], 1);
+  if (valid) atomicAdd(&s_int[1], valid);
+  __syncthreads();
+  if (s_int[0]) return false;                        // uniform: read after the barrier
+  block_bitonic_sort(ck, nc, false);                 // by id, best entry of an id first
+  uint64_t kept[kPer];
+  int n_kept = 0, n_drop = 0;
+#pragma unroll
+  for (int c = 0; c < kPer; ++c) {
+    const int j = tid + c * kThreads;
+    kept[c] = 0ull;
+    if (j >= nc) continue;
+    const uint64_t ik = ck[j];
+    if (ik == ~0ull || (j > 0 && (uint32_t)(ck[j - 1] >> 32) == (uint32_t)(ik >> 32))) continue;
+    const uint64_t rk = rank_from_id_key(ik);
+    const int32_t id = key_id(rk);
+    bool keep = true;
+    for (uint32_t h = beam_hash<kSlots>(id);; h = (h + 1) & (kSlots - 1)) {
+      const uint32_t p = slots[h];
+      if (p == kEmpty) break;
+      if (key_id(bk[p]) == id) {                     // one list entry per id: no race on drop[p]
+        if (rk > bk[p]) { drop[p] = 1; ++n_drop; } else keep = false;
+        break;
+      }
+    }
+    if (keep) { kept[c] = rk; ++n_kept; }
+  }
+  if (n_drop) atomicAdd(&s_int[2], n_drop);
+  if (n_kept) atomicAdd(&s_int[3], n_kept);
+  __syncthreads();                                   // every read of the id-sorted list is done
+#pragma unroll
+  for (int c = 0; c < kPer; ++c) {
+    const int j = tid + c * kThreads;
+    if (j < nc) ck[j] = kept[c];
+  }
+  __syncthreads();
+  block_bitonic_sort(ck, nc, true);                  // survivors by rank, then the zeros
+  const int nb = s_int[1], dropped = s_int[2], ns = s_int[3];
+  if (dropped) {
+    // inclusive count of dropped beam entries up to each position (rare:
+    // a listed id scored above the beam's entry for it)
+    for (int off = 1; off < nb; off <<= 1) {
+      uint32_t v[kPer];
+#pragma unroll
+      for (int c = 0; c < kPer; ++c) {
+        const int r = tid + c * kThreads;
+        v[c] = r < nb ? drop[r] + (r >= off ? drop[r - off] : 0u) : 0u;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < kPer; ++c) {
+        const int r = tid + c * kThreads;
+        if (r < nb) drop[r] = v[c];
+      }
+      __syncthreads();
+    }
+  }
+  // beam entry i (kept): position (i - dropped before i) + (list keys above it)
+  for (int i = tid; i < nb; i += kThreads) {
+    const uint32_t upto = dropped ? drop[i] : 0u;
+    if (dropped && upto != (i > 0 ? drop[i - 1] : 0u)) continue;
+    const uint64_t k = bk[i];
+    int lo = 0, hi = ns;                             // first list position ranked below k
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (ck[mid] > k) lo = mid + 1; else hi = mid;
+    }
+    const int pos = i - (int)upto + lo;
+    if (pos < ef) { bs[pos] = key_score(k); bi[pos] = key_id(k); }
+  }
+  // list entry j: position j + (kept beam entries above it)
+  for (int j = tid; j < ns; j += kThreads) {
+    const uint64_t k = ck[j];
+    int lo = 0, hi = nb;                             // first beam position ranked below k
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (bk[mid] > k) lo = mid + 1; else hi = mid;
+    }
+    const int pos = j + lo - (int)(dropped && lo > 0 ? drop[lo - 1] : 0u);
+    if (pos < ef) { bs[pos] = key_score(k); bi[pos] = key_id(k); }
+  }
+  for (int r = nb - dropped + ns + tid; r < ef; r += kThreads) {
+    bs[r] = neg_inf();
+    bi[r] = -1;
+  }
+  return true;
+}
+
+// kSorted: rows in the stored form with at most kCap / 2 beam and list
+// entries take merge_sorted_beam (which needs kCap * 6 more bytes of LDS).
+template <int kCap, int kThreads, bool kSorted>
 __global__ __launch_bounds__(kThreads) void beam_merge_kernel(const float* __restrict__ cand_scores, CandsView C,
                                                                  int64_t n_q, int32_t ef,
                                                                  float* __restrict__ beam_scores,
                                                                  int32_t* __restrict__ beam_ids) {
   __shared__ uint64_t keys[kCap];
+  __shared__ uint32_t slots[kSorted ? kCap : 1];
+  __shared__ uint32_t drop[kSorted ? kCap / 2 : 1];
+  __shared__ int s_int[4];
   __shared__ int s_cnt;
   const int tid = threadIdx.x;
   for (int64_t q = blockIdx.x; q < n_q; q += gridDim.x) {
@@ -327,10 +481,16 @@ __global__ __launch_bounds__(kThreads) void beam_merge_kernel(const float* __res
   int64_t lb, le;
   if (C.off) { lb = C.off[q]; le = C.off[q + 1]; }
   else { lb = q * (int64_t)C.stride; le = lb + C.stride; }
-  if (tid == 0) s_cnt = 0;
-  __syncthreads();
   float* bs = beam_scores + q * ef;
   int32_t* bi = beam_ids + q * ef;
+  if (kSorted && ef <= kCap / 2 && le - lb <= kCap / 2) {
+    if (merge_sorted_beam<kCap, kThreads>(keys, slots, drop, s_int, cand_scores + lb, C.ids + lb, (int)(le - lb),
+                                          ef, bs, bi))
+      continue;
+    __syncthreads();                                 // the fast path's reads of keys are done
+  }
+  if (tid == 0) s_cnt = 0;
+  __syncthreads();
   for (int r = tid; r < ef; r += kThreads) {
     const int32_t id = bi[r];
     if (id >= 0) {
@@ -363,10 +523,10 @@ hipError_t launch_beam_merge(const float* cand_scores, const CandsView& C, int64
   // merges of at most 2048 entries (ef + the longest list, when known) run
   // in half the LDS with 256 threads: twice the workgroups per CU
   if (max_entries > 0 && max_entries <= 2048)
-    hipLaunchKernelGGL((beam_merge_kernel<2048, 256>), dim3(capped_blocks(n_q, 256)), dim3(256), 0, s, cand_scores,
+    hipLaunchKernelGGL((beam_merge_kernel<2048, 256, true>), dim3(capped_blocks(n_q, 256)), dim3(256), 0, s, cand_scores,
                        C, n_q, ef, beam_scores, beam_ids);
   else
-    hipLaunchKernelGGL((beam_merge_kernel<kSelCap, kSelThreads>), dim3(capped_blocks(n_q, kSelThreads)),
+    hipLaunchKernelGGL((beam_merge_kernel<kSelCap, kSelThreads, false>), dim3(capped_blocks(n_q, kSelThreads)),
                        dim3(kSelThreads), 0, s, cand_scores, C, n_q, ef, beam_scores, beam_ids);
   return hipGetLastError();
 }

@@ -459,10 +459,14 @@ def test_topk_long_segments_with_repeats():
 
 
 # ----------------------------------------------------------------------- beam
-@pytest.mark.parametrize("n_q,ef,max_list,n_docs", [(9, 50, 80, 2000), (5, 1024, 3000, 20000)])
+@pytest.mark.parametrize("n_q,ef,max_list,n_docs", [(9, 50, 80, 2000), (6, 1000, 1000, 30000),
+                                                    (5, 8, 1500, 20000), (5, 1024, 3000, 20000)])
 def test_beam_merge_bitwise(n_q, ef, max_list, n_docs):
-    """Beam updates against the oracle's replay, up to ef = 1024 with 3000-entry
-    lists (the largest merge is ef + list = 4024 entries)."""
+    """Beam updates against the oracle's replay: merges of up to 2048 entries
+    with beams and lists of up to 1024 (the sorted-beam merge), lists longer
+    than that (the full sort) and ef = 1024 with 3000-entry lists (the largest
+    merge is ef + list = 4024 entries). Even steps draw scores with ties, so a
+    listed id the beam holds may score above or below the beam's entry."""
     beam = gem.Beam(n_q, ef, DEV)
     steps = []
     for st in range(6):
@@ -475,6 +479,61 @@ def test_beam_merge_bitwise(n_q, ef, max_list, n_docs):
         steps.append((s.numpy(), off.numpy(), ids.numpy()))
     torch.cuda.synchronize()
     rs, ri = oracle.beam_replay(n_q, ef, steps)
+    np.testing.assert_array_equal(_np(beam.ids), ri)
+    np.testing.assert_array_equal(_np(beam.scores), rs.astype(np.float32))
+
+
+def test_beam_merge_rows_in_any_form():
+    """Beam rows written by the caller: in the stored form (sorted, padded at
+    the tail), out of order, with a repeated id, with padding in the middle and
+    empty; lists with padding ids, repeated ids and ids the beam holds at a
+    better, equal or worse score. Every row is the oracle's merge, bitwise."""
+    rng = np.random.default_rng(31)
+    ef, n_q = 64, 6
+    bs = np.full((n_q, ef), -np.inf, np.float32)
+    bi = np.full((n_q, ef), -1, np.int32)
+
+    def stored(ids, sc):
+        o = np.lexsort((ids, -sc))
+        return sc[o], ids[o]
+
+    for q in (0, 5):
+        ids = rng.choice(500, 40, replace=False).astype(np.int32)
+        sc = rng.integers(0, 8, 40).astype(np.float32)              # ties
+        bs[q, :40], bi[q, :40] = stored(ids, sc)
+    ids = rng.choice(500, ef, replace=False).astype(np.int32)
+    bs[1], bi[1] = rng.standard_normal(ef).astype(np.float32), ids    # out of order
+    sc2, id2 = stored(rng.choice(500, 30, replace=False).astype(np.int32),
+                      rng.standard_normal(30).astype(np.float32))
+    id2[20] = id2[3]                                                # a repeated id
+    bs[2, :30], bi[2, :30] = sc2, id2
+    sc3, id3 = stored(rng.choice(500, 30, replace=False).astype(np.int32),
+                      rng.standard_normal(30).astype(np.float32))
+    bs[3, :10], bi[3, :10] = sc3[:10], id3[:10]
+    bs[3, 12:32], bi[3, 12:32] = sc3[10:], id3[10:]                 # padding in the middle
+    lists_s, lists_i = [], []
+    for q in range(n_q):
+        n = int(rng.integers(0, 90))
+        li = rng.integers(0, 500, n).astype(np.int32)
+        ls = rng.integers(0, 8, n).astype(np.float32)
+        held = bi[q][bi[q] >= 0]
+        if held.size:                                               # ids the beam holds
+            pick = rng.choice(held.size, min(12, held.size), replace=False)
+            base = bs[q][bi[q] >= 0][pick]
+            li = np.concatenate([li, held[pick]])
+            ls = np.concatenate([ls, base + rng.choice([-1.0, 0.0, 1.0], pick.size).astype(np.float32)])
+        li[rng.random(li.size) < 0.1] = -1                          # padding ids
+        lists_s.append(ls), lists_i.append(li)
+    off = np.zeros(n_q + 1, np.int64)
+    off[1:] = np.cumsum([len(x) for x in lists_i])
+    cs, ci = np.concatenate(lists_s), np.concatenate(lists_i).astype(np.int32)
+    beam = gem.Beam(n_q, ef, DEV)
+    beam.scores.copy_(torch.from_numpy(bs))
+    beam.ids.copy_(torch.from_numpy(bi))
+    gem.beam_merge(torch.from_numpy(cs).to(DEV), gem.Cands(torch.from_numpy(ci).to(DEV),
+                                                            torch.from_numpy(off).to(DEV)), beam)
+    torch.cuda.synchronize()
+    rs, ri = oracle.beam_merge(bs, bi, cs, off, ci, ef)
     np.testing.assert_array_equal(_np(beam.ids), ri)
     np.testing.assert_array_equal(_np(beam.scores), rs.astype(np.float32))
 
