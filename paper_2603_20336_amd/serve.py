@@ -254,7 +254,7 @@ class DeviceExecutor(Executor):
     """
 
     def __init__(self, D8, D32, n_chunks: int, max_slots: int, shortlist: int = 1000, k: int = 100,
-                 max_query_len: int = 64, stream=None, copy_stream: bool = False):
+                 max_query_len: int = 64, stream=None, copy_stream: bool = False, max_ahead: int = 1):
         import importlib
         self._gem = importlib.import_module(__package__)
         self.D8, self.D32 = D8, D32
@@ -265,6 +265,7 @@ class DeviceExecutor(Executor):
         self.shortlist, self.k = int(shortlist), int(k)
         self.L = int(max_query_len)
         self.max_slots = int(max_slots)
+        self.max_ahead = max(1, int(max_ahead))
         self.device = D8.device
         self.stream = stream
         self.est = torch.empty(max_slots, self.n_docs, dtype=torch.float32, device=self.device)
@@ -402,9 +403,11 @@ class DeviceExecutor(Executor):
         self.score_chunks(chunk, 1)
 
     def score_chunks(self, chunk: int, span: int) -> None:
-        # the host runs at most two iterations ahead of the device: deeper
-        # queues add their whole backlog to a new request's latency
-        if len(self._iter_evts) >= 2:
+        # the host runs at most max_ahead iterations ahead of the device:
+        # deeper queues add their whole backlog to a new request's latency
+        # (the next iteration's admission and gather are issued before this
+        # wait, so they still overlap the previous iteration's scoring)
+        if len(self._iter_evts) >= self.max_ahead:
             self._iter_evts.pop(0).synchronize()
         end = chunk + span
         ranges = [(chunk, min(end, self.n_chunks))]
