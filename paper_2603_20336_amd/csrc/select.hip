@@ -29,22 +29,85 @@ __device__ __forceinline__ uint64_t rank_from_id_key(uint64_t ik) {
   return ((uint64_t)(~(uint32_t)ik) << 32) | (uint64_t)(~(uint32_t)(ik >> 32));
 }
 
-// Bitonic sort of a[0..n) (n a power of two), descending if `desc`. Every
-// stage has n / 2 compare-exchange pairs; thread t takes pairs t, t + T, ...
-// (pair p of stage j is elements i = 2 j (p / j) + p % j and i + j).
-__device__ void block_bitonic_sort(uint64_t* a, int n, bool desc) {
+// One compare-exchange stage of merge k with partner distance j over
+// a[0..n): n / 2 pairs, thread t takes pairs t, t + T, ... (pair p is
+// elements i = 2 j (p / j) + p % j and i + j).
+__device__ __forceinline__ void bitonic_stage(uint64_t* a, int half, int k, int j, bool desc) {
+  for (int p = threadIdx.x; p < half; p += blockDim.x) {
+    const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+    const int ixj = i + j;
+    const uint64_t x = a[i], y = a[ixj];
+    const bool up = ((i & k) == 0) != desc;             // this pair ascending?
+    if ((x > y) == up) { a[i] = y; a[ixj] = x; }
+  }
+}
+
+// Bitonic sort with the stages of partner distance below E in registers:
+// thread t holds elements [t E, t E + E) (t < n / E), so those stages pair
+// only its own elements. The merges k <= E run wholly in registers; every
+// later merge runs its stages j >= E through LDS, one pass each, then its
+// last log2(E) stages in registers (for k > E the direction is the same over
+// a thread's E elements). The same network as stage by stage, with one LDS
+// pass for the last log2(E) stages of each merge.
+template <int E>
+__device__ void bitonic_sort_regs(uint64_t* a, int n, bool desc) {
   const int half = n >> 1;
-  for (int k = 2; k <= n; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int p = threadIdx.x; p < half; p += blockDim.x) {
-        const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
-        const int ixj = i + j;
-        const uint64_t x = a[i], y = a[ixj];
-        const bool up = ((i & k) == 0) != desc;         // this pair ascending?
-        if ((x > y) == up) { a[i] = y; a[ixj] = x; }
-      }
+  const bool owner = (int)threadIdx.x < n / E;
+  const int i0 = (int)threadIdx.x * E;
+  uint64_t v[E];
+  auto cx = [&](int e, int j, bool up) {
+    const uint64_t x = v[e], y = v[e + j];
+    if ((x > y) == up) { v[e] = y; v[e + j] = x; }
+  };
+  if (owner) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = a[i0 + e];
+#pragma unroll
+    for (int k = 2; k <= E; k <<= 1)
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if ((e & j) == 0) cx(e, j, (((i0 | e) & k) == 0) != desc);
+#pragma unroll
+    for (int e = 0; e < E; ++e) a[i0 + e] = v[e];
+  }
+  __syncthreads();
+  for (int k = 2 * E; k <= n; k <<= 1) {
+    for (int j = k >> 1; j >= E; j >>= 1) {
+      bitonic_stage(a, half, k, j, desc);
       __syncthreads();
     }
+    if (owner) {
+      const bool up = ((i0 & k) == 0) != desc;
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = a[i0 + e];
+#pragma unroll
+      for (int j = E >> 1; j > 0; j >>= 1)
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if ((e & j) == 0) cx(e, j, up);
+#pragma unroll
+      for (int e = 0; e < E; ++e) a[i0 + e] = v[e];
+    }
+    __syncthreads();
+  }
+}
+
+// Bitonic sort of a[0..n) (n a power of two), descending if `desc`; every
+// thread of the block takes part, and a[] is published at the end.
+__device__ void block_bitonic_sort(uint64_t* a, int n, bool desc) {
+  if (n < 2) return;
+  const int per = n / (int)blockDim.x;                  // elements per thread
+  if (per <= 2) bitonic_sort_regs<2>(a, n, desc);
+  else if (per == 4) bitonic_sort_regs<4>(a, n, desc);
+  else if (per == 8) bitonic_sort_regs<8>(a, n, desc);
+  else {
+    for (int k = 2; k <= n; k <<= 1)
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        bitonic_stage(a, n >> 1, k, j, desc);
+        __syncthreads();
+      }
   }
 }
 
@@ -112,7 +175,7 @@ __device__ __forceinline__ void hist_add(uint32_t* hist, bool active, uint32_t b
   }
 }
 
-__global__ __launch_bounds__(kSelThreads) void topk_kernel(TopkSegs S, int32_t k, float* __restrict__ top_scores,
+__global__ __launch_bounds__(kSelThreads, 8) void topk_kernel(TopkSegs S, int32_t k, float* __restrict__ top_scores,
                                                           int32_t* __restrict__ top_ids) {
   __shared__ uint64_t keys[kSelCap];
   __shared__ uint32_t hist[256];
