@@ -698,8 +698,7 @@ gem_status gem_search_step(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, co
   int32_t row = 0;
   gem_status st = check_search(Q, D, G, S, beam, &v, &row);
   if (st != GEM_OK) return st;
-  hipError_t e = launch_search_select(v, Q->n_sets, beam->ids, beam->ef, stream);
-  if (e == hipSuccess) e = launch_search_expand(v, Q->n_sets, S->cand_ids, row, stream);
+  hipError_t e = launch_search_step(v, Q->n_sets, beam->ids, beam->ef, S->cand_ids, row, stream);
   if (e != hipSuccess) return hip_fail(e, "search step");
   if (Q->n_sets == 0) return GEM_OK;
   return search_score_merge(Q, D, S, beam, row, stream);

@@ -135,8 +135,9 @@ hipError_t launch_query_clusters(const int64_t* q_off, const float* q, int64_t n
 hipError_t launch_search_clear(const SearchView& S, int64_t n_q, hipStream_t s);
 hipError_t launch_search_entries(const SearchView& S, int64_t n_q, const uint32_t* u, int32_t* cand, int32_t stride,
                                  hipStream_t s);
-hipError_t launch_search_select(const SearchView& S, int64_t n_q, const int32_t* beam_ids, int32_t ef, hipStream_t s);
-hipError_t launch_search_expand(const SearchView& S, int64_t n_q, int32_t* cand, int32_t stride, hipStream_t s);
+// One search step's select and expand (clears *S.active first).
+hipError_t launch_search_step(const SearchView& S, int64_t n_q, const int32_t* beam_ids, int32_t ef, int32_t* cand,
+                              int32_t stride, hipStream_t s);
 
 // Entropic EMD of set pairs (one workgroup per pair).
 constexpr int kMaxEmdCost = 36864;     // entries of the LDS cost matrix (m1 * m2)

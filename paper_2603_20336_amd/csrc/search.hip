@@ -295,13 +295,20 @@ __global__ __launch_bounds__(256) void search_entries_kernel(SearchView S, int64
   }
 }
 
-// One wave per query: the first w entries of R (sorted, padding at the end)
-// that are not expanded become the frontier and are marked expanded.
-__global__ __launch_bounds__(256) void search_select_kernel(SearchView S, int64_t n_q, const int32_t* __restrict__ beam_ids,
-                                                            int32_t ef) {
+// One wave per query, one step of the search:
+// - select: the first w entries of R (sorted, padding at the end) that are
+//   not expanded become the frontier and are marked expanded; lane f keeps
+//   frontier entry f (w <= 64), which is also written to S.frontier;
+// - expand: the neighbours of the frontier (lists in order) that share a
+//   cluster with C_query and were not visited (marked now), compacted into
+//   the query's candidate row; the rest is padding.
+__global__ __launch_bounds__(256) void search_step_kernel(SearchView S, int64_t n_q, const int32_t* __restrict__ beam_ids,
+                                                          int32_t ef, int32_t* __restrict__ cand, int32_t stride) {
   const int l = threadIdx.x & 63;
+  const int words = (S.k2 + 31) / 32;
   for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < n_q; q += (int64_t)gridDim.x * 4) {
     int taken = 0;
+    int fr = -1;                                                 // lane f: frontier entry f
     for (int e0 = 0; e0 < ef && taken < S.width; e0 += 64) {
       const int e = e0 + l;
       const int id = e < ef ? beam_ids[q * ef + e] : -1;
@@ -312,27 +319,23 @@ __global__ __launch_bounds__(256) void search_select_kernel(SearchView S, int64_
         S.frontier[q * S.width + rank] = id;
         atomicOr(&S.expanded[q * S.bitmap_words + (id >> 5)], 1u << (id & 31));
       }
+      // the entries taken here move to lanes taken, taken + 1, ... in order
+      uint64_t rest = bal;
+      for (int f = taken; f < S.width && rest != 0; ++f) {
+        const int src = __builtin_ctzll(rest);
+        rest &= rest - 1;
+        const int v = __builtin_amdgcn_readlane(id, src);
+        if (l == f) fr = v;
+      }
       taken += __popcll(bal);
       if (__ballot(id < 0 && e < ef)) break;                     // reached the padding
     }
     taken = min(taken, S.width);
     for (int i = taken + l; i < S.width; i += 64) S.frontier[q * S.width + i] = -1;
     if (l == 0 && taken > 0) atomicAdd(S.active, 1u);
-  }
-}
-
-// One wave per query: the neighbours of its frontier (lists in order) that
-// share a cluster with C_query and were not visited (marked now), compacted
-// into the query's candidate row; the rest is padding.
-__global__ __launch_bounds__(256) void search_expand_kernel(SearchView S, int64_t n_q, int32_t* __restrict__ cand,
-                                                            int32_t stride) {
-  const int l = threadIdx.x & 63;
-  const int words = (S.k2 + 31) / 32;
-  for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < n_q; q += (int64_t)gridDim.x * 4) {
     int pos = 0;
-    for (int f = 0; f < S.width; ++f) {
-      const int p = S.frontier[q * S.width + f];
-      if (p < 0) break;
+    for (int f = 0; f < taken; ++f) {
+      const int p = __builtin_amdgcn_readlane(fr, f);
       for (int d0 = 0; d0 < S.degree; d0 += 64) {
         const int d = d0 + l;
         int nb = d < S.degree ? S.neighbors[(int64_t)p * S.degree + d] : -1;
@@ -374,18 +377,12 @@ hipError_t launch_search_entries(const SearchView& S, int64_t n_q, const uint32_
   return hipGetLastError();
 }
 
-hipError_t launch_search_select(const SearchView& S, int64_t n_q, const int32_t* beam_ids, int32_t ef, hipStream_t s) {
+hipError_t launch_search_step(const SearchView& S, int64_t n_q, const int32_t* beam_ids, int32_t ef, int32_t* cand,
+                              int32_t stride, hipStream_t s) {
   hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, s, S.active, (int64_t)1, 0u);
   if (n_q == 0) return hipGetLastError();
-  hipLaunchKernelGGL(search_select_kernel, dim3(capped_blocks((n_q + 3) / 4, 256)), dim3(256), 0, s, S, n_q, beam_ids,
-                     ef);
-  return hipGetLastError();
-}
-
-hipError_t launch_search_expand(const SearchView& S, int64_t n_q, int32_t* cand, int32_t stride, hipStream_t s) {
-  if (n_q == 0) return hipSuccess;
-  hipLaunchKernelGGL(search_expand_kernel, dim3(capped_blocks((n_q + 3) / 4, 256)), dim3(256), 0, s, S, n_q, cand,
-                     stride);
+  hipLaunchKernelGGL(search_step_kernel, dim3(capped_blocks((n_q + 3) / 4, 256)), dim3(256), 0, s, S, n_q, beam_ids,
+                     ef, cand, stride);
   return hipGetLastError();
 }
 
