@@ -483,6 +483,30 @@ def test_beam_merge_bitwise(n_q, ef, max_list, n_docs):
     np.testing.assert_array_equal(_np(beam.scores), rs.astype(np.float32))
 
 
+@pytest.mark.parametrize("ef", [1, 64, 1023])
+def test_beam_merge_list_length_boundaries(ef):
+    """Lists of exactly 1024 entries (the longest the sorted-beam merge takes),
+    1025 (the full sort in the same launch), a single entry and none, merged
+    twice (the second time into rows in the stored form), against the oracle."""
+    rng = np.random.default_rng(ef)
+    lens = [1024, 1025, 1, 0]
+    beam = gem.Beam(len(lens), ef, DEV)
+    steps = []
+    for st in range(2):
+        off = np.zeros(len(lens) + 1, np.int64)
+        off[1:] = np.cumsum(lens)
+        ids = rng.integers(0, 3000, int(off[-1])).astype(np.int32)       # repeats across and within lists
+        sc = np.sin(ids.astype(np.float64) * 0.71 + st).astype(np.float32) if st else \
+            rng.integers(0, 16, ids.size).astype(np.float32)            # ties, then one score per id
+        gem.beam_merge(torch.from_numpy(sc).to(DEV), gem.Cands(torch.from_numpy(ids).to(DEV),
+                                                                torch.from_numpy(off).to(DEV)), beam)
+        steps.append((sc, off, ids))
+    torch.cuda.synchronize()
+    rs, ri = oracle.beam_replay(len(lens), ef, steps)
+    np.testing.assert_array_equal(_np(beam.ids), ri)
+    np.testing.assert_array_equal(_np(beam.scores), rs.astype(np.float32))
+
+
 def test_beam_merge_rows_in_any_form():
     """Beam rows written by the caller: in the stored form (sorted, padded at
     the tail), out of order, with a repeated id, with padding in the middle and
