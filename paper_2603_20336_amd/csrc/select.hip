@@ -14,6 +14,7 @@ namespace gem {
 constexpr int kSelThreads = 512;
 constexpr int kSelCap = 4096;     // entries a workgroup can hold in LDS
 constexpr int kSelUnroll = 8;     // score loads in flight per thread in the radix passes
+constexpr int kSelVec = 4;        // 16-byte score loads in flight per thread in the sampled collect pass
 constexpr int kTopkSample = 2048; // entries sampled for the threshold of a long positional segment
 
 __device__ __forceinline__ uint64_t rank_key(float s, int32_t id) {
@@ -252,24 +253,39 @@ __global__ __launch_bounds__(kSelThreads, 8) void topk_kernel(TopkSegs S, int32_
       __syncthreads();
       if (tid == 0) s_cnt = 0;
       __syncthreads();
-      for (int64_t j0 = 0; j0 < A.n; j0 += (int64_t)kSelThreads * kSelUnroll) {
-        float v[kSelUnroll];
+      auto take = [&](float x, int64_t j) {
+        const uint64_t key = rank_key(x, (int32_t)j);
+        if (key >= thr) {
+          const int pos = atomicAdd(&s_cnt, 1);
+          if (pos < kSelCap) keys[pos] = key;
+        }
+      };
+      // 16-byte loads: the entries before the segment's first 16-byte
+      // boundary and after its last whole float4 one by one
+      const int64_t head = min<int64_t>(A.n, (int64_t)(((16u - ((uint32_t)reinterpret_cast<uintptr_t>(A.sc) & 15u)) & 15u) >> 2));
+      const int64_t nv = (A.n - head) >> 2;
+      const float4* sc4 = reinterpret_cast<const float4*>(A.sc + head);
+      if (tid < head) take(A.sc[tid], tid);
+      for (int64_t i0 = 0; i0 < nv; i0 += (int64_t)kSelThreads * kSelVec) {
+        float4 v[kSelVec];
 #pragma unroll
-        for (int u = 0; u < kSelUnroll; ++u) {
-          const int64_t j = j0 + u * kSelThreads + tid;
-          v[u] = j < A.n ? A.sc[j] : 0.0f;
+        for (int u = 0; u < kSelVec; ++u) {
+          const int64_t i = i0 + u * kSelThreads + tid;
+          v[u] = i < nv ? sc4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
-        for (int u = 0; u < kSelUnroll; ++u) {
-          const int64_t j = j0 + u * kSelThreads + tid;
-          if (j >= A.n) continue;
-          const uint64_t key = rank_key(v[u], (int32_t)j);
-          if (key >= thr) {
-            const int pos = atomicAdd(&s_cnt, 1);
-            if (pos < kSelCap) keys[pos] = key;
-          }
+        for (int u = 0; u < kSelVec; ++u) {
+          const int64_t i = i0 + u * kSelThreads + tid;
+          if (i >= nv) continue;
+          const int64_t j = head + 4 * i;
+          take(v[u].x, j);
+          take(v[u].y, j + 1);
+          take(v[u].z, j + 2);
+          take(v[u].w, j + 3);
         }
       }
+      const int64_t tail = head + 4 * nv;
+      if (tail + tid < A.n) take(A.sc[tail + tid], tail + tid);
       __syncthreads();
       const int got = s_cnt;
       __syncthreads();
