@@ -251,6 +251,8 @@ class DeviceExecutor(Executor):
 
     Each slot holds one request's query vectors on the device (float32 for the
     rerank, FP8 codes and scales for the estimate), written once at admission.
+    max_ahead: iterations the host may issue before the device has finished
+    the oldest of them (1 keeps a new request behind at most one iteration).
     """
 
     def __init__(self, D8, D32, n_chunks: int, max_slots: int, shortlist: int = 1000, k: int = 100,
