@@ -441,6 +441,26 @@ def test_topk_bitwise(mode):
         np.testing.assert_array_equal(_np(ts), rs.astype(np.float32))
 
 
+def test_topk_long_positional_segments_every_alignment():
+    """Positional segments longer than the in-LDS capacity (the sampled path
+    reads them with 16-byte loads) starting at every offset mod 4 and ending
+    with 0-3 entries past the last whole vector: bitwise the oracle's top-k."""
+    rng = np.random.default_rng(21)
+    lens = [5001, 4097, 6002, 4099, 8192, 4103, 7000, 4098]
+    off = np.zeros(len(lens) + 2, np.int64)
+    off[1] = 1                                                      # segments start 1 entry in
+    off[2:] = 1 + np.cumsum(lens)
+    starts = off[1:-1]
+    assert sorted(set(int(x) % 4 for x in starts)) == [0, 1, 2, 3]
+    sc = rng.standard_normal(int(off[-1])).astype(np.float32)
+    sc[off[1]:off[2]] = rng.integers(0, 40, lens[0]).astype(np.float32)   # heavy ties in one segment
+    for k in (1, 100, 1000):
+        ts, ti = gem.topk(torch.from_numpy(sc).to(DEV), k, seg_offsets=torch.from_numpy(off[1:]).to(DEV))
+        rs, ri = oracle.topk_segments(sc, off[1:], k)
+        np.testing.assert_array_equal(_np(ti), ri)
+        np.testing.assert_array_equal(_np(ts), rs.astype(np.float32))
+
+
 def test_topk_long_segments_with_repeats():
     """Radix path (segments longer than the in-LDS capacity) with repeated ids."""
     rng = np.random.default_rng(8)
