@@ -672,3 +672,103 @@ def test_expansion_graph_replays_equal_eager():
         torch.cuda.synchronize()
         assert torch.equal(eg.beam.ids, ref_i), rep
         assert torch.equal(eg.beam.scores, ref_s), rep
+
+
+# --------------------------------------------- gathered scorer at its full split
+def _sampled_lists_ref(q_ops, q_off, d_ops, d_off, off, ids, rows):
+    """Oracle scores of the listed queries' candidate entries, CSR over `rows`."""
+    so = _csr([int(off[r + 1] - off[r]) for r in rows])
+    si = np.concatenate([ids[off[r]:off[r + 1]] for r in rows])
+    qsel = np.concatenate([np.arange(q_off[r], q_off[r + 1]) for r in rows])
+    qo = _csr([int(q_off[r + 1] - q_off[r]) for r in rows])
+    return oracle.ch_cands(q_ops[qsel], qo, d_ops, d_off, so, si), so, si
+
+
+def test_expand_batch_full_split_matches_oracle():
+    """Beam expansion in its full-size launch shape: 4096 queries x 512 ids a
+    step, so that every wave of the gathered scorer takes 16 entries. 64
+    sampled lists against the oracle, and their beams against its replay."""
+    w = wl.WORKLOADS[4]
+    n_docs, n_q, ef = 4000, 4096, 100
+    c = wl.corpus(w, n_docs=n_docs)
+    q = wl.queries(w, n_queries=n_q)
+    D8 = _device_sets(c, "fp8")
+    Q8 = gem.Sets.from_batch(q, DEV).to_fp8()
+    beam = gem.Beam(n_q, ef, DEV)
+    rows = sorted(set(np.random.default_rng(21).integers(0, n_q, 61).tolist()) | {0, 1, n_q - 1})
+    qo_all = q.offsets.numpy()
+    q_ops = _operands(q.vecs.numpy(), "fp8")
+    d_ops = _operands(c.vecs.numpy(), "fp8")
+    steps = []
+    for st in range(2):
+        off, ids = wl.step_candidates(w, st, n_queries=n_q, n_docs=n_docs)
+        C = gem.Cands(ids.to(DEV), off.to(DEV), max_list_len=w.cands_per_step)
+        assert C.n_lists * C.max_list_len >= 16 * 4096              # the 16-entries-per-wave split
+        cs = torch.empty(ids.numel(), device=DEV)
+        gem.expand_batch(Q8, D8, C, beam, cand_scores=cs)
+        torch.cuda.synchronize()
+        ref, so, si = _sampled_lists_ref(q_ops, qo_all, d_ops, c.offsets.numpy(), off.numpy(), ids.numpy(), rows)
+        got = np.concatenate([_np(cs[int(off[r]):int(off[r + 1])]) for r in rows])
+        assert_close(got, ref, what=f"full-split expansion step {st}")
+        steps.append((ref, so, si))
+    rs, ri = oracle.beam_replay(len(rows), ef, steps)
+    bs, bi = _np(beam.scores)[rows], _np(beam.ids)[rows]
+    assert_close(bs, rs, what="full-split beam scores")
+    for j in range(len(rows)):
+        exact = np.full(n_docs, -np.inf)
+        for (sc_, so_, si_) in steps:
+            seg = slice(so_[j], so_[j + 1])
+            exact[si_[seg]] = sc_[seg]
+        tau = 2 * TOL * max(abs(rs[j][ef - 1]), 1.0)
+        ok, bad, missing = oracle.tie_aware_match(bi[j], exact, ef, tau)
+        assert ok, (rows[j], bad, missing)
+
+
+def test_rerank_f32_full_split_matches_oracle_and_dense():
+    """The float32 rerank in its full-size shape (1000 queries x 1000
+    candidates, 16 entries per wave): sampled lists against the oracle and
+    bitwise against the dense float32 scorer."""
+    w2 = wl.WORKLOADS[2]
+    n_docs, n_q, sl = 6000, 1000, 1000
+    c = wl.corpus(w2, n_docs=n_docs)
+    q = wl.queries(w2, n_queries=n_q)
+    rng = np.random.default_rng(22)
+    ids = np.argsort(rng.random((n_q, n_docs)), axis=1)[:, :sl].astype(np.int32)
+    D, Q = gem.Sets.from_batch(c, DEV), gem.Sets.from_batch(q, DEV)
+    C = gem.Cands(torch.from_numpy(ids.reshape(-1)).to(DEV), stride=sl)
+    assert C.n_lists * C.max_list_len >= 16 * 4096
+    got = _np(gem.score_exact(Q, D, cands=C, compute="f32")).reshape(n_q, sl)
+    dense = _np(gem.score_exact(Q, D, compute="f32"))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(got, np.take_along_axis(dense, ids.astype(np.int64), axis=1))
+    rows = [0, 1, 2, 499, 998, 999] + sorted(rng.integers(3, 998, 10).tolist())
+    off = np.arange(0, (n_q + 1) * sl, sl, dtype=np.int64)
+    ref, _, _ = _sampled_lists_ref(q.vecs.numpy().astype(np.float64), q.offsets.numpy(), c.vecs.numpy(),
+                                   c.offsets.numpy(), off, ids.reshape(-1), rows)
+    assert_close(got[rows].reshape(-1), ref, what="full-split f32 rerank")
+
+
+def test_streamed_fp8_query_full_split():
+    """One FP8 query streamed over 70,000 short documents (range mode, 16
+    documents a wave), written through a row map and row stride: bitwise the
+    dense scorer's row for the same query, and the oracle on sampled documents."""
+    rng = np.random.default_rng(23)
+    n_docs = 70000
+    c = _ragged(list(rng.integers(0, 9, n_docs)), 70)
+    q = _ragged([37, 5, 64, 12], 71)
+    D8 = _device_sets(c, "fp8")
+    Q = gem.Sets.from_batch(q, DEV)
+    ld = n_docs + 13
+    out = torch.full((3, ld), 7.0, device=DEV)
+    rows = torch.tensor([2], dtype=torch.int32, device=DEV)
+    gem.score_quant(Q.view(0, 1), D8, scores=out, ld=ld, rows=rows)
+    dense = _np(gem.score_quant(Q, D8))                                # four queries: the dense scorer
+    torch.cuda.synchronize()
+    o = _np(out)
+    np.testing.assert_array_equal(o[2, :n_docs], dense[0])
+    assert (o[2, n_docs:] == 7.0).all() and (o[:2] == 7.0).all()
+    ds = sorted(set(rng.integers(0, n_docs, 300).tolist()) | {0, 15, 16, 17, n_docs - 1})
+    sq, sd = _sub_host(q, [0]), _sub_host(c, ds)
+    ref = oracle.ch_dense(_operands(sq.vecs.numpy(), "fp8"), sq.offsets.numpy(),
+                          _operands(sd.vecs.numpy(), "fp8"), sd.offsets.numpy())
+    assert_close(o[2, ds][None], ref, what="streamed fp8 full split")
