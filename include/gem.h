@@ -157,6 +157,23 @@ const char* gem_last_error(void);
 /* Library version string. */
 const char* gem_version(void);
 
+/* Context options.
+ *   GEM_OPT_TOPK_FUSION: how an exhaustive scoring call (C == NULL) with k > 0
+ *   and no `scores` buffer finds the per-query top-k.
+ *     GEM_TOPK_AUTO (default): fused into the dense scorer (no score matrix:
+ *       each query keeps, per piece of the corpus, the documents that beat its
+ *       running k-th best, and a merge takes the k best of those) when that
+ *       needs less workspace than staging the [n_q][n_docs] scores, else staged.
+ *     GEM_TOPK_FUSED: always fused (small batches then run the dense scorer
+ *       instead of the streamed path).
+ *     GEM_TOPK_STAGED: always staged, then gem_topk's kernel.
+ *   Every mode returns the same top-k, bitwise. gem_workspace_bytes follows the
+ *   option, so set it before sizing a workspace. */
+typedef enum { GEM_OPT_TOPK_FUSION = 0 } gem_option;
+typedef enum { GEM_TOPK_AUTO = 0, GEM_TOPK_FUSED = 1, GEM_TOPK_STAGED = 2 } gem_topk_mode;
+gem_status gem_set_option(gem_ctx ctx, int32_t option, int64_t value);
+gem_status gem_get_option(gem_ctx ctx, int32_t option, int64_t* value);
+
 /* Workspace bytes that the matching call needs for these arguments (0 if none).
  * For GEM_OP_SCORE_*: `compute` is the gem_dtype the scoring runs in, and
  * `scores_given` says whether the caller passes its own dense/entry score
@@ -239,7 +256,9 @@ gem_status gem_copy_rows(gem_ctx ctx, const void* src, const int64_t* src_idx, v
  *   C != NULL: scores[e] = CH(Q_i, D_ids[e]) for each entry e of list i (the
  *     exact rerank of a shortlist, Alg. 5 final step).
  *   k > 0: per-query top-k of those scores into top_scores / top_ids [n_q][k]
- *     (ids are document indices of D). `scores` may then be NULL (staged in ws).
+ *     (ids are document indices of D). `scores` may then be NULL: with C == NULL
+ *     the top-k is fused into the scorer or the scores are staged in ws
+ *     (GEM_OPT_TOPK_FUSION); with C != NULL the entry scores are staged.
  *   k == 0: scores only.
  *   Limits: Q->max_set_len <= GEM_MAX_QUERY_LEN, k <= GEM_MAX_K.
  */

@@ -25,7 +25,7 @@ __all__ = ["Sets", "Cands", "Beam", "GemError", "convert_bf16", "quantize_fp8", 
            "library", "GEM_F32", "GEM_BF16", "GEM_FP8_E4M3", "GEM_MXFP4", "quantize_mxfp4", "GEM_MAX_K", "GEM_MAX_QUERY_LEN", "dense_schedule",
            "set_dense_schedule", "autotune_dense", "copy_rows", "nearest_centroid", "centroid_update",
            "kmeans", "encode", "codebook_size",
-           "emd_sinkhorn"]
+           "emd_sinkhorn", "set_topk_fusion", "topk_fusion", "score_workspace_bytes"]
 
 _DTYPES = {"f32": GEM_F32, "bf16": GEM_BF16, "fp8": GEM_FP8_E4M3, "mxfp4": GEM_MXFP4,
            GEM_F32: GEM_F32, GEM_BF16: GEM_BF16, GEM_FP8_E4M3: GEM_FP8_E4M3, GEM_MXFP4: GEM_MXFP4}
@@ -251,6 +251,34 @@ def _score(fn_exact: bool, Q: Sets, D: Sets, cands: Optional[Cands], k: int, com
     if k == 0:
         return scores
     return (top_s, top_i, scores) if want_scores else (top_s, top_i)
+
+
+_TOPK_MODES = {"auto": _abi.GEM_TOPK_AUTO, "fused": _abi.GEM_TOPK_FUSED, "staged": _abi.GEM_TOPK_STAGED}
+
+
+def set_topk_fusion(mode: str, device="cuda") -> None:
+    """How exhaustive calls with k > 0 and no score buffer find the top-k:
+    "auto" (fused into the scorer when that needs less workspace than staging
+    the score rows), "fused" or "staged". Every mode gives the same result."""
+    _abi.check(library().gem_set_option(_ctx(torch.device(device)), _abi.GEM_OPT_TOPK_FUSION, _TOPK_MODES[mode]))
+
+
+def topk_fusion(device="cuda") -> str:
+    v = ctypes.c_int64(0)
+    _abi.check(library().gem_get_option(_ctx(torch.device(device)), _abi.GEM_OPT_TOPK_FUSION, ctypes.byref(v)))
+    return {b: a for a, b in _TOPK_MODES.items()}[int(v.value)]
+
+
+def score_workspace_bytes(Q: Sets, D: Sets, cands: Optional[Cands] = None, k: int = 0, compute=None,
+                          scores_given: bool = False) -> int:
+    """Workspace bytes of a scoring call with these arguments (gem_workspace_bytes)."""
+    compute = D.dtype if compute is None else _DTYPES[compute]
+    qs, ds = Q.struct(), D.struct()
+    cs = cands.struct() if cands is not None else None
+    op = _abi.GEM_OP_SCORE_QUANT if compute in _QUANT else _abi.GEM_OP_SCORE_EXACT
+    return int(library().gem_workspace_bytes(_ctx(D.device), op, ctypes.byref(qs), ctypes.byref(ds),
+                                             ctypes.byref(cs) if cs is not None else None, compute, int(k),
+                                             int(scores_given)))
 
 
 def score_exact(Q: Sets, D: Sets, cands: Optional[Cands] = None, k: int = 0, compute="f32",

@@ -23,6 +23,7 @@ struct gem_ctx_s {
   // keyed by (dtype, shape class)
   std::mutex mu;
   std::map<uint64_t, gem::DenseSchedule> dense;
+  int32_t topk_mode = GEM_TOPK_AUTO;     // GEM_OPT_TOPK_FUSION
 };
 
 namespace {
@@ -121,15 +122,31 @@ CandsView cview(const gem_cands* C) {
   return v;
 }
 
+// Query batches up to this size take the streamed (gathered) path of a dense
+// call: at most this many passes over the corpus, each at memory speed. FP8
+// batches of two or more queries do better on the dense scorer's narrow-block
+// variant (two workgroups per CU), other formats only from four queries on.
+constexpr int64_t kRangeMaxQueries = 3;
+constexpr int64_t kRangeMaxQueriesFp8 = 1;
+
+bool range_call(const gem_sets* Q, int32_t compute) {
+  return Q->n_sets <= (compute == GEM_FP8_E4M3 ? kRangeMaxQueriesFp8 : kRangeMaxQueries);
+}
+
 // Workspace layout of a scoring call.
 struct ScoreLayout {
   size_t q_conv = 0, q_scales = 0, qb = 0, qcol = 0, staged = 0, total = 0;
   int64_t n_blocks_max = 0;
   int block_rows = 0;
+  // fused top-k of a dense call (k > 0 without a score matrix): regions,
+  // their entry counts and the per-query bounds
+  bool fused = false;
+  int32_t tk_np = 0, tk_cap = 0;
+  size_t tk_keys = 0, tk_cnt = 0, tk_gthr = 0;
 };
 
 ScoreLayout score_layout(const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t compute, int32_t k,
-                         bool scores_given) {
+                         bool scores_given, int slots_per_xcd, int32_t topk_mode = GEM_TOPK_AUTO) {
   ScoreLayout L;
   size_t off = 0;
   if (Q->dtype != compute) {
@@ -148,8 +165,29 @@ ScoreLayout score_layout(const gem_sets* Q, const gem_sets* D, const gem_cands* 
     L.qcol = off;
     off = align_up(off + (size_t)(Q->n_sets + 1) * 8);
     if (k > 0 && !scores_given) {
-      L.staged = off;
-      off = align_up(off + (size_t)Q->n_sets * (size_t)D->n_sets * 4);
+      // the top-k fused into the dense scorer, unless staging the score rows
+      // takes less memory (small batches; the streamed path always stages)
+      const size_t staged = (size_t)Q->n_sets * (size_t)D->n_sets * 4;
+      if (topk_mode != GEM_TOPK_STAGED && D->n_sets > 0 && (topk_mode == GEM_TOPK_FUSED || !range_call(Q, compute))) {
+        const bool narrow = compute == GEM_FP8_E4M3 && L.block_rows <= 64 && !D->codes;
+        const int64_t bg_min = std::max<int64_t>(1, (Q->n_vecs + 8LL * L.block_rows - 1) / (8LL * L.block_rows));
+        topk_fuse_shape(k, D->n_sets, bg_min, (narrow ? 2 : 1) * slots_per_xcd, &L.tk_np, &L.tk_cap);
+        const size_t regions = (size_t)Q->n_sets * 8 * (size_t)L.tk_np;
+        const size_t fused = regions * (size_t)L.tk_cap * 8 + regions * 4 + (size_t)Q->n_sets * 8 + 3 * 256;
+        L.fused = topk_mode == GEM_TOPK_FUSED || fused < staged;
+      }
+      if (L.fused) {
+        const size_t regions = (size_t)Q->n_sets * 8 * (size_t)L.tk_np;
+        L.tk_keys = off;
+        off = align_up(off + regions * (size_t)L.tk_cap * 8);
+        L.tk_cnt = off;
+        off = align_up(off + regions * 4);
+        L.tk_gthr = off;
+        off = align_up(off + (size_t)Q->n_sets * 8);
+      } else {
+        L.staged = off;
+        off = align_up(off + staged);
+      }
     }
   } else if (k > 0 && !scores_given) {
     L.staged = off;
@@ -209,13 +247,6 @@ DenseSchedule lookup_dense(gem_ctx ctx, int32_t dtype, int64_t q_rows, int64_t n
   return default_dense_schedule(dtype, q_rows, n_docs, ctx->n_cu / 8);
 }
 
-// Query batches up to this size take the streamed (gathered) path of a dense
-// call: at most this many passes over the corpus, each at memory speed. FP8
-// batches of two or more queries do better on the dense scorer's narrow-block
-// variant (two workgroups per CU), other formats only from four queries on.
-constexpr int64_t kRangeMaxQueries = 3;
-constexpr int64_t kRangeMaxQueriesFp8 = 1;
-
 gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t compute,
                         int32_t k, float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,
                         int32_t* top_ids, void* ws, size_t ws_bytes, hipStream_t stream,
@@ -235,7 +266,7 @@ gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const
     if (ld_scores < D->n_sets) return fail(GEM_ERR_INVALID, "ld_scores %lld < number of documents",
                                            (long long)ld_scores);
   }
-  const ScoreLayout L = score_layout(Q, D, C, compute, k, scores != nullptr);
+  const ScoreLayout L = score_layout(Q, D, C, compute, k, scores != nullptr, ctx->n_cu / 8, ctx->topk_mode);
   if (ws_bytes < L.total) return fail(GEM_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.total);
   if (L.total > 0 && !ws) return fail(GEM_ERR_INVALID, "workspace is NULL");
   if (Q->n_sets == 0) return GEM_OK;
@@ -251,11 +282,23 @@ gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const
       }
       return GEM_OK;
     }
-    DenseOut out;
-    out.scores = scores ? scores : reinterpret_cast<float*>(at(ws, L.staged));
-    out.ld = scores ? ld_scores : D->n_sets;
-    out.rows = scores ? score_rows : nullptr;
-    if (Q->n_sets <= (compute == GEM_FP8_E4M3 ? kRangeMaxQueriesFp8 : kRangeMaxQueries) && !sched) {
+    DenseOut out{};
+    if (L.fused) {
+      // top-k fused into the scorer: cleared region counts and bounds
+      const int64_t regions = Q->n_sets * 8 * (int64_t)L.tk_np;
+      out.tk.k = k; out.tk.cap = L.tk_cap; out.tk.np = L.tk_np;
+      out.tk.keys = reinterpret_cast<uint64_t*>(at(ws, L.tk_keys));
+      out.tk.cnt = reinterpret_cast<int32_t*>(at(ws, L.tk_cnt));
+      out.tk.gthr = reinterpret_cast<unsigned long long*>(at(ws, L.tk_gthr));
+      e = launch_fill_u32(reinterpret_cast<uint32_t*>(out.tk.cnt), regions, 0u, stream);
+      if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t*>(out.tk.gthr), 2 * Q->n_sets, 0u, stream);
+      if (e != hipSuccess) return hip_fail(e, "top-k regions");
+    } else {
+      out.scores = scores ? scores : reinterpret_cast<float*>(at(ws, L.staged));
+      out.ld = scores ? ld_scores : D->n_sets;
+      out.rows = scores ? score_rows : nullptr;
+    }
+    if (range_call(Q, compute) && !sched && !L.fused) {
       // a few queries: every document streamed by the gathered scorer (the
       // same scores; the dense scorer would run one lightly loaded block group)
       e = launch_score_range(compute, view(&Qc), view(D), out, stream);
@@ -270,7 +313,11 @@ gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const
       e = launch_score_dense(compute, view(&Qc), view(D), qb, qcol, L.n_blocks_max, out, ds, L.block_rows, stream);
       if (e != hipSuccess) return hip_fail(e, "dense scoring");
     }
-    if (k > 0) {
+    if (L.fused) {
+      e = launch_topk_regions(out.tk.keys, out.tk.cnt, Q->n_sets, 8 * L.tk_np, L.tk_cap, k, top_scores, top_ids,
+                              stream);
+      if (e != hipSuccess) return hip_fail(e, "top-k merge");
+    } else if (k > 0) {
       TopkSegs S;
       S.scores = out.scores; S.off = nullptr; S.ids = nullptr; S.rows = out.rows;
       S.n_segs = Q->n_sets; S.len = D->n_sets; S.ld = out.ld;
@@ -393,23 +440,44 @@ const char* gem_status_string(gem_status s) {
 
 const char* gem_last_error(void) { return g_last_error.c_str(); }
 
-const char* gem_version(void) { return "gem-mi355x 0.1 (gfx950)"; }
+const char* gem_version(void) { return "gem-mi355x 0.2 (gfx950)"; }
+
+gem_status gem_set_option(gem_ctx ctx, int32_t option, int64_t value) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  switch (option) {
+    case GEM_OPT_TOPK_FUSION:
+      if (value != GEM_TOPK_AUTO && value != GEM_TOPK_FUSED && value != GEM_TOPK_STAGED)
+        return fail(GEM_ERR_INVALID, "top-k fusion mode %lld", (long long)value);
+      ctx->topk_mode = (int32_t)value;
+      return GEM_OK;
+    default:
+      return fail(GEM_ERR_INVALID, "unknown option %d", option);
+  }
+}
+
+gem_status gem_get_option(gem_ctx ctx, int32_t option, int64_t* value) {
+  if (!ctx || !value) return fail(GEM_ERR_INVALID, "NULL argument");
+  switch (option) {
+    case GEM_OPT_TOPK_FUSION: *value = ctx->topk_mode; return GEM_OK;
+    default: return fail(GEM_ERR_INVALID, "unknown option %d", option);
+  }
+}
 
 size_t gem_workspace_bytes(gem_ctx ctx, int32_t op, const gem_sets* Q, const gem_sets* D, const gem_cands* C,
                            int32_t compute, int32_t k, int32_t scores_given) {
-  (void)ctx;
-  if (!Q) return 0;
+  if (!Q || !ctx) return 0;
   switch (op) {
     case GEM_OP_SCORE_EXACT:
     case GEM_OP_SCORE_QUANT: {
       if (!D) return 0;
       const int32_t cd = op == GEM_OP_SCORE_QUANT ? (D->dtype == GEM_MXFP4 ? (int32_t)GEM_MXFP4 : (int32_t)GEM_FP8_E4M3)
                                                   : compute;
-      return score_layout(Q, D, C, cd, k, scores_given != 0).total;
+      return score_layout(Q, D, C, cd, k, scores_given != 0, ctx->n_cu / 8, ctx->topk_mode).total;
     }
     case GEM_OP_EXPAND: {
       if (!D || !C) return 0;
-      return score_layout(Q, D, C, D->dtype == GEM_MXFP4 ? GEM_MXFP4 : GEM_FP8_E4M3, 1, scores_given != 0).total;
+      return score_layout(Q, D, C, D->dtype == GEM_MXFP4 ? GEM_MXFP4 : GEM_FP8_E4M3, 1, scores_given != 0,
+                          ctx->n_cu / 8).total;
     }
     default:
       return 0;
@@ -563,7 +631,7 @@ gem_status gem_expand_batch(gem_ctx ctx, const gem_sets* Q8, const gem_sets* D8,
   if (Q8->n_sets > 0 && (!beam->scores || !beam->ids)) return fail(GEM_ERR_INVALID, "beam buffers are NULL");
   if ((int64_t)beam->ef + list_len_bound(C) > kBeamMaxEntries)
     return fail(GEM_ERR_UNSUPPORTED, "ef + longest list = %d exceeds %d", beam->ef + list_len_bound(C), kBeamMaxEntries);
-  const ScoreLayout L = score_layout(Q8, D8, C, cd, 1, cand_scores != nullptr);
+  const ScoreLayout L = score_layout(Q8, D8, C, cd, 1, cand_scores != nullptr, ctx->n_cu / 8);
   if (ws_bytes < L.total) return fail(GEM_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.total);
   if (L.total > 0 && !ws) return fail(GEM_ERR_INVALID, "workspace is NULL");
   if (Q8->n_sets == 0) return GEM_OK;

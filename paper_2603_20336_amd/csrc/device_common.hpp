@@ -71,6 +71,17 @@ __device__ __forceinline__ float float_from_order_key(uint32_t k) {
 // ----------------------------------------------------------------- wave helpers
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// 64-bit values of one lane (both halves read as unsigned: the builtins return
+// int, which would sign-extend into the high half)
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int lane) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(v >> 32), lane) << 32) |
+         (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)v, lane);
+}
+__device__ __forceinline__ uint64_t readfirstlane_u64(uint64_t v) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+         (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+
 __device__ __forceinline__ float wave_max(float v) {
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
   return v;

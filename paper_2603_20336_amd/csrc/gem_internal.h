@@ -49,11 +49,38 @@ int64_t dense_blocks_upper(int64_t n_q, int64_t n_rows, int block_rows, int max_
 hipError_t launch_plan_query_blocks(const int64_t* q_off, int64_t n_q, int block_rows, int max_len,
                                     int32_t* qb_start, int64_t* qcol, int64_t n_blocks_max, hipStream_t s);
 
+// Fused per-query top-k of the dense scorer (the k-argmax of Sec. 3.1 without a
+// score matrix). Query q's documents are split into 8 * np pieces (np per
+// XCD); the wave that scores piece p of query q keeps, in region (q, p) of
+// `keys`, every document whose rank key beats the query's running threshold,
+// and when the region is full it selects the region's k best, keeps them and
+// raises the threshold to the k-th (also the shared bound gthr[q]). A merge
+// then takes the k best of the regions: exactly the top-k of the whole row.
+struct TopkFuse {
+  int32_t k;                  // 0: the scores are stored instead
+  int32_t cap;                // entries per region: >= k + 64, or >= the piece's documents
+  int32_t np;                 // pieces per XCD
+  uint64_t* keys;             // [n_q][8 np][cap] rank keys (score bits above the complemented id)
+  int32_t* cnt;               // [n_q][8 np] entries per region (zero before the launch)
+  unsigned long long* gthr;   // [n_q] a lower bound of the query's k-th key (zero before the launch)
+};
+
 struct DenseOut {
   float* scores;          // score (i, j) at scores[row(i) * ld + j]
   int64_t ld;
   const int32_t* rows;    // nullable
+  TopkFuse tk;            // tk.k > 0: no scores are stored, the regions are filled instead
 };
+
+// Regions per XCD and entries per region of a fused top-k over n_docs documents
+// for a batch whose block groups are at least n_bg_min, on a grid of
+// `slots_per_xcd` workgroups per XCD (so that every workgroup gets an item).
+void topk_fuse_shape(int32_t k, int64_t n_docs, int64_t n_bg_min, int slots_per_xcd, int32_t* np, int32_t* cap);
+// The k best keys of each query's regions -> [n_q][k] scores and ids (padding
+// (-inf, -1)), the same as gem_topk on the query's whole score row.
+hipError_t launch_topk_regions(const uint64_t* keys, const int32_t* cnt, int64_t n_q, int32_t regions, int32_t cap,
+                               int32_t k, float* top_scores, int32_t* top_ids, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 
 // Schedule of the persistent dense scorer (never changes a result).
 struct DenseSchedule {

@@ -382,6 +382,145 @@ __device__ __forceinline__ float readlane_f(float v, int lane) {
   return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), lane));
 }
 
+// --------------------------------------------------------------------------
+// Fused top-k: one wave's region of candidate keys for one query and piece.
+// A key holds the score's order-preserving bits above the complemented
+// document id, so a larger key is a higher score or, on equal scores, a
+// smaller id; the keys of one query's documents are distinct.
+__device__ __forceinline__ uint64_t tk_rank_key(float s, int32_t id) {
+  return ((uint64_t)float_order_key(s) << 32) | (uint64_t)(~(uint32_t)id);
+}
+
+// Region reads take the entries other lanes of the wave stored: they wait for
+// those stores and read past the vector L1.
+__device__ __forceinline__ uint64_t tk_load(uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum over the wave of v (every lane receives it).
+__device__ __forceinline__ uint32_t tk_wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Histogram add from the whole wave: one LDS atomic per lane group that hits
+// the same bin as the first active lane when all active lanes agree.
+__device__ __forceinline__ void tk_hist_add(uint32_t* hist, bool active, uint32_t bin) {
+  const uint64_t act = __ballot(active);
+  if (act == 0) return;
+  const uint32_t first = __builtin_amdgcn_readfirstlane(active ? bin : 0xffffffffu);
+  const uint64_t same = __ballot(active && bin == first);
+  if (same == act) {
+    if (lane_id() == __ffsll((unsigned long long)act) - 1) atomicAdd(&hist[first], (uint32_t)__popcll(act));
+  } else if (active) {
+    atomicAdd(&hist[bin], 1u);
+  }
+}
+
+// Keys a region holds at most (k <= 1024 plus 1024 free slots).
+constexpr int kTkMaxCap = 2048;
+// Keys a lane reads per batch in a selection (loads in flight).
+constexpr int kTkBatch = 8;
+
+// The k best of the n (k < n <= kTkMaxCap) distinct keys R[0..n) move to
+// R[0..k); returns the k-th best. Radix select over the wave, eight bits a
+// round from the top, with a 256-bin histogram in `hist` (this wave's own
+// LDS); each round reads the keys in batches of kTkBatch per lane, and the
+// select stops early once the selected bin holds exactly the keys still
+// needed (the threshold is then the least key kept). It runs rarely (when a
+// region is full) and out of line, so that its registers stay out of the
+// scorer's. Wave-uniform arguments; all lanes call it.
+__device__ __attribute__((noinline)) uint64_t tk_select_k(uint64_t* R, int n, int k, uint32_t* hist) {
+  const int l = lane_id();
+  __builtin_amdgcn_s_waitcnt(0);                        // this wave's stores into R are done
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  uint64_t prefix = 0, mask = 0;
+  uint32_t need = (uint32_t)k;
+  bool whole_bin = false;                               // keep every key of the selected bin
+  for (int shift = 56; shift >= 0; shift -= 8) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) hist[4 * l + b] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int i0 = 0; i0 < n; i0 += 64 * kTkBatch) {
+      uint64_t kv[kTkBatch];
+#pragma unroll
+      for (int u = 0; u < kTkBatch; ++u) {
+        const int i = i0 + 64 * u + l;
+        kv[u] = i < n ? tk_load(R + i) : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < kTkBatch; ++u) {
+        const int i = i0 + 64 * u + l;
+        tk_hist_add(hist, i < n && (kv[u] & mask) == prefix, (uint32_t)(kv[u] >> shift) & 0xffu);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // lane l holds bins 4l..4l+3; `above` counts the keys in higher bins
+    const uint32_t h0 = hist[4 * l], h1 = hist[4 * l + 1], h2 = hist[4 * l + 2], h3 = hist[4 * l + 3];
+    const uint32_t own = h0 + h1 + h2 + h3;
+    uint32_t incl = own;                                // sum over lanes >= l
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t v = __shfl_down(incl, o);
+      if (l + o < 64) incl += v;
+    }
+    uint32_t gt = incl - own;
+    int digit = -1;
+    uint32_t gt_sel = 0, h_sel = 0;
+    const uint32_t hb[4] = {h0, h1, h2, h3};
+#pragma unroll
+    for (int b = 3; b >= 0; --b) {
+      if (digit < 0 && gt < need && need <= gt + hb[b]) { digit = 4 * l + b; gt_sel = gt; h_sel = hb[b]; }
+      gt += hb[b];
+    }
+    const uint64_t who = __ballot(digit >= 0);
+    const int src = __ffsll((unsigned long long)who) - 1;
+    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane(digit, src);
+    const uint32_t g_above = (uint32_t)__builtin_amdgcn_readlane(gt_sel, src);
+    const uint32_t in_bin = (uint32_t)__builtin_amdgcn_readlane(h_sel, src);
+    need -= g_above;
+    prefix |= (uint64_t)d << shift;
+    mask |= 0xffull << shift;
+    if (in_bin == need) { whole_bin = true; break; }
+  }
+  // keep the keys above the selected bin and (all of, or the one key of) it,
+  // in their order; every key kept moves left, so a batch's stores only hit
+  // entries this batch or earlier ones read
+  uint64_t kmin = ~0ull;
+  int pos = 0;
+  for (int i0 = 0; i0 < n; i0 += 64 * kTkBatch) {
+    uint64_t kv[kTkBatch];
+#pragma unroll
+    for (int u = 0; u < kTkBatch; ++u) {
+      const int i = i0 + 64 * u + l;
+      kv[u] = i < n ? tk_load(R + i) : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < kTkBatch; ++u) {
+      const int i = i0 + 64 * u + l;
+      const uint64_t key = kv[u];
+      const bool keep = i < n && ((key & mask) > prefix || (whole_bin ? (key & mask) == prefix : key == prefix));
+      const uint64_t b = __ballot(keep);
+      if (keep) {
+        R[pos + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u))] = key;
+        kmin = key < kmin ? key : kmin;
+      }
+      pos += __popcll(b);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t v = __shfl_xor(kmin, o);
+    kmin = v < kmin ? v : kmin;
+  }
+  return kmin;
+}
+
 // State of one wave over one pass of the dense scorer.
 template <int DT, int NTO = 0> struct DensePass {
   using O = Op<DT>;
@@ -439,7 +578,9 @@ template <int DT, int NTO = 0> struct DensePass {
 // slots of one of three LDS code arrays (one per group buffer) two groups
 // ahead, with the copies of the group two before, so that a copy never waits
 // on a dependent load and the wait counts stay static.
-template <int DT, bool kCodes, int NTO>
+// kTopk: the fused top-k (P.out.tk) takes the finished scores instead of the
+// score matrix.
+template <int DT, bool kCodes, int NTO, bool kTopk>
 __device__ __forceinline__ void dense_body(const DenseParams& P) {
   using O = Op<DT>;
   using Frag = typename O::Frag;
@@ -459,6 +600,8 @@ __device__ __forceinline__ void dense_body(const DenseParams& P) {
   __shared__ u32x4 lds_buf2[TS::kGroupVecs];
   __shared__ int lds_npass[kDenseWaves];
   __shared__ float lds_tsum[kDenseWaves][NT * 64];              // parked tile sums, per wave
+  // fused top-k: the wave's selection histogram
+  __shared__ uint32_t lds_tk_hist[kTopk ? kDenseWaves * 256 : 1];
 
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, g = l >> 4, c16 = l & 15;
@@ -484,11 +627,17 @@ __device__ __forceinline__ void dense_body(const DenseParams& P) {
   const int64_t even = n_slots / ga;                           // piece counts that divide evenly: multiples of this
   int64_t np = ((int64_t)P.items_per_slot * n_slots + n_bg - 1) / n_bg;
   np = min(((np + even - 1) / even) * even, C);
+  if constexpr (kTopk) np = min((int64_t)P.out.tk.np, C);       // the caller's pieces (its regions)
   const int64_t n_items = np * n_bg;
+  const int64_t tk_regions = kTopk ? 8 * (int64_t)P.out.tk.np : 0;
 
   DensePass<DT, NT> S;
   S.tsum = lds_tsum[w];
   int64_t cur_bg = -1;
+  // fused top-k: lane j holds query j's running threshold and its region's
+  // entry count (query j of the wave's current block)
+  uint64_t tk_thr = 0;
+  int tk_cnt = 0;
   int q0 = 0, nq = 0, n_pass = 0, total_tiles = 0;
   int64_t qrow = 0;
   int qm = 0, qt0 = 0, qnt = 0;
@@ -528,6 +677,12 @@ __device__ __forceinline__ void dense_body(const DenseParams& P) {
     const int64_t pidx = it / n_bg;
     const int64_t pc0 = c_lo + (pidx * C) / np;
     const int64_t pc1 = c_lo + ((pidx + 1) * C) / np;
+    const int64_t tk_piece = xcd * (int64_t)(kTopk ? P.out.tk.np : 0) + pidx;
+    if constexpr (kTopk) {
+      // this piece's regions start empty, behind the query's shared bound
+      tk_thr = l < nq ? tk_load(reinterpret_cast<uint64_t*>(P.out.tk.gthr + q0 + l)) : 0ull;
+      tk_cnt = 0;
+    }
     for (int64_t chunk = pc0; chunk < pc1; ++chunk) {
       const int64_t p0 = chunk * P.chunk_docs;
       const int64_t p1 = min(P.D.n_sets, p0 + P.chunk_docs);
@@ -612,6 +767,37 @@ __device__ __forceinline__ void dense_body(const DenseParams& P) {
         }
       };
 
+      // fused top-k: lane l's score (document p0 + l) for query j of the
+      // block joins the query's region if its key beats the threshold; a full
+      // region keeps its k best first and raises the threshold to the k-th
+      auto tk_append = [&](int j, float sc) {
+        uint64_t thr = readlane_u64(tk_thr, j);
+        int cnt = __builtin_amdgcn_readlane(tk_cnt, j);
+        const uint64_t key = tk_rank_key(sc, (int32_t)(p0 + l));
+        bool v = l < nd && key > thr;
+        uint64_t b = __ballot(v);
+        if (b == 0) return;
+        int nb = __popcll(b);
+        const int cap = P.out.tk.cap;
+        uint64_t* R = P.out.tk.keys + ((int64_t)(q0 + j) * tk_regions + tk_piece) * cap;
+        if (cnt + nb > cap && cnt > P.out.tk.k) {
+          const uint64_t kth = tk_select_k(R, cnt, P.out.tk.k, lds_tk_hist + w * 256);
+          unsigned long long old = 0;
+          if (l == 0) old = atomicMax(P.out.tk.gthr + q0 + j, (unsigned long long)kth);
+          old = readfirstlane_u64(old);
+          thr = kth > old ? kth : (uint64_t)old;
+          tk_thr = l == j ? thr : tk_thr;
+          cnt = P.out.tk.k;
+          v = v && key > thr;
+          b = __ballot(v);
+          nb = __popcll(b);
+        }
+        const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+        if (v && pos < cap) R[pos] = key;                       // (cap bounds every piece by construction)
+        cnt = min(cnt + nb, cap);
+        tk_cnt = l == j ? cnt : tk_cnt;
+      };
+
       float part = 0.0f;                                        // lane dd: partial score carried to the next pass
       for (int pass = 0; pass < n_pass; ++pass) {
         if (!(b_loaded && n_pass == 1)) {
@@ -632,8 +818,7 @@ __device__ __forceinline__ void dense_body(const DenseParams& P) {
               const int j = __ffsll((unsigned long long)own) - 1;
               const int jt0 = __builtin_amdgcn_readlane(qt0, j);
               const int jm = __builtin_amdgcn_readlane(qm, j);
-              const int64_t jrow = (int64_t)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(qrow >> 32), j) << 32) |
-                                             __builtin_amdgcn_readlane((uint32_t)qrow, j));
+              const int64_t jrow = (int64_t)readlane_u64((uint64_t)qrow, j);
               const int k = t - jt0;                            // tile index inside query j
               if (l == ct) S.tq_lane = j;
               if (k == 0) S.first_mask |= 1ull << ct;
@@ -702,27 +887,53 @@ __device__ __forceinline__ void dense_body(const DenseParams& P) {
         // queries store one row of the chunk's documents each (empty
         // documents score -inf)
         float s_run = part;
+        uint64_t fin = 0;                                       // fused top-k: column tiles whose query has news
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct) {
           if (ct < S.nct) {
             const float tv = S.tsum[ct * 64 + l];
             s_run = ((S.first_mask >> ct) & 1) ? tv : s_run + tv;
             if ((S.last_mask >> ct) & 1) {
-              const int j = __builtin_amdgcn_readlane(S.tq_lane, ct);
-              const int64_t row = P.out.rows ? (int64_t)P.out.rows[q0 + j] : (int64_t)(q0 + j);
-              if (l < nd) P.out.scores[row * P.out.ld + p0 + l] = doc_empty ? ninf : s_run;
+              if constexpr (kTopk) {
+                // a query with a document that beats its threshold joins its
+                // region below (the score waits in the parked-sum slot, read above)
+                const int j = __builtin_amdgcn_readlane(S.tq_lane, ct);
+                const float sc = doc_empty ? ninf : s_run;
+                if (__ballot(l < nd && tk_rank_key(sc, (int32_t)(p0 + l)) > readlane_u64(tk_thr, j))) {
+                  S.tsum[ct * 64 + l] = sc;
+                  fin |= 1ull << ct;
+                }
+              } else {
+                const int j = __builtin_amdgcn_readlane(S.tq_lane, ct);
+                const int64_t row = P.out.rows ? (int64_t)P.out.rows[q0 + j] : (int64_t)(q0 + j);
+                if (l < nd) P.out.scores[row * P.out.ld + p0 + l] = doc_empty ? ninf : s_run;
+              }
             }
+          }
+        }
+        if constexpr (kTopk) {
+          // those queries join their regions, one at a time
+          while (fin) {
+            const int ct = __builtin_ctzll(fin);
+            fin &= fin - 1;
+            tk_append(__builtin_amdgcn_readlane(S.tq_lane, ct), S.tsum[ct * 64 + l]);
           }
         }
         part = s_run;
       }
       // empty queries score 0 against every document
       for (int j = 0; j < nq; ++j) {
-        if (__builtin_amdgcn_readlane(qm, j) == 0 && l < nd) {
+        if constexpr (kTopk) {
+          if (__builtin_amdgcn_readlane(qm, j) == 0) tk_append(j, 0.0f);
+        } else if (__builtin_amdgcn_readlane(qm, j) == 0 && l < nd) {
           const int64_t row = P.out.rows ? (int64_t)P.out.rows[q0 + j] : (int64_t)(q0 + j);
           P.out.scores[row * P.out.ld + p0 + l] = 0.0f;
         }
       }
+    }
+    if constexpr (kTopk) {
+      // the piece's entry counts, for the merge
+      if (l < nq) P.out.tk.cnt[(int64_t)(q0 + l) * tk_regions + tk_piece] = tk_cnt;
     }
   }
 }
@@ -731,13 +942,13 @@ __device__ __forceinline__ void dense_body(const DenseParams& P) {
 // (small batches): four column tiles a wave, a quarter of the parked-sum LDS
 // and of the query registers, compiled for four waves per SIMD (two resident
 // workgroups per CU).
-template <int DT, bool kCodes>
+template <int DT, bool kCodes, bool kTopk>
 __global__ __launch_bounds__(kDenseThreads) void score_dense_kernel(DenseParams P) {
-  dense_body<DT, kCodes, 0>(P);
+  dense_body<DT, kCodes, 0, kTopk>(P);
 }
-template <int DT>
+template <int DT, bool kTopk>
 __global__ __launch_bounds__(kDenseThreads, 4) void score_dense_narrow_kernel(DenseParams P) {
-  dense_body<DT, false, 4>(P);
+  dense_body<DT, false, 4, kTopk>(P);
 }
 
 DenseSchedule default_dense_schedule(int dtype, int64_t q_rows, int64_t n_docs, int cus_per_xcd) {
@@ -749,9 +960,55 @@ DenseSchedule default_dense_schedule(int dtype, int64_t q_rows, int64_t n_docs, 
   return d;
 }
 
+void topk_fuse_shape(int32_t k, int64_t n_docs, int64_t n_bg_min, int slots_per_xcd, int32_t* np_out,
+                     int32_t* cap_out) {
+  // enough pieces per XCD that every workgroup of the XCD gets an item
+  const int64_t bg = std::max<int64_t>(1, n_bg_min);
+  const int64_t np = std::min<int64_t>(64, std::max<int64_t>(1, (slots_per_xcd + bg - 1) / bg));
+  // a region holds the k best of its piece plus room for new entries (a
+  // selection frees at least 1024 slots, or k when k is larger), unless the
+  // piece's documents fit in less: then no selection ever runs
+  const int64_t kr = (k + 63) & ~(int64_t)63;
+  const int64_t cap_k = kr + std::max<int64_t>(1024, kr);
+  int64_t piece_docs = 0;
+  for (int64_t cd : {(int64_t)32, (int64_t)kMaxChunkDocs}) {
+    const int64_t chunks_xcd = ((n_docs + cd - 1) / cd + 7) / 8;
+    piece_docs = std::max(piece_docs, ((chunks_xcd + np - 1) / np) * cd);
+  }
+  const int64_t cap_p = std::max<int64_t>(64, (piece_docs + 63) & ~(int64_t)63);
+  *np_out = (int32_t)np;
+  *cap_out = (int32_t)std::min(cap_k, cap_p);
+}
+
 bool dense_schedule_valid(const DenseSchedule& d, int cus_per_xcd) {
   return (d.chunk_docs == 32 || d.chunk_docs == 64) && d.items_per_slot >= 1 && d.items_per_slot <= 64 &&
          d.slots_per_xcd >= 1 && d.slots_per_xcd <= cus_per_xcd;
+}
+
+template <bool kTopk>
+static void launch_dense_variant(int dtype, bool codes, int32_t block_rows, dim3 grid, dim3 blk, const DenseParams& P,
+                                 hipStream_t s) {
+  switch (dtype) {
+    case GEM_F32:
+      if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_F32, true, kTopk>), grid, blk, 0, s, P);
+      else hipLaunchKernelGGL((score_dense_kernel<GEM_F32, false, kTopk>), grid, blk, 0, s, P);
+      break;
+    case GEM_BF16:
+      if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_BF16, true, kTopk>), grid, blk, 0, s, P);
+      else hipLaunchKernelGGL((score_dense_kernel<GEM_BF16, false, kTopk>), grid, blk, 0, s, P);
+      break;
+    case GEM_FP8_E4M3:
+      if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_FP8_E4M3, true, kTopk>), grid, blk, 0, s, P);
+      else if (block_rows <= 64)                             // two workgroups per CU
+        hipLaunchKernelGGL((score_dense_narrow_kernel<GEM_FP8_E4M3, kTopk>), dim3(2 * grid.x), blk, 0, s, P);
+      else hipLaunchKernelGGL((score_dense_kernel<GEM_FP8_E4M3, false, kTopk>), grid, blk, 0, s, P);
+      break;
+    case GEM_MXFP4:
+      if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_MXFP4, true, kTopk>), grid, blk, 0, s, P);
+      else hipLaunchKernelGGL((score_dense_kernel<GEM_MXFP4, false, kTopk>), grid, blk, 0, s, P);
+      break;
+    default: break;
+  }
 }
 
 hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, const int32_t* qb_start,
@@ -768,28 +1025,16 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
   if (P.n_bgroups == 0 || P.n_chunks == 0) return hipSuccess;
   if (sched.chunk_docs < 1 || sched.chunk_docs > kMaxChunkDocs || sched.items_per_slot < 1 || sched.slots_per_xcd < 1)
     return hipErrorInvalidValue;
+  if (dtype != GEM_F32 && dtype != GEM_BF16 && dtype != GEM_FP8_E4M3 && dtype != GEM_MXFP4) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(8 * sched.slots_per_xcd)), blk(kDenseThreads);
   const bool codes = D.codes != nullptr;
-  switch (dtype) {
-    case GEM_F32:
-      if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_F32, true>), grid, blk, 0, s, P);
-      else hipLaunchKernelGGL((score_dense_kernel<GEM_F32, false>), grid, blk, 0, s, P);
-      break;
-    case GEM_BF16:
-      if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_BF16, true>), grid, blk, 0, s, P);
-      else hipLaunchKernelGGL((score_dense_kernel<GEM_BF16, false>), grid, blk, 0, s, P);
-      break;
-    case GEM_FP8_E4M3:
-      if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_FP8_E4M3, true>), grid, blk, 0, s, P);
-      else if (block_rows <= 64)                             // two workgroups per CU
-        hipLaunchKernelGGL(score_dense_narrow_kernel<GEM_FP8_E4M3>, dim3(2 * grid.x), blk, 0, s, P);
-      else hipLaunchKernelGGL((score_dense_kernel<GEM_FP8_E4M3, false>), grid, blk, 0, s, P);
-      break;
-    case GEM_MXFP4:
-      if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_MXFP4, true>), grid, blk, 0, s, P);
-      else hipLaunchKernelGGL((score_dense_kernel<GEM_MXFP4, false>), grid, blk, 0, s, P);
-      break;
-    default: return hipErrorInvalidValue;
+  if (out.tk.k > 0) {
+    if (out.tk.np < 1 || out.tk.cap < 64 || (out.tk.cap & 63) || out.tk.cap > kTkMaxCap || out.tk.k > GEM_MAX_K ||
+        !out.tk.keys || !out.tk.cnt || !out.tk.gthr)
+      return hipErrorInvalidValue;
+    launch_dense_variant<true>(dtype, codes, block_rows, grid, blk, P, s);
+  } else {
+    launch_dense_variant<false>(dtype, codes, block_rows, grid, blk, P, s);
   }
   return hipGetLastError();
 }
@@ -885,8 +1130,7 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
     const int e = 63 - __builtin_clzll(msk);
     const int k = T - __builtin_amdgcn_readlane(d_t0, e);
     const int len = __builtin_amdgcn_readlane(d_len, e);
-    const int64_t beg = (int64_t)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(d_beg >> 32), e) << 32) |
-                                  __builtin_amdgcn_readlane((uint32_t)d_beg, e));
+    const int64_t beg = (int64_t)readlane_u64((uint64_t)d_beg, e);
     return beg + min(16 * k + c16, len - 1);
   };
 

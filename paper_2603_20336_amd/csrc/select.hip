@@ -6,6 +6,8 @@
 // the complemented id, so a larger key is a higher score or, on equal scores,
 // a smaller id. A repeated id keeps its best entry; identical (score, id)
 // copies have identical keys.
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "gem_internal.h"
 
@@ -387,6 +389,56 @@ hipError_t launch_topk(const TopkSegs& segs, int32_t k, float* top_scores, int32
   if (segs.n_segs == 0 || k == 0) return hipSuccess;
   hipLaunchKernelGGL(topk_kernel, dim3(capped_blocks(segs.n_segs, kSelThreads)), dim3(kSelThreads), 0, s, segs, k,
                      top_scores, top_ids);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Merge of the fused top-k's regions (one workgroup per query): the region
+// keys stream through LDS; whenever the buffer is full it is sorted and cut to
+// the best k (a key dropped there is beaten by k others), and the final sort
+// gives the query's top-k. Keys are distinct within a query, so this is the
+// top-k of the whole score row, written as topk_kernel writes it.
+__global__ __launch_bounds__(kSelThreads, 8) void topk_regions_kernel(const uint64_t* __restrict__ keys,
+                                                                  const int32_t* __restrict__ cnt, int64_t n_q,
+                                                                  int32_t regions, int32_t cap, int32_t k,
+                                                                  float* __restrict__ top_scores,
+                                                                  int32_t* __restrict__ top_ids) {
+  __shared__ uint64_t buf[kSelCap];
+  __shared__ int s_cnt;
+  const int tid = threadIdx.x;
+  for (int64_t q = blockIdx.x; q < n_q; q += gridDim.x) {
+    __syncthreads();                                   // LDS reuse across queries
+    int fill = 0;
+    for (int r = 0; r < regions; ++r) {
+      const int n_r = cnt[q * regions + r];
+      const uint64_t* src = keys + (q * regions + r) * (int64_t)cap;
+      for (int e0 = 0; e0 < n_r;) {
+        const int take = min(n_r - e0, kSelCap - fill);
+        for (int i = tid; i < take; i += kSelThreads) buf[fill + i] = src[e0 + i];
+        fill += take;
+        e0 += take;
+        if (fill == kSelCap) {
+          __syncthreads();
+          fill = min(dedup_and_sort<kSelCap, kSelThreads>(buf, fill, false, &s_cnt), (int)k);
+        }
+      }
+    }
+    __syncthreads();
+    const int n_keys = dedup_and_sort<kSelCap, kSelThreads>(buf, fill, false, &s_cnt);
+    for (int r = tid; r < k; r += kSelThreads) {
+      const uint64_t key = r < n_keys ? buf[r] : 0ull;
+      top_scores[q * k + r] = key ? key_score(key) : neg_inf();
+      top_ids[q * k + r] = key ? key_id(key) : -1;
+    }
+  }
+}
+
+hipError_t launch_topk_regions(const uint64_t* keys, const int32_t* cnt, int64_t n_q, int32_t regions, int32_t cap,
+                               int32_t k, float* top_scores, int32_t* top_ids, hipStream_t s) {
+  if (n_q == 0 || k == 0) return hipSuccess;
+  if (k > kSelCap / 2 || regions < 1 || cap < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(topk_regions_kernel, dim3(capped_blocks(n_q, kSelThreads)), dim3(kSelThreads), 0, s, keys, cnt,
+                     n_q, regions, cap, k, top_scores, top_ids);
   return hipGetLastError();
 }
 

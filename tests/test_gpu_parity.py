@@ -349,6 +349,24 @@ def test_dense_full_size_row_and_top100(exhaustive_100k):
     assert ok, (bad, missing)
 
 
+def test_fused_topk_full_size(exhaustive_100k):
+    """The benchmark's calls with the top-k fused into the scorer (no score
+    matrix): bf16 top-100 and the FP8 shortlist of 1000, bitwise the top-k of
+    the staged score rows."""
+    w2, c, q = exhaustive_100k
+    Q = gem.Sets(q.vecs, q.offsets, "f32", q.max_len())
+    for dtype, k in (("bf16", 100), ("fp8", 1000)):
+        D = _device_sets(c, dtype)
+        assert gem.score_workspace_bytes(Q, D, k=k) < Q.n_sets * D.n_sets * 4
+        fs, fi = _score(Q, D, dtype, k=k)
+        scores = _score(Q, D, dtype)
+        ss, si = gem.topk(scores, k)
+        torch.cuda.synchronize()
+        assert torch.equal(fi, si), dtype
+        assert torch.equal(fs.view(torch.int32), ss.view(torch.int32)), dtype
+        del D, scores
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 def test_dense_schedules_bitwise_and_autotune(dtype):
     """Every dense schedule computes bitwise the same scores; the autotuner
