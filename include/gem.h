@@ -280,6 +280,24 @@ gem_status gem_score_quant(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, co
                            float* top_scores, int32_t* top_ids,
                            void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* gem_score_quant without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc. Its workspace is a static device array of
+ * GEM_STATIC_SCRATCH_BYTES that the library holds on each device it runs on
+ * (its address is taken once per device in gem_create). The call allocates
+ * nothing and computes exactly what gem_score_quant computes with the same
+ * arguments (bitwise). A call whose workspace (gem_workspace_bytes with
+ * GEM_OP_SCORE_QUANT) exceeds the array returns GEM_ERR_WORKSPACE with nothing
+ * enqueued. Every call on a device shares that device's array and keeps the
+ * last call's contents: calls that overlap on one device (other streams,
+ * other threads, other contexts of the device) race and must be serialized by
+ * the caller. */
+#define GEM_STATIC_SCRATCH_BYTES (64 << 20)
+gem_status gem_score_quant_static(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C,
+                                  int32_t k,
+                                  float* scores, int64_t ld_scores, const int32_t* score_rows,
+                                  float* top_scores, int32_t* top_ids, hipStream_t stream);
+
 /* Segmented top-k (the k-argmax of Sec. 3.1 applied per segment).
  *   seg_offsets != NULL: segment i = scores[seg_offsets[i] .. seg_offsets[i+1]-1],
  *     ids from seg_ids (NULL: position within the segment). Entries with a

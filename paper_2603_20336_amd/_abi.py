@@ -20,6 +20,7 @@ GEM_OP_SCORE_EXACT, GEM_OP_SCORE_QUANT, GEM_OP_TOPK, GEM_OP_EXPAND = 0, 1, 2, 3
 GEM_OP_NEAREST_CENTROID, GEM_OP_CENTROID_UPDATE = 4, 5
 GEM_OPT_TOPK_FUSION = 0
 GEM_TOPK_AUTO, GEM_TOPK_FUSED, GEM_TOPK_STAGED = 0, 1, 2
+GEM_STATIC_SCRATCH_BYTES = 64 << 20
 GEM_MAX_QUERY_LEN = 256
 GEM_MAX_K = 1024
 GEM_DIM = 128
@@ -80,6 +81,7 @@ SIGNATURES = {
     "gem_quantize_mxfp4": (i32, [c_p, c_p, i64, i32, c_p, c_p, c_p]),
     "gem_score_exact": (i32, [c_p, P_SETS, P_SETS, P_CANDS, i32, i32, c_p, i64, c_p, c_p, c_p, c_p, sz, c_p]),
     "gem_score_quant": (i32, [c_p, P_SETS, P_SETS, P_CANDS, i32, c_p, i64, c_p, c_p, c_p, c_p, sz, c_p]),
+    "gem_score_quant_static": (i32, [c_p, P_SETS, P_SETS, P_CANDS, i32, c_p, i64, c_p, c_p, c_p, c_p]),
     "gem_topk": (i32, [c_p, c_p, c_p, c_p, i64, i64, i64, c_p, i32, c_p, c_p, c_p, sz, c_p]),
     "gem_expand_batch": (i32, [c_p, P_SETS, P_SETS, P_CANDS, P_BEAM, c_p, c_p, sz, c_p]),
     "gem_beam_merge": (i32, [c_p, c_p, P_CANDS, P_BEAM, c_p]),

@@ -24,7 +24,13 @@ struct gem_ctx_s {
   std::mutex mu;
   std::map<uint64_t, gem::DenseSchedule> dense;
   int32_t topk_mode = GEM_TOPK_AUTO;     // GEM_OPT_TOPK_FUSION
+  void* scratch = nullptr;               // this device's copy of `scratch` (gem_score_quant_static)
 };
+
+// Device memory that gem_score_quant_static uses as its workspace, for callers
+// that cannot allocate. Each device the library runs on holds its own copy
+// until the process ends; every call on a device shares it.
+static __device__ __align__(256) unsigned char scratch[GEM_STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -416,6 +422,22 @@ gem_status gem_create(gem_ctx* out, int device) {
   if (!c) return fail(GEM_ERR_INVALID, "out of host memory");
   c->device = device;
   c->n_cu = prop.multiProcessorCount;
+  // the device address of this device's scratch array (the name itself is a
+  // host-side stand-in), taken with the device current
+  {
+    int prev = 0;
+    e = hipGetDevice(&prev);
+    if (e == hipSuccess) e = hipSetDevice(device);
+    void* p = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    const hipError_t e2 = hipSetDevice(prev);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) {
+      delete c;
+      return hip_fail(e, "static scratch address");
+    }
+    c->scratch = p;
+  }
   std::snprintf(c->arch, sizeof(c->arch), "%s", prop.gcnArchName);
   *out = c;
   return GEM_OK;
@@ -586,6 +608,25 @@ gem_status gem_score_quant(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, co
   if (!quant_dtype(D->dtype)) return fail(GEM_ERR_INVALID, "D: dtype %d is not a quantized format", D->dtype);
   return score_common(ctx, Q, D, C, D->dtype, k, scores, ld_scores, score_rows, top_scores, top_ids, ws, ws_bytes,
                       stream);
+}
+
+gem_status gem_score_quant_static(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t k,
+                                  float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,
+                                  int32_t* top_ids, hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (!Q || !D) return fail(GEM_ERR_INVALID, "NULL sets");
+  if (!quant_dtype(D->dtype)) return fail(GEM_ERR_INVALID, "D: dtype %d is not a quantized format", D->dtype);
+  if (!ctx->scratch) return fail(GEM_ERR_HIP, "no static scratch on device %d", ctx->device);
+  gem_status st;
+  if ((st = check_sets(Q, "Q", true)) != GEM_OK) return st;
+  if ((st = check_sets(D, "D", false)) != GEM_OK) return st;
+  if (C && (st = check_cands(C, Q->n_sets)) != GEM_OK) return st;
+  const size_t need = score_layout(Q, D, C, D->dtype, k, scores != nullptr, ctx->n_cu / 8, ctx->topk_mode).total;
+  if (need > (size_t)GEM_STATIC_SCRATCH_BYTES)
+    return fail(GEM_ERR_WORKSPACE, "this call needs %zu bytes of workspace; the static scratch holds %zu", need,
+                (size_t)GEM_STATIC_SCRATCH_BYTES);
+  return score_common(ctx, Q, D, C, D->dtype, k, scores, ld_scores, score_rows, top_scores, top_ids, ctx->scratch,
+                      (size_t)GEM_STATIC_SCRATCH_BYTES, stream);
 }
 
 gem_status gem_topk(gem_ctx ctx, const float* scores, const int64_t* seg_offsets, const int32_t* seg_ids,
