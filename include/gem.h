@@ -147,8 +147,13 @@ typedef struct {
   int32_t* ids;                /* [device] [n_queries * ef] */
 } gem_beam;
 
-/* Create a context bound to HIP device `device`. Reads device properties once. */
-gem_status gem_create(gem_ctx* out, int device);
+/* Create a context bound to HIP device `device`. Reads device properties once
+ * and takes the address of the device's static scratch (gem_score_quant_static).
+ * tune_cache_json: NULL, or the path of a tune cache written by
+ * gem_save_tune_cache; its schedules for this GPU's architecture are installed
+ * (entries of other architectures are skipped). A path that does not exist
+ * is an empty cache; a file that is not a valid cache fails the call. */
+gem_status gem_create(gem_ctx* out, int device, const char* tune_cache_json);
 gem_status gem_destroy(gem_ctx ctx);
 /* Static string naming a status code. */
 const char* gem_status_string(gem_status s);
@@ -457,13 +462,54 @@ gem_status gem_set_dense_schedule(gem_ctx ctx, int32_t dtype, int64_t q_rows, in
  * scores [n_q][ld_scores]) once untimed and `reps` (1..100) times timed under
  * each candidate schedule, installs the fastest for the call's shape class and
  * returns it with its mean time per call in milliseconds. Synchronizes `stream`.
- * The candidates vary chunk_docs (64, 32) and items_per_slot (4, 8, 16). The
- * workspace must hold gem_workspace_bytes(ctx, op, Q, D, NULL, compute, 0, 1)
- * bytes (op GEM_OP_SCORE_EXACT, or GEM_OP_SCORE_QUANT for FP8).
+ * The candidates: the library default, then chunk_docs (64, 32) x
+ * items_per_slot (2, 4, 8, 16) at one workgroup per CU, then 3/4 and 1/2 of
+ * the workgroups per XCD for the best of those. A candidate's time is the
+ * median of three rounds of `reps` calls, and it displaces the best so far
+ * only when faster by more than 0.5 % (so near ties keep the earlier, and the
+ * choice is stable from run to run). The workspace must hold
+ * gem_workspace_bytes(ctx, op, Q, D, NULL, compute, 0, 1) bytes (op
+ * GEM_OP_SCORE_EXACT, or GEM_OP_SCORE_QUANT for FP8 / MXFP4).
  */
 gem_status gem_autotune_dense(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, int32_t compute, float* scores,
                               int64_t ld_scores, void* ws, size_t ws_bytes, hipStream_t stream, int32_t reps,
                               gem_dense_schedule* best, float* best_ms);
+
+/* Schedule of the gathered scorer (candidate lists: the rerank, beam
+ * expansion and search steps): entries of a list per wave (1..64; 0 = the
+ * library's rule: 16, or fewer when a call has too few entries to fill the
+ * GPU) and document tiles in flight per wave (one of three depths per format:
+ * F32 1/2/3, BF16 2/4/6, FP8 4/6/8, MXFP4 6/8/12; 0 or the middle one is the
+ * default). Kept per shape class: the compute dtype and the power-of-two
+ * classes of the list count and of the longest list. A schedule changes the
+ * time of a call, never its results. */
+typedef struct {
+  int32_t entries_per_wave;
+  int32_t depth;
+  int32_t reserved[2];
+} gem_gather_schedule;
+gem_status gem_get_gather_schedule(gem_ctx ctx, int32_t dtype, int64_t n_lists, int64_t max_list_len,
+                                   gem_gather_schedule* out);
+gem_status gem_set_gather_schedule(gem_ctx ctx, int32_t dtype, int64_t n_lists, int64_t max_list_len,
+                                   const gem_gather_schedule* sched);
+
+/* Autotuner for the gathered scorer: runs the scoring of Q's candidate lists C
+ * against D (as gem_score_exact / gem_score_quant with k = 0 would, writing
+ * scores [C->n_entries]) under the library rule and every entries_per_wave in
+ * (0, 8, 16, 32, 64) x depth, with the timing and tie rule of
+ * gem_autotune_dense; installs the fastest for the call's shape class.
+ * Synchronizes `stream`. ws: gem_workspace_bytes(ctx, op, Q, D, C, compute, 0, 1). */
+gem_status gem_autotune_gather(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C,
+                               int32_t compute, float* scores, void* ws, size_t ws_bytes, hipStream_t stream,
+                               int32_t reps, gem_gather_schedule* best, float* best_ms);
+
+/* The tune cache: every installed dense and gathered schedule of the context,
+ * keyed by (architecture, kind, dtype, shape class), as a JSON document at
+ * `path` (host file I/O only). gem_load_tune_cache installs a cache's entries
+ * for this GPU's architecture (a missing or invalid file is an error;
+ * nothing is installed from an invalid one); gem_create does the same. */
+gem_status gem_save_tune_cache(gem_ctx ctx, const char* path);
+gem_status gem_load_tune_cache(gem_ctx ctx, const char* path);
 
 #ifdef __cplusplus
 }

@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import ctypes
 import math
+import os
 from typing import Optional
 
 import torch
@@ -25,7 +26,8 @@ __all__ = ["Sets", "Cands", "Beam", "GemError", "convert_bf16", "quantize_fp8", 
            "library", "GEM_F32", "GEM_BF16", "GEM_FP8_E4M3", "GEM_MXFP4", "quantize_mxfp4", "GEM_MAX_K", "GEM_MAX_QUERY_LEN", "dense_schedule",
            "set_dense_schedule", "autotune_dense", "copy_rows", "nearest_centroid", "centroid_update",
            "kmeans", "encode", "codebook_size",
-           "emd_sinkhorn", "set_topk_fusion", "topk_fusion", "score_workspace_bytes"]
+           "emd_sinkhorn", "set_topk_fusion", "topk_fusion", "score_workspace_bytes", "gather_schedule",
+           "set_gather_schedule", "autotune_gather", "save_tune_cache", "load_tune_cache"]
 
 _DTYPES = {"f32": GEM_F32, "bf16": GEM_BF16, "fp8": GEM_FP8_E4M3, "mxfp4": GEM_MXFP4,
            GEM_F32: GEM_F32, GEM_BF16: GEM_BF16, GEM_FP8_E4M3: GEM_FP8_E4M3, GEM_MXFP4: GEM_MXFP4}
@@ -49,10 +51,13 @@ def _stream(stream) -> int:
 
 
 class _Context:
+    """One library context per device; GEM_TUNE_CACHE names a tune cache to load."""
+
     def __init__(self, device: int):
         lib = library()
         h = ctypes.c_void_p()
-        _abi.check(lib.gem_create(ctypes.byref(h), device))
+        cache = os.environ.get("GEM_TUNE_CACHE")
+        _abi.check(lib.gem_create(ctypes.byref(h), device, cache.encode() if cache else None))
         self.handle = h
         self.device = device
 
@@ -455,6 +460,60 @@ def autotune_dense(Q: Sets, D: Sets, compute=None, reps: int = 2, scores: Option
                                             int(ld), _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream),
                                             int(reps), ctypes.byref(best), ctypes.byref(ms)))
     return _sched_dict(best), float(ms.value)
+
+
+def _gather_dict(g) -> dict:
+    return {"entries_per_wave": int(g.entries_per_wave), "depth": int(g.depth)}
+
+
+def gather_schedule(dtype, n_lists: int, max_list_len: int, device="cuda") -> dict:
+    """The gathered-scorer schedule a call of this shape class uses (entries_per_wave 0: the library's rule)."""
+    g = _abi.gem_gather_schedule()
+    _abi.check(library().gem_get_gather_schedule(_ctx(torch.device(device)), _DTYPES[dtype], int(n_lists),
+                                                 int(max_list_len), ctypes.byref(g)))
+    return _gather_dict(g)
+
+
+def set_gather_schedule(dtype, n_lists: int, max_list_len: int, schedule: Optional[dict], device="cuda") -> None:
+    """Install a gathered-scorer schedule for the shape class (None: back to the library's rule)."""
+    p = None
+    if schedule is not None:
+        g = _abi.gem_gather_schedule(int(schedule["entries_per_wave"]), int(schedule["depth"]))
+        p = ctypes.byref(g)
+    _abi.check(library().gem_set_gather_schedule(_ctx(torch.device(device)), _DTYPES[dtype], int(n_lists),
+                                                 int(max_list_len), p))
+
+
+def autotune_gather(Q: Sets, D: Sets, cands: Cands, compute=None, reps: int = 2,
+                    scores: Optional[torch.Tensor] = None, stream=None):
+    """Time the gathered scorer's candidate schedules on this call (scoring the
+    candidate lists), install the fastest for its shape class and return
+    (schedule, ms per call)."""
+    compute = D.dtype if compute is None else _DTYPES[compute]
+    dev = D.device
+    if scores is None:
+        scores = torch.empty(cands.ids.numel(), dtype=torch.float32, device=dev)
+    qs, ds, cs = Q.struct(), D.struct(), cands.struct()
+    op = _abi.GEM_OP_SCORE_QUANT if compute in _QUANT else _abi.GEM_OP_SCORE_EXACT
+    need = library().gem_workspace_bytes(_ctx(dev), op, ctypes.byref(qs), ctypes.byref(ds), ctypes.byref(cs),
+                                         compute, 0, 1)
+    ws = _ws(need, dev)
+    best = _abi.gem_gather_schedule()
+    ms = ctypes.c_float(0.0)
+    _abi.check(library().gem_autotune_gather(_ctx(dev), ctypes.byref(qs), ctypes.byref(ds), ctypes.byref(cs), compute,
+                                             _ptr(scores), _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream),
+                                             int(reps), ctypes.byref(best), ctypes.byref(ms)))
+    return _gather_dict(best), float(ms.value)
+
+
+def save_tune_cache(path: str, device="cuda") -> None:
+    """Write every installed dense and gathered schedule to a JSON tune cache."""
+    _abi.check(library().gem_save_tune_cache(_ctx(torch.device(device)), str(path).encode()))
+
+
+def load_tune_cache(path: str, device="cuda") -> None:
+    """Install the schedules of a JSON tune cache for this GPU's architecture."""
+    _abi.check(library().gem_load_tune_cache(_ctx(torch.device(device)), str(path).encode()))
 
 
 def score_quant(Q: Sets, D8: Sets, cands: Optional[Cands] = None, k: int = 0,

@@ -51,6 +51,10 @@ class gem_dense_schedule(ctypes.Structure):
     _fields_ = [("chunk_docs", i32), ("items_per_slot", i32), ("slots_per_xcd", i32), ("reserved", i32)]
 
 
+class gem_gather_schedule(ctypes.Structure):
+    _fields_ = [("entries_per_wave", i32), ("depth", i32), ("reserved", i32 * 2)]
+
+
 class gem_graph(ctypes.Structure):
     _fields_ = [("n_sets", i64), ("k2", i32), ("degree", i32), ("neighbors", c_p), ("set_masks", c_p),
                 ("member_offsets", c_p), ("members", c_p)]
@@ -68,7 +72,7 @@ P_CANDS = ctypes.POINTER(gem_cands)
 P_BEAM = ctypes.POINTER(gem_beam)
 
 SIGNATURES = {
-    "gem_create": (i32, [ctypes.POINTER(c_p), ctypes.c_int]),
+    "gem_create": (i32, [ctypes.POINTER(c_p), ctypes.c_int, ctypes.c_char_p]),
     "gem_destroy": (i32, [c_p]),
     "gem_status_string": (ctypes.c_char_p, [i32]),
     "gem_last_error": (ctypes.c_char_p, []),
@@ -104,6 +108,12 @@ SIGNATURES = {
     "gem_set_dense_schedule": (i32, [c_p, i32, i64, i64, ctypes.POINTER(gem_dense_schedule)]),
     "gem_autotune_dense": (i32, [c_p, P_SETS, P_SETS, i32, c_p, i64, c_p, sz, c_p, i32,
                                  ctypes.POINTER(gem_dense_schedule), ctypes.POINTER(ctypes.c_float)]),
+    "gem_get_gather_schedule": (i32, [c_p, i32, i64, i64, ctypes.POINTER(gem_gather_schedule)]),
+    "gem_set_gather_schedule": (i32, [c_p, i32, i64, i64, ctypes.POINTER(gem_gather_schedule)]),
+    "gem_autotune_gather": (i32, [c_p, P_SETS, P_SETS, P_CANDS, i32, c_p, c_p, sz, c_p, i32,
+                                  ctypes.POINTER(gem_gather_schedule), ctypes.POINTER(ctypes.c_float)]),
+    "gem_save_tune_cache": (i32, [c_p, ctypes.c_char_p]),
+    "gem_load_tune_cache": (i32, [c_p, ctypes.c_char_p]),
 }
 
 _lib = None

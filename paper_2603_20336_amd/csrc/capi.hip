@@ -23,6 +23,9 @@ struct gem_ctx_s {
   // keyed by (dtype, shape class)
   std::mutex mu;
   std::map<uint64_t, gem::DenseSchedule> dense;
+  // gathered-scorer schedules (gem_set_gather_schedule / gem_autotune_gather),
+  // keyed by (dtype, class of the list count, class of the longest list)
+  std::map<uint64_t, gem::GatherSchedule> gather;
   int32_t topk_mode = GEM_TOPK_AUTO;     // GEM_OPT_TOPK_FUSION
   void* scratch = nullptr;               // this device's copy of `scratch` (gem_score_quant_static)
 };
@@ -244,6 +247,17 @@ uint64_t dense_key(int32_t dtype, int64_t q_rows, int64_t n_docs) {
          (uint64_t)log2_class(n_docs + 1);
 }
 
+uint64_t gather_key(int32_t dtype, int64_t n_lists, int64_t max_list_len) {
+  return ((uint64_t)(uint32_t)dtype << 16) | ((uint64_t)log2_class(n_lists + 1) << 8) |
+         (uint64_t)log2_class(max_list_len + 1);
+}
+
+GatherSchedule lookup_gather(gem_ctx ctx, int32_t dtype, int64_t n_lists, int64_t max_list_len) {
+  std::lock_guard<std::mutex> g(ctx->mu);
+  auto it = ctx->gather.find(gather_key(dtype, n_lists, max_list_len));
+  return it != ctx->gather.end() ? it->second : GatherSchedule{};
+}
+
 DenseSchedule lookup_dense(gem_ctx ctx, int32_t dtype, int64_t q_rows, int64_t n_docs) {
   {
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -256,7 +270,7 @@ DenseSchedule lookup_dense(gem_ctx ctx, int32_t dtype, int64_t q_rows, int64_t n
 gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t compute,
                         int32_t k, float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,
                         int32_t* top_ids, void* ws, size_t ws_bytes, hipStream_t stream,
-                        const DenseSchedule* sched = nullptr) {
+                        const DenseSchedule* sched = nullptr, const GatherSchedule* gsched = nullptr) {
   gem_status st;
   if ((st = check_sets(Q, "Q", true)) != GEM_OK) return st;
   if ((st = check_sets(D, "D", false)) != GEM_OK) return st;
@@ -332,7 +346,8 @@ gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const
     }
   } else {
     float* es = scores ? scores : reinterpret_cast<float*>(at(ws, L.staged));
-    e = launch_score_gather(compute, view(&Qc), view(D), cview(C), list_len_bound(C), Q->max_set_len, es, stream);
+    const GatherSchedule gs = gsched ? *gsched : lookup_gather(ctx, compute, C->n_lists, list_len_bound(C));
+    e = launch_score_gather(compute, view(&Qc), view(D), cview(C), list_len_bound(C), Q->max_set_len, es, gs, stream);
     if (e != hipSuccess) return hip_fail(e, "gathered scoring");
     if (k > 0) {
       TopkSegs S;
@@ -403,11 +418,256 @@ gem_status reset_validation(hipStream_t stream) {
   return GEM_OK;
 }
 
+// Timing of schedule candidates: each candidate runs once untimed, then
+// kRounds rounds of `reps` calls between two events on the caller's stream;
+// its time is the median round. A candidate replaces the best so far only
+// when it is faster by more than 0.5 %, so the first candidate (the
+// incumbent) keeps near ties and timing noise does not flip the choice from
+// run to run.
+struct Timer {
+  static constexpr int kRounds = 3;
+  hipStream_t stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  explicit Timer(hipStream_t s) : stream(s) {}
+  ~Timer() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+  gem_status init() {
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    return he == hipSuccess ? GEM_OK : hip_fail(he, "hipEventCreate");
+  }
+  template <class S, class F>
+  gem_status pick(const std::vector<S>& cand, F&& run, int reps, S* best, float* best_ms) {
+    for (const S& c : cand) {
+      gem_status st = run(c);
+      if (st != GEM_OK) return st;
+      float t[kRounds];
+      for (int r = 0; r < kRounds; ++r) {
+        hipError_t he = hipEventRecord(e0, stream);
+        if (he != hipSuccess) return hip_fail(he, "hipEventRecord");
+        for (int i = 0; i < reps; ++i)
+          if ((st = run(c)) != GEM_OK) return st;
+        if ((he = hipEventRecord(e1, stream)) != hipSuccess) return hip_fail(he, "hipEventRecord");
+        if ((he = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(he, "hipEventSynchronize");
+        if ((he = hipEventElapsedTime(&t[r], e0, e1)) != hipSuccess) return hip_fail(he, "hipEventElapsedTime");
+        t[r] /= (float)reps;
+      }
+      std::sort(t, t + kRounds);
+      const float ms = t[kRounds / 2];
+      if (*best_ms < 0.0f || ms < *best_ms * 0.995f) {
+        *best_ms = ms;
+        *best = c;
+      }
+    }
+    return GEM_OK;
+  }
+};
+
+// Tune cache: a small JSON document of installed schedules, e.g.
+//   {"format": "gem-tune-cache", "version": 1, "entries": [
+//     {"arch": "gfx950", "kind": "dense", "dtype": 1, "q_rows_class": 15,
+//      "n_docs_class": 16, "chunk_docs": 32, "items_per_slot": 8, "slots_per_xcd": 32},
+//     {"arch": "gfx950", "kind": "gather", "dtype": 2, "lists_class": 12,
+//      "list_len_class": 9, "entries_per_wave": 16, "depth": 6}]}
+// Classes are floor(log2(x + 1)) of the shape numbers the schedule keys use.
+
+std::string arch_base(const char* arch) {
+  std::string a(arch);
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+std::string tune_cache_json(gem_ctx ctx) {
+  const std::string arch = arch_base(ctx->arch);
+  std::string o = "{\"format\": \"gem-tune-cache\", \"version\": 1, \"entries\": [";
+  bool first = true;
+  char buf[384];
+  for (const auto& kv : ctx->dense) {
+    std::snprintf(buf, sizeof(buf),
+                  "%s\n  {\"arch\": \"%s\", \"kind\": \"dense\", \"dtype\": %u, \"q_rows_class\": %u, "
+                  "\"n_docs_class\": %u, \"chunk_docs\": %d, \"items_per_slot\": %d, \"slots_per_xcd\": %d}",
+                  first ? "" : ",", arch.c_str(), (unsigned)(kv.first >> 16), (unsigned)((kv.first >> 8) & 0xff),
+                  (unsigned)(kv.first & 0xff), kv.second.chunk_docs, kv.second.items_per_slot,
+                  kv.second.slots_per_xcd);
+    o += buf;
+    first = false;
+  }
+  for (const auto& kv : ctx->gather) {
+    std::snprintf(buf, sizeof(buf),
+                  "%s\n  {\"arch\": \"%s\", \"kind\": \"gather\", \"dtype\": %u, \"lists_class\": %u, "
+                  "\"list_len_class\": %u, \"entries_per_wave\": %d, \"depth\": %d}",
+                  first ? "" : ",", arch.c_str(), (unsigned)(kv.first >> 16), (unsigned)((kv.first >> 8) & 0xff),
+                  (unsigned)(kv.first & 0xff), kv.second.entries_per_wave, kv.second.depth);
+    o += buf;
+    first = false;
+  }
+  o += "\n]}\n";
+  return o;
+}
+
+// A minimal reader for that document: objects, arrays, strings without
+// escapes, integers, true / false / null.
+struct JVal {
+  enum Kind { NUL, NUM, STR, ARR, OBJ } kind = NUL;
+  long long num = 0;
+  std::string str;
+  std::vector<JVal> arr;
+  std::vector<std::pair<std::string, JVal>> obj;
+  const JVal* get(const char* k) const {
+    for (const auto& kv : obj)
+      if (kv.first == k) return &kv.second;
+    return nullptr;
+  }
+};
+
+struct JParser {
+  const char* p;
+  const char* end;
+  int depth = 0;
+  void ws() {
+    while (p < end && (*p == ' ' || *p == '\n' || *p == '\r' || *p == '\t')) ++p;
+  }
+  bool lit(const char* w) {
+    const size_t n = std::strlen(w);
+    if ((size_t)(end - p) < n || std::strncmp(p, w, n) != 0) return false;
+    p += n;
+    return true;
+  }
+  bool str(std::string& out) {
+    if (p >= end || *p != '"') return false;
+    const char* b = ++p;
+    while (p < end && *p != '"') {
+      if (*p == '\\') return false;
+      ++p;
+    }
+    if (p >= end) return false;
+    out.assign(b, p);
+    ++p;
+    return true;
+  }
+  bool val(JVal& v) {
+    if (++depth > 16) return false;
+    ws();
+    bool ok = false;
+    if (p < end && *p == '{') {
+      ++p;
+      v.kind = JVal::OBJ;
+      ws();
+      if (p < end && *p == '}') { ++p; ok = true; }
+      while (!ok) {
+        ws();
+        std::string k;
+        JVal x;
+        if (!str(k)) break;
+        ws();
+        if (p >= end || *p != ':') break;
+        ++p;
+        if (!val(x)) break;
+        v.obj.emplace_back(k, std::move(x));
+        ws();
+        if (p < end && *p == ',') { ++p; continue; }
+        if (p < end && *p == '}') { ++p; ok = true; }
+        break;
+      }
+    } else if (p < end && *p == '[') {
+      ++p;
+      v.kind = JVal::ARR;
+      ws();
+      if (p < end && *p == ']') { ++p; ok = true; }
+      while (!ok) {
+        JVal x;
+        if (!val(x)) break;
+        v.arr.push_back(std::move(x));
+        ws();
+        if (p < end && *p == ',') { ++p; continue; }
+        if (p < end && *p == ']') { ++p; ok = true; }
+        break;
+      }
+    } else if (p < end && *p == '"') {
+      v.kind = JVal::STR;
+      ok = str(v.str);
+    } else if (p < end && (*p == '-' || (*p >= '0' && *p <= '9'))) {
+      v.kind = JVal::NUM;
+      std::string digits;
+      while (p < end && (digits.empty() ? (*p == '-' || (*p >= '0' && *p <= '9')) : (*p >= '0' && *p <= '9')) &&
+             digits.size() < 20)
+        digits.push_back(*p++);
+      char* q = nullptr;
+      v.num = std::strtoll(digits.c_str(), &q, 10);
+      ok = q && *q == '\0' && digits != "-";
+    } else {
+      v.kind = JVal::NUL;
+      ok = lit("null") || lit("true") || lit("false");
+    }
+    --depth;
+    return ok;
+  }
+};
+
+gem_status load_tune_cache(gem_ctx ctx, const char* path, bool missing_ok) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return missing_ok ? GEM_OK : fail(GEM_ERR_INVALID, "cannot read %s", path);
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof(buf), f)) > 0 && text.size() < (1u << 24)) text.append(buf, n);
+  std::fclose(f);
+  JParser P{text.data(), text.data() + text.size()};
+  JVal root;
+  if (!P.val(root) || root.kind != JVal::OBJ) return fail(GEM_ERR_INVALID, "%s is not a JSON object", path);
+  const JVal* fmt = root.get("format");
+  const JVal* ent = root.get("entries");
+  if (!fmt || fmt->kind != JVal::STR || fmt->str != "gem-tune-cache" || !ent || ent->kind != JVal::ARR)
+    return fail(GEM_ERR_INVALID, "%s is not a gem tune cache", path);
+  const std::string arch = arch_base(ctx->arch);
+  std::map<uint64_t, DenseSchedule> dense;
+  std::map<uint64_t, GatherSchedule> gather;
+  auto num = [](const JVal& o, const char* k, long long lo, long long hi, long long* out) {
+    const JVal* v = o.get(k);
+    if (!v || v->kind != JVal::NUM || v->num < lo || v->num > hi) return false;
+    *out = v->num;
+    return true;
+  };
+  for (const JVal& e : ent->arr) {
+    if (e.kind != JVal::OBJ) return fail(GEM_ERR_INVALID, "%s: an entry is not an object", path);
+    const JVal* a = e.get("arch");
+    const JVal* kind = e.get("kind");
+    if (!a || a->kind != JVal::STR || !kind || kind->kind != JVal::STR)
+      return fail(GEM_ERR_INVALID, "%s: an entry lacks arch or kind", path);
+    if (a->str != arch) continue;                            // another GPU's schedules
+    long long dt = 0, c1 = 0, c2 = 0, x = 0, y = 0, z = 0;
+    if (kind->str == "dense") {
+      if (!num(e, "dtype", 0, 3, &dt) || !num(e, "q_rows_class", 0, 62, &c1) || !num(e, "n_docs_class", 0, 62, &c2) ||
+          !num(e, "chunk_docs", 0, 1 << 20, &x) || !num(e, "items_per_slot", 0, 1 << 20, &y) ||
+          !num(e, "slots_per_xcd", 0, 1 << 20, &z))
+        return fail(GEM_ERR_INVALID, "%s: malformed dense entry", path);
+      const DenseSchedule d{(int32_t)x, (int32_t)y, (int32_t)z};
+      if (!dense_schedule_valid(d, ctx->n_cu / 8)) return fail(GEM_ERR_INVALID, "%s: invalid dense schedule", path);
+      dense[((uint64_t)dt << 16) | ((uint64_t)c1 << 8) | (uint64_t)c2] = d;
+    } else if (kind->str == "gather") {
+      if (!num(e, "dtype", 0, 3, &dt) || !num(e, "lists_class", 0, 62, &c1) || !num(e, "list_len_class", 0, 62, &c2) ||
+          !num(e, "entries_per_wave", 0, 64, &x) || !num(e, "depth", 0, 64, &y))
+        return fail(GEM_ERR_INVALID, "%s: malformed gather entry", path);
+      const GatherSchedule g{(int32_t)x, (int32_t)y};
+      if (!gather_schedule_valid((int)dt, g)) return fail(GEM_ERR_INVALID, "%s: invalid gather schedule", path);
+      gather[((uint64_t)dt << 16) | ((uint64_t)c1 << 8) | (uint64_t)c2] = g;
+    } else {
+      return fail(GEM_ERR_INVALID, "%s: unknown entry kind %s", path, kind->str.c_str());
+    }
+  }
+  std::lock_guard<std::mutex> g(ctx->mu);
+  for (const auto& kv : dense) ctx->dense[kv.first] = kv.second;
+  for (const auto& kv : gather) ctx->gather[kv.first] = kv.second;
+  return GEM_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-gem_status gem_create(gem_ctx* out, int device) {
+gem_status gem_create(gem_ctx* out, int device, const char* tune_cache_json) {
   if (!out) return fail(GEM_ERR_INVALID, "out is NULL");
   int n = 0;
   hipError_t e = hipGetDeviceCount(&n);
@@ -439,6 +699,13 @@ gem_status gem_create(gem_ctx* out, int device) {
     c->scratch = p;
   }
   std::snprintf(c->arch, sizeof(c->arch), "%s", prop.gcnArchName);
+  if (tune_cache_json) {
+    const gem_status st = load_tune_cache(c, tune_cache_json, true);
+    if (st != GEM_OK) {
+      delete c;
+      return st;
+    }
+  }
   *out = c;
   return GEM_OK;
 }
@@ -680,7 +947,7 @@ gem_status gem_expand_batch(gem_ctx ctx, const gem_sets* Q8, const gem_sets* D8,
   if ((st = convert_query(Q8, cd, ws, L, &Qc, stream)) != GEM_OK) return st;
   float* es = cand_scores ? cand_scores : reinterpret_cast<float*>(at(ws, L.staged));
   hipError_t e = launch_score_gather(cd, view(&Qc), view(D8), cview(C), list_len_bound(C), Q8->max_set_len,
-                                     es, stream);
+                                     es, lookup_gather(ctx, cd, C->n_lists, list_len_bound(C)), stream);
   if (e != hipSuccess) return hip_fail(e, "gathered scoring");
   e = launch_beam_merge(es, cview(C), Q8->n_sets, beam->ef, beam->scores, beam->ids,
                         list_len_bound(C) > 0 ? beam->ef + list_len_bound(C) : 0, stream);
@@ -772,11 +1039,12 @@ gem_status check_search(const gem_sets* Q, const gem_sets* D, const gem_graph* G
   return GEM_OK;
 }
 
-gem_status search_score_merge(const gem_sets* Q, const gem_sets* D, const gem_search_state* S, gem_beam* beam,
-                              int32_t row, hipStream_t stream) {
+gem_status search_score_merge(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_search_state* S,
+                              gem_beam* beam, int32_t row, hipStream_t stream) {
   CandsView c;
   c.off = nullptr; c.ids = S->cand_ids; c.n_lists = Q->n_sets; c.stride = row;
-  hipError_t e = launch_score_gather(D->dtype, view(Q), view(D), c, row, Q->max_set_len, S->cand_scores, stream);
+  hipError_t e = launch_score_gather(D->dtype, view(Q), view(D), c, row, Q->max_set_len, S->cand_scores,
+                                     lookup_gather(ctx, D->dtype, Q->n_sets, row), stream);
   if (e != hipSuccess) return hip_fail(e, "search scoring");
   e = launch_beam_merge(S->cand_scores, c, Q->n_sets, beam->ef, beam->scores, beam->ids, beam->ef + row, stream);
   return e == hipSuccess ? GEM_OK : hip_fail(e, "search merge");
@@ -797,7 +1065,7 @@ gem_status gem_search_begin(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, c
   if (e == hipSuccess) e = launch_search_entries(v, Q->n_sets, random_words, S->cand_ids, row, stream);
   if (e == hipSuccess) e = launch_beam_reset(beam->scores, beam->ids, Q->n_sets * (int64_t)beam->ef, stream);
   if (e != hipSuccess) return hip_fail(e, "search start");
-  return search_score_merge(Q, D, S, beam, row, stream);
+  return search_score_merge(ctx, Q, D, S, beam, row, stream);
 }
 
 gem_status gem_search_step(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_graph* G,
@@ -810,7 +1078,7 @@ gem_status gem_search_step(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, co
   hipError_t e = launch_search_step(v, Q->n_sets, beam->ids, beam->ef, S->cand_ids, row, stream);
   if (e != hipSuccess) return hip_fail(e, "search step");
   if (Q->n_sets == 0) return GEM_OK;
-  return search_score_merge(Q, D, S, beam, row, stream);
+  return search_score_merge(ctx, Q, D, S, beam, row, stream);
 }
 
 gem_status gem_beam_merge(gem_ctx ctx, const float* cand_scores, const gem_cands* C, gem_beam* beam,
@@ -925,38 +1193,29 @@ gem_status gem_autotune_dense(gem_ctx ctx, const gem_sets* Q, const gem_sets* D,
   if (reps < 1 || reps > 100) return fail(GEM_ERR_INVALID, "reps = %d outside [1, 100]", reps);
   if (!Q || !D) return fail(GEM_ERR_INVALID, "NULL sets");
   const int cpx = ctx->n_cu / 8;
-  std::vector<DenseSchedule> cand;
-  for (int cd : {64, 32})
-    for (int ips : {4, 8, 16})
-      cand.push_back(DenseSchedule{cd, ips, cpx});
-  hipEvent_t e0, e1;
-  hipError_t he = hipEventCreate(&e0);
-  if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
-  he = hipEventCreate(&e1);
-  if (he != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(he, "hipEventCreate"); }
-  float best_t = -1.0f;
-  DenseSchedule best_s = cand[0];
-  gem_status st = GEM_OK;
-  for (const DenseSchedule& c : cand) {
-    // one untimed run, then `reps` timed back to back
-    st = score_common(ctx, Q, D, nullptr, compute, 0, scores, ld_scores, nullptr, nullptr, nullptr, ws, ws_bytes,
-                      stream, &c);
-    if (st != GEM_OK) break;
-    if ((he = hipEventRecord(e0, stream)) != hipSuccess) { st = hip_fail(he, "hipEventRecord"); break; }
-    for (int r = 0; r < reps && st == GEM_OK; ++r)
-      st = score_common(ctx, Q, D, nullptr, compute, 0, scores, ld_scores, nullptr, nullptr, nullptr, ws, ws_bytes,
-                        stream, &c);
-    if (st != GEM_OK) break;
-    if ((he = hipEventRecord(e1, stream)) != hipSuccess) { st = hip_fail(he, "hipEventRecord"); break; }
-    if ((he = hipEventSynchronize(e1)) != hipSuccess) { st = hip_fail(he, "hipEventSynchronize"); break; }
-    float ms = 0.0f;
-    if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { st = hip_fail(he, "hipEventElapsedTime"); break; }
-    ms /= (float)reps;
-    if (best_t < 0.0f || ms < best_t) { best_t = ms; best_s = c; }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  Timer T(stream);
+  gem_status st = T.init();
   if (st != GEM_OK) return st;
+  auto run = [&](const DenseSchedule& c) {
+    return score_common(ctx, Q, D, nullptr, compute, 0, scores, ld_scores, nullptr, nullptr, nullptr, ws, ws_bytes,
+                        stream, &c);
+  };
+  // stage 1: chunk size x items per workgroup at one workgroup per CU (the
+  // library default first: it keeps ties); stage 2: fewer workgroups per XCD
+  std::vector<DenseSchedule> cand;
+  cand.push_back(default_dense_schedule(compute, Q->n_vecs, D->n_sets, cpx));
+  for (int cd : {64, 32})
+    for (int ips : {2, 4, 8, 16}) {
+      const DenseSchedule c{cd, ips, cpx};
+      if (c.chunk_docs != cand[0].chunk_docs || c.items_per_slot != cand[0].items_per_slot) cand.push_back(c);
+    }
+  DenseSchedule best_s = cand[0];
+  float best_t = -1.0f;
+  if ((st = T.pick(cand, run, reps, &best_s, &best_t)) != GEM_OK) return st;
+  std::vector<DenseSchedule> cand2;
+  for (int sl : {(3 * cpx) / 4, cpx / 2})
+    if (sl >= 1 && sl != best_s.slots_per_xcd) cand2.push_back(DenseSchedule{best_s.chunk_docs, best_s.items_per_slot, sl});
+  if ((st = T.pick(cand2, run, reps, &best_s, &best_t)) != GEM_OK) return st;
   {
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->dense[dense_key(compute, Q->n_vecs, D->n_sets)] = best_s;
@@ -964,6 +1223,92 @@ gem_status gem_autotune_dense(gem_ctx ctx, const gem_sets* Q, const gem_sets* D,
   if (best) to_public(best_s, best);
   if (best_ms) *best_ms = best_t;
   return GEM_OK;
+}
+
+gem_status gem_get_gather_schedule(gem_ctx ctx, int32_t dtype, int64_t n_lists, int64_t max_list_len,
+                                   gem_gather_schedule* out) {
+  if (!ctx || !out) return fail(GEM_ERR_INVALID, "NULL argument");
+  if (!valid_dtype(dtype)) return fail(GEM_ERR_INVALID, "dtype %d", dtype);
+  const GatherSchedule g = lookup_gather(ctx, dtype, n_lists, max_list_len);
+  out->entries_per_wave = g.entries_per_wave;
+  out->depth = g.depth > 0 ? g.depth : gather_depth_choice(dtype, 1);
+  out->reserved[0] = out->reserved[1] = 0;
+  return GEM_OK;
+}
+
+gem_status gem_set_gather_schedule(gem_ctx ctx, int32_t dtype, int64_t n_lists, int64_t max_list_len,
+                                   const gem_gather_schedule* sched) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (!valid_dtype(dtype)) return fail(GEM_ERR_INVALID, "dtype %d", dtype);
+  const uint64_t key = gather_key(dtype, n_lists, max_list_len);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (!sched) {
+    ctx->gather.erase(key);
+    return GEM_OK;
+  }
+  const GatherSchedule gs{sched->entries_per_wave, sched->depth};
+  if (!gather_schedule_valid(dtype, gs))
+    return fail(GEM_ERR_INVALID, "gather schedule (entries_per_wave %d, depth %d) outside the supported set",
+                gs.entries_per_wave, gs.depth);
+  ctx->gather[key] = gs;
+  return GEM_OK;
+}
+
+gem_status gem_autotune_gather(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C,
+                               int32_t compute, float* scores, void* ws, size_t ws_bytes, hipStream_t stream,
+                               int32_t reps, gem_gather_schedule* best, float* best_ms) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (!valid_dtype(compute)) return fail(GEM_ERR_INVALID, "compute dtype %d", compute);
+  if (!C) return fail(GEM_ERR_INVALID, "autotuning the gathered scorer needs candidate lists");
+  if (!scores) return fail(GEM_ERR_INVALID, "autotuning needs a scores buffer");
+  if (reps < 1 || reps > 100) return fail(GEM_ERR_INVALID, "reps = %d outside [1, 100]", reps);
+  if (!Q || !D) return fail(GEM_ERR_INVALID, "NULL sets");
+  Timer T(stream);
+  gem_status st = T.init();
+  if (st != GEM_OK) return st;
+  auto run = [&](const GatherSchedule& g) {
+    return score_common(ctx, Q, D, C, compute, 0, scores, 0, nullptr, nullptr, nullptr, ws, ws_bytes, stream,
+                        nullptr, &g);
+  };
+  // the library's rule first (it keeps ties), then entries per wave x depth
+  std::vector<GatherSchedule> cand{GatherSchedule{}};
+  for (int e : {0, 8, 16, 32, 64})
+    for (int i = 0; i < 3; ++i)
+      if (!(e == 0 && i == 1)) cand.push_back(GatherSchedule{e, gather_depth_choice(compute, i)});
+  GatherSchedule best_s = cand[0];
+  float best_t = -1.0f;
+  if ((st = T.pick(cand, run, reps, &best_s, &best_t)) != GEM_OK) return st;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->gather[gather_key(compute, C->n_lists, list_len_bound(C))] = best_s;
+  }
+  if (best) {
+    best->entries_per_wave = best_s.entries_per_wave;
+    best->depth = best_s.depth > 0 ? best_s.depth : gather_depth_choice(compute, 1);
+    best->reserved[0] = best->reserved[1] = 0;
+  }
+  if (best_ms) *best_ms = best_t;
+  return GEM_OK;
+}
+
+gem_status gem_save_tune_cache(gem_ctx ctx, const char* path) {
+  if (!ctx || !path) return fail(GEM_ERR_INVALID, "NULL argument");
+  std::string out;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    out = tune_cache_json(ctx);
+  }
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(GEM_ERR_INVALID, "cannot write %s", path);
+  const size_t n = std::fwrite(out.data(), 1, out.size(), f);
+  const int c = std::fclose(f);
+  if (n != out.size() || c != 0) return fail(GEM_ERR_INVALID, "write of %s failed", path);
+  return GEM_OK;
+}
+
+gem_status gem_load_tune_cache(gem_ctx ctx, const char* path) {
+  if (!ctx || !path) return fail(GEM_ERR_INVALID, "NULL argument");
+  return load_tune_cache(ctx, path, false);
 }
 
 }  // extern "C"

@@ -95,8 +95,19 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
                               const int64_t* qcol, int64_t n_blocks_max, const DenseOut& out,
                               const DenseSchedule& sched, int32_t block_rows, hipStream_t s);
 
+// Schedule of the gathered scorer (never changes a result): entries of a list
+// per wave (0: the library's rule) and tiles in flight per wave (0: the
+// format's default; else one of gather_depth_choice(dtype, 0..2)).
+struct GatherSchedule {
+  int32_t entries_per_wave = 0;
+  int32_t depth = 0;
+};
+int gather_depth_choice(int dtype, int i);
+bool gather_schedule_valid(int dtype, const GatherSchedule& g);
+
 hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C,
-                               int32_t max_list_len, int32_t max_q_len, float* scores, hipStream_t s);
+                               int32_t max_list_len, int32_t max_q_len, float* scores, const GatherSchedule& g,
+                               hipStream_t s);
 // The dense output of a small query batch by the gathered scorer: every
 // document of D is an entry of every query's list (bitwise the dense scorer's
 // scores, one wave per few documents: memory-bound streaming instead of one

@@ -1049,11 +1049,23 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
 // sum of per-tile column sums, in tile order, as in the dense scorer.
 constexpr int kGatherEntries = 16;
 constexpr int kGatherNT = 4;
-// tiles in flight per wave (registers: a float32 tile fragment takes 32 VGPRs,
-// bf16 16, FP8 9)
-template <int DT> struct GatherDepth {
-  static constexpr int value = DT == GEM_F32 ? 2 : (DT == GEM_BF16 ? 4 : (DT == GEM_FP8_E4M3 ? 6 : 8));
-};
+// Tiles in flight per wave: the choices of each format (registers: a float32
+// tile fragment takes 32 VGPRs, bf16 16, FP8 9, MXFP4 5); the middle one is
+// the default.
+template <int DT> struct GatherDepths;
+template <> struct GatherDepths<GEM_F32> { static constexpr int d[3] = {1, 2, 3}; };
+template <> struct GatherDepths<GEM_BF16> { static constexpr int d[3] = {2, 4, 6}; };
+template <> struct GatherDepths<GEM_FP8_E4M3> { static constexpr int d[3] = {4, 6, 8}; };
+template <> struct GatherDepths<GEM_MXFP4> { static constexpr int d[3] = {6, 8, 12}; };
+
+int gather_depth_choice(int dtype, int i) {
+  switch (dtype) {
+    case GEM_F32: return GatherDepths<GEM_F32>::d[i];
+    case GEM_BF16: return GatherDepths<GEM_BF16>::d[i];
+    case GEM_FP8_E4M3: return GatherDepths<GEM_FP8_E4M3>::d[i];
+    default: return GatherDepths<GEM_MXFP4>::d[i];
+  }
+}
 
 struct GatherParams {
   SetsView Q, D;
@@ -1072,13 +1084,12 @@ struct GatherParams {
 // kCodes: the documents are a code set. Each lane then loads the code of the
 // row it will load PF tiles before that row's load is issued (a second ring of
 // PF codes), so tile loads never wait on a dependent load.
-template <int DT, bool kCodes>
+template <int DT, bool kCodes, int PF>
 __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
   using O = Op<DT>;
   using Frag = typename O::Frag;
   constexpr int NT = kGatherNT;
   constexpr int PASS = 16 * NT;
-  constexpr int PF = GatherDepth<DT>::value;
 
   const int l = threadIdx.x & 63, g = l >> 4, c16 = l & 15;
   const int64_t gw = P.wave0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -1235,17 +1246,43 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
   }
 }
 
+template <int DT, int PF>
+static void launch_gather_pf(bool codes, dim3 gr, dim3 blk, const GatherParams& P, hipStream_t s) {
+  if (codes) hipLaunchKernelGGL((score_gather_kernel<DT, true, PF>), gr, blk, 0, s, P);
+  else hipLaunchKernelGGL((score_gather_kernel<DT, false, PF>), gr, blk, 0, s, P);
+}
+
+template <int DT>
+static bool launch_gather_depth(int depth, bool codes, dim3 gr, dim3 blk, const GatherParams& P, hipStream_t s) {
+  using G = GatherDepths<DT>;
+  if (depth == G::d[0]) launch_gather_pf<DT, G::d[0]>(codes, gr, blk, P, s);
+  else if (depth == G::d[1]) launch_gather_pf<DT, G::d[1]>(codes, gr, blk, P, s);
+  else if (depth == G::d[2]) launch_gather_pf<DT, G::d[2]>(codes, gr, blk, P, s);
+  else return false;
+  return true;
+}
+
+bool gather_schedule_valid(int dtype, const GatherSchedule& g) {
+  if (g.entries_per_wave != 0 && (g.entries_per_wave < 1 || g.entries_per_wave > 64)) return false;
+  if (g.depth == 0) return true;
+  for (int i = 0; i < 3; ++i)
+    if (g.depth == gather_depth_choice(dtype, i)) return true;
+  return false;
+}
+
 // Launches the gathered scorer over C.n_lists lists of at most max_list_len
 // entries (in slices of at most kMaxGridThreads threads).
-static hipError_t run_gather(int dtype, GatherParams P, int64_t max_list_len, hipStream_t s) {
-  // entries per wave: kGatherEntries, or as few as one when the call holds
-  // fewer than kGatherWaves full waves (a single request's rerank of 1000
-  // candidates then runs on 1000 waves rather than 63)
+static hipError_t run_gather(int dtype, GatherParams P, int64_t max_list_len, const GatherSchedule& g, hipStream_t s) {
+  // entries per wave: the schedule's, else kGatherEntries, or as few as one
+  // when the call holds fewer than kGatherWaves full waves (a single
+  // request's rerank of 1000 candidates then runs on 1000 waves rather than 63)
   constexpr int64_t kGatherWaves = 4096;
   const int64_t cap = P.C.n_lists * std::max<int64_t>(max_list_len, 0);
-  P.entries_per_wave = cap >= kGatherEntries * kGatherWaves
-                           ? kGatherEntries
-                           : (int32_t)std::max<int64_t>(1, (cap + kGatherWaves - 1) / kGatherWaves);
+  if (g.entries_per_wave > 0) P.entries_per_wave = g.entries_per_wave;
+  else P.entries_per_wave = cap >= kGatherEntries * kGatherWaves
+                                ? kGatherEntries
+                                : (int32_t)std::max<int64_t>(1, (cap + kGatherWaves - 1) / kGatherWaves);
+  const int depth = g.depth > 0 ? g.depth : gather_depth_choice(dtype, 1);
   P.chunks_per_query = (max_list_len + P.entries_per_wave - 1) / P.entries_per_wave;
   if (P.chunks_per_query == 0 || P.C.n_lists == 0) return hipSuccess;
   const int64_t waves = P.chunks_per_query * P.C.n_lists;
@@ -1255,25 +1292,15 @@ static hipError_t run_gather(int dtype, GatherParams P, int64_t max_list_len, hi
     const int64_t grid = std::min(max_blocks, (waves + 3) / 4 - b0);
     const dim3 gr((unsigned)grid), blk(256);
     const bool codes = P.D.codes != nullptr;
+    bool ok = false;
     switch (dtype) {
-      case GEM_F32:
-        if (codes) hipLaunchKernelGGL((score_gather_kernel<GEM_F32, true>), gr, blk, 0, s, P);
-        else hipLaunchKernelGGL((score_gather_kernel<GEM_F32, false>), gr, blk, 0, s, P);
-        break;
-      case GEM_BF16:
-        if (codes) hipLaunchKernelGGL((score_gather_kernel<GEM_BF16, true>), gr, blk, 0, s, P);
-        else hipLaunchKernelGGL((score_gather_kernel<GEM_BF16, false>), gr, blk, 0, s, P);
-        break;
-      case GEM_FP8_E4M3:
-        if (codes) hipLaunchKernelGGL((score_gather_kernel<GEM_FP8_E4M3, true>), gr, blk, 0, s, P);
-        else hipLaunchKernelGGL((score_gather_kernel<GEM_FP8_E4M3, false>), gr, blk, 0, s, P);
-        break;
-      case GEM_MXFP4:
-        if (codes) hipLaunchKernelGGL((score_gather_kernel<GEM_MXFP4, true>), gr, blk, 0, s, P);
-        else hipLaunchKernelGGL((score_gather_kernel<GEM_MXFP4, false>), gr, blk, 0, s, P);
-        break;
-      default: return hipErrorInvalidValue;
+      case GEM_F32: ok = launch_gather_depth<GEM_F32>(depth, codes, gr, blk, P, s); break;
+      case GEM_BF16: ok = launch_gather_depth<GEM_BF16>(depth, codes, gr, blk, P, s); break;
+      case GEM_FP8_E4M3: ok = launch_gather_depth<GEM_FP8_E4M3>(depth, codes, gr, blk, P, s); break;
+      case GEM_MXFP4: ok = launch_gather_depth<GEM_MXFP4>(depth, codes, gr, blk, P, s); break;
+      default: break;
     }
+    if (!ok) return hipErrorInvalidValue;
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1281,11 +1308,11 @@ static hipError_t run_gather(int dtype, GatherParams P, int64_t max_list_len, hi
 }
 
 hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C,
-                               int32_t max_list_len, int32_t, float* scores, hipStream_t s) {
+                               int32_t max_list_len, int32_t, float* scores, const GatherSchedule& g, hipStream_t s) {
   GatherParams P{};
   P.Q = Q; P.D = D; P.C = C; P.scores = scores;
   P.range = 0;
-  return run_gather(dtype, P, max_list_len, s);
+  return run_gather(dtype, P, max_list_len, g, s);
 }
 
 hipError_t launch_score_range(int dtype, const SetsView& Q, const SetsView& D, const DenseOut& out, hipStream_t s) {
@@ -1295,7 +1322,7 @@ hipError_t launch_score_range(int dtype, const SetsView& Q, const SetsView& D, c
   P.C.off = nullptr; P.C.ids = nullptr; P.C.n_lists = Q.n_sets; P.C.stride = 0;
   P.scores = out.scores; P.out_rows = out.rows; P.out_ld = out.ld;
   P.range = 1;
-  return run_gather(dtype, P, D.n_sets, s);
+  return run_gather(dtype, P, D.n_sets, GatherSchedule{}, s);
 }
 
 }  // namespace gem

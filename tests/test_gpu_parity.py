@@ -394,7 +394,8 @@ def test_dense_schedules_bitwise_and_autotune(dtype):
         gem.set_dense_schedule(dtype, Q.n_vecs, D.n_sets, {"chunk_docs": 48, "items_per_slot": 8,
                                                            "slots_per_xcd": spx})
     best, ms = gem.autotune_dense(Q, D, reps=1)
-    assert ms > 0 and best["chunk_docs"] in (32, 64) and best["items_per_slot"] in (4, 8, 16)
+    assert ms > 0 and best["chunk_docs"] in (32, 64) and best["items_per_slot"] in (2, 4, 8, 16)
+    assert best["slots_per_xcd"] in (spx, (3 * spx) // 4, spx // 2)
     assert gem.dense_schedule(dtype, Q.n_vecs, D.n_sets) == best
     np.testing.assert_array_equal(_np(_score(Q, D, dtype)), base)
     gem.set_dense_schedule(dtype, Q.n_vecs, D.n_sets, None)
