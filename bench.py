@@ -245,16 +245,20 @@ def copy_calibration(n_bytes: int = 1 << 30, reps: int = 3) -> None:
     log(f"copy calibration: {reps} x {n_bytes} bytes read + written")
 
 
-def recall_vs_exact(top_ids: np.ndarray, exact: np.ndarray, k: int) -> float:
-    import oracle
-    rs = []
-    for r in range(exact.shape[0]):
-        s_k = np.sort(exact[r])[::-1][k - 1]
-        rs.append(oracle.recall_at_k(top_ids[r], exact[r], k, tau=2e-4 * max(abs(s_k), 1.0)))
-    return float(np.mean(rs))
+def recall_gpu(top_ids: torch.Tensor, exact: torch.Tensor, exact_kth: torch.Tensor, k: int) -> float:
+    """Recall@k (Sec. 5.1) of every query's returned ids against its exact
+    float32 scores, tie-aware: a returned id counts when its exact score is at
+    least the exact k-th score minus a band of 2e-4 * max(|s_k|, 1)."""
+    ids = top_ids[:, :k].long()
+    valid = ids >= 0
+    s = exact.gather(1, ids.clamp(min=0))
+    tau = 2e-4 * exact_kth.abs().clamp(min=1.0)
+    hits = ((s >= (exact_kth - tau)[:, None]) & valid).float().sum(1)
+    return float((hits / k).mean().item())
 
 
 def bench_exhaustive(args):
+    import oracle
     dev = torch.device("cuda:0")
     w2 = wl.WORKLOADS[2]
     log("generating the 100k-document corpus and 1000 queries on the GPU")
@@ -277,27 +281,31 @@ def bench_exhaustive(args):
     torch.cuda.synchronize()
 
     k = w2.k
+    flops = 2.0 * 128 * q_rows * V
+    pairs = n_q * n_d
     scores = torch.empty(n_q, n_d, dtype=torch.float32, device=dev)
-    Q16 = None
     # the autotuner picks the dense scorer's schedule for this shape (untimed)
     sched = {}
     sched["bf16"], _ = gem.autotune_dense(gem.convert_bf16(Q), D16, reps=2, scores=scores)
     log(f"bf16 schedule {sched['bf16']}")
+    ws_fused = gem.score_workspace_bytes(Q, D16, k=k, compute="bf16")
 
     def step():
-        nonlocal Q16
         Q16 = gem.convert_bf16(Q)                                   # a2: query ingest
-        gem.score_exact(Q16, D16, compute="bf16", scores=scores)    # a3-a5: MFMA scoring
-        return gem.topk(scores, k)                                  # a6: per-query top-k
+        return gem.score_exact(Q16, D16, compute="bf16", k=k)       # a3-a6: MFMA scoring, fused top-100
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     # per-stage timings (events on the stream the kernels run on)
-    t_conv = timed(lambda: gem.convert_bf16(Q), max(1, args.steps))
     Q16 = gem.convert_bf16(Q)
+    t_conv = timed(lambda: gem.convert_bf16(Q), max(1, args.steps))
+    t_fused = timed(lambda: gem.score_exact(Q16, D16, compute="bf16", k=k), max(1, args.steps))
     t_score = timed(lambda: gem.score_exact(Q16, D16, compute="bf16", scores=scores), max(1, args.steps))
     t_topk = timed(lambda: gem.topk(scores, k), max(1, args.steps))
+    gem.set_topk_fusion("staged")
+    ws_staged = gem.score_workspace_bytes(Q, D16, k=k, compute="bf16")
+    gem.set_topk_fusion("auto")
 
     torch.cuda.synchronize()
     gc.disable()                        # no collector pause inside the timed steps
@@ -308,125 +316,124 @@ def bench_exhaustive(args):
     dt = time.perf_counter() - t0
     gc.enable()
     ms_per_step = dt * 1e3 / args.steps
-    pairs = n_q * n_d
-    flops = 2.0 * 128 * q_rows * V
-    log(f"bf16 step {ms_per_step:.2f} ms (convert {t_conv:.3f}, score {t_score:.2f}, top-k {t_topk:.2f})")
-    # the bf16 scores of the accuracy sample (later legs reuse the score buffer)
-    bf16_rows = scores[:max(1, args.cpu_sample)].clone()
+    log(f"bf16 step {ms_per_step:.2f} ms (convert {t_conv:.3f}, fused score+top-{k} {t_fused:.2f}; "
+        f"staged: score {t_score:.2f} + top-k {t_topk:.2f})")
+    bf16_sample = scores[:max(1, args.cpu_sample)].clone()     # the bf16 scores of the accuracy sample
 
-    # float32 exact path (reference "plain FP32 GPU path") on the same batch
+    # float32 exact path (the "plain FP32 GPU path") on the same batch; its
+    # full score rows are the reference every recall below is taken against
     sched["f32"], _ = gem.autotune_dense(Q, D32, reps=1, scores=scores)
-    top32_s, top32_i = gem.score_exact(Q, D32, compute="f32", k=k)
+    exact = torch.empty(n_q, n_d, dtype=torch.float32, device=dev)
+    gem.score_exact(Q, D32, compute="f32", scores=exact)
+    top32_s, top32_i = gem.topk(exact, k)
     torch.cuda.synchronize()
     t_f32 = timed(lambda: gem.score_exact(Q, D32, compute="f32", k=k), 1)
+    exact_kth = top32_s[:, k - 1].clone()
     log(f"f32 exact path {t_f32:.1f} ms")
 
-    # FP8 estimate -> top-1000 shortlist -> float32 rerank -> top-100
-    sl = 1000
+    def rerank(short_i, sl):
+        C = gem.Cands(short_i.reshape(-1), stride=sl, n_lists=n_q)
+        return gem.score_exact(Q, D32, cands=C, compute="f32", k=k)
+
+    # estimate -> top-sl shortlist -> float32 rerank -> top-100, swept over
+    # the shortlist length (Sec. 5, "Effect of #rerank")
+    sweep_sl = [int(x) for x in args.shortlists.split(",") if x]
+
+    def sweep(name, make_q, score_k):
+        out = {}
+        for sl in sweep_sl:
+            def path(sl=sl):
+                _, short_i = score_k(make_q(), sl)
+                return rerank(short_i, sl)
+            r_s, r_i = path()
+            torch.cuda.synchronize()
+            t = timed(path, max(1, args.steps // 4))
+            out[str(sl)] = {"ms": t, "pair_scores_per_s": pairs / (t / 1e3), "speedup_vs_f32_path": t_f32 / t,
+                            f"recall_at_{k}": recall_gpu(r_i, exact, exact_kth, k)}
+            log(f"{name} shortlist {sl}: {t:.2f} ms, recall@{k} {out[str(sl)][f'recall_at_{k}']:.4f}")
+        return out, r_s, r_i
+
+    # FP8 E4M3 estimate
     Q8 = gem.quantize_fp8(Q)
     est = torch.empty(n_q, n_d, dtype=torch.float32, device=dev)
     sched["fp8"], _ = gem.autotune_dense(Q8, D8, reps=2, scores=est)
-
-    def fp8_path():
-        q8 = gem.quantize_fp8(Q)
-        gem.score_quant(q8, D8, scores=est)
-        _, short_i = gem.topk(est, sl)
-        C = gem.Cands(short_i.reshape(-1), stride=sl, n_lists=n_q)
-        return gem.score_exact(Q, D32, cands=C, compute="f32", k=k)
-
-    r8_s, r8_i = fp8_path()
-    torch.cuda.synchronize()
-    t_fp8_path = timed(fp8_path, max(1, args.steps))
     t_fp8_score = timed(lambda: gem.score_quant(Q8, D8, scores=est), max(1, args.steps))
-    fp8_rows = est[:max(1, args.cpu_sample)].clone()          # (later legs reuse est)
-    log(f"fp8 estimate + rerank path {t_fp8_path:.2f} ms (fp8 scoring {t_fp8_score:.2f} ms)")
+    fp8_sample = est[:max(1, args.cpu_sample)].clone()
+    fp8_sweep, r8_s, r8_i = sweep("fp8", lambda: gem.quantize_fp8(Q), lambda q8, sl: gem.score_quant(q8, D8, k=sl))
+    r8_s, r8_i = rerank(gem.score_quant(gem.quantize_fp8(Q), D8, k=1000)[1], 1000)
 
-    # MXFP4 estimate (E2M1 codes, a power-of-two scale per 32 dims) -> top-1000
-    # -> f32 rerank -> top-100: half the bytes and twice the MFMA rate of FP8
+    # MXFP4 estimate (E2M1 codes, a power-of-two scale per 32 dims)
     D4 = gem.quantize_mxfp4(D32)
     Q4 = gem.quantize_mxfp4(Q)
     sched["mxfp4"], _ = gem.autotune_dense(Q4, D4, reps=2, scores=est)
-
-    def mx_path():
-        q4 = gem.quantize_mxfp4(Q)
-        gem.score_quant(q4, D4, scores=est)
-        _, short_i = gem.topk(est, sl)
-        C = gem.Cands(short_i.reshape(-1), stride=sl, n_lists=n_q)
-        return gem.score_exact(Q, D32, cands=C, compute="f32", k=k)
-
-    r4_s, r4_i = mx_path()
-    torch.cuda.synchronize()
-    t_mx_path = timed(mx_path, max(1, args.steps))
     t_mx_score = timed(lambda: gem.score_quant(Q4, D4, scores=est), max(1, args.steps))
-    log(f"mxfp4 estimate + rerank path {t_mx_path:.2f} ms (mxfp4 scoring {t_mx_score:.2f} ms)")
+    mx_sweep, _, _ = sweep("mxfp4", lambda: gem.quantize_mxfp4(Q), lambda q4, sl: gem.score_quant(q4, D4, k=sl))
     del D4, Q4
 
     # qCH (Sec. 4.5): every vector replaced by its nearest centroid of the
-    # k-means codebook (Secs. 4.1, 4.2); estimate -> top-1000 -> f32 rerank
+    # k-means codebook (Secs. 4.1, 4.2); estimate -> shortlist -> f32 rerank
     log("qCH: k-means codebook and corpus codes")
     C, Dc, qch = build_codebook(D32, n_iter=8, assign="f32", seed=7)
-    qch_top = {}
     for cdt in ("bf16", "fp8"):
         Dcc = Dc.to_bf16() if cdt == "bf16" else Dc.to_fp8()
 
-        def qch_path(Dcc=Dcc, cdt=cdt):
+        def make_qc(cdt=cdt):
             Qc = gem.encode(Q, C, assign="f32")                        # NN(q) of every query vector
-            Qcc = Qc.to_bf16() if cdt == "bf16" else Qc.to_fp8()
-            if cdt == "bf16":
-                gem.score_exact(Qcc, Dcc, compute="bf16", scores=est)
-            else:
-                gem.score_quant(Qcc, Dcc, scores=est)
-            _, short_i = gem.topk(est, sl)
-            Cs = gem.Cands(short_i.reshape(-1), stride=sl, n_lists=n_q)
-            return gem.score_exact(Q, D32, cands=Cs, compute="f32", k=k)
+            return Qc.to_bf16() if cdt == "bf16" else Qc.to_fp8()
 
-        qch_top[cdt] = qch_path()
-        torch.cuda.synchronize()
-        t_path = timed(qch_path, max(1, args.steps // 2))
-        Qc = gem.encode(Q, C, assign="f32")
-        Qcc = Qc.to_bf16() if cdt == "bf16" else Qc.to_fp8()
-        t_enc_q = timed(lambda: gem.encode(Q, C, assign="f32"), max(1, args.steps // 2))
+        def score_k(Qcc, sl, cdt=cdt, Dcc=Dcc):
+            if cdt == "bf16":
+                return gem.score_exact(Qcc, Dcc, compute="bf16", k=sl)
+            return gem.score_quant(Qcc, Dcc, k=sl)
+
+        Qcc = make_qc()
         if cdt == "bf16":
             t_sc = timed(lambda: gem.score_exact(Qcc, Dcc, compute="bf16", scores=est), max(1, args.steps // 2))
         else:
             t_sc = timed(lambda: gem.score_quant(Qcc, Dcc, scores=est), max(1, args.steps // 2))
+        t_enc_q = timed(lambda: gem.encode(Q, C, assign="f32"), max(1, args.steps // 2))
+        sw, _, _ = sweep(f"qCH {cdt}", make_qc, score_k)
         peak = PEAK_BF16 if cdt == "bf16" else PEAK_FP8
-        qch[cdt] = {"path_ms": t_path, "query_encode_ms": t_enc_q, "score_ms": t_sc,
-                    "score_frac_of_peak": flops / (t_sc / 1e3) / peak,
-                    "pair_scores_per_s": pairs / (t_path / 1e3), "speedup_vs_f32_path": t_f32 / t_path}
-        log(f"qCH {cdt}: path {t_path:.2f} ms (query codes {t_enc_q:.2f}, scoring {t_sc:.2f})")
+        qch[cdt] = {"query_encode_ms": t_enc_q, "score_ms": t_sc, "score_frac_of_peak": flops / (t_sc / 1e3) / peak,
+                    "shortlist_sweep": sw}
     qch["corpus_code_bytes"] = D32.n_vecs * 4
     qch["codebook_bytes_bf16"] = qch["codebook_size"] * 256
-    qch["shortlist"] = sl
-    qch_q8 = qch_top
+    del C, Dc
 
-    # accuracy on a sample of queries against float64 exact scores (CPU oracle)
-    c_host = wl.SetBatch(c_dev.vecs.cpu(), c_dev.offsets.cpu())
-    q_host = wl.SetBatch(q_dev.vecs.cpu(), q_dev.offsets.cpu())
+    # accuracy: the f32 path against float64 (CPU oracle) on a sample, which
+    # also times the oracle; recall of every path over all queries against
+    # the f32 scores
     res = {}
     if not args.skip_cpu:
+        c_host = wl.SetBatch(c_dev.vecs.cpu(), c_dev.offsets.cpu())
+        q_host = wl.SetBatch(q_dev.vecs.cpu(), q_dev.offsets.cpu())
         ref, cpu = cpu_baseline(q_host, c_host, args.cpu_sample)
         ns = ref.shape[0]
         res["cpu_baseline"] = cpu
-        got16 = bf16_rows[:ns].double().cpu().numpy()
+        ex_np = exact[:ns].double().cpu().numpy()
+        t32 = top32_i[:ns].cpu().numpy()
+        matched = 0
+        for r in range(ns):
+            tau = 2e-4 * max(abs(np.sort(ref[r])[::-1][k - 1]), 1.0)
+            matched += int(oracle.tie_aware_match(t32[r], ref[r], k, tau)[0])
+        res["f32_exact_vs_float64"] = {
+            "queries": ns, "top100_match_outside_ties": f"{matched}/{ns}",
+            "max_rel_err_all_scores": float((np.abs(ex_np - ref) / np.maximum(np.abs(ref), 1)).max())}
+        got16 = bf16_sample[:ns].double().cpu().numpy()
         res["bf16_max_rel_err"] = float((np.abs(got16 - ref) / np.maximum(np.abs(ref), 1)).max())
-        res["recall_at_100_bf16"] = recall_vs_exact(top_i[:ns].cpu().numpy(), ref, k)
-        res["recall_at_100_f32"] = recall_vs_exact(top32_i[:ns].cpu().numpy(), ref, k)
-        res["recall_at_100_fp8_rerank"] = recall_vs_exact(r8_i[:ns].cpu().numpy(), ref, k)
-        res["recall_at_100_mxfp4_rerank"] = recall_vs_exact(r4_i[:ns].cpu().numpy(), ref, k)
-        for cdt, (_, qi) in qch_q8.items():
-            qch[cdt]["recall_at_100_rerank"] = recall_vs_exact(qi[:ns].cpu().numpy(), ref, k)
-        # exact-mode error: the f32 path's and the FP8 + rerank path's top-100
-        # scores against the float64 scores of the same documents
         for name, (ts_, ti_) in (("f32", (top32_s, top32_i)), ("fp8_rerank", (r8_s, r8_i))):
             ts_np, ti_np = ts_[:ns].double().cpu().numpy(), ti_[:ns].cpu().numpy()
             rr = np.take_along_axis(ref, ti_np, axis=1)
             res[f"{name}_top100_max_rel_err"] = float((np.abs(ts_np - rr) / np.maximum(np.abs(rr), 1)).max())
-        est_np = fp8_rows[:ns].double().cpu().numpy()
+        est_np = fp8_sample[:ns].double().cpu().numpy()
         res["fp8_estimate_rel_err_p50"] = float(np.median(np.abs(est_np - ref) / np.maximum(np.abs(ref), 1)))
-        res["recall_sample_queries"] = ns
+    res["recall_at_100_bf16"] = recall_gpu(top_i, exact, exact_kth, k)
+    res["recall_at_100_fp8_rerank"] = fp8_sweep.get("1000", {}).get(f"recall_at_{k}")
+    res["recall_at_100_mxfp4_rerank"] = mx_sweep.get("1000", {}).get(f"recall_at_{k}")
+    res["recall_queries"] = n_q
+    res["recall_reference"] = "float32 exact scores of every (query, document) pair, checked against float64"
     value = pairs / (ms_per_step / 1e3)
-    achieved = flops / (t_score / 1e3)
+    achieved = flops / (t_fused / 1e3)
     line = {
         "metric": "query-doc set scores/sec + recall@100 vs FP64 exact; p50/p99 query latency",
         "value": value,
@@ -440,36 +447,40 @@ def bench_exhaustive(args):
                    "doc_vectors": V, "query_vectors": q_rows, "k": k},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_BF16, "traffic": measured_traffic(),
-                     "kernel": "score_dense_kernel<bf16>", "kernel_ms": t_score,
+                     "kernel": "score_dense_kernel<bf16, fused top-k>", "kernel_ms": t_fused,
                      "flops_per_launch": flops, "traffic_unit": "HBM bytes per launch",
-                     "algorithmic_bytes_per_launch": V * 128 * 2 + q_rows * 128 * 2 + n_q * n_d * 4},
-        "stages_ms": {"query_convert": t_conv, "score_dense_bf16": t_score, "topk_100": t_topk},
+                     "algorithmic_bytes_per_launch": V * 128 * 2 + q_rows * 128 * 2 + n_q * k * 8},
+        "stages_ms": {"query_convert": t_conv, "score_dense_bf16_fused_top100": t_fused,
+                      "staged_score_dense_bf16": t_score, "staged_topk_100": t_topk},
+        "topk_workspace_bytes": {"fused": ws_fused, "staged": ws_staged},
         "dense_schedule": sched,
         "corpus_convert_ms": {"bf16": t_bf16, "fp8": t_fp8},
         "f32_exact_path": {"ms": t_f32, "pair_scores_per_s": pairs / (t_f32 / 1e3),
                            "tflops": flops / (t_f32 / 1e3) / 1e12,
                            "frac_of_fp32_matrix_peak": flops / (t_f32 / 1e3) / PEAK_FP32_MATRIX},
-        "fp8_rerank_path": {"ms": t_fp8_path, "pair_scores_per_s": pairs / (t_fp8_path / 1e3),
-                            "speedup_vs_f32_path": t_f32 / t_fp8_path, "shortlist": sl,
-                            "fp8_score_ms": t_fp8_score,
-                            "fp8_tflops": flops / (t_fp8_score / 1e3) / 1e12,
-                            "fp8_frac_of_peak": flops / (t_fp8_score / 1e3) / PEAK_FP8},
-        "mxfp4_rerank_path": {"ms": t_mx_path, "pair_scores_per_s": pairs / (t_mx_path / 1e3),
-                              "speedup_vs_f32_path": t_f32 / t_mx_path, "shortlist": sl,
-                              "mxfp4_score_ms": t_mx_score,
-                              "mxfp4_tflops": flops / (t_mx_score / 1e3) / 1e12,
-                              "mxfp4_frac_of_peak": flops / (t_mx_score / 1e3) / PEAK_FP4,
-                              "corpus_bytes": V * 68},
+        "fp8_rerank_path": dict(fp8_sweep.get("1000", {}), shortlist=1000, fp8_score_ms=t_fp8_score,
+                                fp8_tflops=flops / (t_fp8_score / 1e3) / 1e12,
+                                fp8_frac_of_peak=flops / (t_fp8_score / 1e3) / PEAK_FP8,
+                                shortlist_sweep=fp8_sweep),
+        "mxfp4_rerank_path": dict(mx_sweep.get("1000", {}), shortlist=1000, mxfp4_score_ms=t_mx_score,
+                                  mxfp4_tflops=flops / (t_mx_score / 1e3) / 1e12,
+                                  mxfp4_frac_of_peak=flops / (t_mx_score / 1e3) / PEAK_FP4,
+                                  corpus_bytes=V * 68, shortlist_sweep=mx_sweep),
         "qch_rerank_path": qch,
     }
     line.update(res)
     if "cpu_baseline" not in line:
         line["cpu_baseline"] = None
+    del exact, est, scores
     return line, (D8, D32)
 
 
-def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_chunks=8, rate_idx=0):
-    """Continuous-batching serving loop on the resident corpus: QPS and p50/p99 latency."""
+def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_chunks=8, rate_idx=0,
+                  max_resident=None):
+    """Continuous-batching serving loop on the resident corpus: QPS and p50/p99
+    latency. max_resident: a device-memory budget for that many requests'
+    state (None: half the free device memory); the slot count stays 1024, so
+    with a small budget it is the memory check that refuses requests."""
     from paper_2603_20336_amd import serve
     w5 = wl.WORKLOADS[5]
     q = wl.queries(w5, n_queries=n_req, query_len=q_len)
@@ -478,11 +489,12 @@ def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_
     vecs = q.vecs.numpy()
     reqs = [serve.Request(i, vecs[off[i]:off[i + 1]], float(arrivals[i])) for i in range(n_req)]
     ex = serve.DeviceExecutor(D8, D32, n_chunks=n_chunks, max_slots=1024, shortlist=w5.shortlist, k=w5.k)
+    budget = None if max_resident is None else int(max_resident) * ex.bytes_per_request
     # an iteration scores as many chunks as fit 8192 (query vectors x chunks)
     work = 8192
-    eng = serve.ServingEngine(ex, max_slots=1024, mem_budget_bytes=8 << 30, chunk_work=work)
+    eng = serve.ServingEngine(ex, max_slots=1024, mem_budget_bytes=budget, chunk_work=work)
     # warm-up on a few requests, then the measured run
-    warm = serve.ServingEngine(ex, max_slots=1024, mem_budget_bytes=8 << 30, chunk_work=work)
+    warm = serve.ServingEngine(ex, max_slots=1024, chunk_work=work)
     warm.run([serve.Request(-1 - i, r.vecs, r.t_arrival) for i, r in enumerate(reqs[:200])])
     torch.cuda.synchronize()
     done = eng.run(reqs)
@@ -490,6 +502,8 @@ def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_
     st.update({"rate_per_s": rate, "requests": n_req, "chunks": n_chunks, "chunk_work": work,
                "iterations": eng.iteration,
                "mean_active": eng.active_sum / max(1, eng.iteration),
+               "device_budget_bytes": eng.mem_budget, "bytes_per_request": ex.bytes_per_request,
+               "refused_for_memory": eng.refused_for_memory,
                "shortlist": w5.shortlist, "k": w5.k, "query_len": f"U{{{q_len[1]}..{q_len[2]}}}"})
     return st
 
@@ -516,6 +530,11 @@ def bench_expansion(args):
         pair_bytes += int(rows.sum().item()) * 132
         uniq = torch.unique(ids)
         uniq_bytes += int(lens[uniq.long()].sum().item()) * 132
+    # the autotuner picks the gathered scorer's schedule for this step shape
+    # (entries per wave, tiles in flight); every step has the same shape class
+    t_default = timed(lambda: gem.score_quant(Q8, D8, cands=steps[0]), 3)
+    gsched, t_tuned = gem.autotune_gather(Q8, D8, steps[0], reps=3)
+    log(f"expansion gather schedule {gsched}: {t_tuned:.3f} ms (library rule {t_default:.3f} ms)")
     eg = ExpansionGraph(Q8, D8, steps, ef=w4.ef)
     eg.capture()
     eg.replay()
@@ -530,7 +549,8 @@ def bench_expansion(args):
            "gbps_per_pair_bytes": pair_bytes / w4.steps / (per_step / 1e3) / 1e9,
            "gbps_unique_bytes": uniq_bytes / w4.steps / (per_step / 1e3) / 1e9,
            "frac_of_hbm_peak_per_pair": pair_bytes / w4.steps / (per_step / 1e3) / PEAK_HBM,
-           "rerank_f32_top100_ms": r_ms}
+           "rerank_f32_top100_ms": r_ms,
+           "gather_schedule": dict(gsched, tuned_ms=t_tuned, library_rule_ms=t_default)}
     # MXFP4 rows: 64 bytes of codes + 4 exponent bytes per vector
     D4 = gem.quantize_mxfp4(D32)
     Q4 = gem.quantize_mxfp4(Q32)
@@ -612,14 +632,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=2, choices=[2])
     ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU oracle leg and recall")
-    ap.add_argument("--cpu-sample", type=int, default=8, help="query sets in the CPU-oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=64,
+                    help="query sets in the CPU-oracle sample (float64 check of the f32 path, oracle timing)")
+    ap.add_argument("--shortlists", type=str, default="200,500,1000,2000",
+                    help="shortlist lengths of the estimate -> rerank sweep")
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--skip-expansion", action="store_true")
     ap.add_argument("--skip-graph", action="store_true", help="skip the graph-search leg (Alg. 5)")
     ap.add_argument("--only-graph", action="store_true", help="run the graph-search leg alone")
-    ap.add_argument("--serve-rates", type=str, default="1000,2000,4000,8000,16000",
+    ap.add_argument("--serve-rates", type=str, default="1000,2000,4000,8000,16000,32000",
                     help="comma-separated arrival rates (1/s)")
     ap.add_argument("--serve-requests", type=int, default=1500, help="minimum requests per rate")
+    ap.add_argument("--serve-max-requests", type=int, default=20000, help="maximum requests per rate")
+    ap.add_argument("--only-serving", action="store_true", help="run the serving leg alone (for profiling)")
+    ap.add_argument("--tune-cache", type=str, default=None,
+                    help="JSON tune cache: loaded before tuning and written with the schedules tuned here")
     ap.add_argument("--expand-docs", type=int, default=1_000_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB copy kernel (reference for the HBM byte counters)")
@@ -641,7 +668,15 @@ def main():
             copy_calibration()
         print(json.dumps({"beam_expansion": res}), flush=True)
         return
-    line, keep = bench_exhaustive(args)
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        gem.load_tune_cache(args.tune_cache)
+    if args.only_serving:
+        w2 = wl.WORKLOADS[2]
+        c_dev = wl.corpus(w2, device=torch.device("cuda:0"))
+        D32 = gem.Sets(c_dev.vecs, c_dev.offsets, "f32", c_dev.max_len())
+        line, keep = {}, (gem.quantize_fp8(D32), D32)
+    else:
+        line, keep = bench_exhaustive(args)
     if args.copy_calibration:
         copy_calibration()
     if not args.skip_serving:
@@ -649,9 +684,16 @@ def main():
         line["serving"] = []
         for ri, rate in enumerate([float(r) for r in args.serve_rates.split(",") if r]):
             log(f"serving at {rate:.0f} requests/s")
-            # about 1.5 s of arrivals per rate (at least --serve-requests)
-            n_req = max(args.serve_requests, int(rate * 1.5))
+            # about 1.25 s of arrivals per rate, within the request bounds
+            n_req = min(args.serve_max_requests, max(args.serve_requests, int(rate * 1.25)))
             line["serving"].append(bench_serving(D8, D32, rate=rate, n_req=n_req, rate_idx=ri))
+        if args.serve_rates:
+            # a device-memory budget for 256 requests' state at 16,000/s: the
+            # memory check, not the slot count, is what refuses requests
+            log("serving at 16000 requests/s with a device budget of 256 requests")
+            r = bench_serving(D8, D32, rate=16000.0, n_req=min(args.serve_max_requests, 20000), rate_idx=99,
+                              max_resident=256)
+            line["serving_memory_limited"] = r
         if line["serving"]:
             # headline latency: the 2000/s point if swept, else the first rate
             ref = next((r for r in line["serving"] if r["rate_per_s"] == 2000.0), line["serving"][0])
@@ -660,11 +702,17 @@ def main():
             line["serving_rate_for_p50_p99"] = ref["rate_per_s"]
     del keep
     torch.cuda.empty_cache()
+    if args.only_serving:
+        print(json.dumps(line), flush=True)
+        return
     if not args.skip_expansion:
         line["beam_expansion"] = bench_expansion(args)
         torch.cuda.empty_cache()
     if not args.skip_graph:
         line["graph_search"] = bench_graph_search()
+    if args.tune_cache:
+        gem.save_tune_cache(args.tune_cache)
+        line["tune_cache"] = args.tune_cache
     print(json.dumps(line), flush=True)
 
 

@@ -22,7 +22,9 @@
  * Conventions (all entry points):
  *   - Pointers marked [device] point to device memory on the context's device;
  *     the caller owns every buffer, including the workspace. The library never
- *     allocates device memory and never synchronizes the stream in these calls.
+ *     allocates device memory, and never synchronizes the stream except in the
+ *     validation calls, the autotuners, gem_check_status and in GEM_OPT_CHECK
+ *     mode.
  *   - Every call enqueues its kernels on `stream` (0 = the null stream) and
  *     returns once they are enqueued; results are ready when the stream reaches
  *     that point.
@@ -80,8 +82,9 @@ typedef enum {
 
 /* Largest query set (rows) a scoring call accepts. */
 #define GEM_MAX_QUERY_LEN 256
-/* Largest k (top-k) and ef (beam width). */
-#define GEM_MAX_K 1024
+/* Largest k of a top-k, and largest ef (beam width). */
+#define GEM_MAX_K 2048
+#define GEM_MAX_EF 1024
 /* Vector dimension. */
 #define GEM_DIM 128
 
@@ -169,15 +172,28 @@ const char* gem_version(void);
  *       each query keeps, per piece of the corpus, the documents that beat its
  *       running k-th best, and a merge takes the k best of those) when that
  *       needs less workspace than staging the [n_q][n_docs] scores, else staged.
- *     GEM_TOPK_FUSED: always fused (small batches then run the dense scorer
- *       instead of the streamed path).
+ *     GEM_TOPK_FUSED: always fused for k <= 1024 (small batches then run the
+ *       dense scorer instead of the streamed path).
  *     GEM_TOPK_STAGED: always staged, then gem_topk's kernel.
  *   Every mode returns the same top-k, bitwise. gem_workspace_bytes follows the
- *   option, so set it before sizing a workspace. */
-typedef enum { GEM_OPT_TOPK_FUSION = 0 } gem_option;
+ *   option, so set it before sizing a workspace.
+ *
+ *   GEM_OPT_CHECK (0 = off, the default; 1 = on): device-data checking. Every
+ *   scoring, expansion, search-start and EMD call first validates its device
+ *   inputs (the conditions gem_validate_sets / gem_validate_cands check, plus
+ *   finite float32 rows, and EMD pair indices inside their batches) and, if
+ *   any is violated, returns GEM_ERR_DEVICE_CHECK without computing anything.
+ *   The check synchronizes the stream; it is a debugging aid. The violations
+ *   are also counted for gem_check_status. */
+typedef enum { GEM_OPT_TOPK_FUSION = 0, GEM_OPT_CHECK = 1 } gem_option;
 typedef enum { GEM_TOPK_AUTO = 0, GEM_TOPK_FUSED = 1, GEM_TOPK_STAGED = 2 } gem_topk_mode;
 gem_status gem_set_option(gem_ctx ctx, int32_t option, int64_t value);
 gem_status gem_get_option(gem_ctx ctx, int32_t option, int64_t* value);
+/* Synchronizes `stream` and reports what happened since the last call:
+ * GEM_ERR_HIP if a kernel on the stream failed, GEM_ERR_DEVICE_CHECK if
+ * checked calls (GEM_OPT_CHECK) found invalid device values (the count is
+ * then cleared), else GEM_OK. */
+gem_status gem_check_status(gem_ctx ctx, hipStream_t stream);
 
 /* Workspace bytes that the matching call needs for these arguments (0 if none).
  * For GEM_OP_SCORE_*: `compute` is the gem_dtype the scoring runs in, and
@@ -265,7 +281,8 @@ gem_status gem_copy_rows(gem_ctx ctx, const void* src, const int64_t* src_idx, v
  *     the top-k is fused into the scorer or the scores are staged in ws
  *     (GEM_OPT_TOPK_FUSION); with C != NULL the entry scores are staged.
  *   k == 0: scores only.
- *   Limits: Q->max_set_len <= GEM_MAX_QUERY_LEN, k <= GEM_MAX_K.
+ *   Limits: Q->max_set_len <= GEM_MAX_QUERY_LEN, k <= GEM_MAX_K (the fused top-k
+ *   takes k <= 1024; a larger k is staged).
  */
 gem_status gem_score_exact(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C,
                            int32_t compute, int32_t k,
@@ -416,7 +433,7 @@ typedef struct {
 /* Start a batch: clears the visited and expanded maps, takes one entry per
  * cluster of each query's C_query (member floor(u * count / 2^32) of the
  * cluster, u = random_words[i * k2 + j], drawn by the caller), scores the
- * entries and makes them the beam (R of Alg. 5; ef <= GEM_MAX_K). Scores are
+ * entries and makes them the beam (R of Alg. 5; ef <= GEM_MAX_EF). Scores are
  * CH in D's dtype (the estimate for FP8 / MXFP4 sets, qCH for code sets); Q
  * must already be in D's dtype. */
 gem_status gem_search_begin(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_graph* G,

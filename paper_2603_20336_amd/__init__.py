@@ -27,7 +27,7 @@ __all__ = ["Sets", "Cands", "Beam", "GemError", "convert_bf16", "quantize_fp8", 
            "set_dense_schedule", "autotune_dense", "copy_rows", "nearest_centroid", "centroid_update",
            "kmeans", "encode", "codebook_size",
            "emd_sinkhorn", "set_topk_fusion", "topk_fusion", "score_workspace_bytes", "gather_schedule",
-           "set_gather_schedule", "autotune_gather", "save_tune_cache", "load_tune_cache"]
+           "set_check", "check_status", "set_gather_schedule", "autotune_gather", "save_tune_cache", "load_tune_cache"]
 
 _DTYPES = {"f32": GEM_F32, "bf16": GEM_BF16, "fp8": GEM_FP8_E4M3, "mxfp4": GEM_MXFP4,
            GEM_F32: GEM_F32, GEM_BF16: GEM_BF16, GEM_FP8_E4M3: GEM_FP8_E4M3, GEM_MXFP4: GEM_MXFP4}
@@ -266,6 +266,16 @@ def set_topk_fusion(mode: str, device="cuda") -> None:
     "auto" (fused into the scorer when that needs less workspace than staging
     the score rows), "fused" or "staged". Every mode gives the same result."""
     _abi.check(library().gem_set_option(_ctx(torch.device(device)), _abi.GEM_OPT_TOPK_FUSION, _TOPK_MODES[mode]))
+
+
+def set_check(on: bool, device="cuda") -> None:
+    """GEM_CHECK mode: every call validates its device inputs first (synchronizing)."""
+    _abi.check(library().gem_set_option(_ctx(torch.device(device)), _abi.GEM_OPT_CHECK, int(bool(on))))
+
+
+def check_status(stream=None, device="cuda") -> None:
+    """Synchronize the stream and raise GemError if a kernel failed or checked calls found bad data."""
+    _abi.check(library().gem_check_status(_ctx(torch.device(device)), _stream(stream)))
 
 
 def topk_fusion(device="cuda") -> str:

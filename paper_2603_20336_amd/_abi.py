@@ -18,11 +18,12 @@ GEM_OK, GEM_ERR_INVALID, GEM_ERR_WORKSPACE, GEM_ERR_UNSUPPORTED, GEM_ERR_HIP, GE
 GEM_F32, GEM_BF16, GEM_FP8_E4M3, GEM_MXFP4 = 0, 1, 2, 3
 GEM_OP_SCORE_EXACT, GEM_OP_SCORE_QUANT, GEM_OP_TOPK, GEM_OP_EXPAND = 0, 1, 2, 3
 GEM_OP_NEAREST_CENTROID, GEM_OP_CENTROID_UPDATE = 4, 5
-GEM_OPT_TOPK_FUSION = 0
+GEM_OPT_TOPK_FUSION, GEM_OPT_CHECK = 0, 1
 GEM_TOPK_AUTO, GEM_TOPK_FUSED, GEM_TOPK_STAGED = 0, 1, 2
 GEM_STATIC_SCRATCH_BYTES = 64 << 20
 GEM_MAX_QUERY_LEN = 256
-GEM_MAX_K = 1024
+GEM_MAX_K = 2048
+GEM_MAX_EF = 1024
 GEM_DIM = 128
 BEAM_MAX_ENTRIES = 4096
 
@@ -80,6 +81,7 @@ SIGNATURES = {
     "gem_workspace_bytes": (sz, [c_p, i32, P_SETS, P_SETS, P_CANDS, i32, i32, i32]),
     "gem_set_option": (i32, [c_p, i32, i64]),
     "gem_get_option": (i32, [c_p, i32, ctypes.POINTER(i64)]),
+    "gem_check_status": (i32, [c_p, c_p]),
     "gem_convert_bf16": (i32, [c_p, c_p, i64, i32, c_p, c_p]),
     "gem_quantize_fp8": (i32, [c_p, c_p, i64, i32, c_p, c_p, c_p]),
     "gem_quantize_mxfp4": (i32, [c_p, c_p, i64, i32, c_p, c_p, c_p]),

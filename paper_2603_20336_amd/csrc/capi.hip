@@ -28,6 +28,8 @@ struct gem_ctx_s {
   std::map<uint64_t, gem::GatherSchedule> gather;
   int32_t topk_mode = GEM_TOPK_AUTO;     // GEM_OPT_TOPK_FUSION
   void* scratch = nullptr;               // this device's copy of `scratch` (gem_score_quant_static)
+  bool check = false;                    // GEM_OPT_CHECK: validate device inputs before computing
+  unsigned long long check_bad = 0;      // violations since the last gem_check_status (under mu)
 };
 
 // Device memory that gem_score_quant_static uses as its workspace, for callers
@@ -138,6 +140,10 @@ CandsView cview(const gem_cands* C) {
 constexpr int64_t kRangeMaxQueries = 3;
 constexpr int64_t kRangeMaxQueriesFp8 = 1;
 
+// Largest k of the top-k fused into the dense scorer (a region holds the k best
+// plus as many free entries).
+constexpr int32_t kTopkFusedMaxK = 1024;
+
 bool range_call(const gem_sets* Q, int32_t compute) {
   return Q->n_sets <= (compute == GEM_FP8_E4M3 ? kRangeMaxQueriesFp8 : kRangeMaxQueries);
 }
@@ -177,7 +183,8 @@ ScoreLayout score_layout(const gem_sets* Q, const gem_sets* D, const gem_cands* 
       // the top-k fused into the dense scorer, unless staging the score rows
       // takes less memory (small batches; the streamed path always stages)
       const size_t staged = (size_t)Q->n_sets * (size_t)D->n_sets * 4;
-      if (topk_mode != GEM_TOPK_STAGED && D->n_sets > 0 && (topk_mode == GEM_TOPK_FUSED || !range_call(Q, compute))) {
+      if (topk_mode != GEM_TOPK_STAGED && D->n_sets > 0 && k <= kTopkFusedMaxK &&
+          (topk_mode == GEM_TOPK_FUSED || !range_call(Q, compute))) {
         const bool narrow = compute == GEM_FP8_E4M3 && L.block_rows <= 64 && !D->codes;
         const int64_t bg_min = std::max<int64_t>(1, (Q->n_vecs + 8LL * L.block_rows - 1) / (8LL * L.block_rows));
         topk_fuse_shape(k, D->n_sets, bg_min, (narrow ? 2 : 1) * slots_per_xcd, &L.tk_np, &L.tk_cap);
@@ -267,6 +274,13 @@ DenseSchedule lookup_dense(gem_ctx ctx, int32_t dtype, int64_t q_rows, int64_t n
   return default_dense_schedule(dtype, q_rows, n_docs, ctx->n_cu / 8);
 }
 
+// GEM_CHECK mode: validates the call's device inputs (offsets, scales, codes,
+// ids, finite float32 values) before anything is computed; returns
+// GEM_ERR_DEVICE_CHECK (and counts the violations for gem_check_status) when
+// they are bad. Synchronizes the stream; does nothing when the mode is off.
+gem_status device_check(gem_ctx ctx, const gem_sets* A, const gem_sets* B, const gem_cands* C, int64_t cand_sets,
+                        hipStream_t stream, const char* what);
+
 gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t compute,
                         int32_t k, float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,
                         int32_t* top_ids, void* ws, size_t ws_bytes, hipStream_t stream,
@@ -290,6 +304,7 @@ gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const
   if (ws_bytes < L.total) return fail(GEM_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.total);
   if (L.total > 0 && !ws) return fail(GEM_ERR_INVALID, "workspace is NULL");
   if (Q->n_sets == 0) return GEM_OK;
+  if ((st = device_check(ctx, Q, D, C, D->n_sets, stream, "scoring")) != GEM_OK) return st;
 
   gem_sets Qc;
   if ((st = convert_query(Q, compute, ws, L, &Qc, stream)) != GEM_OK) return st;
@@ -384,6 +399,19 @@ __global__ void validate_ids_kernel(const int32_t* ids, int64_t n, int64_t n_set
     if (ids[i] >= n_sets) atomicAdd(&g_validate_bad, 1ull);
 }
 
+// Indices that must lie in [0, hi).
+__global__ void validate_index_kernel(const int32_t* ids, int64_t n, int64_t hi) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    if (ids[i] < 0 || ids[i] >= hi) atomicAdd(&g_validate_bad, 1ull);
+}
+
+__global__ void validate_finite_kernel(const float* x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const uint32_t u = __float_as_uint(x[i]);
+    if ((u & 0x7f800000u) == 0x7f800000u) atomicAdd(&g_validate_bad, 1ull);
+  }
+}
+
 // E8M0 byte 0xFF is NaN: no block scale may use it.
 __global__ void validate_mx_exps_kernel(const uint32_t* w, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
@@ -407,6 +435,38 @@ gem_status run_validation(hipStream_t stream, const char* what) {
   if (e != hipSuccess) return hip_fail(e, "validation sync");
   if (bad) return fail(GEM_ERR_DEVICE_CHECK, "%s: %llu violations", what, bad);
   return GEM_OK;
+}
+
+unsigned blocks_for(int64_t n) { return capped_blocks(std::min<int64_t>((n + 255) / 256, 1 << 16), 256); }
+
+// The checks of a set batch, enqueued (the caller resets and reads the word).
+hipError_t launch_set_validation(const gem_sets* S, hipStream_t stream) {
+  if (S->n_sets > 0)
+    hipLaunchKernelGGL(validate_offsets_kernel, dim3(blocks_for(S->n_sets + 1)), dim3(256), 0, stream, S->offsets,
+                       S->n_sets, S->n_vecs);
+  const int64_t rows = vec_rows(S);
+  if (S->dtype == GEM_MXFP4 && rows > 0)
+    hipLaunchKernelGGL(validate_mx_exps_kernel, dim3(blocks_for(rows)), dim3(256), 0, stream,
+                       reinterpret_cast<const uint32_t*>(S->scales), rows);
+  if (S->dtype == GEM_FP8_E4M3 && rows > 0)
+    hipLaunchKernelGGL(validate_scales_kernel, dim3(blocks_for(rows)), dim3(256), 0, stream, S->scales, rows);
+  if (S->dtype == GEM_F32 && rows > 0)
+    hipLaunchKernelGGL(validate_finite_kernel, dim3(blocks_for(rows * GEM_DIM)), dim3(256), 0, stream,
+                       static_cast<const float*>(S->vecs), rows * GEM_DIM);
+  if (S->codes && S->n_vecs > 0)
+    hipLaunchKernelGGL(validate_codes_kernel, dim3(blocks_for(S->n_vecs)), dim3(256), 0, stream, S->codes, S->n_vecs,
+                       S->codebook_rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_cand_validation(const gem_cands* C, int64_t n_sets, hipStream_t stream) {
+  if (C->offsets && C->n_lists > 0)
+    hipLaunchKernelGGL(validate_offsets_kernel, dim3(blocks_for(C->n_lists + 1)), dim3(256), 0, stream, C->offsets,
+                       C->n_lists, C->n_entries);
+  if (C->n_entries > 0)
+    hipLaunchKernelGGL(validate_ids_kernel, dim3(blocks_for(C->n_entries)), dim3(256), 0, stream, C->ids,
+                       C->n_entries, n_sets);
+  return hipGetLastError();
 }
 
 gem_status reset_validation(hipStream_t stream) {
@@ -663,6 +723,53 @@ gem_status load_tune_cache(gem_ctx ctx, const char* path, bool missing_ok) {
   return GEM_OK;
 }
 
+// Reads back the violation count of the checks enqueued since the reset.
+gem_status read_validation(hipStream_t stream, unsigned long long* bad) {
+  hipError_t e = hipMemcpyFromSymbolAsync(bad, HIP_SYMBOL(g_validate_bad), sizeof(*bad), 0, hipMemcpyDeviceToHost,
+                                          stream);
+  if (e != hipSuccess) return hip_fail(e, "validation read-back");
+  e = hipStreamSynchronize(stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "validation sync");
+}
+
+gem_status device_check_extra(gem_ctx ctx, const gem_sets* A, const gem_sets* B, const gem_cands* C,
+                              int64_t cand_sets, const int32_t* idx, int64_t n_idx, int64_t idx_hi,
+                              const int32_t* idx2, int64_t n_idx2, int64_t idx2_hi, hipStream_t stream,
+                              const char* what) {
+  if (!ctx->check) return GEM_OK;
+  gem_status st = reset_validation(stream);
+  if (st != GEM_OK) return st;
+  hipError_t e = hipSuccess;
+  if (A) e = launch_set_validation(A, stream);
+  if (e == hipSuccess && B) e = launch_set_validation(B, stream);
+  if (e == hipSuccess && C) e = launch_cand_validation(C, cand_sets, stream);
+  if (e == hipSuccess && idx && n_idx > 0) {
+    hipLaunchKernelGGL(validate_index_kernel, dim3(blocks_for(n_idx)), dim3(256), 0, stream, idx, n_idx, idx_hi);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && idx2 && n_idx2 > 0) {
+    hipLaunchKernelGGL(validate_index_kernel, dim3(blocks_for(n_idx2)), dim3(256), 0, stream, idx2, n_idx2, idx2_hi);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return hip_fail(e, "validation launch");
+  unsigned long long bad = 0;
+  if ((st = read_validation(stream, &bad)) != GEM_OK) return st;
+  if (bad) {
+    {
+      std::lock_guard<std::mutex> g(ctx->mu);
+      ctx->check_bad += bad;
+    }
+    return fail(GEM_ERR_DEVICE_CHECK, "%s: %llu invalid device values (GEM_OPT_CHECK); nothing was computed", what,
+                bad);
+  }
+  return GEM_OK;
+}
+
+gem_status device_check(gem_ctx ctx, const gem_sets* A, const gem_sets* B, const gem_cands* C, int64_t cand_sets,
+                        hipStream_t stream, const char* what) {
+  return device_check_extra(ctx, A, B, C, cand_sets, nullptr, 0, 0, nullptr, 0, 0, stream, what);
+}
+
 }  // namespace
 
 extern "C" {
@@ -739,15 +846,34 @@ gem_status gem_set_option(gem_ctx ctx, int32_t option, int64_t value) {
         return fail(GEM_ERR_INVALID, "top-k fusion mode %lld", (long long)value);
       ctx->topk_mode = (int32_t)value;
       return GEM_OK;
+    case GEM_OPT_CHECK:
+      if (value != 0 && value != 1) return fail(GEM_ERR_INVALID, "check mode %lld", (long long)value);
+      ctx->check = value != 0;
+      return GEM_OK;
     default:
       return fail(GEM_ERR_INVALID, "unknown option %d", option);
   }
+}
+
+gem_status gem_check_status(gem_ctx ctx, hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  const hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "stream");
+  unsigned long long bad;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    bad = ctx->check_bad;
+    ctx->check_bad = 0;
+  }
+  if (bad) return fail(GEM_ERR_DEVICE_CHECK, "%llu invalid device values in checked calls since the last check", bad);
+  return GEM_OK;
 }
 
 gem_status gem_get_option(gem_ctx ctx, int32_t option, int64_t* value) {
   if (!ctx || !value) return fail(GEM_ERR_INVALID, "NULL argument");
   switch (option) {
     case GEM_OPT_TOPK_FUSION: *value = ctx->topk_mode; return GEM_OK;
+    case GEM_OPT_CHECK: *value = ctx->check ? 1 : 0; return GEM_OK;
     default: return fail(GEM_ERR_INVALID, "unknown option %d", option);
   }
 }
@@ -935,7 +1061,7 @@ gem_status gem_expand_batch(gem_ctx ctx, const gem_sets* Q8, const gem_sets* D8,
   if (!C) return fail(GEM_ERR_INVALID, "cands is NULL");
   if ((st = check_cands(C, Q8->n_sets)) != GEM_OK) return st;
   if (!beam) return fail(GEM_ERR_INVALID, "beam is NULL");
-  if (beam->ef < 1 || beam->ef > GEM_MAX_K) return fail(GEM_ERR_INVALID, "ef = %d outside [1, %d]", beam->ef, GEM_MAX_K);
+  if (beam->ef < 1 || beam->ef > GEM_MAX_EF) return fail(GEM_ERR_INVALID, "ef = %d outside [1, %d]", beam->ef, GEM_MAX_EF);
   if (Q8->n_sets > 0 && (!beam->scores || !beam->ids)) return fail(GEM_ERR_INVALID, "beam buffers are NULL");
   if ((int64_t)beam->ef + list_len_bound(C) > kBeamMaxEntries)
     return fail(GEM_ERR_UNSUPPORTED, "ef + longest list = %d exceeds %d", beam->ef + list_len_bound(C), kBeamMaxEntries);
@@ -943,6 +1069,7 @@ gem_status gem_expand_batch(gem_ctx ctx, const gem_sets* Q8, const gem_sets* D8,
   if (ws_bytes < L.total) return fail(GEM_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.total);
   if (L.total > 0 && !ws) return fail(GEM_ERR_INVALID, "workspace is NULL");
   if (Q8->n_sets == 0) return GEM_OK;
+  if ((st = device_check(ctx, Q8, D8, C, D8->n_sets, stream, "expansion")) != GEM_OK) return st;
   gem_sets Qc;
   if ((st = convert_query(Q8, cd, ws, L, &Qc, stream)) != GEM_OK) return st;
   float* es = cand_scores ? cand_scores : reinterpret_cast<float*>(at(ws, L.staged));
@@ -973,6 +1100,9 @@ gem_status gem_emd_sinkhorn(gem_ctx ctx, const gem_sets* A, const gem_sets* B, c
   if (n_pairs > 0 && (!a_idx || !b_idx || !out)) return fail(GEM_ERR_INVALID, "NULL buffer");
   const size_t need = emd_ws_bytes(n_pairs);
   if (n_pairs > 0 && (ws_bytes < need || !ws)) return fail(GEM_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+  if ((st = device_check_extra(ctx, A, B, nullptr, 0, a_idx, n_pairs, A->n_sets, b_idx, n_pairs, B->n_sets, stream,
+                               "emd")) != GEM_OK)
+    return st;
   EmdParams P;
   P.A = view(A); P.B = view(B); P.a_idx = a_idx; P.b_idx = b_idx; P.n_pairs = n_pairs;
   P.eps = eps; P.n_iter = n_iter; P.out = out;
@@ -1023,7 +1153,7 @@ gem_status check_search(const gem_sets* Q, const gem_sets* D, const gem_graph* G
   if (G->k2 < 1 || G->k2 > kMaxSearchClusters) return fail(GEM_ERR_UNSUPPORTED, "k2 = %d", G->k2);
   if (G->degree < 1 || G->degree > 64) return fail(GEM_ERR_UNSUPPORTED, "degree = %d outside [1, 64]", G->degree);
   if (S->width < 1 || S->width > 64) return fail(GEM_ERR_UNSUPPORTED, "width = %d outside [1, 64]", S->width);
-  if (beam->ef < 1 || beam->ef > GEM_MAX_K) return fail(GEM_ERR_INVALID, "ef = %d outside [1, %d]", beam->ef, GEM_MAX_K);
+  if (beam->ef < 1 || beam->ef > GEM_MAX_EF) return fail(GEM_ERR_INVALID, "ef = %d outside [1, %d]", beam->ef, GEM_MAX_EF);
   *row = std::max(G->k2, S->width * G->degree);
   if ((int64_t)beam->ef + *row > kBeamMaxEntries)
     return fail(GEM_ERR_UNSUPPORTED, "ef + candidate row = %d exceeds %d", beam->ef + *row, kBeamMaxEntries);
@@ -1061,6 +1191,13 @@ gem_status gem_search_begin(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, c
   if (st != GEM_OK) return st;
   if (Q->n_sets > 0 && !random_words) return fail(GEM_ERR_INVALID, "random_words is NULL");
   if (Q->n_sets == 0) return GEM_OK;
+  {
+    // GEM_CHECK mode: the sets and the graph's neighbour lists (ids < n_sets, -1 padding)
+    gem_cands nb{};
+    nb.n_lists = G->n_sets; nb.n_entries = G->n_sets * (int64_t)G->degree; nb.stride = G->degree;
+    nb.max_list_len = G->degree; nb.offsets = nullptr; nb.ids = G->neighbors;
+    if ((st = device_check(ctx, Q, D, &nb, G->n_sets, stream, "search")) != GEM_OK) return st;
+  }
   hipError_t e = launch_search_clear(v, Q->n_sets, stream);
   if (e == hipSuccess) e = launch_search_entries(v, Q->n_sets, random_words, S->cand_ids, row, stream);
   if (e == hipSuccess) e = launch_beam_reset(beam->scores, beam->ids, Q->n_sets * (int64_t)beam->ef, stream);
@@ -1086,7 +1223,7 @@ gem_status gem_beam_merge(gem_ctx ctx, const float* cand_scores, const gem_cands
   if (!ctx || !C || !beam) return fail(GEM_ERR_INVALID, "NULL argument");
   gem_status st = check_cands(C, C->n_lists);
   if (st != GEM_OK) return st;
-  if (beam->ef < 1 || beam->ef > GEM_MAX_K) return fail(GEM_ERR_INVALID, "ef = %d outside [1, %d]", beam->ef, GEM_MAX_K);
+  if (beam->ef < 1 || beam->ef > GEM_MAX_EF) return fail(GEM_ERR_INVALID, "ef = %d outside [1, %d]", beam->ef, GEM_MAX_EF);
   if (C->n_lists > 0 && (!beam->scores || !beam->ids)) return fail(GEM_ERR_INVALID, "beam buffers are NULL");
   if (C->n_entries > 0 && !cand_scores) return fail(GEM_ERR_INVALID, "cand_scores is NULL");
   if ((int64_t)beam->ef + list_len_bound(C) > kBeamMaxEntries)
@@ -1098,7 +1235,7 @@ gem_status gem_beam_merge(gem_ctx ctx, const float* cand_scores, const gem_cands
 
 gem_status gem_beam_reset(gem_ctx ctx, gem_beam* beam, int64_t n_queries, hipStream_t stream) {
   if (!ctx || !beam) return fail(GEM_ERR_INVALID, "NULL argument");
-  if (beam->ef < 1 || beam->ef > GEM_MAX_K) return fail(GEM_ERR_INVALID, "ef = %d outside [1, %d]", beam->ef, GEM_MAX_K);
+  if (beam->ef < 1 || beam->ef > GEM_MAX_EF) return fail(GEM_ERR_INVALID, "ef = %d outside [1, %d]", beam->ef, GEM_MAX_EF);
   if (n_queries < 0) return fail(GEM_ERR_INVALID, "negative n_queries");
   if (n_queries > 0 && (!beam->scores || !beam->ids)) return fail(GEM_ERR_INVALID, "beam buffers are NULL");
   hipError_t e = launch_beam_reset(beam->scores, beam->ids, n_queries * (int64_t)beam->ef, stream);
@@ -1110,24 +1247,7 @@ gem_status gem_validate_sets(gem_ctx ctx, const gem_sets* S, hipStream_t stream)
   gem_status st = check_sets(S, "sets", false);
   if (st != GEM_OK) return st;
   if ((st = reset_validation(stream)) != GEM_OK) return st;
-  if (S->n_sets > 0) {
-    hipLaunchKernelGGL(validate_offsets_kernel, dim3(capped_blocks((S->n_sets + 1 + 255) / 256, 256)), dim3(256), 0, stream,
-                       S->offsets, S->n_sets, S->n_vecs);
-  }
-  const int64_t rows = vec_rows(S);
-  if (S->dtype == GEM_MXFP4 && rows > 0) {
-    hipLaunchKernelGGL(validate_mx_exps_kernel, dim3(capped_blocks((rows + 255) / 256, 256)), dim3(256), 0, stream,
-                       reinterpret_cast<const uint32_t*>(S->scales), rows);
-  }
-  if (S->dtype == GEM_FP8_E4M3 && rows > 0) {
-    hipLaunchKernelGGL(validate_scales_kernel, dim3(capped_blocks((rows + 255) / 256, 256)), dim3(256), 0, stream,
-                       S->scales, rows);
-  }
-  if (S->codes && S->n_vecs > 0) {
-    hipLaunchKernelGGL(validate_codes_kernel, dim3(capped_blocks((S->n_vecs + 255) / 256, 256)), dim3(256), 0, stream,
-                       S->codes, S->n_vecs, S->codebook_rows);
-  }
-  hipError_t e = hipGetLastError();
+  const hipError_t e = launch_set_validation(S, stream);
   if (e != hipSuccess) return hip_fail(e, "validation launch");
   return run_validation(stream, "sets");
 }
@@ -1137,15 +1257,7 @@ gem_status gem_validate_cands(gem_ctx ctx, const gem_cands* C, int64_t n_sets, h
   gem_status st = check_cands(C, C->n_lists);
   if (st != GEM_OK) return st;
   if ((st = reset_validation(stream)) != GEM_OK) return st;
-  if (C->offsets && C->n_lists > 0) {
-    hipLaunchKernelGGL(validate_offsets_kernel, dim3(capped_blocks((C->n_lists + 1 + 255) / 256, 256)), dim3(256), 0, stream,
-                       C->offsets, C->n_lists, C->n_entries);
-  }
-  if (C->n_entries > 0) {
-    hipLaunchKernelGGL(validate_ids_kernel, dim3(capped_blocks((C->n_entries + 255) / 256, 256)), dim3(256), 0, stream,
-                       C->ids, C->n_entries, n_sets);
-  }
-  hipError_t e = hipGetLastError();
+  const hipError_t e = launch_cand_validation(C, n_sets, stream);
   if (e != hipSuccess) return hip_fail(e, "validation launch");
   return run_validation(stream, "cands");
 }

@@ -1029,7 +1029,7 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
   const dim3 grid((unsigned)(8 * sched.slots_per_xcd)), blk(kDenseThreads);
   const bool codes = D.codes != nullptr;
   if (out.tk.k > 0) {
-    if (out.tk.np < 1 || out.tk.cap < 64 || (out.tk.cap & 63) || out.tk.cap > kTkMaxCap || out.tk.k > GEM_MAX_K ||
+    if (out.tk.np < 1 || out.tk.cap < 64 || (out.tk.cap & 63) || out.tk.cap > kTkMaxCap || 2 * out.tk.k > kTkMaxCap ||
         !out.tk.keys || !out.tk.cnt || !out.tk.gthr)
       return hipErrorInvalidValue;
     launch_dense_variant<true>(dtype, codes, block_rows, grid, blk, P, s);

@@ -92,17 +92,22 @@ class Executor:
 class ServingEngine:
     """Admission, round-robin chunk schedule and completion bookkeeping."""
 
-    def __init__(self, executor: Executor, max_slots: int, mem_budget_bytes: int,
+    def __init__(self, executor: Executor, max_slots: int, mem_budget_bytes: Optional[int] = None,
                  clock: Optional[Callable[[], float]] = None, chunk_work: int = 0):
-        """chunk_work: if > 0, an iteration scores as many consecutive chunks as
+        """mem_budget_bytes: device memory for request state (None: the
+        executor's own budget, `device_budget`, which it derives from the
+        device's free memory). A request is admitted only while the state of
+        the active requests plus its own fits the budget.
+
+        chunk_work: if > 0, an iteration scores as many consecutive chunks as
         fit chunk_work (query vectors x chunks) for the active batch, at least
         one: a light batch then takes the corpus in fewer, fuller iterations
         (less per-iteration host time in each request's latency), a heavy one
         keeps one chunk per iteration. 0: always one chunk."""
         self.ex = executor
         self.chunk_work = int(chunk_work)
-        self.max_slots = int(max_slots)
-        self.mem_budget = int(mem_budget_bytes)
+        self.max_slots = min(int(max_slots), int(getattr(executor, "max_slots", max_slots)))
+        self.mem_budget = int(mem_budget_bytes if mem_budget_bytes is not None else executor.device_budget)
         self._t0 = None
         self._clock = clock
         self.waiting: deque = deque()
@@ -252,11 +257,19 @@ class DeviceExecutor(Executor):
     Each slot holds one request's query vectors on the device (float32 for the
     rerank, FP8 codes and scales for the estimate), written once at admission.
     max_ahead: iterations the host may issue before the device has finished
-    the oldest of them (1 keeps a new request behind at most one iteration).
+    the oldest of them (1 keeps a new request behind at most one iteration;
+    at most the result ring's length minus 2).
+    mem_budget_bytes: device memory for request state; None takes half of
+    the device's free memory at construction. The slots (and their score
+    rows) are sized to it: at most budget // bytes_per_request requests are
+    resident, and the engine admits by the same budget.
     """
 
+    RESULT_RING = 16
+
     def __init__(self, D8, D32, n_chunks: int, max_slots: int, shortlist: int = 1000, k: int = 100,
-                 max_query_len: int = 64, stream=None, copy_stream: bool = False, max_ahead: int = 1):
+                 max_query_len: int = 64, stream=None, copy_stream: bool = False, max_ahead: int = 1,
+                 mem_budget_bytes: Optional[int] = None):
         import importlib
         self._gem = importlib.import_module(__package__)
         self.D8, self.D32 = D8, D32
@@ -266,12 +279,21 @@ class DeviceExecutor(Executor):
         self.bounds = [int(b) for b in bounds]
         self.shortlist, self.k = int(shortlist), int(k)
         self.L = int(max_query_len)
-        self.max_slots = int(max_slots)
         self.max_ahead = max(1, int(max_ahead))
+        if self.max_ahead > self.RESULT_RING - 2:
+            raise ValueError(f"max_ahead {max_ahead} exceeds {self.RESULT_RING - 2} (the result ring's length - 2)")
         self.device = D8.device
         self.stream = stream
-        self.est = torch.empty(max_slots, self.n_docs, dtype=torch.float32, device=self.device)
+        # device state per request: its estimate row, its query slot (float32
+        # and FP8 rows) and its shortlist
         self.bytes_per_request = self.n_docs * 4 + max_query_len * 128 * 9 + shortlist * 8
+        if mem_budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            mem_budget_bytes = free // 2
+        self.device_budget = int(mem_budget_bytes)
+        self.max_slots = max(1, min(int(max_slots), self.device_budget // self.bytes_per_request))
+        max_slots = self.max_slots
+        self.est = torch.empty(max_slots, self.n_docs, dtype=torch.float32, device=self.device)
         # slot storage: slot s owns rows [s L, s L + len)
         n_rows = self.max_slots * self.L
         self.q32 = torch.zeros(n_rows, 128, dtype=torch.float32, device=self.device)
@@ -298,10 +320,11 @@ class DeviceExecutor(Executor):
         self._ring_evt = {k: [None] * len(v) for k, v in self._rings.items()}
         self._ring_at = {"v": 0, "i": 0}
         self._copy = torch.cuda.Stream(device=self.device) if copy_stream else None
-        # ring of pinned result buffers for finished requests
+        # ring of pinned result buffers for finished requests: entry j holds
+        # [device copy event, results read by the host]
         self._ring = [(torch.empty(self.max_slots, self.k, dtype=torch.float32).pin_memory(),
-                       torch.empty(self.max_slots, self.k, dtype=torch.int32).pin_memory(), [None])
-                      for _ in range(16)]
+                       torch.empty(self.max_slots, self.k, dtype=torch.int32).pin_memory(), [None, True])
+                      for _ in range(self.RESULT_RING)]
         self._ring_pos = 0
         self._off2 = torch.zeros(2, dtype=torch.int64, device=self.device)
         self._iter_evts = []
@@ -378,13 +401,17 @@ class DeviceExecutor(Executor):
         off = np.zeros(n + 1, np.int64)
         off[1:] = np.cumsum(lens)
         hi, ji = self._stage("i")
+        # one upload: row indices and offsets (int64), then the slots as int32
+        # (the row map of the scores), packed two to an int64 word
         st = hi.numpy()
         st[:idx.size] = idx
         st[idx.size:idx.size + n + 1] = off
-        st[idx.size + n + 1:idx.size + 2 * n + 1] = slots
-        dev = self._upload(hi[:idx.size + 2 * n + 1], "i", ji)
+        n_w = (n + 1) // 2
+        st[idx.size + n + 1:idx.size + n + 1 + n_w].view(np.int32)[:n] = slots
+        dev = self._upload(hi[:idx.size + n + 1 + n_w], "i", ji)
         with torch.cuda.stream(self._stream()):
-            ri, o, rows = dev[:idx.size], dev[idx.size:idx.size + n + 1], dev[idx.size + n + 1:]
+            ri, o = dev[:idx.size], dev[idx.size:idx.size + n + 1]
+            rows32 = dev[idx.size + n + 1:].view(torch.int32)[:n]
             mx = int(lens.max()) if n else 0
             r = idx.size
             cs = self._stream()
@@ -395,7 +422,6 @@ class DeviceExecutor(Executor):
             else:
                 g.copy_rows(self.q32, self.pk32, src_idx=ri, n=r, stream=cs)
                 S = g.Sets(self.pk32[:r], o, "f32", mx)
-            rows32 = rows.to(torch.int32)
         return S, rows32
 
     def set_batch(self, slots, queries):
@@ -435,8 +461,12 @@ class DeviceExecutor(Executor):
             ts, ti = g.score_exact(Q, self.D32, cands=C, compute="f32", k=self.k, stream=self.stream)
             hs_full, hi_full, slot_evt = self._ring[self._ring_pos]
             self._ring_pos = (self._ring_pos + 1) % len(self._ring)
+            if not slot_evt[1]:
+                # (max_ahead < ring length - 1 keeps every pending result's
+                # buffer out of reach; this guards that bound)
+                raise RuntimeError("result ring overrun: a finished batch's results were not read yet")
             if slot_evt[0] is not None:
-                slot_evt[0].synchronize()                       # the buffer's previous results were read
+                slot_evt[0].synchronize()                       # the buffer's previous device copy is done
             n = len(slots)
             hs, hi = hs_full[:n], hi_full[:n]
             hs.copy_(ts, non_blocking=True)
@@ -444,7 +474,8 @@ class DeviceExecutor(Executor):
             evt = torch.cuda.Event()
             evt.record(self._stream())
             slot_evt[0] = evt
-        return (evt, hs, hi, ts, ti)
+            slot_evt[1] = False
+        return (evt, hs, hi, ts, ti, slot_evt)
 
     def ready(self, handle) -> bool:
         return handle[0].query()
@@ -452,7 +483,9 @@ class DeviceExecutor(Executor):
     def results(self, handle):
         evt, hs, hi = handle[0], handle[1], handle[2]
         evt.synchronize()
-        return hs.numpy().copy(), hi.numpy().copy()
+        out = hs.numpy().copy(), hi.numpy().copy()
+        handle[5][1] = True                                     # the ring entry may be reused
+        return out
 
     def finish(self, slots, queries):
         h = self.finish_async(slots, queries)

@@ -436,7 +436,7 @@ def test_topk_bitwise(mode):
     s_np, off_np = s.numpy(), off.numpy()
     rng = np.random.default_rng(6)
     ids = rng.integers(-1, 5000, s_np.size).astype(np.int32)        # repeats and padding ids
-    for k in (1, 10, 100, 1000, 1024):
+    for k in (1, 10, 100, 1000, 1024, 2048):
         if mode == "rows":
             n, L = 12, 7000
             mat = np.random.default_rng(7).standard_normal((n, L)).astype(np.float32)
@@ -642,7 +642,7 @@ def test_error_paths_enqueue_nothing():
         gem.score_exact(q, c.to_bf16(), compute="f32")            # D dtype != compute
     assert e.value.status == gem._abi.GEM_ERR_INVALID
     with pytest.raises(gem.GemError) as e:
-        gem.score_exact(q, c, k=2000)                              # k > GEM_MAX_K
+        gem.score_exact(q, c, k=4096)                              # k > GEM_MAX_K
     assert e.value.status == gem._abi.GEM_ERR_INVALID
     big = gem.Sets.from_batch(_ragged([300], 52), DEV)
     with pytest.raises(gem.GemError) as e:
