@@ -475,8 +475,57 @@ def bench_exhaustive(args):
     return line, (D8, D32)
 
 
+def bench_dense_only(args):
+    """The dense scorers alone, for counter runs: the bf16 step (fused top-100,
+    then staged), and FP8 and MXFP4 exhaustive scoring into a score matrix."""
+    dev = torch.device("cuda:0")
+    w2 = wl.WORKLOADS[2]
+    c_dev, q_dev = wl.corpus(w2, device=dev), wl.queries(w2, device=dev)
+    Q = gem.Sets(q_dev.vecs, q_dev.offsets, "f32", q_dev.max_len())
+    D32 = gem.Sets(c_dev.vecs, c_dev.offsets, "f32", c_dev.max_len())
+    D16, D8, D4 = gem.convert_bf16(D32), gem.quantize_fp8(D32), gem.quantize_mxfp4(D32)
+    Q16, Q8, Q4 = gem.convert_bf16(Q), gem.quantize_fp8(Q), gem.quantize_mxfp4(Q)
+    scores = torch.empty(Q.n_sets, D32.n_sets, dtype=torch.float32, device=dev)
+    flops = 2.0 * 128 * Q.n_vecs * D32.n_vecs
+    out = {}
+    for name, QQ, DD, peak in (("bf16", Q16, D16, PEAK_BF16), ("fp8", Q8, D8, PEAK_FP8), ("mxfp4", Q4, D4, PEAK_FP4)):
+        sched, _ = gem.autotune_dense(QQ, DD, reps=2, scores=scores)
+        if name == "bf16":
+            t_f = timed(lambda: gem.score_exact(QQ, DD, compute="bf16", k=100), max(1, args.steps))
+            out["bf16_fused_top100_ms"] = t_f
+            t = timed(lambda: gem.score_exact(QQ, DD, compute="bf16", scores=scores), max(1, args.steps))
+        else:
+            t = timed(lambda: gem.score_quant(QQ, DD, scores=scores), max(1, args.steps))
+        out[name] = {"schedule": sched, "ms": t, "frac_of_peak": flops / (t / 1e3) / peak}
+        log(f"dense {name}: {t:.2f} ms ({out[name]['frac_of_peak']:.3f} of peak)")
+    return out
+
+
+def serving_shortlist_recall(D8, D32, shortlists, n_q=1000, q_len=("uniform", 4, 64)):
+    """Recall@k of the serving path (FP8 estimate -> top-s shortlist -> float32
+    rerank -> top-k) against exact float32 scores, on queries of the serving
+    mix, for each shortlist length s."""
+    w5 = wl.WORKLOADS[5]
+    k = w5.k
+    q = wl.queries(w5, n_queries=n_q, query_len=q_len)
+    Q32 = gem.Sets.from_batch(q, D32.device)
+    Q8 = gem.quantize_fp8(Q32)
+    exact = torch.empty(n_q, D32.n_sets, dtype=torch.float32, device=D32.device)
+    gem.score_exact(Q32, D32, compute="f32", scores=exact)
+    top_s, _ = gem.topk(exact, k)
+    exact_kth = top_s[:, k - 1].clone()
+    out = {}
+    for sl in shortlists:
+        _, short_i = gem.score_quant(Q8, D8, k=sl)
+        C = gem.Cands(short_i.reshape(-1), stride=sl, n_lists=n_q)
+        _, r_i = gem.score_exact(Q32, D32, cands=C, compute="f32", k=k)
+        out[str(sl)] = recall_gpu(r_i, exact, exact_kth, k)
+        log(f"serving mix: FP8 shortlist {sl} -> recall@{k} {out[str(sl)]:.5f}")
+    return {"queries": n_q, "query_len": f"U{{{q_len[1]}..{q_len[2]}}}", f"recall_at_{k}": out}
+
+
 def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_chunks=8, rate_idx=0,
-                  max_resident=None):
+                  max_resident=None, shortlist=None):
     """Continuous-batching serving loop on the resident corpus: QPS and p50/p99
     latency. max_resident: a device-memory budget for that many requests'
     state (None: half the free device memory); the slot count stays 1024, so
@@ -488,7 +537,8 @@ def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_
     off = q.offsets.numpy()
     vecs = q.vecs.numpy()
     reqs = [serve.Request(i, vecs[off[i]:off[i + 1]], float(arrivals[i])) for i in range(n_req)]
-    ex = serve.DeviceExecutor(D8, D32, n_chunks=n_chunks, max_slots=1024, shortlist=w5.shortlist, k=w5.k)
+    shortlist = w5.shortlist if shortlist is None else int(shortlist)
+    ex = serve.DeviceExecutor(D8, D32, n_chunks=n_chunks, max_slots=1024, shortlist=shortlist, k=w5.k)
     budget = None if max_resident is None else int(max_resident) * ex.bytes_per_request
     # an iteration scores as many chunks as fit 8192 (query vectors x chunks)
     work = 8192
@@ -504,7 +554,7 @@ def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_
                "mean_active": eng.active_sum / max(1, eng.iteration),
                "device_budget_bytes": eng.mem_budget, "bytes_per_request": ex.bytes_per_request,
                "refused_for_memory": eng.refused_for_memory,
-               "shortlist": w5.shortlist, "k": w5.k, "query_len": f"U{{{q_len[1]}..{q_len[2]}}}"})
+               "shortlist": shortlist, "k": w5.k, "query_len": f"U{{{q_len[1]}..{q_len[2]}}}"})
     return st
 
 
@@ -644,7 +694,13 @@ def main():
                     help="comma-separated arrival rates (1/s)")
     ap.add_argument("--serve-requests", type=int, default=1500, help="minimum requests per rate")
     ap.add_argument("--serve-max-requests", type=int, default=20000, help="maximum requests per rate")
+    ap.add_argument("--serve-shortlist", type=int, default=None,
+                    help="FP8 shortlist reranked per serving request (default: the serving workload's)")
+    ap.add_argument("--serve-shortlists", type=str, default="100,200,300,500,1000",
+                    help="shortlist lengths whose recall is measured on the serving query mix")
     ap.add_argument("--only-serving", action="store_true", help="run the serving leg alone (for profiling)")
+    ap.add_argument("--dense-only", action="store_true",
+                    help="run the bf16 / FP8 / MXFP4 dense scorers alone (for counter runs)")
     ap.add_argument("--tune-cache", type=str, default=None,
                     help="JSON tune cache: loaded before tuning and written with the schedules tuned here")
     ap.add_argument("--expand-docs", type=int, default=1_000_000)
@@ -670,6 +726,12 @@ def main():
         return
     if args.tune_cache and os.path.exists(args.tune_cache):
         gem.load_tune_cache(args.tune_cache)
+    if args.dense_only:
+        res = bench_dense_only(args)
+        if args.copy_calibration:
+            copy_calibration()
+        print(json.dumps({"dense": res}), flush=True)
+        return
     if args.only_serving:
         w2 = wl.WORKLOADS[2]
         c_dev = wl.corpus(w2, device=torch.device("cuda:0"))
@@ -681,19 +743,28 @@ def main():
         copy_calibration()
     if not args.skip_serving:
         D8, D32 = keep
+        line["serving_shortlist_recall"] = serving_shortlist_recall(
+            D8, D32, [int(x) for x in args.serve_shortlists.split(",") if x])
         line["serving"] = []
         for ri, rate in enumerate([float(r) for r in args.serve_rates.split(",") if r]):
             log(f"serving at {rate:.0f} requests/s")
             # about 1.25 s of arrivals per rate, within the request bounds
             n_req = min(args.serve_max_requests, max(args.serve_requests, int(rate * 1.25)))
-            line["serving"].append(bench_serving(D8, D32, rate=rate, n_req=n_req, rate_idx=ri))
+            line["serving"].append(bench_serving(D8, D32, rate=rate, n_req=n_req, rate_idx=ri,
+                                               shortlist=args.serve_shortlist))
         if args.serve_rates:
-            # a device-memory budget for 256 requests' state at 16,000/s: the
+            # a device-memory budget for 256 requests' state at 32,000/s: the
             # memory check, not the slot count, is what refuses requests
-            log("serving at 16000 requests/s with a device budget of 256 requests")
-            r = bench_serving(D8, D32, rate=16000.0, n_req=min(args.serve_max_requests, 20000), rate_idx=99,
-                              max_resident=256)
+            log("serving at 32000 requests/s with a device budget of 256 requests")
+            r = bench_serving(D8, D32, rate=32000.0, n_req=min(args.serve_max_requests, 20000), rate_idx=99,
+                              max_resident=256, shortlist=args.serve_shortlist)
             line["serving_memory_limited"] = r
+            # the same offered load with the 1000-document shortlist of the
+            # fixed-length rerank workload, for comparison
+            log("serving at 16000 requests/s with a shortlist of 1000")
+            line["serving_shortlist_1000"] = bench_serving(D8, D32, rate=16000.0,
+                                                           n_req=min(args.serve_max_requests, 20000),
+                                                           rate_idx=98, shortlist=1000)
         if line["serving"]:
             # headline latency: the 2000/s point if swept, else the first rate
             ref = next((r for r in line["serving"] if r["rate_per_s"] == 2000.0), line["serving"][0])

@@ -421,7 +421,7 @@ __device__ __forceinline__ void tk_hist_add(uint32_t* hist, bool active, uint32_
 // Keys a region holds at most (k <= 1024 plus 1024 free slots).
 constexpr int kTkMaxCap = 2048;
 // Keys a lane reads per batch in a selection (loads in flight).
-constexpr int kTkBatch = 8;
+constexpr int kTkBatch = 16;
 
 // The k best of the n (k < n <= kTkMaxCap) distinct keys R[0..n) move to
 // R[0..k); returns the k-th best. Radix select over the wave, eight bits a
@@ -895,13 +895,27 @@ __device__ __forceinline__ void dense_body(const DenseParams& P) {
             s_run = ((S.first_mask >> ct) & 1) ? tv : s_run + tv;
             if ((S.last_mask >> ct) & 1) {
               if constexpr (kTopk) {
-                // a query with a document that beats its threshold joins its
-                // region below (the score waits in the parked-sum slot, read above)
+                // the documents that beat the query's threshold join its
+                // region; when the region is full, the query is taken below
+                // (its region selected first; the score waits in the
+                // parked-sum slot, read above)
                 const int j = __builtin_amdgcn_readlane(S.tq_lane, ct);
                 const float sc = doc_empty ? ninf : s_run;
-                if (__ballot(l < nd && tk_rank_key(sc, (int32_t)(p0 + l)) > readlane_u64(tk_thr, j))) {
-                  S.tsum[ct * 64 + l] = sc;
-                  fin |= 1ull << ct;
+                const uint64_t key = tk_rank_key(sc, (int32_t)(p0 + l));
+                const bool v = l < nd && key > readlane_u64(tk_thr, j);
+                const uint64_t b = __ballot(v);
+                if (b) {
+                  const int cnt = __builtin_amdgcn_readlane(tk_cnt, j);
+                  const int nb = __popcll(b);
+                  if (cnt + nb <= P.out.tk.cap) {
+                    uint64_t* R = P.out.tk.keys + ((int64_t)(q0 + j) * tk_regions + tk_piece) * P.out.tk.cap;
+                    if (v) R[cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u))] = key;
+                    tk_cnt = l == j ? cnt + nb : tk_cnt;
+                  } else {
+                    S.tsum[ct * 64 + l] = sc;
+                    fin |= 1ull << ct;
+                  }
                 }
               } else {
                 const int j = __builtin_amdgcn_readlane(S.tq_lane, ct);
@@ -912,7 +926,7 @@ __device__ __forceinline__ void dense_body(const DenseParams& P) {
           }
         }
         if constexpr (kTopk) {
-          // those queries join their regions, one at a time
+          // queries whose regions are full: select, then append
           while (fin) {
             const int ct = __builtin_ctzll(fin);
             fin &= fin - 1;

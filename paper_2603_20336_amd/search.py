@@ -15,12 +15,18 @@ unpruned neighbours of the best unexpanded results (GraphSearch).
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 from typing import List, Optional, Sequence
 
 import torch
 
 from . import GEM_FP8_E4M3, GEM_MXFP4, Beam, Cands, Sets, expand_batch, expand_workspace_bytes, score_exact
+
+
+def _on_stream(stream):
+    """Make `stream` current for a block (no change when it is None)."""
+    return contextlib.nullcontext() if stream is None else torch.cuda.stream(stream)
 
 
 class ExpansionGraph:
@@ -56,10 +62,13 @@ class ExpansionGraph:
             self.run_eager(s)
         self.graph = g
 
-    def replay(self) -> None:
+    def replay(self, stream=None) -> None:
+        """Replay the recorded steps on `stream` (default: the current stream);
+        a graph replays on the stream that is current when it is launched."""
         if self.graph is None:
             self.capture()
-        self.graph.replay()
+        with _on_stream(stream):
+            self.graph.replay()
 
     def rerank(self, Q32: Sets, D32: Sets, k: int):
         """Exact float32 Chamfer rerank of the beam (Alg. 5 final step) -> (scores, ids) [n_q, k]."""
@@ -243,21 +252,21 @@ class GraphSearch:
         `check_every` steps (a finished query's extra steps change nothing).
         With graph=True the block of steps between checks is one replay of a
         captured HIP graph."""
+        if graph and (self._hip_graph is None or self._hip_graph_steps != check_every):
+            self.capture(check_every)
         self.begin(random_words, stream)
-        if graph:
-            if self._hip_graph is None or self._hip_graph_steps != check_every:
-                self.capture(check_every)
+        # Replays and the reads of the active count are ordered on `stream`,
+        # behind begin() and every step before them.
+        with _on_stream(stream):
             while self.steps < max_steps:
-                self._hip_graph.replay()
-                self.steps += check_every
+                if graph:
+                    self._hip_graph.replay()
+                    self.steps += check_every
+                else:
+                    for _ in range(check_every):
+                        self.step(stream)
                 if int(self.active.item()) == 0:
                     break
-            return self.steps
-        while self.steps < max_steps:
-            for _ in range(check_every):
-                self.step(stream)
-            if int(self.active.item()) == 0:
-                break
         return self.steps
 
     def rerank(self, Q32: Sets, D32: Sets, k: int):

@@ -425,7 +425,13 @@ class DeviceExecutor(Executor):
         return S, rows32
 
     def set_batch(self, slots, queries):
-        self.Q8, self.rows = self._gather(slots, fp8=True)
+        # longest queries first: the scorer packs queries, in order, into
+        # blocks of a fixed column count, and decreasing lengths leave the
+        # least padding at the block ends (the row map keeps each score in
+        # its request's row, so the order changes no result)
+        slots = np.asarray(slots, np.int64)
+        order = np.argsort(-self.lens[slots], kind="stable")
+        self.Q8, self.rows = self._gather(slots[order], fp8=True)
 
     def score_chunk(self, chunk: int) -> None:
         self.score_chunks(chunk, 1)

@@ -691,6 +691,12 @@ def test_expansion_graph_replays_equal_eager():
         torch.cuda.synchronize()
         assert torch.equal(eg.beam.ids, ref_i), rep
         assert torch.equal(eg.beam.scores, ref_s), rep
+    side = torch.cuda.Stream(device=DEV)                # a replay ordered on a side stream
+    eg.beam.scores.fill_(123.0)
+    side.wait_stream(torch.cuda.current_stream(DEV))
+    eg.replay(stream=side)
+    torch.cuda.current_stream(DEV).wait_stream(side)
+    assert torch.equal(eg.beam.ids, ref_i) and torch.equal(eg.beam.scores, ref_s)
 
 
 # --------------------------------------------- gathered scorer at its full split

@@ -126,6 +126,14 @@ def test_search_matches_oracle_exactly(ef, width):
         np.testing.assert_array_equal(_np(srch.beam.ids), bi)
         np.testing.assert_array_equal(_np(srch.beam.scores), bs)
         gem.score_quant(Q8, D8, k=2)
+    # on a side stream: begin, the replays and the active-count reads all
+    # follow that stream, with no synchronization from the caller in between
+    side = torch.cuda.Stream(device=DEV)
+    side.wait_stream(torch.cuda.current_stream(DEV))
+    srch.run(words, check_every=3, graph=True, stream=side)
+    torch.cuda.current_stream(DEV).wait_stream(side)
+    np.testing.assert_array_equal(_np(srch.beam.ids), bi)
+    np.testing.assert_array_equal(_np(srch.beam.scores), bs)
     # the oracle on the same (exact) operand values
     dvals = oracle.dequantize_fp8(*oracle.quantize_fp8(dv))
     qvals = oracle.dequantize_fp8(*oracle.quantize_fp8(qv))
