@@ -14,9 +14,9 @@ path computes, written from the paper (GEM, arXiv 2603.20336):
     set-level clustering of Sec. 4.1, in a batched reading
   * EMD between vector sets (Sec. 4.2, Eq. EMD / qEMD), exact and as the
     entropic Sinkhorn approximation the GPU computes
-  * MXFP4 (OCP Microscaling, E2M1 elements with one power-of-two scale per
-    32-element block), the ultra-low-bit estimate the paper names as future
-    work (Sec. 6)
+  * MXFP4 and MXFP6 (OCP Microscaling, E2M1 / E2M3 elements with one
+    power-of-two scale per 32-element block), the ultra-low-bit estimates the
+    paper names as future work (Sec. 6)
   * the bf16 / OCP FP8 E4M3 codecs used for the quantized estimate (the paper's
     qCH replaces vectors by coarser codes, Sec. 4.2 "Quantization"; here the
     code is an FP8 E4M3 value times a per-vector power-of-two scale)
@@ -37,7 +37,8 @@ from .codebook import (codebook_size, sq_distances, nn_assign, lloyd_update, kme
 from .search import (tfidf_top_clusters, cluster_members, query_clusters, entry_points, beam_search,
                      ch_scorer)
 from .emd import cost_matrix, emd_exact, sinkhorn, chamfer_distance
-from .mx import e2m1_decode, e2m1_table, e2m1_encode, block_exponent, quantize_mxfp4, dequantize_mxfp4
+from .mx import (e2m1_decode, e2m1_table, e2m1_encode, block_exponent, quantize_mxfp4, dequantize_mxfp4,
+                 e2m3_decode, e2m3_table, e2m3_encode, quantize_mxfp6, dequantize_mxfp6)
 from .codecs import (bf16_round_bits, bf16_decode, e4m3_decode, e4m3_decode_table,
                      e4m3_encode, pow2_scale, quantize_fp8, dequantize_fp8)
 
