@@ -38,6 +38,7 @@ from paper_2603_20336_amd import workloads as wl  # noqa: E402
 PEAK_BF16 = 2.5e15
 PEAK_FP8 = 5.0e15
 PEAK_FP4 = 10.1e15
+PEAK_FP6 = 10.1e15
 PEAK_FP32_MATRIX = 157.3e12
 PEAK_HBM = 8.0e12
 
@@ -369,6 +370,13 @@ def bench_exhaustive(args):
     t_mx_score = timed(lambda: gem.score_quant(Q4, D4, scores=est), max(1, args.steps))
     mx_sweep, _, _ = sweep("mxfp4", lambda: gem.quantize_mxfp4(Q), lambda q4, sl: gem.score_quant(q4, D4, k=sl))
     del D4, Q4
+    # MXFP6 (E2M3) estimate
+    D6 = gem.quantize_mxfp6(D32)
+    Q6 = gem.quantize_mxfp6(Q)
+    sched["mxfp6"], _ = gem.autotune_dense(Q6, D6, reps=2, scores=est)
+    t_mx6_score = timed(lambda: gem.score_quant(Q6, D6, scores=est), max(1, args.steps))
+    mx6_sweep, _, _ = sweep("mxfp6", lambda: gem.quantize_mxfp6(Q), lambda q6, sl: gem.score_quant(q6, D6, k=sl))
+    del D6, Q6
 
     # qCH (Sec. 4.5): every vector replaced by its nearest centroid of the
     # k-means codebook (Secs. 4.1, 4.2); estimate -> shortlist -> f32 rerank
@@ -430,6 +438,7 @@ def bench_exhaustive(args):
     res["recall_at_100_bf16"] = recall_gpu(top_i, exact, exact_kth, k)
     res["recall_at_100_fp8_rerank"] = fp8_sweep.get("1000", {}).get(f"recall_at_{k}")
     res["recall_at_100_mxfp4_rerank"] = mx_sweep.get("1000", {}).get(f"recall_at_{k}")
+    res["recall_at_100_mxfp6_rerank"] = mx6_sweep.get("1000", {}).get(f"recall_at_{k}")
     res["recall_queries"] = n_q
     res["recall_reference"] = "float32 exact scores of every (query, document) pair, checked against float64"
     value = pairs / (ms_per_step / 1e3)
@@ -466,6 +475,10 @@ def bench_exhaustive(args):
                                   mxfp4_tflops=flops / (t_mx_score / 1e3) / 1e12,
                                   mxfp4_frac_of_peak=flops / (t_mx_score / 1e3) / PEAK_FP4,
                                   corpus_bytes=V * 68, shortlist_sweep=mx_sweep),
+        "mxfp6_rerank_path": dict(mx6_sweep.get("1000", {}), shortlist=1000, mxfp6_score_ms=t_mx6_score,
+                                  mxfp6_tflops=flops / (t_mx6_score / 1e3) / 1e12,
+                                  mxfp6_frac_of_peak=flops / (t_mx6_score / 1e3) / PEAK_FP6,
+                                  corpus_bytes=V * 100, shortlist_sweep=mx6_sweep),
         "qch_rerank_path": qch,
     }
     line.update(res)
@@ -477,18 +490,20 @@ def bench_exhaustive(args):
 
 def bench_dense_only(args):
     """The dense scorers alone, for counter runs: the bf16 step (fused top-100,
-    then staged), and FP8 and MXFP4 exhaustive scoring into a score matrix."""
+    then staged), and FP8, MXFP4 and MXFP6 exhaustive scoring into a score
+    matrix."""
     dev = torch.device("cuda:0")
     w2 = wl.WORKLOADS[2]
     c_dev, q_dev = wl.corpus(w2, device=dev), wl.queries(w2, device=dev)
     Q = gem.Sets(q_dev.vecs, q_dev.offsets, "f32", q_dev.max_len())
     D32 = gem.Sets(c_dev.vecs, c_dev.offsets, "f32", c_dev.max_len())
-    D16, D8, D4 = gem.convert_bf16(D32), gem.quantize_fp8(D32), gem.quantize_mxfp4(D32)
-    Q16, Q8, Q4 = gem.convert_bf16(Q), gem.quantize_fp8(Q), gem.quantize_mxfp4(Q)
+    D16, D8, D4, D6 = gem.convert_bf16(D32), gem.quantize_fp8(D32), gem.quantize_mxfp4(D32), gem.quantize_mxfp6(D32)
+    Q16, Q8, Q4, Q6 = gem.convert_bf16(Q), gem.quantize_fp8(Q), gem.quantize_mxfp4(Q), gem.quantize_mxfp6(Q)
     scores = torch.empty(Q.n_sets, D32.n_sets, dtype=torch.float32, device=dev)
     flops = 2.0 * 128 * Q.n_vecs * D32.n_vecs
     out = {}
-    for name, QQ, DD, peak in (("bf16", Q16, D16, PEAK_BF16), ("fp8", Q8, D8, PEAK_FP8), ("mxfp4", Q4, D4, PEAK_FP4)):
+    for name, QQ, DD, peak in (("bf16", Q16, D16, PEAK_BF16), ("fp8", Q8, D8, PEAK_FP8), ("mxfp4", Q4, D4, PEAK_FP4),
+                               ("mxfp6", Q6, D6, PEAK_FP6)):
         sched, _ = gem.autotune_dense(QQ, DD, reps=2, scores=scores)
         if name == "bf16":
             t_f = timed(lambda: gem.score_exact(QQ, DD, compute="bf16", k=100), max(1, args.steps))
@@ -617,6 +632,21 @@ def bench_expansion(args):
                     "pair_scores_per_s": pairs / (ms4 / 1e3), "beam_overlap_with_fp8_rows": float(ov4)}
     log(f"mxfp4 expansion {ms4 / w4.steps:.3f} ms/step")
     del eg4, D4, Q4
+    # MXFP6 rows: 96 bytes of codes + 4 exponent bytes per vector
+    D6 = gem.quantize_mxfp6(D32)
+    Q6 = gem.quantize_mxfp6(Q32)
+    eg6 = ExpansionGraph(Q6, D6, steps, ef=w4.ef)
+    eg6.capture()
+    eg6.replay()
+    torch.cuda.synchronize()
+    ms6 = timed(eg6.replay, 3)
+    b6 = eg6.beam.ids.cpu().numpy()
+    ov6 = np.mean([np.intersect1d(a8[i][a8[i] >= 0], b6[i][b6[i] >= 0]).size / w4.ef for i in range(a8.shape[0])])
+    res["mxfp6"] = {"ms_per_step": ms6 / w4.steps, "speedup_vs_fp8_rows": per_step / (ms6 / w4.steps),
+                    "gbps_per_pair_bytes": pair_bytes / 132 * 100 / w4.steps / (ms6 / w4.steps / 1e3) / 1e9,
+                    "pair_scores_per_s": pairs / (ms6 / 1e3), "beam_overlap_with_fp8_rows": float(ov6)}
+    log(f"mxfp6 expansion {ms6 / w4.steps:.3f} ms/step")
+    del eg6, D6, Q6
 
     # qCH expansion: the same steps with the corpus and the queries as codes
     # over an FP8 codebook (Secs. 4.2, 4.5): 4 bytes of code per vector

@@ -66,9 +66,13 @@ typedef enum {
   GEM_F32 = 0,               /* float32 rows, 512 bytes per 128-d vector */
   GEM_BF16 = 1,              /* bfloat16 rows (uint16 bit patterns), 256 bytes */
   GEM_FP8_E4M3 = 2,          /* OCP E4M3 codes (uint8), 128 bytes, plus a float32 scale */
-  GEM_MXFP4 = 3              /* OCP MXFP4: E2M1 codes, 64 bytes (element t in byte t/2, the low
+  GEM_MXFP4 = 3,             /* OCP MXFP4: E2M1 codes, 64 bytes (element t in byte t/2, the low
                                 nibble for even t), plus 4 E8M0 block exponents (one per 32
                                 elements) per row */
+  GEM_MXFP6 = 4              /* OCP MXFP6: E2M3 codes, 96 bytes: block j (elements 32j .. 32j + 31)
+                                fills bytes 24j .. 24j + 23, its element t in bits 6t .. 6t + 5
+                                of those 192 bits (least significant bit first), plus 4 E8M0
+                                block exponents per row as for MXFP4 */
 } gem_dtype;
 
 typedef enum {
@@ -96,8 +100,8 @@ typedef struct gem_ctx_s* gem_ctx;
  *   vecs: [n_vecs][dim] row-major, element type `dtype`.
  *   scales: FP8: [n_vecs] float32; row r's values are scales[r] * decode(code).
  *           Scales must be powers of two (gem_quantize_fp8 writes such scales).
- *           MXFP4: [n_vecs] 32-bit words of 4 E8M0 bytes; byte j of row r's word
- *           is the exponent e + 127 of the scale 2^e of dims 32j .. 32j + 31.
+ *           MXFP4, MXFP6: [n_vecs] 32-bit words of 4 E8M0 bytes; byte j of row r's
+ *           word is the exponent e + 127 of the scale 2^e of dims 32j .. 32j + 31.
  *   max_set_len: host-side upper bound of the set lengths (needed for query sets).
  *
  * Code sets (the quantized representation of Secs. 4.2 and 4.5, where every
@@ -257,6 +261,17 @@ size_t gem_codebook_workspace_bytes(int32_t op, int64_t n_rows, int64_t n_centro
 gem_status gem_quantize_mxfp4(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim, uint8_t* out,
                               uint8_t* exps, hipStream_t stream);
 
+/* float32 rows -> OCP MXFP6 with E2M3 elements: per block of 32 consecutive
+ * dims, the scale 2^e with the smallest e in [-127, 127] such that
+ * max|x| <= 7.5 * 2^e (2^0 for an all-zero block), and each element's E2M3
+ * code of x / 2^e (nearest value, ties to the even code; zero is code 0).
+ * Like MXFP4, an ultra-low-bit form of the quantized estimate (Sec. 6).
+ *   out: [device] [n_rows * 96] packed codes (layout of GEM_MXFP6); exps:
+ *   [device] [n_rows * 4] E8M0 bytes (the `scales` of a GEM_MXFP6 set).
+ *   dim must be 128; errors as gem_quantize_mxfp4. */
+gem_status gem_quantize_mxfp6(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim, uint8_t* out,
+                              uint8_t* exps, hipStream_t stream);
+
 /* Row copies for assembling batches (a serving loop gathers the active
  * requests' query rows from per-request slots, and writes admitted requests'
  * rows into their slots): for i < n, row (dst_idx ? dst_idx[i] : i) of dst
@@ -293,9 +308,9 @@ gem_status gem_score_exact(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, co
 /* Quantized estimate: the same outputs as gem_score_exact, computed on the
  * quantized operands of D's format with their scales (products and float32
  * accumulation of scaled code products): D->dtype is GEM_FP8_E4M3 (a scale per
- * vector) or GEM_MXFP4 (a scale per 32-element block). Q is either in D's
- * format, or GEM_F32 and is quantized into the workspace by the rule of
- * gem_quantize_fp8 / gem_quantize_mxfp4. */
+ * vector), GEM_MXFP4 or GEM_MXFP6 (a scale per 32-element block). Q is either
+ * in D's format, or GEM_F32 and is quantized into the workspace by the rule of
+ * gem_quantize_fp8 / gem_quantize_mxfp4 / gem_quantize_mxfp6. */
 gem_status gem_score_quant(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_cands* C,
                            int32_t k,
                            float* scores, int64_t ld_scores, const int32_t* score_rows,
@@ -336,8 +351,8 @@ gem_status gem_topk(gem_ctx ctx, const float* scores, const int64_t* seg_offsets
  * estimate CH(Q_i, D_id) with quantized operands for every entry of list i,
  * then replace beam row i by the best ef of (beam row i) U (scored entries),
  * ids distinct (a repeated id keeps its best entry). D8->dtype is
- * GEM_FP8_E4M3 or GEM_MXFP4; Q8 is in D8's format or GEM_F32 (quantized into
- * ws). If
+ * GEM_FP8_E4M3, GEM_MXFP4 or GEM_MXFP6; Q8 is in D8's format or GEM_F32
+ * (quantized into ws). If
  * cand_scores is not NULL the step's entry scores are also written there
  * ([C->n_entries]). The beam is updated in place. */
 gem_status gem_expand_batch(gem_ctx ctx, const gem_sets* Q8, const gem_sets* D8, const gem_cands* C,
@@ -434,7 +449,7 @@ typedef struct {
  * cluster of each query's C_query (member floor(u * count / 2^32) of the
  * cluster, u = random_words[i * k2 + j], drawn by the caller), scores the
  * entries and makes them the beam (R of Alg. 5; ef <= GEM_MAX_EF). Scores are
- * CH in D's dtype (the estimate for FP8 / MXFP4 sets, qCH for code sets); Q
+ * CH in D's dtype (the estimate for FP8 / MX sets, qCH for code sets); Q
  * must already be in D's dtype. */
 gem_status gem_search_begin(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const gem_graph* G,
                             gem_search_state* S, const uint32_t* random_words, gem_beam* beam, hipStream_t stream);
@@ -486,7 +501,7 @@ gem_status gem_set_dense_schedule(gem_ctx ctx, int32_t dtype, int64_t q_rows, in
  * only when faster by more than 0.5 % (so near ties keep the earlier, and the
  * choice is stable from run to run). The workspace must hold
  * gem_workspace_bytes(ctx, op, Q, D, NULL, compute, 0, 1) bytes (op
- * GEM_OP_SCORE_EXACT, or GEM_OP_SCORE_QUANT for FP8 / MXFP4).
+ * GEM_OP_SCORE_EXACT, or GEM_OP_SCORE_QUANT for FP8 / MXFP4 / MXFP6).
  */
 gem_status gem_autotune_dense(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, int32_t compute, float* scores,
                               int64_t ld_scores, void* ws, size_t ws_bytes, hipStream_t stream, int32_t reps,
@@ -496,7 +511,7 @@ gem_status gem_autotune_dense(gem_ctx ctx, const gem_sets* Q, const gem_sets* D,
  * expansion and search steps): entries of a list per wave (1..64; 0 = the
  * library's rule: 16, or fewer when a call has too few entries to fill the
  * GPU) and document tiles in flight per wave (one of three depths per format:
- * F32 1/2/3, BF16 2/4/6, FP8 4/6/8, MXFP4 6/8/12; 0 or the middle one is the
+ * F32 1/2/3, BF16 2/4/6, FP8 4/6/8, MXFP4 6/8/12, MXFP6 4/6/8; 0 or the middle one is the
  * default). Kept per shape class: the compute dtype and the power-of-two
  * classes of the list count and of the longest list. A schedule changes the
  * time of a call, never its results. */

@@ -19,21 +19,23 @@ from typing import Optional
 import torch
 
 from . import _abi
-from ._abi import (GEM_BF16, GEM_F32, GEM_FP8_E4M3, GEM_MAX_K, GEM_MAX_QUERY_LEN, GEM_MXFP4, GemError)
+from ._abi import (GEM_BF16, GEM_F32, GEM_FP8_E4M3, GEM_MAX_K, GEM_MAX_QUERY_LEN, GEM_MXFP4, GEM_MXFP6, GemError)
 
 __all__ = ["Sets", "Cands", "Beam", "GemError", "convert_bf16", "quantize_fp8", "score_exact",
            "score_quant", "topk", "expand_batch", "beam_merge", "beam_reset", "validate_sets", "validate_cands",
-           "library", "GEM_F32", "GEM_BF16", "GEM_FP8_E4M3", "GEM_MXFP4", "quantize_mxfp4", "GEM_MAX_K", "GEM_MAX_QUERY_LEN", "dense_schedule",
+           "library", "GEM_F32", "GEM_BF16", "GEM_FP8_E4M3", "GEM_MXFP4", "quantize_mxfp4", "GEM_MXFP6", "quantize_mxfp6", "GEM_MAX_K", "GEM_MAX_QUERY_LEN", "dense_schedule",
            "set_dense_schedule", "autotune_dense", "copy_rows", "nearest_centroid", "centroid_update",
            "kmeans", "encode", "codebook_size",
            "emd_sinkhorn", "set_topk_fusion", "topk_fusion", "score_workspace_bytes", "gather_schedule",
            "set_check", "check_status", "set_gather_schedule", "autotune_gather", "save_tune_cache", "load_tune_cache"]
 
-_DTYPES = {"f32": GEM_F32, "bf16": GEM_BF16, "fp8": GEM_FP8_E4M3, "mxfp4": GEM_MXFP4,
-           GEM_F32: GEM_F32, GEM_BF16: GEM_BF16, GEM_FP8_E4M3: GEM_FP8_E4M3, GEM_MXFP4: GEM_MXFP4}
-_ROW_TORCH = {GEM_F32: torch.float32, GEM_BF16: torch.uint16, GEM_FP8_E4M3: torch.uint8, GEM_MXFP4: torch.uint8}
-_ROW_WIDTH = {GEM_F32: 128, GEM_BF16: 128, GEM_FP8_E4M3: 128, GEM_MXFP4: 64}     # tensor columns per row
-_QUANT = (GEM_FP8_E4M3, GEM_MXFP4)
+_DTYPES = {"f32": GEM_F32, "bf16": GEM_BF16, "fp8": GEM_FP8_E4M3, "mxfp4": GEM_MXFP4, "mxfp6": GEM_MXFP6,
+           GEM_F32: GEM_F32, GEM_BF16: GEM_BF16, GEM_FP8_E4M3: GEM_FP8_E4M3, GEM_MXFP4: GEM_MXFP4,
+           GEM_MXFP6: GEM_MXFP6}
+_ROW_TORCH = {GEM_F32: torch.float32, GEM_BF16: torch.uint16, GEM_FP8_E4M3: torch.uint8, GEM_MXFP4: torch.uint8,
+              GEM_MXFP6: torch.uint8}
+_ROW_WIDTH = {GEM_F32: 128, GEM_BF16: 128, GEM_FP8_E4M3: 128, GEM_MXFP4: 64, GEM_MXFP6: 96}   # tensor columns per row
+_QUANT = (GEM_FP8_E4M3, GEM_MXFP4, GEM_MXFP6)
 
 
 def library():
@@ -77,10 +79,11 @@ class Sets:
     """A ragged batch of 128-d vector sets on the device (CSR).
 
     vecs: [n_vecs, 128] float32 / uint16 (bf16 bits) / uint8 (E4M3 codes), or
-        [n_vecs, 64] uint8 (MXFP4: two E2M1 codes a byte)
+        [n_vecs, 64] uint8 (MXFP4: two E2M1 codes a byte), or [n_vecs, 96] uint8
+        (MXFP6: 6-bit E2M3 codes, 24 bytes per 32-element block)
     offsets: [n_sets + 1] int64 absolute row indices
-    scales: FP8: [n_vecs] float32 powers of two; MXFP4: [n_vecs, 4] uint8 E8M0
-        block exponents
+    scales: FP8: [n_vecs] float32 powers of two; MXFP4, MXFP6: [n_vecs, 4] uint8
+        E8M0 block exponents
     max_len: host-side bound of the set lengths
     codes: code sets only, [n_vecs] int32: entry r stands for row codes[r] of
         vecs, which then holds the codebook (its nearest centroid, Sec. 4.2);
@@ -139,6 +142,9 @@ class Sets:
 
     def to_mxfp4(self, stream=None) -> "Sets":
         return quantize_mxfp4(self, stream)
+
+    def to_mxfp6(self, stream=None) -> "Sets":
+        return quantize_mxfp6(self, stream)
 
 
 class Cands:
@@ -224,6 +230,18 @@ def quantize_mxfp4(S: Sets, stream=None) -> Sets:
     _abi.check(library().gem_quantize_mxfp4(_ctx(S.device), _ptr(S.vecs), n, _abi.GEM_DIM, _ptr(out), _ptr(ex),
                                             _stream(stream)))
     return Sets(out, S.offsets, GEM_MXFP4, S.max_len, scales=ex, n_sets=S.n_sets, codes=S.codes)
+
+
+def quantize_mxfp6(S: Sets, stream=None) -> Sets:
+    """float32 sets -> MXFP6: E2M3 codes with one power-of-two scale per 32-element block."""
+    if S.dtype != GEM_F32:
+        raise TypeError("quantize_mxfp6 takes float32 sets")
+    n = int(S.vecs.shape[0])                       # (a code set converts its codebook)
+    out = torch.empty(n, 96, dtype=torch.uint8, device=S.device)
+    ex = torch.empty(n, 4, dtype=torch.uint8, device=S.device)
+    _abi.check(library().gem_quantize_mxfp6(_ctx(S.device), _ptr(S.vecs), n, _abi.GEM_DIM, _ptr(out), _ptr(ex),
+                                            _stream(stream)))
+    return Sets(out, S.offsets, GEM_MXFP6, S.max_len, scales=ex, n_sets=S.n_sets, codes=S.codes)
 
 
 def _score(fn_exact: bool, Q: Sets, D: Sets, cands: Optional[Cands], k: int, compute: int,
@@ -529,9 +547,9 @@ def load_tune_cache(path: str, device="cuda") -> None:
 def score_quant(Q: Sets, D8: Sets, cands: Optional[Cands] = None, k: int = 0,
                 scores: Optional[torch.Tensor] = None, ld: int = 0, rows: Optional[torch.Tensor] = None,
                 want_scores: bool = False, stream=None, ws: Optional[torch.Tensor] = None):
-    """Quantized estimate in D8's format, FP8 E4M3 or MXFP4 (same conventions as score_exact)."""
+    """Quantized estimate in D8's format, FP8 E4M3, MXFP4 or MXFP6 (same conventions as score_exact)."""
     if D8.dtype not in _QUANT:
-        raise TypeError("score_quant takes FP8 or MXFP4 documents")
+        raise TypeError("score_quant takes FP8, MXFP4 or MXFP6 documents")
     return _score(False, Q, D8, cands, k, D8.dtype, scores, ld, rows, want_scores, stream, ws)
 
 

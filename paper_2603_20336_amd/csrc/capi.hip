@@ -64,14 +64,16 @@ int row_bytes(int dtype) {
     case GEM_BF16: return 2 * GEM_DIM;
     case GEM_FP8_E4M3: return GEM_DIM;
     case GEM_MXFP4: return GEM_DIM / 2;
+    case GEM_MXFP6: return GEM_DIM * 3 / 4;
     default: return 0;
   }
 }
 
-bool valid_dtype(int32_t d) { return d == GEM_F32 || d == GEM_BF16 || d == GEM_FP8_E4M3 || d == GEM_MXFP4; }
+bool mx_dtype(int32_t d) { return d == GEM_MXFP4 || d == GEM_MXFP6; }
+bool valid_dtype(int32_t d) { return d == GEM_F32 || d == GEM_BF16 || d == GEM_FP8_E4M3 || mx_dtype(d); }
 // Formats that carry a 32-bit scale word per row.
-bool scaled_dtype(int32_t d) { return d == GEM_FP8_E4M3 || d == GEM_MXFP4; }
-bool quant_dtype(int32_t d) { return d == GEM_FP8_E4M3 || d == GEM_MXFP4; }
+bool scaled_dtype(int32_t d) { return d == GEM_FP8_E4M3 || mx_dtype(d); }
+bool quant_dtype(int32_t d) { return d == GEM_FP8_E4M3 || mx_dtype(d); }
 
 gem_status check_sets(const gem_sets* S, const char* name, bool need_max_len) {
   if (!S) return fail(GEM_ERR_INVALID, "%s is NULL", name);
@@ -82,7 +84,7 @@ gem_status check_sets(const gem_sets* S, const char* name, bool need_max_len) {
   if (S->n_sets > 0 && !S->offsets) return fail(GEM_ERR_INVALID, "%s: offsets is NULL", name);
   if (S->n_vecs > 0 && !S->vecs) return fail(GEM_ERR_INVALID, "%s: vecs is NULL", name);
   if (scaled_dtype(S->dtype) && S->n_vecs > 0 && !S->scales)
-    return fail(GEM_ERR_INVALID, "%s: FP8 and MXFP4 sets need scales", name);
+    return fail(GEM_ERR_INVALID, "%s: FP8 and MX sets need scales", name);
   if (S->max_set_len < 0) return fail(GEM_ERR_INVALID, "%s: negative max_set_len", name);
   if (need_max_len && S->max_set_len > GEM_MAX_QUERY_LEN)
     return fail(GEM_ERR_UNSUPPORTED, "%s: max_set_len %d exceeds %d", name, S->max_set_len, GEM_MAX_QUERY_LEN);
@@ -93,7 +95,7 @@ gem_status check_sets(const gem_sets* S, const char* name, bool need_max_len) {
     if (S->codebook_rows > INT32_MAX) return fail(GEM_ERR_UNSUPPORTED, "%s: codebook of more than 2^31-1 rows", name);
     if (S->codebook_rows > 0 && !S->vecs) return fail(GEM_ERR_INVALID, "%s: codebook (vecs) is NULL", name);
     if (scaled_dtype(S->dtype) && S->codebook_rows > 0 && !S->scales)
-      return fail(GEM_ERR_INVALID, "%s: FP8 and MXFP4 codebooks need scales", name);
+      return fail(GEM_ERR_INVALID, "%s: FP8 and MX codebooks need scales", name);
   } else if (S->codebook_rows != 0) {
     return fail(GEM_ERR_INVALID, "%s: codebook_rows set without codes", name);
   }
@@ -225,10 +227,10 @@ gem_status convert_query(const gem_sets* Q, int32_t compute, void* ws, const Sco
   if (compute == GEM_BF16) {
     e = launch_convert_bf16(static_cast<const float*>(Q->vecs), vec_rows(Q) * GEM_DIM,
                             reinterpret_cast<uint16_t*>(at(ws, L.q_conv)), stream);
-  } else if (compute == GEM_MXFP4) {
-    e = launch_quantize_mxfp4(static_cast<const float*>(Q->vecs), vec_rows(Q),
-                              reinterpret_cast<uint8_t*>(at(ws, L.q_conv)),
-                              reinterpret_cast<uint8_t*>(at(ws, L.q_scales)), stream);
+  } else if (mx_dtype(compute)) {
+    e = (compute == GEM_MXFP4 ? launch_quantize_mxfp4 : launch_quantize_mxfp6)(
+        static_cast<const float*>(Q->vecs), vec_rows(Q), reinterpret_cast<uint8_t*>(at(ws, L.q_conv)),
+        reinterpret_cast<uint8_t*>(at(ws, L.q_scales)), stream);
     Qc->scales = reinterpret_cast<const float*>(at(ws, L.q_scales));
   } else {
     e = launch_quantize_fp8(static_cast<const float*>(Q->vecs), vec_rows(Q), reinterpret_cast<uint8_t*>(at(ws, L.q_conv)),
@@ -445,7 +447,7 @@ hipError_t launch_set_validation(const gem_sets* S, hipStream_t stream) {
     hipLaunchKernelGGL(validate_offsets_kernel, dim3(blocks_for(S->n_sets + 1)), dim3(256), 0, stream, S->offsets,
                        S->n_sets, S->n_vecs);
   const int64_t rows = vec_rows(S);
-  if (S->dtype == GEM_MXFP4 && rows > 0)
+  if (mx_dtype(S->dtype) && rows > 0)
     hipLaunchKernelGGL(validate_mx_exps_kernel, dim3(blocks_for(rows)), dim3(256), 0, stream,
                        reinterpret_cast<const uint32_t*>(S->scales), rows);
   if (S->dtype == GEM_FP8_E4M3 && rows > 0)
@@ -885,13 +887,12 @@ size_t gem_workspace_bytes(gem_ctx ctx, int32_t op, const gem_sets* Q, const gem
     case GEM_OP_SCORE_EXACT:
     case GEM_OP_SCORE_QUANT: {
       if (!D) return 0;
-      const int32_t cd = op == GEM_OP_SCORE_QUANT ? (D->dtype == GEM_MXFP4 ? (int32_t)GEM_MXFP4 : (int32_t)GEM_FP8_E4M3)
-                                                  : compute;
+      const int32_t cd = op == GEM_OP_SCORE_QUANT ? (mx_dtype(D->dtype) ? D->dtype : (int32_t)GEM_FP8_E4M3) : compute;
       return score_layout(Q, D, C, cd, k, scores_given != 0, ctx->n_cu / 8, ctx->topk_mode).total;
     }
     case GEM_OP_EXPAND: {
       if (!D || !C) return 0;
-      return score_layout(Q, D, C, D->dtype == GEM_MXFP4 ? GEM_MXFP4 : GEM_FP8_E4M3, 1, scores_given != 0,
+      return score_layout(Q, D, C, mx_dtype(D->dtype) ? D->dtype : (int32_t)GEM_FP8_E4M3, 1, scores_given != 0,
                           ctx->n_cu / 8).total;
     }
     default:
@@ -927,6 +928,16 @@ gem_status gem_quantize_mxfp4(gem_ctx ctx, const float* x, int64_t n_rows, int32
   if (n_rows > 0 && (!x || !out || !exps)) return fail(GEM_ERR_INVALID, "NULL buffer");
   hipError_t e = launch_quantize_mxfp4(x, n_rows, out, exps, stream);
   return e == hipSuccess ? GEM_OK : hip_fail(e, "mxfp4 quantization");
+}
+
+gem_status gem_quantize_mxfp6(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim, uint8_t* out, uint8_t* exps,
+                              hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (dim != GEM_DIM) return fail(GEM_ERR_UNSUPPORTED, "dim %d (only %d is supported)", dim, GEM_DIM);
+  if (n_rows < 0) return fail(GEM_ERR_INVALID, "negative n_rows");
+  if (n_rows > 0 && (!x || !out || !exps)) return fail(GEM_ERR_INVALID, "NULL buffer");
+  hipError_t e = launch_quantize_mxfp6(x, n_rows, out, exps, stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "mxfp6 quantization");
 }
 
 size_t gem_codebook_workspace_bytes(int32_t op, int64_t n_rows, int64_t n_centroids) {
@@ -1055,7 +1066,7 @@ gem_status gem_expand_batch(gem_ctx ctx, const gem_sets* Q8, const gem_sets* D8,
   gem_status st;
   if ((st = check_sets(Q8, "Q8", true)) != GEM_OK) return st;
   if ((st = check_sets(D8, "D8", false)) != GEM_OK) return st;
-  if (!quant_dtype(D8->dtype)) return fail(GEM_ERR_INVALID, "D8 must be FP8 E4M3 or MXFP4");
+  if (!quant_dtype(D8->dtype)) return fail(GEM_ERR_INVALID, "D8 must be FP8 E4M3, MXFP4 or MXFP6");
   const int32_t cd = D8->dtype;
   if (Q8->dtype != cd && Q8->dtype != GEM_F32) return fail(GEM_ERR_INVALID, "Q8 must be in D8's format or F32");
   if (!C) return fail(GEM_ERR_INVALID, "cands is NULL");

@@ -70,12 +70,14 @@ __device__ __forceinline__ uint32_t e2m1_code(float y) {
   return m | ((y < 0.0f && m != 0u) ? 8u : 0u);
 }
 
-__device__ __forceinline__ int mx_block_exponent(float amax) {
+// Smallest e in [-127, 127] with amax <= top * 2^e (top: the element
+// format's largest magnitude, 6 for E2M1 and 7.5 for E2M3; 0 for amax = 0).
+__device__ __forceinline__ int mx_block_exponent(float amax, float top) {
   if (!(amax > 0.0f)) return 0;
   int E;
   (void)frexpf(amax, &E);                                   // amax = f * 2^E, f in [0.5, 1)
-  int e = E - 4;
-  while (amax > ldexpf(6.0f, e)) ++e;
+  int e = E - 4;                                            // below the answer for top < 8
+  while (amax > ldexpf(top, e)) ++e;
   return e < -127 ? -127 : (e > 127 ? 127 : e);
 }
 
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(256) void quantize_mxfp4_kernel(const float* __rest
     float amax = fmaxf(fabsf(v.x), fabsf(v.y));
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1) amax = fmaxf(amax, __shfl_xor(amax, o));   // within the 16-lane block
-    const int e = mx_block_exponent(amax);
+    const int e = mx_block_exponent(amax, 6.0f);
     // x * 2^-e, exact: two steps keep the factor a normal float for e = 127
     const float y0 = ldexpf(ldexpf(v.x, -e / 2), -(e - e / 2));
     const float y1 = ldexpf(ldexpf(v.y, -e / 2), -(e - e / 2));
@@ -99,6 +101,55 @@ __global__ __launch_bounds__(256) void quantize_mxfp4_kernel(const float* __rest
 hipError_t launch_quantize_mxfp4(const float* x, int64_t n_rows, uint8_t* out, uint8_t* exps, hipStream_t s) {
   if (n_rows == 0) return hipSuccess;
   hipLaunchKernelGGL(quantize_mxfp4_kernel, dim3(capped_blocks((n_rows + 3) / 4, 256)), dim3(256), 0, s, x, n_rows, out,
+                     exps);
+  return hipGetLastError();
+}
+
+// float32 rows -> OCP MXFP6 (E2M3 elements). As for MXFP4, one wave per row,
+// two elements per lane, and a 32-element block's scale 2^e the smallest with
+// max|x| <= 7.5 * 2^e. The E2M3 magnitudes are the multiples of 1/8 in [0, 2),
+// of 1/4 in [2, 4) and of 1/2 in [4, 7.5]; on each of these uniform pieces the
+// code index is the piece's first index (even) plus y rounded on the piece's
+// step, half to even, so ties go to the even code. Each scaling is exact.
+__device__ __forceinline__ uint32_t e2m3_code(float y) {
+  const float a = fminf(fabsf(y), 7.5f);
+  uint32_t idx;
+  if (a < 2.0f) idx = (uint32_t)__builtin_rintf(a * 8.0f);                     // 0 .. 16
+  else if (a < 4.0f) idx = 16u + (uint32_t)__builtin_rintf((a - 2.0f) * 4.0f);  // 16 .. 24
+  else idx = 24u + (uint32_t)__builtin_rintf((a - 4.0f) * 2.0f);                // 24 .. 31
+  return idx | ((y < 0.0f && idx != 0u) ? 0x20u : 0u);
+}
+
+// Packing: lane i of a block (i = l % 16) holds the block's bits 12i .. 12i + 11
+// (its two codes, the even element low); the first lane of every four writes
+// their 48 bits as three 16-bit words at byte 6 (i / 4) of the block.
+__global__ __launch_bounds__(256) void quantize_mxfp6_kernel(const float* __restrict__ x, int64_t n_rows,
+                                                             uint8_t* __restrict__ out, uint8_t* __restrict__ exps) {
+  const int l = threadIdx.x & 63;
+  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < n_rows; row += (int64_t)gridDim.x * 4) {
+    const float2 v = reinterpret_cast<const float2*>(x + row * kDim)[l];
+    float amax = fmaxf(fabsf(v.x), fabsf(v.y));
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) amax = fmaxf(amax, __shfl_xor(amax, o));   // within the 16-lane block
+    const int e = mx_block_exponent(amax, 7.5f);
+    const float y0 = ldexpf(ldexpf(v.x, -e / 2), -(e - e / 2));
+    const float y1 = ldexpf(ldexpf(v.y, -e / 2), -(e - e / 2));
+    const uint32_t bits = e2m3_code(y0) | (e2m3_code(y1) << 6);                 // 12 bits
+    const uint32_t b1 = __shfl_down(bits, 1), b2 = __shfl_down(bits, 2), b3 = __shfl_down(bits, 3);
+    if ((l & 3) == 0) {
+      const uint64_t u = (uint64_t)bits | ((uint64_t)b1 << 12) | ((uint64_t)b2 << 24) | ((uint64_t)b3 << 36);
+      uint16_t* dst = reinterpret_cast<uint16_t*>(out + row * 96 + (l >> 4) * 24 + ((l & 15) >> 2) * 6);
+      dst[0] = (uint16_t)u;
+      dst[1] = (uint16_t)(u >> 16);
+      dst[2] = (uint16_t)(u >> 32);
+    }
+    if ((l & 15) == 0) exps[row * 4 + (l >> 4)] = (uint8_t)(e + 127);
+  }
+}
+
+hipError_t launch_quantize_mxfp6(const float* x, int64_t n_rows, uint8_t* out, uint8_t* exps, hipStream_t s) {
+  if (n_rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(quantize_mxfp6_kernel, dim3(capped_blocks((n_rows + 3) / 4, 256)), dim3(256), 0, s, x, n_rows, out,
                      exps);
   return hipGetLastError();
 }

@@ -117,6 +117,7 @@ hipError_t launch_score_range(int dtype, const SetsView& Q, const SetsView& D, c
 hipError_t launch_convert_bf16(const float* x, int64_t n_elems, uint16_t* out, hipStream_t s);
 hipError_t launch_quantize_fp8(const float* x, int64_t n_rows, uint8_t* out, float* scales, hipStream_t s);
 hipError_t launch_quantize_mxfp4(const float* x, int64_t n_rows, uint8_t* out, uint8_t* exps, hipStream_t s);
+hipError_t launch_quantize_mxfp6(const float* x, int64_t n_rows, uint8_t* out, uint8_t* exps, hipStream_t s);
 // Codebook kernels (nearest centroid, k-means update).
 size_t nearest_centroid_ws_bytes(int64_t n_rows, int64_t n_centroids);
 hipError_t launch_nearest_centroid(int dtype, const void* x, int64_t n_rows, const void* centroids,

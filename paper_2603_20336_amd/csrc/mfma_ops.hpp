@@ -122,4 +122,32 @@ template <> struct Op<GEM_MXFP4> {
   static constexpr int kSteps = 1;
 };
 
+// OCP MXFP6 (E2M3 elements): lane group g holds block g of the row, 24 bytes
+// of 6-bit codes (element t of the block in bits 6t .. 6t + 5), in the six
+// low registers of the operand, with that block's E8M0 exponent as the
+// lane's MFMA scale, for A and B alike.
+template <> struct Op<GEM_MXFP6> {
+  static constexpr int kRowBytes = 96;
+  struct Frag { i32x8 v; int scale; };
+  static __device__ __forceinline__ void load(Frag& f, const void* vecs, const float* scales, int64_t row, int g) {
+    const uint2* p = reinterpret_cast<const uint2*>(static_cast<const char*>(vecs) + row * kRowBytes + g * 24);
+    const uint2 a = p[0], b = p[1], c = p[2];
+    f.v = i32x8{(int)a.x, (int)a.y, (int)b.x, (int)b.y, (int)c.x, (int)c.y, 0, 0};
+    f.scale = (int)reinterpret_cast<const uint8_t*>(scales)[row * 4 + g];
+  }
+  static __device__ __forceinline__ void zero(Frag& f) {
+    f.v = i32x8{0, 0, 0, 0, 0, 0, 0, 0};
+    f.scale = 127;
+  }
+  static __device__ __forceinline__ void load_b(Frag& f, const void* v, const float* sc, int64_t row, int g) {
+    load(f, v, sc, row, g);
+  }
+  static constexpr bool kColumnScale = false;
+  static __device__ __forceinline__ f32x4 mma(const Frag& a, const Frag& b, f32x4 acc, int) {
+    // E2M3 for both operands (format code 2); each lane's block exponent
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a.v, b.v, acc, 2, 2, 0, a.scale, 0, b.scale);
+  }
+  static constexpr int kSteps = 1;
+};
+
 }  // namespace gem

@@ -36,6 +36,7 @@ template <> struct DenseCfg<GEM_F32> { static constexpr int kNT = 4; static cons
 template <> struct DenseCfg<GEM_BF16> { static constexpr int kNT = 8; static constexpr int kGroup = 8; };
 template <> struct DenseCfg<GEM_FP8_E4M3> { static constexpr int kNT = 16; static constexpr int kGroup = 8; };
 template <> struct DenseCfg<GEM_MXFP4> { static constexpr int kNT = 16; static constexpr int kGroup = 8; };
+template <> struct DenseCfg<GEM_MXFP6> { static constexpr int kNT = 16; static constexpr int kGroup = 8; };
 
 int dense_pass_rows(int dtype) {
   switch (dtype) {
@@ -247,15 +248,18 @@ struct DenseParams {
 };
 
 // LDS image of one 16-row tile: row r at r * kRowBytes, 16-byte chunk c at
-// position c ^ swz(r); FP8 tiles are followed by their 16 row scales.
+// position c ^ swz(r); FP8 and MX tiles are followed by their 16 row scales.
+// MXFP6 rows (96 bytes in memory) are staged as 128-byte rows: chunks 6 and 7
+// of a row repeat its chunk 5 and are never read.
 template <int DT> struct TileStage {
   using O = Op<DT>;
-  static constexpr int kRowBytes = O::kRowBytes;
+  static constexpr int kRowBytes = DT == GEM_MXFP6 ? 128 : O::kRowBytes;
+  static constexpr int kGlobalChunks = O::kRowBytes / 16;      // chunks of a row in memory
   static constexpr int kChunksPerRow = kRowBytes / 16;
   static constexpr int kTileBytes = 16 * kRowBytes;
   static constexpr int kSlots = kTileBytes / 16;                 // 16-byte pieces per tile
   static constexpr int kPieceWaves = kSlots / 64;                // waves copying one piece per lane
-  static constexpr bool kScales = DT == GEM_FP8_E4M3 || DT == GEM_MXFP4;   // one 32-bit scale word per row
+  static constexpr bool kScales = DT == GEM_FP8_E4M3 || DT == GEM_MXFP4 || DT == GEM_MXFP6;   // a scale word per row
   static constexpr int kCopyWaves = kPieceWaves + (kScales ? 1 : 0);   // waves busy copying one tile
   // FP8: the tile's 16 row scales, copied by a whole wave (lanes past 16 fill
   // the rest of the slot with repeats)
@@ -287,6 +291,12 @@ template <int DT> struct TileStage {
   static __device__ __forceinline__ int swz(int r) {
     return kRowBytes == 64 ? ((r >> 2) & 3) : (kRowBytes == 128 ? ((r >> 1) & 7) : (r & 15));
   }
+  // the memory chunk copied into LDS chunk c (the padding chunks of a staged
+  // MXFP6 row repeat the row's last chunk)
+  static __device__ __forceinline__ int mem_chunk(int c) {
+    if constexpr (kGlobalChunks < kChunksPerRow) return min(c, kGlobalChunks - 1);
+    else return c;
+  }
 
   // Piece `role` (1 KiB) of tile k of the document whose rows are
   // base + [rs, re), into `stage`.
@@ -294,9 +304,9 @@ template <int DT> struct TileStage {
                                                     u32x4* stage, int role, int l) {
     const int slot = 64 * role + l;
     const int r = slot / kChunksPerRow, pos = slot % kChunksPerRow;
-    const int c = pos ^ swz(r);
+    const int c = mem_chunk(pos ^ swz(r));
     const int64_t row = base + min(rs + 16 * k + r, re - 1);
-    __builtin_amdgcn_global_load_lds(static_cast<const char*>(vecs) + row * kRowBytes + c * 16,
+    __builtin_amdgcn_global_load_lds(static_cast<const char*>(vecs) + row * O::kRowBytes + c * 16,
                                      (lds_void_ptr)(stage + 64 * role), 16, 0, 0);
   }
   // Code sets: the same piece, when the lane's row of the vector array is
@@ -305,8 +315,8 @@ template <int DT> struct TileStage {
                                                         int l) {
     const int slot = 64 * role + l;
     const int r = slot / kChunksPerRow, pos = slot % kChunksPerRow;
-    const int c = pos ^ swz(r);
-    __builtin_amdgcn_global_load_lds(static_cast<const char*>(vecs) + vrow * kRowBytes + c * 16,
+    const int c = mem_chunk(pos ^ swz(r));
+    __builtin_amdgcn_global_load_lds(static_cast<const char*>(vecs) + vrow * O::kRowBytes + c * 16,
                                      (lds_void_ptr)(stage + 64 * role), 16, 0, 0);
   }
   // Entry index whose row lane l copies in piece `role` of tile k.
@@ -361,6 +371,21 @@ __device__ __forceinline__ void frag_from_lds<GEM_MXFP4>(Op<GEM_MXFP4>::Frag& f,
   const u32x4 v = stage[c16 * 4 + (g ^ ((c16 >> 2) & 3))];
   const uint32_t sc = reinterpret_cast<const uint32_t*>(stage + 64)[c16];
   f.v = i32x4{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+  f.scale = (int)((sc >> (8 * g)) & 0xffu);
+}
+
+// MXFP6: block g (24 bytes) of the staged 128-byte row is chunk 3h (whole)
+// and the low half of chunk 3h + 1 for g = 2h, the high half of chunk 3h + 1
+// and chunk 3h + 2 (whole) for g = 2h + 1.
+template <>
+__device__ __forceinline__ void frag_from_lds<GEM_MXFP6>(Op<GEM_MXFP6>::Frag& f, const u32x4* stage, int c16, int g) {
+  const u32x4* row = stage + c16 * 8;
+  const int sw = (c16 >> 1) & 7, h = g >> 1, odd = g & 1;
+  const u32x4 w = row[(3 * h + 2 * odd) ^ sw];
+  const uint2 m = reinterpret_cast<const uint2*>(row + ((3 * h + 1) ^ sw))[odd];
+  const uint32_t sc = reinterpret_cast<const uint32_t*>(stage + 128)[c16];
+  f.v = odd ? i32x8{(int)m.x, (int)m.y, (int)w.x, (int)w.y, (int)w.z, (int)w.w, 0, 0}
+            : i32x8{(int)w.x, (int)w.y, (int)w.z, (int)w.w, (int)m.x, (int)m.y, 0, 0};
   f.scale = (int)((sc >> (8 * g)) & 0xffu);
 }
 
@@ -1021,6 +1046,10 @@ static void launch_dense_variant(int dtype, bool codes, int32_t block_rows, dim3
       if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_MXFP4, true, kTopk>), grid, blk, 0, s, P);
       else hipLaunchKernelGGL((score_dense_kernel<GEM_MXFP4, false, kTopk>), grid, blk, 0, s, P);
       break;
+    case GEM_MXFP6:
+      if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_MXFP6, true, kTopk>), grid, blk, 0, s, P);
+      else hipLaunchKernelGGL((score_dense_kernel<GEM_MXFP6, false, kTopk>), grid, blk, 0, s, P);
+      break;
     default: break;
   }
 }
@@ -1039,7 +1068,8 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
   if (P.n_bgroups == 0 || P.n_chunks == 0) return hipSuccess;
   if (sched.chunk_docs < 1 || sched.chunk_docs > kMaxChunkDocs || sched.items_per_slot < 1 || sched.slots_per_xcd < 1)
     return hipErrorInvalidValue;
-  if (dtype != GEM_F32 && dtype != GEM_BF16 && dtype != GEM_FP8_E4M3 && dtype != GEM_MXFP4) return hipErrorInvalidValue;
+  if (dtype != GEM_F32 && dtype != GEM_BF16 && dtype != GEM_FP8_E4M3 && dtype != GEM_MXFP4 && dtype != GEM_MXFP6)
+    return hipErrorInvalidValue;
   const dim3 grid((unsigned)(8 * sched.slots_per_xcd)), blk(kDenseThreads);
   const bool codes = D.codes != nullptr;
   if (out.tk.k > 0) {
@@ -1064,19 +1094,21 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
 constexpr int kGatherEntries = 16;
 constexpr int kGatherNT = 4;
 // Tiles in flight per wave: the choices of each format (registers: a float32
-// tile fragment takes 32 VGPRs, bf16 16, FP8 9, MXFP4 5); the middle one is
-// the default.
+// tile fragment takes 32 VGPRs, bf16 16, FP8 9, MXFP6 7, MXFP4 5); the middle
+// one is the default.
 template <int DT> struct GatherDepths;
 template <> struct GatherDepths<GEM_F32> { static constexpr int d[3] = {1, 2, 3}; };
 template <> struct GatherDepths<GEM_BF16> { static constexpr int d[3] = {2, 4, 6}; };
 template <> struct GatherDepths<GEM_FP8_E4M3> { static constexpr int d[3] = {4, 6, 8}; };
 template <> struct GatherDepths<GEM_MXFP4> { static constexpr int d[3] = {6, 8, 12}; };
+template <> struct GatherDepths<GEM_MXFP6> { static constexpr int d[3] = {4, 6, 8}; };
 
 int gather_depth_choice(int dtype, int i) {
   switch (dtype) {
     case GEM_F32: return GatherDepths<GEM_F32>::d[i];
     case GEM_BF16: return GatherDepths<GEM_BF16>::d[i];
     case GEM_FP8_E4M3: return GatherDepths<GEM_FP8_E4M3>::d[i];
+    case GEM_MXFP6: return GatherDepths<GEM_MXFP6>::d[i];
     default: return GatherDepths<GEM_MXFP4>::d[i];
   }
 }
@@ -1312,6 +1344,7 @@ static hipError_t run_gather(int dtype, GatherParams P, int64_t max_list_len, co
       case GEM_BF16: ok = launch_gather_depth<GEM_BF16>(depth, codes, gr, blk, P, s); break;
       case GEM_FP8_E4M3: ok = launch_gather_depth<GEM_FP8_E4M3>(depth, codes, gr, blk, P, s); break;
       case GEM_MXFP4: ok = launch_gather_depth<GEM_MXFP4>(depth, codes, gr, blk, P, s); break;
+      case GEM_MXFP6: ok = launch_gather_depth<GEM_MXFP6>(depth, codes, gr, blk, P, s); break;
       default: break;
     }
     if (!ok) return hipErrorInvalidValue;

@@ -21,7 +21,7 @@ from typing import List, Optional, Sequence
 
 import torch
 
-from . import GEM_FP8_E4M3, GEM_MXFP4, Beam, Cands, Sets, expand_batch, expand_workspace_bytes, score_exact
+from . import GEM_FP8_E4M3, GEM_MXFP4, GEM_MXFP6, Beam, Cands, Sets, expand_batch, expand_workspace_bytes, score_exact
 
 
 def _on_stream(stream):
@@ -33,8 +33,9 @@ class ExpansionGraph:
     """`steps` beam-expansion steps over fixed candidate lists, recorded into a graph."""
 
     def __init__(self, Q8: Sets, D8: Sets, steps: Sequence[Cands], ef: int, stream=None):
-        if Q8.dtype != D8.dtype or D8.dtype not in (GEM_FP8_E4M3, GEM_MXFP4):
-            raise TypeError("Q8 and D8 must both be FP8 or both MXFP4 (quantize the queries once, outside the graph)")
+        if Q8.dtype != D8.dtype or D8.dtype not in (GEM_FP8_E4M3, GEM_MXFP4, GEM_MXFP6):
+            raise TypeError("Q8 and D8 must share one quantized format, FP8, MXFP4 or MXFP6 (quantize the queries "
+                            "once, outside the graph)")
         self.Q8, self.D8, self.steps = Q8, D8, list(steps)
         self.device = D8.device
         self.beam = Beam(Q8.n_sets, ef, self.device)
