@@ -728,6 +728,8 @@ def main():
                     help="FP8 shortlist reranked per serving request (default: the serving workload's)")
     ap.add_argument("--serve-shortlists", type=str, default="100,200,300,500,1000",
                     help="shortlist lengths whose recall is measured on the serving query mix")
+    ap.add_argument("--serve-points-only", action="store_true",
+                    help="serve the listed rates only (no memory-limited or 1000-shortlist comparison points)")
     ap.add_argument("--only-serving", action="store_true", help="run the serving leg alone (for profiling)")
     ap.add_argument("--dense-only", action="store_true",
                     help="run the bf16 / FP8 / MXFP4 dense scorers alone (for counter runs)")
@@ -773,8 +775,9 @@ def main():
         copy_calibration()
     if not args.skip_serving:
         D8, D32 = keep
-        line["serving_shortlist_recall"] = serving_shortlist_recall(
-            D8, D32, [int(x) for x in args.serve_shortlists.split(",") if x])
+        sls = [int(x) for x in args.serve_shortlists.split(",") if x]
+        if sls:
+            line["serving_shortlist_recall"] = serving_shortlist_recall(D8, D32, sls)
         line["serving"] = []
         for ri, rate in enumerate([float(r) for r in args.serve_rates.split(",") if r]):
             log(f"serving at {rate:.0f} requests/s")
@@ -782,7 +785,7 @@ def main():
             n_req = min(args.serve_max_requests, max(args.serve_requests, int(rate * 1.25)))
             line["serving"].append(bench_serving(D8, D32, rate=rate, n_req=n_req, rate_idx=ri,
                                                shortlist=args.serve_shortlist))
-        if args.serve_rates:
+        if args.serve_rates and not args.serve_points_only:
             # a device-memory budget for 256 requests' state at 32,000/s: the
             # memory check, not the slot count, is what refuses requests
             log("serving at 32000 requests/s with a device budget of 256 requests")
