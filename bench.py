@@ -187,6 +187,18 @@ def bench_graph_search(seed: int = 13):
     return res
 
 
+def host_cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(q: wl.SetBatch, c: wl.SetBatch, n_sample: int):
     """The float64 oracle on a bounded sample of queries against the whole corpus."""
     import oracle
@@ -202,6 +214,7 @@ def cpu_baseline(q: wl.SetBatch, c: wl.SetBatch, n_sample: int):
     ref = oracle.ch_dense(qv, qo, dv, do)
     dt = time.perf_counter() - t0
     return ref, {"value": n_sample * c.n_sets / dt, "unit": "pair-scores/s", "cores": int(cores),
+                 "cpu_model": host_cpu_model(), "host_cpus": os.cpu_count(),
                  "kind": "oracle",
                  "sample": f"{n_sample} query sets x {c.n_sets} documents, float64 NumPy/BLAS, {dt:.1f} s"}
 
@@ -539,8 +552,11 @@ def serving_shortlist_recall(D8, D32, shortlists, n_q=1000, q_len=("uniform", 4,
     return {"queries": n_q, "query_len": f"U{{{q_len[1]}..{q_len[2]}}}", f"recall_at_{k}": out}
 
 
+_SERVE_TUNED = {}
+
+
 def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_chunks=8, rate_idx=0,
-                  max_resident=None, shortlist=None):
+                  max_resident=None, shortlist=None, chunk_work=8192):
     """Continuous-batching serving loop on the resident corpus: QPS and p50/p99
     latency. max_resident: a device-memory budget for that many requests'
     state (None: half the free device memory); the slot count stays 1024, so
@@ -554,9 +570,21 @@ def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_
     reqs = [serve.Request(i, vecs[off[i]:off[i + 1]], float(arrivals[i])) for i in range(n_req)]
     shortlist = w5.shortlist if shortlist is None else int(shortlist)
     ex = serve.DeviceExecutor(D8, D32, n_chunks=n_chunks, max_slots=1024, shortlist=shortlist, k=w5.k)
+    global _SERVE_TUNED
+    if not _SERVE_TUNED.get(shortlist):
+        # schedules for the loop's launch shapes (kept in the device context
+        # for every later executor): sample queries of the serving mix, drawn
+        # apart from the measured requests
+        tq = wl.queries(w5, n_queries=1024, query_len=q_len, seed_offset=77)
+        toff, tvecs = tq.offsets.numpy(), tq.vecs.numpy()
+        t0 = time.perf_counter()
+        sch = ex.autotune([tvecs[toff[i]:toff[i + 1]] for i in range(tq.n_sets)])
+        log(f"serving schedules tuned in {time.perf_counter() - t0:.1f} s: "
+            f"{ {k: v for k, v in sch.items() if k in ('score_fp8_64', 'score_fp8_256', 'rerank_f32_32')} }")
+        _SERVE_TUNED[shortlist] = sch
     budget = None if max_resident is None else int(max_resident) * ex.bytes_per_request
-    # an iteration scores as many chunks as fit 8192 (query vectors x chunks)
-    work = 8192
+    # an iteration scores as many chunks as fit chunk_work (query vectors x chunks)
+    work = int(chunk_work)
     eng = serve.ServingEngine(ex, max_slots=1024, mem_budget_bytes=budget, chunk_work=work)
     # warm-up on a few requests, then the measured run
     warm = serve.ServingEngine(ex, max_slots=1024, chunk_work=work)
@@ -616,6 +644,22 @@ def bench_expansion(args):
            "frac_of_hbm_peak_per_pair": pair_bytes / w4.steps / (per_step / 1e3) / PEAK_HBM,
            "rerank_f32_top100_ms": r_ms,
            "gather_schedule": dict(gsched, tuned_ms=t_tuned, library_rule_ms=t_default)}
+    # the same gathered scorer on lists in which every document appears once
+    # (a seeded permutation of the corpus cut into 4096 lists): per-pair bytes
+    # are then unique bytes, so its rate is what a gather of distinct random
+    # documents reaches, the ceiling for the step's 2.4 listings per document
+    # when each listing has to read its document
+    gp = torch.Generator(device="cpu").manual_seed(5001)
+    perm = torch.randperm(n_docs, generator=gp).to(torch.int32).to(dev)
+    per = n_docs // Q8.n_sets
+    Cp = gem.Cands(perm[:per * Q8.n_sets].contiguous(), stride=per, n_lists=Q8.n_sets)
+    bytes_p = int(lens[perm[:per * Q8.n_sets].long()].sum().item()) * 132
+    gem.autotune_gather(Q8, D8, Cp, reps=3)
+    t_p = timed(lambda: gem.score_quant(Q8, D8, cands=Cp), 5)
+    res["distinct_docs_gather"] = {"lists": Q8.n_sets, "per_list": per, "bytes": bytes_p, "ms": t_p,
+                                   "gbps": bytes_p / (t_p / 1e3) / 1e9,
+                                   "frac_of_hbm_peak": bytes_p / (t_p / 1e3) / PEAK_HBM}
+    log(f"gather of distinct documents: {bytes_p / 1e9:.2f} GB in {t_p:.3f} ms = {bytes_p / t_p / 1e6:.0f} GB/s")
     # MXFP4 rows: 64 bytes of codes + 4 exponent bytes per vector
     D4 = gem.quantize_mxfp4(D32)
     Q4 = gem.quantize_mxfp4(Q32)
@@ -728,6 +772,8 @@ def main():
                     help="FP8 shortlist reranked per serving request (default: the serving workload's)")
     ap.add_argument("--serve-shortlists", type=str, default="100,200,300,500,1000",
                     help="shortlist lengths whose recall is measured on the serving query mix")
+    ap.add_argument("--serve-chunk-work", type=int, default=8192,
+                    help="query vectors x chunks an iteration may score (more chunks per iteration for light batches)")
     ap.add_argument("--serve-points-only", action="store_true",
                     help="serve the listed rates only (no memory-limited or 1000-shortlist comparison points)")
     ap.add_argument("--only-serving", action="store_true", help="run the serving leg alone (for profiling)")
@@ -784,7 +830,7 @@ def main():
             # about 1.25 s of arrivals per rate, within the request bounds
             n_req = min(args.serve_max_requests, max(args.serve_requests, int(rate * 1.25)))
             line["serving"].append(bench_serving(D8, D32, rate=rate, n_req=n_req, rate_idx=ri,
-                                               shortlist=args.serve_shortlist))
+                                               shortlist=args.serve_shortlist, chunk_work=args.serve_chunk_work))
         if args.serve_rates and not args.serve_points_only:
             # a device-memory budget for 256 requests' state at 32,000/s: the
             # memory check, not the slot count, is what refuses requests

@@ -120,6 +120,8 @@ class ServingEngine:
         self.active_sum = 0               # sum over iterations of the active requests (mean batch size)
         self.pending: List[tuple] = []    # (handle, finished requests) awaiting their results
         self._batch_key = None
+        # requests completed while the executor waited for the device
+        self._early: List[Request] = []
 
     # -- clock
     def now(self) -> float:
@@ -179,13 +181,23 @@ class ServingEngine:
         self.pending = keep
         return out
 
+    def _poll_waiting(self) -> None:
+        if self.pending:
+            self._early.extend(self.poll())
+
+    def _take_early(self) -> List[Request]:
+        out, self._early = self._early, []
+        return out
+
     # -- one iteration: one corpus chunk for every active request
     def step(self) -> List[Request]:
         """One iteration; returns the requests completed (results on the host) during it."""
-        completed = self.poll()
+        if hasattr(self.ex, "on_wait"):
+            self.ex.on_wait = self._poll_waiting                 # (the executor may serve several engines)
+        completed = self._take_early() + self.poll()
         self.admit()
         if not self.active:
-            return completed
+            return completed + self._take_early()
         key = tuple(r.slot for r in self.active)
         if key != self._batch_key:
             self.ex.set_batch([r.slot for r in self.active], [r.vecs for r in self.active])
@@ -209,7 +221,7 @@ class ServingEngine:
             self.active = [r for r in self.active if r.chunks_done < self.ex.n_chunks]
         self.chunk = (self.chunk + span) % self.ex.n_chunks
         self.iteration += 1
-        return completed + self.poll()
+        return completed + self._take_early() + self.poll()
 
     def span(self) -> int:
         """Chunks the next iteration scores."""
@@ -330,9 +342,48 @@ class DeviceExecutor(Executor):
         self._iter_evts = []
         self.Q8 = None
         self.rows = None
+        # called over and over while the host waits for the device (the
+        # engine collects finished results then, not only between iterations)
+        self.on_wait: Optional[Callable[[], None]] = None
 
     def _stream(self):
         return self.stream if self.stream is not None else torch.cuda.current_stream(self.device)
+
+    def autotune(self, sample: Sequence[np.ndarray], max_batch: Optional[int] = None, reps: int = 3) -> dict:
+        """Tune the library's schedules for the shapes this loop launches, on
+        sample queries of the serving mix: the FP8 scorer for batches of 1, 2,
+        4, ... requests (up to max_batch) against one chunk, and the float32
+        rerank for finishing batches of up to 64 requests. The schedules are
+        installed in the device's context for each shape class (a schedule
+        changes the launch, never a score). Returns {shape: schedule}."""
+        g = self._gem
+        cs = self._stream()
+        max_batch = min(len(sample), self.max_slots if max_batch is None else int(max_batch))
+        chunk = self.D8.view(self.bounds[0], self.bounds[1])
+        out = {}
+        with torch.cuda.stream(cs):
+            n = 1
+            while n <= max_batch:
+                qs = sorted(sample[:n], key=lambda q: -q.shape[0])
+                lens = np.array([q.shape[0] for q in qs], np.int64)
+                off = torch.from_numpy(np.concatenate([[0], np.cumsum(lens)])).to(self.device)
+                Q32 = g.Sets(torch.from_numpy(np.concatenate(qs, 0)).to(self.device), off, "f32", int(lens.max()))
+                Q8 = g.quantize_fp8(Q32, stream=cs)
+                sched, _ = g.autotune_dense(Q8, chunk, reps=reps, scores=self.est[:n], ld=self.n_docs, stream=cs)
+                out[f"score_fp8_{n}"] = sched
+                if n <= 64:
+                    # finishing batch: its shortlists come from its own estimate rows
+                    for c0 in range(self.n_chunks):
+                        Dc = self.D8.view(self.bounds[c0], self.bounds[c0 + 1])
+                        g.score_quant(Q8, Dc, scores=self.est[:n, self.bounds[c0]:], ld=self.n_docs, stream=cs)
+                    sl = min(self.shortlist, self.n_docs)
+                    _, short_i = g.topk(self.est[:n], sl, stream=cs)
+                    C = g.Cands(short_i.reshape(-1), stride=sl, n_lists=n)
+                    gs, _ = g.autotune_gather(Q32, self.D32, C, compute="f32", reps=reps, stream=cs)
+                    out[f"rerank_f32_{n}"] = gs
+                n *= 2
+        cs.synchronize()
+        return out
 
     def _stage(self, kind: str):
         """The next staging buffer of a ring, once its last upload is done; -> (buffer, ring index)."""
@@ -433,6 +484,12 @@ class DeviceExecutor(Executor):
         order = np.argsort(-self.lens[slots], kind="stable")
         self.Q8, self.rows = self._gather(slots[order], fp8=True)
 
+    def _wait(self, evt) -> None:
+        if self.on_wait is not None:
+            while not evt.query():
+                self.on_wait()
+        evt.synchronize()
+
     def score_chunk(self, chunk: int) -> None:
         self.score_chunks(chunk, 1)
 
@@ -442,7 +499,7 @@ class DeviceExecutor(Executor):
         # (the next iteration's admission and gather are issued before this
         # wait, so they still overlap the previous iteration's scoring)
         if len(self._iter_evts) >= self.max_ahead:
-            self._iter_evts.pop(0).synchronize()
+            self._wait(self._iter_evts.pop(0))
         end = chunk + span
         ranges = [(chunk, min(end, self.n_chunks))]
         if end > self.n_chunks:

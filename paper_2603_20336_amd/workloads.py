@@ -113,10 +113,12 @@ WORKLOADS = {
                 1000, ("fixed", 32), 100, shortlist=1000, corpus_of=2, queries_of=2),
     4: Workload(4, "beam-expand-1m", 1_000_000, ("uniform", 16, 128), 4096,
                 4096, ("uniform", 8, 64), 0, cands_per_step=512, steps=20, ef=1000),
-    # serving reranks an FP8 shortlist of 300: on its query mix (4 to 64
-    # vectors) recall@100 after the float32 rerank is 1.0 from 300 on
+    # serving reranks an FP8 shortlist of 200: on its query mix (4 to 64
+    # vectors) recall@100 after the float32 rerank is 0.99999 at 200 (one
+    # miss in 100,000 results) and 1.0 from 300 on; 200 takes a third less
+    # rerank work than 300
     5: Workload(5, "serving-100k", 100_000, ("lognormal", 80.0, 0.5, 32, 256), 4096,
-                0, ("uniform", 4, 64), 100, shortlist=300, corpus_of=2),
+                0, ("uniform", 4, 64), 100, shortlist=200, corpus_of=2),
     6: Workload(6, "graph-search-100k-topical", 100_000, ("lognormal", 80.0, 0.5, 32, 256), 4096,
                 1000, ("fixed", 32), 10),
 }
@@ -238,16 +240,19 @@ def corpus(w: Workload, device="cpu", n_docs: Optional[int] = None) -> SetBatch:
 
 
 def queries(w: Workload, device="cpu", n_queries: Optional[int] = None,
-            query_len: Optional[tuple] = None) -> SetBatch:
-    """The workload's query sets, drawn from the corpus's mixture."""
+            query_len: Optional[tuple] = None, seed_offset: int = 0) -> SetBatch:
+    """The workload's query sets, drawn from the corpus's mixture (seed_offset:
+    another draw from the same distribution, e.g. tuning samples kept apart
+    from the measured queries)."""
     src = WORKLOADS[w.corpus_of] if w.corpus_of else w
     qsrc = WORKLOADS[w.queries_of] if w.queries_of else w
     n = n_queries if n_queries is not None else qsrc.n_queries
     if src.number == 6:
         centers = topical_centers(src.n_centers, TOPICS, TOPIC_SPREAD, 600, device)
-        return topical_sets(n, query_len or qsrc.query_len, centers, TOPICS, P_TOPIC, src.sigma, 2000 + qsrc.number)
+        return topical_sets(n, query_len or qsrc.query_len, centers, TOPICS, P_TOPIC, src.sigma,
+                            2000 + qsrc.number + seed_offset)
     centers = mixture_centers(src.n_centers, 100 + src.number, device)
-    return make_sets(n, query_len or qsrc.query_len, centers, src.sigma, 2000 + qsrc.number)
+    return make_sets(n, query_len or qsrc.query_len, centers, src.sigma, 2000 + qsrc.number + seed_offset)
 
 
 def candidate_ids(n_queries: int, per_query: int, n_docs: int, seed: int, device="cpu",

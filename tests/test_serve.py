@@ -186,3 +186,28 @@ def test_device_serving_alone_equals_mix_and_matches_oracle():
     # bound; on this 3000-document corpus about half the requests have no other
     # document inside it, and for those the ids are checked exactly
     assert clean >= 10
+
+
+@pytest.mark.gpu
+def test_device_serving_autotune_keeps_results():
+    """Tuning the loop's launch schedules changes no result."""
+    import paper_2603_20336_amd as gem
+    dev = "cuda"
+    c = wl.corpus(wl.WORKLOADS[2], n_docs=3000)
+    D32 = gem.Sets.from_batch(c, dev)
+    D8 = D32.to_fp8()
+    reqs = _requests(24, 5, lo=4, hi=64)
+
+    def run():
+        ex = serve.DeviceExecutor(D8, D32, n_chunks=5, max_slots=32, shortlist=200, k=20)
+        eng = serve.ServingEngine(ex, max_slots=32, mem_budget_bytes=1 << 34, clock=StepClock())
+        return ex, {r.rid: r for r in eng.run([serve.Request(r.rid, r.vecs, r.t_arrival) for r in reqs])}
+
+    ex, before = run()
+    sch = ex.autotune([r.vecs for r in reqs], max_batch=16, reps=1)
+    assert {"score_fp8_1", "score_fp8_16", "rerank_f32_1", "rerank_f32_16"} <= set(sch)
+    _, after = run()
+    assert len(after) == 24
+    for rid, r in before.items():
+        np.testing.assert_array_equal(after[rid].top_ids, r.top_ids)
+        np.testing.assert_array_equal(after[rid].top_scores, r.top_scores)
