@@ -286,10 +286,19 @@ template <int DT> struct TileStage {
   static __device__ __forceinline__ int wave_piece(int w, int j) { return (w * kPieceCopiesPerWave + j) % kPieceWaves; }
   static_assert(kStageBytes % 16 == 0, "stage alignment");
 
-  // chunk c of row r sits at position c ^ swz(r): the 16 rows read by one
-  // 16-lane group then cover all 64 banks (128-byte rows pair up first)
+  // chunk c of row r sits at position c ^ swz(r). A 16-byte LDS read serves
+  // its 64 lanes in two halves of 32 lanes (16 rows x two lane groups), and a
+  // half runs without bank conflicts when its 32 reads fall in 32 distinct
+  // 16-byte columns of the 512-byte bank space. For 256- and 512-byte rows the
+  // plain row XOR (r & 15) maps the two lane groups of a half onto the same
+  // columns (measured: twice the cycles of a conflict-free read); the forms
+  // below keep the two groups apart. 64-byte rows interleave four rows and
+  // 128-byte rows pair up first.
   static __device__ __forceinline__ int swz(int r) {
-    return kRowBytes == 64 ? ((r >> 2) & 3) : (kRowBytes == 128 ? ((r >> 1) & 7) : (r & 15));
+    if constexpr (kRowBytes == 64) return (r >> 2) & 3;
+    else if constexpr (kRowBytes == 128) return (r >> 1) & 7;
+    else if constexpr (kRowBytes == 256) return ((r >> 1) & 3) | (r & 8) | ((r & 1) << 2);
+    else return (r & 7) | ((r & 8) << 1);
   }
   // the memory chunk copied into LDS chunk c (the padding chunks of a staged
   // MXFP6 row repeat the row's last chunk)
@@ -351,8 +360,9 @@ __device__ __forceinline__ void frag_from_lds(typename Op<DT>::Frag& f, const u3
 template <>
 __device__ __forceinline__ void frag_from_lds<GEM_BF16>(Op<GEM_BF16>::Frag& f, const u32x4* stage, int c16, int g) {
   const u32x4* row = stage + c16 * 16;
+  const int sw = TileStage<GEM_BF16>::swz(c16);
 #pragma unroll
-  for (int s = 0; s < 4; ++s) f.v[s] = __builtin_bit_cast(bf16x8, row[(4 * g + s) ^ c16]);
+  for (int s = 0; s < 4; ++s) f.v[s] = __builtin_bit_cast(bf16x8, row[(4 * g + s) ^ sw]);
 }
 
 template <>
@@ -392,9 +402,10 @@ __device__ __forceinline__ void frag_from_lds<GEM_MXFP6>(Op<GEM_MXFP6>::Frag& f,
 template <>
 __device__ __forceinline__ void frag_from_lds<GEM_F32>(Op<GEM_F32>::Frag& f, const u32x4* stage, int c16, int g) {
   const u32x4* row = stage + c16 * 32;
+  const int sw = TileStage<GEM_F32>::swz(c16);
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
-    const u32x4 v = row[(8 * g + s) ^ c16];
+    const u32x4 v = row[(8 * g + s) ^ sw];
     f.v[4 * s + 0] = __uint_as_float(v.x); f.v[4 * s + 1] = __uint_as_float(v.y);
     f.v[4 * s + 2] = __uint_as_float(v.z); f.v[4 * s + 3] = __uint_as_float(v.w);
   }
