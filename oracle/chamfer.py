@@ -20,6 +20,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from .codecs import bf16_decode, split_bf16x3
+
 NEG_INF = -np.inf
 
 
@@ -47,14 +49,34 @@ def _segment_max_cols(S: np.ndarray, starts: np.ndarray, lens: np.ndarray) -> np
     return out
 
 
-def ch_dense(q_vecs, q_offsets, d_vecs, d_offsets, max_rows: int = 1 << 20) -> np.ndarray:
+def _dot_plain(A: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """<a, p> for every row a of A and p of D."""
+    return _f64(A) @ _f64(D).T
+
+
+def _split_parts(X) -> tuple[np.ndarray, np.ndarray]:
+    hi, lo = split_bf16x3(X)
+    return bf16_decode(hi), bf16_decode(lo)
+
+
+def _dot_bf16x3(A: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """The split-bfloat16 inner products: with a = ah + al + ea and p = ph + pl + ep
+    (codecs.split_bf16x3), <a, p> taken as <ah, ph> + <ah, pl> + <al, ph>, every
+    term exact (float64 here), the al*pl and ea / ep terms dropped."""
+    ah, al = _split_parts(A)
+    ph, pl = _split_parts(D)
+    return ah @ ph.T + (ah @ pl.T + al @ ph.T)
+
+
+def ch_dense(q_vecs, q_offsets, d_vecs, d_offsets, max_rows: int = 1 << 20, dot=_dot_plain) -> np.ndarray:
     """CH(Q_i, P_j) for every query set i and document set j -> [n_q, n_d] float64.
 
     The problem statement of Sec. 3.1 ranks every document of the database by
     CH; this is that full score matrix. Documents are processed in groups of at
-    most `max_rows` vectors to bound memory.
+    most `max_rows` vectors to bound memory. `dot` gives the matrix of inner
+    products of two row blocks (the exact one by default).
     """
-    qv, dv = _f64(q_vecs), np.asarray(d_vecs)
+    qv, dv = np.asarray(q_vecs), np.asarray(d_vecs)
     qo, do = np.asarray(q_offsets, np.int64), np.asarray(d_offsets, np.int64)
     n_q, n_d = len(qo) - 1, len(do) - 1
     out = np.zeros((n_q, n_d))
@@ -68,7 +90,7 @@ def ch_dense(q_vecs, q_offsets, d_vecs, d_offsets, max_rows: int = 1 << 20) -> n
         j = j1
     for (j0, j1) in groups:
         r0, r1 = do[j0], do[j1]
-        D = _f64(dv[r0:r1])
+        D = dv[r0:r1]
         starts = do[j0:j1] - r0
         lens = do[j0 + 1:j1 + 1] - do[j0:j1]
         for i in range(n_q):
@@ -76,20 +98,20 @@ def ch_dense(q_vecs, q_offsets, d_vecs, d_offsets, max_rows: int = 1 << 20) -> n
             if A.shape[0] == 0:
                 out[i, j0:j1] = 0.0
                 continue
-            S = A @ D.T                                  # <a, p> for all a in Q_i, p in group
+            S = dot(A, D)                                # <a, p> for all a in Q_i, p in group
             r = _segment_max_cols(S, starts, lens)       # max over p in each document
             out[i, j0:j1] = r.sum(axis=0)                # sum over a in Q_i
     return out
 
 
-def ch_cands(q_vecs, q_offsets, d_vecs, d_offsets, cand_offsets, cand_ids) -> np.ndarray:
+def ch_cands(q_vecs, q_offsets, d_vecs, d_offsets, cand_offsets, cand_ids, dot=_dot_plain) -> np.ndarray:
     """CH(Q_i, P_id) for every entry of each query's candidate list -> flat float64.
 
     The candidate lists stand for the neighbours a beam-search step scores
     (Alg. 5, neighbour loop) or for the shortlist that is reranked by exact CH
-    (Alg. 5, final step).
+    (Alg. 5, final step). `dot` as in ch_dense.
     """
-    qv, dv = _f64(q_vecs), np.asarray(d_vecs)
+    qv, dv = np.asarray(q_vecs), np.asarray(d_vecs)
     qo, do = np.asarray(q_offsets, np.int64), np.asarray(d_offsets, np.int64)
     co, ci = np.asarray(cand_offsets, np.int64), np.asarray(cand_ids, np.int64)
     out = np.zeros(len(ci))
@@ -104,12 +126,24 @@ def ch_cands(q_vecs, q_offsets, d_vecs, d_offsets, cand_offsets, cand_ids) -> np
             continue
         lens = do[ids + 1] - do[ids]
         rows = np.concatenate([np.arange(do[d], do[d + 1]) for d in ids]) if lens.sum() else np.zeros(0, np.int64)
-        G = _f64(dv[rows])
+        G = dv[rows]
         starts = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
-        S = A @ G.T
+        S = dot(A, G)
         r = _segment_max_cols(S, starts, lens)
         out[a:b] = r.sum(axis=0)
     return out
+
+
+def ch_dense_bf16x3(q_vecs, q_offsets, d_vecs, d_offsets, max_rows: int = 1 << 20) -> np.ndarray:
+    """CH of float32 sets with every inner product taken in the split-bfloat16
+    form (_dot_bf16x3): what the three-bfloat16-product exact mode computes,
+    up to its float32 accumulation."""
+    return ch_dense(q_vecs, q_offsets, d_vecs, d_offsets, max_rows, dot=_dot_bf16x3)
+
+
+def ch_cands_bf16x3(q_vecs, q_offsets, d_vecs, d_offsets, cand_offsets, cand_ids) -> np.ndarray:
+    """ch_cands with the split-bfloat16 inner products."""
+    return ch_cands(q_vecs, q_offsets, d_vecs, d_offsets, cand_offsets, cand_ids, dot=_dot_bf16x3)
 
 
 def _order(scores: np.ndarray, ids: np.ndarray) -> np.ndarray:

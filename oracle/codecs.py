@@ -7,7 +7,8 @@ and the exact paths may run on bfloat16 operands. Everything below is written
 from the format definitions, in plain NumPy:
 
   * bfloat16: the top 16 bits of an IEEE binary32, rounded to nearest, ties to
-    even on the dropped 16 bits.
+    even on the dropped 16 bits; and the split of a float32 into two bfloat16
+    parts (hi, lo) that lets float32 products run as three bfloat16 products.
   * OCP FP8 E4M3 (OCP 8-bit Floating Point Specification, 2023): 1 sign bit,
     4 exponent bits with bias 7, 3 mantissa bits; exponent field 0 encodes
     subnormals 2^-6 * m/8; S.1111.111 is NaN; there is no infinity; the largest
@@ -44,6 +45,17 @@ def bf16_decode(bits) -> np.ndarray:
     """bfloat16 bit patterns (uint16) -> float64 values (exact)."""
     b = np.ascontiguousarray(np.asarray(bits, dtype=np.uint16)).astype(np.uint32) << 16
     return b.view(np.float32).astype(np.float64)
+
+
+def split_bf16x3(x) -> tuple[np.ndarray, np.ndarray]:
+    """float32 array -> bfloat16 bit patterns (hi, lo) of the split x = hi + lo + e:
+    hi = bf16(x), lo = bf16(x - hi), each rounded to nearest even. x - hi is
+    exact in float32 (both are multiples of x's float32 ulp and the difference
+    is at most half a bfloat16 ulp of x), so |e| <= 2^-8 |x - hi| <= 2^-16 |x|."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    hi = bf16_round_bits(x)
+    rest = (x.astype(np.float64) - bf16_decode(hi)).astype(np.float32)
+    return hi, bf16_round_bits(rest)
 
 
 def e4m3_decode(code: int) -> float:

@@ -322,3 +322,87 @@ def test_quantize_fp8_roundtrip_bound():
     # subnormal range: absolute error <= half the subnormal spacing
     sub = ~normal
     assert (np.abs(deq - x)[sub] / np.broadcast_to(scales[:, None], x.shape)[sub]).max() <= 2.0 ** -10 + 1e-15
+
+
+# --- the split of float32 values into two bfloat16 parts (exact mode on
+# three bfloat16 products)
+
+def _bf16_values(rng, n):
+    """Random finite bfloat16 values (as float64) over a wide exponent range."""
+    expo = rng.integers(60, 190, n, dtype=np.uint32) << 23
+    man = rng.integers(0, 2 ** 7, n, dtype=np.uint32) << 16
+    sign = rng.integers(0, 2, n, dtype=np.uint32) << 31
+    return (sign | expo | man).view(np.float32).astype(np.float64)
+
+
+def test_split_bf16x3_round_trips_exact_two_part_values():
+    # x = h + l with bfloat16 h and l, |l| at most a quarter of h's bfloat16
+    # ulp: such an x is a float32 whose nearest bfloat16 is h, and x - h = l
+    # is itself a bfloat16, so the split must return exactly (h, l)
+    rng = np.random.default_rng(21)
+    h = _bf16_values(rng, 20000)
+    ulp = np.ldexp(1.0, np.frexp(np.abs(h))[1] - 8)            # bfloat16 spacing at |h|
+    frac = rng.integers(-2 ** 6, 2 ** 6 + 1, h.size) / 2.0 ** 8  # |l| <= ulp / 4, on an 8-bit grid
+    l = frac * ulp
+    x = (h + l).astype(np.float32)
+    assert (x.astype(np.float64) == h + l).all()                 # representable exactly
+    hi, lo = oracle.split_bf16x3(x)
+    np.testing.assert_array_equal(oracle.bf16_decode(hi), h)
+    np.testing.assert_array_equal(oracle.bf16_decode(lo), l)
+    # a bfloat16 value splits into itself and zero
+    hi, lo = oracle.split_bf16x3(h.astype(np.float32))
+    np.testing.assert_array_equal(oracle.bf16_decode(hi), h)
+    assert (oracle.bf16_decode(lo) == 0.0).all()
+
+
+def test_split_bf16x3_parts_match_torch_and_the_error_bound():
+    rng = np.random.default_rng(22)
+    x = (rng.standard_normal(200000) * 10.0 ** rng.integers(-20, 20, 200000)).astype(np.float32)
+    hi, lo = oracle.split_bf16x3(x)
+    t = torch.from_numpy(x)
+    th = t.to(torch.bfloat16)
+    rest = t - th.to(torch.float32)                               # exact in float32
+    np.testing.assert_array_equal(hi, th.view(torch.int16).numpy().view(np.uint16))
+    np.testing.assert_array_equal(lo, rest.to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16))
+    err = np.abs(x.astype(np.float64) - oracle.bf16_decode(hi) - oracle.bf16_decode(lo))
+    assert (err <= 2.0 ** -16 * np.abs(x.astype(np.float64))).all()
+
+
+def test_ch_bf16x3_reduces_to_ch_on_bfloat16_values_and_stays_within_the_product_bound():
+    rng = np.random.default_rng(23)
+    q_off = np.array([0, 3, 7, 7, 12])
+    d_off = np.array([0, 5, 6, 6, 14, 20])
+    Q = rng.standard_normal((12, 128)).astype(np.float32)
+    D = rng.standard_normal((20, 128)).astype(np.float32)
+    # bfloat16-valued inputs: every lo part is zero and the three-product form
+    # is the exact inner product
+    Qb = oracle.bf16_decode(oracle.bf16_round_bits(Q)).astype(np.float32)
+    Db = oracle.bf16_decode(oracle.bf16_round_bits(D)).astype(np.float32)
+    np.testing.assert_array_equal(oracle.ch_dense_bf16x3(Qb, q_off, Db, d_off), oracle.ch_dense(Qb, q_off, Db, d_off))
+    # general inputs: with a = ah + al + ea, |al| <= (1 + 2^-8) 2^-8 |a| and
+    # |ea| <= 2^-16 |a| (likewise p), the dropped terms ah*ep + al*pl + ea*ph
+    # + al*ep + ea*pl + ea*ep of a*p add up to at most 3.1 * 2^-16 |a||p|, and
+    # a max moves by at most the largest change of its arguments
+    got = oracle.ch_dense_bf16x3(Q, q_off, D, d_off)
+    ref = oracle.ch_dense(Q, q_off, D, d_off)
+    absQ, absD = np.abs(Q.astype(np.float64)), np.abs(D.astype(np.float64))
+    bound = np.zeros_like(ref)
+    for i in range(len(q_off) - 1):
+        for j in range(len(d_off) - 1):
+            if q_off[i] == q_off[i + 1]:
+                continue
+            if d_off[j] == d_off[j + 1]:
+                continue
+            B = absQ[q_off[i]:q_off[i + 1]] @ absD[d_off[j]:d_off[j + 1]].T
+            bound[i, j] = 3.1 * 2.0 ** -16 * B.max(axis=1).sum()
+    fin = np.isfinite(ref)
+    assert (np.abs(got[fin] - ref[fin]) <= bound[fin]).all()
+    np.testing.assert_array_equal(np.isfinite(got), fin)
+    # the difference is real (the mode is not the float32 products) and small
+    assert np.abs(got[fin] - ref[fin]).max() > 0
+    # candidate lists give the same values as the dense matrix
+    c_off = np.array([0, 2, 2, 5, 6])
+    c_ids = np.array([4, 0, 1, 3, 0, 2])
+    cand = oracle.ch_cands_bf16x3(Q, q_off, D, d_off, c_off, c_ids)
+    want = np.concatenate([got[i, c_ids[c_off[i]:c_off[i + 1]]] for i in range(4)])
+    np.testing.assert_array_equal(cand, want)
