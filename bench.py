@@ -345,6 +345,19 @@ def bench_exhaustive(args):
     exact_kth = top32_s[:, k - 1].clone()
     log(f"f32 exact path {t_f32:.1f} ms")
 
+    # the exact mode that takes each float32 product as three bfloat16
+    # products (corpus split once, queries split in the workspace)
+    t_split = timed(lambda: gem.split_bf16x3(D32), 1)
+    Dx3 = gem.split_bf16x3(D32)
+    sched["bf16x3"], _ = gem.autotune_dense(Q, Dx3, reps=1, scores=scores)
+    x3_s, x3_i = gem.score_exact(Q, Dx3, compute="bf16x3", k=k)
+    torch.cuda.synchronize()
+    t_x3 = timed(lambda: gem.score_exact(Q, Dx3, compute="bf16x3", k=k), max(1, args.steps // 4))
+    gem.score_exact(Q, Dx3, compute="bf16x3", scores=scores)
+    x3_sample = scores[:max(1, args.cpu_sample)].clone()
+    del Dx3
+    log(f"bf16x3 exact path {t_x3:.1f} ms ({t_f32 / t_x3:.2f}x the f32 path)")
+
     def rerank(short_i, sl):
         C = gem.Cands(short_i.reshape(-1), stride=sl, n_lists=n_q)
         return gem.score_exact(Q, D32, cands=C, compute="f32", k=k)
@@ -442,6 +455,15 @@ def bench_exhaustive(args):
             "max_rel_err_all_scores": float((np.abs(ex_np - ref) / np.maximum(np.abs(ref), 1)).max())}
         got16 = bf16_sample[:ns].double().cpu().numpy()
         res["bf16_max_rel_err"] = float((np.abs(got16 - ref) / np.maximum(np.abs(ref), 1)).max())
+        got3 = x3_sample[:ns].double().cpu().numpy()
+        t3 = x3_i[:ns].cpu().numpy()
+        m3 = 0
+        for r in range(ns):
+            tau = 2e-4 * max(abs(np.sort(ref[r])[::-1][k - 1]), 1.0)
+            m3 += int(oracle.tie_aware_match(t3[r], ref[r], k, tau)[0])
+        res["bf16x3_exact_vs_float64"] = {
+            "queries": ns, "top100_match_outside_ties": f"{m3}/{ns}",
+            "max_rel_err_all_scores": float((np.abs(got3 - ref) / np.maximum(np.abs(ref), 1)).max())}
         for name, (ts_, ti_) in (("f32", (top32_s, top32_i)), ("fp8_rerank", (r8_s, r8_i))):
             ts_np, ti_np = ts_[:ns].double().cpu().numpy(), ti_[:ns].cpu().numpy()
             rr = np.take_along_axis(ref, ti_np, axis=1)
@@ -480,6 +502,11 @@ def bench_exhaustive(args):
         "f32_exact_path": {"ms": t_f32, "pair_scores_per_s": pairs / (t_f32 / 1e3),
                            "tflops": flops / (t_f32 / 1e3) / 1e12,
                            "frac_of_fp32_matrix_peak": flops / (t_f32 / 1e3) / PEAK_FP32_MATRIX},
+        "bf16x3_exact_path": {"ms": t_x3, "pair_scores_per_s": pairs / (t_x3 / 1e3),
+                              "speedup_vs_f32_path": t_f32 / t_x3, "corpus_split_ms": t_split,
+                              "tflops_algorithmic": flops / (t_x3 / 1e3) / 1e12,
+                              "mfma_frac_of_bf16_peak": 3 * flops / (t_x3 / 1e3) / PEAK_BF16,
+                              f"recall_at_{k}_vs_f32": recall_gpu(x3_i, exact, exact_kth, k)},
         "fp8_rerank_path": dict(fp8_sweep.get("1000", {}), shortlist=1000, fp8_score_ms=t_fp8_score,
                                 fp8_tflops=flops / (t_fp8_score / 1e3) / 1e12,
                                 fp8_frac_of_peak=flops / (t_fp8_score / 1e3) / PEAK_FP8,

@@ -69,10 +69,18 @@ typedef enum {
   GEM_MXFP4 = 3,             /* OCP MXFP4: E2M1 codes, 64 bytes (element t in byte t/2, the low
                                 nibble for even t), plus 4 E8M0 block exponents (one per 32
                                 elements) per row */
-  GEM_MXFP6 = 4              /* OCP MXFP6: E2M3 codes, 96 bytes: block j (elements 32j .. 32j + 31)
+  GEM_MXFP6 = 4,             /* OCP MXFP6: E2M3 codes, 96 bytes: block j (elements 32j .. 32j + 31)
                                 fills bytes 24j .. 24j + 23, its element t in bits 6t .. 6t + 5
                                 of those 192 bits (least significant bit first), plus 4 E8M0
                                 block exponents per row as for MXFP4 */
+  GEM_BF16X3 = 5             /* float32 values as two bfloat16 parts, x = hi + lo + e with
+                                hi = bf16(x), lo = bf16(x - hi) (round to nearest even; x - hi
+                                is exact in float32), |e| <= 2^-16 |x|. 512 bytes per row: four
+                                128-byte blocks, block j holding hi of elements 32j .. 32j + 31
+                                (64 bytes) and then lo of the same elements (64 bytes). A product
+                                a*b is taken as ah*bh + ah*bl + al*bh on bf16 MFMA (the dropped
+                                terms al*bl, ah*eb, ea*bh and smaller ones add up to at most
+                                3.1 * 2^-16 |a||b|), accumulated in float32 */
 } gem_dtype;
 
 typedef enum {
@@ -211,6 +219,14 @@ size_t gem_workspace_bytes(gem_ctx ctx, int32_t op, const gem_sets* Q, const gem
 gem_status gem_convert_bf16(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim,
                             uint16_t* out, hipStream_t stream);
 
+/* float32 rows -> GEM_BF16X3 rows (hi = bf16(x), lo = bf16(x - hi), round to
+ * nearest even), for the exact mode that runs float32 products as three
+ * bfloat16 products.
+ *   x: [device] [n_rows * dim] float32; out: [device] [n_rows * dim] pairs of
+ *   uint16 in the GEM_BF16X3 row layout (512 bytes per row). dim must be 128. */
+gem_status gem_split_bf16x3(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim, uint16_t* out,
+                            hipStream_t stream);
+
 /* float32 rows -> OCP FP8 E4M3 codes + one power-of-two scale per row.
  *   scale = smallest 2^e (e clamped to [-126, 127]) with max|x| <= 448 * 2^e
  *   (1 for an all-zero row); code = E4M3(x / scale), round to nearest, ties to
@@ -283,9 +299,14 @@ gem_status gem_copy_rows(gem_ctx ctx, const void* src, const int64_t* src_idx, v
                          int64_t n, int64_t row_bytes, hipStream_t stream);
 
 /* Exact Chamfer scores CH(Q_i, D_j) (Def. 1).
- *   compute = GEM_F32 or GEM_BF16: the operand type of the products; D->dtype must
- *   equal it. Q->dtype may equal it, or be GEM_F32 when compute is GEM_BF16 (Q is
- *   then converted into the workspace).
+ *   compute = GEM_F32, GEM_BF16 or GEM_BF16X3: the operand type of the products;
+ *   D->dtype must equal it. Q->dtype may equal it, or be GEM_F32 when compute is
+ *   GEM_BF16 or GEM_BF16X3 (Q is then converted into the workspace). GEM_F32
+ *   runs float32 MFMA products; GEM_BF16X3 runs each float32 product as three
+ *   bfloat16 products (see gem_dtype), several times the float32 MFMA rate,
+ *   with a dot product off the exact one by at most 3.1 * 2^-16 *
+ *   sum_t |a_t b_t| plus the float32 accumulation; GEM_BF16 takes the products
+ *   of bfloat16-rounded operands.
  *   C == NULL: every query against every document. Score (i, j) is written to
  *     scores[row(i) * ld_scores + j], row(i) = score_rows ? score_rows[i] : i,
  *     ld_scores >= D->n_sets (0 means D->n_sets).

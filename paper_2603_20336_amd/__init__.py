@@ -19,7 +19,8 @@ from typing import Optional
 import torch
 
 from . import _abi
-from ._abi import (GEM_BF16, GEM_F32, GEM_FP8_E4M3, GEM_MAX_K, GEM_MAX_QUERY_LEN, GEM_MXFP4, GEM_MXFP6, GemError)
+from ._abi import (GEM_BF16, GEM_BF16X3, GEM_F32, GEM_FP8_E4M3, GEM_MAX_K, GEM_MAX_QUERY_LEN, GEM_MXFP4, GEM_MXFP6,
+                   GemError)
 
 __all__ = ["Sets", "Cands", "Beam", "GemError", "convert_bf16", "quantize_fp8", "score_exact",
            "score_quant", "topk", "expand_batch", "beam_merge", "beam_reset", "validate_sets", "validate_cands",
@@ -27,14 +28,16 @@ __all__ = ["Sets", "Cands", "Beam", "GemError", "convert_bf16", "quantize_fp8", 
            "set_dense_schedule", "autotune_dense", "copy_rows", "nearest_centroid", "centroid_update",
            "kmeans", "encode", "codebook_size",
            "emd_sinkhorn", "set_topk_fusion", "topk_fusion", "score_workspace_bytes", "gather_schedule",
-           "set_check", "check_status", "set_gather_schedule", "autotune_gather", "save_tune_cache", "load_tune_cache"]
+           "set_check", "check_status", "set_gather_schedule", "autotune_gather", "save_tune_cache", "load_tune_cache",
+           "GEM_BF16X3", "split_bf16x3"]
 
 _DTYPES = {"f32": GEM_F32, "bf16": GEM_BF16, "fp8": GEM_FP8_E4M3, "mxfp4": GEM_MXFP4, "mxfp6": GEM_MXFP6,
-           GEM_F32: GEM_F32, GEM_BF16: GEM_BF16, GEM_FP8_E4M3: GEM_FP8_E4M3, GEM_MXFP4: GEM_MXFP4,
-           GEM_MXFP6: GEM_MXFP6}
+           "bf16x3": GEM_BF16X3, GEM_F32: GEM_F32, GEM_BF16: GEM_BF16, GEM_FP8_E4M3: GEM_FP8_E4M3,
+           GEM_MXFP4: GEM_MXFP4, GEM_MXFP6: GEM_MXFP6, GEM_BF16X3: GEM_BF16X3}
 _ROW_TORCH = {GEM_F32: torch.float32, GEM_BF16: torch.uint16, GEM_FP8_E4M3: torch.uint8, GEM_MXFP4: torch.uint8,
-              GEM_MXFP6: torch.uint8}
-_ROW_WIDTH = {GEM_F32: 128, GEM_BF16: 128, GEM_FP8_E4M3: 128, GEM_MXFP4: 64, GEM_MXFP6: 96}   # tensor columns per row
+              GEM_MXFP6: torch.uint8, GEM_BF16X3: torch.uint16}
+_ROW_WIDTH = {GEM_F32: 128, GEM_BF16: 128, GEM_FP8_E4M3: 128, GEM_MXFP4: 64, GEM_MXFP6: 96,
+              GEM_BF16X3: 256}   # tensor columns per row
 _QUANT = (GEM_FP8_E4M3, GEM_MXFP4, GEM_MXFP6)
 
 
@@ -137,6 +140,9 @@ class Sets:
     def to_bf16(self, stream=None) -> "Sets":
         return convert_bf16(self, stream)
 
+    def to_bf16x3(self, stream=None) -> "Sets":
+        return split_bf16x3(self, stream)
+
     def to_fp8(self, stream=None) -> "Sets":
         return quantize_fp8(self, stream)
 
@@ -206,6 +212,18 @@ def convert_bf16(S: Sets, stream=None) -> Sets:
     _abi.check(library().gem_convert_bf16(_ctx(S.device), _ptr(S.vecs), n, _abi.GEM_DIM,
                                           _ptr(out), _stream(stream)))
     return Sets(out, S.offsets, GEM_BF16, S.max_len, n_sets=S.n_sets, codes=S.codes)
+
+
+def split_bf16x3(S: Sets, stream=None) -> Sets:
+    """float32 sets -> bfloat16 (hi, lo) pairs, the operands of the exact mode
+    that runs float32 products as three bfloat16 products (GEM_BF16X3)."""
+    if S.dtype != GEM_F32:
+        raise TypeError("split_bf16x3 takes float32 sets")
+    n = int(S.vecs.shape[0])                       # (a code set converts its codebook)
+    out = torch.empty(n, 2 * _abi.GEM_DIM, dtype=torch.uint16, device=S.device)
+    _abi.check(library().gem_split_bf16x3(_ctx(S.device), _ptr(S.vecs), n, _abi.GEM_DIM,
+                                          _ptr(out), _stream(stream)))
+    return Sets(out, S.offsets, GEM_BF16X3, S.max_len, n_sets=S.n_sets, codes=S.codes)
 
 
 def quantize_fp8(S: Sets, stream=None) -> Sets:
@@ -317,7 +335,9 @@ def score_workspace_bytes(Q: Sets, D: Sets, cands: Optional[Cands] = None, k: in
 def score_exact(Q: Sets, D: Sets, cands: Optional[Cands] = None, k: int = 0, compute="f32",
                 scores: Optional[torch.Tensor] = None, ld: int = 0, rows: Optional[torch.Tensor] = None,
                 want_scores: bool = False, stream=None, ws: Optional[torch.Tensor] = None):
-    """Exact Chamfer scores (Def. 1) in float32 or bf16 operands.
+    """Exact Chamfer scores (Def. 1): compute "f32" (float32 products), "bf16x3"
+    (each float32 product as three bfloat16 products, D split by split_bf16x3)
+    or "bf16" (products of bfloat16-rounded operands).
 
     cands None: every query against every document -> [n_q, n_docs] (or into
     `scores` with row stride `ld` and optional row map `rows`). With cands:

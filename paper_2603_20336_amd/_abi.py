@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgem.so")
 
 GEM_OK, GEM_ERR_INVALID, GEM_ERR_WORKSPACE, GEM_ERR_UNSUPPORTED, GEM_ERR_HIP, GEM_ERR_DEVICE_CHECK = range(6)
-GEM_F32, GEM_BF16, GEM_FP8_E4M3, GEM_MXFP4, GEM_MXFP6 = 0, 1, 2, 3, 4
+GEM_F32, GEM_BF16, GEM_FP8_E4M3, GEM_MXFP4, GEM_MXFP6, GEM_BF16X3 = 0, 1, 2, 3, 4, 5
 GEM_OP_SCORE_EXACT, GEM_OP_SCORE_QUANT, GEM_OP_TOPK, GEM_OP_EXPAND = 0, 1, 2, 3
 GEM_OP_NEAREST_CENTROID, GEM_OP_CENTROID_UPDATE = 4, 5
 GEM_OPT_TOPK_FUSION, GEM_OPT_CHECK = 0, 1
@@ -83,6 +83,7 @@ SIGNATURES = {
     "gem_get_option": (i32, [c_p, i32, ctypes.POINTER(i64)]),
     "gem_check_status": (i32, [c_p, c_p]),
     "gem_convert_bf16": (i32, [c_p, c_p, i64, i32, c_p, c_p]),
+    "gem_split_bf16x3": (i32, [c_p, c_p, i64, i32, c_p, c_p]),
     "gem_quantize_fp8": (i32, [c_p, c_p, i64, i32, c_p, c_p, c_p]),
     "gem_quantize_mxfp4": (i32, [c_p, c_p, i64, i32, c_p, c_p, c_p]),
     "gem_quantize_mxfp6": (i32, [c_p, c_p, i64, i32, c_p, c_p, c_p]),

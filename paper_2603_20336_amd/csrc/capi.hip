@@ -61,6 +61,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 int row_bytes(int dtype) {
   switch (dtype) {
     case GEM_F32: return 4 * GEM_DIM;
+    case GEM_BF16X3: return 4 * GEM_DIM;
     case GEM_BF16: return 2 * GEM_DIM;
     case GEM_FP8_E4M3: return GEM_DIM;
     case GEM_MXFP4: return GEM_DIM / 2;
@@ -70,7 +71,9 @@ int row_bytes(int dtype) {
 }
 
 bool mx_dtype(int32_t d) { return d == GEM_MXFP4 || d == GEM_MXFP6; }
-bool valid_dtype(int32_t d) { return d == GEM_F32 || d == GEM_BF16 || d == GEM_FP8_E4M3 || mx_dtype(d); }
+bool valid_dtype(int32_t d) {
+  return d == GEM_F32 || d == GEM_BF16 || d == GEM_BF16X3 || d == GEM_FP8_E4M3 || mx_dtype(d);
+}
 // Formats that carry a 32-bit scale word per row.
 bool scaled_dtype(int32_t d) { return d == GEM_FP8_E4M3 || mx_dtype(d); }
 bool quant_dtype(int32_t d) { return d == GEM_FP8_E4M3 || mx_dtype(d); }
@@ -226,6 +229,9 @@ gem_status convert_query(const gem_sets* Q, int32_t compute, void* ws, const Sco
   // (a code set converts its codebook; the codes stay as they are)
   if (compute == GEM_BF16) {
     e = launch_convert_bf16(static_cast<const float*>(Q->vecs), vec_rows(Q) * GEM_DIM,
+                            reinterpret_cast<uint16_t*>(at(ws, L.q_conv)), stream);
+  } else if (compute == GEM_BF16X3) {
+    e = launch_split_bf16x3(static_cast<const float*>(Q->vecs), vec_rows(Q),
                             reinterpret_cast<uint16_t*>(at(ws, L.q_conv)), stream);
   } else if (mx_dtype(compute)) {
     e = (compute == GEM_MXFP4 ? launch_quantize_mxfp4 : launch_quantize_mxfp6)(
@@ -910,6 +916,16 @@ gem_status gem_convert_bf16(gem_ctx ctx, const float* x, int64_t n_rows, int32_t
   return e == hipSuccess ? GEM_OK : hip_fail(e, "bf16 conversion");
 }
 
+gem_status gem_split_bf16x3(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim, uint16_t* out,
+                            hipStream_t stream) {
+  if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
+  if (dim != GEM_DIM) return fail(GEM_ERR_UNSUPPORTED, "dim %d (only %d is supported)", dim, GEM_DIM);
+  if (n_rows < 0) return fail(GEM_ERR_INVALID, "negative n_rows");
+  if (n_rows > 0 && (!x || !out)) return fail(GEM_ERR_INVALID, "NULL buffer");
+  hipError_t e = launch_split_bf16x3(x, n_rows, out, stream);
+  return e == hipSuccess ? GEM_OK : hip_fail(e, "bf16 split");
+}
+
 gem_status gem_quantize_fp8(gem_ctx ctx, const float* x, int64_t n_rows, int32_t dim, uint8_t* out, float* scales,
                             hipStream_t stream) {
   if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
@@ -998,8 +1014,8 @@ gem_status gem_score_exact(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, co
                            int32_t k, float* scores, int64_t ld_scores, const int32_t* score_rows, float* top_scores,
                            int32_t* top_ids, void* ws, size_t ws_bytes, hipStream_t stream) {
   if (!ctx) return fail(GEM_ERR_INVALID, "ctx is NULL");
-  if (compute != GEM_F32 && compute != GEM_BF16)
-    return fail(GEM_ERR_INVALID, "exact scoring computes in F32 or BF16, not dtype %d", compute);
+  if (compute != GEM_F32 && compute != GEM_BF16 && compute != GEM_BF16X3)
+    return fail(GEM_ERR_INVALID, "exact scoring computes in F32, BF16 or BF16X3, not dtype %d", compute);
   return score_common(ctx, Q, D, C, compute, k, scores, ld_scores, score_rows, top_scores, top_ids, ws, ws_bytes,
                       stream);
 }

@@ -1,5 +1,6 @@
-// Operand conversion for the scoring paths: float32 rows -> bfloat16, and
-// float32 rows -> OCP FP8 E4M3 codes with one power-of-two scale per row.
+// Operand conversion for the scoring paths: float32 rows -> bfloat16, float32
+// rows -> bfloat16 (hi, lo) pairs, and float32 rows -> OCP FP8 E4M3 codes with
+// one power-of-two scale per row (and the MX formats).
 #include "device_common.hpp"
 #include "gem_internal.h"
 
@@ -30,6 +31,48 @@ hipError_t launch_convert_bf16(const float* x, int64_t n_elems, uint16_t* out, h
   const int64_t threads = (n_elems + 7) / 8;
   const int64_t grid = (threads + 255) / 256;
   hipLaunchKernelGGL(convert_bf16_kernel, dim3(capped_blocks(grid, 256)), dim3(256), 0, s, x, n_elems, out);
+  return hipGetLastError();
+}
+
+// float32 rows -> bfloat16 (hi, lo) pairs: hi = bf16(x), lo = bf16(x - hi),
+// both round to nearest even (x - hi is exact in float32). Row layout: four
+// 128-byte blocks, block j = hi of elements 32j .. 32j + 31, then their lo.
+// One thread per 8 consecutive elements of a row (a 16-byte store of hi and
+// one of lo).
+__global__ __launch_bounds__(256) void split_bf16x3_kernel(const float* __restrict__ x, int64_t n_rows,
+                                                           uint16_t* __restrict__ out) {
+  const int64_t n8 = n_rows * (kDim / 8);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n8; i += (int64_t)gridDim.x * 256) {
+    const int64_t row = i / (kDim / 8);
+    const int e0 = (int)(i % (kDim / 8)) * 8;                 // first element of the eight
+    const float4 a = *reinterpret_cast<const float4*>(x + row * kDim + e0);
+    const float4 b = *reinterpret_cast<const float4*>(x + row * kDim + e0 + 4);
+    const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint32_t h[4], lo[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint32_t hh[2], ll[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const float xv = v[2 * j + t];
+        const uint16_t hb = f32_to_bf16_rne(xv);
+        hh[t] = hb;
+        ll[t] = f32_to_bf16_rne(xv - __uint_as_float((uint32_t)hb << 16));
+      }
+      h[j] = hh[0] | (hh[1] << 16);
+      lo[j] = ll[0] | (ll[1] << 16);
+    }
+    // block of element e0: e0 / 32; hi at block * 64 + (e0 % 32), lo 32 elements later
+    uint16_t* o = out + row * (2 * kDim) + (e0 / 32) * 64 + (e0 % 32);
+    *reinterpret_cast<uint4*>(o) = make_uint4(h[0], h[1], h[2], h[3]);
+    *reinterpret_cast<uint4*>(o + 32) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+  }
+}
+
+hipError_t launch_split_bf16x3(const float* x, int64_t n_rows, uint16_t* out, hipStream_t s) {
+  if (n_rows == 0) return hipSuccess;
+  const int64_t grid = (n_rows * (kDim / 8) + 255) / 256;
+  hipLaunchKernelGGL(split_bf16x3_kernel, dim3(capped_blocks(grid, 256)), dim3(256), 0, s, x, n_rows, out);
   return hipGetLastError();
 }
 

@@ -115,6 +115,7 @@ hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, 
 hipError_t launch_score_range(int dtype, const SetsView& Q, const SetsView& D, const DenseOut& out, hipStream_t s);
 
 hipError_t launch_convert_bf16(const float* x, int64_t n_elems, uint16_t* out, hipStream_t s);
+hipError_t launch_split_bf16x3(const float* x, int64_t n_rows, uint16_t* out, hipStream_t s);
 hipError_t launch_quantize_fp8(const float* x, int64_t n_rows, uint8_t* out, float* scales, hipStream_t s);
 hipError_t launch_quantize_mxfp4(const float* x, int64_t n_rows, uint8_t* out, uint8_t* exps, hipStream_t s);
 hipError_t launch_quantize_mxfp6(const float* x, int64_t n_rows, uint8_t* out, uint8_t* exps, hipStream_t s);

@@ -61,6 +61,39 @@ template <> struct Op<GEM_BF16> {
   static __device__ __forceinline__ void load_b(Frag& f, const void* v, const float* sc, int64_t row, int g) { load(f, v, sc, row, g); }
 };
 
+// float32 values as bfloat16 pairs (hi, lo): lane group g reads block g of
+// the row (hi of dims 32g .. 32g + 31, then lo of the same dims), and each
+// bf16 step s multiplies lo x hi, hi x lo, then hi x hi into one float32
+// accumulator (the small terms first), so a product a*b becomes
+// ah*bh + ah*bl + al*bh with every partial product exact.
+template <> struct Op<GEM_BF16X3> {
+  static constexpr int kRowBytes = 512;
+  struct Frag { bf16x8 h[4]; bf16x8 l[4]; };
+  static __device__ __forceinline__ void load(Frag& f, const void* vecs, const float*, int64_t row, int g) {
+    const uint4* p = reinterpret_cast<const uint4*>(static_cast<const char*>(vecs) + row * kRowBytes + g * 128);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      f.h[i] = __builtin_bit_cast(bf16x8, p[i]);
+      f.l[i] = __builtin_bit_cast(bf16x8, p[4 + i]);
+    }
+  }
+  static __device__ __forceinline__ void zero(Frag& f) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      f.h[i] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+      f.l[i] = f.h[i];
+    }
+  }
+  static __device__ __forceinline__ f32x4 mma(const Frag& a, const Frag& b, f32x4 acc, int s) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l[s], b.h[s], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h[s], b.l[s], acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h[s], b.h[s], acc, 0, 0, 0);
+  }
+  static constexpr int kSteps = 4;
+  static constexpr bool kColumnScale = false;
+  static __device__ __forceinline__ void load_b(Frag& f, const void* v, const float* sc, int64_t row, int g) { load(f, v, sc, row, g); }
+};
+
 template <> struct Op<GEM_FP8_E4M3> {
   static constexpr int kRowBytes = 128;
   struct Frag { i32x8 v; int scale; };   // scale: E8M0 exponent byte of the row's power-of-two scale

@@ -33,6 +33,7 @@ __device__ __forceinline__ int64_t vec_row(const SetsView& S, int64_t r) {
 template <int DT> struct DenseCfg;
 // kNT: 16-column tiles a wave holds; kGroup: document tiles per LDS group buffer.
 template <> struct DenseCfg<GEM_F32> { static constexpr int kNT = 4; static constexpr int kGroup = 4; };
+template <> struct DenseCfg<GEM_BF16X3> { static constexpr int kNT = 4; static constexpr int kGroup = 4; };
 template <> struct DenseCfg<GEM_BF16> { static constexpr int kNT = 8; static constexpr int kGroup = 8; };
 template <> struct DenseCfg<GEM_FP8_E4M3> { static constexpr int kNT = 16; static constexpr int kGroup = 8; };
 template <> struct DenseCfg<GEM_MXFP4> { static constexpr int kNT = 16; static constexpr int kGroup = 8; };
@@ -41,6 +42,7 @@ template <> struct DenseCfg<GEM_MXFP6> { static constexpr int kNT = 16; static c
 int dense_pass_rows(int dtype) {
   switch (dtype) {
     case GEM_F32: return 16 * DenseCfg<GEM_F32>::kNT;
+    case GEM_BF16X3: return 16 * DenseCfg<GEM_BF16X3>::kNT;
     case GEM_BF16: return 16 * DenseCfg<GEM_BF16>::kNT;
     default: return 16 * DenseCfg<GEM_FP8_E4M3>::kNT;
   }
@@ -408,6 +410,20 @@ __device__ __forceinline__ void frag_from_lds<GEM_F32>(Op<GEM_F32>::Frag& f, con
     const u32x4 v = row[(8 * g + s) ^ sw];
     f.v[4 * s + 0] = __uint_as_float(v.x); f.v[4 * s + 1] = __uint_as_float(v.y);
     f.v[4 * s + 2] = __uint_as_float(v.z); f.v[4 * s + 3] = __uint_as_float(v.w);
+  }
+}
+
+// GEM_BF16X3: block g of the staged 512-byte row is chunks 8g .. 8g + 7 (hi
+// in the first four, lo in the last four).
+template <>
+__device__ __forceinline__ void frag_from_lds<GEM_BF16X3>(Op<GEM_BF16X3>::Frag& f, const u32x4* stage, int c16,
+                                                          int g) {
+  const u32x4* row = stage + c16 * 32;
+  const int sw = TileStage<GEM_BF16X3>::swz(c16);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    f.h[i] = __builtin_bit_cast(bf16x8, row[(8 * g + i) ^ sw]);
+    f.l[i] = __builtin_bit_cast(bf16x8, row[(8 * g + 4 + i) ^ sw]);
   }
 }
 
@@ -1047,6 +1063,10 @@ static void launch_dense_variant(int dtype, bool codes, int32_t block_rows, dim3
       if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_BF16, true, kTopk>), grid, blk, 0, s, P);
       else hipLaunchKernelGGL((score_dense_kernel<GEM_BF16, false, kTopk>), grid, blk, 0, s, P);
       break;
+    case GEM_BF16X3:
+      if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_BF16X3, true, kTopk>), grid, blk, 0, s, P);
+      else hipLaunchKernelGGL((score_dense_kernel<GEM_BF16X3, false, kTopk>), grid, blk, 0, s, P);
+      break;
     case GEM_FP8_E4M3:
       if (codes) hipLaunchKernelGGL((score_dense_kernel<GEM_FP8_E4M3, true, kTopk>), grid, blk, 0, s, P);
       else if (block_rows <= 64)                             // two workgroups per CU
@@ -1079,7 +1099,8 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
   if (P.n_bgroups == 0 || P.n_chunks == 0) return hipSuccess;
   if (sched.chunk_docs < 1 || sched.chunk_docs > kMaxChunkDocs || sched.items_per_slot < 1 || sched.slots_per_xcd < 1)
     return hipErrorInvalidValue;
-  if (dtype != GEM_F32 && dtype != GEM_BF16 && dtype != GEM_FP8_E4M3 && dtype != GEM_MXFP4 && dtype != GEM_MXFP6)
+  if (dtype != GEM_F32 && dtype != GEM_BF16 && dtype != GEM_BF16X3 && dtype != GEM_FP8_E4M3 && dtype != GEM_MXFP4 &&
+      dtype != GEM_MXFP6)
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)(8 * sched.slots_per_xcd)), blk(kDenseThreads);
   const bool codes = D.codes != nullptr;
@@ -1105,10 +1126,11 @@ hipError_t launch_score_dense(int dtype, const SetsView& Q, const SetsView& D, c
 constexpr int kGatherEntries = 16;
 constexpr int kGatherNT = 4;
 // Tiles in flight per wave: the choices of each format (registers: a float32
-// tile fragment takes 32 VGPRs, bf16 16, FP8 9, MXFP6 7, MXFP4 5); the middle
-// one is the default.
+// tile fragment takes 32 VGPRs, a split-bf16 one 32, bf16 16, FP8 9, MXFP6 7,
+// MXFP4 5); the middle one is the default.
 template <int DT> struct GatherDepths;
 template <> struct GatherDepths<GEM_F32> { static constexpr int d[3] = {1, 2, 3}; };
+template <> struct GatherDepths<GEM_BF16X3> { static constexpr int d[3] = {1, 2, 3}; };
 template <> struct GatherDepths<GEM_BF16> { static constexpr int d[3] = {2, 4, 6}; };
 template <> struct GatherDepths<GEM_FP8_E4M3> { static constexpr int d[3] = {4, 6, 8}; };
 template <> struct GatherDepths<GEM_MXFP4> { static constexpr int d[3] = {6, 8, 12}; };
@@ -1117,6 +1139,7 @@ template <> struct GatherDepths<GEM_MXFP6> { static constexpr int d[3] = {4, 6, 
 int gather_depth_choice(int dtype, int i) {
   switch (dtype) {
     case GEM_F32: return GatherDepths<GEM_F32>::d[i];
+    case GEM_BF16X3: return GatherDepths<GEM_BF16X3>::d[i];
     case GEM_BF16: return GatherDepths<GEM_BF16>::d[i];
     case GEM_FP8_E4M3: return GatherDepths<GEM_FP8_E4M3>::d[i];
     case GEM_MXFP6: return GatherDepths<GEM_MXFP6>::d[i];
@@ -1352,6 +1375,7 @@ static hipError_t run_gather(int dtype, GatherParams P, int64_t max_list_len, co
     bool ok = false;
     switch (dtype) {
       case GEM_F32: ok = launch_gather_depth<GEM_F32>(depth, codes, gr, blk, P, s); break;
+      case GEM_BF16X3: ok = launch_gather_depth<GEM_BF16X3>(depth, codes, gr, blk, P, s); break;
       case GEM_BF16: ok = launch_gather_depth<GEM_BF16>(depth, codes, gr, blk, P, s); break;
       case GEM_FP8_E4M3: ok = launch_gather_depth<GEM_FP8_E4M3>(depth, codes, gr, blk, P, s); break;
       case GEM_MXFP4: ok = launch_gather_depth<GEM_MXFP4>(depth, codes, gr, blk, P, s); break;
