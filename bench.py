@@ -530,8 +530,8 @@ def bench_exhaustive(args):
 
 def bench_dense_only(args):
     """The dense scorers alone, for counter runs: the bf16 step (fused top-100,
-    then staged), and FP8, MXFP4 and MXFP6 exhaustive scoring into a score
-    matrix."""
+    then staged), and FP8, MXFP4, MXFP6 and split-bf16 exact exhaustive scoring
+    into a score matrix."""
     dev = torch.device("cuda:0")
     w2 = wl.WORKLOADS[2]
     c_dev, q_dev = wl.corpus(w2, device=dev), wl.queries(w2, device=dev)
@@ -539,16 +539,21 @@ def bench_dense_only(args):
     D32 = gem.Sets(c_dev.vecs, c_dev.offsets, "f32", c_dev.max_len())
     D16, D8, D4, D6 = gem.convert_bf16(D32), gem.quantize_fp8(D32), gem.quantize_mxfp4(D32), gem.quantize_mxfp6(D32)
     Q16, Q8, Q4, Q6 = gem.convert_bf16(Q), gem.quantize_fp8(Q), gem.quantize_mxfp4(Q), gem.quantize_mxfp6(Q)
+    Dx3 = gem.split_bf16x3(D32)
     scores = torch.empty(Q.n_sets, D32.n_sets, dtype=torch.float32, device=dev)
     flops = 2.0 * 128 * Q.n_vecs * D32.n_vecs
     out = {}
+    # (the split-bf16 exact mode runs three bf16 products per float32 product:
+    # its MFMA fraction counts them against the bf16 peak)
     for name, QQ, DD, peak in (("bf16", Q16, D16, PEAK_BF16), ("fp8", Q8, D8, PEAK_FP8), ("mxfp4", Q4, D4, PEAK_FP4),
-                               ("mxfp6", Q6, D6, PEAK_FP6)):
+                               ("mxfp6", Q6, D6, PEAK_FP6), ("bf16x3", Q, Dx3, PEAK_BF16 / 3)):
         sched, _ = gem.autotune_dense(QQ, DD, reps=2, scores=scores)
         if name == "bf16":
             t_f = timed(lambda: gem.score_exact(QQ, DD, compute="bf16", k=100), max(1, args.steps))
             out["bf16_fused_top100_ms"] = t_f
             t = timed(lambda: gem.score_exact(QQ, DD, compute="bf16", scores=scores), max(1, args.steps))
+        elif name == "bf16x3":
+            t = timed(lambda: gem.score_exact(QQ, DD, compute="bf16x3", scores=scores), max(1, args.steps))
         else:
             t = timed(lambda: gem.score_quant(QQ, DD, scores=scores), max(1, args.steps))
         out[name] = {"schedule": sched, "ms": t, "frac_of_peak": flops / (t / 1e3) / peak}
@@ -598,20 +603,20 @@ def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_
     shortlist = w5.shortlist if shortlist is None else int(shortlist)
     ex = serve.DeviceExecutor(D8, D32, n_chunks=n_chunks, max_slots=1024, shortlist=shortlist, k=w5.k)
     global _SERVE_TUNED
-    if not _SERVE_TUNED.get(shortlist):
+    work = int(chunk_work)
+    if not _SERVE_TUNED.get((shortlist, n_chunks, work)):
         # schedules for the loop's launch shapes (kept in the device context
         # for every later executor): sample queries of the serving mix, drawn
         # apart from the measured requests
         tq = wl.queries(w5, n_queries=1024, query_len=q_len, seed_offset=77)
         toff, tvecs = tq.offsets.numpy(), tq.vecs.numpy()
         t0 = time.perf_counter()
-        sch = ex.autotune([tvecs[toff[i]:toff[i + 1]] for i in range(tq.n_sets)])
+        sch = ex.autotune([tvecs[toff[i]:toff[i + 1]] for i in range(tq.n_sets)], chunk_work=work)
         log(f"serving schedules tuned in {time.perf_counter() - t0:.1f} s: "
             f"{ {k: v for k, v in sch.items() if k in ('score_fp8_64', 'score_fp8_256', 'rerank_f32_32')} }")
-        _SERVE_TUNED[shortlist] = sch
+        _SERVE_TUNED[(shortlist, n_chunks, work)] = sch
     budget = None if max_resident is None else int(max_resident) * ex.bytes_per_request
     # an iteration scores as many chunks as fit chunk_work (query vectors x chunks)
-    work = int(chunk_work)
     eng = serve.ServingEngine(ex, max_slots=1024, mem_budget_bytes=budget, chunk_work=work)
     # warm-up on a few requests, then the measured run
     warm = serve.ServingEngine(ex, max_slots=1024, chunk_work=work)
@@ -799,6 +804,8 @@ def main():
                     help="FP8 shortlist reranked per serving request (default: the serving workload's)")
     ap.add_argument("--serve-shortlists", type=str, default="100,200,300,500,1000",
                     help="shortlist lengths whose recall is measured on the serving query mix")
+    ap.add_argument("--serve-chunks", type=int, default=8,
+                    help="corpus chunks of the serving loop (a request finishes after one pass over all of them)")
     ap.add_argument("--serve-chunk-work", type=int, default=8192,
                     help="query vectors x chunks an iteration may score (more chunks per iteration for light batches)")
     ap.add_argument("--serve-points-only", action="store_true",
@@ -857,7 +864,8 @@ def main():
             # about 1.25 s of arrivals per rate, within the request bounds
             n_req = min(args.serve_max_requests, max(args.serve_requests, int(rate * 1.25)))
             line["serving"].append(bench_serving(D8, D32, rate=rate, n_req=n_req, rate_idx=ri,
-                                               shortlist=args.serve_shortlist, chunk_work=args.serve_chunk_work))
+                                               shortlist=args.serve_shortlist, chunk_work=args.serve_chunk_work,
+                                               n_chunks=args.serve_chunks))
         if args.serve_rates and not args.serve_points_only:
             # a device-memory budget for 256 requests' state at 32,000/s: the
             # memory check, not the slot count, is what refuses requests

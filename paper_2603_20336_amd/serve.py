@@ -349,17 +349,19 @@ class DeviceExecutor(Executor):
     def _stream(self):
         return self.stream if self.stream is not None else torch.cuda.current_stream(self.device)
 
-    def autotune(self, sample: Sequence[np.ndarray], max_batch: Optional[int] = None, reps: int = 3) -> dict:
+    def autotune(self, sample: Sequence[np.ndarray], max_batch: Optional[int] = None, reps: int = 3,
+                 chunk_work: int = 0) -> dict:
         """Tune the library's schedules for the shapes this loop launches, on
         sample queries of the serving mix: the FP8 scorer for batches of 1, 2,
-        4, ... requests (up to max_batch) against one chunk, and the float32
-        rerank for finishing batches of up to 64 requests. The schedules are
-        installed in the device's context for each shape class (a schedule
-        changes the launch, never a score). Returns {shape: schedule}."""
+        4, ... requests (up to max_batch) against the chunks an iteration of
+        that batch scores (one, or as many as fit chunk_work query vectors x
+        chunks: ServingEngine's rule), and the float32 rerank for finishing
+        batches of up to 64 requests. The schedules are installed in the
+        device's context for each shape class (a schedule changes the launch,
+        never a score). Returns {shape: schedule}."""
         g = self._gem
         cs = self._stream()
         max_batch = min(len(sample), self.max_slots if max_batch is None else int(max_batch))
-        chunk = self.D8.view(self.bounds[0], self.bounds[1])
         out = {}
         with torch.cuda.stream(cs):
             n = 1
@@ -369,6 +371,8 @@ class DeviceExecutor(Executor):
                 off = torch.from_numpy(np.concatenate([[0], np.cumsum(lens)])).to(self.device)
                 Q32 = g.Sets(torch.from_numpy(np.concatenate(qs, 0)).to(self.device), off, "f32", int(lens.max()))
                 Q8 = g.quantize_fp8(Q32, stream=cs)
+                span = 1 if chunk_work <= 0 else max(1, min(self.n_chunks, int(chunk_work) // int(lens.sum())))
+                chunk = self.D8.view(self.bounds[0], self.bounds[span])
                 sched, _ = g.autotune_dense(Q8, chunk, reps=reps, scores=self.est[:n], ld=self.n_docs, stream=cs)
                 out[f"score_fp8_{n}"] = sched
                 if n <= 64:
