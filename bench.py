@@ -587,7 +587,7 @@ def serving_shortlist_recall(D8, D32, shortlists, n_q=1000, q_len=("uniform", 4,
 _SERVE_TUNED = {}
 
 
-def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_chunks=8, rate_idx=0,
+def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_chunks=4, rate_idx=0,
                   max_resident=None, shortlist=None, chunk_work=8192):
     """Continuous-batching serving loop on the resident corpus: QPS and p50/p99
     latency. max_resident: a device-memory budget for that many requests'
@@ -622,7 +622,14 @@ def bench_serving(D8, D32, q_len=("uniform", 4, 64), rate=2000.0, n_req=1500, n_
     warm = serve.ServingEngine(ex, max_slots=1024, chunk_work=work)
     warm.run([serve.Request(-1 - i, r.vecs, r.t_arrival) for i, r in enumerate(reqs[:200])])
     torch.cuda.synchronize()
-    done = eng.run(reqs)
+    # the loop runs with the garbage collector paused (a full collection
+    # stalls the host for tens of milliseconds, which shows as a p99 spike)
+    gc.collect()
+    gc.disable()
+    try:
+        done = eng.run(reqs)
+    finally:
+        gc.enable()
     st = serve.latency_stats(done)
     st.update({"rate_per_s": rate, "requests": n_req, "chunks": n_chunks, "chunk_work": work,
                "iterations": eng.iteration,
@@ -804,7 +811,7 @@ def main():
                     help="FP8 shortlist reranked per serving request (default: the serving workload's)")
     ap.add_argument("--serve-shortlists", type=str, default="100,200,300,500,1000",
                     help="shortlist lengths whose recall is measured on the serving query mix")
-    ap.add_argument("--serve-chunks", type=int, default=8,
+    ap.add_argument("--serve-chunks", type=int, default=4,
                     help="corpus chunks of the serving loop (a request finishes after one pass over all of them)")
     ap.add_argument("--serve-chunk-work", type=int, default=8192,
                     help="query vectors x chunks an iteration may score (more chunks per iteration for light batches)")
@@ -871,14 +878,16 @@ def main():
             # memory check, not the slot count, is what refuses requests
             log("serving at 32000 requests/s with a device budget of 256 requests")
             r = bench_serving(D8, D32, rate=32000.0, n_req=min(args.serve_max_requests, 20000), rate_idx=99,
-                              max_resident=256, shortlist=args.serve_shortlist)
+                              max_resident=256, shortlist=args.serve_shortlist, n_chunks=args.serve_chunks,
+                              chunk_work=args.serve_chunk_work)
             line["serving_memory_limited"] = r
             # the same offered load with the 1000-document shortlist of the
             # fixed-length rerank workload, for comparison
             log("serving at 16000 requests/s with a shortlist of 1000")
             line["serving_shortlist_1000"] = bench_serving(D8, D32, rate=16000.0,
                                                            n_req=min(args.serve_max_requests, 20000),
-                                                           rate_idx=98, shortlist=1000)
+                                                           rate_idx=98, shortlist=1000, n_chunks=args.serve_chunks,
+                                                           chunk_work=args.serve_chunk_work)
         if line["serving"]:
             # headline latency: the 2000/s point if swept, else the first rate
             ref = next((r for r in line["serving"] if r["rate_per_s"] == 2000.0), line["serving"][0])

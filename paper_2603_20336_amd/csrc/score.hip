@@ -51,7 +51,7 @@ int dense_pass_rows(int dtype) {
 static int pad16(int m) { return (m + 15) & ~15; }
 constexpr int64_t kDenseWavesPerGroup = 8;       // query blocks per block group (waves per workgroup)
 constexpr int kNarrowCols = 64;                    // block width of the FP8 narrow-block variant
-constexpr int64_t kNarrowGroups = 2;   // block groups a batch may fill with narrow blocks
+constexpr int64_t kNarrowGroups = 16;  // block groups a batch may fill with narrow blocks
 
 int dense_block_rows(int dtype, int max_len) {
   const int r = dense_pass_rows(dtype);
@@ -68,8 +68,11 @@ int dense_block_rows_for(int dtype, int max_len, int64_t n_q, int64_t n_vecs) {
   const int64_t cols = n_vecs + 15 * n_q;                                   // padded columns, upper bound
   const int64_t per_wave = (((cols + kDenseWavesPerGroup - 1) / kDenseWavesPerGroup) + 15) & ~(int64_t)15;
   const int64_t narrow = std::max<int64_t>(pad16(max_len > 0 ? max_len : 1), per_wave);
-  // FP8: a batch of short queries that a few block groups of 64-column
-  // blocks hold takes such blocks (the narrow-block variant of the scorer)
+  // FP8: a batch of short queries that up to 16 block groups of 64-column
+  // blocks hold takes such blocks (the narrow-block variant of the scorer,
+  // four waves per SIMD): against 256-column blocks, whose last block group
+  // a batch of this size fills only in part, 32 and 64 serving-mix queries
+  // score 1.55-1.65x faster, 128 about 5 % faster, 256 the same
   if (dtype == GEM_FP8_E4M3 && narrow > kNarrowCols && max_len <= kNarrowCols &&
       cols <= kNarrowCols * kDenseWavesPerGroup * kNarrowGroups)
     return kNarrowCols;

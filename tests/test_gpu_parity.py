@@ -268,6 +268,34 @@ def test_small_batches_stream_bitwise_as_dense(dtype):
         assert_close(big2, ref2, what=f"dense {dtype}, 80 short queries")
 
 
+def test_fp8_narrow_blocks_over_many_block_groups():
+    """A batch of 150 short FP8 queries takes 64-column blocks over many block
+    groups (the narrow-block variant): the same scores, bitwise, as inside a
+    batch of 400 (full-width blocks), the oracle's within the tolerance, and the
+    fused top-k equal to the top-k of those scores."""
+    rng = np.random.default_rng(14)
+    q = _ragged(list(rng.integers(1, 65, 400)), 52)
+    c = _ragged(list(rng.integers(1, 120, 900)), 53)
+    D = _device_sets(c, "fp8")
+    big = _np(gem.score_quant(gem.Sets.from_batch(q, DEV), D))
+    idx = list(range(100, 250))
+    Qs = gem.Sets.from_batch(q.subset(idx), DEV)
+    small = gem.score_quant(Qs, D)
+    np.testing.assert_array_equal(_np(small), big[idx])
+    gem.set_topk_fusion("fused")
+    try:
+        ts, ti = gem.score_quant(Qs, D, k=10)
+    finally:
+        gem.set_topk_fusion("auto")
+    rs, ri = gem.topk(small, 10)
+    np.testing.assert_array_equal(_np(ti), _np(ri))
+    np.testing.assert_array_equal(_np(ts), _np(rs))
+    sub = q.subset(idx)
+    ref = oracle.ch_dense(_operands(sub.vecs.numpy(), "fp8"), sub.offsets.numpy(),
+                          _operands(c.vecs.numpy(), "fp8"), c.offsets.numpy())
+    assert_close(_np(small), ref, what="fp8 narrow blocks, 150 queries")
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 def test_dense_many_blocks_long_documents(dtype):
     """More than 32 block groups for every dtype (more groups than workgroups
