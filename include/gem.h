@@ -196,9 +196,27 @@ const char* gem_version(void);
  *   finite float32 rows, and EMD pair indices inside their batches) and, if
  *   any is violated, returns GEM_ERR_DEVICE_CHECK without computing anything.
  *   The check synchronizes the stream; it is a debugging aid. The violations
- *   are also counted for gem_check_status. */
-typedef enum { GEM_OPT_TOPK_FUSION = 0, GEM_OPT_CHECK = 1 } gem_option;
+ *   are also counted for gem_check_status.
+ *
+ *   GEM_OPT_GATHER_ORDER: how a gathered scoring call (C != NULL) of
+ *   gem_score_exact / gem_score_quant reads the listed documents (the final
+ *   rerank of Alg. 5 over a batch of shortlists, or any candidate lists).
+ *     GEM_GATHER_BY_QUERY: one wave per query and run of its entries, each
+ *       listed document read once per listing.
+ *     GEM_GATHER_BY_DOCUMENT: the entries are grouped by document on the
+ *       device (a counting sort in the workspace); each document is staged in
+ *       LDS once and scored against every query that lists it. Pays when the
+ *       lists share documents (a batch of top-1000 shortlists lists each of
+ *       its documents tens of times). Needs D->max_set_len in [1, 256] (a bound
+ *       of every document's length; a longer document's entries get NaN) and
+ *       no code sets; otherwise the call reads by query.
+ *     GEM_GATHER_AUTO (default): by document when those conditions hold and
+ *       the lists hold at least four entries per document of D, else by query.
+ *   Every order gives the same scores, bitwise. gem_workspace_bytes follows
+ *   the option. gem_expand_batch always reads by query. */
+typedef enum { GEM_OPT_TOPK_FUSION = 0, GEM_OPT_CHECK = 1, GEM_OPT_GATHER_ORDER = 2 } gem_option;
 typedef enum { GEM_TOPK_AUTO = 0, GEM_TOPK_FUSED = 1, GEM_TOPK_STAGED = 2 } gem_topk_mode;
+typedef enum { GEM_GATHER_AUTO = 0, GEM_GATHER_BY_QUERY = 1, GEM_GATHER_BY_DOCUMENT = 2 } gem_gather_order;
 gem_status gem_set_option(gem_ctx ctx, int32_t option, int64_t value);
 gem_status gem_get_option(gem_ctx ctx, int32_t option, int64_t* value);
 /* Synchronizes `stream` and reports what happened since the last call:

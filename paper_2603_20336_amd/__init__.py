@@ -27,7 +27,7 @@ __all__ = ["Sets", "Cands", "Beam", "GemError", "convert_bf16", "quantize_fp8", 
            "library", "GEM_F32", "GEM_BF16", "GEM_FP8_E4M3", "GEM_MXFP4", "quantize_mxfp4", "GEM_MXFP6", "quantize_mxfp6", "GEM_MAX_K", "GEM_MAX_QUERY_LEN", "dense_schedule",
            "set_dense_schedule", "autotune_dense", "copy_rows", "nearest_centroid", "centroid_update",
            "kmeans", "encode", "codebook_size",
-           "emd_sinkhorn", "set_topk_fusion", "topk_fusion", "score_workspace_bytes", "gather_schedule",
+           "emd_sinkhorn", "set_topk_fusion", "topk_fusion", "set_gather_order", "get_gather_order", "score_workspace_bytes", "gather_schedule",
            "set_check", "check_status", "set_gather_schedule", "autotune_gather", "save_tune_cache", "load_tune_cache",
            "GEM_BF16X3", "split_bf16x3"]
 
@@ -302,6 +302,26 @@ def set_topk_fusion(mode: str, device="cuda") -> None:
     "auto" (fused into the scorer when that needs less workspace than staging
     the score rows), "fused" or "staged". Every mode gives the same result."""
     _abi.check(library().gem_set_option(_ctx(torch.device(device)), _abi.GEM_OPT_TOPK_FUSION, _TOPK_MODES[mode]))
+
+
+_GATHER_ORDERS = {"auto": _abi.GEM_GATHER_AUTO, "query": _abi.GEM_GATHER_BY_QUERY,
+                  "document": _abi.GEM_GATHER_BY_DOCUMENT}
+
+
+def set_gather_order(mode: str, device="cuda") -> None:
+    """How candidate-list calls walk their entries: "query" (one wave per run of
+    a query's entries, documents streamed), "document" (entries grouped by
+    document, each document staged once in LDS and scored against all of its
+    queries) or "auto" (by document once the lists name each document four
+    times or more on average). Both orders give bitwise the same scores."""
+    _abi.check(library().gem_set_option(_ctx(torch.device(device)), _abi.GEM_OPT_GATHER_ORDER,
+                                        _GATHER_ORDERS[mode]))
+
+
+def get_gather_order(device="cuda") -> str:
+    v = ctypes.c_int64(0)
+    _abi.check(library().gem_get_option(_ctx(torch.device(device)), _abi.GEM_OPT_GATHER_ORDER, ctypes.byref(v)))
+    return {b: a for a, b in _GATHER_ORDERS.items()}[int(v.value)]
 
 
 def set_check(on: bool, device="cuda") -> None:

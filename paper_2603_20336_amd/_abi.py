@@ -18,8 +18,9 @@ GEM_OK, GEM_ERR_INVALID, GEM_ERR_WORKSPACE, GEM_ERR_UNSUPPORTED, GEM_ERR_HIP, GE
 GEM_F32, GEM_BF16, GEM_FP8_E4M3, GEM_MXFP4, GEM_MXFP6, GEM_BF16X3 = 0, 1, 2, 3, 4, 5
 GEM_OP_SCORE_EXACT, GEM_OP_SCORE_QUANT, GEM_OP_TOPK, GEM_OP_EXPAND = 0, 1, 2, 3
 GEM_OP_NEAREST_CENTROID, GEM_OP_CENTROID_UPDATE = 4, 5
-GEM_OPT_TOPK_FUSION, GEM_OPT_CHECK = 0, 1
+GEM_OPT_TOPK_FUSION, GEM_OPT_CHECK, GEM_OPT_GATHER_ORDER = 0, 1, 2
 GEM_TOPK_AUTO, GEM_TOPK_FUSED, GEM_TOPK_STAGED = 0, 1, 2
+GEM_GATHER_AUTO, GEM_GATHER_BY_QUERY, GEM_GATHER_BY_DOCUMENT = 0, 1, 2
 GEM_STATIC_SCRATCH_BYTES = 64 << 20
 GEM_MAX_QUERY_LEN = 256
 GEM_MAX_K = 2048

@@ -27,6 +27,7 @@ struct gem_ctx_s {
   // keyed by (dtype, class of the list count, class of the longest list)
   std::map<uint64_t, gem::GatherSchedule> gather;
   int32_t topk_mode = GEM_TOPK_AUTO;     // GEM_OPT_TOPK_FUSION
+  int32_t gather_order = GEM_GATHER_AUTO;  // GEM_OPT_GATHER_ORDER
   void* scratch = nullptr;               // this device's copy of `scratch` (gem_score_quant_static)
   bool check = false;                    // GEM_OPT_CHECK: validate device inputs before computing
   unsigned long long check_bad = 0;      // violations since the last gem_check_status (under mu)
@@ -153,9 +154,26 @@ bool range_call(const gem_sets* Q, int32_t compute) {
   return Q->n_sets <= (compute == GEM_FP8_E4M3 ? kRangeMaxQueriesFp8 : kRangeMaxQueries);
 }
 
+// Whether a gathered call scores by document: the caller's choice, or (auto)
+// when the lists hold at least four entries per corpus document, so that
+// every listed document is listed at least four times on average. Documents
+// must be bounded by kByDocMaxRows (D->max_set_len), without code sets.
+constexpr int64_t kByDocMinEntriesPerDoc = 4;
+
+bool bydoc_call(const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t gather_order) {
+  if (!C || gather_order == GEM_GATHER_BY_QUERY) return false;
+  const bool ok = !D->codes && !Q->codes && D->n_sets > 0 && D->n_sets < INT32_MAX && D->max_set_len >= 1 &&
+                  D->max_set_len <= kByDocMaxRows && C->n_entries > 0 && C->n_entries <= INT32_MAX &&
+                  C->n_lists <= INT32_MAX;
+  if (!ok) return false;
+  return gather_order == GEM_GATHER_BY_DOCUMENT || C->n_entries >= kByDocMinEntriesPerDoc * D->n_sets;
+}
+
 // Workspace layout of a scoring call.
 struct ScoreLayout {
   size_t q_conv = 0, q_scales = 0, qb = 0, qcol = 0, staged = 0, total = 0;
+  bool bydoc = false;
+  size_t bydoc_ws = 0;
   int64_t n_blocks_max = 0;
   int block_rows = 0;
   // fused top-k of a dense call (k > 0 without a score matrix): regions,
@@ -166,7 +184,8 @@ struct ScoreLayout {
 };
 
 ScoreLayout score_layout(const gem_sets* Q, const gem_sets* D, const gem_cands* C, int32_t compute, int32_t k,
-                         bool scores_given, int slots_per_xcd, int32_t topk_mode = GEM_TOPK_AUTO) {
+                         bool scores_given, int slots_per_xcd, int32_t topk_mode = GEM_TOPK_AUTO,
+                         int32_t gather_order = GEM_GATHER_BY_QUERY) {
   ScoreLayout L;
   size_t off = 0;
   if (Q->dtype != compute) {
@@ -210,9 +229,16 @@ ScoreLayout score_layout(const gem_sets* Q, const gem_sets* D, const gem_cands* 
         off = align_up(off + staged);
       }
     }
-  } else if (k > 0 && !scores_given) {
-    L.staged = off;
-    off = align_up(off + (size_t)C->n_entries * 4);
+  } else {
+    if (k > 0 && !scores_given) {
+      L.staged = off;
+      off = align_up(off + (size_t)C->n_entries * 4);
+    }
+    if (bydoc_call(Q, D, C, gather_order)) {
+      L.bydoc = true;
+      L.bydoc_ws = off;
+      off = align_up(off + bydoc_ws_bytes(D->n_sets, C->n_entries));
+    }
   }
   L.total = off;
   return L;
@@ -308,7 +334,8 @@ gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const
     if (ld_scores < D->n_sets) return fail(GEM_ERR_INVALID, "ld_scores %lld < number of documents",
                                            (long long)ld_scores);
   }
-  const ScoreLayout L = score_layout(Q, D, C, compute, k, scores != nullptr, ctx->n_cu / 8, ctx->topk_mode);
+  const ScoreLayout L = score_layout(Q, D, C, compute, k, scores != nullptr, ctx->n_cu / 8, ctx->topk_mode,
+                                     gsched ? (int32_t)GEM_GATHER_BY_QUERY : ctx->gather_order);
   if (ws_bytes < L.total) return fail(GEM_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.total);
   if (L.total > 0 && !ws) return fail(GEM_ERR_INVALID, "workspace is NULL");
   if (Q->n_sets == 0) return GEM_OK;
@@ -369,9 +396,15 @@ gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const
     }
   } else {
     float* es = scores ? scores : reinterpret_cast<float*>(at(ws, L.staged));
-    const GatherSchedule gs = gsched ? *gsched : lookup_gather(ctx, compute, C->n_lists, list_len_bound(C));
-    e = launch_score_gather(compute, view(&Qc), view(D), cview(C), list_len_bound(C), Q->max_set_len, es, gs, stream);
-    if (e != hipSuccess) return hip_fail(e, "gathered scoring");
+    if (L.bydoc) {
+      e = launch_score_bydoc(compute, view(&Qc), view(D), cview(C), C->n_entries, es, at(ws, L.bydoc_ws), stream);
+      if (e != hipSuccess) return hip_fail(e, "gathered scoring by document");
+    } else {
+      const GatherSchedule gs = gsched ? *gsched : lookup_gather(ctx, compute, C->n_lists, list_len_bound(C));
+      e = launch_score_gather(compute, view(&Qc), view(D), cview(C), list_len_bound(C), Q->max_set_len, es, gs,
+                              stream);
+      if (e != hipSuccess) return hip_fail(e, "gathered scoring");
+    }
     if (k > 0) {
       TopkSegs S;
       S.scores = es; S.off = C->offsets; S.ids = C->ids; S.rows = nullptr;
@@ -854,6 +887,11 @@ gem_status gem_set_option(gem_ctx ctx, int32_t option, int64_t value) {
         return fail(GEM_ERR_INVALID, "top-k fusion mode %lld", (long long)value);
       ctx->topk_mode = (int32_t)value;
       return GEM_OK;
+    case GEM_OPT_GATHER_ORDER:
+      if (value != GEM_GATHER_AUTO && value != GEM_GATHER_BY_QUERY && value != GEM_GATHER_BY_DOCUMENT)
+        return fail(GEM_ERR_INVALID, "gather order %lld", (long long)value);
+      ctx->gather_order = (int32_t)value;
+      return GEM_OK;
     case GEM_OPT_CHECK:
       if (value != 0 && value != 1) return fail(GEM_ERR_INVALID, "check mode %lld", (long long)value);
       ctx->check = value != 0;
@@ -881,6 +919,7 @@ gem_status gem_get_option(gem_ctx ctx, int32_t option, int64_t* value) {
   if (!ctx || !value) return fail(GEM_ERR_INVALID, "NULL argument");
   switch (option) {
     case GEM_OPT_TOPK_FUSION: *value = ctx->topk_mode; return GEM_OK;
+    case GEM_OPT_GATHER_ORDER: *value = ctx->gather_order; return GEM_OK;
     case GEM_OPT_CHECK: *value = ctx->check ? 1 : 0; return GEM_OK;
     default: return fail(GEM_ERR_INVALID, "unknown option %d", option);
   }
@@ -894,7 +933,7 @@ size_t gem_workspace_bytes(gem_ctx ctx, int32_t op, const gem_sets* Q, const gem
     case GEM_OP_SCORE_QUANT: {
       if (!D) return 0;
       const int32_t cd = op == GEM_OP_SCORE_QUANT ? (mx_dtype(D->dtype) ? D->dtype : (int32_t)GEM_FP8_E4M3) : compute;
-      return score_layout(Q, D, C, cd, k, scores_given != 0, ctx->n_cu / 8, ctx->topk_mode).total;
+      return score_layout(Q, D, C, cd, k, scores_given != 0, ctx->n_cu / 8, ctx->topk_mode, ctx->gather_order).total;
     }
     case GEM_OP_EXPAND: {
       if (!D || !C) return 0;
@@ -1041,7 +1080,8 @@ gem_status gem_score_quant_static(gem_ctx ctx, const gem_sets* Q, const gem_sets
   if ((st = check_sets(Q, "Q", true)) != GEM_OK) return st;
   if ((st = check_sets(D, "D", false)) != GEM_OK) return st;
   if (C && (st = check_cands(C, Q->n_sets)) != GEM_OK) return st;
-  const size_t need = score_layout(Q, D, C, D->dtype, k, scores != nullptr, ctx->n_cu / 8, ctx->topk_mode).total;
+  const size_t need = score_layout(Q, D, C, D->dtype, k, scores != nullptr, ctx->n_cu / 8, ctx->topk_mode,
+                                   ctx->gather_order).total;
   if (need > (size_t)GEM_STATIC_SCRATCH_BYTES)
     return fail(GEM_ERR_WORKSPACE, "this call needs %zu bytes of workspace; the static scratch holds %zu", need,
                 (size_t)GEM_STATIC_SCRATCH_BYTES);

@@ -108,6 +108,17 @@ bool gather_schedule_valid(int dtype, const GatherSchedule& g);
 hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C,
                                int32_t max_list_len, int32_t max_q_len, float* scores, const GatherSchedule& g,
                                hipStream_t s);
+// Gathered scoring by document, for candidate lists that share documents (a
+// batch of shortlists drawn from the same corpus region): the call's entries
+// are grouped by document (a counting sort), and each workgroup stages one
+// document in LDS once and scores it against up to kByDocListings of the
+// queries that list it. Every score is bitwise the gathered scorer's.
+// Documents of up to kByDocMaxRows vectors, sets without codes.
+constexpr int kByDocListings = 64;
+constexpr int kByDocMaxRows = 256;
+size_t bydoc_ws_bytes(int64_t n_docs, int64_t n_entries);
+hipError_t launch_score_bydoc(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C, int64_t n_entries,
+                              float* scores, void* ws, hipStream_t s);
 // The dense output of a small query batch by the gathered scorer: every
 // document of D is an entry of every query's list (bitwise the dense scorer's
 // scores, one wave per few documents: memory-bound streaming instead of one

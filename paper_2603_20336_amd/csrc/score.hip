@@ -1410,4 +1410,309 @@ hipError_t launch_score_range(int dtype, const SetsView& Q, const SetsView& D, c
   return run_gather(dtype, P, D.n_sets, GatherSchedule{}, s);
 }
 
+// --------------------------------------------------------------------------
+// Gathered scoring by document. A batch of shortlists drawn from one corpus
+// lists the same documents many times (a rerank of 1000 queries' top-1000
+// holds about 26k distinct documents, each about 39 times), and the per-query
+// gathered scorer reads a document once per listing. Here the entries are
+// grouped by document first:
+//   1. count the listings of every document (negative ids are padding: their
+//      entries get -inf now and take no further part);
+//   2. exclusive scan of the counts (each document's first slot) and of the
+//      work items per document (ceil(count / kByDocListings));
+//   3. scatter every entry to its document's slots (entry index and query);
+//   4. one workgroup per work item stages its document's tiles in LDS once
+//      and its waves score the document against the item's listings, each
+//      listing query's operands loaded from memory (queries are few and stay
+//      in the caches).
+// The order of the entries inside a document's slots depends on the atomics,
+// but every entry's score is computed on its own, in the gathered scorer's
+// arithmetic: the same products, the running max over the document's tiles
+// in tile order, the column sums in tile order. So every score is bitwise the
+// per-query scorer's.
+
+namespace {
+constexpr int kScanBlock = 1024;
+
+// Query of entry e of list i: lists are walked by one wave each.
+__global__ __launch_bounds__(256) void bydoc_count_kernel(CandsView C, int64_t n_docs, int32_t* __restrict__ cnt,
+                                                          float* __restrict__ scores) {
+  const int l = threadIdx.x & 63;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < C.n_lists; i += (int64_t)gridDim.x * 4) {
+    const int64_t lb = C.off ? C.off[i] : i * (int64_t)C.stride;
+    const int64_t le = C.off ? C.off[i + 1] : lb + C.stride;
+    for (int64_t e = lb + l; e < le; e += 64) {
+      const int32_t id = C.ids[e];
+      if (id < 0 || id >= n_docs) scores[e] = neg_inf();
+      else atomicAdd(cnt + id, 1);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void bydoc_scatter_kernel(CandsView C, int64_t n_docs,
+                                                            const int32_t* __restrict__ start,
+                                                            int32_t* __restrict__ cursor,
+                                                            int32_t* __restrict__ slot_entry,
+                                                            int32_t* __restrict__ slot_query) {
+  const int l = threadIdx.x & 63;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < C.n_lists; i += (int64_t)gridDim.x * 4) {
+    const int64_t lb = C.off ? C.off[i] : i * (int64_t)C.stride;
+    const int64_t le = C.off ? C.off[i + 1] : lb + C.stride;
+    for (int64_t e = lb + l; e < le; e += 64) {
+      const int32_t id = C.ids[e];
+      if (id < 0 || id >= n_docs) continue;
+      const int32_t pos = start[id] + atomicAdd(cursor + id, 1);
+      slot_entry[pos] = (int32_t)e;
+      slot_query[pos] = (int32_t)i;
+    }
+  }
+}
+
+// Work items of each document: ceil(count / kByDocListings).
+__global__ __launch_bounds__(256) void bydoc_items_kernel(const int32_t* __restrict__ cnt, int64_t n,
+                                                          int32_t* __restrict__ items) {
+  for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < n; d += (int64_t)gridDim.x * 256)
+    items[d] = (cnt[d] + kByDocListings - 1) / kByDocListings;
+}
+
+// Exclusive scan of blocks of kScanBlock values: out[i] = sum of the block's
+// values before i; sums[b] = the block's total.
+__global__ __launch_bounds__(kScanBlock) void scan_blocks_kernel(const int32_t* __restrict__ in, int64_t n,
+                                                                 int32_t* __restrict__ out,
+                                                                 int32_t* __restrict__ sums) {
+  __shared__ int32_t buf[kScanBlock];
+  const int t = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kScanBlock + t;
+  const int32_t v = i < n ? in[i] : 0;
+  buf[t] = v;
+  __syncthreads();
+  for (int o = 1; o < kScanBlock; o <<= 1) {
+    const int32_t a = t >= o ? buf[t - o] : 0;
+    __syncthreads();
+    buf[t] += a;
+    __syncthreads();
+  }
+  if (i < n) out[i] = buf[t] - v;
+  if (t == kScanBlock - 1) sums[blockIdx.x] = buf[t];
+}
+
+// Exclusive scan of the block totals in one workgroup (chunks of kScanBlock
+// with a running carry); sums[n_blocks] receives the grand total.
+__global__ __launch_bounds__(kScanBlock) void scan_sums_kernel(int32_t* __restrict__ sums, int64_t n_blocks) {
+  __shared__ int32_t buf[kScanBlock];
+  const int t = threadIdx.x;
+  int32_t carry = 0;
+  for (int64_t c0 = 0; c0 < n_blocks; c0 += kScanBlock) {
+    const int64_t i = c0 + t;
+    const int32_t v = i < n_blocks ? sums[i] : 0;
+    buf[t] = v;
+    __syncthreads();
+    for (int o = 1; o < kScanBlock; o <<= 1) {
+      const int32_t a = t >= o ? buf[t - o] : 0;
+      __syncthreads();
+      buf[t] += a;
+      __syncthreads();
+    }
+    if (i < n_blocks) sums[i] = carry + buf[t] - v;
+    const int32_t tot = buf[kScanBlock - 1];
+    __syncthreads();
+    carry += tot;
+  }
+  if (t == 0) sums[n_blocks] = carry;
+}
+
+__global__ __launch_bounds__(256) void scan_add_kernel(int32_t* __restrict__ out, int64_t n,
+                                                       const int32_t* __restrict__ sums) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    out[i] += sums[i / kScanBlock];
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums[(n + kScanBlock - 1) / kScanBlock];
+}
+
+// out[0..n] = exclusive scan of in[0..n) with out[n] the total (sums: scratch
+// of n / kScanBlock + 2 values).
+hipError_t exclusive_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* sums, hipStream_t s) {
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb > 0) hipLaunchKernelGGL(scan_blocks_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n, out, sums);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kScanBlock), 0, s, sums, nb);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(capped_blocks((n + 255) / 256 + 1, 256)), dim3(256), 0, s, out, n,
+                     sums);
+  return hipGetLastError();
+}
+
+constexpr int kByDocWaves = 8;
+constexpr int kByDocMaxTiles = kByDocMaxRows / 16;
+
+struct ByDocParams {
+  SetsView Q, D;
+  const int32_t* start;       // [n_docs + 1] first slot of each document
+  const int32_t* item_start;  // [n_docs + 1] first work item of each document
+  const int32_t* slot_entry;  // entry index of each slot
+  const int32_t* slot_query;  // list (query) of each slot
+  int64_t n_docs;
+  float* scores;
+};
+}  // namespace
+
+template <int DT>
+__global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocParams P) {
+  using O = Op<DT>;
+  using TS = TileStage<DT>;
+  using Frag = typename O::Frag;
+  constexpr int NT = kGatherNT;
+  constexpr int PASS = 16 * NT;
+  __shared__ u32x4 stage[kByDocMaxTiles * TS::kStageBytes / 16];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c16 = l & 15;
+  const float ninf = neg_inf();
+
+  // work item -> document (the last d with item_start[d] <= item) and its listings
+  const int32_t item = (int32_t)blockIdx.x;
+  if (item >= P.item_start[P.n_docs]) return;
+  int64_t lo = 0, hi = P.n_docs;                       // item_start[lo] <= item < item_start[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (P.item_start[mid] <= item) lo = mid;
+    else hi = mid;
+  }
+  const int64_t d = lo;
+  const int32_t s0 = P.start[d] + (item - P.item_start[d]) * kByDocListings;
+  const int32_t s1 = min(P.start[d + 1], s0 + kByDocListings);
+
+  // the document's tiles into LDS (rows past its end repeat its last row)
+  const int64_t base = P.D.off[d];
+  const int d_len = (int)(P.D.off[d + 1] - base);
+  const int n_tiles = (d_len + 15) >> 4;
+  if (n_tiles > kByDocMaxTiles) {
+    // longer than the documents this path takes (the caller's bound was
+    // wrong): NaN scores, nothing staged
+    for (int32_t sl = s0 + w; sl < s1; sl += kByDocWaves)
+      if (l == 0) P.scores[P.slot_entry[sl]] = __int_as_float(0x7fc00000);
+    return;
+  }
+  for (int p = w; p < n_tiles * TS::kPieceWaves; p += kByDocWaves) {
+    const int k = p / TS::kPieceWaves, role = p % TS::kPieceWaves;
+    TS::copy_piece(P.D.vecs, base, 0, d_len, k, stage + k * (TS::kStageBytes / 16), role, l);
+  }
+  if constexpr (TS::kScales) {
+    for (int k = w; k < n_tiles; k += kByDocWaves)
+      TS::copy_scales(P.D.scales, base, 0, d_len, k, stage + k * (TS::kStageBytes / 16), l);
+  }
+  wait_vm<0>();
+  __syncthreads();
+
+  for (int32_t sl = s0 + w; sl < s1; sl += kByDocWaves) {
+    const int32_t e = P.slot_entry[sl];
+    const int32_t q = P.slot_query[sl];
+    const int64_t r0 = P.Q.off[q];
+    const int m = (int)(P.Q.off[q + 1] - r0);
+    float res = (d_len == 0 && m > 0) ? ninf : 0.0f;
+    if (m > 0 && n_tiles > 0) {
+      for (int prow0 = 0; prow0 < m; prow0 += PASS) {
+        const int pr = min(PASS, m - prow0);
+        const int nct = __builtin_amdgcn_readfirstlane((pr + 15) >> 4);
+        const bool first_pass = prow0 == 0;
+        Frag B[NT];
+        float qs[NT / 4];
+#pragma unroll
+        for (int i = 0; i < NT / 4; ++i) qs[i] = 1.0f;
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+          const int col = prow0 + 16 * ct + c16;
+          if (ct < nct && col < m) {
+            const int64_t vr = vec_row(P.Q, r0 + col);
+            O::load_b(B[ct], P.Q.vecs, P.Q.scales, vr, g);
+            if constexpr (O::kColumnScale)
+              if (g == (ct & 3)) qs[ct >> 2] = P.Q.scales[vr];
+          } else {
+            O::zero(B[ct]);
+          }
+        }
+        float rm[NT];
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) rm[ct] = ninf;
+        for (int T = 0; T < n_tiles; ++T) {
+          Frag A;
+          frag_from_lds<DT>(A, stage + T * (TS::kStageBytes / 16), c16, g);
+          f32x4 acc[NT];
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int c0 = 0; c0 < NT; c0 += 2) {
+            if (c0 < nct) {
+#pragma unroll
+              for (int s = 0; s < O::kSteps; ++s) {
+                acc[c0] = O::mma(A, B[c0], acc[c0], s);
+                acc[c0 + 1] = O::mma(A, B[c0 + 1], acc[c0 + 1], s);
+              }
+            }
+          }
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct) update_max(rm[ct], acc[ct]);
+        }
+        float R[NT / 4];
+        tile_sums<NT, O::kColumnScale>(rm, R, qs);
+        float s_run = first_pass ? tile_sum_at<NT>(R, 0) : res + tile_sum_at<NT>(R, 0);
+#pragma unroll
+        for (int ct = 1; ct < NT; ++ct)
+          if (ct < nct) s_run += tile_sum_at<NT>(R, ct);
+        res = s_run;
+      }
+    }
+    if (l == 0) P.scores[e] = res;
+  }
+}
+
+size_t bydoc_ws_bytes(int64_t n_docs, int64_t n_entries) {
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t nd1 = (size_t)n_docs + 1;
+  const size_t nb = (size_t)(n_docs + kScanBlock - 1) / kScanBlock + 2;
+  return 4 * up(nd1 * 4) + up(nb * 4) + 2 * up((size_t)n_entries * 4);
+}
+
+hipError_t launch_score_bydoc(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C, int64_t n_entries,
+                              float* scores, void* ws, hipStream_t s) {
+  if (C.n_lists == 0 || n_entries == 0) return hipSuccess;
+  if (D.n_sets <= 0 || D.codes || Q.codes || n_entries > INT32_MAX || D.n_sets > INT32_MAX - 1)
+    return hipErrorInvalidValue;
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const int64_t n_docs = D.n_sets;
+  const size_t nd1 = (size_t)n_docs + 1;
+  char* p = static_cast<char*>(ws);
+  int32_t* cnt = reinterpret_cast<int32_t*>(p);        p += up(nd1 * 4);
+  int32_t* start = reinterpret_cast<int32_t*>(p);      p += up(nd1 * 4);
+  int32_t* items = reinterpret_cast<int32_t*>(p);      p += up(nd1 * 4);
+  int32_t* item_start = reinterpret_cast<int32_t*>(p); p += up(nd1 * 4);
+  int32_t* sums = reinterpret_cast<int32_t*>(p);       p += up(((size_t)(n_docs + kScanBlock - 1) / kScanBlock + 2) * 4);
+  int32_t* slot_entry = reinterpret_cast<int32_t*>(p); p += up((size_t)n_entries * 4);
+  int32_t* slot_query = reinterpret_cast<int32_t*>(p);
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), n_docs, 0u, s);
+  if (e != hipSuccess) return e;
+  const unsigned lgrid = capped_blocks((C.n_lists + 3) / 4, 256);
+  hipLaunchKernelGGL(bydoc_count_kernel, dim3(lgrid), dim3(256), 0, s, C, n_docs, cnt, scores);
+  if ((e = exclusive_scan(cnt, n_docs, start, sums, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(bydoc_items_kernel, dim3(capped_blocks((n_docs + 255) / 256, 256)), dim3(256), 0, s, cnt,
+                     n_docs, items);
+  if ((e = exclusive_scan(items, n_docs, item_start, sums, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), n_docs, 0u, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(bydoc_scatter_kernel, dim3(lgrid), dim3(256), 0, s, C, n_docs, start, cnt, slot_entry,
+                     slot_query);
+  ByDocParams P;
+  P.Q = Q; P.D = D; P.start = start; P.item_start = item_start; P.slot_entry = slot_entry;
+  P.slot_query = slot_query; P.n_docs = n_docs; P.scores = scores;
+  // work items: at most one per kByDocListings listed entries plus one per
+  // listed document; workgroups past the item count exit at once
+  const int64_t grid = n_entries / kByDocListings + std::min<int64_t>(n_docs, n_entries) + 1;
+  if (grid > INT32_MAX) return hipErrorInvalidValue;
+  const dim3 gr((unsigned)grid), blk(64 * kByDocWaves);
+  switch (dtype) {
+    case GEM_F32: hipLaunchKernelGGL(score_bydoc_kernel<GEM_F32>, gr, blk, 0, s, P); break;
+    case GEM_BF16X3: hipLaunchKernelGGL(score_bydoc_kernel<GEM_BF16X3>, gr, blk, 0, s, P); break;
+    case GEM_BF16: hipLaunchKernelGGL(score_bydoc_kernel<GEM_BF16>, gr, blk, 0, s, P); break;
+    case GEM_FP8_E4M3: hipLaunchKernelGGL(score_bydoc_kernel<GEM_FP8_E4M3>, gr, blk, 0, s, P); break;
+    case GEM_MXFP4: hipLaunchKernelGGL(score_bydoc_kernel<GEM_MXFP4>, gr, blk, 0, s, P); break;
+    case GEM_MXFP6: hipLaunchKernelGGL(score_bydoc_kernel<GEM_MXFP6>, gr, blk, 0, s, P); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace gem
