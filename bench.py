@@ -355,7 +355,6 @@ def bench_exhaustive(args):
     t_x3 = timed(lambda: gem.score_exact(Q, Dx3, compute="bf16x3", k=k), max(1, args.steps // 4))
     gem.score_exact(Q, Dx3, compute="bf16x3", scores=scores)
     x3_sample = scores[:max(1, args.cpu_sample)].clone()
-    del Dx3
     log(f"bf16x3 exact path {t_x3:.1f} ms ({t_f32 / t_x3:.2f}x the f32 path)")
 
     def rerank(short_i, sl):
@@ -388,6 +387,23 @@ def bench_exhaustive(args):
     fp8_sample = est[:max(1, args.cpu_sample)].clone()
     fp8_sweep, r8_s, r8_i = sweep("fp8", lambda: gem.quantize_fp8(Q), lambda q8, sl: gem.score_quant(q8, D8, k=sl))
     r8_s, r8_i = rerank(gem.score_quant(gem.quantize_fp8(Q), D8, k=1000)[1], 1000)
+
+    # the rerank of the FP8 top-1000 (1M entries over about 26k distinct
+    # documents) in both gather orders, in float32 and in split-bf16
+    short1000 = gem.score_quant(gem.quantize_fp8(Q), D8, k=1000)[1]
+    C1000 = gem.Cands(short1000.reshape(-1), stride=1000, n_lists=n_q)
+    rerank_orders = {"entries": n_q * 1000, "distinct_docs": int(torch.unique(short1000).numel())}
+    for order in ("query", "document"):
+        gem.set_gather_order(order)
+        rerank_orders[f"f32_by_{order}_ms"] = timed(
+            lambda: gem.score_exact(Q, D32, cands=C1000, compute="f32", k=k), max(1, args.steps // 4))
+        rerank_orders[f"bf16x3_by_{order}_ms"] = timed(
+            lambda: gem.score_exact(Q, Dx3, cands=C1000, compute="bf16x3", k=k), max(1, args.steps // 4))
+    gem.set_gather_order("auto")
+    _, rx3_i = gem.score_exact(Q, Dx3, cands=C1000, compute="bf16x3", k=k)
+    rerank_orders[f"bf16x3_rerank_recall_at_{k}"] = recall_gpu(rx3_i, exact, exact_kth, k)
+    log(f"rerank of the FP8 top-1000: {rerank_orders}")
+    del Dx3, C1000, short1000
 
     # MXFP4 estimate (E2M1 codes, a power-of-two scale per 32 dims)
     D4 = gem.quantize_mxfp4(D32)
@@ -510,7 +526,7 @@ def bench_exhaustive(args):
         "fp8_rerank_path": dict(fp8_sweep.get("1000", {}), shortlist=1000, fp8_score_ms=t_fp8_score,
                                 fp8_tflops=flops / (t_fp8_score / 1e3) / 1e12,
                                 fp8_frac_of_peak=flops / (t_fp8_score / 1e3) / PEAK_FP8,
-                                shortlist_sweep=fp8_sweep),
+                                shortlist_sweep=fp8_sweep, rerank_gather_orders=rerank_orders),
         "mxfp4_rerank_path": dict(mx_sweep.get("1000", {}), shortlist=1000, mxfp4_score_ms=t_mx_score,
                                   mxfp4_tflops=flops / (t_mx_score / 1e3) / 1e12,
                                   mxfp4_frac_of_peak=flops / (t_mx_score / 1e3) / PEAK_FP4,

@@ -1475,6 +1475,14 @@ __global__ __launch_bounds__(256) void bydoc_items_kernel(const int32_t* __restr
     items[d] = (cnt[d] + kByDocListings - 1) / kByDocListings;
 }
 
+// Document of every work item: items item_start[d] .. item_start[d + 1] - 1
+// belong to document d.
+__global__ __launch_bounds__(256) void bydoc_item_doc_kernel(const int32_t* __restrict__ item_start, int64_t n,
+                                                             int32_t* __restrict__ item_doc) {
+  for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < n; d += (int64_t)gridDim.x * 256)
+    for (int32_t it = item_start[d]; it < item_start[d + 1]; ++it) item_doc[it] = (int32_t)d;
+}
+
 // Exclusive scan of blocks of kScanBlock values: out[i] = sum of the block's
 // values before i; sums[b] = the block's total.
 __global__ __launch_bounds__(kScanBlock) void scan_blocks_kernel(const int32_t* __restrict__ in, int64_t n,
@@ -1546,12 +1554,58 @@ struct ByDocParams {
   SetsView Q, D;
   const int32_t* start;       // [n_docs + 1] first slot of each document
   const int32_t* item_start;  // [n_docs + 1] first work item of each document
+  const int32_t* item_doc;    // document of each work item
   const int32_t* slot_entry;  // entry index of each slot
   const int32_t* slot_query;  // list (query) of each slot
   int64_t n_docs;
   float* scores;
 };
 }  // namespace
+
+// The running maxima of one pass of the document-major scorer over the staged
+// tiles 0..n_tiles-1: the products of each used column tile's query columns
+// with every document tile, in the gathered scorer's order (each column
+// tile's accumulator takes the K steps in order). With more than two column
+// tiles in use the four accumulators advance together, so that consecutive
+// products never wait on one another; the next tile's A operand is read while
+// the last products finish.
+template <int DT>
+__device__ __forceinline__ void bydoc_tiles(typename Op<DT>::Frag A, const typename Op<DT>::Frag (&B)[kGatherNT],
+                                            float (&rm)[kGatherNT], const u32x4* stage, int n_tiles, int nct,
+                                            int c16, int g) {
+  using O = Op<DT>;
+  using TS = TileStage<DT>;
+  constexpr int NT = kGatherNT;
+  static_assert(NT == 4, "column tiles of a pass");
+  for (int T = 0; T < n_tiles; ++T) {
+    f32x4 acc[NT];
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (nct > 2) {
+#pragma unroll
+      for (int s = 0; s < O::kSteps; ++s) {
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) acc[ct] = O::mma(A, B[ct], acc[ct], s);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < O::kSteps; ++s) {
+        acc[0] = O::mma(A, B[0], acc[0], s);
+        acc[1] = O::mma(A, B[1], acc[1], s);
+      }
+    }
+    if (T + 1 < n_tiles) frag_from_lds<DT>(A, stage + (T + 1) * (TS::kStageBytes / 16), c16, g);
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) update_max(rm[ct], acc[ct]);
+  }
+}
+
+template <int DT>
+__device__ __forceinline__ typename Op<DT>::Frag A_first(const u32x4* stage, int c16, int g) {
+  typename Op<DT>::Frag A;
+  frag_from_lds<DT>(A, stage, c16, g);
+  return A;
+}
 
 template <int DT>
 __global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocParams P) {
@@ -1564,16 +1618,10 @@ __global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocPara
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c16 = l & 15;
   const float ninf = neg_inf();
 
-  // work item -> document (the last d with item_start[d] <= item) and its listings
+  // work item -> document and its listings
   const int32_t item = (int32_t)blockIdx.x;
   if (item >= P.item_start[P.n_docs]) return;
-  int64_t lo = 0, hi = P.n_docs;                       // item_start[lo] <= item < item_start[hi]
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (P.item_start[mid] <= item) lo = mid;
-    else hi = mid;
-  }
-  const int64_t d = lo;
+  const int64_t d = P.item_doc[item];
   const int32_t s0 = P.start[d] + (item - P.item_start[d]) * kByDocListings;
   const int32_t s1 = min(P.start[d + 1], s0 + kByDocListings);
 
@@ -1588,6 +1636,17 @@ __global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocPara
       if (l == 0) P.scores[P.slot_entry[sl]] = __int_as_float(0x7fc00000);
     return;
   }
+  // the wave's listings s0 + w + kByDocWaves * i (at most 8): lane i holds
+  // listing i's entry, query's first row and length, loaded while the
+  // document's tiles are in flight
+  const int n_mine = s1 > s0 + w ? (s1 - s0 - w + kByDocWaves - 1) / kByDocWaves : 0;
+  int32_t my_e = 0, my_q = 0, my_m = 0;
+  int64_t my_r0 = 0;
+  if (l < n_mine) {
+    const int32_t sl = s0 + w + kByDocWaves * l;
+    my_e = P.slot_entry[sl];
+    my_q = P.slot_query[sl];
+  }
   for (int p = w; p < n_tiles * TS::kPieceWaves; p += kByDocWaves) {
     const int k = p / TS::kPieceWaves, role = p % TS::kPieceWaves;
     TS::copy_piece(P.D.vecs, base, 0, d_len, k, stage + k * (TS::kStageBytes / 16), role, l);
@@ -1596,17 +1655,58 @@ __global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocPara
     for (int k = w; k < n_tiles; k += kByDocWaves)
       TS::copy_scales(P.D.scales, base, 0, d_len, k, stage + k * (TS::kStageBytes / 16), l);
   }
+  if (l < n_mine) {
+    my_r0 = P.Q.off[my_q];
+    my_m = (int)(P.Q.off[my_q + 1] - my_r0);
+  }
   wait_vm<0>();
   __syncthreads();
 
-  for (int32_t sl = s0 + w; sl < s1; sl += kByDocWaves) {
-    const int32_t e = P.slot_entry[sl];
-    const int32_t q = P.slot_query[sl];
-    const int64_t r0 = P.Q.off[q];
-    const int m = (int)(P.Q.off[q + 1] - r0);
-    float res = (d_len == 0 && m > 0) ? ninf : 0.0f;
-    if (m > 0 && n_tiles > 0) {
-      for (int prow0 = 0; prow0 < m; prow0 += PASS) {
+  // The wave takes the item's listings s0 + w, s0 + w + kByDocWaves, ...
+  // Consecutive ones whose queries fit one pass of PASS columns together
+  // share it: listing j takes the column tiles [qc_j, qc_j + qn_j) (qn_j = its
+  // query's 16-column tiles), NT in all. A column tile's maxima and sum depend
+  // only on that tile's own column values, so a listing's score does not
+  // depend on the listings it shares a pass with. A query of more than PASS
+  // vectors takes passes of its own.
+  int i = 0;
+  while (i < n_mine) {
+    int32_t ent[NT], qn[NT], qc[NT], qm[NT];
+    int64_t qr[NT];
+    int nl = 0, ctot = 0;
+    bool open = true, alone = false;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      ent[j] = 0; qn[j] = 0; qc[j] = 0; qm[j] = 0; qr[j] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      if (open && i < n_mine) {
+        const int32_t e = __builtin_amdgcn_readlane(my_e, i);
+        const int64_t r0 = (int64_t)readlane_u64((uint64_t)my_r0, i);
+        const int m = __builtin_amdgcn_readlane(my_m, i);
+        const int n = (m + 15) >> 4;
+        if (m > PASS) {
+          if (j == 0) {
+            ent[0] = e; qr[0] = r0; qm[0] = m; nl = 1; alone = true;
+            ++i;
+          }
+          open = false;
+        } else if (ctot + n > NT) {
+          open = false;
+        } else {
+          ent[j] = e; qr[j] = r0; qm[j] = m; qn[j] = n; qc[j] = ctot;
+          ctot += n; nl = j + 1;
+          ++i;
+        }
+      }
+    }
+
+    if (alone) {
+      // one listing in passes of PASS columns
+      const int m = qm[0];
+      float res = d_len == 0 ? ninf : 0.0f;
+      for (int prow0 = 0; prow0 < m && n_tiles > 0; prow0 += PASS) {
         const int pr = min(PASS, m - prow0);
         const int nct = __builtin_amdgcn_readfirstlane((pr + 15) >> 4);
         const bool first_pass = prow0 == 0;
@@ -1618,7 +1718,7 @@ __global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocPara
         for (int ct = 0; ct < NT; ++ct) {
           const int col = prow0 + 16 * ct + c16;
           if (ct < nct && col < m) {
-            const int64_t vr = vec_row(P.Q, r0 + col);
+            const int64_t vr = vec_row(P.Q, qr[0] + col);
             O::load_b(B[ct], P.Q.vecs, P.Q.scales, vr, g);
             if constexpr (O::kColumnScale)
               if (g == (ct & 3)) qs[ct >> 2] = P.Q.scales[vr];
@@ -1629,25 +1729,7 @@ __global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocPara
         float rm[NT];
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct) rm[ct] = ninf;
-        for (int T = 0; T < n_tiles; ++T) {
-          Frag A;
-          frag_from_lds<DT>(A, stage + T * (TS::kStageBytes / 16), c16, g);
-          f32x4 acc[NT];
-#pragma unroll
-          for (int ct = 0; ct < NT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int c0 = 0; c0 < NT; c0 += 2) {
-            if (c0 < nct) {
-#pragma unroll
-              for (int s = 0; s < O::kSteps; ++s) {
-                acc[c0] = O::mma(A, B[c0], acc[c0], s);
-                acc[c0 + 1] = O::mma(A, B[c0 + 1], acc[c0 + 1], s);
-              }
-            }
-          }
-#pragma unroll
-          for (int ct = 0; ct < NT; ++ct) update_max(rm[ct], acc[ct]);
-        }
+        bydoc_tiles<DT>(A_first<DT>(stage, c16, g), B, rm, stage, n_tiles, nct, c16, g);
         float R[NT / 4];
         tile_sums<NT, O::kColumnScale>(rm, R, qs);
         float s_run = first_pass ? tile_sum_at<NT>(R, 0) : res + tile_sum_at<NT>(R, 0);
@@ -1656,16 +1738,77 @@ __global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocPara
           if (ct < nct) s_run += tile_sum_at<NT>(R, ct);
         res = s_run;
       }
+      if (l == 0) P.scores[ent[0]] = res;
+      continue;
     }
-    if (l == 0) P.scores[e] = res;
+
+    if (n_tiles == 0 || ctot == 0) {
+      // an empty document (-inf, or 0 for an empty query) or empty queries (0)
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+        if (j < nl && l == 0) P.scores[ent[j]] = (d_len == 0 && qm[j] > 0) ? ninf : 0.0f;
+      continue;
+    }
+
+    // the group's shared pass
+    const int nct = __builtin_amdgcn_readfirstlane(ctot);
+    Frag B[NT];
+    float qs[NT / 4];
+#pragma unroll
+    for (int i = 0; i < NT / 4; ++i) qs[i] = 1.0f;
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) {
+      int64_t vr = -1;
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        if (j < nl && ct >= qc[j] && ct < qc[j] + qn[j]) {
+          const int col = 16 * (ct - qc[j]) + c16;
+          if (col < qm[j]) vr = vec_row(P.Q, qr[j] + col);
+        }
+      }
+      if (vr >= 0) {
+        O::load_b(B[ct], P.Q.vecs, P.Q.scales, vr, g);
+        if constexpr (O::kColumnScale)
+          if (g == (ct & 3)) qs[ct >> 2] = P.Q.scales[vr];
+      } else {
+        O::zero(B[ct]);
+      }
+    }
+    float rm[NT];
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) rm[ct] = ninf;
+    bydoc_tiles<DT>(A_first<DT>(stage, c16, g), B, rm, stage, n_tiles, nct, c16, g);
+    float R[NT / 4];
+    tile_sums<NT, O::kColumnScale>(rm, R, qs);
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      if (j < nl) {
+        // the listing's column tiles in order, as a pass of its own sums them
+        float res = 0.0f;
+        if (qn[j] > 0) {
+          res = tile_sum_at<NT>(R, qc[j]);
+#pragma unroll
+          for (int t = 1; t < NT; ++t)
+            if (t < qn[j]) res += tile_sum_at<NT>(R, qc[j] + t);
+        }
+        if (l == 0) P.scores[ent[j]] = res;
+      }
+    }
   }
+}
+
+// Work items of a call: at most one per kByDocListings listed entries plus
+// one per listed document.
+static int64_t bydoc_items_bound(int64_t n_docs, int64_t n_entries) {
+  return n_entries / kByDocListings + std::min<int64_t>(n_docs, n_entries) + 1;
 }
 
 size_t bydoc_ws_bytes(int64_t n_docs, int64_t n_entries) {
   auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t nd1 = (size_t)n_docs + 1;
   const size_t nb = (size_t)(n_docs + kScanBlock - 1) / kScanBlock + 2;
-  return 4 * up(nd1 * 4) + up(nb * 4) + 2 * up((size_t)n_entries * 4);
+  return 4 * up(nd1 * 4) + up(nb * 4) + 2 * up((size_t)n_entries * 4) +
+         up((size_t)bydoc_items_bound(n_docs, n_entries) * 4);
 }
 
 hipError_t launch_score_bydoc(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C, int64_t n_entries,
@@ -1683,7 +1826,8 @@ hipError_t launch_score_bydoc(int dtype, const SetsView& Q, const SetsView& D, c
   int32_t* item_start = reinterpret_cast<int32_t*>(p); p += up(nd1 * 4);
   int32_t* sums = reinterpret_cast<int32_t*>(p);       p += up(((size_t)(n_docs + kScanBlock - 1) / kScanBlock + 2) * 4);
   int32_t* slot_entry = reinterpret_cast<int32_t*>(p); p += up((size_t)n_entries * 4);
-  int32_t* slot_query = reinterpret_cast<int32_t*>(p);
+  int32_t* slot_query = reinterpret_cast<int32_t*>(p); p += up((size_t)n_entries * 4);
+  int32_t* item_doc = reinterpret_cast<int32_t*>(p);
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), n_docs, 0u, s);
   if (e != hipSuccess) return e;
   const unsigned lgrid = capped_blocks((C.n_lists + 3) / 4, 256);
@@ -1692,15 +1836,16 @@ hipError_t launch_score_bydoc(int dtype, const SetsView& Q, const SetsView& D, c
   hipLaunchKernelGGL(bydoc_items_kernel, dim3(capped_blocks((n_docs + 255) / 256, 256)), dim3(256), 0, s, cnt,
                      n_docs, items);
   if ((e = exclusive_scan(items, n_docs, item_start, sums, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(bydoc_item_doc_kernel, dim3(capped_blocks((n_docs + 255) / 256, 256)), dim3(256), 0, s,
+                     item_start, n_docs, item_doc);
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), n_docs, 0u, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(bydoc_scatter_kernel, dim3(lgrid), dim3(256), 0, s, C, n_docs, start, cnt, slot_entry,
                      slot_query);
   ByDocParams P;
-  P.Q = Q; P.D = D; P.start = start; P.item_start = item_start; P.slot_entry = slot_entry;
+  P.Q = Q; P.D = D; P.start = start; P.item_start = item_start; P.item_doc = item_doc; P.slot_entry = slot_entry;
   P.slot_query = slot_query; P.n_docs = n_docs; P.scores = scores;
-  // work items: at most one per kByDocListings listed entries plus one per
-  // listed document; workgroups past the item count exit at once
-  const int64_t grid = n_entries / kByDocListings + std::min<int64_t>(n_docs, n_entries) + 1;
+  // workgroups past the item count exit at once
+  const int64_t grid = bydoc_items_bound(n_docs, n_entries);
   if (grid > INT32_MAX) return hipErrorInvalidValue;
   const dim3 gr((unsigned)grid), blk(64 * kByDocWaves);
   switch (dtype) {
