@@ -680,6 +680,8 @@ def bench_expansion(args):
         uniq_bytes += int(lens[uniq.long()].sum().item()) * 132
     # the autotuner picks the gathered scorer's schedule for this step shape
     # (entries per wave, tiles in flight); every step has the same shape class
+    gem.score_quant(Q8, D8, cands=steps[0])
+    torch.cuda.synchronize()
     t_default = timed(lambda: gem.score_quant(Q8, D8, cands=steps[0]), 3)
     gsched, t_tuned = gem.autotune_gather(Q8, D8, steps[0], reps=3)
     log(f"expansion gather schedule {gsched}: {t_tuned:.3f} ms (library rule {t_default:.3f} ms)")

@@ -208,10 +208,14 @@ const char* gem_version(void);
  *       LDS once and scored against every query that lists it. Pays when the
  *       lists share documents (a batch of top-1000 shortlists lists each of
  *       its documents tens of times). Needs D->max_set_len in [1, 256] (a bound
- *       of every document's length; a longer document's entries get NaN) and
- *       no code sets; otherwise the call reads by query.
- *     GEM_GATHER_AUTO (default): by document when those conditions hold and
- *       the lists hold at least four entries per document of D, else by query.
+ *       of every document's length; a longer document scored by document
+ *       gets NaN scores) and no code sets; otherwise the call reads by query.
+ *     GEM_GATHER_AUTO (default): when those conditions hold and the lists
+ *       hold at least two entries per document of D (four in bf16, FP8 and
+ *       the MX formats), the mixed order: the counting sort counts each
+ *       document's listings, and a document whose listings times its 16-row
+ *       tiles reach a threshold of the format (f32 192, split bf16 96, others
+ *       64) is scored by document, the other entries by query. Else by query.
  *   Every order gives the same scores, bitwise. gem_workspace_bytes follows
  *   the option. gem_expand_batch always reads by query. */
 typedef enum { GEM_OPT_TOPK_FUSION = 0, GEM_OPT_CHECK = 1, GEM_OPT_GATHER_ORDER = 2 } gem_option;

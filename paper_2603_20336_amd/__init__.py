@@ -312,8 +312,10 @@ def set_gather_order(mode: str, device="cuda") -> None:
     """How candidate-list calls walk their entries: "query" (one wave per run of
     a query's entries, documents streamed), "document" (entries grouped by
     document, each document staged once in LDS and scored against all of its
-    queries) or "auto" (by document once the lists name each document four
-    times or more on average). Both orders give bitwise the same scores."""
+    queries) or "auto" (once the lists hold two or more entries per corpus
+    document in f32 and bf16x3, four in the other formats: a document whose listings times 16-row tiles reach a threshold
+    of the format by document, the rest by query). Every order gives bitwise
+    the same scores."""
     _abi.check(library().gem_set_option(_ctx(torch.device(device)), _abi.GEM_OPT_GATHER_ORDER,
                                         _GATHER_ORDERS[mode]))
 

@@ -105,20 +105,33 @@ struct GatherSchedule {
 int gather_depth_choice(int dtype, int i);
 bool gather_schedule_valid(int dtype, const GatherSchedule& g);
 
+// Entries the gathered scorer leaves to the document-major scorer: those of
+// the documents that have work items there (item_start: the exclusive scan of
+// the items per document, item_start[d + 1] > item_start[d]). Their scores
+// are not written.
+struct GatherSkip {
+  const int32_t* item_start = nullptr;
+};
 hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C,
                                int32_t max_list_len, int32_t max_q_len, float* scores, const GatherSchedule& g,
-                               hipStream_t s);
+                               hipStream_t s, const GatherSkip& skip = GatherSkip{});
 // Gathered scoring by document, for candidate lists that share documents (a
 // batch of shortlists drawn from the same corpus region): the call's entries
 // are grouped by document (a counting sort), and each workgroup stages one
 // document in LDS once and scores it against up to kByDocListings of the
 // queries that list it. Every score is bitwise the gathered scorer's.
-// Documents of up to kByDocMaxRows vectors, sets without codes.
+// Documents of up to kByDocMaxRows vectors, sets without codes. Only documents
+// with at least min_work listing-tiles (listings x 16-row tiles) are scored
+// (every listed document for min_work <= 1); *skip receives what the gathered
+// scorer needs to take the others.
 constexpr int kByDocListings = 64;
 constexpr int kByDocMaxRows = 256;
+// The mixed order's threshold of a format: a document's listing-tiles from
+// which scoring it by document takes less time than streaming it per listing.
+int32_t bydoc_min_work(int dtype);
 size_t bydoc_ws_bytes(int64_t n_docs, int64_t n_entries);
 hipError_t launch_score_bydoc(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C, int64_t n_entries,
-                              float* scores, void* ws, hipStream_t s);
+                              float* scores, void* ws, int32_t min_work, GatherSkip* skip, hipStream_t s);
 // The dense output of a small query batch by the gathered scorer: every
 // document of D is an entry of every query's list (bitwise the dense scorer's
 // scores, one wave per few documents: memory-bound streaming instead of one

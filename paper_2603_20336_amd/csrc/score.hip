@@ -1162,6 +1162,9 @@ struct GatherParams {
   int32_t range;
   const int32_t* out_rows;
   int64_t out_ld;
+  // entries of documents with work items in the document-major scorer
+  // (skip_items: its item scan) are left to it
+  const int32_t* skip_items;
 };
 
 // kCodes: the documents are a code set. Each lane then loads the code of the
@@ -1195,9 +1198,16 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
   int32_t my_id = -1;
   int64_t d_beg = 0;
   int d_len = 0;
+  bool skip = false;                                   // scored by the document-major scorer
   if (l < ne) {
     my_id = P.range ? (int32_t)(e0 + l) : P.C.ids[e0 + l];
-    if (my_id >= 0) { d_beg = P.D.off[my_id]; d_len = (int)(P.D.off[my_id + 1] - d_beg); }
+    if (my_id >= 0) {
+      // (the skip test's loads go out with the offsets', not before them)
+      d_beg = P.D.off[my_id];
+      d_len = (int)(P.D.off[my_id + 1] - d_beg);
+      if (P.skip_items) skip = P.skip_items[my_id + 1] > P.skip_items[my_id];
+      if (skip) d_len = 0;
+    }
   }
   const int d_nt = (d_len + 15) >> 4;
   int d_incl = d_nt;
@@ -1323,7 +1333,7 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
       }
     }
   }
-  if (l < ne) {
+  if (l < ne && !skip) {
     if (P.range) P.scores[(P.out_rows ? (int64_t)P.out_rows[q] : q) * P.out_ld + e0 + l] = res;
     else P.scores[e0 + l] = res;
   }
@@ -1393,10 +1403,12 @@ static hipError_t run_gather(int dtype, GatherParams P, int64_t max_list_len, co
 }
 
 hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C,
-                               int32_t max_list_len, int32_t, float* scores, const GatherSchedule& g, hipStream_t s) {
+                               int32_t max_list_len, int32_t, float* scores, const GatherSchedule& g, hipStream_t s,
+                               const GatherSkip& skip) {
   GatherParams P{};
   P.Q = Q; P.D = D; P.C = C; P.scores = scores;
   P.range = 0;
+  P.skip_items = skip.item_start;
   return run_gather(dtype, P, max_list_len, g, s);
 }
 
@@ -1450,6 +1462,7 @@ __global__ __launch_bounds__(256) void bydoc_count_kernel(CandsView C, int64_t n
 }
 
 __global__ __launch_bounds__(256) void bydoc_scatter_kernel(CandsView C, int64_t n_docs,
+                                                            const int32_t* __restrict__ item_start,
                                                             const int32_t* __restrict__ start,
                                                             int32_t* __restrict__ cursor,
                                                             int32_t* __restrict__ slot_entry,
@@ -1460,7 +1473,7 @@ __global__ __launch_bounds__(256) void bydoc_scatter_kernel(CandsView C, int64_t
     const int64_t le = C.off ? C.off[i + 1] : lb + C.stride;
     for (int64_t e = lb + l; e < le; e += 64) {
       const int32_t id = C.ids[e];
-      if (id < 0 || id >= n_docs) continue;
+      if (id < 0 || id >= n_docs || item_start[id + 1] == item_start[id]) continue;
       const int32_t pos = start[id] + atomicAdd(cursor + id, 1);
       slot_entry[pos] = (int32_t)e;
       slot_query[pos] = (int32_t)i;
@@ -1468,11 +1481,18 @@ __global__ __launch_bounds__(256) void bydoc_scatter_kernel(CandsView C, int64_t
   }
 }
 
-// Work items of each document: ceil(count / kByDocListings).
-__global__ __launch_bounds__(256) void bydoc_items_kernel(const int32_t* __restrict__ cnt, int64_t n,
-                                                          int32_t* __restrict__ items) {
-  for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < n; d += (int64_t)gridDim.x * 256)
-    items[d] = (cnt[d] + kByDocListings - 1) / kByDocListings;
+// Work items of each document: ceil(count / kByDocListings), none when its
+// listings times its 16-row tiles fall below min_work (min_work <= 1: every
+// listed document).
+__global__ __launch_bounds__(256) void bydoc_items_kernel(const int32_t* __restrict__ cnt,
+                                                          const int64_t* __restrict__ d_off, int64_t n,
+                                                          int32_t min_work, int32_t* __restrict__ items) {
+  for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < n; d += (int64_t)gridDim.x * 256) {
+    const int32_t c = cnt[d];
+    const int64_t tiles = (d_off[d + 1] - d_off[d] + 15) >> 4;
+    const bool take = c > 0 && (min_work <= 1 || (int64_t)c * tiles >= min_work);
+    items[d] = take ? (c + kByDocListings - 1) / kByDocListings : 0;
+  }
 }
 
 // Document of every work item: items item_start[d] .. item_start[d + 1] - 1
@@ -1811,8 +1831,22 @@ size_t bydoc_ws_bytes(int64_t n_docs, int64_t n_entries) {
          up((size_t)bydoc_items_bound(n_docs, n_entries) * 4);
 }
 
+// Listing-tiles from which a document is scored by document in the mixed
+// order. Measured on reranks of FP8 top-200 to top-2000 shortlists of 1000
+// queries over 100k documents and of 4096 beams of 1000 over 1M documents,
+// thresholds 48 to 768: float32 best at 192-384 (below that the short,
+// rarely listed beam documents lose to streaming), split bf16 flat from 48 to
+// 192, FP8 best at 32-64.
+int32_t bydoc_min_work(int dtype) {
+  switch (dtype) {
+    case GEM_F32: return 192;
+    case GEM_BF16X3: return 96;
+    default: return 64;
+  }
+}
+
 hipError_t launch_score_bydoc(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C, int64_t n_entries,
-                              float* scores, void* ws, hipStream_t s) {
+                              float* scores, void* ws, int32_t min_work, GatherSkip* skip, hipStream_t s) {
   if (C.n_lists == 0 || n_entries == 0) return hipSuccess;
   if (D.n_sets <= 0 || D.codes || Q.codes || n_entries > INT32_MAX || D.n_sets > INT32_MAX - 1)
     return hipErrorInvalidValue;
@@ -1833,14 +1867,15 @@ hipError_t launch_score_bydoc(int dtype, const SetsView& Q, const SetsView& D, c
   const unsigned lgrid = capped_blocks((C.n_lists + 3) / 4, 256);
   hipLaunchKernelGGL(bydoc_count_kernel, dim3(lgrid), dim3(256), 0, s, C, n_docs, cnt, scores);
   if ((e = exclusive_scan(cnt, n_docs, start, sums, s)) != hipSuccess) return e;
+  if (skip) skip->item_start = item_start;
   hipLaunchKernelGGL(bydoc_items_kernel, dim3(capped_blocks((n_docs + 255) / 256, 256)), dim3(256), 0, s, cnt,
-                     n_docs, items);
+                     D.off, n_docs, min_work, items);
   if ((e = exclusive_scan(items, n_docs, item_start, sums, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(bydoc_item_doc_kernel, dim3(capped_blocks((n_docs + 255) / 256, 256)), dim3(256), 0, s,
                      item_start, n_docs, item_doc);
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), n_docs, 0u, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(bydoc_scatter_kernel, dim3(lgrid), dim3(256), 0, s, C, n_docs, start, cnt, slot_entry,
-                     slot_query);
+  hipLaunchKernelGGL(bydoc_scatter_kernel, dim3(lgrid), dim3(256), 0, s, C, n_docs, item_start, start, cnt,
+                     slot_entry, slot_query);
   ByDocParams P;
   P.Q = Q; P.D = D; P.start = start; P.item_start = item_start; P.item_doc = item_doc; P.slot_entry = slot_entry;
   P.slot_query = slot_query; P.n_docs = n_docs; P.scores = scores;

@@ -163,8 +163,8 @@ def test_document_order_bounds():
 def test_rerank_shape_by_document_matches_oracle_sample():
     """A rerank in the shape of an FP8 shortlist: 400 queries x 500 ids over
     8000 documents drawn from a skewed popularity (about 25 listings per
-    document), by document against by query bitwise and 6 lists against the
-    oracle."""
+    document), by document and in the mixed order against by query bitwise,
+    and 6 lists against the oracle."""
     w = wl.WORKLOADS[2]
     rng = np.random.default_rng(100)
     n_docs, n_q, sl = 8000, 400, 500
@@ -179,6 +179,10 @@ def test_rerank_shape_by_document_matches_oracle_sample():
     by_q = _run(Q, D, "f32", C, "query")
     by_d = _run(Q, D, "f32", C, "document")
     np.testing.assert_array_equal(_bits(by_d), _bits(by_q))
+    # the mixed order: popular documents by document, the rest by query
+    cnt = np.bincount(ids.reshape(-1), minlength=n_docs)
+    assert (cnt >= 8).any() and ((cnt > 0) & (cnt < 8)).any()
+    np.testing.assert_array_equal(_bits(_run(Q, D, "f32", C, "auto")), _bits(by_q))
     got = by_d.cpu().numpy().reshape(n_q, sl)
     qv, qo, dv, do = q.vecs.numpy(), q.offsets.numpy(), c.vecs.numpy(), c.offsets.numpy()
     for r in rng.choice(n_q, 6, replace=False):
