@@ -179,11 +179,30 @@ int32_t bydoc_min_work_of(const gem_sets* Q, const gem_sets* D, const gem_cands*
   return C->n_entries >= bydoc_min_entries_per_doc(compute) * D->n_sets ? bydoc_min_work(compute) : 0;
 }
 
+// A gathered call large enough for the gathered scorer's full split (16
+// entries a wave), with lists that fit the sort and documents that are rows
+// (not code sets), scores its lists sorted by document id and walks them
+// chunk-major: the listings of a document then run close together and find
+// its rows in the Infinity Cache. An expansion step of 4096 lists of 512
+// random ids over 1M documents: the FP8 gather 3.33 -> 3.06 ms, MXFP4 1.73 ->
+// 1.58, MXFP6 2.55 -> 2.27 (the sort 0.05 ms); the float32 rerank of the FP8
+// top-1000 in the query order 18.1 -> 16.1 ms; code sets gain nothing.
+constexpr int64_t kSortMinEntries = 65536;
+
+bool sorted_walk(const gem_sets* D, const gem_cands* C) {
+  const int64_t len = list_len_bound(C);
+  return !D->codes && len >= 1 && len <= kSortMaxList && C->n_lists * len >= kSortMinEntries &&
+         C->n_entries <= INT32_MAX;
+}
+
 // Workspace layout of a scoring call.
 struct ScoreLayout {
   size_t q_conv = 0, q_scales = 0, qb = 0, qcol = 0, staged = 0, total = 0;
   int32_t bydoc_work = 0;       // see bydoc_min_work_of
   size_t bydoc_ws = 0;
+  // candidate lists sorted by document id and walked chunk-major (sorted_walk)
+  bool sorted = false;
+  size_t sort_ids = 0, sort_pos = 0;
   int64_t n_blocks_max = 0;
   int block_rows = 0;
   // fused top-k of a dense call (k > 0 without a score matrix): regions,
@@ -249,12 +268,41 @@ ScoreLayout score_layout(const gem_sets* Q, const gem_sets* D, const gem_cands* 
       L.bydoc_ws = off;
       off = align_up(off + bydoc_ws_bytes(D->n_sets, C->n_entries));
     }
+    // (not in the mixed order: its per-query entries are the rarely listed
+    // documents, which the sort cannot bring together, while the chunk-major
+    // walk loses the reuse of each query's operands: the float32 rerank of
+    // the FP8 top-1000 took 16.4 ms sorted against 15.7)
+    L.sorted = L.bydoc_work == 0 && sorted_walk(D, C);
+    if (L.sorted) {
+      L.sort_ids = off;
+      off = align_up(off + (size_t)C->n_entries * 4);
+      L.sort_pos = off;
+      off = align_up(off + (size_t)C->n_entries * 4);
+    }
   }
   L.total = off;
   return L;
 }
 
 char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+// The sorted walk of a gathered call (L.sorted): the lists sorted into the
+// workspace, *cv reading them and *opts writing each score back to its
+// entry's position in the caller's list.
+hipError_t sort_for_walk(const ScoreLayout& L, void* ws, int32_t max_list_len, CandsView* cv, GatherOpts* opts,
+                         hipStream_t stream) {
+  if (!L.sorted) return hipSuccess;
+  int32_t* sid = reinterpret_cast<int32_t*>(at(ws, L.sort_ids));
+  int32_t* spos = reinterpret_cast<int32_t*>(at(ws, L.sort_pos));
+  hipError_t e = launch_sort_lists(*cv, max_list_len, sid, spos, stream);
+  if (e != hipSuccess) return e;
+  cv->ids = sid;
+  opts->out_pos = spos;
+  opts->chunk_major = true;
+  return hipSuccess;
+}
+
+
 
 gem_status convert_query(const gem_sets* Q, int32_t compute, void* ws, const ScoreLayout& L, gem_sets* Qc,
                          hipStream_t stream) {
@@ -406,7 +454,7 @@ gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const
     }
   } else {
     float* es = scores ? scores : reinterpret_cast<float*>(at(ws, L.staged));
-    GatherSkip skip;
+    GatherOpts skip;
     if (L.bydoc_work > 0) {
       e = launch_score_bydoc(compute, view(&Qc), view(D), cview(C), C->n_entries, es, at(ws, L.bydoc_ws),
                              L.bydoc_work, &skip, stream);
@@ -415,9 +463,12 @@ gem_status score_common(gem_ctx ctx, const gem_sets* Q, const gem_sets* D, const
     if (L.bydoc_work != 1) {
       // the query order, or in the mixed order the entries of the documents
       // with fewer listings
+      CandsView cv = cview(C);
+      if ((e = sort_for_walk(L, ws, list_len_bound(C), &cv, &skip, stream)) != hipSuccess)
+        return hip_fail(e, "candidate sort");
       const GatherSchedule gs = gsched ? *gsched : lookup_gather(ctx, compute, C->n_lists, list_len_bound(C));
-      e = launch_score_gather(compute, view(&Qc), view(D), cview(C), list_len_bound(C), Q->max_set_len, es, gs,
-                              stream, skip);
+      e = launch_score_gather(compute, view(&Qc), view(D), cv, list_len_bound(C), Q->max_set_len, es, gs, stream,
+                              skip);
       if (e != hipSuccess) return hip_fail(e, "gathered scoring");
     }
     if (k > 0) {
@@ -1155,8 +1206,12 @@ gem_status gem_expand_batch(gem_ctx ctx, const gem_sets* Q8, const gem_sets* D8,
   gem_sets Qc;
   if ((st = convert_query(Q8, cd, ws, L, &Qc, stream)) != GEM_OK) return st;
   float* es = cand_scores ? cand_scores : reinterpret_cast<float*>(at(ws, L.staged));
-  hipError_t e = launch_score_gather(cd, view(&Qc), view(D8), cview(C), list_len_bound(C), Q8->max_set_len,
-                                     es, lookup_gather(ctx, cd, C->n_lists, list_len_bound(C)), stream);
+  CandsView cv = cview(C);
+  GatherOpts go;
+  hipError_t e = sort_for_walk(L, ws, list_len_bound(C), &cv, &go, stream);
+  if (e != hipSuccess) return hip_fail(e, "candidate sort");
+  e = launch_score_gather(cd, view(&Qc), view(D8), cv, list_len_bound(C), Q8->max_set_len, es,
+                          lookup_gather(ctx, cd, C->n_lists, list_len_bound(C)), stream, go);
   if (e != hipSuccess) return hip_fail(e, "gathered scoring");
   e = launch_beam_merge(es, cview(C), Q8->n_sets, beam->ef, beam->scores, beam->ids,
                         list_len_bound(C) > 0 ? beam->ef + list_len_bound(C) : 0, stream);

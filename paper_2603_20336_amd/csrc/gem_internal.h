@@ -105,16 +105,33 @@ struct GatherSchedule {
 int gather_depth_choice(int dtype, int i);
 bool gather_schedule_valid(int dtype, const GatherSchedule& g);
 
-// Entries the gathered scorer leaves to the document-major scorer: those of
-// the documents that have work items there (item_start: the exclusive scan of
-// the items per document, item_start[d + 1] > item_start[d]). Their scores
-// are not written.
-struct GatherSkip {
+// Options of a gathered-scorer launch (none change a score):
+//   item_start: entries of the documents that have work items in the
+//     document-major scorer (the exclusive scan of its items per document,
+//     item_start[d + 1] > item_start[d]) are left to it; their scores are not
+//     written.
+//   out_pos: the lists were reordered; entry e is the caller's entry
+//     out_pos[e] (an index into the caller's entry array), and its score goes
+//     there.
+//   chunk_major: waves take chunk c of every list before chunk c + 1 of any
+//     (with lists sorted by document id, every chunk then reads one region of
+//     the corpus at a time, so that the listings of a document run close
+//     together and find it in the Infinity Cache).
+struct GatherOpts {
   const int32_t* item_start = nullptr;
+  const int32_t* out_pos = nullptr;
+  bool chunk_major = false;
 };
 hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C,
                                int32_t max_list_len, int32_t max_q_len, float* scores, const GatherSchedule& g,
-                               hipStream_t s, const GatherSkip& skip = GatherSkip{});
+                               hipStream_t s, const GatherOpts& opts = GatherOpts{});
+// Sorts every candidate list by document id (padding ids last): sorted_ids
+// and pos (each sorted entry's index in the caller's entry array) in the
+// lists' layout. Lists of at most kSortMaxList entries (a longer list keeps
+// its order); at most 2^31 - 1 entries.
+constexpr int kSortMaxList = 2048;
+hipError_t launch_sort_lists(const CandsView& C, int32_t max_list_len, int32_t* sorted_ids, int32_t* pos,
+                             hipStream_t s);
 // Gathered scoring by document, for candidate lists that share documents (a
 // batch of shortlists drawn from the same corpus region): the call's entries
 // are grouped by document (a counting sort), and each workgroup stages one
@@ -131,7 +148,7 @@ constexpr int kByDocMaxRows = 256;
 int32_t bydoc_min_work(int dtype);
 size_t bydoc_ws_bytes(int64_t n_docs, int64_t n_entries);
 hipError_t launch_score_bydoc(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C, int64_t n_entries,
-                              float* scores, void* ws, int32_t min_work, GatherSkip* skip, hipStream_t s);
+                              float* scores, void* ws, int32_t min_work, GatherOpts* skip, hipStream_t s);
 // The dense output of a small query batch by the gathered scorer: every
 // document of D is an entry of every query's list (bitwise the dense scorer's
 // scores, one wave per few documents: memory-bound streaming instead of one

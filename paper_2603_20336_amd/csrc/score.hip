@@ -1165,6 +1165,9 @@ struct GatherParams {
   // entries of documents with work items in the document-major scorer
   // (skip_items: its item scan) are left to it
   const int32_t* skip_items;
+  // reordered lists: each entry's index in the caller's entry array
+  const int32_t* out_pos;
+  int32_t chunk_major;
 };
 
 // kCodes: the documents are a code set. Each lane then loads the code of the
@@ -1179,9 +1182,16 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
 
   const int l = threadIdx.x & 63, g = l >> 4, c16 = l & 15;
   const int64_t gw = P.wave0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t q = gw / P.chunks_per_query;
-  if (q >= P.C.n_lists) return;
-  const int64_t ch = gw % P.chunks_per_query;
+  int64_t q, ch;
+  if (P.chunk_major) {
+    q = gw % P.C.n_lists;
+    ch = gw / P.C.n_lists;
+    if (ch >= P.chunks_per_query) return;
+  } else {
+    q = gw / P.chunks_per_query;
+    if (q >= P.C.n_lists) return;
+    ch = gw % P.chunks_per_query;
+  }
   int64_t lb, le;
   if (P.range) { lb = 0; le = P.D.n_sets; }
   else if (P.C.off) { lb = P.C.off[q]; le = P.C.off[q + 1]; }
@@ -1335,7 +1345,7 @@ __global__ __launch_bounds__(256) void score_gather_kernel(GatherParams P) {
   }
   if (l < ne && !skip) {
     if (P.range) P.scores[(P.out_rows ? (int64_t)P.out_rows[q] : q) * P.out_ld + e0 + l] = res;
-    else P.scores[e0 + l] = res;
+    else P.scores[P.out_pos ? (int64_t)P.out_pos[e0 + l] : e0 + l] = res;
   }
 }
 
@@ -1404,11 +1414,13 @@ static hipError_t run_gather(int dtype, GatherParams P, int64_t max_list_len, co
 
 hipError_t launch_score_gather(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C,
                                int32_t max_list_len, int32_t, float* scores, const GatherSchedule& g, hipStream_t s,
-                               const GatherSkip& skip) {
+                               const GatherOpts& opts) {
   GatherParams P{};
   P.Q = Q; P.D = D; P.C = C; P.scores = scores;
   P.range = 0;
-  P.skip_items = skip.item_start;
+  P.skip_items = opts.item_start;
+  P.out_pos = opts.out_pos;
+  P.chunk_major = opts.chunk_major ? 1 : 0;
   return run_gather(dtype, P, max_list_len, g, s);
 }
 
@@ -1420,6 +1432,56 @@ hipError_t launch_score_range(int dtype, const SetsView& Q, const SetsView& D, c
   P.scores = out.scores; P.out_rows = out.rows; P.out_ld = out.ld;
   P.range = 1;
   return run_gather(dtype, P, D.n_sets, GatherSchedule{}, s);
+}
+
+// --------------------------------------------------------------------------
+// Candidate lists sorted by document id, one workgroup per list: a bitonic
+// sort of (id, position) keys in LDS, padding ids (negative) last.
+__global__ __launch_bounds__(256) void sort_lists_kernel(CandsView C, int32_t* __restrict__ sorted_ids,
+                                                         int32_t* __restrict__ pos) {
+  __shared__ uint64_t key[kSortMaxList];
+  const int t = threadIdx.x;
+  for (int64_t i = blockIdx.x; i < C.n_lists; i += gridDim.x) {
+    const int64_t lb = C.off ? C.off[i] : i * (int64_t)C.stride;
+    const int64_t len64 = (C.off ? C.off[i + 1] : lb + C.stride) - lb;
+    if (len64 > kSortMaxList) {
+      // longer than the stated bound: kept in its order
+      for (int64_t j = t; j < len64; j += 256) {
+        sorted_ids[lb + j] = C.ids[lb + j];
+        pos[lb + j] = (int32_t)(lb + j);
+      }
+      continue;
+    }
+    const int len = (int)len64;
+    int n = 2;
+    while (n < len) n <<= 1;
+    for (int j = t; j < n; j += 256)
+      key[j] = j < len ? ((uint64_t)(uint32_t)C.ids[lb + j] << 32) | (uint32_t)j : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= n; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int x = t; x < (n >> 1); x += 256) {
+          const int a = 2 * j * (x / j) + (x % j), b = a + j;
+          const uint64_t ka = key[a], kb = key[b];
+          if (((a & k) == 0) == (ka > kb)) { key[a] = kb; key[b] = ka; }
+        }
+        __syncthreads();
+      }
+    }
+    for (int j = t; j < len; j += 256) {
+      sorted_ids[lb + j] = (int32_t)(key[j] >> 32);
+      pos[lb + j] = (int32_t)(lb + (uint32_t)key[j]);
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_sort_lists(const CandsView& C, int32_t max_list_len, int32_t* sorted_ids, int32_t* pos,
+                             hipStream_t s) {
+  if (C.n_lists == 0 || max_list_len == 0) return hipSuccess;
+  if (max_list_len > kSortMaxList || max_list_len < 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sort_lists_kernel, dim3(capped_blocks(C.n_lists, 256)), dim3(256), 0, s, C, sorted_ids, pos);
+  return hipGetLastError();
 }
 
 // --------------------------------------------------------------------------
@@ -1846,7 +1908,7 @@ int32_t bydoc_min_work(int dtype) {
 }
 
 hipError_t launch_score_bydoc(int dtype, const SetsView& Q, const SetsView& D, const CandsView& C, int64_t n_entries,
-                              float* scores, void* ws, int32_t min_work, GatherSkip* skip, hipStream_t s) {
+                              float* scores, void* ws, int32_t min_work, GatherOpts* skip, hipStream_t s) {
   if (C.n_lists == 0 || n_entries == 0) return hipSuccess;
   if (D.n_sets <= 0 || D.codes || Q.codes || n_entries > INT32_MAX || D.n_sets > INT32_MAX - 1)
     return hipErrorInvalidValue;

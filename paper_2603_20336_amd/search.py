@@ -41,16 +41,17 @@ class ExpansionGraph:
         self.beam = Beam(Q8.n_sets, ef, self.device)
         n = max((c.ids.numel() for c in self.steps), default=0)
         self.cand_scores = torch.empty(max(n, 1), dtype=torch.float32, device=self.device)
-        for c in self.steps:
-            if expand_workspace_bytes(Q8, D8, c, True) != 0:
-                raise RuntimeError("expansion with quantized queries and a score buffer needs no workspace")
+        # one workspace for every step (large steps sort their lists there),
+        # allocated before any capture
+        ws = max((expand_workspace_bytes(Q8, D8, c, True) for c in self.steps), default=0)
+        self.ws = torch.empty(ws, dtype=torch.uint8, device=self.device) if ws > 0 else None
         self.graph: Optional[torch.cuda.CUDAGraph] = None
 
     def run_eager(self, stream=None) -> None:
         self.beam.reset(stream)
         for c in self.steps:
             expand_batch(self.Q8, self.D8, c, self.beam, cand_scores=self.cand_scores[: c.ids.numel()],
-                         stream=stream)
+                         stream=stream, ws=self.ws)
 
     def capture(self) -> None:
         s = torch.cuda.Stream(device=self.device)

@@ -777,6 +777,76 @@ def test_expand_batch_full_split_matches_oracle():
         assert ok, (rows[j], bad, missing)
 
 
+@pytest.mark.parametrize("fmt", ["fp8", "mxfp4"])
+def test_expand_batch_sorted_lists_match_the_query_order(fmt):
+    """Steps large enough for the sorted, chunk-major walk (n_lists x longest
+    list >= 65,536): ragged CSR lists (empty ones, padding ids, repeated ids,
+    lengths up to 700) give bitwise the per-query scorer's entry scores, in
+    the caller's order, and the same beam as merging those scores."""
+    rng = np.random.default_rng(33)
+    n_docs, n_q, ef = 3000, 200, 64
+    c = _ragged(list(rng.integers(1, 120, n_docs)), 34)
+    q = _ragged(list(rng.integers(1, 65, n_q)), 35)
+    S = gem.Sets.from_batch(c, DEV)
+    D = S.to_fp8() if fmt == "fp8" else S.to_mxfp4()
+    Qf = gem.Sets.from_batch(q, DEV)
+    Qx = Qf.to_fp8() if fmt == "fp8" else Qf.to_mxfp4()
+    lens = rng.integers(0, 701, n_q)
+    lens[[3, 9]] = 0
+    lens[0] = 700
+    lists = [rng.integers(0, n_docs, int(m)) for m in lens]
+    for ids in lists[10:20]:
+        ids[rng.random(ids.size) < 0.1] = -1
+        if ids.size > 4:
+            ids[:3] = ids[3]
+    off = _csr(lens)
+    ids = np.concatenate(lists).astype(np.int32)
+    C = gem.Cands(torch.from_numpy(ids).to(DEV), torch.from_numpy(off).to(DEV), max_list_len=700)
+    assert C.n_lists * C.max_list_len >= 65536
+    beam, beam_ref = gem.Beam(n_q, ef, DEV), gem.Beam(n_q, ef, DEV)
+    cs = torch.full((ids.size,), 7.0, device=DEV)
+    gem.expand_batch(Qx, D, C, beam, cand_scores=cs)
+    gem.set_gather_order("query")
+    try:
+        ref = gem.score_quant(Qx, D, cands=C)
+    finally:
+        gem.set_gather_order("auto")
+    gem.beam_merge(ref, C, beam_ref)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_np(cs).view(np.int32), _np(ref).view(np.int32))
+    assert np.all(np.isneginf(_np(cs)[ids < 0]))
+    assert torch.equal(beam.ids, beam_ref.ids) and torch.equal(beam.scores, beam_ref.scores)
+
+
+def test_expansion_graph_sorted_lists_replay_equal_eager():
+    """The sorted walk's sort kernel inside a captured step graph: replays,
+    with eager work between them, reproduce the eager beams exactly."""
+    from paper_2603_20336_amd.search import ExpansionGraph
+    w = wl.WORKLOADS[4]
+    n_q = 256
+    c = wl.corpus(w, n_docs=4000)
+    q = wl.queries(w, n_queries=n_q)
+    D8 = _device_sets(c, "fp8")
+    Q8 = gem.Sets.from_batch(q, DEV).to_fp8()
+    steps = []
+    for st in range(4):
+        off, ids = wl.step_candidates(w, st, n_queries=n_q, n_docs=4000)
+        steps.append(gem.Cands(ids.to(DEV), off.to(DEV), max_list_len=w.cands_per_step))
+    assert n_q * w.cands_per_step >= 65536
+    eg = ExpansionGraph(Q8, D8, steps, ef=200)
+    eg.run_eager()
+    torch.cuda.synchronize()
+    ref_s, ref_i = eg.beam.scores.clone(), eg.beam.ids.clone()
+    eg.capture()
+    for rep in range(3):
+        eg.beam.scores.fill_(123.0)
+        torch.cuda.synchronize()
+        eg.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(eg.beam.ids, ref_i), rep
+        assert torch.equal(eg.beam.scores, ref_s), rep
+
+
 def test_rerank_f32_full_split_matches_oracle_and_dense():
     """The float32 rerank in its full-size shape (1000 queries x 1000
     candidates, 16 entries per wave): sampled lists against the oracle and
