@@ -389,11 +389,12 @@ def bench_exhaustive(args):
     r8_s, r8_i = rerank(gem.score_quant(gem.quantize_fp8(Q), D8, k=1000)[1], 1000)
 
     # the rerank of the FP8 top-1000 (1M entries over about 26k distinct
-    # documents) in both gather orders, in float32 and in split-bf16
+    # documents) by query, by document and in the mixed order (auto), in
+    # float32 and in split-bf16
     short1000 = gem.score_quant(gem.quantize_fp8(Q), D8, k=1000)[1]
     C1000 = gem.Cands(short1000.reshape(-1), stride=1000, n_lists=n_q)
     rerank_orders = {"entries": n_q * 1000, "distinct_docs": int(torch.unique(short1000).numel())}
-    for order in ("query", "document"):
+    for order in ("query", "document", "auto"):
         gem.set_gather_order(order)
         rerank_orders[f"f32_by_{order}_ms"] = timed(
             lambda: gem.score_exact(Q, D32, cands=C1000, compute="f32", k=k), max(1, args.steps // 4))
