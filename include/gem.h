@@ -202,7 +202,10 @@ const char* gem_version(void);
  *   gem_score_exact / gem_score_quant reads the listed documents (the final
  *   rerank of Alg. 5 over a batch of shortlists, or any candidate lists).
  *     GEM_GATHER_BY_QUERY: one wave per query and run of its entries, each
- *       listed document read once per listing.
+ *       listed document read once per listing. A call with n_lists x longest
+ *       list >= 65,536 and lists of at most 2048 entries (rows, not code
+ *       sets) sorts every list by document id into the workspace first and
+ *       walks the sorted lists chunk-major (as gem_expand_batch does).
  *     GEM_GATHER_BY_DOCUMENT: the entries are grouped by document on the
  *       device (a counting sort in the workspace); each document is staged in
  *       LDS once and scored against every query that lists it. Pays when the
@@ -395,9 +398,13 @@ gem_status gem_topk(gem_ctx ctx, const float* scores, const int64_t* seg_offsets
  * then replace beam row i by the best ef of (beam row i) U (scored entries),
  * ids distinct (a repeated id keeps its best entry). D8->dtype is
  * GEM_FP8_E4M3, GEM_MXFP4 or GEM_MXFP6; Q8 is in D8's format or GEM_F32
- * (quantized into ws). If
- * cand_scores is not NULL the step's entry scores are also written there
- * ([C->n_entries]). The beam is updated in place. */
+ * (quantized into ws). If cand_scores is not NULL the step's entry scores
+ * are also written there ([C->n_entries], in the caller's entry order). The
+ * beam is updated in place. A step with n_lists x longest list >= 65,536
+ * and lists of at most 2048 entries (rows, not code sets) first sorts every
+ * list by document id into ws and walks the sorted lists chunk-major, so that
+ * the listings of a document run close together in time; the workspace then
+ * holds 8 bytes per entry more (gem_workspace_bytes includes it). */
 gem_status gem_expand_batch(gem_ctx ctx, const gem_sets* Q8, const gem_sets* D8, const gem_cands* C,
                             gem_beam* beam, float* cand_scores,
                             void* ws, size_t ws_bytes, hipStream_t stream);
