@@ -847,10 +847,22 @@ def test_expansion_graph_sorted_lists_replay_equal_eager():
         assert torch.equal(eg.beam.scores, ref_s), rep
 
 
-def test_rerank_f32_full_split_matches_oracle_and_dense():
+@pytest.mark.parametrize("order", ["auto", "query"])
+def test_rerank_f32_full_split_matches_oracle_and_dense(order):
     """The float32 rerank in its full-size shape (1000 queries x 1000
-    candidates, 16 entries per wave): sampled lists against the oracle and
-    bitwise against the dense float32 scorer."""
+    candidates): sampled lists against the oracle and bitwise against the
+    dense float32 scorer, in the auto order (here every document is listed
+    about 166 times: the document-major scorer) and in the query order (16
+    entries per wave, the lists sorted by document id and walked
+    chunk-major)."""
+    gem.set_gather_order(order)
+    try:
+        _rerank_f32_full_split()
+    finally:
+        gem.set_gather_order("auto")
+
+
+def _rerank_f32_full_split():
     w2 = wl.WORKLOADS[2]
     n_docs, n_q, sl = 6000, 1000, 1000
     c = wl.corpus(w2, n_docs=n_docs)
