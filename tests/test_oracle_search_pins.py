@@ -196,16 +196,16 @@ def test_alg5_single_path_hand_trace():
 
 
 def test_alg5_two_paths_hand_trace():
-    # Entries 0 and 7, ef = 4, two paths advancing in synchronous rounds (the
+    # Entries 0 and 7, ef = 4, two paths advancing in synchronous steps (the
     # w best unexpanded entries of R expand together; a neighbour reached in
-    # the round is marked visited when taken):
-    #   round 1: expand 0, 7 -> score 1, 2, 3 (3 is taken from 0 first);
+    # the step is marked visited when taken):
+    #   step 1: expand 0, 7 -> score 1, 2, 3 (3 is taken from 0 first);
     #            R = {2, 3, 1, 0}
-    #   round 2: expand 2, 3 -> score 5, 6; R = {6, 2, 5, 3}
-    #   round 3: expand 6, 5 -> score 10, 9 (11 pruned); R = {10, 6, 9, 2}
-    #   round 4: expand 10, 9 -> score 8; R = {10, 6, 8, 9}
-    #   round 5: expand 8 -> score 4; R = {10, 6, 4, 8}
-    #   round 6: expand 4 -> nothing; no unexpanded entry is left in R.
+    #   step 2: expand 2, 3 -> score 5, 6; R = {6, 2, 5, 3}
+    #   step 3: expand 6, 5 -> score 10, 9 (11 pruned); R = {10, 6, 9, 2}
+    #   step 4: expand 10, 9 -> score 8; R = {10, 6, 8, 9}
+    #   step 5: expand 8 -> score 4; R = {10, 6, 4, 8}
+    #   step 6: expand 4 -> nothing; no unexpanded entry is left in R.
     R, n_scored, steps, expanded, scored = _ht_run([0, 7], ef=4, w=2)
     assert expanded == [0, 7, 2, 3, 6, 5, 10, 9, 8, 4]
     assert steps == 6
