@@ -361,16 +361,21 @@ def bench_exhaustive(args):
         C = gem.Cands(short_i.reshape(-1), stride=sl, n_lists=n_q)
         return gem.score_exact(Q, D32, cands=C, compute="f32", k=k)
 
+    def rerank_x3(short_i, sl):
+        # the exact rerank in split-bf16 products (within the exactness bound)
+        C = gem.Cands(short_i.reshape(-1), stride=sl, n_lists=n_q)
+        return gem.score_exact(Q, Dx3, cands=C, compute="bf16x3", k=k)
+
     # estimate -> top-sl shortlist -> float32 rerank -> top-100, swept over
     # the shortlist length (Sec. 5, "Effect of #rerank")
     sweep_sl = [int(x) for x in args.shortlists.split(",") if x]
 
-    def sweep(name, make_q, score_k):
+    def sweep(name, make_q, score_k, rr=rerank):
         out = {}
         for sl in sweep_sl:
             def path(sl=sl):
                 _, short_i = score_k(make_q(), sl)
-                return rerank(short_i, sl)
+                return rr(short_i, sl)
             r_s, r_i = path()
             torch.cuda.synchronize()
             t = timed(path, max(1, args.steps // 4))
@@ -386,6 +391,8 @@ def bench_exhaustive(args):
     t_fp8_score = timed(lambda: gem.score_quant(Q8, D8, scores=est), max(1, args.steps))
     fp8_sample = est[:max(1, args.cpu_sample)].clone()
     fp8_sweep, r8_s, r8_i = sweep("fp8", lambda: gem.quantize_fp8(Q), lambda q8, sl: gem.score_quant(q8, D8, k=sl))
+    fp8_x3_sweep, _, _ = sweep("fp8 -> split-bf16 rerank", lambda: gem.quantize_fp8(Q),
+                               lambda q8, sl: gem.score_quant(q8, D8, k=sl), rr=rerank_x3)
     r8_s, r8_i = rerank(gem.score_quant(gem.quantize_fp8(Q), D8, k=1000)[1], 1000)
 
     # the rerank of the FP8 top-1000 (1M entries over about 26k distinct
@@ -528,6 +535,9 @@ def bench_exhaustive(args):
                                 fp8_tflops=flops / (t_fp8_score / 1e3) / 1e12,
                                 fp8_frac_of_peak=flops / (t_fp8_score / 1e3) / PEAK_FP8,
                                 shortlist_sweep=fp8_sweep, rerank_gather_orders=rerank_orders),
+        "fp8_bf16x3_rerank_path": dict(fp8_x3_sweep.get("1000", {}), shortlist=1000,
+                                       rerank="split-bf16 exact mode (three bf16 products per float32 product)",
+                                       shortlist_sweep=fp8_x3_sweep),
         "mxfp4_rerank_path": dict(mx_sweep.get("1000", {}), shortlist=1000, mxfp4_score_ms=t_mx_score,
                                   mxfp4_tflops=flops / (t_mx_score / 1e3) / 1e12,
                                   mxfp4_frac_of_peak=flops / (t_mx_score / 1e3) / PEAK_FP4,
