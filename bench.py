@@ -555,6 +555,36 @@ def bench_exhaustive(args):
     return line, (D8, D32)
 
 
+def bench_rerank_orders(args):
+    """The rerank of the FP8 top-1000 of workload 3 (1000 queries x 1000 ids
+    over the 100k corpus) in every gather order (by query: the sorted
+    chunk-major walk; by document; mixed: auto), in float32 and in split bf16,
+    each order's scores checked bitwise against the query order's."""
+    dev = torch.device("cuda:0")
+    w2 = wl.WORKLOADS[2]
+    c_dev, q_dev = wl.corpus(w2, device=dev), wl.queries(w2, device=dev)
+    Q = gem.Sets(q_dev.vecs, q_dev.offsets, "f32", q_dev.max_len())
+    D32 = gem.Sets(c_dev.vecs, c_dev.offsets, "f32", c_dev.max_len())
+    D8, Dx3 = gem.quantize_fp8(D32), gem.split_bf16x3(D32)
+    short = gem.score_quant(gem.quantize_fp8(Q), D8, k=1000)[1]
+    C = gem.Cands(short.reshape(-1).contiguous(), stride=1000, n_lists=Q.n_sets)
+    res = {"entries": Q.n_sets * 1000, "distinct_docs": int(torch.unique(short).numel())}
+    for name, fn in (("f32", lambda: gem.score_exact(Q, D32, cands=C, compute="f32")),
+                     ("bf16x3", lambda: gem.score_exact(Q, Dx3, cands=C, compute="bf16x3"))):
+        ref = None
+        for order in ("query", "document", "auto"):
+            gem.set_gather_order(order)
+            out = fn()
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = out.clone()
+            res[f"{name}_{order}_bitwise_as_query"] = bool(torch.equal(out.view(torch.int32), ref.view(torch.int32)))
+            res[f"{name}_{order}_ms"] = timed(fn, max(1, args.steps // 4))
+            log(f"rerank {name} by {order}: {res[f'{name}_{order}_ms']:.2f} ms")
+        gem.set_gather_order("auto")
+    return res
+
+
 def bench_dense_only(args):
     """The dense scorers alone, for counter runs: the bf16 step (fused top-100,
     then staged), and FP8, MXFP4, MXFP6 and split-bf16 exact exhaustive scoring
@@ -856,6 +886,8 @@ def main():
                     help="also run a 1 GiB copy kernel (reference for the HBM byte counters)")
     ap.add_argument("--only-expansion", action="store_true",
                     help="run the beam-expansion leg alone (for profiling); prints its result line")
+    ap.add_argument("--only-rerank", action="store_true",
+                    help="run the top-1000 rerank in every gather order alone (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -865,6 +897,9 @@ def main():
         sys.exit(2)
     if args.only_graph:
         print(json.dumps({"graph_search": bench_graph_search()}), flush=True)
+        return
+    if args.only_rerank:
+        print(json.dumps({"rerank_orders": bench_rerank_orders(args)}), flush=True)
         return
     if args.only_expansion:
         res = bench_expansion(args)
