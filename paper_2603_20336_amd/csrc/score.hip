@@ -1651,23 +1651,22 @@ struct ByDocParams {
 // tiles in use the four accumulators advance together, so that consecutive
 // products never wait on one another; the next tile's A operand is read while
 // the last products finish.
-template <int DT>
-__device__ __forceinline__ void bydoc_tiles(typename Op<DT>::Frag A, const typename Op<DT>::Frag (&B)[kGatherNT],
+template <int DT, int NB>
+__device__ __forceinline__ void bydoc_tiles(typename Op<DT>::Frag A, const typename Op<DT>::Frag (&B)[NB],
                                             float (&rm)[kGatherNT], const u32x4* stage, int n_tiles, int nct,
                                             int c16, int g) {
   using O = Op<DT>;
   using TS = TileStage<DT>;
-  constexpr int NT = kGatherNT;
-  static_assert(NT == 4, "column tiles of a pass");
+  static_assert(kGatherNT == 4 && (NB == 2 || NB == 4), "column tiles of a pass");
   for (int T = 0; T < n_tiles; ++T) {
-    f32x4 acc[NT];
+    f32x4 acc[NB];
 #pragma unroll
-    for (int ct = 0; ct < NT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (nct > 2) {
+    for (int ct = 0; ct < NB; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (NB > 2 && nct > 2) {
 #pragma unroll
       for (int s = 0; s < O::kSteps; ++s) {
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct) acc[ct] = O::mma(A, B[ct], acc[ct], s);
+        for (int ct = 0; ct < NB; ++ct) acc[ct] = O::mma(A, B[ct], acc[ct], s);
       }
     } else {
 #pragma unroll
@@ -1678,7 +1677,7 @@ __device__ __forceinline__ void bydoc_tiles(typename Op<DT>::Frag A, const typen
     }
     if (T + 1 < n_tiles) frag_from_lds<DT>(A, stage + (T + 1) * (TS::kStageBytes / 16), c16, g);
 #pragma unroll
-    for (int ct = 0; ct < NT; ++ct) update_max(rm[ct], acc[ct]);
+    for (int ct = 0; ct < NB; ++ct) update_max(rm[ct], acc[ct]);
   }
 }
 
@@ -1689,13 +1688,18 @@ __device__ __forceinline__ typename Op<DT>::Frag A_first(const u32x4* stage, int
   return A;
 }
 
-template <int DT>
-__global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocParams P) {
+// NB: column tiles of query operands a wave holds (4, or 2 for the float32
+// operands, which then leave room for three waves per SIMD); WAVES: waves of
+// a workgroup. The column sums stay in the layout of four column tiles, and a
+// listing's sums are added in column-tile order across passes, so every
+// variant gives the gathered scorer's scores bitwise.
+template <int DT, int NB, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void score_bydoc_kernel(ByDocParams P) {
   using O = Op<DT>;
   using TS = TileStage<DT>;
   using Frag = typename O::Frag;
   constexpr int NT = kGatherNT;
-  constexpr int PASS = 16 * NT;
+  constexpr int PASS = 16 * NB;
   __shared__ u32x4 stage[kByDocMaxTiles * TS::kStageBytes / 16];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c16 = l & 15;
   const float ninf = neg_inf();
@@ -1714,27 +1718,27 @@ __global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocPara
   if (n_tiles > kByDocMaxTiles) {
     // longer than the documents this path takes (the caller's bound was
     // wrong): NaN scores, nothing staged
-    for (int32_t sl = s0 + w; sl < s1; sl += kByDocWaves)
+    for (int32_t sl = s0 + w; sl < s1; sl += WAVES)
       if (l == 0) P.scores[P.slot_entry[sl]] = __int_as_float(0x7fc00000);
     return;
   }
-  // the wave's listings s0 + w + kByDocWaves * i (at most 8): lane i holds
+  // the wave's listings s0 + w + WAVES * i (at most 8): lane i holds
   // listing i's entry, query's first row and length, loaded while the
   // document's tiles are in flight
-  const int n_mine = s1 > s0 + w ? (s1 - s0 - w + kByDocWaves - 1) / kByDocWaves : 0;
+  const int n_mine = s1 > s0 + w ? (s1 - s0 - w + WAVES - 1) / WAVES : 0;
   int32_t my_e = 0, my_q = 0, my_m = 0;
   int64_t my_r0 = 0;
   if (l < n_mine) {
-    const int32_t sl = s0 + w + kByDocWaves * l;
+    const int32_t sl = s0 + w + WAVES * l;
     my_e = P.slot_entry[sl];
     my_q = P.slot_query[sl];
   }
-  for (int p = w; p < n_tiles * TS::kPieceWaves; p += kByDocWaves) {
+  for (int p = w; p < n_tiles * TS::kPieceWaves; p += WAVES) {
     const int k = p / TS::kPieceWaves, role = p % TS::kPieceWaves;
     TS::copy_piece(P.D.vecs, base, 0, d_len, k, stage + k * (TS::kStageBytes / 16), role, l);
   }
   if constexpr (TS::kScales) {
-    for (int k = w; k < n_tiles; k += kByDocWaves)
+    for (int k = w; k < n_tiles; k += WAVES)
       TS::copy_scales(P.D.scales, base, 0, d_len, k, stage + k * (TS::kStageBytes / 16), l);
   }
   if (l < n_mine) {
@@ -1744,7 +1748,7 @@ __global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocPara
   wait_vm<0>();
   __syncthreads();
 
-  // The wave takes the item's listings s0 + w, s0 + w + kByDocWaves, ...
+  // The wave takes the item's listings s0 + w, s0 + w + WAVES, ...
   // Consecutive ones whose queries fit one pass of PASS columns together
   // share it: listing j takes the column tiles [qc_j, qc_j + qn_j) (qn_j = its
   // query's 16-column tiles), NT in all. A column tile's maxima and sum depend
@@ -1774,7 +1778,7 @@ __global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocPara
             ++i;
           }
           open = false;
-        } else if (ctot + n > NT) {
+        } else if (ctot + n > NB) {
           open = false;
         } else {
           ent[j] = e; qr[j] = r0; qm[j] = m; qn[j] = n; qc[j] = ctot;
@@ -1792,12 +1796,12 @@ __global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocPara
         const int pr = min(PASS, m - prow0);
         const int nct = __builtin_amdgcn_readfirstlane((pr + 15) >> 4);
         const bool first_pass = prow0 == 0;
-        Frag B[NT];
+        Frag B[NB];
         float qs[NT / 4];
 #pragma unroll
         for (int i = 0; i < NT / 4; ++i) qs[i] = 1.0f;
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct) {
+        for (int ct = 0; ct < NB; ++ct) {
           const int col = prow0 + 16 * ct + c16;
           if (ct < nct && col < m) {
             const int64_t vr = vec_row(P.Q, qr[0] + col);
@@ -1811,12 +1815,12 @@ __global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocPara
         float rm[NT];
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct) rm[ct] = ninf;
-        bydoc_tiles<DT>(A_first<DT>(stage, c16, g), B, rm, stage, n_tiles, nct, c16, g);
+        bydoc_tiles<DT, NB>(A_first<DT>(stage, c16, g), B, rm, stage, n_tiles, nct, c16, g);
         float R[NT / 4];
         tile_sums<NT, O::kColumnScale>(rm, R, qs);
         float s_run = first_pass ? tile_sum_at<NT>(R, 0) : res + tile_sum_at<NT>(R, 0);
 #pragma unroll
-        for (int ct = 1; ct < NT; ++ct)
+        for (int ct = 1; ct < NB; ++ct)
           if (ct < nct) s_run += tile_sum_at<NT>(R, ct);
         res = s_run;
       }
@@ -1834,12 +1838,12 @@ __global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocPara
 
     // the group's shared pass
     const int nct = __builtin_amdgcn_readfirstlane(ctot);
-    Frag B[NT];
+    Frag B[NB];
     float qs[NT / 4];
 #pragma unroll
     for (int i = 0; i < NT / 4; ++i) qs[i] = 1.0f;
 #pragma unroll
-    for (int ct = 0; ct < NT; ++ct) {
+    for (int ct = 0; ct < NB; ++ct) {
       int64_t vr = -1;
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
@@ -1859,7 +1863,7 @@ __global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocPara
     float rm[NT];
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) rm[ct] = ninf;
-    bydoc_tiles<DT>(A_first<DT>(stage, c16, g), B, rm, stage, n_tiles, nct, c16, g);
+    bydoc_tiles<DT, NB>(A_first<DT>(stage, c16, g), B, rm, stage, n_tiles, nct, c16, g);
     float R[NT / 4];
     tile_sums<NT, O::kColumnScale>(rm, R, qs);
 #pragma unroll
@@ -1870,7 +1874,7 @@ __global__ __launch_bounds__(64 * kByDocWaves) void score_bydoc_kernel(ByDocPara
         if (qn[j] > 0) {
           res = tile_sum_at<NT>(R, qc[j]);
 #pragma unroll
-          for (int t = 1; t < NT; ++t)
+          for (int t = 1; t < NB; ++t)
             if (t < qn[j]) res += tile_sum_at<NT>(R, qc[j] + t);
         }
         if (l == 0) P.scores[ent[j]] = res;
@@ -1944,14 +1948,14 @@ hipError_t launch_score_bydoc(int dtype, const SetsView& Q, const SetsView& D, c
   // workgroups past the item count exit at once
   const int64_t grid = bydoc_items_bound(n_docs, n_entries);
   if (grid > INT32_MAX) return hipErrorInvalidValue;
-  const dim3 gr((unsigned)grid), blk(64 * kByDocWaves);
+  const dim3 gr((unsigned)grid), blk(64 * kByDocWaves), blk12(64 * 12);
   switch (dtype) {
-    case GEM_F32: hipLaunchKernelGGL(score_bydoc_kernel<GEM_F32>, gr, blk, 0, s, P); break;
-    case GEM_BF16X3: hipLaunchKernelGGL(score_bydoc_kernel<GEM_BF16X3>, gr, blk, 0, s, P); break;
-    case GEM_BF16: hipLaunchKernelGGL(score_bydoc_kernel<GEM_BF16>, gr, blk, 0, s, P); break;
-    case GEM_FP8_E4M3: hipLaunchKernelGGL(score_bydoc_kernel<GEM_FP8_E4M3>, gr, blk, 0, s, P); break;
-    case GEM_MXFP4: hipLaunchKernelGGL(score_bydoc_kernel<GEM_MXFP4>, gr, blk, 0, s, P); break;
-    case GEM_MXFP6: hipLaunchKernelGGL(score_bydoc_kernel<GEM_MXFP6>, gr, blk, 0, s, P); break;
+    case GEM_F32: hipLaunchKernelGGL((score_bydoc_kernel<GEM_F32, 2, 12>), gr, blk12, 0, s, P); break;
+    case GEM_BF16X3: hipLaunchKernelGGL((score_bydoc_kernel<GEM_BF16X3, 2, 12>), gr, blk12, 0, s, P); break;
+    case GEM_BF16: hipLaunchKernelGGL((score_bydoc_kernel<GEM_BF16, 4, kByDocWaves>), gr, blk, 0, s, P); break;
+    case GEM_FP8_E4M3: hipLaunchKernelGGL((score_bydoc_kernel<GEM_FP8_E4M3, 4, kByDocWaves>), gr, blk, 0, s, P); break;
+    case GEM_MXFP4: hipLaunchKernelGGL((score_bydoc_kernel<GEM_MXFP4, 4, kByDocWaves>), gr, blk, 0, s, P); break;
+    case GEM_MXFP6: hipLaunchKernelGGL((score_bydoc_kernel<GEM_MXFP6, 4, kByDocWaves>), gr, blk, 0, s, P); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
