@@ -339,6 +339,10 @@ class DeviceExecutor(Executor):
                       for _ in range(self.RESULT_RING)]
         self._ring_pos = 0
         self._off2 = torch.zeros(2, dtype=torch.int64, device=self.device)
+        # one workspace for the loop's scoring calls (they run in order on the
+        # executor's stream), grown only when a call needs more: a batch size
+        # the loop has not met before then allocates nothing
+        self._wsbuf = torch.empty(16 << 20, dtype=torch.uint8, device=self.device)
         self._iter_evts = []
         self.Q8 = None
         self.rows = None
@@ -488,6 +492,11 @@ class DeviceExecutor(Executor):
         order = np.argsort(-self.lens[slots], kind="stable")
         self.Q8, self.rows = self._gather(slots[order], fp8=True)
 
+    def _workspace(self, need: int) -> Optional[torch.Tensor]:
+        if need > self._wsbuf.numel():
+            self._wsbuf = torch.empty(2 * need, dtype=torch.uint8, device=self.device)
+        return self._wsbuf
+
     def _wait(self, evt) -> None:
         if self.on_wait is not None:
             while not evt.query():
@@ -513,7 +522,9 @@ class DeviceExecutor(Executor):
             if b > a:
                 Dc = self.D8.view(a, b)
                 out = self.est[:, a:]
-                self._gem.score_quant(self.Q8, Dc, scores=out, ld=self.n_docs, rows=self.rows, stream=self.stream)
+                ws = self._workspace(self._gem.score_workspace_bytes(self.Q8, Dc, scores_given=True))
+                self._gem.score_quant(self.Q8, Dc, scores=out, ld=self.n_docs, rows=self.rows, stream=self.stream,
+                                      ws=ws)
         evt = torch.cuda.Event()
         evt.record(self._stream())
         self._iter_evts.append(evt)
@@ -525,7 +536,8 @@ class DeviceExecutor(Executor):
         with torch.cuda.stream(self._stream()):
             _, short_i = g.topk(self.est, sl, seg_rows=rows, stream=self.stream)
             C = g.Cands(short_i.reshape(-1), stride=sl, n_lists=len(slots))
-            ts, ti = g.score_exact(Q, self.D32, cands=C, compute="f32", k=self.k, stream=self.stream)
+            ws = self._workspace(g.score_workspace_bytes(Q, self.D32, cands=C, k=self.k, compute="f32"))
+            ts, ti = g.score_exact(Q, self.D32, cands=C, compute="f32", k=self.k, stream=self.stream, ws=ws)
             hs_full, hi_full, slot_evt = self._ring[self._ring_pos]
             self._ring_pos = (self._ring_pos + 1) % len(self._ring)
             if not slot_evt[1]:
