@@ -332,6 +332,12 @@ class DeviceExecutor(Executor):
         self._ring_evt = {k: [None] * len(v) for k, v in self._rings.items()}
         self._ring_at = {"v": 0, "i": 0}
         self._copy = torch.cuda.Stream(device=self.device) if copy_stream else None
+        # admission vectors uploaded on the compute stream land in device
+        # buffers of their own, one per staging buffer, reused in stream order
+        # (admit consumes them at once; index uploads stay fresh tensors, since
+        # the packed batch keeps views of them across iterations)
+        self._dev_rings = None if copy_stream else {
+            "v": [torch.empty_like(h, device=self.device) for h in self._rings["v"]]}
         # ring of pinned result buffers for finished requests: entry j holds
         # [device copy event, results read by the host]
         self._ring = [(torch.empty(self.max_slots, self.k, dtype=torch.float32).pin_memory(),
@@ -409,7 +415,11 @@ class DeviceExecutor(Executor):
         cs = self._stream()
         st = cs if self._copy is None else self._copy
         with torch.cuda.stream(st):
-            dev = host.to(self.device, non_blocking=True)
+            if self._dev_rings is not None and kind in self._dev_rings:
+                dev = self._dev_rings[kind][j].view(-1)[: host.numel()].view(host.shape)
+                dev.copy_(host, non_blocking=True)
+            else:
+                dev = host.to(self.device, non_blocking=True)
             evt = torch.cuda.Event()
             evt.record(st)
         self._ring_evt[kind][j] = evt
