@@ -204,6 +204,28 @@ def test_qch_gather_matches_dense_and_oracle(dtype):
     assert rel.max() <= TOL
 
 
+@pytest.mark.parametrize("order", ["document", "auto"])
+def test_qch_gather_orders_fall_back_to_the_query_order(order):
+    """Code sets are not scored by document: asking for the document order
+    (or auto, with lists that hold many entries per document) gives the query
+    order's scores bitwise, here on lists of 2000 entries over 500 documents."""
+    C, qo, qc, do, dc, qmax = _qch_case(8)
+    Q = _code_sets(C, qo, qc, qmax, "fp8")
+    D = _code_sets(C, do, dc, 90, "fp8")
+    rng = np.random.default_rng(10)
+    n_q = len(qo) - 1
+    ids = rng.integers(0, 500, n_q * 2000).astype(np.int32)
+    cands = gem.Cands(torch.from_numpy(ids).to(DEV), stride=2000, n_lists=n_q)
+    gem.set_gather_order("query")
+    try:
+        want = _np(_score(Q, D, "fp8", cands=cands))
+        gem.set_gather_order(order)
+        got = _np(_score(Q, D, "fp8", cands=cands))
+    finally:
+        gem.set_gather_order("auto")
+    np.testing.assert_array_equal(got.view(np.int32), want.view(np.int32))
+
+
 def test_code_set_validation_and_mixed_sets():
     C, qo, qc, do, dc, qmax = _qch_case(7)
     D = _code_sets(C, do, dc, 90, "bf16")
